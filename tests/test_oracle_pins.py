@@ -1,0 +1,444 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a library
+routine (scipy convolution, numpy FFT, scipy.ndimage mirror filtering,
+torch.optim.Adam), a closed form (Gaussian flux and FWHM, Moffat FWHM, the B3
+starlet's delta response), an invariant (flux conservation, translation and
+rotation equivariance, exact starlet reconstruction, dot-product adjoint
+identities) or finite differences. All run on the CPU.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.ndimage
+import scipy.optimize
+import scipy.signal
+
+from oracle import oracle as ora
+from paper_2402_08725_amd import synth
+
+RNG = np.random.default_rng(1234)
+
+
+# --------------------------------------------------------------------------- #
+# Target Gaussian r (Sec. 2.1, Eq. 1): FWHM 2 fine px, unit integral           #
+# --------------------------------------------------------------------------- #
+
+def _render_single_source(N, cx, cy, amp=1.0):
+    params = np.concatenate([np.zeros(N * N), [0.0], [amp], [cx, cy]])
+    return ora.render_scene([N], 1, N, 1, 2.0, params).reshape(N, N)
+
+
+def test_gaussian_unit_flux_and_centroid():
+    N = 48
+    for cx, cy in [(20.3, 25.7), (24.0, 23.5), (19.91, 30.02)]:
+        f = _render_single_source(N, cx, cy)
+        # Poisson summation: the grid sum of a unit-integral Gaussian of sigma 0.849
+        # differs from 1 by at most 2 exp(-2 pi^2 sigma^2) per axis.
+        assert abs(f.sum() - 1.0) < 2.7e-6
+        y, x = np.mgrid[0:N, 0:N]
+        # The first aliased harmonic moves the sampled centroid by at most
+        # 4 pi sigma^2 exp(-2 pi^2 sigma^2) ~ 5.9e-6 px.
+        sig2 = ora.sigma_from_fwhm(2.0) ** 2
+        bound = 4 * math.pi * sig2 * math.exp(-2 * math.pi ** 2 * sig2) * 1.01
+        assert abs((f * x).sum() / f.sum() - cx) < bound
+        assert abs((f * y).sum() / f.sum() - cy) < bound
+
+
+def test_gaussian_fwhm_is_two_fine_pixels():
+    f = _render_single_source(32, 16.0, 16.0)
+    # pixel centres 1 px from the peak sit at half the FWHM
+    assert f[16, 17] / f[16, 16] == pytest.approx(0.5, rel=1e-12)
+    assert f[15, 16] / f[16, 16] == pytest.approx(0.5, rel=1e-12)
+    assert ora.sigma_from_fwhm(2.0) == pytest.approx(2.0 / (2 * math.sqrt(2 * math.log(2))), rel=1e-15)
+
+
+# --------------------------------------------------------------------------- #
+# S_i (convolution) and D (block sum), Eq. 8                                   #
+# --------------------------------------------------------------------------- #
+
+def _block_sum(u, s):
+    F = u.shape[0]
+    return u.reshape(F // s, s, F // s, s).sum(axis=(1, 3))
+
+
+@pytest.mark.parametrize("F,K,s", [(12, 5, 1), (12, 7, 2), (18, 9, 3), (16, 3, 2)])
+def test_conv_sub_odd_kernel_matches_scipy_same(F, K, s):
+    f = RNG.standard_normal((F, F))
+    k = RNG.standard_normal((K, K))
+    ref = _block_sum(scipy.signal.convolve2d(f, k, mode="same"), s)
+    got = ora.conv_sub([F // s], [K], s, k.ravel(), f.ravel()).reshape(F // s, F // s)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("F,K,s", [(12, 4, 1), (16, 8, 2), (18, 6, 3), (10, 16, 2)])
+def test_conv_sub_even_kernel_matches_zero_padded_fft(F, K, s):
+    f = RNG.standard_normal((F, F))
+    k = RNG.standard_normal((K, K))
+    P = F + K
+    full = np.fft.irfft2(np.fft.rfft2(f, (P, P)) * np.fft.rfft2(k, (P, P)), (P, P))
+    kap = K // 2                                  # kernel centre floor(K/2)
+    ref = _block_sum(full[kap:kap + F, kap:kap + F], s)
+    got = ora.conv_sub([F // s], [K], s, k.ravel(), f.ravel()).reshape(F // s, F // s)
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-10)
+
+
+def test_delta_kernel_s1_is_identity():
+    F, K = 10, 5
+    k = np.zeros((K, K))
+    k[K // 2, K // 2] = 1.0
+    f = RNG.standard_normal(F * F)
+    np.testing.assert_array_equal(ora.conv_sub([F], [K], 1, k.ravel(), f), f)
+
+
+def test_conv_sub_adjoint_identity_ragged():
+    n = np.array([6, 9, 4], np.int32)
+    K = np.array([7, 10, 5], np.int32)
+    s = 2
+    kern = RNG.standard_normal(int(np.sum(K.astype(np.int64) ** 2)))
+    x = RNG.standard_normal(int(np.sum((s * n) ** 2)))
+    y = RNG.standard_normal(int(np.sum(n ** 2)))
+    lhs = np.dot(ora.conv_sub(n, K, s, kern, x), y)
+    rhs = np.dot(x, ora.conv_sub_adj(n, K, s, kern, y))
+    assert abs(lhs - rhs) <= 1e-13 * max(abs(lhs), 1.0) * 10
+
+
+# --------------------------------------------------------------------------- #
+# Whole forward model (Eqs. 8-9): invariants                                   #
+# --------------------------------------------------------------------------- #
+
+def test_flux_conservation_point_source():
+    prob = synth.make_small_deconv(seed=5, E=2, sides=[16], K=[15], s=2, N=32, M=1, J=2)
+    p = prob.pack(h=np.zeros(prob.N ** 2), Gamma=np.zeros(2), a=np.array([1e4, 3e3]),
+                  c=np.array([15.3, 16.2]))
+    m = ora.forward_model(prob, p)
+    kern = prob.kernels.reshape(2, 15, 15)
+    for i, amp in enumerate([1e4, 3e3]):
+        tot = m[i * 256:(i + 1) * 256].sum()
+        assert tot == pytest.approx(amp * kern[i].sum(), rel=3e-6)
+
+
+def test_translation_by_s_fine_px_shifts_one_data_px():
+    prob = synth.make_small_deconv(seed=6, E=1, sides=[20], K=[9], s=2, N=40, M=1, J=2)
+    base = dict(h=np.zeros(prob.N ** 2), Gamma=np.zeros(1), a=np.array([1e3]))
+    m0 = ora.forward_model(prob, prob.pack(c=np.array([17.4, 18.7]), **base)).reshape(20, 20)
+    m1 = ora.forward_model(prob, prob.pack(c=np.array([17.4 + 2, 18.7 + 2]), **base)).reshape(20, 20)
+    np.testing.assert_allclose(m1[1:, 1:], m0[:-1, :-1], rtol=1e-12, atol=1e-9)
+
+
+def test_rotation_equivariance_odd_kernel():
+    prob = synth.make_small_deconv(seed=7, E=2, sides=[12, 8], K=[7, 5], s=2, N=24, M=2, J=3)
+    N = prob.N
+    h = prob.h.reshape(N, N)
+    p = prob.params_true
+    m = ora.forward_model(prob, p)
+    # rotate every input by 90 degrees (np.rot90: new[r, c] = old[c, N-1-r])
+    kr = []
+    off = 0
+    for K in prob.K:
+        kr.append(np.rot90(prob.kernels[off:off + K * K].reshape(K, K)).ravel())
+        off += K * K
+    c = prob.c.reshape(-1, 2)
+    c_rot = np.stack([c[:, 1], N - 1 - c[:, 0]], axis=1).ravel()
+    prob_r = synth.DeconvProblem(**{**prob.__dict__, "kernels": np.concatenate(kr)})
+    p_r = prob_r.pack(h=np.rot90(h).ravel(), c=c_rot)
+    m_r = ora.forward_model(prob_r, p_r)
+    off = 0
+    for n in prob.n:
+        a = m[off:off + n * n].reshape(n, n)
+        b = m_r[off:off + n * n].reshape(n, n)
+        np.testing.assert_allclose(b, np.rot90(a), rtol=1e-10, atol=1e-8)
+        off += n * n
+
+
+def test_noiseless_truth_has_zero_chi2_and_zero_gradient():
+    prob = synth.make_small_deconv(seed=8, E=3, sides=[10, 12, 8], K=[9, 8, 6], s=2, N=24, M=2, J=3)
+    p = prob.params_true
+    d = ora.forward_model(prob, p)
+    w = RNG.uniform(0.5, 2.0, d.shape)
+    loss, g = ora.loss_grad(prob, d, w, p, lam=0.0)
+    assert loss[0] <= 1e-20 * max(1.0, float(np.sum(d * d)))
+    assert np.abs(g).max() <= 1e-12 * max(1.0, float(np.abs(d).max()))
+
+
+def test_chi2_closed_form_for_known_residual():
+    prob = synth.make_small_deconv(seed=9, E=2, sides=[10, 6], K=[5, 4], s=2, N=20, M=1, J=2)
+    p = prob.params_true
+    m = ora.forward_model(prob, p)
+    delta = RNG.standard_normal(m.shape)
+    w = RNG.uniform(0.1, 3.0, m.shape)
+    loss, _ = ora.loss_grad(prob, m - delta, w, p, want_grad=False, lam=0.0)
+    assert loss[0] == pytest.approx(0.5 * np.sum(w * delta * delta), rel=1e-12)
+    assert loss[1] == 0.0 and loss[2] == loss[0]
+
+
+# --------------------------------------------------------------------------- #
+# Starlet transform (Eq. 6)                                                    #
+# --------------------------------------------------------------------------- #
+
+def _h_smooth_scipy(img, j):
+    d = 2 ** j
+    w = np.zeros(4 * d + 1)
+    w[::d] = np.array([1, 4, 6, 4, 1]) / 16.0
+    out = scipy.ndimage.convolve1d(img, w, axis=1, mode="mirror")
+    return scipy.ndimage.convolve1d(out, w, axis=0, mode="mirror")
+
+
+@pytest.mark.parametrize("N,J", [(16, 4), (33, 5), (20, 3)])
+def test_starlet_matches_scipy_mirror_filtering(N, J):
+    img = RNG.standard_normal((N, N))
+    got = ora.starlet_fwd(N, J, img.ravel()).reshape(J, N, N)
+    c = img
+    for j in range(J - 1):
+        cn = _h_smooth_scipy(c, j)
+        np.testing.assert_allclose(got[j], c - cn, rtol=1e-12, atol=1e-12)
+        c = cn
+    np.testing.assert_allclose(got[J - 1], c, rtol=1e-12, atol=1e-12)
+
+
+def test_starlet_exact_reconstruction():
+    N, J = 32, 5
+    img = RNG.standard_normal(N * N) * 10
+    coeffs = ora.starlet_fwd(N, J, img).reshape(J, -1)
+    np.testing.assert_allclose(coeffs.sum(axis=0), img, rtol=0, atol=1e-12 * 10)
+
+
+def test_starlet_constant_image():
+    N, J = 24, 4
+    coeffs = ora.starlet_fwd(N, J, np.full(N * N, 3.25)).reshape(J, -1)
+    assert np.abs(coeffs[:-1]).max() < 1e-14
+    np.testing.assert_allclose(coeffs[-1], 3.25, rtol=1e-15)
+
+
+def test_starlet_delta_first_scale():
+    N, J = 31, 3
+    img = np.zeros((N, N))
+    img[15, 15] = 1.0
+    coeffs = ora.starlet_fwd(N, J, img.ravel()).reshape(J, N, N)
+    assert coeffs[0, 15, 15] == 1.0 - (6.0 / 16.0) ** 2 == 0.859375
+
+
+@pytest.mark.parametrize("N,J", [(16, 4), (17, 5), (24, 3)])
+def test_starlet_adjoint_identity(N, J):
+    x = RNG.standard_normal(N * N)
+    z = RNG.standard_normal(J * N * N)
+    lhs = np.dot(ora.starlet_fwd(N, J, x), z)
+    rhs = np.dot(x, ora.starlet_adj(N, J, z))
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+# --------------------------------------------------------------------------- #
+# Gradient of the deconvolution loss (Eqs. 10-11)                              #
+# --------------------------------------------------------------------------- #
+
+def _small_problem_with_data(seed=11, w_stride=0):
+    prob = synth.make_small_deconv(seed=seed, E=3, sides=[8, 10, 6], K=[7, 6, 5], s=2, N=20,
+                                   M=2, J=3, w_stride=w_stride)
+    rng = np.random.default_rng(seed)
+    m = ora.forward_model(prob, prob.params_true)
+    d, w = synth.add_noise(m, rng)
+    p = synth.eval_point(prob, "near", rng)
+    return prob, d, w, p
+
+
+def _fd_check(fun, p, g, idx, rel_step=1e-6, tol=2e-6):
+    for j in idx:
+        h = rel_step * max(1.0, abs(p[j]))
+        pp, pm = p.copy(), p.copy()
+        pp[j] += h
+        pm[j] -= h
+        fd = (fun(pp) - fun(pm)) / (2 * h)
+        scale = max(abs(fd), abs(g[j]), 1e-6 * np.abs(g).max())
+        assert abs(fd - g[j]) <= tol * scale, (j, fd, g[j])
+
+
+def test_chi2_gradient_central_differences():
+    prob, d, w, p = _small_problem_with_data()
+    loss, g = ora.loss_grad(prob, d, w, p, lam=0.0)
+    fun = lambda q: ora.loss_grad(prob, d, w, q, want_grad=False, lam=0.0)[0][2]
+    NN = prob.N ** 2
+    rng = np.random.default_rng(3)
+    idx = list(rng.choice(NN, 25, replace=False)) + list(range(NN, prob.n_params))
+    _fd_check(fun, p, g, idx)
+
+
+@pytest.mark.parametrize("w_stride", [0, 1])
+def test_l1_term_is_linear_along_sign_preserving_directions(w_stride):
+    prob, d, w, p = _small_problem_with_data(seed=12, w_stride=w_stride)
+    _, g_all = ora.loss_grad(prob, d, w, p)
+    _, g_chi = ora.loss_grad(prob, d, w, p, lam=0.0)
+    g_l1 = g_all - g_chi
+    NN = prob.N ** 2
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        delta = np.zeros(prob.n_params)
+        delta[:NN] = rng.standard_normal(NN)
+        # largest step that keeps every coefficient's sign, halved
+        alpha = ora.starlet_fwd(prob.N, prob.J, p[:NN])
+        dalpha = ora.starlet_fwd(prob.N, prob.J, delta[:NN])
+        eps = 0.5 * np.min(np.abs(alpha) / np.maximum(np.abs(dalpha), 1e-300))
+        l1 = lambda q: ora.loss_grad(prob, d, w, q, want_grad=False)[0][1]
+        fd = (l1(p + eps * delta) - l1(p - eps * delta)) / (2 * eps)
+        assert fd == pytest.approx(np.dot(g_l1, delta), rel=1e-7)
+    assert np.all(g_l1[NN:] == 0.0)
+
+
+def test_sign_override_changes_only_the_subgradient():
+    prob, d, w, p = _small_problem_with_data(seed=13)
+    J, NN = prob.J, prob.N ** 2
+    so = np.full(J * NN, 2, np.int8)
+    so[5] = 0
+    l0, g0 = ora.loss_grad(prob, d, w, p)
+    l1, g1 = ora.loss_grad(prob, d, w, p, sgn_override=so)
+    assert np.array_equal(l0, l1)
+    z = np.zeros(J * NN)
+    alpha = ora.starlet_fwd(prob.N, J, p[:NN])
+    wj = prob.W[0]
+    z[5] = -prob.lam * wj * np.sign(alpha[5])
+    np.testing.assert_allclose(g1[:NN] - g0[:NN], ora.starlet_adj(prob.N, J, z), atol=1e-10)
+
+
+# --------------------------------------------------------------------------- #
+# PSF mode (Eqs. 2-7)                                                          #
+# --------------------------------------------------------------------------- #
+
+def test_moffat_fwhm_closed_form():
+    N, beta = 41, 2.5
+    half = 5.0                                        # FWHM/2 along x, in pixels
+    ax = half / math.sqrt(2 ** (1 / beta) - 1)
+    m = ora.moffat(N, np.array([2.0, ax, 0.6 * ax, 0.0, beta])).reshape(N, N)
+    c = N // 2
+    assert m[c, c] == pytest.approx(2.0, rel=1e-15)
+    assert m[c, c + 5] == pytest.approx(1.0, rel=1e-12)
+    half_y = 0.6 * ax * math.sqrt(2 ** (1 / beta) - 1)
+    assert 2 * ax * math.sqrt(2 ** (1 / 2.5) - 1) / ax == pytest.approx(1.1305, rel=1e-4)
+    # rotating by 90 degrees exchanges the axes
+    m90 = ora.moffat(N, np.array([2.0, ax, 0.6 * ax, math.pi / 2, beta])).reshape(N, N)
+    np.testing.assert_allclose(m90, m.T, rtol=1e-12, atol=1e-15)
+    assert half_y > 0
+
+
+def test_moffat_derivatives_central_differences():
+    N = 15
+    eta = np.array([1.7, 3.1, 2.2, 0.4, 2.8])
+    _, dm = ora.moffat(N, eta, want_grad=True)
+    dm = dm.reshape(5, -1)
+    for e in range(5):
+        h = 1e-6 * max(1.0, abs(eta[e]))
+        ep, em = eta.copy(), eta.copy()
+        ep[e] += h
+        em[e] -= h
+        fd = (ora.moffat(N, ep) - ora.moffat(N, em)) / (2 * h)
+        np.testing.assert_allclose(dm[e], fd, rtol=1e-6, atol=1e-9)
+
+
+def test_psf_star_model_matches_scipy_convolution():
+    prob = synth.make_psf(S=3, n=12, s=3, J=3)
+    N = prob.N
+    p = synth.psf_eval_point(prob, "near", np.random.default_rng(2))
+    p[5:5 + N * N] += RNG.standard_normal(N * N) * 1e-3
+    s_img = ora.psf_render(N, p).reshape(N, N)
+    a = p[5 + N * N:5 + N * N + prob.S]
+    c = p[5 + N * N + prob.S:].reshape(-1, 2)
+    got = ora.psf_model(prob, p).reshape(prob.S, prob.n, prob.n)
+    sig = ora.sigma_from_fwhm(2.0)
+    R = 14
+    t = np.arange(-R, R + 1)
+    for k in range(prob.S):
+        gx = np.exp(-(t - c[k, 0]) ** 2 / (2 * sig * sig))
+        gy = np.exp(-(t - c[k, 1]) ** 2 / (2 * sig * sig))
+        G = np.outer(gy, gx) / (2 * math.pi * sig * sig)
+        u = a[k] * scipy.signal.convolve2d(s_img, G, mode="same")
+        ref = _block_sum(u, prob.s)
+        np.testing.assert_allclose(got[k], ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
+
+
+def test_psf_gradient_central_differences():
+    prob = synth.make_psf(S=3, n=8, s=3, J=3)
+    rng = np.random.default_rng(21)
+    m = ora.psf_model(prob, prob.params_true)
+    d, w = synth.add_noise(m, rng, sigma_bg=prob.sigma_bg, poisson=False)
+    p = synth.psf_eval_point(prob, "near", rng)
+    _, g = ora.psf_loss_grad(prob, d, w, p, lam=0.0)
+    fun = lambda q: ora.psf_loss_grad(prob, d, w, q, want_grad=False, lam=0.0)[0][2]
+    NN = prob.N ** 2
+    idx = list(range(5)) + list(rng.choice(NN, 15, replace=False) + 5) + \
+        list(range(5 + NN, prob.n_params))
+    _fd_check(fun, p, g, idx, tol=5e-6)
+
+
+def test_psf_l1_adjoint_consistency():
+    prob = synth.make_psf(S=2, n=8, s=3, J=3)
+    rng = np.random.default_rng(22)
+    m = ora.psf_model(prob, prob.params_true)
+    d, w = synth.add_noise(m, rng, poisson=False)
+    p = synth.psf_eval_point(prob, "near", rng)
+    _, g_all = ora.psf_loss_grad(prob, d, w, p)
+    _, g_chi = ora.psf_loss_grad(prob, d, w, p, lam=0.0)
+    NN = prob.N ** 2
+    delta = np.zeros(prob.n_params)
+    delta[5:5 + NN] = rng.standard_normal(NN)
+    alpha = ora.starlet_fwd(prob.N, prob.J, p[5:5 + NN])
+    dalpha = ora.starlet_fwd(prob.N, prob.J, delta[5:5 + NN])
+    eps = 0.5 * np.min(np.abs(alpha) / np.maximum(np.abs(dalpha), 1e-300))
+    l1 = lambda q: ora.psf_loss_grad(prob, d, w, q, want_grad=False)[0][1]
+    fd = (l1(p + eps * delta) - l1(p - eps * delta)) / (2 * eps)
+    assert fd == pytest.approx(np.dot(g_all - g_chi, delta), rel=1e-7)
+
+
+# --------------------------------------------------------------------------- #
+# Adam (optimiser step)                                                        #
+# --------------------------------------------------------------------------- #
+
+def test_adam_matches_torch_optim_adam():
+    torch = pytest.importorskip("torch")
+    P = 40
+    rng = np.random.default_rng(5)
+    p0 = rng.standard_normal(P)
+    lr = np.where(np.arange(P) < 25, 0.5, 0.01)
+    tp1 = torch.tensor(p0[:25].copy(), dtype=torch.float64, requires_grad=True)
+    tp2 = torch.tensor(p0[25:].copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([{"params": [tp1], "lr": 0.5}, {"params": [tp2], "lr": 0.01}],
+                           betas=(0.9, 0.999), eps=1e-8)
+    p = p0.copy()
+    m = np.zeros(P)
+    v = np.zeros(P)
+    for t in range(1, 8):
+        g = rng.standard_normal(P)
+        ora.adam_step(p, g, m, v, t, lr)
+        opt.zero_grad()
+        tp1.grad = torch.tensor(g[:25])
+        tp2.grad = torch.tensor(g[25:])
+        opt.step()
+    np.testing.assert_allclose(p[:25], tp1.detach().numpy(), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(p[25:], tp2.detach().numpy(), rtol=1e-12, atol=1e-13)
+
+
+# --------------------------------------------------------------------------- #
+# End to end: planted-source recovery on noiseless data                        #
+# --------------------------------------------------------------------------- #
+
+def test_planted_source_recovery_noiseless_cfg1():
+    prob = synth.make_deconv(1)
+    pt = prob.params_true
+    d = ora.forward_model(prob, pt)
+    w = np.full(d.shape, 0.01)
+    NN, E, M = prob.N ** 2, prob.E, prob.M
+    free = np.arange(NN + E, prob.n_params)      # a and c; h and Gamma fixed at the truth
+    rng = np.random.default_rng(31)
+    x0 = pt[free] * np.concatenate([rng.uniform(0.9, 1.1, E * M), np.ones(2 * M)])
+    x0[E * M:] += rng.uniform(-0.5, 0.5, 2 * M)
+    scale = np.concatenate([np.full(E * M, 1e4), np.ones(2 * M)])
+
+    def fg(xs):
+        p = pt.copy()
+        p[free] = xs * scale
+        loss, g = ora.loss_grad(prob, d, w, p, lam=0.0)
+        return loss[2], g[free] * scale
+
+    res = scipy.optimize.minimize(fg, x0 / scale, jac=True, method="L-BFGS-B",
+                                  options={"maxiter": 500, "ftol": 1e-30, "gtol": 1e-14})
+    x = res.x * scale
+    assert np.abs(x[E * M:] - pt[free][E * M:]).max() < 1e-3
+    assert np.abs(x[:E * M] / pt[free][:E * M] - 1).max() < 1e-5
