@@ -1,0 +1,186 @@
+/*
+ * starred.h -- C ABI of the MI355X (gfx950) library that evaluates the loss and
+ * gradient of STARRED's joint multi-epoch two-channel deconvolution and of its
+ * PSF-reconstruction mode (Millon et al., "Image deconvolution and PSF
+ * reconstruction with STARRED", Sec. 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All float* / double* arguments are DEVICE pointers owned by the caller. The
+ *    library never frees them. Pointers passed to starred_set_frames are kept by
+ *    the plan (not copied) and must stay valid until the next starred_set_frames
+ *    or starred_plan_destroy.
+ *  - The plan owns its scratch memory, its device tables and its captured graph.
+ *  - Every call enqueues work on the plan's stream and returns without
+ *    synchronising (starred_plan_create / starred_set_frames synchronise once).
+ *  - Status codes: 0 = STARRED_OK; negative = error. Argument errors are found
+ *    on the host before anything is launched. The message of the last error of
+ *    the calling thread is returned by starred_last_error().
+ *  - A plan must not be used from two host threads at once.
+ *  - Images are square, row-major, FP32. Fine pixel (y, x) has its centre at
+ *    coordinate (x, y) in fine-pixel units. Data pixel (p, q) covers the fine
+ *    pixels [s p, s p + s) x [s q, s q + s) (the subsampling operator D of
+ *    Eq. 3 and Eq. 8 is the block sum).
+ *  - Frame i of data side n_i sees the central window of the fine grid h with
+ *    offset o_i = (N - s n_i)/2, which must be a non-negative integer.
+ *  - Per-frame arrays are packed frame after frame: data and inverse variance
+ *    n_i^2 each, scenes (s n_i)^2 each, kernels K_i^2 each.
+ */
+#ifndef STARRED_H
+#define STARRED_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STARRED_ABI_VERSION 1
+
+enum {
+    STARRED_OK = 0,
+    STARRED_EINVAL = -1,      /* bad argument, detected before any launch */
+    STARRED_ENOMEM = -2,      /* device allocation failed */
+    STARRED_EHIP = -3,        /* HIP runtime error (see starred_last_error) */
+    STARRED_EUNSUPPORTED = -4,/* valid request this build does not support */
+    STARRED_ESTATE = -5       /* call out of order (e.g. loss_grad before set_frames) */
+};
+
+enum { STARRED_DECONV = 0, STARRED_PSF = 1 };
+
+/* Convolution algorithm for the S_i / D pair of the deconvolution mode. */
+enum { STARRED_CONV_AUTO = 0, STARRED_CONV_DIRECT = 1, STARRED_CONV_FFT = 2 };
+
+typedef struct starred_plan starred_plan;
+
+/* Problem description (Sec. 2.1 Eqs. 2-7 for STARRED_PSF, Sec. 2.2 Eqs. 8-11
+ * for STARRED_DECONV).
+ *   mode        STARRED_DECONV or STARRED_PSF.
+ *   n_frames    E epochs (deconvolution) or S star stamps (PSF mode), >= 1.
+ *   side_host   host array [n_frames]: data side n_i of each frame (PSF mode: all
+ *               equal to grid_side / subsample).
+ *   ksize_host  host array [n_frames]: side K_i of each narrow-PSF kernel s_i
+ *               (deconvolution only; NULL in PSF mode). Centre at floor(K_i/2).
+ *   subsample   s >= 1 (1, 2 or 3 in this build).
+ *   grid_side   N: side of h (deconvolution) or of the PSF grid (PSF mode).
+ *   n_sources   M point sources (deconvolution), >= 0.
+ *   n_scales    J starlet planes including the coarse one, >= 1, with
+ *               2^(J-1) <= N-1 so that one mirror fold covers every tap.
+ *   w_pixel_stride  0: W holds J per-scale values; 1: W holds J*N*N maps.
+ *   lambda      regularisation strength of the starlet L1 term (Eq. 6, Eq. 11).
+ *   gauss_fwhm  FWHM of the target Gaussian r in fine pixels (2 in the paper,
+ *               Sec. 2.1).
+ *   conv_algo   STARRED_CONV_AUTO / DIRECT / FFT (deconvolution only). */
+typedef struct {
+    int32_t mode;
+    int32_t n_frames;
+    const int32_t *side_host;
+    const int32_t *ksize_host;
+    int32_t subsample;
+    int32_t grid_side;
+    int32_t n_sources;
+    int32_t n_scales;
+    int32_t w_pixel_stride;
+    int32_t conv_algo;
+    double lambda;
+    double gauss_fwhm;
+} starred_desc;
+
+/* Adam hyper-parameters; lr is given per parameter block:
+ *   deconvolution: lr[0] h, lr[1] Gamma, lr[2] a, lr[3] c
+ *   PSF mode:      lr[0] eta_M, lr[1] b, lr[2] a, lr[3] c */
+typedef struct {
+    float lr[4];
+    float beta1, beta2, eps;
+} starred_adam;
+
+/* Create a plan: validates the description, builds the frame tables and the
+ * work lists, allocates scratch. stream is a hipStream_t (NULL = default stream).
+ * Returns EINVAL for bad descriptions, ENOMEM / EHIP on device failures. */
+int starred_plan_create(const starred_desc *desc, void *stream, starred_plan **plan_out);
+int starred_plan_destroy(starred_plan *plan);
+
+/* Number of float parameters of the flat parameter vector:
+ *   deconvolution: [h N^2 | Gamma E | a E*M (epoch-major, a[i*M+k]) | c M*2 (x,y)]
+ *   PSF mode:      [eta_M 5 = (A, alpha_x, alpha_y, phi, beta) | b N^2 | a S | c S*2]
+ * and of the packed data arrays (sum of n_i^2) and scenes (sum of (s n_i)^2). */
+int64_t starred_num_params(const starred_plan *plan);
+int64_t starred_num_data(const starred_plan *plan);
+int64_t starred_num_scene(const starred_plan *plan);
+
+/* Bind the observations (Eq. 4 and Eq. 10): data d_i (or star stamps t_k),
+ * inverse variance w_i = diagonal of C^-1 (0 masks a pixel), the per-epoch
+ * narrow-PSF kernels s_i (packed K_i^2; NULL in PSF mode) and the starlet weights
+ * W (J values or J*N*N maps, see w_pixel_stride). The kernels are preprocessed
+ * on the device (box-folded and phase-split copies owned by the plan); data,
+ * inv_var and W are referenced, not copied. Synchronises the plan's stream. */
+int starred_set_frames(starred_plan *plan, const float *data, const float *inv_var,
+                       const float *psf, const float *W);
+
+/* Eq. 9: scene f_i = Gamma_i + h[window_i] + sum_k a_ki r_k for every frame,
+ * written packed (s n_i)^2. r_k is the Gaussian of FWHM gauss_fwhm centred at
+ * c_k (unit integral, point-sampled). PSF mode: writes the narrow PSF
+ * s = m(eta_M) + b (Eq. 2) on the N x N grid instead. */
+int starred_render_scene(starred_plan *plan, const float *params, float *scene);
+
+/* Eq. 8 without noise: model m_i = D S_i f_i for every frame (deconvolution).
+ * scene packed (s n_i)^2, model packed n_i^2. S_i is the linear 'same'
+ * convolution with zero padding. */
+int starred_convolve_subsample(starred_plan *plan, const float *scene, float *model);
+
+/* Adjoint of starred_convolve_subsample: grad_scene_i = S_i^T D^T resid_i. */
+int starred_convolve_subsample_adj(starred_plan *plan, const float *resid, float *grad_scene);
+
+/* Starlet transform Phi^T (Eq. 6): coeffs = J planes of N^2; plane j < J-1 is
+ * c_j - c_{j+1}, plane J-1 the coarse c_{J-1}; c_0 = img, c_{j+1} = H_j c_j with
+ * the B3 filter [1,4,6,4,1]/16 at dilation 2^j and a whole-sample mirror
+ * boundary. starred_starlet_adj applies the exact transpose Phi. */
+int starred_starlet_fwd(starred_plan *plan, const float *img, float *coeffs);
+int starred_starlet_adj(starred_plan *plan, const float *coeffs, float *img);
+
+/* Loss and gradient (Eq. 11 with lambda_pts = 0, or Eq. 7 in PSF mode).
+ * loss_out: device double[3] = {1/2 chi^2, lambda ||W o Phi^T h||_1, total}.
+ * grad (same layout as params) may be NULL: forward only (line searches).
+ * Deterministic: no floating-point atomics; repeated calls give identical bits. */
+int starred_loss_grad(starred_plan *plan, const float *params, float *grad, double *loss_out);
+
+/* One optimiser step: loss_grad at params, then the Adam update (Kingma & Ba)
+ * of params, m and v in place, t = step number starting at 1. The plan keeps
+ * the gradient in its own scratch. loss_out as above (may be NULL). */
+int starred_step(starred_plan *plan, float *params, float *m, float *v, int32_t t,
+                 const starred_adam *hp, double *loss_out);
+
+/* Capture the loss_grad (or step) sequence of the current bindings into a HIP
+ * graph and replay it on later calls with the same pointers; 0 disables. */
+int starred_set_graph_mode(starred_plan *plan, int32_t enable);
+
+/* Which convolution algorithm the plan runs (STARRED_CONV_DIRECT or _FFT). */
+int starred_conv_algo(const starred_plan *plan);
+
+/* Stage timing, for measurement. While enabled, loss_grad and step record a
+ * pair of HIP events on the plan's stream around each stage below.
+ * starred_profile_read synchronises the stream, returns per stage the summed
+ * milliseconds (ms_out[STARRED_NUM_STAGES]) and the number of timed launches
+ * (count_out[STARRED_NUM_STAGES]; either pointer may be NULL), then resets. */
+enum {
+    STARRED_STAGE_RENDER = 0,   /* scene rendering (Eq. 9) */
+    STARRED_STAGE_CONV_FWD,     /* S_i and D with the residual and chi-square (Eqs. 8, 10) */
+    STARRED_STAGE_CONV_ADJ,     /* S_i^T D^T of the weighted residuals */
+    STARRED_STAGE_GRAD_SUMS,    /* per-frame sums for Gamma, a and c */
+    STARRED_STAGE_STARLET,      /* starlet transform, L1 term, subgradient and adjoint (Eq. 6) */
+    STARRED_STAGE_FINALIZE,     /* cross-frame gradient of h and the final reductions */
+    STARRED_STAGE_ADAM,         /* optimiser update */
+    STARRED_STAGE_SPECTRA,      /* FFT path: spectra shared by all frames */
+    STARRED_NUM_STAGES
+};
+int starred_set_profiling(starred_plan *plan, int32_t enable);
+int starred_profile_read(starred_plan *plan, double *ms_out, int64_t *count_out);
+
+const char *starred_last_error(void);
+int starred_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STARRED_H */

@@ -120,6 +120,7 @@ def starlet_adj(N, J, coeffs):
 
 
 def forward_model(prob, params):
+    frame_offsets(prob.n, prob.s, prob.N)
     n, K = _i32(prob.n), _i32(prob.K)
     params, kernels = _f64(params), _f64(prob.kernels)
     out = np.zeros(int(np.sum(n.astype(np.int64) ** 2)))
@@ -130,6 +131,7 @@ def forward_model(prob, params):
 
 def loss_grad(prob, data, invvar, params, want_grad=True, sgn_override=None, lam=None, W=None):
     """Deconvolution loss (Eqs. 10-11) and gradient. Returns (loss[3], grad|None)."""
+    frame_offsets(prob.n, prob.s, prob.N)
     n, K = _i32(prob.n), _i32(prob.K)
     data, invvar, params = _f64(data), _f64(invvar), _f64(params)
     kernels = _f64(prob.kernels)

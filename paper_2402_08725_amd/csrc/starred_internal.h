@@ -1,0 +1,104 @@
+// Internal declarations shared by the host side of the library and the kernels.
+// Not part of the public C ABI (include/starred.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace starred {
+
+// Per-frame description kept in device memory (deconvolution mode).
+//
+// Direct algorithm: the fused S_i + D forward is the stride-s correlation
+//   m(p,q) = sum_{a,b < Kp} kf(a,b) f(s p + A0 + a, s q + A0 + b),  A0 = cp - (Kp - 1),
+// with kf the flipped kernel box-folded over s x s (side Kp = K + s - 1) and
+// cp = floor(K/2) + s - 1. kf is stored [a][psi][t], b = s t + psi, t < Tpad.
+// The adjoint is split into s^2 phases: for phase (py, px)
+//   g(s P + py, s Q + px) = sum_{al < Ar, be < Bpad} kp(al,be) rho(P + dmin + al, Q + dmin + be),
+// kp stored [py][px][al][be].
+struct FrameDev {
+    int n;      // data side
+    int F;      // fine side s*n
+    int K;      // kernel side
+    int Kp;     // folded kernel side K + s - 1
+    int o;      // window offset inside h
+    int cp;     // floor(K/2) + s - 1
+    int Tpad;   // forward taps per residue, padded to a multiple of 4
+    int Ar;     // adjoint phase-kernel rows
+    int Bpad;   // adjoint phase-kernel columns, padded to a multiple of 4
+    int dmin;   // adjoint row/column offset of phase kernels
+    int pad0, pad1;
+    long long data_off;  // into packed n_i^2 arrays
+    long long fine_off;  // into packed (s n_i)^2 arrays
+    long long kern_off;  // into packed K_i^2 kernels
+    long long kf_off;    // into the forward folded kernels
+    long long ka_off;    // into the adjoint phase kernels
+};
+
+// One work item of a tiled launch: frame and tile origin (data pixels),
+// plus the slot of its partial results (frame-major enumeration).
+struct Item {
+    int frame;
+    int p0;
+    int q0;
+    int slot;
+};
+
+// Tile shapes of the direct kernels (data pixels; every thread owns 4
+// consecutive outputs of one row).
+constexpr int kFwdTP = 16, kFwdTQ = 32, kFwdCA = 16;
+constexpr int kAdjTP = 16, kAdjTQ = 32;
+constexpr int kFwdThreads = kFwdTP * kFwdTQ / 4;
+constexpr int kAdjThreads = kAdjTP * kAdjTQ / 4;
+
+constexpr int kGaussRadius = 8;  // r is evaluated within +-8 fine px of c_k
+
+// ---- kernel launchers (starred_kernels.hip) ----
+hipError_t launch_prep_kernels(hipStream_t st, const FrameDev *fr_dev, const FrameDev *fr_host,
+                               int E, int s, const float *psf, float *kf, float *ka);
+hipError_t launch_render(hipStream_t st, const FrameDev *fr, int E, int Fmax, int N, int M,
+                         float sigma, const float *params, float *scene);
+hipError_t launch_fwd_direct(hipStream_t st, int s, const FrameDev *fr, const Item *items,
+                             int n_items, int Tmax, const float *scene, const float *kf,
+                             const float *data, const float *invvar, float *out, double *part_chi);
+hipError_t launch_adj_direct(hipStream_t st, int s, const FrameDev *fr, const Item *items,
+                             int n_items, int Ar_max, int Bpad_max, const float *rho,
+                             const float *ka, float *g);
+hipError_t launch_frame_sums(hipStream_t st, const FrameDev *fr, int E, int N, int M, float sigma,
+                             const float *params, const float *g, double *fsum);
+hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, const float *g,
+                             const float *prior, float *grad_h);
+hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const double *part_chi,
+                                 int n_l1, const double *part_l1, double lambda,
+                                 const double *fsum, const float *params, int N,
+                                 float *grad, double *loss);
+
+hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, float *coeffs,
+                              float *z, const float *W, int w_stride, float lam, float *c_a,
+                              float *c_b, float *tmp, double *part_l1, int *n_l1);
+hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, float *out,
+                              float *v_a, float *v_b, float *tmp);
+
+hipError_t launch_adam(hipStream_t st, long long P, const long long *seg_end, const float *lr,
+                       float *params, const float *grad, float *m, float *v, int t, float beta1,
+                       float beta2, float eps);
+
+hipError_t launch_fill(hipStream_t st, float *p, long long n, float v);
+
+// PSF mode
+hipError_t launch_psf_render(hipStream_t st, int N, const float *params, float *s_out);
+hipError_t launch_psf_fwd(hipStream_t st, int S, int n, int ss, int N, float sigma,
+                          const float *params, const float *s_img, const float *data,
+                          const float *invvar, float *rho, double *part_chi, float *gpart);
+hipError_t launch_psf_adj(hipStream_t st, int S, int n, int ss, int N, float sigma,
+                          const float *params, const float *rho, float *gstar);
+hipError_t launch_psf_finalize(hipStream_t st, int S, int N, const float *params,
+                               const float *gstar, const float *prior, const float *gpart,
+                               float *grad, double *part_eta);
+hipError_t launch_psf_finalize_small(hipStream_t st, int S, int n_chi, const double *part_chi,
+                                     int n_l1, const double *part_l1, double lambda,
+                                     int n_eta_blocks, const double *part_eta, float *grad,
+                                     double *loss);
+
+}  // namespace starred

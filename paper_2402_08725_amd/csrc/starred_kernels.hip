@@ -1,0 +1,705 @@
+// Device kernels of the deconvolution path (Sec. 2.2, Eqs. 8-11) and the shared
+// starlet / optimiser kernels, for gfx950 (wave64).
+//
+// Precision: FP32 arithmetic with FP32 accumulation for every pixel; the
+// chi-square and L1 global sums and the small per-frame dot products are
+// reduced in FP64 with fixed (deterministic) trees. No floating-point atomics.
+#include "starred_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace starred {
+
+// --------------------------------------------------------------------------
+// helpers
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ int mirror_idx(int i, int N)
+{
+    i = i < 0 ? -i : i;
+    return i > N - 1 ? 2 * (N - 1) - i : i;
+}
+
+__device__ __forceinline__ int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+
+// Deterministic block sum of one double per thread; result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum_d(double v, double *sh)
+{
+    #pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        #pragma unroll
+        for (int i = 0; i < NT / 64; ++i) r += sh[i];
+    }
+    __syncthreads();
+    return r;
+}
+
+// --------------------------------------------------------------------------
+// Kernel preprocessing (once per set_frames)
+// --------------------------------------------------------------------------
+
+// kf[a][psi][t]  = sum_{al,be < s} k(K-1-a+al, K-1-b+be),  b = s t + psi   (flipped, box-folded)
+// ka[py][px][al][be] = sf(s(dmin+al) + cp - py, s(dmin+be) + cp - px),
+//   sf(T,U) = sum_{al,be < s} k(T-(s-1)+al, U-(s-1)+be)                      (box-folded)
+__global__ void k_prep_kernels(const FrameDev *__restrict__ frames, int s,
+                               const float *__restrict__ psf, float *__restrict__ kf,
+                               float *__restrict__ ka)
+{
+    const FrameDev fr = frames[blockIdx.x];
+    const float *k = psf + fr.kern_off;
+    const int K = fr.K, Kp = fr.Kp;
+    auto kv = [&](int v, int u) -> float {
+        return (v >= 0 && v < K && u >= 0 && u < K) ? k[v * K + u] : 0.0f;
+    };
+    const int nf = Kp * s * fr.Tpad;
+    for (int e = threadIdx.x; e < nf; e += blockDim.x) {
+        int t = e % fr.Tpad;
+        int psi = (e / fr.Tpad) % s;
+        int a = e / (fr.Tpad * s);
+        int b = s * t + psi;
+        float acc = 0.0f;
+        if (b < Kp)
+            for (int al = 0; al < s; ++al)
+                for (int be = 0; be < s; ++be) acc += kv(K - 1 - a + al, K - 1 - b + be);
+        kf[fr.kf_off + e] = acc;
+    }
+    const int na = s * s * fr.Ar * fr.Bpad;
+    for (int e = threadIdx.x; e < na; e += blockDim.x) {
+        int be = e % fr.Bpad;
+        int al = (e / fr.Bpad) % fr.Ar;
+        int ph = e / (fr.Bpad * fr.Ar);
+        int py = ph / s, px = ph % s;
+        int T = s * (fr.dmin + al) + fr.cp - py;
+        int U = s * (fr.dmin + be) + fr.cp - px;
+        float acc = 0.0f;
+        if (be < fr.Ar && T >= 0 && T < Kp && U >= 0 && U < Kp)
+            for (int a2 = 0; a2 < s; ++a2)
+                for (int b2 = 0; b2 < s; ++b2) acc += kv(T - (s - 1) + a2, U - (s - 1) + b2);
+        ka[fr.ka_off + e] = acc;
+    }
+}
+
+hipError_t launch_prep_kernels(hipStream_t st, const FrameDev *fr_dev, const FrameDev *, int E,
+                               int s, const float *psf, float *kf, float *ka)
+{
+    if (E <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prep_kernels, dim3(E), dim3(256), 0, st, fr_dev, s, psf, kf, ka);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// a1: scene rendering f_i = Gamma_i + h[window_i] + sum_k a_ki r_k   (Eq. 9)
+// --------------------------------------------------------------------------
+
+__global__ void k_render(const FrameDev *__restrict__ frames, int N, int M, float sigma,
+                         const float *__restrict__ params, float *__restrict__ scene)
+{
+    const FrameDev fr = frames[blockIdx.y];
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= fr.F * fr.F) return;
+    const int y = pix / fr.F, x = pix % fr.F;
+    const int Y = y + fr.o, X = x + fr.o;
+    const int E = gridDim.y;
+    const float *h = params;
+    const float *a = params + (long long)N * N + E;
+    const float *c = a + (long long)E * M;
+    float v = params[(long long)N * N + blockIdx.y] + h[(long long)Y * N + X];
+    const float inv2s2 = 1.0f / (2.0f * sigma * sigma);
+    const float norm = 1.0f / (2.0f * 3.14159265358979f * sigma * sigma);
+    for (int k = 0; k < M; ++k) {
+        float dx = (float)X - c[2 * k], dy = (float)Y - c[2 * k + 1];
+        if (fabsf(dx) <= (float)kGaussRadius && fabsf(dy) <= (float)kGaussRadius)
+            v += a[(long long)blockIdx.y * M + k] * (norm * expf(-(dx * dx + dy * dy) * inv2s2));
+    }
+    scene[fr.fine_off + pix] = v;
+}
+
+hipError_t launch_render(hipStream_t st, const FrameDev *fr, int E, int Fmax, int N, int M,
+                         float sigma, const float *params, float *scene)
+{
+    if (E <= 0) return hipSuccess;
+    dim3 grid((Fmax * Fmax + 255) / 256, E);
+    hipLaunchKernelGGL(k_render, grid, dim3(256), 0, st, fr, N, M, sigma, params, scene);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Register-blocked correlation row: acc[j] += sum_{t < T} tap[t] * pl[j + t],
+// j = 0..3, with pl 16-byte aligned in LDS and tap wave-uniform.
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ void corr_row4(const float *__restrict__ pl, const float *__restrict__ tap,
+                                          int T, float (&acc)[4])
+{
+    float4 w0 = *reinterpret_cast<const float4 *>(pl);
+    for (int t = 0; t < T; t += 4) {
+        const float4 w1 = *reinterpret_cast<const float4 *>(pl + t + 4);
+        const float k0 = tap[t], k1 = tap[t + 1], k2 = tap[t + 2], k3 = tap[t + 3];
+        acc[0] = fmaf(k0, w0.x, acc[0]);
+        acc[1] = fmaf(k0, w0.y, acc[1]);
+        acc[2] = fmaf(k0, w0.z, acc[2]);
+        acc[3] = fmaf(k0, w0.w, acc[3]);
+        acc[0] = fmaf(k1, w0.y, acc[0]);
+        acc[1] = fmaf(k1, w0.z, acc[1]);
+        acc[2] = fmaf(k1, w0.w, acc[2]);
+        acc[3] = fmaf(k1, w1.x, acc[3]);
+        acc[0] = fmaf(k2, w0.z, acc[0]);
+        acc[1] = fmaf(k2, w0.w, acc[1]);
+        acc[2] = fmaf(k2, w1.x, acc[2]);
+        acc[3] = fmaf(k2, w1.y, acc[3]);
+        acc[0] = fmaf(k3, w0.w, acc[0]);
+        acc[1] = fmaf(k3, w1.x, acc[1]);
+        acc[2] = fmaf(k3, w1.y, acc[2]);
+        acc[3] = fmaf(k3, w1.z, acc[3]);
+        w0 = w1;
+    }
+}
+
+// --------------------------------------------------------------------------
+// a2 + a3 + a4: fused S_i, D, residual and chi-square partials (direct)
+// --------------------------------------------------------------------------
+//
+// One work group per (frame, 16 x 32 data-pixel tile). The scene region the
+// tile needs is staged in LDS, split into s column planes so that every
+// residue class of kernel columns reads consecutive floats; kernel rows are
+// streamed in chunks of kFwdCA.
+template <int S, bool RESID>
+__global__ __launch_bounds__(kFwdThreads) void k_fwd_direct(
+    const FrameDev *__restrict__ frames, const Item *__restrict__ items,
+    const float *__restrict__ scene, const float *__restrict__ kf, const float *__restrict__ data,
+    const float *__restrict__ invvar, float *__restrict__ out, double *__restrict__ part_chi)
+{
+    extern __shared__ float4 lds4[];
+    float *lds = reinterpret_cast<float *>(lds4);
+    __shared__ double red[kFwdThreads / 64];
+    const Item it = items[blockIdx.x];
+    const FrameDev fr = frames[it.frame];
+    const int tid = threadIdx.x;
+    constexpr int NTX = kFwdTQ / 4;
+    const int tx = tid % NTX, ty = tid / NTX;
+    const int Kp = fr.Kp, F = fr.F, T = fr.Tpad;
+    const int PW = kFwdTQ + T;  // floats per plane row
+    const int RW = S * PW;      // floats per region row
+    constexpr int ROWS = S * (kFwdTP - 1) + kFwdCA;
+    const int A0 = fr.cp - (Kp - 1);
+    const int rowF0 = S * it.p0 + A0;
+    const int colF0 = S * it.q0 + A0;
+    const float *scn = scene + fr.fine_off;
+    const float *kfr = kf + fr.kf_off;
+
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int a0 = 0; a0 < Kp; a0 += kFwdCA) {
+        __syncthreads();
+        const int tot = ROWS * RW;
+        for (int e = tid; e < tot; e += kFwdThreads) {
+            const int r = e / RW, c = e - r * RW;
+            const int yy = rowF0 + a0 + r, xx = colF0 + c;
+            float v = 0.f;
+            if (yy >= 0 && yy < F && xx >= 0 && xx < F) v = scn[yy * F + xx];
+            lds[r * RW + (c % S) * PW + c / S] = v;
+        }
+        __syncthreads();
+        const int na = min(kFwdCA, Kp - a0);
+        for (int a = 0; a < na; ++a) {
+            float racc[4] = {0.f, 0.f, 0.f, 0.f};
+            const float *lrow = lds + (S * ty + a) * RW + 4 * tx;
+            const float *krow = kfr + (long long)(a0 + a) * S * T;
+            #pragma unroll
+            for (int psi = 0; psi < S; ++psi) corr_row4(lrow + psi * PW, krow + psi * T, T, racc);
+            #pragma unroll
+            for (int j = 0; j < 4; ++j) acc[j] += racc[j];
+        }
+    }
+
+    const int p = it.p0 + ty;
+    double chi = 0.0;
+    #pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int q = it.q0 + 4 * tx + j;
+        if (p < fr.n && q < fr.n) {
+            const long long idx = fr.data_off + (long long)p * fr.n + q;
+            if (RESID) {
+                const float r = acc[j] - data[idx];
+                const float w = invvar[idx];
+                out[idx] = w * r;
+                chi += 0.5 * (double)w * (double)r * (double)r;
+            } else {
+                out[idx] = acc[j];
+            }
+        }
+    }
+    if (RESID) {
+        const double tot = block_sum_d<kFwdThreads>(chi, red);
+        if (tid == 0) part_chi[it.slot] = tot;
+    }
+}
+
+size_t fwd_lds_bytes(int s, int Tmax) { return (size_t)(s * (kFwdTP - 1) + kFwdCA) * s * (kFwdTQ + Tmax) * 4; }
+
+hipError_t launch_fwd_direct(hipStream_t st, int s, const FrameDev *fr, const Item *items,
+                             int n_items, int Tmax, const float *scene, const float *kf,
+                             const float *data, const float *invvar, float *out, double *part_chi)
+{
+    if (n_items <= 0) return hipSuccess;
+    const size_t lds = fwd_lds_bytes(s, Tmax);
+    const bool resid = (part_chi != nullptr);
+#define FWD_CASE(SS)                                                                               \
+    if (s == SS) {                                                                                 \
+        if (resid)                                                                                 \
+            hipLaunchKernelGGL((k_fwd_direct<SS, true>), dim3(n_items), dim3(kFwdThreads), lds, st, \
+                               fr, items, scene, kf, data, invvar, out, part_chi);                 \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_fwd_direct<SS, false>), dim3(n_items), dim3(kFwdThreads), lds,   \
+                               st, fr, items, scene, kf, data, invvar, out, part_chi);             \
+        return hipGetLastError();                                                                  \
+    }
+    FWD_CASE(1)
+    FWD_CASE(2)
+    FWD_CASE(3)
+#undef FWD_CASE
+    return hipErrorInvalidValue;
+}
+
+// --------------------------------------------------------------------------
+// a5: adjoint g_i = S_i^T D^T rho_i, phase by phase (direct)
+// --------------------------------------------------------------------------
+//
+// One work group per (frame, 16 x 32 coarse tile); each of the s^2 phases is a
+// stride-1 correlation of rho with the phase kernel, producing the fine pixels
+// (s P + py, s Q + px).
+template <int S>
+__global__ __launch_bounds__(kAdjThreads) void k_adj_direct(
+    const FrameDev *__restrict__ frames, const Item *__restrict__ items,
+    const float *__restrict__ rho, const float *__restrict__ ka, float *__restrict__ g)
+{
+    extern __shared__ float4 lds4[];
+    float *lds = reinterpret_cast<float *>(lds4);
+    const Item it = items[blockIdx.x];
+    const FrameDev fr = frames[it.frame];
+    const int tid = threadIdx.x;
+    constexpr int NTX = kAdjTQ / 4;
+    const int tx = tid % NTX, ty = tid / NTX;
+    const int n = fr.n, Ar = fr.Ar, Bp = fr.Bpad;
+    const int PW = kAdjTQ + Bp;
+    const int rows = kAdjTP - 1 + Ar;
+    const int r0 = it.p0 + fr.dmin, c0 = it.q0 + fr.dmin;
+    const float *rh = rho + fr.data_off;
+    for (int e = tid; e < rows * PW; e += kAdjThreads) {
+        const int r = e / PW, c = e - r * PW;
+        const int yy = r0 + r, xx = c0 + c;
+        float v = 0.f;
+        if (yy >= 0 && yy < n && xx >= 0 && xx < n) v = rh[yy * n + xx];
+        lds[e] = v;
+    }
+    __syncthreads();
+    const int P = it.p0 + ty;
+    const float *kfr = ka + fr.ka_off;
+    float *gf = g + fr.fine_off;
+    for (int py = 0; py < S; ++py)
+        for (int px = 0; px < S; ++px) {
+            float acc[4] = {0.f, 0.f, 0.f, 0.f};
+            const float *kph = kfr + (long long)(py * S + px) * Ar * Bp;
+            for (int al = 0; al < Ar; ++al) {
+                float racc[4] = {0.f, 0.f, 0.f, 0.f};
+                corr_row4(lds + (ty + al) * PW + 4 * tx, kph + (long long)al * Bp, Bp, racc);
+                #pragma unroll
+                for (int j = 0; j < 4; ++j) acc[j] += racc[j];
+            }
+            if (P < n) {
+                #pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int Q = it.q0 + 4 * tx + j;
+                    if (Q < n) gf[(long long)(S * P + py) * fr.F + S * Q + px] = acc[j];
+                }
+            }
+        }
+}
+
+size_t adj_lds_bytes(int Ar_max, int Bpad_max) { return (size_t)(kAdjTP - 1 + Ar_max) * (kAdjTQ + Bpad_max) * 4; }
+
+hipError_t launch_adj_direct(hipStream_t st, int s, const FrameDev *fr, const Item *items,
+                             int n_items, int Ar_max, int Bpad_max, const float *rho,
+                             const float *ka, float *g)
+{
+    if (n_items <= 0) return hipSuccess;
+    const size_t lds = adj_lds_bytes(Ar_max, Bpad_max);
+    if (s == 1)
+        hipLaunchKernelGGL(k_adj_direct<1>, dim3(n_items), dim3(kAdjThreads), lds, st, fr, items, rho, ka, g);
+    else if (s == 2)
+        hipLaunchKernelGGL(k_adj_direct<2>, dim3(n_items), dim3(kAdjThreads), lds, st, fr, items, rho, ka, g);
+    else if (s == 3)
+        hipLaunchKernelGGL(k_adj_direct<3>, dim3(n_items), dim3(kAdjThreads), lds, st, fr, items, rho, ka, g);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// a5: per-frame gradient sums. Block (i, 0): dL/dGamma_i = sum g_i.
+// Block (i, 1+k): <g_i, r_k>, <g_i, r_k (X-cx)/sigma^2>, <g_i, r_k (Y-cy)/sigma^2>
+// over the +-8 px window of source k.  fsum[i][1+3M].
+// --------------------------------------------------------------------------
+
+constexpr int kSumThreads = 256;
+
+__global__ __launch_bounds__(kSumThreads) void k_frame_sums(
+    const FrameDev *__restrict__ frames, int N, int M, float sigma,
+    const float *__restrict__ params, const float *__restrict__ g, double *__restrict__ fsum)
+{
+    __shared__ double red[kSumThreads / 64];
+    const int i = blockIdx.x;
+    const int E = gridDim.x;
+    const FrameDev fr = frames[i];
+    const float *gi = g + fr.fine_off;
+    const int stride = 1 + 3 * M;
+    if (blockIdx.y == 0) {
+        double acc = 0.0;
+        const int tot = fr.F * fr.F;
+        for (int p = threadIdx.x; p < tot; p += kSumThreads) acc += (double)gi[p];
+        const double s = block_sum_d<kSumThreads>(acc, red);
+        if (threadIdx.x == 0) fsum[(long long)i * stride] = s;
+        return;
+    }
+    const int k = blockIdx.y - 1;
+    const float *c = params + (long long)N * N + E + (long long)E * M;
+    const float cx = c[2 * k], cy = c[2 * k + 1];
+    const float inv2s2 = 1.0f / (2.0f * sigma * sigma);
+    const float invs2 = 1.0f / (sigma * sigma);
+    const float norm = 1.0f / (2.0f * 3.14159265358979f * sigma * sigma);
+    const int x_lo = max(fr.o, (int)ceilf(cx - kGaussRadius)), x_hi = min(fr.o + fr.F - 1, (int)floorf(cx + kGaussRadius));
+    const int y_lo = max(fr.o, (int)ceilf(cy - kGaussRadius)), y_hi = min(fr.o + fr.F - 1, (int)floorf(cy + kGaussRadius));
+    const int wx = x_hi - x_lo + 1, wy = y_hi - y_lo + 1;
+    double sa = 0.0, sx = 0.0, sy = 0.0;
+    if (wx > 0 && wy > 0) {
+        for (int e = threadIdx.x; e < wx * wy; e += kSumThreads) {
+            const int Y = y_lo + e / wx, X = x_lo + e % wx;
+            const float dx = (float)X - cx, dy = (float)Y - cy;
+            const float r = norm * expf(-(dx * dx + dy * dy) * inv2s2);
+            const float gv = gi[(long long)(Y - fr.o) * fr.F + (X - fr.o)];
+            const float gr = gv * r;
+            sa += (double)gr;
+            sx += (double)(gr * dx * invs2);
+            sy += (double)(gr * dy * invs2);
+        }
+    }
+    sa = block_sum_d<kSumThreads>(sa, red);
+    sx = block_sum_d<kSumThreads>(sx, red);
+    sy = block_sum_d<kSumThreads>(sy, red);
+    if (threadIdx.x == 0) {
+        fsum[(long long)i * stride + 1 + k] = sa;
+        fsum[(long long)i * stride + 1 + M + k] = sx;
+        fsum[(long long)i * stride + 1 + 2 * M + k] = sy;
+    }
+}
+
+hipError_t launch_frame_sums(hipStream_t st, const FrameDev *fr, int E, int N, int M, float sigma,
+                             const float *params, const float *g, double *fsum)
+{
+    if (E <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_frame_sums, dim3(E, 1 + M), dim3(kSumThreads), 0, st, fr, N, M, sigma,
+                       params, g, fsum);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// dL/dh = Phi z + sum over frames covering the pixel of g_i (frame order)
+// --------------------------------------------------------------------------
+
+__global__ void k_finalize_h(const FrameDev *__restrict__ frames, int E, int N,
+                             const float *__restrict__ g, const float *__restrict__ prior,
+                             float *__restrict__ grad_h)
+{
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= N * N) return;
+    const int Y = pix / N, X = pix % N;
+    float acc = prior ? prior[pix] : 0.f;
+    for (int i = 0; i < E; ++i) {
+        const int o = frames[i].o, F = frames[i].F;
+        const int y = Y - o, x = X - o;
+        if (y >= 0 && y < F && x >= 0 && x < F) acc += g[frames[i].fine_off + (long long)y * F + x];
+    }
+    grad_h[pix] = acc;
+}
+
+hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, const float *g,
+                             const float *prior, float *grad_h)
+{
+    hipLaunchKernelGGL(k_finalize_h, dim3((N * N + 255) / 256), dim3(256), 0, st, fr, E, N, g, prior,
+                       grad_h);
+    return hipGetLastError();
+}
+
+// loss[0] = sum chi partials, loss[1] = sum L1 partials, loss[2] = total;
+// grad Gamma, a, c from the per-frame sums (frames summed in order).
+constexpr int kFinThreads = 256;
+
+__global__ __launch_bounds__(kFinThreads) void k_finalize_small(
+    int E, int M, int n_chi, const double *__restrict__ part_chi, int n_l1,
+    const double *__restrict__ part_l1, const double *__restrict__ fsum,
+    const float *__restrict__ params, int N, float *__restrict__ grad, double *__restrict__ loss)
+{
+    __shared__ double red[kFinThreads / 64];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n_chi; i += kFinThreads) a += part_chi[i];
+    const double chi = block_sum_d<kFinThreads>(a, red);
+    double b = 0.0;
+    for (int i = threadIdx.x; i < n_l1; i += kFinThreads) b += part_l1[i];
+    const double l1 = block_sum_d<kFinThreads>(b, red);
+    if (threadIdx.x == 0 && loss) {
+        loss[0] = chi;
+        loss[1] = l1;
+        loss[2] = chi + l1;
+    }
+    if (!grad) return;
+    const long long NN = (long long)N * N;
+    const int stride = 1 + 3 * M;
+    float *gG = grad + NN, *ga = gG + E, *gc = ga + (long long)E * M;
+    const float *pa = params + NN + E;
+    for (int i = threadIdx.x; i < E; i += kFinThreads) {
+        gG[i] = (float)fsum[(long long)i * stride];
+        for (int k = 0; k < M; ++k) ga[(long long)i * M + k] = (float)fsum[(long long)i * stride + 1 + k];
+    }
+    for (int q = threadIdx.x; q < 2 * M; q += kFinThreads) {
+        const int k = q >> 1, axis = q & 1;
+        double acc = 0.0;
+        for (int i = 0; i < E; ++i)
+            acc += (double)pa[(long long)i * M + k] * fsum[(long long)i * stride + 1 + (1 + axis) * M + k];
+        gc[q] = (float)acc;
+    }
+}
+
+hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const double *part_chi,
+                                 int n_l1, const double *part_l1, double,
+                                 const double *fsum, const float *params, int N,
+                                 float *grad, double *loss)
+{
+    hipLaunchKernelGGL(k_finalize_small, dim3(1), dim3(kFinThreads), 0, st, E, M, n_chi, part_chi,
+                       n_l1, part_l1, fsum, params, N, grad, loss);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// a6 + a7: starlet forward (B3 a-trous, mirror boundary) with the weighted L1
+// term and its subgradient fused into the column pass.
+// --------------------------------------------------------------------------
+
+__constant__ float kB3[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
+constexpr int kStarThreads = 256;
+
+__global__ void k_star_row(const float *__restrict__ in, float *__restrict__ out, int N, int d)
+{
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= N * N) return;
+    const int y = pix / N, x = pix % N;
+    const float *row = in + (long long)y * N;
+    float acc = 0.f;
+    #pragma unroll
+    for (int t = -2; t <= 2; ++t) acc = fmaf(kB3[t + 2], row[mirror_idx(x + t * d, N)], acc);
+    out[pix] = acc;
+}
+
+__device__ __forceinline__ float sgnf(float v) { return (float)((v > 0.f) - (v < 0.f)); }
+
+// c_next = C_j tmp; alpha_j = c_j - c_next; optionally also the coarse plane.
+__global__ __launch_bounds__(kStarThreads) void k_star_col(
+    const float *__restrict__ cj, const float *__restrict__ tmp, float *__restrict__ cnext,
+    float *__restrict__ coeffs, float *__restrict__ z, const float *__restrict__ W, int w_stride,
+    float lam, int N, int d, int j, int last, double *__restrict__ part_l1)
+{
+    __shared__ double red[kStarThreads / 64];
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    const long long NN = (long long)N * N;
+    double l1 = 0.0;
+    if (pix < N * N) {
+        const int y = pix / N, x = pix % N;
+        float acc = 0.f;
+        #pragma unroll
+        for (int t = -2; t <= 2; ++t) acc = fmaf(kB3[t + 2], tmp[(long long)mirror_idx(y + t * d, N) * N + x], acc);
+        cnext[pix] = acc;
+        const float al = cj[pix] - acc;
+        const float wj = w_stride ? W[j * NN + pix] : W[j];
+        if (coeffs) coeffs[j * NN + pix] = al;
+        if (z) z[j * NN + pix] = lam * wj * sgnf(al);
+        l1 += (double)lam * (double)wj * (double)fabsf(al);
+        if (last) {
+            const float wl = w_stride ? W[(j + 1) * NN + pix] : W[j + 1];
+            if (coeffs) coeffs[(j + 1) * NN + pix] = acc;
+            if (z) z[(j + 1) * NN + pix] = lam * wl * sgnf(acc);
+            l1 += (double)lam * (double)wl * (double)fabsf(acc);
+        }
+    }
+    const double s = block_sum_d<kStarThreads>(l1, red);
+    if (threadIdx.x == 0 && part_l1) part_l1[blockIdx.x] = s;
+}
+
+// J == 1: the only plane is the image itself.
+__global__ __launch_bounds__(kStarThreads) void k_star_plane(
+    const float *__restrict__ img, float *__restrict__ coeffs, float *__restrict__ z,
+    const float *__restrict__ W, int w_stride, float lam, int N, double *__restrict__ part_l1)
+{
+    __shared__ double red[kStarThreads / 64];
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    double l1 = 0.0;
+    if (pix < N * N) {
+        const float al = img[pix];
+        const float wj = w_stride ? W[pix] : W[0];
+        if (coeffs) coeffs[pix] = al;
+        if (z) z[pix] = lam * wj * sgnf(al);
+        l1 = (double)lam * (double)wj * (double)fabsf(al);
+    }
+    const double s = block_sum_d<kStarThreads>(l1, red);
+    if (threadIdx.x == 0 && part_l1) part_l1[blockIdx.x] = s;
+}
+
+hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, float *coeffs,
+                              float *z, const float *W, int w_stride, float lam, float *c_a,
+                              float *c_b, float *tmp, double *part_l1, int *n_l1)
+{
+    const int nb = (N * N + kStarThreads - 1) / kStarThreads;
+    if (J == 1) {
+        hipLaunchKernelGGL(k_star_plane, dim3(nb), dim3(kStarThreads), 0, st, img, coeffs, z, W,
+                           w_stride, lam, N, part_l1);
+        if (n_l1) *n_l1 = nb;
+        return hipGetLastError();
+    }
+    const float *cur = img;
+    for (int j = 0; j < J - 1; ++j) {
+        float *nxt = (j % 2 == 0) ? c_a : c_b;
+        hipLaunchKernelGGL(k_star_row, dim3(nb), dim3(kStarThreads), 0, st, cur, tmp, N, 1 << j);
+        hipLaunchKernelGGL(k_star_col, dim3(nb), dim3(kStarThreads), 0, st, cur, tmp, nxt, coeffs, z,
+                           W, w_stride, lam, N, 1 << j, j, (int)(j == J - 2),
+                           part_l1 ? part_l1 + (long long)j * nb : nullptr);
+        cur = nxt;
+    }
+    if (n_l1) *n_l1 = (J - 1) * nb;
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// a8: starlet adjoint Phi z:  v = z_{J-1};  v = z_j + H_j^T (v - z_j), j = J-2..0.
+// H_j^T = R_j^T C_j^T; each 1-D transpose gathers the taps that the mirror
+// boundary folded onto the target pixel.
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ float mirrorT_gather(const float *__restrict__ u, long long stride, int i,
+                                                int N, int d, const float *__restrict__ zsub,
+                                                bool sub)
+{
+    // sum over taps t of w_t * u'(y) for every y with mirror(y + t d) == i,
+    // where u' = u - zsub (if sub).
+    float acc = 0.f;
+    #pragma unroll
+    for (int t = -2; t <= 2; ++t) {
+        const float w = kB3[t + 2];
+        int y = i - t * d;
+        if (y >= 0 && y < N) acc = fmaf(w, u[y * stride] - (sub ? zsub[y * stride] : 0.f), acc);
+        if (i > 0) {
+            y = -i - t * d;
+            if (y >= 0 && y < N) acc = fmaf(w, u[y * stride] - (sub ? zsub[y * stride] : 0.f), acc);
+        }
+        if (i < N - 1) {
+            y = 2 * (N - 1) - i - t * d;
+            if (y >= 0 && y < N) acc = fmaf(w, u[y * stride] - (sub ? zsub[y * stride] : 0.f), acc);
+        }
+    }
+    return acc;
+}
+
+// tmp = C_j^T (v - z_j)   (columns)
+__global__ void k_star_colT(const float *__restrict__ v, const float *__restrict__ zj,
+                            float *__restrict__ tmp, int N, int d)
+{
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= N * N) return;
+    const int y = pix / N, x = pix % N;
+    tmp[pix] = mirrorT_gather(v + x, N, y, N, d, zj + x, true);
+}
+
+// vout = z_j + R_j^T tmp   (rows)
+__global__ void k_star_rowT(const float *__restrict__ tmp, const float *__restrict__ zj,
+                            float *__restrict__ vout, int N, int d)
+{
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= N * N) return;
+    const int y = pix / N, x = pix % N;
+    vout[pix] = zj[pix] + mirrorT_gather(tmp + (long long)y * N, 1, x, N, d, nullptr, false);
+}
+
+__global__ void k_copy(const float *__restrict__ a, float *__restrict__ b, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, float *out,
+                              float *v_a, float *v_b, float *tmp)
+{
+    const long long NN = (long long)N * N;
+    const int nb = (int)((NN + kStarThreads - 1) / kStarThreads);
+    if (J == 1) {
+        hipLaunchKernelGGL(k_copy, dim3(nb), dim3(kStarThreads), 0, st, z, out, NN);
+        return hipGetLastError();
+    }
+    const float *v = z + (J - 1) * NN;
+    for (int j = J - 2; j >= 0; --j) {
+        float *vn = (j == 0) ? out : ((j % 2 == 0) ? v_a : v_b);
+        hipLaunchKernelGGL(k_star_colT, dim3(nb), dim3(kStarThreads), 0, st, v, z + j * NN, tmp, N, 1 << j);
+        hipLaunchKernelGGL(k_star_rowT, dim3(nb), dim3(kStarThreads), 0, st, tmp, z + j * NN, vn, N, 1 << j);
+        v = vn;
+    }
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// a12: Adam update (per-block learning rates)
+// --------------------------------------------------------------------------
+
+__global__ void k_adam(long long P, long long e0, long long e1, long long e2, float lr0, float lr1,
+                       float lr2, float lr3, float *__restrict__ params,
+                       const float *__restrict__ grad, float *__restrict__ m,
+                       float *__restrict__ v, float beta1, float beta2, float bc1, float bc2,
+                       float eps)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const float lr = i < e0 ? lr0 : (i < e1 ? lr1 : (i < e2 ? lr2 : lr3));
+    const float g = grad[i];
+    const float mi = beta1 * m[i] + (1.f - beta1) * g;
+    const float vi = beta2 * v[i] + (1.f - beta2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    params[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+hipError_t launch_adam(hipStream_t st, long long P, const long long *seg_end, const float *lr,
+                       float *params, const float *grad, float *m, float *v, int t, float beta1,
+                       float beta2, float eps)
+{
+    const float bc1 = (float)(1.0 - pow((double)beta1, (double)t));
+    const float bc2 = (float)(1.0 - pow((double)beta2, (double)t));
+    const int nb = (int)((P + 255) / 256);
+    hipLaunchKernelGGL(k_adam, dim3(nb), dim3(256), 0, st, P, seg_end[0], seg_end[1], seg_end[2],
+                       lr[0], lr[1], lr[2], lr[3], params, grad, m, v, beta1, beta2, bc1, bc2, eps);
+    return hipGetLastError();
+}
+
+__global__ void k_fill(float *p, long long n, float v)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill(hipStream_t st, float *p, long long n, float v)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace starred

@@ -1,0 +1,258 @@
+"""Python binding of libstarred.so (include/starred.h).
+
+Argument marshalling only: every step of the loss and gradient runs in the HIP
+kernels of the library. PyTorch supplies device memory (tensors) and streams;
+only raw device pointers and the stream handle cross the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libstarred.so")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5
+DECONV, PSF = 0, 1
+CONV_AUTO, CONV_DIRECT, CONV_FFT = 0, 1, 2
+
+EXPORTED = [
+    "starred_plan_create", "starred_plan_destroy", "starred_num_params", "starred_num_data",
+    "starred_num_scene", "starred_set_frames", "starred_render_scene",
+    "starred_convolve_subsample", "starred_convolve_subsample_adj", "starred_starlet_fwd",
+    "starred_starlet_adj", "starred_loss_grad", "starred_step", "starred_set_graph_mode",
+    "starred_conv_algo", "starred_last_error", "starred_abi_version", "starred_set_profiling",
+    "starred_profile_read",
+]
+STAGES = ["render", "conv_fwd", "conv_adj", "grad_sums", "starlet", "finalize", "adam", "spectra"]
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("mode", ctypes.c_int32), ("n_frames", ctypes.c_int32),
+        ("side_host", ctypes.POINTER(ctypes.c_int32)), ("ksize_host", ctypes.POINTER(ctypes.c_int32)),
+        ("subsample", ctypes.c_int32), ("grid_side", ctypes.c_int32), ("n_sources", ctypes.c_int32),
+        ("n_scales", ctypes.c_int32), ("w_pixel_stride", ctypes.c_int32), ("conv_algo", ctypes.c_int32),
+        ("lambda_", ctypes.c_double), ("gauss_fwhm", ctypes.c_double),
+    ]
+
+
+class AdamHP(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float * 4), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
+class StarredError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"starred error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libstarred.so; fails loudly when the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.starred_plan_create.argtypes = [ctypes.POINTER(Desc), vp, ctypes.POINTER(vp)]
+        L.starred_plan_destroy.argtypes = [vp]
+        for f in ["starred_num_params", "starred_num_data", "starred_num_scene"]:
+            getattr(L, f).argtypes = [vp]
+            getattr(L, f).restype = i64
+        L.starred_set_frames.argtypes = [vp, vp, vp, vp, vp]
+        for f in ["starred_render_scene", "starred_convolve_subsample", "starred_convolve_subsample_adj",
+                  "starred_starlet_fwd", "starred_starlet_adj"]:
+            getattr(L, f).argtypes = [vp, vp, vp]
+        L.starred_loss_grad.argtypes = [vp, vp, vp, vp]
+        L.starred_step.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(AdamHP), vp]
+        L.starred_set_graph_mode.argtypes = [vp, i32]
+        L.starred_conv_algo.argtypes = [vp]
+        L.starred_last_error.restype = ctypes.c_char_p
+        L.starred_set_profiling.argtypes = [vp, i32]
+        L.starred_profile_read.argtypes = [vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise StarredError(rc, lib().starred_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f32(x, device):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.float32).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32), device=device)
+
+
+class Plan:
+    """A problem plan: frame tables, preprocessed kernels and scratch on one GPU."""
+
+    def __init__(self, mode, sides, ksizes, s, N, M, J, lam, w_stride=0, fwhm=2.0,
+                 conv_algo=CONV_AUTO, device="cuda:0"):
+        self.device = torch.device(device)
+        self.mode = mode
+        self.E = len(sides)
+        self.s, self.N, self.M, self.J = int(s), int(N), int(M), int(J)
+        self._sides = np.ascontiguousarray(sides, dtype=np.int32)
+        self._ks = np.ascontiguousarray(ksizes, dtype=np.int32) if ksizes is not None else None
+        d = Desc()
+        d.mode = mode
+        d.n_frames = self.E
+        d.side_host = self._sides.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.ksize_host = (self._ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+                        if self._ks is not None else None)
+        d.subsample, d.grid_side, d.n_sources, d.n_scales = self.s, self.N, self.M, self.J
+        d.w_pixel_stride, d.conv_algo = w_stride, conv_algo
+        d.lambda_, d.gauss_fwhm = float(lam), float(fwhm)
+        self.stream = torch.cuda.Stream(self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().starred_plan_create(ctypes.byref(d), ctypes.c_void_p(self.stream.cuda_stream),
+                                             ctypes.byref(h)))
+        self._h = h
+        self.n_params = lib().starred_num_params(h)
+        self.n_data = lib().starred_num_data(h)
+        self.n_scene = lib().starred_num_scene(h)
+        self._bound = ()
+
+    @classmethod
+    def for_problem(cls, prob, conv_algo=CONV_AUTO, device="cuda:0", lam=None):
+        return cls(DECONV, prob.n, prob.K, prob.s, prob.N, prob.M, prob.J,
+                   prob.lam if lam is None else lam, prob.w_stride, prob.fwhm, conv_algo, device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().starred_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- stream ordering with PyTorch's current stream --
+    def _call(self, fn, *args):
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        with torch.cuda.device(self.device):
+            rc = fn(self._h, *args)
+        cur.wait_stream(self.stream)
+        _check(rc)
+
+    @property
+    def conv_algo(self):
+        return lib().starred_conv_algo(self._h)
+
+    def set_frames(self, data, invvar, psf, W):
+        t = [_f32(x, self.device) if x is not None else None for x in (data, invvar, psf, W)]
+        self._bound = tuple(t)  # keep the memory alive while the plan references it
+        self._call(lib().starred_set_frames, *[_ptr(x) for x in t])
+
+    def render_scene(self, params):
+        params = _f32(params, self.device)
+        out = torch.empty(self.n_scene if self.mode == DECONV else self.N * self.N,
+                          dtype=torch.float32, device=self.device)
+        self._call(lib().starred_render_scene, _ptr(params), _ptr(out))
+        return out
+
+    def convolve_subsample(self, scene):
+        scene = _f32(scene, self.device)
+        out = torch.empty(self.n_data, dtype=torch.float32, device=self.device)
+        self._call(lib().starred_convolve_subsample, _ptr(scene), _ptr(out))
+        return out
+
+    def convolve_subsample_adj(self, resid):
+        resid = _f32(resid, self.device)
+        out = torch.empty(self.n_scene, dtype=torch.float32, device=self.device)
+        self._call(lib().starred_convolve_subsample_adj, _ptr(resid), _ptr(out))
+        return out
+
+    def starlet_fwd(self, img):
+        img = _f32(img, self.device)
+        out = torch.empty(self.J * self.N * self.N, dtype=torch.float32, device=self.device)
+        self._call(lib().starred_starlet_fwd, _ptr(img), _ptr(out))
+        return out
+
+    def starlet_adj(self, coeffs):
+        coeffs = _f32(coeffs, self.device)
+        out = torch.empty(self.N * self.N, dtype=torch.float32, device=self.device)
+        self._call(lib().starred_starlet_adj, _ptr(coeffs), _ptr(out))
+        return out
+
+    def loss_grad(self, params, want_grad=True, grad_out=None, loss_out=None):
+        """Returns (loss double[3] tensor, grad float32 tensor or None)."""
+        params = _f32(params, self.device)
+        loss = loss_out if loss_out is not None else torch.empty(3, dtype=torch.float64, device=self.device)
+        grad = None
+        if want_grad:
+            grad = grad_out if grad_out is not None else torch.empty(self.n_params, dtype=torch.float32,
+                                                                      device=self.device)
+        self._call(lib().starred_loss_grad, _ptr(params), _ptr(grad), _ptr(loss))
+        return loss, grad
+
+    def step(self, params, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, loss_out=None):
+        """One Adam step in place on (params, m, v); returns the loss at the old params."""
+        hp = AdamHP()
+        for i in range(4):
+            hp.lr[i] = float(lr[i])
+        hp.beta1, hp.beta2, hp.eps = beta1, beta2, eps
+        loss = loss_out if loss_out is not None else torch.empty(3, dtype=torch.float64, device=self.device)
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        with torch.cuda.device(self.device):
+            rc = lib().starred_step(self._h, _ptr(params), _ptr(m), _ptr(v), int(t), ctypes.byref(hp),
+                                    _ptr(loss))
+        cur.wait_stream(self.stream)
+        _check(rc)
+        return loss
+
+    def set_profiling(self, enable: bool):
+        _check(lib().starred_set_profiling(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        """Per-stage summed milliseconds and launch counts since the last read."""
+        ms = np.zeros(len(STAGES), np.float64)
+        cnt = np.zeros(len(STAGES), np.int64)
+        _check(lib().starred_profile_read(self._h, ctypes.c_void_p(ms.ctypes.data),
+                                          ctypes.c_void_p(cnt.ctypes.data)))
+        return {name: {"ms": float(ms[i]), "count": int(cnt[i])} for i, name in enumerate(STAGES)}
+
+    def set_graph_mode(self, enable: bool):
+        _check(lib().starred_set_graph_mode(self._h, int(bool(enable))))
+
+
+class StarredLoss(torch.autograd.Function):
+    """Loss of Eq. (11) (or Eq. (7)) as an autograd function whose backward is
+    the library's hand-written adjoint: forward calls loss_grad and keeps the
+    gradient, backward scales it by the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, params, plan):
+        loss, grad = plan.loss_grad(params.detach())
+        ctx.save_for_backward(grad)
+        return loss[2].clone()
+
+    @staticmethod
+    def backward(ctx, grad_output):
+        (grad,) = ctx.saved_tensors
+        return (grad_output.to(grad.dtype) * grad), None
+
+
+def starred_loss(params, plan):
+    return StarredLoss.apply(params, plan)
