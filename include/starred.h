@@ -128,8 +128,14 @@ int starred_render_scene(starred_plan *plan, const float *params, float *scene);
  * convolution with zero padding. */
 int starred_convolve_subsample(starred_plan *plan, const float *scene, float *model);
 
-/* Adjoint of starred_convolve_subsample: grad_scene_i = S_i^T D^T resid_i. */
+/* Adjoint of starred_convolve_subsample: grad_scene_i = S_i^T D^T resid_i.
+ * Both are deconvolution-mode operators (EUNSUPPORTED in PSF mode). */
 int starred_convolve_subsample_adj(starred_plan *plan, const float *resid, float *grad_scene);
+
+/* PSF mode, Eq. 3 without noise: star models m_k = D(s * a_k r_k), s = m(eta_M) + b,
+ * r_k the Gaussian of FWHM gauss_fwhm shifted by c_k from the grid centre
+ * floor(N/2). params in the PSF-mode layout; model packed S x n^2. */
+int starred_psf_model(starred_plan *plan, const float *params, float *model);
 
 /* Starlet transform Phi^T (Eq. 6): coeffs = J planes of N^2; plane j < J-1 is
  * c_j - c_{j+1}, plane J-1 the coarse c_{J-1}; c_0 = img, c_{j+1} = H_j c_j with

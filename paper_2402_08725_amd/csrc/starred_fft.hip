@@ -1,0 +1,614 @@
+// FFT path of the deconvolution operators S_i and D (Eq. 8) and their adjoint.
+//
+// For a frame of fine side F = s n and kernel side K the linear 'same'
+// convolution equals a circular one of size P >= F + floor(K/2) (P a multiple of
+// 2s, P = 2^a 3^b 5^c). Fold the s x s block sum into the kernel
+// (kb = kernel embedded at its centre and box-summed), take S''(K) = DFT_P(kb) /
+// (s^2 Q^2) with Q = P/s; then the subsampled model is
+//     m = IDFT_Q( sum over the s^2 aliases K = k + (a,b) Q of S''(K) F(K) ),
+// where F is the spectrum of the scene. The scene spectrum is assembled from
+// the spectrum of the window of h (one transform per shape class) and rank-1
+// tables of the point sources and of the window indicator (Eq. 9). The adjoint
+// is g = window of IDFT_P( conj(S''(K)) rho_hat(K mod Q) ), rho_hat = DFT_Q(rho).
+// Transforms are unnormalised; every constant sits in S''.
+//
+// All 2-D transforms are row/column passes of batched 1-D Stockham FFTs
+// (radices 4, 2, 3, 5) staged in LDS; each pass is one launch over every frame
+// of every shape class (a table of line groups), with loads and stores that
+// fuse the spectral products, the Hermitian extensions, the crops and the
+// residual / chi-square epilogue.
+#include "starred_fft.h"
+
+#include <hip/hip_runtime.h>
+
+namespace starred {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b)  // a * conj(b)
+{
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// radix-R DFT of v in place; sign -1 forward (e^{-i}), +1 inverse
+template <int R>
+__device__ __forceinline__ void dft_small(float2 (&v)[5], bool inv);
+
+template <>
+__device__ __forceinline__ void dft_small<2>(float2 (&v)[5], bool)
+{
+    const float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<4>(float2 (&v)[5], bool inv)
+{
+    const float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    const float2 b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
+    // -i * b1 (forward) or +i * b1 (inverse)
+    const float2 rb1 = inv ? make_float2(-b1.y, b1.x) : make_float2(b1.y, -b1.x);
+    v[0] = cadd(a0, b0);
+    v[2] = csub(a0, b0);
+    v[1] = cadd(a1, rb1);
+    v[3] = csub(a1, rb1);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<3>(float2 (&v)[5], bool inv)
+{
+    const float c1 = -0.5f;
+    const float s1 = inv ? 0.86602540378443865f : -0.86602540378443865f;
+    const float2 a = v[0], b = v[1], c = v[2];
+    const float2 t = cadd(b, c), d = csub(b, c);
+    v[0] = cadd(a, t);
+    const float2 m = make_float2(a.x + c1 * t.x, a.y + c1 * t.y);
+    // s1 * i * d
+    const float2 id = make_float2(-s1 * d.y, s1 * d.x);
+    v[1] = cadd(m, id);
+    v[2] = csub(m, id);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<5>(float2 (&v)[5], bool inv)
+{
+    const float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
+    const float sg = inv ? 1.f : -1.f;
+    const float s1 = sg * 0.95105651629515357f, s2 = sg * 0.58778525229247313f;
+    const float2 a = v[0];
+    const float2 t1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
+    const float2 t2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
+    v[0] = cadd(a, cadd(t1, t2));
+    const float2 m1 = make_float2(a.x + c1 * t1.x + c2 * t2.x, a.y + c1 * t1.y + c2 * t2.y);
+    const float2 m2 = make_float2(a.x + c2 * t1.x + c1 * t2.x, a.y + c2 * t1.y + c1 * t2.y);
+    // i*(s1 d1 + s2 d2) and i*(s2 d1 - s1 d2)
+    const float2 u1 = make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
+    const float2 u2 = make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
+    const float2 iu1 = make_float2(-u1.y, u1.x), iu2 = make_float2(-u2.y, u2.x);
+    v[1] = cadd(m1, iu1);
+    v[4] = csub(m1, iu1);
+    v[2] = cadd(m2, iu2);
+    v[3] = csub(m2, iu2);
+}
+
+template <int R>
+__device__ __forceinline__ void stockham_stage(const float2 *__restrict__ src, float2 *__restrict__ dst,
+                                               int nl, int L, int Ns, const float2 *__restrict__ tw,
+                                               bool inv)
+{
+    const int LR = L / R;
+    const int twstep = L / (Ns * R);
+    for (int b = threadIdx.x; b < nl * LR; b += blockDim.x) {
+        const int l = b / LR, j = b - l * LR;
+        const float2 *in = src + l * L;
+        float2 *out = dst + l * L;
+        const int k = j % Ns;
+        float2 v[5];
+        #pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = in[j + r * LR];
+        if (Ns > 1) {
+            #pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const float2 t = tw[(r * k * twstep) % L];
+                v[r] = inv ? cmulc(v[r], t) : cmul(v[r], t);
+            }
+        }
+        dft_small<R>(v, inv);
+        const int idxD = (j / Ns) * Ns * R + k;
+        #pragma unroll
+        for (int r = 0; r < R; ++r) out[idxD + r * Ns] = v[r];
+    }
+}
+
+// 1-D FFTs of nl lines of length f.L held consecutively in LDS buffer a; b is
+// scratch of the same size. Returns the buffer that holds the result.
+__device__ float2 *lds_fft(float2 *a, float2 *b, int nl, const FftLen &f, const float2 *__restrict__ tw,
+                           bool inv)
+{
+    int Ns = 1;
+    for (int st = 0; st < f.nst; ++st) {
+        const int R = f.rad[st];
+        if (R == 4) stockham_stage<4>(a, b, nl, f.L, Ns, tw, inv);
+        else if (R == 2) stockham_stage<2>(a, b, nl, f.L, Ns, tw, inv);
+        else if (R == 3) stockham_stage<3>(a, b, nl, f.L, Ns, tw, inv);
+        else stockham_stage<5>(a, b, nl, f.L, Ns, tw, inv);
+        __syncthreads();
+        float2 *t = a;
+        a = b;
+        b = t;
+        Ns *= R;
+    }
+    return a;
+}
+
+// --------------------------------------------------------------------------
+// Generic line pass: load -> FFT -> store, for a table of line groups
+// --------------------------------------------------------------------------
+
+template <class Op>
+__global__ __launch_bounds__(kFftThreads) void k_lines(const LineItem *__restrict__ items,
+                                                       const ClassFft *__restrict__ classes,
+                                                       const float2 *__restrict__ tw, Op op)
+{
+    extern __shared__ float2 sm[];
+    const LineItem it = items[blockIdx.x];
+    const ClassFft &cl = classes[it.cls];
+    const FftLen f = op.len(cl);
+    float2 *a = sm;
+    float2 *b = sm + it.nl * f.L;
+    const int tot = it.nl * f.L;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int l = e / f.L, j = e - l * f.L;
+        a[e] = op.load(cl, it.frame, it.line0 + l, j);
+    }
+    __syncthreads();
+    float2 *r = lds_fft(a, b, it.nl, f, tw + f.tw_off, op.inverse);
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int l = e / f.L, j = e - l * f.L;
+        op.store(cl, it.frame, it.line0 + l, j, r[e]);
+    }
+}
+
+// Half-spectrum access with Hermitian symmetry: X is [P][P/2+1]; returns X(ky, kx)
+// for any kx in [0, P).
+__device__ __forceinline__ float2 half_get(const float2 *__restrict__ X, int P, int ky, int kx)
+{
+    const int H = P / 2 + 1;
+    if (kx < H) return X[(long long)ky * H + kx];
+    const int ky2 = ky == 0 ? 0 : P - ky;
+    return conjf2(X[(long long)ky2 * H + (P - kx)]);
+}
+
+// ---- pass A: rows of the h window of each class (real -> half spectrum) ----
+struct OpHRows {
+    const float *h;
+    int N;
+    float2 *Th;
+    static constexpr bool inverse = false;
+    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ float2 load(const ClassFft &c, int, int y, int x) const
+    {
+        return make_float2(x < c.F ? h[(long long)(c.o + y) * N + c.o + x] : 0.f, 0.f);
+    }
+    __device__ void store(const ClassFft &c, int, int y, int kx, float2 v) const
+    {
+        const int H = c.P / 2 + 1;
+        if (kx < H) Th[c.th_off + (long long)y * H + kx] = v;
+    }
+};
+
+// ---- pass B: columns -> H_hat[P][P/2+1] ----
+struct OpHCols {
+    const float2 *Th;
+    float2 *Hh;
+    static constexpr bool inverse = false;
+    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ float2 load(const ClassFft &c, int, int kx, int y) const
+    {
+        const int H = c.P / 2 + 1;
+        return y < c.F ? Th[c.th_off + (long long)y * H + kx] : make_float2(0.f, 0.f);
+    }
+    __device__ void store(const ClassFft &c, int, int kx, int ky, float2 v) const
+    {
+        const int H = c.P / 2 + 1;
+        Hh[c.hh_off + (long long)ky * H + kx] = v;
+    }
+};
+
+// ---- set_frames: kernel spectra. Rows of kb, kb(y,x) = sum_{al,be<s} kt((y+al+kap)%P, (x+be+kap)%P)
+struct OpKRows {
+    const FrameFft *fr;
+    const float *psf;
+    int s;
+    float2 *TS;
+    static constexpr bool inverse = false;
+    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ float2 load(const ClassFft &c, int i, int y, int x) const
+    {
+        const FrameFft &f = fr[i];
+        const int P = c.P, K = c.K, kap = K / 2;
+        const float *k = psf + f.kern_off;
+        float acc = 0.f;
+        for (int al = 0; al < s; ++al) {
+            const int v = (y + al + kap) % P;
+            if (v >= K) continue;
+            for (int be = 0; be < s; ++be) {
+                const int u = (x + be + kap) % P;
+                if (u < K) acc += k[v * K + u];
+            }
+        }
+        return make_float2(acc, 0.f);
+    }
+    __device__ void store(const ClassFft &c, int i, int y, int kx, float2 v) const
+    {
+        const int H = c.P / 2 + 1;
+        if (kx < H) TS[fr[i].t3_off + (long long)y * H + kx] = v;
+    }
+};
+
+struct OpKCols {
+    const FrameFft *fr;
+    const float2 *TS;
+    float2 *S;
+    static constexpr bool inverse = false;
+    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ float2 load(const ClassFft &c, int i, int kx, int y) const
+    {
+        const int H = c.P / 2 + 1;
+        return TS[fr[i].t3_off + (long long)y * H + kx];
+    }
+    __device__ void store(const ClassFft &c, int i, int kx, int ky, float2 v) const
+    {
+        const int H = c.P / 2 + 1;
+        S[fr[i].s_off + (long long)ky * H + kx] = cscale(v, c.sscale);
+    }
+};
+
+// ---- pass D: forward spectral product + alias fold + inverse along ky ----
+struct OpFwdCols {
+    const FrameFft *fr;
+    const float2 *S;
+    const float2 *Hh;
+    const float2 *tab;
+    const float *params;
+    int N, E, M, s;
+    float2 *T;
+    const float2 *scene_spec;  // per-frame scene spectra (standalone operator) or NULL
+    static constexpr bool inverse = true;
+    __device__ FftLen len(const ClassFft &c) const { return c.fQ; }
+    // scene spectrum at K (any Kx in [0,P)): Gamma w(Ky) w(Kx) + H(K) + sum_k a g_y(Ky) g_x(Kx)
+    __device__ float2 scene_hat(const ClassFft &c, int i, int Ky, int Kx) const
+    {
+        const int P = c.P;
+        if (scene_spec) return half_get(scene_spec + fr[i].t3_off, P, Ky, Kx);
+        const float2 *t = tab + c.tab_off;
+        float2 v = half_get(Hh + c.hh_off, P, Ky, Kx);
+        const float G = params[(long long)N * N + i];
+        v = cadd(v, cscale(cmul(t[Ky], t[Kx]), G));
+        const float *a = params + (long long)N * N + E + (long long)i * M;
+        for (int k = 0; k < M; ++k) {
+            const float2 *tk = t + (long long)(1 + 2 * k) * P;  // [gx | gy]
+            v = cadd(v, cscale(cmul(tk[P + Ky], tk[Kx]), a[k]));
+        }
+        return v;
+    }
+    __device__ float2 load(const ClassFft &c, int i, int kx, int ky) const
+    {
+        const FrameFft &f = fr[i];
+        const int P = c.P, Q = c.Q;
+        const float2 *Si = S + f.s_off;
+        float2 acc = make_float2(0.f, 0.f);
+        for (int al = 0; al < s; ++al)
+            for (int be = 0; be < s; ++be) {
+                const int Ky = ky + al * Q, Kx = kx + be * Q;
+                acc = cadd(acc, cmul(half_get(Si, P, Ky, Kx), scene_hat(c, i, Ky, Kx)));
+            }
+        return acc;
+    }
+    __device__ void store(const ClassFft &c, int i, int kx, int y, float2 v) const
+    {
+        const int H = c.Q / 2 + 1;
+        if (y < c.n) T[fr[i].t_off + (long long)y * H + kx] = v;
+    }
+};
+
+// ---- pass F: forward along ky of the rho row spectra -> rho_hat[Q][Q/2+1] ----
+struct OpRhoCols {
+    const FrameFft *fr;
+    const float2 *T2;
+    float2 *Rh;
+    static constexpr bool inverse = false;
+    __device__ FftLen len(const ClassFft &c) const { return c.fQ; }
+    __device__ float2 load(const ClassFft &c, int i, int kx, int y) const
+    {
+        const int H = c.Q / 2 + 1;
+        return y < c.n ? T2[fr[i].t_off + (long long)y * H + kx] : make_float2(0.f, 0.f);
+    }
+    __device__ void store(const ClassFft &c, int i, int kx, int ky, float2 v) const
+    {
+        const int H = c.Q / 2 + 1;
+        Rh[fr[i].r_off + (long long)ky * H + kx] = v;
+    }
+};
+
+// ---- pass G: conj(S'') * rho_hat(K mod Q), inverse along Ky, crop rows < F ----
+struct OpAdjCols {
+    const FrameFft *fr;
+    const float2 *S;
+    const float2 *Rh;
+    float2 *T3;
+    static constexpr bool inverse = true;
+    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ float2 load(const ClassFft &c, int i, int Kx, int Ky) const
+    {
+        const FrameFft &f = fr[i];
+        const int P = c.P, Q = c.Q, HP = P / 2 + 1;
+        const float2 sv = S[f.s_off + (long long)Ky * HP + Kx];
+        const int ky = Ky % Q, kx = Kx % Q;
+        const float2 rv = half_get(Rh + f.r_off, Q, ky, kx);
+        return cmulc(rv, sv);
+    }
+    __device__ void store(const ClassFft &c, int i, int Kx, int y, float2 v) const
+    {
+        const int H = c.P / 2 + 1;
+        if (y < c.F) T3[fr[i].t3_off + (long long)y * H + Kx] = v;
+    }
+};
+
+// ---- pass H: rows, Hermitian extension, inverse, crop x < F -> g_i ----
+struct OpAdjRows {
+    const FrameFft *fr;
+    const float2 *T3;
+    float *g;
+    static constexpr bool inverse = true;
+    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ float2 load(const ClassFft &c, int i, int y, int Kx) const
+    {
+        const int P = c.P, H = P / 2 + 1;
+        const float2 *row = T3 + fr[i].t3_off + (long long)y * H;
+        return Kx < H ? row[Kx] : conjf2(row[P - Kx]);
+    }
+    __device__ void store(const ClassFft &c, int i, int y, int x, float2 v) const
+    {
+        if (x < c.F) g[fr[i].fine_off + (long long)y * c.F + x] = v.x;
+    }
+};
+
+// ---- standalone adjoint: rows of a given residual -> T2 ----
+struct OpResidRows {
+    const FrameFft *fr;
+    const float *resid;
+    float2 *T2;
+    static constexpr bool inverse = false;
+    __device__ FftLen len(const ClassFft &c) const { return c.fQ; }
+    __device__ float2 load(const ClassFft &c, int i, int y, int x) const
+    {
+        return make_float2(x < c.n ? resid[fr[i].data_off + (long long)y * c.n + x] : 0.f, 0.f);
+    }
+    __device__ void store(const ClassFft &c, int i, int y, int kx, float2 v) const
+    {
+        const int H = c.Q / 2 + 1;
+        if (kx < H) T2[fr[i].t_off + (long long)y * H + kx] = v;
+    }
+};
+
+// ---- standalone forward: spectrum of a given scene, rows then columns in place ----
+struct OpSceneRows {
+    const FrameFft *fr;
+    const float *scene;
+    float2 *T3;
+    static constexpr bool inverse = false;
+    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ float2 load(const ClassFft &c, int i, int y, int x) const
+    {
+        return make_float2(x < c.F ? scene[fr[i].fine_off + (long long)y * c.F + x] : 0.f, 0.f);
+    }
+    __device__ void store(const ClassFft &c, int i, int y, int kx, float2 v) const
+    {
+        const int H = c.P / 2 + 1;
+        if (kx < H) T3[fr[i].t3_off + (long long)y * H + kx] = v;
+    }
+};
+
+struct OpSceneCols {  // every column is read and written by the same work group
+    const FrameFft *fr;
+    float2 *T3;
+    static constexpr bool inverse = false;
+    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ float2 load(const ClassFft &c, int i, int kx, int y) const
+    {
+        const int H = c.P / 2 + 1;
+        return y < c.F ? T3[fr[i].t3_off + (long long)y * H + kx] : make_float2(0.f, 0.f);
+    }
+    __device__ void store(const ClassFft &c, int i, int kx, int ky, float2 v) const
+    {
+        const int H = c.P / 2 + 1;
+        T3[fr[i].t3_off + (long long)ky * H + kx] = v;
+    }
+};
+
+// ---- pass E: model rows (inverse), residual and chi-square, rho rows (forward) ----
+__global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__restrict__ items,
+                                                          const ClassFft *__restrict__ classes,
+                                                          const FrameFft *__restrict__ fr,
+                                                          const float2 *__restrict__ tw,
+                                                          const float2 *__restrict__ T,
+                                                          const float *__restrict__ data,
+                                                          const float *__restrict__ invvar,
+                                                          float2 *__restrict__ T2, float *model,
+                                                          double *__restrict__ part_chi)
+{
+    extern __shared__ float2 sm[];
+    __shared__ double red[kFftThreads / 64];
+    const LineItem it = items[blockIdx.x];
+    const ClassFft &c = classes[it.cls];
+    const FrameFft &f = fr[it.frame];
+    const FftLen fl = c.fQ;
+    const int Q = c.Q, H = Q / 2 + 1, n = c.n;
+    float2 *a = sm;
+    float2 *b = sm + it.nl * Q;
+    const int tot = it.nl * Q;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int l = e / Q, kx = e - l * Q;
+        const float2 *row = T + f.t_off + (long long)(it.line0 + l) * H;
+        a[e] = kx < H ? row[kx] : conjf2(row[Q - kx]);
+    }
+    __syncthreads();
+    float2 *r = lds_fft(a, b, it.nl, fl, tw + fl.tw_off, true);
+    float2 *o = (r == a) ? b : a;
+    double chi = 0.0;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int l = e / Q, x = e - l * Q;
+        const int y = it.line0 + l;
+        float v = 0.f;
+        if (x < n) {
+            const long long idx = f.data_off + (long long)y * n + x;
+            const float m = r[e].x;
+            if (model) {
+                model[idx] = m;
+            } else {
+                const float res = m - data[idx];
+                const float w = invvar[idx];
+                v = w * res;
+                chi += 0.5 * (double)w * (double)res * (double)res;
+            }
+        }
+        o[e] = make_float2(v, 0.f);
+    }
+    const double tchi = block_sum_d_fft(chi, red);
+    if (threadIdx.x == 0 && part_chi) part_chi[blockIdx.x] = tchi;
+    if (model) return;
+    __syncthreads();
+    float2 *q = lds_fft(o, r, it.nl, fl, tw + fl.tw_off, false);
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int l = e / Q, kx = e - l * Q;
+        if (kx < H) T2[f.t_off + (long long)(it.line0 + l) * H + kx] = q[e];
+    }
+}
+
+// ---- per-eval tables: window indicator and point-source factors ----
+// tab[c]: [w (P) | for each source k: gx (P), gy (P)], the 1-D DFTs of the
+// window indicator and of g(x + o - c) over the frame (r = g(dx) g(dy), Eq. 9).
+__global__ void k_tables(const ClassFft *__restrict__ classes, const float2 *__restrict__ tw,
+                         const float *__restrict__ params, int N, int E, int M, float sigma,
+                         float2 *__restrict__ tab)
+{
+    const ClassFft &c = classes[blockIdx.x];
+    const int P = c.P;
+    const float2 *twP = tw + c.fP.tw_off;
+    float2 *t = tab + c.tab_off;
+    const float *cc = params + (long long)N * N + E + (long long)E * M;
+    const float inv2s2 = 1.0f / (2.0f * sigma * sigma);
+    const float norm = 1.0f / (2.50662827463100050f * sigma);  // 1/(sqrt(2 pi) sigma)
+    const int nent = (1 + 2 * M) * P;
+    for (int e = threadIdx.x + blockIdx.y * blockDim.x; e < nent; e += blockDim.x * gridDim.y) {
+        const int which = e / P, K = e - which * P;
+        if (which == 0) continue;  // the window factor is static, written at plan creation
+        const int k = (which - 1) / 2, part = (which - 1) % 2;
+        const float ctr = cc[2 * k + part];
+        const int lo = max(0, (int)ceilf(ctr - c.o - kGaussRadius));
+        const int hi = min(c.F - 1, (int)floorf(ctr - c.o + kGaussRadius));
+        float2 acc = make_float2(0.f, 0.f);
+        for (int x = lo; x <= hi; ++x) {
+            const float d = (float)(x + c.o) - ctr;
+            const float g = norm * expf(-d * d * inv2s2);
+            const float2 w = twP[(int)(((long long)K * x) % P)];
+            acc.x += g * w.x;
+            acc.y += g * w.y;
+        }
+        t[e] = acc;
+    }
+}
+
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+
+template <class Op>
+static hipError_t run_lines(hipStream_t st, const LinePass &lp, const ClassFft *classes, const float2 *tw,
+                            const Op &op)
+{
+    if (lp.n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_lines<Op>), dim3(lp.n_items), dim3(kFftThreads), lp.lds_bytes, st, lp.items,
+                       classes, tw, op);
+    return hipGetLastError();
+}
+
+hipError_t fft_prep_kernels(hipStream_t st, const FftPlanDev &d, const float *psf, int s)
+{
+    hipError_t e = run_lines(st, d.krows, d.classes, d.tw, OpKRows{d.frames, psf, s, d.T3});
+    if (e != hipSuccess) return e;
+    return run_lines(st, d.kcols, d.classes, d.tw, OpKCols{d.frames, d.T3, d.S});
+}
+
+hipError_t fft_spectra(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M,
+                       float sigma)
+{
+    hipError_t e = run_lines(st, d.hrows, d.classes, d.tw, OpHRows{params, N, d.Th});
+    if (e != hipSuccess) return e;
+    e = run_lines(st, d.hcols, d.classes, d.tw, OpHCols{d.Th, d.Hh});
+    if (e != hipSuccess) return e;
+    if (M > 0) {
+        hipLaunchKernelGGL(k_tables, dim3(d.n_classes, 4), dim3(256), 0, st, d.classes, d.tw, params, N, E, M,
+                           sigma, d.tab);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t fft_forward(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,
+                       const float *data, const float *invvar, double *part_chi, float *model)
+{
+    hipError_t e = run_lines(st, d.fcols, d.classes, d.tw,
+                             OpFwdCols{d.frames, d.S, d.Hh, d.tab, params, N, E, M, s, d.T, nullptr});
+    if (e != hipSuccess) return e;
+    if (d.frows.n_items > 0) {
+        hipLaunchKernelGGL(k_fwd_rows, dim3(d.frows.n_items), dim3(kFftThreads), d.frows.lds_bytes, st,
+                           d.frows.items, d.classes, d.frames, d.tw, d.T, data, invvar, d.T2, model, part_chi);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t fft_scene_model(hipStream_t st, const FftPlanDev &d, const float *scene, int s, float *model)
+{
+    // the kernel spectra are indexed like the row passes over P lines
+    hipError_t e = run_lines(st, d.srows, d.classes, d.tw, OpSceneRows{d.frames, scene, d.T3});
+    if (e != hipSuccess) return e;
+    e = run_lines(st, d.scols, d.classes, d.tw, OpSceneCols{d.frames, d.T3});
+    if (e != hipSuccess) return e;
+    e = run_lines(st, d.fcols, d.classes, d.tw,
+                  OpFwdCols{d.frames, d.S, d.Hh, d.tab, nullptr, 0, 0, 0, s, d.T, d.T3});
+    if (e != hipSuccess) return e;
+    if (d.frows.n_items > 0) {
+        hipLaunchKernelGGL(k_fwd_rows, dim3(d.frows.n_items), dim3(kFftThreads), d.frows.lds_bytes, st,
+                           d.frows.items, d.classes, d.frames, d.tw, d.T, nullptr, nullptr, d.T2, model,
+                           nullptr);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t fft_resid_rows(hipStream_t st, const FftPlanDev &d, const float *resid)
+{
+    return run_lines(st, d.rrows, d.classes, d.tw, OpResidRows{d.frames, resid, d.T2});
+}
+
+hipError_t fft_adjoint(hipStream_t st, const FftPlanDev &d, float *g)
+{
+    hipError_t e = run_lines(st, d.rcols, d.classes, d.tw, OpRhoCols{d.frames, d.T2, d.Rh});
+    if (e != hipSuccess) return e;
+    e = run_lines(st, d.acols, d.classes, d.tw, OpAdjCols{d.frames, d.S, d.Rh, d.T3});
+    if (e != hipSuccess) return e;
+    return run_lines(st, d.arows, d.classes, d.tw, OpAdjRows{d.frames, d.T3, g});
+}
+
+}  // namespace starred

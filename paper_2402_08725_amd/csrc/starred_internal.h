@@ -53,6 +53,10 @@ constexpr int kFwdThreads = kFwdTP * kFwdTQ / 4;
 constexpr int kAdjThreads = kAdjTP * kAdjTQ / 4;
 
 constexpr int kGaussRadius = 8;  // r is evaluated within +-8 fine px of c_k
+constexpr size_t kMaxLds = 160 * 1024;
+
+size_t fwd_lds_bytes(int s, int Tmax);
+size_t adj_lds_bytes(int Ar_max, int Bpad_max);
 
 // ---- kernel launchers (starred_kernels.hip) ----
 hipError_t launch_prep_kernels(hipStream_t st, const FrameDev *fr_dev, const FrameDev *fr_host,
@@ -86,19 +90,22 @@ hipError_t launch_adam(hipStream_t st, long long P, const long long *seg_end, co
 
 hipError_t launch_fill(hipStream_t st, float *p, long long n, float v);
 
-// PSF mode
+// PSF mode (starred_psf.hip)
 hipError_t launch_psf_render(hipStream_t st, int N, const float *params, float *s_out);
-hipError_t launch_psf_fwd(hipStream_t st, int S, int n, int ss, int N, float sigma,
-                          const float *params, const float *s_img, const float *data,
-                          const float *invvar, float *rho, double *part_chi, float *gpart);
-hipError_t launch_psf_adj(hipStream_t st, int S, int n, int ss, int N, float sigma,
-                          const float *params, const float *rho, float *gstar);
-hipError_t launch_psf_finalize(hipStream_t st, int S, int N, const float *params,
-                               const float *gstar, const float *prior, const float *gpart,
-                               float *grad, double *part_eta);
-hipError_t launch_psf_finalize_small(hipStream_t st, int S, int n_chi, const double *part_chi,
-                                     int n_l1, const double *part_l1, double lambda,
-                                     int n_eta_blocks, const double *part_eta, float *grad,
+hipError_t launch_psf_fwd(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
+                          const float *s_img, const float *data, const float *invvar, float *rho,
+                          double *part_chi, float *grad);
+hipError_t launch_psf_model(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
+                            const float *s_img, float *model);
+hipError_t launch_psf_adj(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
+                          const float *rho, float *gstar);
+hipError_t launch_psf_sum(hipStream_t st, int S, int N, const float *params, const float *gstar,
+                          const float *prior, float *grad, double *part_eta);
+hipError_t launch_psf_finalize_small(hipStream_t st, int S, int n_chi, const double *part_chi, int n_l1,
+                                     const double *part_l1, int n_eta, const double *part_eta, float *grad,
                                      double *loss);
+int psf_sum_blocks(int N);
+size_t psf_fwd_lds(int n, int N);
+size_t psf_adj_lds(int n, int N);
 
 }  // namespace starred

@@ -1,12 +1,15 @@
 // Host side of the C ABI (include/starred.h): plan validation, frame tables,
 // work lists, scratch ownership and the launch sequences of loss_grad / step.
 #include "starred.h"
+#include "starred_fft.h"
 #include "starred_internal.h"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -77,6 +80,20 @@ struct starred_plan {
     float *d_grad = nullptr;
     float *d_wzero = nullptr;
     std::vector<void *> owned;
+
+    // FFT path
+    bool fft_ready = false;
+    FftPlanDev fd;
+    std::vector<ClassFft> cls;
+    std::vector<FrameFft> ffr;
+    double *d_part_chi_fft = nullptr;
+    // PSF mode
+    int psf_n = 0;
+    float *d_simg = nullptr, *d_gstar = nullptr;
+    double *d_part_eta = nullptr;
+    int algo_req = STARRED_CONV_AUTO;
+    bool direct_ok = true;
+    double tune_ms[3] = {0, 0, 0};
 
     // stage timing
     bool prof_on = false;
@@ -171,6 +188,10 @@ static int validate(const starred_desc *d)
     if (d->mode == STARRED_DECONV) {
         if (d->conv_algo < STARRED_CONV_AUTO || d->conv_algo > STARRED_CONV_FFT)
             return fail(STARRED_EINVAL, "unknown conv_algo");
+    } else {
+        for (int i = 0; i < d->n_frames; ++i)
+            if (d->side_host[i] * d->subsample != d->grid_side)
+                return fail(STARRED_EINVAL, "PSF mode: every star stamp must have side grid_side/subsample");
     }
     return STARRED_OK;
 }
@@ -274,13 +295,227 @@ static int build_deconv(starred_plan *p)
     return STARRED_OK;
 }
 
+// ---- FFT path: shape classes, transform lengths, line passes ----
+
+static bool smooth235(int v)
+{
+    for (int f : {2, 3, 5})
+        while (v % f == 0) v /= f;
+    return v == 1;
+}
+
+// smallest P >= need with P a multiple of 2s and P = 2^a 3^b 5^c
+static int good_size(int need, int s)
+{
+    for (int P = need;; ++P)
+        if (P % (2 * s) == 0 && smooth235(P)) return P;
+}
+
+static FftLen make_len(int L, std::map<int, long long> &tw_offsets, long long &tw_total)
+{
+    FftLen f;
+    memset(&f, 0, sizeof f);
+    f.L = L;
+    int v = L;
+    while (v % 4 == 0) { f.rad[f.nst++] = 4; v /= 4; }
+    while (v % 2 == 0) { f.rad[f.nst++] = 2; v /= 2; }
+    while (v % 3 == 0) { f.rad[f.nst++] = 3; v /= 3; }
+    while (v % 5 == 0) { f.rad[f.nst++] = 5; v /= 5; }
+    auto it = tw_offsets.find(L);
+    if (it == tw_offsets.end()) {
+        tw_offsets[L] = tw_total;
+        f.tw_off = tw_total;
+        tw_total += L;
+    } else {
+        f.tw_off = it->second;
+    }
+    return f;
+}
+
+static int build_fft(starred_plan *p)
+{
+    const int s = p->s, E = p->E;
+    std::map<std::pair<int, int>, int> cls_of;  // (n, K) -> class
+    std::map<int, long long> tw_off;
+    long long tw_total = 0;
+    std::vector<int> fcls(E);
+    for (int i = 0; i < E; ++i) {
+        auto key = std::make_pair(p->n[i], p->K[i]);
+        auto it = cls_of.find(key);
+        if (it == cls_of.end()) {
+            ClassFft c;
+            memset(&c, 0, sizeof c);
+            c.n = p->n[i];
+            c.F = s * c.n;
+            c.K = p->K[i];
+            c.o = (p->N - c.F) / 2;
+            c.P = good_size(c.F + c.K / 2, s);
+            c.Q = c.P / s;
+            if (c.P > 4096) return fail(STARRED_EUNSUPPORTED, "FFT size above 4096");
+            c.fP = make_len(c.P, tw_off, tw_total);
+            c.fQ = make_len(c.Q, tw_off, tw_total);
+            c.sscale = (float)(1.0 / ((double)s * s * (double)c.Q * c.Q));
+            cls_of[key] = (int)p->cls.size();
+            p->cls.push_back(c);
+            fcls[i] = (int)p->cls.size() - 1;
+        } else {
+            fcls[i] = it->second;
+        }
+    }
+    const int M = p->M;
+    long long th = 0, hh = 0, tb = 0;
+    for (auto &c : p->cls) {
+        const long long HP = c.P / 2 + 1;
+        c.th_off = th;
+        th += (long long)c.F * HP;
+        c.hh_off = hh;
+        hh += (long long)c.P * HP;
+        c.tab_off = tb;
+        tb += (long long)(1 + 2 * M) * c.P;
+    }
+    p->ffr.resize(E);
+    long long so = 0, to = 0, ro = 0, t3o = 0;
+    for (int i = 0; i < E; ++i) {
+        const ClassFft &c = p->cls[fcls[i]];
+        FrameFft &f = p->ffr[i];
+        memset(&f, 0, sizeof f);
+        f.cls = fcls[i];
+        f.kern_off = p->fr[i].kern_off;
+        f.data_off = p->fr[i].data_off;
+        f.fine_off = p->fr[i].fine_off;
+        const long long HP = c.P / 2 + 1, HQ = c.Q / 2 + 1;
+        f.s_off = so;
+        so += (long long)c.P * HP;
+        f.t_off = to;
+        to += (long long)c.n * HQ;
+        f.r_off = ro;
+        ro += (long long)c.Q * HQ;
+        f.t3_off = t3o;
+        t3o += (long long)c.P * HP;
+    }
+    int rc;
+    FftPlanDev &d = p->fd;
+    d.n_classes = (int)p->cls.size();
+    if ((rc = p->alloc(&d.classes, p->cls.size()))) return rc;
+    if ((rc = p->alloc(&d.frames, E))) return rc;
+    if ((rc = p->alloc(&d.tw, tw_total))) return rc;
+    if ((rc = p->alloc(&d.S, so))) return rc;
+    if ((rc = p->alloc(&d.T, to))) return rc;
+    if ((rc = p->alloc(&d.T2, to))) return rc;
+    if ((rc = p->alloc(&d.Rh, ro))) return rc;
+    if ((rc = p->alloc(&d.T3, t3o))) return rc;
+    if ((rc = p->alloc(&d.Th, th))) return rc;
+    if ((rc = p->alloc(&d.Hh, hh))) return rc;
+    if ((rc = p->alloc(&d.tab, tb))) return rc;
+
+    // twiddles e^{-2 pi i m / L} rounded from double
+    std::vector<float2> tw(tw_total);
+    for (auto &kv : tw_off)
+        for (int m = 0; m < kv.first; ++m) {
+            const double a = -2.0 * M_PI * m / kv.first;
+            tw[kv.second + m] = make_float2((float)std::cos(a), (float)std::sin(a));
+        }
+    // static window factor of every class: w(K) = sum_{x < F} e^{-2 pi i K x / P}
+    std::vector<float2> tabh(tb, make_float2(0.f, 0.f));
+    for (auto &c : p->cls)
+        for (int K = 0; K < c.P; ++K) {
+            std::complex<double> acc = 0.0;
+            for (int x = 0; x < c.F; ++x) {
+                const long long m = ((long long)K * x) % c.P;
+                acc += std::polar(1.0, -2.0 * M_PI * (double)m / c.P);
+            }
+            tabh[c.tab_off + K] = make_float2((float)acc.real(), (float)acc.imag());
+        }
+    HIP_TRY(hipMemcpy(d.classes, p->cls.data(), sizeof(ClassFft) * p->cls.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.frames, p->ffr.data(), sizeof(FrameFft) * E, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.tw, tw.data(), sizeof(float2) * tw_total, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.tab, tabh.data(), sizeof(float2) * tb, hipMemcpyHostToDevice));
+
+    // line passes: groups of lines of one frame (or class), longest transforms first
+    auto make_pass = [&](LinePass &lp, bool per_class, auto lines_of, auto len_of) -> int {
+        struct G { int L; LineItem it; };
+        std::vector<G> g;
+        const int nunits = per_class ? (int)p->cls.size() : E;
+        int maxL = 1;
+        for (int u = 0; u < nunits; ++u) {
+            const int c = per_class ? u : fcls[u];
+            const ClassFft &cl = p->cls[c];
+            const int L = len_of(cl);
+            const int lines = lines_of(cl);
+            const int lpw = std::max(1, kFftTargetElems / L);
+            maxL = std::max(maxL, L * lpw);
+            for (int l0 = 0; l0 < lines; l0 += lpw)
+                g.push_back({L, LineItem{c, per_class ? -1 : u, l0, std::min(lpw, lines - l0)}});
+        }
+        std::stable_sort(g.begin(), g.end(), [](const G &a, const G &b) { return a.L > b.L; });
+        std::vector<LineItem> items;
+        for (auto &x : g) items.push_back(x.it);
+        lp.n_items = (int)items.size();
+        lp.lds_bytes = (size_t)2 * maxL * sizeof(float2);
+        int rc2 = p->alloc(&lp.items, items.size());
+        if (rc2) return rc2;
+        if (!items.empty()) {
+            hipError_t e = hipMemcpy(lp.items, items.data(), sizeof(LineItem) * items.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return fail_hip(e, "hipMemcpy(line items)");
+        }
+        return STARRED_OK;
+    };
+    auto LP = [](const ClassFft &c) { return c.P; };
+    auto LQ = [](const ClassFft &c) { return c.Q; };
+    if ((rc = make_pass(d.hrows, true, [](const ClassFft &c) { return c.F; }, LP))) return rc;
+    if ((rc = make_pass(d.hcols, true, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
+    if ((rc = make_pass(d.krows, false, [](const ClassFft &c) { return c.P; }, LP))) return rc;
+    if ((rc = make_pass(d.kcols, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
+    if ((rc = make_pass(d.fcols, false, [](const ClassFft &c) { return c.Q / 2 + 1; }, LQ))) return rc;
+    if ((rc = make_pass(d.frows, false, [](const ClassFft &c) { return c.n; }, LQ))) return rc;
+    if ((rc = make_pass(d.rrows, false, [](const ClassFft &c) { return c.n; }, LQ))) return rc;
+    if ((rc = make_pass(d.rcols, false, [](const ClassFft &c) { return c.Q / 2 + 1; }, LQ))) return rc;
+    if ((rc = make_pass(d.acols, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
+    if ((rc = make_pass(d.arows, false, [](const ClassFft &c) { return c.F; }, LP))) return rc;
+    if ((rc = make_pass(d.srows, false, [](const ClassFft &c) { return c.F; }, LP))) return rc;
+    if ((rc = make_pass(d.scols, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
+    if ((rc = p->alloc(&p->d_part_chi_fft, std::max(1, d.frows.n_items)))) return rc;
+    p->fft_ready = true;
+    return STARRED_OK;
+}
+
+static int build_psf(starred_plan *p)
+{
+    const int S = p->E, n = p->n[0], N = p->N;
+    p->psf_n = n;
+    p->nparams = 5 + (long long)N * N + 3LL * S;
+    p->ndata = (long long)S * n * n;
+    p->nfine = (long long)N * N;
+    const long long NN = (long long)N * N;
+    const int nb_star = (int)((NN + 255) / 256);
+    if (psf_fwd_lds(n, N) > kMaxLds) return fail(STARRED_EUNSUPPORTED, "PSF grid too large for one work group");
+    int rc;
+    if ((rc = p->alloc(&p->d_simg, NN))) return rc;
+    if ((rc = p->alloc(&p->d_rho, p->ndata))) return rc;
+    if ((rc = p->alloc(&p->d_gstar, (size_t)S * NN))) return rc;
+    if ((rc = p->alloc(&p->d_part_chi, S))) return rc;
+    if ((rc = p->alloc(&p->d_part_eta, (size_t)psf_sum_blocks(N) * 5))) return rc;
+    if ((rc = p->alloc(&p->d_part_l1, (size_t)std::max(1, p->J - 1) * nb_star))) return rc;
+    if ((rc = p->alloc(&p->d_z, (size_t)p->J * NN))) return rc;
+    if ((rc = p->alloc(&p->d_ca, NN))) return rc;
+    if ((rc = p->alloc(&p->d_cb, NN))) return rc;
+    if ((rc = p->alloc(&p->d_tmp, NN))) return rc;
+    if ((rc = p->alloc(&p->d_prior, NN))) return rc;
+    if ((rc = p->alloc(&p->d_grad, p->nparams))) return rc;
+    if ((rc = p->alloc(&p->d_wzero, (size_t)p->J * NN))) return rc;
+    HIP_TRY(hipMemset(p->d_wzero, 0, sizeof(float) * p->J * NN));
+    return STARRED_OK;
+}
+
+static int loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out);
+static int autotune(starred_plan *p);
+
 int starred_plan_create(const starred_desc *desc, void *stream, starred_plan **plan_out)
 {
     if (!plan_out) return fail(STARRED_EINVAL, "plan_out is NULL");
     *plan_out = nullptr;
     int rc = validate(desc);
     if (rc) return rc;
-    if (desc->mode == STARRED_PSF) return fail(STARRED_EUNSUPPORTED, "PSF mode is not available in this build");
     starred_plan *p = new starred_plan();
     p->mode = desc->mode;
     p->E = desc->n_frames;
@@ -295,15 +530,31 @@ int starred_plan_create(const starred_desc *desc, void *stream, starred_plan **p
     p->st = (hipStream_t)stream;
     p->n.assign(desc->side_host, desc->side_host + p->E);
     if (desc->ksize_host) p->K.assign(desc->ksize_host, desc->ksize_host + p->E);
-    p->algo = (desc->conv_algo == STARRED_CONV_FFT) ? STARRED_CONV_FFT : STARRED_CONV_DIRECT;
-    if (p->algo == STARRED_CONV_FFT) {
-        delete p;
-        return fail(STARRED_EUNSUPPORTED, "FFT convolution is not available in this build");
+    if (p->mode == STARRED_PSF) {
+        p->algo_req = p->algo = STARRED_CONV_DIRECT;
+        rc = build_psf(p);
+        if (rc) {
+            delete p;
+            return rc;
+        }
+        *plan_out = p;
+        return STARRED_OK;
     }
+    p->algo_req = desc->conv_algo;
+    p->algo = (desc->conv_algo == STARRED_CONV_FFT) ? STARRED_CONV_FFT : STARRED_CONV_DIRECT;
     rc = build_deconv(p);
+    if (!rc) rc = build_fft(p);
     if (rc) {
         delete p;
         return rc;
+    }
+    p->direct_ok = fwd_lds_bytes(p->s, p->Tmax) <= kMaxLds && adj_lds_bytes(p->Ar_max, p->Bpad_max) <= kMaxLds;
+    if (p->algo == STARRED_CONV_DIRECT && !p->direct_ok) {
+        if (p->algo_req == STARRED_CONV_DIRECT) {
+            delete p;
+            return fail(STARRED_EUNSUPPORTED, "kernels too large for the direct path's LDS tiles");
+        }
+        p->algo = STARRED_CONV_FFT;
     }
     *plan_out = p;
     return STARRED_OK;
@@ -332,15 +583,25 @@ int starred_set_frames(starred_plan *p, const float *data, const float *inv_var,
     p->data = data;
     p->invvar = inv_var;
     p->W = W;
+    if (p->mode == STARRED_PSF) {
+        p->frames_set = true;
+        return STARRED_OK;
+    }
     HIP_TRY(launch_prep_kernels(p->st, p->d_fr, p->fr.data(), p->E, p->s, psf, p->d_kf, p->d_ka));
+    if (p->fft_ready) HIP_TRY(fft_prep_kernels(p->st, p->fd, psf, p->s));
     HIP_TRY(hipStreamSynchronize(p->st));
     p->frames_set = true;
+    if (p->algo_req == STARRED_CONV_AUTO && p->direct_ok) return autotune(p);
     return STARRED_OK;
 }
 
 int starred_render_scene(starred_plan *p, const float *params, float *scene)
 {
     if (!p || !params || !scene) return fail(STARRED_EINVAL, "NULL argument");
+    if (p->mode == STARRED_PSF) {
+        HIP_TRY(launch_psf_render(p->st, p->N, params, scene));
+        return STARRED_OK;
+    }
     HIP_TRY(launch_render(p->st, p->d_fr, p->E, p->Fmax, p->N, p->M, p->sigma, params, scene));
     return STARRED_OK;
 }
@@ -348,7 +609,12 @@ int starred_render_scene(starred_plan *p, const float *params, float *scene)
 int starred_convolve_subsample(starred_plan *p, const float *scene, float *model)
 {
     if (!p || !scene || !model) return fail(STARRED_EINVAL, "NULL argument");
+    if (p->mode == STARRED_PSF) return fail(STARRED_EUNSUPPORTED, "deconvolution-mode operator called on a PSF-mode plan");
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
+    if (p->algo == STARRED_CONV_FFT) {
+        HIP_TRY(fft_scene_model(p->st, p->fd, scene, p->s, model));
+        return STARRED_OK;
+    }
     HIP_TRY(launch_fwd_direct(p->st, p->s, p->d_fr, p->d_fwd_items, (int)p->fwd_items.size(), p->Tmax,
                               scene, p->d_kf, nullptr, nullptr, model, nullptr));
     return STARRED_OK;
@@ -357,7 +623,13 @@ int starred_convolve_subsample(starred_plan *p, const float *scene, float *model
 int starred_convolve_subsample_adj(starred_plan *p, const float *resid, float *grad_scene)
 {
     if (!p || !resid || !grad_scene) return fail(STARRED_EINVAL, "NULL argument");
+    if (p->mode == STARRED_PSF) return fail(STARRED_EUNSUPPORTED, "deconvolution-mode operator called on a PSF-mode plan");
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
+    if (p->algo == STARRED_CONV_FFT) {
+        HIP_TRY(fft_resid_rows(p->st, p->fd, resid));
+        HIP_TRY(fft_adjoint(p->st, p->fd, grad_scene));
+        return STARRED_OK;
+    }
     HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ar_max,
                               p->Bpad_max, resid, p->d_ka, grad_scene));
     return STARRED_OK;
@@ -381,13 +653,31 @@ int starred_starlet_adj(starred_plan *p, const float *coeffs, float *img)
 
 static int loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out)
 {
-    hipEvent_t e0 = p->prof_start();
-    HIP_TRY(launch_render(p->st, p->d_fr, p->E, p->Fmax, p->N, p->M, p->sigma, params, p->d_scene));
-    p->prof_stop(STARRED_STAGE_RENDER, e0);
-    e0 = p->prof_start();
-    HIP_TRY(launch_fwd_direct(p->st, p->s, p->d_fr, p->d_fwd_items, (int)p->fwd_items.size(), p->Tmax,
-                              p->d_scene, p->d_kf, p->data, p->invvar, p->d_rho, p->d_part_chi));
-    p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
+    const bool fft = (p->algo == STARRED_CONV_FFT);
+    hipEvent_t e0;
+    int n_chi;
+    const double *part_chi;
+    if (fft) {
+        e0 = p->prof_start();
+        HIP_TRY(fft_spectra(p->st, p->fd, params, p->N, p->E, p->M, p->sigma));
+        p->prof_stop(STARRED_STAGE_SPECTRA, e0);
+        e0 = p->prof_start();
+        HIP_TRY(fft_forward(p->st, p->fd, params, p->N, p->E, p->M, p->s, p->data, p->invvar,
+                            p->d_part_chi_fft, nullptr));
+        p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
+        n_chi = p->fd.frows.n_items;
+        part_chi = p->d_part_chi_fft;
+    } else {
+        e0 = p->prof_start();
+        HIP_TRY(launch_render(p->st, p->d_fr, p->E, p->Fmax, p->N, p->M, p->sigma, params, p->d_scene));
+        p->prof_stop(STARRED_STAGE_RENDER, e0);
+        e0 = p->prof_start();
+        HIP_TRY(launch_fwd_direct(p->st, p->s, p->d_fr, p->d_fwd_items, (int)p->fwd_items.size(), p->Tmax,
+                                  p->d_scene, p->d_kf, p->data, p->invvar, p->d_rho, p->d_part_chi));
+        p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
+        n_chi = (int)p->fwd_items.size();
+        part_chi = p->d_part_chi;
+    }
     int n_l1 = 0;
     e0 = p->prof_start();
     HIP_TRY(launch_starlet_fwd(p->st, p->N, p->J, params, nullptr, grad ? p->d_z : nullptr, p->W, p->w_stride,
@@ -396,8 +686,11 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     p->prof_stop(STARRED_STAGE_STARLET, e0);
     if (grad) {
         e0 = p->prof_start();
-        HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ar_max,
-                                  p->Bpad_max, p->d_rho, p->d_ka, p->d_g));
+        if (fft)
+            HIP_TRY(fft_adjoint(p->st, p->fd, p->d_g));
+        else
+            HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ar_max,
+                                      p->Bpad_max, p->d_rho, p->d_ka, p->d_g));
         p->prof_stop(STARRED_STAGE_CONV_ADJ, e0);
         e0 = p->prof_start();
         HIP_TRY(launch_frame_sums(p->st, p->d_fr, p->E, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum));
@@ -405,9 +698,99 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     }
     e0 = p->prof_start();
     if (grad) HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad));
-    HIP_TRY(launch_finalize_small(p->st, p->E, p->M, (int)p->fwd_items.size(), p->d_part_chi, n_l1,
-                                  p->d_part_l1, p->lam, p->d_fsum, params, p->N, grad, loss_out));
+    HIP_TRY(launch_finalize_small(p->st, p->E, p->M, n_chi, part_chi, n_l1, p->d_part_l1, p->lam, p->d_fsum,
+                                  params, p->N, grad, loss_out));
     p->prof_stop(STARRED_STAGE_FINALIZE, e0);
+    return STARRED_OK;
+}
+
+// Autotuner: time the direct and the FFT algorithms on this plan's shapes
+// (one warm-up and three timed loss+gradient evaluations each, at h = 0) and
+// keep the faster one.
+static int autotune(starred_plan *p)
+{
+    float *params = nullptr;
+    double *loss = nullptr;
+    int rc = dev_alloc(&params, p->nparams);
+    if (rc) return rc;
+    rc = dev_alloc(&loss, 3);
+    if (rc) {
+        (void)hipFree(params);
+        return rc;
+    }
+    (void)hipMemsetAsync(params, 0, sizeof(float) * p->nparams, p->st);
+    const bool prof = p->prof_on;
+    p->prof_on = false;
+    hipEvent_t a = nullptr, b = nullptr;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    double best = 1e300;
+    int best_algo = STARRED_CONV_DIRECT;
+    const int algos[2] = {STARRED_CONV_DIRECT, STARRED_CONV_FFT};
+    for (int ai = 0; ai < 2 && !rc; ++ai) {
+        p->algo = algos[ai];
+        rc = loss_grad_impl(p, params, p->d_grad, loss);
+        if (rc) break;
+        (void)hipEventRecord(a, p->st);
+        for (int r = 0; r < 3 && !rc; ++r) rc = loss_grad_impl(p, params, p->d_grad, loss);
+        (void)hipEventRecord(b, p->st);
+        if (hipEventSynchronize(b) != hipSuccess) rc = fail(STARRED_EHIP, "autotune synchronisation");
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        p->tune_ms[algos[ai]] = ms / 3.0;
+        if (ms < best) {
+            best = ms;
+            best_algo = algos[ai];
+        }
+    }
+    p->algo = best_algo;
+    p->prof_on = prof;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFree(params);
+    (void)hipFree(loss);
+    return rc;
+}
+
+static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out)
+{
+    const int S = p->E, n = p->psf_n, N = p->N;
+    const long long NN = (long long)N * N;
+    hipEvent_t e0 = p->prof_start();
+    HIP_TRY(launch_psf_render(p->st, N, params, p->d_simg));
+    p->prof_stop(STARRED_STAGE_RENDER, e0);
+    e0 = p->prof_start();
+    HIP_TRY(launch_psf_fwd(p->st, S, n, p->s, N, p->sigma, params, p->d_simg, p->data, p->invvar, p->d_rho,
+                           p->d_part_chi, grad));
+    p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
+    int n_l1 = 0;
+    e0 = p->prof_start();
+    HIP_TRY(launch_starlet_fwd(p->st, N, p->J, params + 5, nullptr, grad ? p->d_z : nullptr, p->W, p->w_stride,
+                               (float)p->lam, p->d_ca, p->d_cb, p->d_tmp, p->d_part_l1, &n_l1));
+    if (grad) HIP_TRY(launch_starlet_adj(p->st, N, p->J, p->d_z, p->d_prior, p->d_ca, p->d_cb, p->d_tmp));
+    p->prof_stop(STARRED_STAGE_STARLET, e0);
+    if (grad) {
+        e0 = p->prof_start();
+        HIP_TRY(launch_psf_adj(p->st, S, n, p->s, N, p->sigma, params, p->d_rho, p->d_gstar));
+        p->prof_stop(STARRED_STAGE_CONV_ADJ, e0);
+        e0 = p->prof_start();
+        HIP_TRY(launch_psf_sum(p->st, S, N, params, p->d_gstar, p->d_prior, grad, p->d_part_eta));
+        p->prof_stop(STARRED_STAGE_GRAD_SUMS, e0);
+    }
+    e0 = p->prof_start();
+    HIP_TRY(launch_psf_finalize_small(p->st, S, S, p->d_part_chi, n_l1, p->d_part_l1, psf_sum_blocks(N),
+                                      p->d_part_eta, grad, loss_out));
+    p->prof_stop(STARRED_STAGE_FINALIZE, e0);
+    (void)NN;
+    return STARRED_OK;
+}
+
+int starred_psf_model(starred_plan *p, const float *params, float *model)
+{
+    if (!p || !params || !model) return fail(STARRED_EINVAL, "NULL argument");
+    if (p->mode != STARRED_PSF) return fail(STARRED_EUNSUPPORTED, "starred_psf_model needs a PSF-mode plan");
+    HIP_TRY(launch_psf_render(p->st, p->N, params, p->d_simg));
+    HIP_TRY(launch_psf_model(p->st, p->E, p->psf_n, p->s, p->N, p->sigma, params, p->d_simg, model));
     return STARRED_OK;
 }
 
@@ -415,6 +798,7 @@ int starred_loss_grad(starred_plan *p, const float *params, float *grad, double 
 {
     if (!p || !params || !loss_out) return fail(STARRED_EINVAL, "NULL argument");
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
+    if (p->mode == STARRED_PSF) return psf_loss_grad_impl(p, params, grad, loss_out);
     return loss_grad_impl(p, params, grad, loss_out);
 }
 
@@ -424,10 +808,16 @@ int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
     if (!p || !params || !m || !v || !hp) return fail(STARRED_EINVAL, "NULL argument");
     if (t < 1) return fail(STARRED_EINVAL, "t must be >= 1");
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
-    int rc = loss_grad_impl(p, params, p->d_grad, loss_out);
+    int rc = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, p->d_grad, loss_out)
+                                      : loss_grad_impl(p, params, p->d_grad, loss_out);
     if (rc) return rc;
     const long long NN = (long long)p->N * p->N;
     long long seg[3] = {NN, NN + p->E, NN + p->E + (long long)p->E * p->M};
+    if (p->mode == STARRED_PSF) {
+        seg[0] = 5;
+        seg[1] = 5 + NN;
+        seg[2] = 5 + NN + p->E;
+    }
     hipEvent_t e0 = p->prof_start();
     HIP_TRY(launch_adam(p->st, p->nparams, seg, hp->lr, params, p->d_grad, m, v, t, hp->beta1, hp->beta2,
                         hp->eps));

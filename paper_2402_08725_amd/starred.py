@@ -25,7 +25,7 @@ EXPORTED = [
     "starred_convolve_subsample", "starred_convolve_subsample_adj", "starred_starlet_fwd",
     "starred_starlet_adj", "starred_loss_grad", "starred_step", "starred_set_graph_mode",
     "starred_conv_algo", "starred_last_error", "starred_abi_version", "starred_set_profiling",
-    "starred_profile_read",
+    "starred_profile_read", "starred_psf_model",
 ]
 STAGES = ["render", "conv_fwd", "conv_adj", "grad_sums", "starlet", "finalize", "adam", "spectra"]
 
@@ -78,6 +78,7 @@ def lib():
         L.starred_last_error.restype = ctypes.c_char_p
         L.starred_set_profiling.argtypes = [vp, i32]
         L.starred_profile_read.argtypes = [vp, vp, vp]
+        L.starred_psf_model.argtypes = [vp, vp, vp]
         _lib = L
     return _lib
 
@@ -134,6 +135,18 @@ class Plan:
     def for_problem(cls, prob, conv_algo=CONV_AUTO, device="cuda:0", lam=None):
         return cls(DECONV, prob.n, prob.K, prob.s, prob.N, prob.M, prob.J,
                    prob.lam if lam is None else lam, prob.w_stride, prob.fwhm, conv_algo, device)
+
+    @classmethod
+    def for_psf(cls, prob, device="cuda:0", lam=None):
+        return cls(PSF, [prob.n] * prob.S, None, prob.s, prob.N, 0, prob.J,
+                   prob.lam if lam is None else lam, prob.w_stride, prob.fwhm, CONV_AUTO, device)
+
+    def psf_model(self, params):
+        """Star models m_k = D(s * a_k r_k) (PSF mode), packed S x n^2."""
+        params = _f32(params, self.device)
+        out = torch.empty(self.n_data, dtype=torch.float32, device=self.device)
+        self._call(lib().starred_psf_model, _ptr(params), _ptr(out))
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

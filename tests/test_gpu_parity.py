@@ -80,14 +80,20 @@ def test_render_scene(case):
     _check_frames(got, ref, [s * n for n in sides], 2e-6)
 
 
+ALGOS = [1, 2]  # direct, FFT
+ALGO_ID = {1: "direct", 2: "fft"}
+
+
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
 @pytest.mark.parametrize("case", SMALL, ids=lambda c: f"seed{c[0]}")
-def test_convolve_subsample_and_adjoint(case):
+def test_convolve_subsample_and_adjoint(case, algo):
     seed, E, sides, K, s, N, M, J = case
     prob = synth.make_small_deconv(seed, E, sides, K, s, N, M, J)
     d, w, rng = _data(prob)
-    plan = _plan(prob, d, w)
+    plan = _plan(prob, d, w, algo)
+    assert plan.conv_algo == algo
     scene = synth.f32(rng.standard_normal(prob.fine_size) * 100)
-    _say(f"conv {seed}")
+    _say(f"conv {seed} {ALGO_ID[algo]}")
     got = plan.convolve_subsample(scene).cpu().numpy()
     ref = ora.conv_sub(prob.n, prob.K, s, prob.kernels, scene)
     _check_frames(got, ref, sides, 1e-5)
@@ -149,23 +155,37 @@ LG_CASES = [
 ]
 
 
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
 @pytest.mark.parametrize("name,make", LG_CASES, ids=[c[0] for c in LG_CASES])
 @pytest.mark.parametrize("point", ["init", "near"])
-def test_loss_grad_parity(name, make, point):
+def test_loss_grad_parity(name, make, point, algo):
     prob = make()
     d, w, rng = _data(prob, seed=sum(map(ord, name)))
-    plan = _plan(prob, d, w)
+    plan = _plan(prob, d, w, algo)
     p = synth.eval_point(prob, point, rng)
-    _compare_loss_grad(prob, d, w, p, plan, f"{name}/{point}")
+    _compare_loss_grad(prob, d, w, p, plan, f"{name}/{point}/{ALGO_ID[algo]}")
 
 
-def test_loss_grad_cfg2_full_size():
+def test_loss_grad_cfg2_full_size_both_algorithms_and_autotune():
     prob = synth.make_deconv(2)
     _say("cfg2 full: oracle data")
     d, w, rng = _data(prob, seed=2)
-    plan = _plan(prob, d, w)
     p = synth.eval_point(prob, "near", rng)
-    _compare_loss_grad(prob, d, w, p, plan, "cfg2/full/near")
+    NN = prob.N * prob.N
+    so, _ = parity.tie_override(prob.N, prob.J, p[:NN], _plan(prob, d, w, 1).starlet_fwd(p[:NN]).cpu().numpy())
+    lo, go = ora.loss_grad(prob, d, w, p, sgn_override=so)
+    for algo in (1, 2, 0):
+        plan = _plan(prob, d, w, algo)
+        loss, grad = plan.loss_grad(p)
+        loss = loss.cpu().numpy()
+        grad = grad.cpu().numpy().astype(np.float64)
+        rl = abs(loss[2] - lo[2]) / abs(lo[2])
+        blocks = {k: parity.rel_err(parity.deconv_blocks(prob, grad)[k], v)
+                  for k, v in parity.deconv_blocks(prob, go).items()}
+        _say(f"cfg2 full algo {algo} -> {plan.conv_algo}: loss rel {rl:.2e} grad {blocks}")
+        assert rl <= 1e-6
+        for k, v in blocks.items():
+            assert v <= 1e-4, (algo, k, v)
 
 
 def test_forward_only_matches_and_is_deterministic():
@@ -273,3 +293,78 @@ def test_loss_grad_before_set_frames_is_an_error():
     with pytest.raises(st.StarredError) as e:
         plan.loss_grad(prob.params_true)
     assert e.value.code == st.ESTATE
+
+
+# --------------------------------------------------------------------------- #
+# PSF-reconstruction mode (Eqs. 2-7)                                           #
+# --------------------------------------------------------------------------- #
+
+PSF_CASES = [
+    ("psf_small_s3", dict(S=4, n=16, s=3, J=4)),
+    ("psf_s2", dict(S=5, n=24, s=2, J=4)),
+    ("psf_cfg3", dict()),
+]
+
+
+def _psf_setup(kw, seed):
+    st = _st()
+    prob = synth.make_psf(**kw)
+    rng = np.random.default_rng(seed)
+    m = ora.psf_model(prob, prob.params_true)
+    d, w = synth.add_noise(m, rng, sigma_bg=prob.sigma_bg, poisson=False)
+    plan = st.Plan.for_psf(prob)
+    plan.set_frames(d, w, None, prob.W)
+    return prob, d, w, rng, plan
+
+
+@pytest.mark.parametrize("name,kw", PSF_CASES, ids=[c[0] for c in PSF_CASES])
+def test_psf_render_and_model(name, kw):
+    prob, d, w, rng, plan = _psf_setup(kw, 41)
+    p = synth.psf_eval_point(prob, "near", rng)
+    s_dev = plan.render_scene(p).cpu().numpy()
+    s_ora = ora.psf_render(prob.N, p)
+    assert np.abs(s_dev - s_ora).max() <= 2e-6 * np.abs(s_ora).max()
+    m_dev = plan.psf_model(p).cpu().numpy()
+    m_ora = ora.psf_model(prob, p)
+    _check_frames(m_dev, m_ora, [prob.n] * prob.S, 2e-6)
+
+
+@pytest.mark.parametrize("name,kw", PSF_CASES, ids=[c[0] for c in PSF_CASES])
+@pytest.mark.parametrize("point", ["init", "near"])
+def test_psf_loss_grad_parity(name, kw, point):
+    prob, d, w, rng, plan = _psf_setup(kw, 42)
+    p = synth.psf_eval_point(prob, point, rng)
+    loss, grad = plan.loss_grad(p)
+    loss = loss.cpu().numpy()
+    grad = grad.cpu().numpy().astype(np.float64)
+    NN = prob.N * prob.N
+    alpha_dev = plan.starlet_fwd(p[5:5 + NN]).cpu().numpy()
+    so, nsub = parity.tie_override(prob.N, prob.J, p[5:5 + NN], alpha_dev)
+    lo, go = ora.psf_loss_grad(prob, d, w, p, sgn_override=so)
+    rl = abs(loss[2] - lo[2]) / abs(lo[2])
+    blocks = {k: parity.rel_err(parity.psf_blocks(prob, grad)[k], v)
+              for k, v in parity.psf_blocks(prob, go).items()}
+    _say(f"{name}/{point}: loss rel {rl:.2e}; grad {blocks}; ties {nsub}")
+    assert rl <= 1e-6
+    assert parity.rel_err(grad, go) <= 1e-4
+    for k, v in blocks.items():
+        assert v <= 1e-4, (k, v)
+
+
+def test_psf_line_search_evaluations_forward_only():
+    prob, d, w, rng, plan = _psf_setup(dict(S=4, n=16, s=3, J=4), 43)
+    p = synth.psf_eval_point(prob, "init", rng)
+    _, g = plan.loss_grad(p)
+    g = g.cpu().numpy().astype(np.float64)
+    # Armijo backtracking along the negative gradient with forward-only evaluations
+    f0 = plan.loss_grad(p, want_grad=False)[0][2].item()
+    step = 1.0 / max(np.abs(g).max(), 1e-30)
+    for _ in range(30):
+        trial = synth.f32(p - step * g)
+        f1 = plan.loss_grad(trial, want_grad=False)[0][2].item()
+        lo, _ = ora.psf_loss_grad(prob, d, w, trial, want_grad=False)
+        assert abs(f1 - lo[2]) <= 1e-6 * abs(lo[2])
+        if f1 <= f0 - 1e-4 * step * float(np.dot(g, g)):
+            break
+        step *= 0.5
+    assert f1 < f0
