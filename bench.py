@@ -81,6 +81,7 @@ def main():
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--algo", default="auto", choices=["auto", "direct", "fft"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
@@ -102,15 +103,15 @@ def main():
     m = torch.zeros_like(x)
     v = torch.zeros_like(x)
     loss = torch.empty(3, dtype=torch.float64, device="cuda")
+    grad = torch.empty_like(x)
     lr4 = [prob.adam_lr[k] for k in ("h", "Gamma", "a", "c")]
 
+    # ---- timed region: optimiser steps, each one captured graph replay ----
+    plan.set_graph_mode(not args.no_graph)
     t = 0
     for _ in range(args.warmup):
         t += 1
         plan.step(x, m, v, t, lr4, loss_out=loss)
-    torch.cuda.synchronize()
-
-    plan.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -118,22 +119,38 @@ def main():
         plan.step(x, m, v, t, lr4, loss_out=loss)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    ms = el * 1e3 / args.steps
+    value = args.steps / el * prob.data_size
+
+    # ---- fused loss+grad alone vs the plain per-epoch baseline ----
+    n_fused = max(20, args.steps // 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_fused):
+        plan.loss_grad(x, grad_out=grad, loss_out=loss)
+    torch.cuda.synchronize()
+    fused_eps = n_fused / (time.perf_counter() - t0)
+    plan.set_graph_mode(False)
+    plan.loss_grad_plain(x, grad_out=grad, loss_out=loss)
+    torch.cuda.synchronize()
+    n_plain = 5
+    t0 = time.perf_counter()
+    for _ in range(n_plain):
+        plan.loss_grad_plain(x, grad_out=grad, loss_out=loss)
+    torch.cuda.synchronize()
+    plain_eps = n_plain / (time.perf_counter() - t0)
+
+    # ---- stage timing (eager launches, HIP events on the launching streams) ----
+    n_prof = max(10, min(args.steps, 50))
+    plan.set_profiling(True)
+    for _ in range(n_prof):
+        t += 1
+        plan.step(x, m, v, t, lr4, loss_out=loss)
     prof = plan.profile_read()
     plan.set_profiling(False)
+    stage_ms = {k: v_["ms"] / max(v_["count"], 1) for k, v_ in prof.items() if v_["count"]}
 
-    ms = el * 1e3 / args.steps
-    evals = args.steps / el
-    value = evals * prob.data_size
-
-    fwd = prof["conv_fwd"]
-    fwd_ms = fwd["ms"] / max(fwd["count"], 1)
-    flops = conv_flops(prob)
-    achieved = flops / (fwd_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": "k_fwd_direct (fused S_i + D + residual + chi2)",
-            "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
-            "avg_launch_ms": round(fwd_ms, 4)}
-
+    roof = roofline(prob, plan, stage_ms)
     out = {
         "metric": "loss+grad evals/s (epoch-pixels/s), fused vs plain, grad rel err <=1e-4",
         "value": value, "unit": "epoch-px/s", "n_gpus": 1, "steps": args.steps,
@@ -143,14 +160,67 @@ def main():
                                f"data, s={prob.s}, {int(prob.K[0])}x{int(prob.K[0])} kernels, "
                                f"M={prob.M}, J={prob.J}",
                    "epochs": prob.E, "data_px_per_eval": prob.data_size,
-                   "conv_algo": {1: "direct", 2: "fft"}.get(plan.conv_algo, "?")},
-        "evals_per_s": evals,
-        "stage_ms_per_step": {k: round(v["ms"] / max(v["count"], 1), 4) for k, v in prof.items()},
+                   "conv_algo": {1: "direct", 2: "fft"}.get(plan.conv_algo, "?"),
+                   "graph": not args.no_graph},
+        "evals_per_s_step": args.steps / el,
+        "fused_vs_plain": {"fused_loss_grad_evals_per_s": fused_eps,
+                           "plain_loss_grad_evals_per_s": plain_eps,
+                           "fused_epoch_px_per_s": fused_eps * prob.data_size,
+                           "plain_epoch_px_per_s": plain_eps * prob.data_size,
+                           "speedup": fused_eps / plain_eps},
+        "stage_ms_per_step": {k: round(v_, 4) for k, v_ in stage_ms.items()},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob.name)
     print(json.dumps(out), flush=True)
+
+
+def roofline(prob, plan, stage_ms):
+    """Roofline of the dominant stage's kernel(s), from its measured average duration."""
+    if plan.conv_algo == 1:
+        fwd_ms = stage_ms["conv_fwd"]
+        flops = conv_flops(prob)
+        achieved = flops / (fwd_ms * 1e-3) / 1e12
+        return {"bound": "alu", "kernel": "k_fwd_direct (fused S_i + D + residual + chi2)",
+                "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": round(fwd_ms, 4), "algorithmic_flops": flops}
+    # FFT path: HBM-bound passes; algorithmic bytes of the forward stage = the kernel
+    # spectra S'' read once, data and inverse variance read once, rho spectra written once
+    by = fft_fwd_bytes(prob)
+    fwd_ms = stage_ms["conv_fwd"]
+    achieved = by / (fwd_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": "forward FFT stage (spectral product + alias fold + inverse + "
+                                      "residual + rho spectra)",
+            "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "avg_launch_ms": round(fwd_ms, 4), "algorithmic_bytes": by}
+
+
+def _good(need, s):
+    P = need
+    while True:
+        if P % (2 * s) == 0:
+            r = P
+            for f in (2, 3, 5):
+                while r % f == 0:
+                    r //= f
+            if r == 1:
+                return P
+        P += 1
+
+
+def fft_fwd_bytes(prob):
+    tot = 0
+    for n, K in zip(prob.n, prob.K):
+        F = prob.s * int(n)
+        P = _good(F + int(K) // 2, prob.s)
+        Q = P // prob.s
+        tot += 8 * P * (P // 2 + 1)        # kernel spectrum, complex64
+        tot += 2 * 4 * int(n) * int(n)     # data and inverse variance
+        tot += 8 * int(n) * (Q // 2 + 1)   # rho row spectra
+    return float(tot)
 
 
 if __name__ == "__main__":

@@ -150,14 +150,27 @@ int starred_starlet_adj(starred_plan *plan, const float *coeffs, float *img);
  * Deterministic: no floating-point atomics; repeated calls give identical bits. */
 int starred_loss_grad(starred_plan *plan, const float *params, float *grad, double *loss_out);
 
+/* Baseline for measurement: the same loss and gradient computed the plain way,
+ * epoch after epoch with one launch per operator (render, full-resolution
+ * convolution S_i, block sum D, residual, D^T, full-resolution correlation
+ * S_i^T, per-frame sums) and no fusion or graph. Results equal
+ * starred_loss_grad's up to rounding. The psf kernels passed to
+ * starred_set_frames must stay valid (they are re-read on the first call). */
+int starred_loss_grad_plain(starred_plan *plan, const float *params, float *grad, double *loss_out);
+
 /* One optimiser step: loss_grad at params, then the Adam update (Kingma & Ba)
  * of params, m and v in place, t = step number starting at 1. The plan keeps
  * the gradient in its own scratch. loss_out as above (may be NULL). */
 int starred_step(starred_plan *plan, float *params, float *m, float *v, int32_t t,
                  const starred_adam *hp, double *loss_out);
 
-/* Capture the loss_grad (or step) sequence of the current bindings into a HIP
- * graph and replay it on later calls with the same pointers; 0 disables. */
+/* Graph mode. When enabled, starred_loss_grad and starred_step capture their
+ * launch sequence into a HIP graph on the first call and replay it while the
+ * argument pointers (and, for step, the Adam hyper-parameters) stay the same;
+ * a change re-captures. The step number t lives in device memory and is
+ * advanced by the step itself, so consecutive steps replay one graph. Needs a
+ * non-default stream. 0 disables and frees the graphs. In graph mode stage
+ * timing reports one STARRED_STAGE_GRAPH interval per call. */
 int starred_set_graph_mode(starred_plan *plan, int32_t enable);
 
 /* Which convolution algorithm the plan runs (STARRED_CONV_DIRECT or _FFT). */
@@ -177,6 +190,7 @@ enum {
     STARRED_STAGE_FINALIZE,     /* cross-frame gradient of h and the final reductions */
     STARRED_STAGE_ADAM,         /* optimiser update */
     STARRED_STAGE_SPECTRA,      /* FFT path: spectra shared by all frames */
+    STARRED_STAGE_GRAPH,        /* graph mode: one whole captured loss_grad or step */
     STARRED_NUM_STAGES
 };
 int starred_set_profiling(starred_plan *plan, int32_t enable);

@@ -100,15 +100,15 @@ __device__ __forceinline__ void dft_small<5>(float2 (&v)[5], bool inv)
 
 template <int R>
 __device__ __forceinline__ void stockham_stage(const float2 *__restrict__ src, float2 *__restrict__ dst,
-                                               int nl, int L, int Ns, const float2 *__restrict__ tw,
+                                               int nl, int L, int Ls, int Ns, const float2 *__restrict__ tw,
                                                bool inv)
 {
     const int LR = L / R;
     const int twstep = L / (Ns * R);
     for (int b = threadIdx.x; b < nl * LR; b += blockDim.x) {
         const int l = b / LR, j = b - l * LR;
-        const float2 *in = src + l * L;
-        float2 *out = dst + l * L;
+        const float2 *in = src + l * Ls;
+        float2 *out = dst + l * Ls;
         const int k = j % Ns;
         float2 v[5];
         #pragma unroll
@@ -127,18 +127,20 @@ __device__ __forceinline__ void stockham_stage(const float2 *__restrict__ src, f
     }
 }
 
-// 1-D FFTs of nl lines of length f.L held consecutively in LDS buffer a; b is
+// 1-D FFTs of nl lines of length f.L held in LDS buffer a with line stride
+// Ls = f.L + 1 (the pad keeps column-order accesses off a single bank); b is
 // scratch of the same size. Returns the buffer that holds the result.
 __device__ float2 *lds_fft(float2 *a, float2 *b, int nl, const FftLen &f, const float2 *__restrict__ tw,
                            bool inv)
 {
     int Ns = 1;
+    const int Ls = f.L + 1;
     for (int st = 0; st < f.nst; ++st) {
         const int R = f.rad[st];
-        if (R == 4) stockham_stage<4>(a, b, nl, f.L, Ns, tw, inv);
-        else if (R == 2) stockham_stage<2>(a, b, nl, f.L, Ns, tw, inv);
-        else if (R == 3) stockham_stage<3>(a, b, nl, f.L, Ns, tw, inv);
-        else stockham_stage<5>(a, b, nl, f.L, Ns, tw, inv);
+        if (R == 4) stockham_stage<4>(a, b, nl, f.L, Ls, Ns, tw, inv);
+        else if (R == 2) stockham_stage<2>(a, b, nl, f.L, Ls, Ns, tw, inv);
+        else if (R == 3) stockham_stage<3>(a, b, nl, f.L, Ls, Ns, tw, inv);
+        else stockham_stage<5>(a, b, nl, f.L, Ls, Ns, tw, inv);
         __syncthreads();
         float2 *t = a;
         a = b;
@@ -161,18 +163,25 @@ __global__ __launch_bounds__(kFftThreads) void k_lines(const LineItem *__restric
     const LineItem it = items[blockIdx.x];
     const ClassFft &cl = classes[it.cls];
     const FftLen f = op.len(cl);
+    const int Ls = f.L + 1;
     float2 *a = sm;
-    float2 *b = sm + it.nl * f.L;
+    float2 *b = sm + it.nl * Ls;
     const int tot = it.nl * f.L;
+    // column passes walk the lines fastest so that neighbouring threads touch
+    // neighbouring columns of a row in global memory
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int l = e / f.L, j = e - l * f.L;
-        a[e] = op.load(cl, it.frame, it.line0 + l, j);
+        int l, j;
+        if (Op::col) { l = e % it.nl; j = e / it.nl; }
+        else { l = e / f.L; j = e - l * f.L; }
+        a[l * Ls + j] = op.load(cl, it.frame, it.line0 + l, j);
     }
     __syncthreads();
     float2 *r = lds_fft(a, b, it.nl, f, tw + f.tw_off, op.inverse);
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int l = e / f.L, j = e - l * f.L;
-        op.store(cl, it.frame, it.line0 + l, j, r[e]);
+        int l, j;
+        if (Op::col) { l = e % it.nl; j = e / it.nl; }
+        else { l = e / f.L; j = e - l * f.L; }
+        op.store(cl, it.frame, it.line0 + l, j, r[l * Ls + j]);
     }
 }
 
@@ -191,6 +200,7 @@ struct OpHRows {
     const float *h;
     int N;
     float2 *Th;
+    static constexpr bool col = false;
     static constexpr bool inverse = false;
     __device__ FftLen len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int, int y, int x) const
@@ -208,6 +218,7 @@ struct OpHRows {
 struct OpHCols {
     const float2 *Th;
     float2 *Hh;
+    static constexpr bool col = true;
     static constexpr bool inverse = false;
     __device__ FftLen len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int, int kx, int y) const
@@ -228,6 +239,7 @@ struct OpKRows {
     const float *psf;
     int s;
     float2 *TS;
+    static constexpr bool col = false;
     static constexpr bool inverse = false;
     __device__ FftLen len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int i, int y, int x) const
@@ -257,6 +269,7 @@ struct OpKCols {
     const FrameFft *fr;
     const float2 *TS;
     float2 *S;
+    static constexpr bool col = true;
     static constexpr bool inverse = false;
     __device__ FftLen len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int i, int kx, int y) const
@@ -281,6 +294,7 @@ struct OpFwdCols {
     int N, E, M, s;
     float2 *T;
     const float2 *scene_spec;  // per-frame scene spectra (standalone operator) or NULL
+    static constexpr bool col = true;
     static constexpr bool inverse = true;
     __device__ FftLen len(const ClassFft &c) const { return c.fQ; }
     // scene spectrum at K (any Kx in [0,P)): Gamma w(Ky) w(Kx) + H(K) + sum_k a g_y(Ky) g_x(Kx)
@@ -324,6 +338,7 @@ struct OpRhoCols {
     const FrameFft *fr;
     const float2 *T2;
     float2 *Rh;
+    static constexpr bool col = true;
     static constexpr bool inverse = false;
     __device__ FftLen len(const ClassFft &c) const { return c.fQ; }
     __device__ float2 load(const ClassFft &c, int i, int kx, int y) const
@@ -344,6 +359,7 @@ struct OpAdjCols {
     const float2 *S;
     const float2 *Rh;
     float2 *T3;
+    static constexpr bool col = true;
     static constexpr bool inverse = true;
     __device__ FftLen len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int i, int Kx, int Ky) const
@@ -367,6 +383,7 @@ struct OpAdjRows {
     const FrameFft *fr;
     const float2 *T3;
     float *g;
+    static constexpr bool col = false;
     static constexpr bool inverse = true;
     __device__ FftLen len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int i, int y, int Kx) const
@@ -386,6 +403,7 @@ struct OpResidRows {
     const FrameFft *fr;
     const float *resid;
     float2 *T2;
+    static constexpr bool col = false;
     static constexpr bool inverse = false;
     __device__ FftLen len(const ClassFft &c) const { return c.fQ; }
     __device__ float2 load(const ClassFft &c, int i, int y, int x) const
@@ -404,6 +422,7 @@ struct OpSceneRows {
     const FrameFft *fr;
     const float *scene;
     float2 *T3;
+    static constexpr bool col = false;
     static constexpr bool inverse = false;
     __device__ FftLen len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int i, int y, int x) const
@@ -420,6 +439,7 @@ struct OpSceneRows {
 struct OpSceneCols {  // every column is read and written by the same work group
     const FrameFft *fr;
     float2 *T3;
+    static constexpr bool col = true;
     static constexpr bool inverse = false;
     __device__ FftLen len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int i, int kx, int y) const
@@ -451,14 +471,14 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
     const ClassFft &c = classes[it.cls];
     const FrameFft &f = fr[it.frame];
     const FftLen fl = c.fQ;
-    const int Q = c.Q, H = Q / 2 + 1, n = c.n;
+    const int Q = c.Q, H = Q / 2 + 1, n = c.n, Ls = Q + 1;
     float2 *a = sm;
-    float2 *b = sm + it.nl * Q;
+    float2 *b = sm + it.nl * Ls;
     const int tot = it.nl * Q;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
         const int l = e / Q, kx = e - l * Q;
         const float2 *row = T + f.t_off + (long long)(it.line0 + l) * H;
-        a[e] = kx < H ? row[kx] : conjf2(row[Q - kx]);
+        a[l * Ls + kx] = kx < H ? row[kx] : conjf2(row[Q - kx]);
     }
     __syncthreads();
     float2 *r = lds_fft(a, b, it.nl, fl, tw + fl.tw_off, true);
@@ -470,7 +490,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
         float v = 0.f;
         if (x < n) {
             const long long idx = f.data_off + (long long)y * n + x;
-            const float m = r[e].x;
+            const float m = r[l * Ls + x].x;
             if (model) {
                 model[idx] = m;
             } else {
@@ -480,7 +500,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
                 chi += 0.5 * (double)w * (double)res * (double)res;
             }
         }
-        o[e] = make_float2(v, 0.f);
+        o[l * Ls + x] = make_float2(v, 0.f);
     }
     const double tchi = block_sum_d_fft(chi, red);
     if (threadIdx.x == 0 && part_chi) part_chi[blockIdx.x] = tchi;
@@ -489,7 +509,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
     float2 *q = lds_fft(o, r, it.nl, fl, tw + fl.tw_off, false);
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
         const int l = e / Q, kx = e - l * Q;
-        if (kx < H) T2[f.t_off + (long long)(it.line0 + l) * H + kx] = q[e];
+        if (kx < H) T2[f.t_off + (long long)(it.line0 + l) * H + kx] = q[l * Ls + kx];
     }
 }
 

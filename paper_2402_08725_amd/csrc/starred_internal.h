@@ -85,15 +85,27 @@ hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, floa
                               float *v_a, float *v_b, float *tmp);
 
 hipError_t launch_adam(hipStream_t st, long long P, const long long *seg_end, const float *lr,
-                       float *params, const float *grad, float *m, float *v, int t, float beta1,
+                       float *params, const float *grad, float *m, float *v, int *d_t, float beta1,
                        float beta2, float eps);
+hipError_t launch_set_step(hipStream_t st, int *d_t, int value);
 
 hipError_t launch_fill(hipStream_t st, float *p, long long n, float v);
 
+// plain (unfused, per-epoch) baseline: one launch per operator per frame
+hipError_t launch_render_frame(hipStream_t st, const FrameDev *fr, int E, int i, int F, int N, int M,
+                               float sigma, const float *params, float *scene);
+// op 0: m = D u; op 1: rho = w (m - d) with chi partials; op 2: gh = D^T rho
+hipError_t launch_plain_frame_ops(hipStream_t st, int op, const FrameDev *fr, int i, int n, int F, int s,
+                                  const float *a, const float *data, const float *invvar, float *out,
+                                  double *part);
+hipError_t launch_frame_sums_one(hipStream_t st, const FrameDev *fr, int E, int i, int N, int M, float sigma,
+                                 const float *params, const float *g, double *fsum);
+
 // PSF mode (starred_psf.hip)
 hipError_t launch_psf_render(hipStream_t st, int N, const float *params, float *s_out);
+hipError_t launch_psf_render64(hipStream_t st, int N, const float *params, double *s64);
 hipError_t launch_psf_fwd(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
-                          const float *s_img, const float *data, const float *invvar, float *rho,
+                          const double *s64, const float *data, const float *invvar, float *rho,
                           double *part_chi, float *grad);
 hipError_t launch_psf_model(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
                             const float *s_img, float *model);
@@ -105,7 +117,7 @@ hipError_t launch_psf_finalize_small(hipStream_t st, int S, int n_chi, const dou
                                      const double *part_l1, int n_eta, const double *part_eta, float *grad,
                                      double *loss);
 int psf_sum_blocks(int N);
-size_t psf_fwd_lds(int n, int N);
+size_t psf_fwd_lds(int n, int s);
 size_t psf_adj_lds(int n, int N);
 
 }  // namespace starred

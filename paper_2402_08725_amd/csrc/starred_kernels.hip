@@ -97,25 +97,25 @@ hipError_t launch_prep_kernels(hipStream_t st, const FrameDev *fr_dev, const Fra
 // a1: scene rendering f_i = Gamma_i + h[window_i] + sum_k a_ki r_k   (Eq. 9)
 // --------------------------------------------------------------------------
 
-__global__ void k_render(const FrameDev *__restrict__ frames, int N, int M, float sigma,
+__global__ void k_render(const FrameDev *__restrict__ frames, int E, int frame0, int N, int M, float sigma,
                          const float *__restrict__ params, float *__restrict__ scene)
 {
-    const FrameDev fr = frames[blockIdx.y];
+    const int i = frame0 + blockIdx.y;
+    const FrameDev fr = frames[i];
     const int pix = blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= fr.F * fr.F) return;
     const int y = pix / fr.F, x = pix % fr.F;
     const int Y = y + fr.o, X = x + fr.o;
-    const int E = gridDim.y;
     const float *h = params;
     const float *a = params + (long long)N * N + E;
     const float *c = a + (long long)E * M;
-    float v = params[(long long)N * N + blockIdx.y] + h[(long long)Y * N + X];
+    float v = params[(long long)N * N + i] + h[(long long)Y * N + X];
     const float inv2s2 = 1.0f / (2.0f * sigma * sigma);
     const float norm = 1.0f / (2.0f * 3.14159265358979f * sigma * sigma);
     for (int k = 0; k < M; ++k) {
         float dx = (float)X - c[2 * k], dy = (float)Y - c[2 * k + 1];
         if (fabsf(dx) <= (float)kGaussRadius && fabsf(dy) <= (float)kGaussRadius)
-            v += a[(long long)blockIdx.y * M + k] * (norm * expf(-(dx * dx + dy * dy) * inv2s2));
+            v += a[(long long)i * M + k] * (norm * expf(-(dx * dx + dy * dy) * inv2s2));
     }
     scene[fr.fine_off + pix] = v;
 }
@@ -125,7 +125,77 @@ hipError_t launch_render(hipStream_t st, const FrameDev *fr, int E, int Fmax, in
 {
     if (E <= 0) return hipSuccess;
     dim3 grid((Fmax * Fmax + 255) / 256, E);
-    hipLaunchKernelGGL(k_render, grid, dim3(256), 0, st, fr, N, M, sigma, params, scene);
+    hipLaunchKernelGGL(k_render, grid, dim3(256), 0, st, fr, E, 0, N, M, sigma, params, scene);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_frame(hipStream_t st, const FrameDev *fr, int E, int i, int F, int N, int M,
+                               float sigma, const float *params, float *scene)
+{
+    dim3 grid((F * F + 255) / 256, 1);
+    hipLaunchKernelGGL(k_render, grid, dim3(256), 0, st, fr, E, i, N, M, sigma, params, scene);
+    return hipGetLastError();
+}
+
+// ---- one-frame operators of the plain (unfused, per-epoch) baseline ----
+
+// m = D u  (block sum over s x s)
+__global__ void k_block_sum(const FrameDev *__restrict__ frames, int i, int s, const float *__restrict__ u,
+                            float *__restrict__ m)
+{
+    const FrameDev fr = frames[i];
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= fr.n * fr.n) return;
+    const int p = pix / fr.n, q = pix % fr.n;
+    const float *uf = u + fr.fine_off;
+    float acc = 0.f;
+    for (int a = 0; a < s; ++a)
+        for (int b = 0; b < s; ++b) acc += uf[(long long)(s * p + a) * fr.F + s * q + b];
+    m[fr.data_off + pix] = acc;
+}
+
+// rho = w (m - d), chi-square partial of each block
+__global__ __launch_bounds__(256) void k_resid(const FrameDev *__restrict__ frames, int i,
+                                               const float *__restrict__ m, const float *__restrict__ data,
+                                               const float *__restrict__ invvar, float *__restrict__ rho,
+                                               double *__restrict__ part)
+{
+    __shared__ double red[4];
+    const FrameDev fr = frames[i];
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    double chi = 0.0;
+    if (pix < fr.n * fr.n) {
+        const long long idx = fr.data_off + pix;
+        const float r = m[idx] - data[idx];
+        const float w = invvar[idx];
+        rho[idx] = w * r;
+        chi = 0.5 * (double)w * (double)r * (double)r;
+    }
+    chi = block_sum_d<256>(chi, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = chi;
+}
+
+// gh = D^T rho (replicate each data pixel over its s x s block)
+__global__ void k_upsample(const FrameDev *__restrict__ frames, int i, int s, const float *__restrict__ rho,
+                           float *__restrict__ gh)
+{
+    const FrameDev fr = frames[i];
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= fr.F * fr.F) return;
+    const int y = pix / fr.F, x = pix % fr.F;
+    gh[fr.fine_off + pix] = rho[fr.data_off + (long long)(y / s) * fr.n + x / s];
+}
+
+hipError_t launch_plain_frame_ops(hipStream_t st, int op, const FrameDev *fr, int i, int n, int F, int s,
+                                  const float *a, const float *data, const float *invvar, float *out,
+                                  double *part)
+{
+    if (op == 0)
+        hipLaunchKernelGGL(k_block_sum, dim3((n * n + 255) / 256), dim3(256), 0, st, fr, i, s, a, out);
+    else if (op == 1)
+        hipLaunchKernelGGL(k_resid, dim3((n * n + 255) / 256), dim3(256), 0, st, fr, i, a, data, invvar, out, part);
+    else
+        hipLaunchKernelGGL(k_upsample, dim3((F * F + 255) / 256), dim3(256), 0, st, fr, i, s, a, out);
     return hipGetLastError();
 }
 
@@ -349,12 +419,11 @@ hipError_t launch_adj_direct(hipStream_t st, int s, const FrameDev *fr, const It
 constexpr int kSumThreads = 256;
 
 __global__ __launch_bounds__(kSumThreads) void k_frame_sums(
-    const FrameDev *__restrict__ frames, int N, int M, float sigma,
+    const FrameDev *__restrict__ frames, int E, int frame0, int N, int M, float sigma,
     const float *__restrict__ params, const float *__restrict__ g, double *__restrict__ fsum)
 {
     __shared__ double red[kSumThreads / 64];
-    const int i = blockIdx.x;
-    const int E = gridDim.x;
+    const int i = frame0 + blockIdx.x;
     const FrameDev fr = frames[i];
     const float *gi = g + fr.fine_off;
     const int stride = 1 + 3 * M;
@@ -402,7 +471,15 @@ hipError_t launch_frame_sums(hipStream_t st, const FrameDev *fr, int E, int N, i
                              const float *params, const float *g, double *fsum)
 {
     if (E <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_frame_sums, dim3(E, 1 + M), dim3(kSumThreads), 0, st, fr, N, M, sigma,
+    hipLaunchKernelGGL(k_frame_sums, dim3(E, 1 + M), dim3(kSumThreads), 0, st, fr, E, 0, N, M, sigma,
+                       params, g, fsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame_sums_one(hipStream_t st, const FrameDev *fr, int E, int i, int N, int M, float sigma,
+                                 const float *params, const float *g, double *fsum)
+{
+    hipLaunchKernelGGL(k_frame_sums, dim3(1, 1 + M), dim3(kSumThreads), 0, st, fr, E, i, N, M, sigma,
                        params, g, fsum);
     return hipGetLastError();
 }
@@ -660,14 +737,22 @@ hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, floa
 // a12: Adam update (per-block learning rates)
 // --------------------------------------------------------------------------
 
+// The step number lives on the device (d_t) so that a captured graph can run
+// consecutive steps: k_adam_tick advances it, k_adam reads it.
+__global__ void k_adam_tick(int *d_t) { *d_t += 1; }
+__global__ void k_set_int(int *d_t, int v) { *d_t = v; }
+
 __global__ void k_adam(long long P, long long e0, long long e1, long long e2, float lr0, float lr1,
                        float lr2, float lr3, float *__restrict__ params,
                        const float *__restrict__ grad, float *__restrict__ m,
-                       float *__restrict__ v, float beta1, float beta2, float bc1, float bc2,
-                       float eps)
+                       float *__restrict__ v, float beta1, float beta2, float eps,
+                       const int *__restrict__ d_t)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
+    const float t = (float)(*d_t);
+    const float bc1 = 1.f - powf(beta1, t);
+    const float bc2 = 1.f - powf(beta2, t);
     const float lr = i < e0 ? lr0 : (i < e1 ? lr1 : (i < e2 ? lr2 : lr3));
     const float g = grad[i];
     const float mi = beta1 * m[i] + (1.f - beta1) * g;
@@ -677,15 +762,20 @@ __global__ void k_adam(long long P, long long e0, long long e1, long long e2, fl
     params[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
+hipError_t launch_set_step(hipStream_t st, int *d_t, int value)
+{
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, d_t, value);
+    return hipGetLastError();
+}
+
 hipError_t launch_adam(hipStream_t st, long long P, const long long *seg_end, const float *lr,
-                       float *params, const float *grad, float *m, float *v, int t, float beta1,
+                       float *params, const float *grad, float *m, float *v, int *d_t, float beta1,
                        float beta2, float eps)
 {
-    const float bc1 = (float)(1.0 - pow((double)beta1, (double)t));
-    const float bc2 = (float)(1.0 - pow((double)beta2, (double)t));
     const int nb = (int)((P + 255) / 256);
+    hipLaunchKernelGGL(k_adam_tick, dim3(1), dim3(1), 0, st, d_t);
     hipLaunchKernelGGL(k_adam, dim3(nb), dim3(256), 0, st, P, seg_end[0], seg_end[1], seg_end[2],
-                       lr[0], lr[1], lr[2], lr[3], params, grad, m, v, beta1, beta2, bc1, bc2, eps);
+                       lr[0], lr[1], lr[2], lr[3], params, grad, m, v, beta1, beta2, eps, d_t);
     return hipGetLastError();
 }
 

@@ -87,13 +87,40 @@ struct starred_plan {
     std::vector<ClassFft> cls;
     std::vector<FrameFft> ffr;
     double *d_part_chi_fft = nullptr;
+    // plain per-epoch baseline (s = 1 tables at fine resolution)
+    bool plain_ready = false;
+    std::vector<FrameDev> frp;
+    FrameDev *d_frp = nullptr;
+    Item *d_pfwd = nullptr, *d_padj = nullptr;
+    std::vector<int> pfwd_start, padj_start, pchi_start;
+    int pTmax = 0, pAr_max = 0, pBpad_max = 0, n_pchi = 0;
+    float *d_pkf = nullptr, *d_pka = nullptr, *d_u = nullptr, *d_gh = nullptr, *d_m = nullptr;
+    double *d_pchi = nullptr;
+    const float *psf_bound = nullptr;
+
     // PSF mode
     int psf_n = 0;
     float *d_simg = nullptr, *d_gstar = nullptr;
+    double *d_s64 = nullptr;
     double *d_part_eta = nullptr;
     int algo_req = STARRED_CONV_AUTO;
     bool direct_ok = true;
     double tune_ms[3] = {0, 0, 0};
+
+    // starlet branch: a second stream forked from and joined back into st
+    hipStream_t st2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int *d_t = nullptr;
+    int next_t = -1;  // step number the device counter will produce next (-1: unknown)
+
+    // captured graphs (slot 0: loss_grad, slot 1: step)
+    bool graph_mode = false;
+    struct GraphSlot {
+        bool valid = false;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
+        std::vector<uintptr_t> key;
+    } gs[2];
 
     // stage timing
     bool prof_on = false;
@@ -104,7 +131,7 @@ struct starred_plan {
     double prof_ms[STARRED_NUM_STAGES] = {};
     long long prof_cnt[STARRED_NUM_STAGES] = {};
 
-    hipEvent_t prof_start()
+    hipEvent_t prof_start(hipStream_t s = nullptr)
     {
         if (!prof_on) return nullptr;
         if (ev_next == ev_pool.size()) {
@@ -113,14 +140,22 @@ struct starred_plan {
             ev_pool.push_back(e);
         }
         hipEvent_t e = ev_pool[ev_next++];
-        (void)hipEventRecord(e, st);
+        (void)hipEventRecord(e, s ? s : st);
         return e;
     }
-    void prof_stop(int stage, hipEvent_t a)
+    void prof_stop(int stage, hipEvent_t a, hipStream_t s = nullptr)
     {
         if (!prof_on || !a) return;
-        hipEvent_t b = prof_start();
+        hipEvent_t b = prof_start(s);
         if (b) recs.push_back({stage, a, b});
+    }
+    void drop_graphs()
+    {
+        for (auto &g : gs) {
+            if (g.x) (void)hipGraphExecDestroy(g.x);
+            if (g.g) (void)hipGraphDestroy(g.g);
+            g = GraphSlot();
+        }
     }
     int prof_collect()
     {
@@ -141,6 +176,10 @@ struct starred_plan {
 
     ~starred_plan()
     {
+        drop_graphs();
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (st2) (void)hipStreamDestroy(st2);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (void *p : owned) (void)hipFree(p);
     }
@@ -436,14 +475,20 @@ static int build_fft(starred_plan *p)
         struct G { int L; LineItem it; };
         std::vector<G> g;
         const int nunits = per_class ? (int)p->cls.size() : E;
+        long long total_lines = 0;
+        for (int u = 0; u < nunits; ++u) total_lines += lines_of(p->cls[per_class ? u : fcls[u]]);
+        // lines per work group: about kFftTargetElems elements, fewer when the
+        // pass is small so that every compute unit gets work
+        const long long want_groups = 1024;
+        const int cap = (int)std::max(1LL, total_lines / want_groups);
         int maxL = 1;
         for (int u = 0; u < nunits; ++u) {
             const int c = per_class ? u : fcls[u];
             const ClassFft &cl = p->cls[c];
             const int L = len_of(cl);
             const int lines = lines_of(cl);
-            const int lpw = std::max(1, kFftTargetElems / L);
-            maxL = std::max(maxL, L * lpw);
+            const int lpw = std::max(1, std::min(kFftTargetElems / L, cap));
+            maxL = std::max(maxL, (L + 1) * lpw);
             for (int l0 = 0; l0 < lines; l0 += lpw)
                 g.push_back({L, LineItem{c, per_class ? -1 : u, l0, std::min(lpw, lines - l0)}});
         }
@@ -488,9 +533,11 @@ static int build_psf(starred_plan *p)
     p->nfine = (long long)N * N;
     const long long NN = (long long)N * N;
     const int nb_star = (int)((NN + 255) / 256);
-    if (psf_fwd_lds(n, N) > kMaxLds) return fail(STARRED_EUNSUPPORTED, "PSF grid too large for one work group");
+    if (psf_fwd_lds(n, p->s) > kMaxLds || psf_adj_lds(n, N) > kMaxLds)
+        return fail(STARRED_EUNSUPPORTED, "PSF grid too large for one work group");
     int rc;
     if ((rc = p->alloc(&p->d_simg, NN))) return rc;
+    if ((rc = p->alloc(&p->d_s64, NN))) return rc;
     if ((rc = p->alloc(&p->d_rho, p->ndata))) return rc;
     if ((rc = p->alloc(&p->d_gstar, (size_t)S * NN))) return rc;
     if ((rc = p->alloc(&p->d_part_chi, S))) return rc;
@@ -528,6 +575,20 @@ int starred_plan_create(const starred_desc *desc, void *stream, starred_plan **p
     p->fwhm = desc->gauss_fwhm;
     p->sigma = (float)(desc->gauss_fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0))));
     p->st = (hipStream_t)stream;
+    {
+        hipError_t e = hipStreamCreate(&p->st2);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            delete p;
+            return fail_hip(e, "stream/event creation");
+        }
+        rc = p->alloc(&p->d_t, 1);
+        if (rc) {
+            delete p;
+            return rc;
+        }
+    }
     p->n.assign(desc->side_host, desc->side_host + p->E);
     if (desc->ksize_host) p->K.assign(desc->ksize_host, desc->ksize_host + p->E);
     if (p->mode == STARRED_PSF) {
@@ -583,6 +644,10 @@ int starred_set_frames(starred_plan *p, const float *data, const float *inv_var,
     p->data = data;
     p->invvar = inv_var;
     p->W = W;
+    p->psf_bound = psf;
+    if (p->plain_ready) {
+        HIP_TRY(launch_prep_kernels(p->st, p->d_frp, p->frp.data(), p->E, 1, psf, p->d_pkf, p->d_pka));
+    }
     if (p->mode == STARRED_PSF) {
         p->frames_set = true;
         return STARRED_OK;
@@ -651,12 +716,32 @@ int starred_starlet_adj(starred_plan *p, const float *coeffs, float *img)
     return STARRED_OK;
 }
 
+// Starlet transform, L1 term, subgradient and adjoint of the image part of
+// params (h, or b in PSF mode) on the second stream: fork from st, join with
+// ev_join (the caller waits on it before the final reductions).
+static int starlet_branch(starred_plan *p, const float *img, bool want_grad, int *n_l1)
+{
+    HIP_TRY(hipEventRecord(p->ev_fork, p->st));
+    HIP_TRY(hipStreamWaitEvent(p->st2, p->ev_fork, 0));
+    hipEvent_t e0 = p->prof_start(p->st2);
+    HIP_TRY(launch_starlet_fwd(p->st2, p->N, p->J, img, nullptr, want_grad ? p->d_z : nullptr, p->W, p->w_stride,
+                               (float)p->lam, p->d_ca, p->d_cb, p->d_tmp, p->d_part_l1, n_l1));
+    if (want_grad) HIP_TRY(launch_starlet_adj(p->st2, p->N, p->J, p->d_z, p->d_prior, p->d_ca, p->d_cb, p->d_tmp));
+    p->prof_stop(STARRED_STAGE_STARLET, e0, p->st2);
+    HIP_TRY(hipEventRecord(p->ev_join, p->st2));
+    return STARRED_OK;
+}
+
 static int loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out)
 {
     const bool fft = (p->algo == STARRED_CONV_FFT);
     hipEvent_t e0;
     int n_chi;
     const double *part_chi;
+    // the starlet prior depends on h only: it runs on the forked stream
+    int n_l1 = 0;
+    int rc = starlet_branch(p, params, grad != nullptr, &n_l1);
+    if (rc) return rc;
     if (fft) {
         e0 = p->prof_start();
         HIP_TRY(fft_spectra(p->st, p->fd, params, p->N, p->E, p->M, p->sigma));
@@ -678,12 +763,6 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         n_chi = (int)p->fwd_items.size();
         part_chi = p->d_part_chi;
     }
-    int n_l1 = 0;
-    e0 = p->prof_start();
-    HIP_TRY(launch_starlet_fwd(p->st, p->N, p->J, params, nullptr, grad ? p->d_z : nullptr, p->W, p->w_stride,
-                               (float)p->lam, p->d_ca, p->d_cb, p->d_tmp, p->d_part_l1, &n_l1));
-    if (grad) HIP_TRY(launch_starlet_adj(p->st, p->N, p->J, p->d_z, p->d_prior, p->d_ca, p->d_cb, p->d_tmp));
-    p->prof_stop(STARRED_STAGE_STARLET, e0);
     if (grad) {
         e0 = p->prof_start();
         if (fft)
@@ -696,6 +775,7 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         HIP_TRY(launch_frame_sums(p->st, p->d_fr, p->E, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum));
         p->prof_stop(STARRED_STAGE_GRAD_SUMS, e0);
     }
+    HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
     e0 = p->prof_start();
     if (grad) HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad));
     HIP_TRY(launch_finalize_small(p->st, p->E, p->M, n_chi, part_chi, n_l1, p->d_part_l1, p->lam, p->d_fsum,
@@ -756,19 +836,16 @@ static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad,
 {
     const int S = p->E, n = p->psf_n, N = p->N;
     const long long NN = (long long)N * N;
+    int n_l1 = 0;
+    int rc = starlet_branch(p, params + 5, grad != nullptr, &n_l1);
+    if (rc) return rc;
     hipEvent_t e0 = p->prof_start();
-    HIP_TRY(launch_psf_render(p->st, N, params, p->d_simg));
+    HIP_TRY(launch_psf_render64(p->st, N, params, p->d_s64));
     p->prof_stop(STARRED_STAGE_RENDER, e0);
     e0 = p->prof_start();
-    HIP_TRY(launch_psf_fwd(p->st, S, n, p->s, N, p->sigma, params, p->d_simg, p->data, p->invvar, p->d_rho,
+    HIP_TRY(launch_psf_fwd(p->st, S, n, p->s, N, p->sigma, params, p->d_s64, p->data, p->invvar, p->d_rho,
                            p->d_part_chi, grad));
     p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
-    int n_l1 = 0;
-    e0 = p->prof_start();
-    HIP_TRY(launch_starlet_fwd(p->st, N, p->J, params + 5, nullptr, grad ? p->d_z : nullptr, p->W, p->w_stride,
-                               (float)p->lam, p->d_ca, p->d_cb, p->d_tmp, p->d_part_l1, &n_l1));
-    if (grad) HIP_TRY(launch_starlet_adj(p->st, N, p->J, p->d_z, p->d_prior, p->d_ca, p->d_cb, p->d_tmp));
-    p->prof_stop(STARRED_STAGE_STARLET, e0);
     if (grad) {
         e0 = p->prof_start();
         HIP_TRY(launch_psf_adj(p->st, S, n, p->s, N, p->sigma, params, p->d_rho, p->d_gstar));
@@ -777,6 +854,7 @@ static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad,
         HIP_TRY(launch_psf_sum(p->st, S, N, params, p->d_gstar, p->d_prior, grad, p->d_part_eta));
         p->prof_stop(STARRED_STAGE_GRAD_SUMS, e0);
     }
+    HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
     e0 = p->prof_start();
     HIP_TRY(launch_psf_finalize_small(p->st, S, S, p->d_part_chi, n_l1, p->d_part_l1, psf_sum_blocks(N),
                                       p->d_part_eta, grad, loss_out));
@@ -794,12 +872,166 @@ int starred_psf_model(starred_plan *p, const float *params, float *model)
     return STARRED_OK;
 }
 
+// ---- plain baseline: per-epoch, full-resolution convolution, one launch per operator ----
+static int build_plain(starred_plan *p)
+{
+    const int E = p->E;
+    p->frp.resize(E);
+    long long kfoff = 0, kaoff = 0;
+    std::vector<Item> fw, ad;
+    int nchi = 0;
+    for (int i = 0; i < E; ++i) {
+        const FrameDev &r = p->fr[i];
+        FrameDev &f = p->frp[i];
+        memset(&f, 0, sizeof f);
+        f.n = r.F;  // the plain convolution runs at fine resolution
+        f.F = r.F;
+        f.K = r.K;
+        f.Kp = r.K;
+        f.o = r.o;
+        f.cp = r.K / 2;
+        f.Tpad = round_up(f.Kp, 4);
+        f.dmin = -f.cp;
+        const int dmax = f.Kp - 1 - f.cp;
+        f.Ar = dmax - f.dmin + 1;
+        f.Bpad = round_up(f.Ar, 4);
+        f.data_off = r.fine_off;
+        f.fine_off = r.fine_off;
+        f.kern_off = r.kern_off;
+        f.kf_off = kfoff;
+        f.ka_off = kaoff;
+        kfoff += (long long)f.Kp * f.Tpad;
+        kaoff += (long long)f.Ar * f.Bpad;
+        p->pTmax = std::max(p->pTmax, f.Tpad);
+        p->pAr_max = std::max(p->pAr_max, f.Ar);
+        p->pBpad_max = std::max(p->pBpad_max, f.Bpad);
+        p->pfwd_start.push_back((int)fw.size());
+        for (int p0 = 0; p0 < f.n; p0 += kFwdTP)
+            for (int q0 = 0; q0 < f.n; q0 += kFwdTQ) fw.push_back(Item{i, p0, q0, 0});
+        p->padj_start.push_back((int)ad.size());
+        for (int p0 = 0; p0 < f.n; p0 += kAdjTP)
+            for (int q0 = 0; q0 < f.n; q0 += kAdjTQ) ad.push_back(Item{i, p0, q0, 0});
+        p->pchi_start.push_back(nchi);
+        nchi += (r.n * r.n + 255) / 256;
+    }
+    p->pfwd_start.push_back((int)fw.size());
+    p->padj_start.push_back((int)ad.size());
+    p->n_pchi = nchi;
+    if (fwd_lds_bytes(1, p->pTmax) > kMaxLds || adj_lds_bytes(p->pAr_max, p->pBpad_max) > kMaxLds)
+        return fail(STARRED_EUNSUPPORTED, "kernels too large for the plain baseline");
+    int rc;
+    if ((rc = p->alloc(&p->d_frp, E))) return rc;
+    if ((rc = p->alloc(&p->d_pfwd, fw.size()))) return rc;
+    if ((rc = p->alloc(&p->d_padj, ad.size()))) return rc;
+    if ((rc = p->alloc(&p->d_pkf, kfoff))) return rc;
+    if ((rc = p->alloc(&p->d_pka, kaoff))) return rc;
+    if ((rc = p->alloc(&p->d_u, p->nfine))) return rc;
+    if ((rc = p->alloc(&p->d_gh, p->nfine))) return rc;
+    if ((rc = p->alloc(&p->d_m, p->ndata))) return rc;
+    if ((rc = p->alloc(&p->d_pchi, std::max(1, nchi)))) return rc;
+    HIP_TRY(hipMemcpy(p->d_frp, p->frp.data(), sizeof(FrameDev) * E, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->d_pfwd, fw.data(), sizeof(Item) * fw.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->d_padj, ad.data(), sizeof(Item) * ad.size(), hipMemcpyHostToDevice));
+    HIP_TRY(launch_prep_kernels(p->st, p->d_frp, p->frp.data(), E, 1, p->psf_bound, p->d_pkf, p->d_pka));
+    HIP_TRY(hipStreamSynchronize(p->st));
+    p->plain_ready = true;
+    return STARRED_OK;
+}
+
+int starred_loss_grad_plain(starred_plan *p, const float *params, float *grad, double *loss_out)
+{
+    if (!p || !params || !loss_out) return fail(STARRED_EINVAL, "NULL argument");
+    if (p->mode != STARRED_DECONV) return fail(STARRED_EUNSUPPORTED, "the plain baseline is a deconvolution-mode path");
+    if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
+    if (!p->plain_ready) {
+        int rc = build_plain(p);
+        if (rc) return rc;
+    }
+    for (int i = 0; i < p->E; ++i) {
+        const FrameDev &f = p->fr[i];
+        HIP_TRY(launch_render_frame(p->st, p->d_fr, p->E, i, f.F, p->N, p->M, p->sigma, params, p->d_scene));
+        HIP_TRY(launch_fwd_direct(p->st, 1, p->d_frp, p->d_pfwd + p->pfwd_start[i],
+                                  p->pfwd_start[i + 1] - p->pfwd_start[i], p->pTmax, p->d_scene, p->d_pkf,
+                                  nullptr, nullptr, p->d_u, nullptr));
+        HIP_TRY(launch_plain_frame_ops(p->st, 0, p->d_fr, i, f.n, f.F, p->s, p->d_u, nullptr, nullptr, p->d_m,
+                                       nullptr));
+        HIP_TRY(launch_plain_frame_ops(p->st, 1, p->d_fr, i, f.n, f.F, p->s, p->d_m, p->data, p->invvar, p->d_rho,
+                                       p->d_pchi + p->pchi_start[i]));
+        if (grad) {
+            HIP_TRY(launch_plain_frame_ops(p->st, 2, p->d_fr, i, f.n, f.F, p->s, p->d_rho, nullptr, nullptr,
+                                           p->d_gh, nullptr));
+            HIP_TRY(launch_adj_direct(p->st, 1, p->d_frp, p->d_padj + p->padj_start[i],
+                                      p->padj_start[i + 1] - p->padj_start[i], p->pAr_max, p->pBpad_max, p->d_gh,
+                                      p->d_pka, p->d_g));
+            HIP_TRY(launch_frame_sums_one(p->st, p->d_fr, p->E, i, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum));
+        }
+    }
+    int n_l1 = 0;
+    HIP_TRY(launch_starlet_fwd(p->st, p->N, p->J, params, nullptr, grad ? p->d_z : nullptr, p->W, p->w_stride,
+                               (float)p->lam, p->d_ca, p->d_cb, p->d_tmp, p->d_part_l1, &n_l1));
+    if (grad) {
+        HIP_TRY(launch_starlet_adj(p->st, p->N, p->J, p->d_z, p->d_prior, p->d_ca, p->d_cb, p->d_tmp));
+        HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad));
+    }
+    HIP_TRY(launch_finalize_small(p->st, p->E, p->M, p->n_pchi, p->d_pchi, n_l1, p->d_part_l1, p->lam, p->d_fsum,
+                                  params, p->N, grad, loss_out));
+    return STARRED_OK;
+}
+
+// Run `body` through a captured HIP graph: replay the graph of `slot` when the
+// key (argument pointers and by-value parameters) matches, otherwise capture
+// the launch sequence on st (the forked starlet stream joins the capture
+// through its events) and instantiate it.
+extern "C++" {
+template <class Body>
+static int run_graph(starred_plan *p, int slot, const std::vector<uintptr_t> &key, Body body)
+{
+    auto &g = p->gs[slot];
+    if (!g.valid || g.key != key) {
+        if (g.x) (void)hipGraphExecDestroy(g.x);
+        if (g.g) (void)hipGraphDestroy(g.g);
+        g = starred_plan::GraphSlot();
+        const bool prof = p->prof_on;
+        p->prof_on = false;
+        HIP_TRY(hipStreamBeginCapture(p->st, hipStreamCaptureModeThreadLocal));
+        int rc = body();
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(p->st, &graph);
+        p->prof_on = prof;
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return fail_hip(e, "hipGraphInstantiate");
+        }
+        g.g = graph;
+        g.x = exec;
+        g.key = key;
+        g.valid = true;
+    }
+    hipEvent_t e0 = p->prof_start();
+    HIP_TRY(hipGraphLaunch(g.x, p->st));
+    p->prof_stop(STARRED_STAGE_GRAPH, e0);
+    return STARRED_OK;
+}
+}  // extern "C++"
+
 int starred_loss_grad(starred_plan *p, const float *params, float *grad, double *loss_out)
 {
     if (!p || !params || !loss_out) return fail(STARRED_EINVAL, "NULL argument");
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
-    if (p->mode == STARRED_PSF) return psf_loss_grad_impl(p, params, grad, loss_out);
-    return loss_grad_impl(p, params, grad, loss_out);
+    auto body = [&]() -> int {
+        return (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, grad, loss_out)
+                                         : loss_grad_impl(p, params, grad, loss_out);
+    };
+    if (!p->graph_mode) return body();
+    std::vector<uintptr_t> key = {(uintptr_t)params, (uintptr_t)grad, (uintptr_t)loss_out, (uintptr_t)p->algo};
+    return run_graph(p, 0, key, body);
 }
 
 int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
@@ -808,27 +1040,51 @@ int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
     if (!p || !params || !m || !v || !hp) return fail(STARRED_EINVAL, "NULL argument");
     if (t < 1) return fail(STARRED_EINVAL, "t must be >= 1");
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
-    int rc = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, p->d_grad, loss_out)
-                                      : loss_grad_impl(p, params, p->d_grad, loss_out);
-    if (rc) return rc;
-    const long long NN = (long long)p->N * p->N;
-    long long seg[3] = {NN, NN + p->E, NN + p->E + (long long)p->E * p->M};
-    if (p->mode == STARRED_PSF) {
-        seg[0] = 5;
-        seg[1] = 5 + NN;
-        seg[2] = 5 + NN + p->E;
+    // the device step counter is advanced inside the step; resynchronise it when
+    // the caller's step number is not the next one
+    if (t != p->next_t) HIP_TRY(launch_set_step(p->st, p->d_t, t - 1));
+    auto body = [&]() -> int {
+        int rc = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, p->d_grad, loss_out)
+                                          : loss_grad_impl(p, params, p->d_grad, loss_out);
+        if (rc) return rc;
+        const long long NN = (long long)p->N * p->N;
+        long long seg[3] = {NN, NN + p->E, NN + p->E + (long long)p->E * p->M};
+        if (p->mode == STARRED_PSF) {
+            seg[0] = 5;
+            seg[1] = 5 + NN;
+            seg[2] = 5 + NN + p->E;
+        }
+        hipEvent_t e0 = p->prof_start();
+        HIP_TRY(launch_adam(p->st, p->nparams, seg, hp->lr, params, p->d_grad, m, v, p->d_t, hp->beta1, hp->beta2,
+                            hp->eps));
+        p->prof_stop(STARRED_STAGE_ADAM, e0);
+        return STARRED_OK;
+    };
+    int rc;
+    if (!p->graph_mode) {
+        rc = body();
+    } else {
+        uint32_t hb[7];
+        memcpy(hb, hp->lr, sizeof(float) * 4);
+        memcpy(hb + 4, &hp->beta1, sizeof(float));
+        memcpy(hb + 5, &hp->beta2, sizeof(float));
+        memcpy(hb + 6, &hp->eps, sizeof(float));
+        std::vector<uintptr_t> key = {(uintptr_t)params, (uintptr_t)m, (uintptr_t)v, (uintptr_t)loss_out,
+                                      (uintptr_t)p->algo};
+        for (uint32_t x : hb) key.push_back(x);
+        rc = run_graph(p, 1, key, body);
     }
-    hipEvent_t e0 = p->prof_start();
-    HIP_TRY(launch_adam(p->st, p->nparams, seg, hp->lr, params, p->d_grad, m, v, t, hp->beta1, hp->beta2,
-                        hp->eps));
-    p->prof_stop(STARRED_STAGE_ADAM, e0);
+    if (rc) return rc;
+    p->next_t = t + 1;
     return STARRED_OK;
 }
 
 int starred_set_graph_mode(starred_plan *p, int32_t enable)
 {
     if (!p) return fail(STARRED_EINVAL, "plan is NULL");
-    if (enable) return fail(STARRED_EUNSUPPORTED, "graph mode is not available in this build");
+    if (enable && !p->st) return fail(STARRED_EUNSUPPORTED, "graph capture needs a non-default stream");
+    if (!enable) p->drop_graphs();
+    p->graph_mode = enable != 0;
     return STARRED_OK;
 }
 

@@ -19,26 +19,30 @@ namespace starred {
 constexpr int kPsfThreads = 256;
 constexpr int kPsfMaxT = 2 * kGaussRadius + 3 + 2;  // s <= 3
 
+// Moffat profile and its parameter derivatives at pixel (y, x). The profile's
+// wings enter the chi-square multiplied by star amplitudes up to 1e6, so the
+// transcendental part is evaluated in FP64 (N^2 evaluations per call) and rounded.
 __device__ __forceinline__ void moffat_eval(const float *eta, int N, int y, int x, float &m, float d[5])
 {
-    const float A = eta[0], ax = eta[1], ay = eta[2], phi = eta[3], beta = eta[4];
-    float sn, cs;
-    sincosf(phi, &sn, &cs);
-    const float dx = (float)(x - N / 2), dy = (float)(y - N / 2);
-    const float u = cs * dx + sn * dy;
-    const float v = -sn * dx + cs * dy;
-    const float qx = u / ax, qy = v / ay;
-    const float Q = qx * qx + qy * qy;
-    const float l1q = log1pf(Q);
-    const float base = expf(-beta * l1q);
-    m = A * base;
+    const double A = eta[0], ax = eta[1], ay = eta[2], phi = eta[3], beta = eta[4];
+    double sn, cs;
+    sincos(phi, &sn, &cs);
+    const double dx = (double)(x - N / 2), dy = (double)(y - N / 2);
+    const double u = cs * dx + sn * dy;
+    const double v = -sn * dx + cs * dy;
+    const double qx = u / ax, qy = v / ay;
+    const double Q = qx * qx + qy * qy;
+    const double l1q = log1p(Q);
+    const double base = exp(-beta * l1q);
+    const double md = A * base;
+    m = (float)md;
     if (d) {
-        const float dQ = -beta * m / (1.0f + Q);
-        d[0] = base;
-        d[1] = dQ * (-2.0f * u * u / (ax * ax * ax));
-        d[2] = dQ * (-2.0f * v * v / (ay * ay * ay));
-        d[3] = dQ * (2.0f * u * v * (1.0f / (ax * ax) - 1.0f / (ay * ay)));
-        d[4] = -m * l1q;
+        const double dQ = -beta * md / (1.0 + Q);
+        d[0] = (float)base;
+        d[1] = (float)(dQ * (-2.0 * u * u / (ax * ax * ax)));
+        d[2] = (float)(dQ * (-2.0 * v * v / (ay * ay * ay)));
+        d[3] = (float)(dQ * (2.0 * u * v * (1.0 / (ax * ax) - 1.0 / (ay * ay))));
+        d[4] = (float)(-md * l1q);
     }
 }
 
@@ -77,70 +81,120 @@ __device__ __forceinline__ void psf_taps(float c, int s, float sigma, int T, flo
     }
 }
 
-// One work group per star: unit model u, centre derivatives ux, uy; model,
-// residual rho = w (m - d), chi-square, and dchi/da, dchi/dc of the star.
-// params = [eta 5 | b N^2 | a S | c 2S]
+// FP64 copy of the narrow PSF for the forward model: with star amplitudes up to
+// 1e6 the chi-square near the truth is set by model errors far below an FP32
+// ulp of the brightest pixels, so the (small) PSF-mode forward runs in FP64.
+__global__ void k_psf_render64(int N, const float *__restrict__ params, double *__restrict__ s64)
+{
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= N * N) return;
+    const int y = pix / N, x = pix % N;
+    const double A = params[0], ax = params[1], ay = params[2], phi = params[3], beta = params[4];
+    double sn, cs;
+    sincos(phi, &sn, &cs);
+    const double dx = (double)(x - N / 2), dy = (double)(y - N / 2);
+    const double u = cs * dx + sn * dy, v = -sn * dx + cs * dy;
+    const double Q = (u / ax) * (u / ax) + (v / ay) * (v / ay);
+    s64[pix] = A * exp(-beta * log1p(Q)) + (double)params[5 + pix];
+}
+
+hipError_t launch_psf_render64(hipStream_t st, int N, const float *params, double *s64)
+{
+    hipLaunchKernelGGL(k_psf_render64, dim3((N * N + 255) / 256), dim3(256), 0, st, N, params, s64);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ void psf_taps64(double c, int s, double sigma, int T, double *G, double *dG)
+{
+    const double fc = floor(c);
+    const double inv2s2 = 1.0 / (2.0 * sigma * sigma), invs2 = 1.0 / (sigma * sigma);
+    const double norm = 1.0 / (2.5066282746310002 * sigma);
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        double g = 0.0, dg = 0.0;
+        for (int b = 0; b < s; ++b) {
+            const double arg = ((double)b + fc + (double)(kGaussRadius + 1 - t)) - c;
+            const double e = norm * exp(-arg * arg * inv2s2);
+            g += e;
+            dg += e * arg * invs2;
+        }
+        G[t] = g;
+        dG[t] = dg;
+    }
+}
+
+constexpr int kPsfRowChunk = 8;  // data rows per pass of the forward
+
+// One work group per star: unit model u and centre derivatives ux, uy (FP64),
+// residual rho = w (m - d) (stored FP32 for the adjoint), chi-square, and
+// dchi/da, dchi/dc of the star. params = [eta 5 | b N^2 | a S | c 2S]
 __global__ __launch_bounds__(kPsfThreads) void k_psf_fwd(
     int S, int n, int s, int N, float sigma, const float *__restrict__ params,
-    const float *__restrict__ s_img, const float *__restrict__ data, const float *__restrict__ invvar,
+    const double *__restrict__ s64, const float *__restrict__ data, const float *__restrict__ invvar,
     float *__restrict__ rho, double *__restrict__ part_chi, float *__restrict__ grad)
 {
-    extern __shared__ float sm[];
-    __shared__ float G[2][kPsfMaxT], dG[2][kPsfMaxT];
+    extern __shared__ double smd[];
+    __shared__ double G[2][kPsfMaxT], dG[2][kPsfMaxT];
     __shared__ double red[kPsfThreads / 64];
     const int k = blockIdx.x;
     const long long NN = (long long)N * N;
-    const float a = params[5 + NN + k];
-    const float cx = params[5 + NN + S + 2 * k], cy = params[5 + NN + S + 2 * k + 1];
+    const double a = params[5 + NN + k];
+    const double cx = params[5 + NN + S + 2 * k], cy = params[5 + NN + S + 2 * k + 1];
     const int T = 2 * kGaussRadius + s + 2;
-    psf_taps(cx, s, sigma, T, G[0], dG[0]);
-    psf_taps(cy, s, sigma, T, G[1], dG[1]);
+    psf_taps64(cx, s, (double)sigma, T, G[0], dG[0]);
+    psf_taps64(cy, s, (double)sigma, T, G[1], dG[1]);
     __syncthreads();
-    const int fx = (int)floorf(cx), fy = (int)floorf(cy);
-    // T1(y', q) = sum_u Gx[u] s(y', xb(q) + u), T1x with dGx  (N rows x n columns each)
-    float *T1 = sm;
-    float *T1x = sm + (long long)N * n;
-    for (int e = threadIdx.x; e < N * n; e += blockDim.x) {
-        const int yp = e / n, q = e - yp * n;
-        const int xb = s * q - fx - kGaussRadius - 1;
-        const float *row = s_img + (long long)yp * N;
-        float acc = 0.f, accx = 0.f;
-        for (int u = 0; u < T; ++u) {
-            const int xx = xb + u;
-            if (xx >= 0 && xx < N) {
-                const float v = row[xx];
-                acc = fmaf(G[0][u], v, acc);
-                accx = fmaf(dG[0][u], v, accx);
-            }
-        }
-        T1[e] = acc;
-        T1x[e] = accx;
-    }
-    __syncthreads();
+    const int fx = (int)floor(cx), fy = (int)floor(cy);
+    const int rows = kPsfRowChunk * s + T;  // grid rows one chunk of data rows needs
+    double *T1 = smd;
+    double *T1x = smd + (long long)rows * n;
     double chi = 0.0, sa = 0.0, sx = 0.0, sy = 0.0;
     const long long doff = (long long)k * n * n;
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int p = e / n, q = e - p * n;
-        const int yb = s * p - fy - kGaussRadius - 1;
-        float u = 0.f, ux = 0.f, uy = 0.f;
-        for (int t = 0; t < T; ++t) {
-            const int yy = yb + t;
-            if (yy >= 0 && yy < N) {
-                const float v = T1[yy * n + q];
-                u = fmaf(G[1][t], v, u);
-                uy = fmaf(dG[1][t], v, uy);
-                ux = fmaf(G[1][t], T1x[yy * n + q], ux);
+    for (int p0 = 0; p0 < n; p0 += kPsfRowChunk) {
+        const int y0 = s * p0 - fy - kGaussRadius - 1;  // grid row of T1 row 0
+        __syncthreads();
+        // T1(y', q) = sum_u Gx[u] s(y', xb(q) + u), T1x with dGx
+        for (int e = threadIdx.x; e < rows * n; e += blockDim.x) {
+            const int r = e / n, q = e - r * n;
+            const int yp = y0 + r;
+            double acc = 0.0, accx = 0.0;
+            if (yp >= 0 && yp < N) {
+                const int xb = s * q - fx - kGaussRadius - 1;
+                const double *row = s64 + (long long)yp * N;
+                for (int u = 0; u < T; ++u) {
+                    const int xx = xb + u;
+                    if (xx >= 0 && xx < N) {
+                        const double v = row[xx];
+                        acc = fma(G[0][u], v, acc);
+                        accx = fma(dG[0][u], v, accx);
+                    }
+                }
             }
+            T1[e] = acc;
+            T1x[e] = accx;
         }
-        const float m = a * u;
-        const float r = m - data[doff + e];
-        const float w = invvar[doff + e];
-        const float rh = w * r;
-        rho[doff + e] = rh;
-        chi += 0.5 * (double)w * (double)r * (double)r;
-        sa += (double)(rh * u);
-        sx += (double)(rh * ux);
-        sy += (double)(rh * uy);
+        __syncthreads();
+        const int np = min(kPsfRowChunk, n - p0);
+        for (int e = threadIdx.x; e < np * n; e += blockDim.x) {
+            const int pl = e / n, q = e - pl * n;
+            const int p = p0 + pl;
+            const int rb = s * pl;  // T1 row of tap 0 for this data row
+            double u = 0.0, ux = 0.0, uy = 0.0;
+            for (int t = 0; t < T; ++t) {
+                const double v = T1[(rb + t) * n + q];
+                u = fma(G[1][t], v, u);
+                uy = fma(dG[1][t], v, uy);
+                ux = fma(G[1][t], T1x[(rb + t) * n + q], ux);
+            }
+            const long long idx = doff + (long long)p * n + q;
+            const double r = a * u - (double)data[idx];
+            const double w = invvar[idx];
+            const double rh = w * r;
+            rho[idx] = (float)rh;
+            chi += 0.5 * w * r * r;
+            sa += rh * u;
+            sx += rh * ux;
+            sy += rh * uy;
+        }
     }
     chi = block_sum_d_fft(chi, red);
     sa = block_sum_d_fft(sa, red);
@@ -150,8 +204,8 @@ __global__ __launch_bounds__(kPsfThreads) void k_psf_fwd(
         if (part_chi) part_chi[k] = chi;
         if (grad) {
             grad[5 + NN + k] = (float)sa;
-            grad[5 + NN + S + 2 * k] = (float)((double)a * sx);
-            grad[5 + NN + S + 2 * k + 1] = (float)((double)a * sy);
+            grad[5 + NN + S + 2 * k] = (float)(a * sx);
+            grad[5 + NN + S + 2 * k + 1] = (float)(a * sy);
         }
     }
 }
@@ -304,15 +358,15 @@ __global__ __launch_bounds__(256) void k_psf_finalize_small(int S, int n_chi, co
     }
 }
 
-size_t psf_fwd_lds(int n, int N) { return (size_t)2 * N * n * sizeof(float); }
+size_t psf_fwd_lds(int n, int s) { return (size_t)2 * (kPsfRowChunk * s + 2 * kGaussRadius + s + 2) * n * sizeof(double); }
 size_t psf_adj_lds(int n, int N) { return (size_t)n * N * sizeof(float); }
 
 hipError_t launch_psf_fwd(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
-                          const float *s_img, const float *data, const float *invvar, float *rho,
+                          const double *s64, const float *data, const float *invvar, float *rho,
                           double *part_chi, float *grad)
 {
-    hipLaunchKernelGGL(k_psf_fwd, dim3(S), dim3(kPsfThreads), psf_fwd_lds(n, N), st, S, n, ss, N, sigma, params,
-                       s_img, data, invvar, rho, part_chi, grad);
+    hipLaunchKernelGGL(k_psf_fwd, dim3(S), dim3(kPsfThreads), psf_fwd_lds(n, ss), st, S, n, ss, N, sigma, params,
+                       s64, data, invvar, rho, part_chi, grad);
     return hipGetLastError();
 }
 

@@ -25,9 +25,10 @@ EXPORTED = [
     "starred_convolve_subsample", "starred_convolve_subsample_adj", "starred_starlet_fwd",
     "starred_starlet_adj", "starred_loss_grad", "starred_step", "starred_set_graph_mode",
     "starred_conv_algo", "starred_last_error", "starred_abi_version", "starred_set_profiling",
-    "starred_profile_read", "starred_psf_model",
+    "starred_profile_read", "starred_psf_model", "starred_loss_grad_plain",
 ]
-STAGES = ["render", "conv_fwd", "conv_adj", "grad_sums", "starlet", "finalize", "adam", "spectra"]
+STAGES = ["render", "conv_fwd", "conv_adj", "grad_sums", "starlet", "finalize", "adam", "spectra",
+          "graph"]
 
 
 class Desc(ctypes.Structure):
@@ -79,6 +80,7 @@ def lib():
         L.starred_set_profiling.argtypes = [vp, i32]
         L.starred_profile_read.argtypes = [vp, vp, vp]
         L.starred_psf_model.argtypes = [vp, vp, vp]
+        L.starred_loss_grad_plain.argtypes = [vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -217,6 +219,17 @@ class Plan:
             grad = grad_out if grad_out is not None else torch.empty(self.n_params, dtype=torch.float32,
                                                                       device=self.device)
         self._call(lib().starred_loss_grad, _ptr(params), _ptr(grad), _ptr(loss))
+        return loss, grad
+
+    def loss_grad_plain(self, params, want_grad=True, grad_out=None, loss_out=None):
+        """The unfused per-epoch baseline (same results, one launch per operator per frame)."""
+        params = _f32(params, self.device)
+        loss = loss_out if loss_out is not None else torch.empty(3, dtype=torch.float64, device=self.device)
+        grad = None
+        if want_grad:
+            grad = grad_out if grad_out is not None else torch.empty(self.n_params, dtype=torch.float32,
+                                                                      device=self.device)
+        self._call(lib().starred_loss_grad_plain, _ptr(params), _ptr(grad), _ptr(loss))
         return loss, grad
 
     def step(self, params, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, loss_out=None):

@@ -368,3 +368,79 @@ def test_psf_line_search_evaluations_forward_only():
             break
         step *= 0.5
     assert f1 < f0
+
+
+# --------------------------------------------------------------------------- #
+# The plain per-epoch baseline computes the same loss and gradient             #
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("name,make", [LG_CASES[0], LG_CASES[1], LG_CASES[3]],
+                         ids=[LG_CASES[i][0] for i in (0, 1, 3)])
+def test_plain_baseline_parity(name, make):
+    prob = make()
+    d, w, rng = _data(prob, seed=7)
+    plan = _plan(prob, d, w, 1)
+    p = synth.eval_point(prob, "near", rng)
+    loss, grad = plan.loss_grad_plain(p)
+    loss = loss.cpu().numpy()
+    grad = grad.cpu().numpy().astype(np.float64)
+    NN = prob.N * prob.N
+    so, _ = parity.tie_override(prob.N, prob.J, p[:NN], plan.starlet_fwd(p[:NN]).cpu().numpy())
+    lo, go = ora.loss_grad(prob, d, w, p, sgn_override=so)
+    rl = abs(loss[2] - lo[2]) / abs(lo[2])
+    rg = parity.rel_err(grad, go)
+    _say(f"plain {name}: loss rel {rl:.2e} grad rel {rg:.2e}")
+    assert rl <= 1e-6 and rg <= 1e-4
+
+
+# --------------------------------------------------------------------------- #
+# Graph mode: every replay equals the eager result                             #
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+def test_graph_replays_match_eager(algo):
+    st = _st()
+    prob = synth.make_deconv(2, E=8)
+    d, w, rng = _data(prob, seed=8)
+    p = torch.tensor(synth.eval_point(prob, "near", rng), dtype=torch.float32, device="cuda")
+    plan = _plan(prob, d, w, algo)
+    le, ge = plan.loss_grad(p)
+    le, ge = le.clone(), ge.clone()
+    plan.set_graph_mode(True)
+    loss = torch.empty(3, dtype=torch.float64, device="cuda")
+    grad = torch.empty(prob.n_params, dtype=torch.float32, device="cuda")
+    for rep in range(4):
+        loss.fill_(-1.0)
+        grad.fill_(-1.0)
+        plan.loss_grad(p, grad_out=grad, loss_out=loss)
+        torch.cuda.synchronize()
+        _ = (torch.randn(1000, device="cuda") * 2).sum().item()  # eager work between replays
+        assert torch.equal(loss, le), rep
+        assert torch.equal(grad, ge), rep
+    # optimiser steps: graph replays vs eager steps from the same state
+    lr4 = [prob.adam_lr[k] for k in ("h", "Gamma", "a", "c")]
+    xg, xe = p.clone(), p.clone()
+    mg, vg = torch.zeros_like(p), torch.zeros_like(p)
+    me, ve = torch.zeros_like(p), torch.zeros_like(p)
+    plan2 = _plan(prob, d, w, algo)
+    for t in range(1, 6):
+        plan.step(xg, mg, vg, t, lr4, loss_out=loss)
+        plan2.step(xe, me, ve, t, lr4)
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xe), t
+        assert torch.equal(mg, me) and torch.equal(vg, ve), t
+
+
+def test_graph_mode_psf():
+    prob, d, w, rng, plan = _psf_setup(dict(S=4, n=16, s=3, J=4), 44)
+    p = torch.tensor(synth.psf_eval_point(prob, "near", rng), dtype=torch.float32, device="cuda")
+    le, ge = plan.loss_grad(p)
+    le, ge = le.clone(), ge.clone()
+    plan.set_graph_mode(True)
+    loss = torch.empty(3, dtype=torch.float64, device="cuda")
+    grad = torch.empty(prob.n_params, dtype=torch.float32, device="cuda")
+    for rep in range(3):
+        grad.fill_(0.0)
+        plan.loss_grad(p, grad_out=grad, loss_out=loss)
+        torch.cuda.synchronize()
+        assert torch.equal(loss, le) and torch.equal(grad, ge), rep
