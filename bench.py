@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--algo", default="auto", choices=["auto", "direct", "fft"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-baseline comparison")
+    ap.add_argument("--copy-calibrate", action="store_true",
+                    help="also run one plain 256 MiB device copy (memory-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
@@ -131,14 +134,21 @@ def main():
     torch.cuda.synchronize()
     fused_eps = n_fused / (time.perf_counter() - t0)
     plan.set_graph_mode(False)
-    plan.loss_grad_plain(x, grad_out=grad, loss_out=loss)
-    torch.cuda.synchronize()
-    n_plain = 5
-    t0 = time.perf_counter()
-    for _ in range(n_plain):
+    plain_eps = None
+    if not args.no_plain:
         plan.loss_grad_plain(x, grad_out=grad, loss_out=loss)
-    torch.cuda.synchronize()
-    plain_eps = n_plain / (time.perf_counter() - t0)
+        torch.cuda.synchronize()
+        n_plain = 5
+        t0 = time.perf_counter()
+        for _ in range(n_plain):
+            plan.loss_grad_plain(x, grad_out=grad, loss_out=loss)
+        torch.cuda.synchronize()
+        plain_eps = n_plain / (time.perf_counter() - t0)
+    if args.copy_calibrate:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        plan.copy_probe(src, dst)
+        torch.cuda.synchronize()
 
     # ---- stage timing (eager launches, HIP events on the launching streams) ----
     n_prof = max(10, min(args.steps, 50))
@@ -163,11 +173,11 @@ def main():
                    "conv_algo": {1: "direct", 2: "fft"}.get(plan.conv_algo, "?"),
                    "graph": not args.no_graph},
         "evals_per_s_step": args.steps / el,
-        "fused_vs_plain": {"fused_loss_grad_evals_per_s": fused_eps,
-                           "plain_loss_grad_evals_per_s": plain_eps,
-                           "fused_epoch_px_per_s": fused_eps * prob.data_size,
-                           "plain_epoch_px_per_s": plain_eps * prob.data_size,
-                           "speedup": fused_eps / plain_eps},
+        "fused_vs_plain": ({"fused_loss_grad_evals_per_s": fused_eps,
+                            "plain_loss_grad_evals_per_s": plain_eps,
+                            "fused_epoch_px_per_s": fused_eps * prob.data_size,
+                            "plain_epoch_px_per_s": plain_eps * prob.data_size,
+                            "speedup": fused_eps / plain_eps} if plain_eps else None),
         "stage_ms_per_step": {k: round(v_, 4) for k, v_ in stage_ms.items()},
         "roofline": roof,
     }

@@ -191,10 +191,21 @@ enum {
     STARRED_STAGE_ADAM,         /* optimiser update */
     STARRED_STAGE_SPECTRA,      /* FFT path: spectra shared by all frames */
     STARRED_STAGE_GRAPH,        /* graph mode: one whole captured loss_grad or step */
+    STARRED_STAGE_FFT_SPEC,     /* FFT path, inside CONV_FWD: spectral product and alias fold */
+    STARRED_STAGE_FFT_MCOLS,    /* ... inverse along the first axis of the model spectra */
+    STARRED_STAGE_FFT_MROWS,    /* ... inverse rows, residual, chi-square, forward rows of rho */
+    STARRED_STAGE_FFT_RCOLS,    /* FFT path, inside CONV_ADJ: forward columns of rho */
+    STARRED_STAGE_FFT_ACOLS,    /* ... kernel-spectrum product and inverse columns */
+    STARRED_STAGE_FFT_AROWS,    /* ... inverse rows of the adjoint images and their sums */
     STARRED_NUM_STAGES
 };
 int starred_set_profiling(starred_plan *plan, int32_t enable);
 int starred_profile_read(starred_plan *plan, double *ms_out, int64_t *count_out);
+
+/* Measurement aid: a plain device copy of n floats (n a multiple of 4) from src to
+ * dst on the plan's stream; its memory-counter readings calibrate the ones of the
+ * library's kernels. */
+int starred_copy_probe(starred_plan *plan, const float *src, float *dst, int64_t n);
 
 const char *starred_last_error(void);
 int starred_abi_version(void);

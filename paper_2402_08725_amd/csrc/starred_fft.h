@@ -28,6 +28,8 @@ struct ClassFft {
     long long hh_off;   // [P][P/2+1]   spectrum of the h window
     long long tab_off;  // [(1 + 2M) P] window and point-source factor tables
     float sscale;       // 1 / (s^2 Q^2)
+    int cf_off;         // first entry of this class in the class-ordered frame list
+    int ncf;            // number of frames of the class
     int pad;
 };
 
@@ -51,6 +53,14 @@ struct LineItem {
     int nl;
 };
 
+// A block of output bins of one class and a chunk of that class's frames.
+struct SpecItem {
+    int cls;
+    int f0;
+    int nf;
+    int bin0;
+};
+
 struct LinePass {
     LineItem *items = nullptr;  // device
     int n_items = 0;
@@ -65,6 +75,13 @@ struct FftPlanDev {
     float2 *S = nullptr, *T = nullptr, *T2 = nullptr, *Rh = nullptr, *T3 = nullptr;
     float2 *Th = nullptr, *Hh = nullptr, *tab = nullptr;
     LinePass hrows, hcols, krows, kcols, fcols, frows, rrows, rcols, acols, arows, srows, scols;
+    SpecItem *spec = nullptr;
+    int n_spec = 0;
+    int *cls_frames = nullptr;
+    // per-frame sums of g from the adjoint row pass: partial per line group and,
+    // for each frame, the list of its groups (CSR)
+    double *gpart = nullptr;
+    int *gcsr_off = nullptr, *gcsr_item = nullptr;
 };
 
 // Deterministic block sum of one double per thread (kFftThreads); thread 0 holds it.
@@ -87,8 +104,13 @@ __device__ __forceinline__ double block_sum_d_fft(double v, double *sh)
 hipError_t fft_prep_kernels(hipStream_t st, const FftPlanDev &d, const float *psf, int s);
 hipError_t fft_spectra(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M,
                        float sigma);
-hipError_t fft_forward(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,
-                       const float *data, const float *invvar, double *part_chi, float *model);
+hipError_t fft_spec_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s);
+hipError_t fft_model_cols(hipStream_t st, const FftPlanDev &d);
+hipError_t fft_model_rows(hipStream_t st, const FftPlanDev &d, const float *data, const float *invvar,
+                          double *part_chi, float *model);
+hipError_t fft_rho_cols(hipStream_t st, const FftPlanDev &d);
+hipError_t fft_adj_cols(hipStream_t st, const FftPlanDev &d);
+hipError_t fft_adj_rows(hipStream_t st, const FftPlanDev &d, float *g);
 hipError_t fft_resid_rows(hipStream_t st, const FftPlanDev &d, const float *resid);
 hipError_t fft_adjoint(hipStream_t st, const FftPlanDev &d, float *g);
 hipError_t fft_scene_model(hipStream_t st, const FftPlanDev &d, const float *scene, int s, float *model);

@@ -116,7 +116,7 @@ __device__ __forceinline__ void stockham_stage(const float2 *__restrict__ src, f
         if (Ns > 1) {
             #pragma unroll
             for (int r = 1; r < R; ++r) {
-                const float2 t = tw[(r * k * twstep) % L];
+                const float2 t = tw[r * k * twstep];  // r k twstep < L
                 v[r] = inv ? cmulc(v[r], t) : cmul(v[r], t);
             }
         }
@@ -150,6 +150,96 @@ __device__ float2 *lds_fft(float2 *a, float2 *b, int nl, const FftLen &f, const 
     return a;
 }
 
+// Compile-time transforms for the lengths the workloads use: with L and the
+// stage parameters constant, every index division becomes a multiply-shift.
+constexpr int ct_nrad(int L)
+{
+    int n = 0;
+    while (L % 4 == 0) { L /= 4; ++n; }
+    while (L % 2 == 0) { L /= 2; ++n; }
+    while (L % 3 == 0) { L /= 3; ++n; }
+    while (L % 5 == 0) { L /= 5; ++n; }
+    return n;
+}
+constexpr int ct_rad(int L, int i)
+{
+    int k = 0;
+    while (L % 4 == 0) { if (k++ == i) return 4; L /= 4; }
+    while (L % 2 == 0) { if (k++ == i) return 2; L /= 2; }
+    while (L % 3 == 0) { if (k++ == i) return 3; L /= 3; }
+    while (L % 5 == 0) { if (k++ == i) return 5; L /= 5; }
+    return 1;
+}
+constexpr int ct_ns(int L, int i)
+{
+    int ns = 1;
+    for (int k = 0; k < i; ++k) ns *= ct_rad(L, k);
+    return ns;
+}
+
+template <int R, int L, int NS, bool INV>
+__device__ __forceinline__ void stage_ct(const float2 *__restrict__ src, float2 *__restrict__ dst, int nl,
+                                         const float2 *__restrict__ tw)
+{
+    constexpr int LR = L / R, Ls = L + 1, TS = L / (NS * R);
+    for (int b = threadIdx.x; b < nl * LR; b += blockDim.x) {
+        const int l = b / LR, j = b - l * LR;
+        const float2 *in = src + l * Ls;
+        float2 *out = dst + l * Ls;
+        const int k = j % NS;
+        float2 v[5];
+        #pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = in[j + r * LR];
+        if (NS > 1) {
+            #pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const float2 t = tw[r * k * TS];  // r k TS < L
+                v[r] = INV ? cmulc(v[r], t) : cmul(v[r], t);
+            }
+        }
+        dft_small<R>(v, INV);
+        const int idxD = (j / NS) * NS * R + k;
+        #pragma unroll
+        for (int r = 0; r < R; ++r) out[idxD + r * NS] = v[r];
+    }
+}
+
+template <int L, bool INV, int I = 0>
+__device__ __forceinline__ float2 *fft_ct(float2 *a, float2 *b, int nl, const float2 *__restrict__ tw)
+{
+    if constexpr (I == ct_nrad(L)) {
+        return a;
+    } else {
+        stage_ct<ct_rad(L, I), L, ct_ns(L, I), INV>(a, b, nl, tw);
+        __syncthreads();
+        return fft_ct<L, INV, I + 1>(b, a, nl, tw);
+    }
+}
+
+// Transform dispatch: compile-time bodies for the common lengths, the runtime
+// Stockham loop otherwise.
+template <bool INV>
+__device__ __forceinline__ float2 *lds_fft_any(float2 *a, float2 *b, int nl, const FftLen &f,
+                                            const float2 *__restrict__ tw)
+{
+    switch (f.L) {
+    case 48: return fft_ct<48, INV>(a, b, nl, tw);
+    case 64: return fft_ct<64, INV>(a, b, nl, tw);
+    case 72: return fft_ct<72, INV>(a, b, nl, tw);
+    case 96: return fft_ct<96, INV>(a, b, nl, tw);
+    case 128: return fft_ct<128, INV>(a, b, nl, tw);
+    case 144: return fft_ct<144, INV>(a, b, nl, tw);
+    case 160: return fft_ct<160, INV>(a, b, nl, tw);
+    case 192: return fft_ct<192, INV>(a, b, nl, tw);
+    case 256: return fft_ct<256, INV>(a, b, nl, tw);
+    case 288: return fft_ct<288, INV>(a, b, nl, tw);
+    case 320: return fft_ct<320, INV>(a, b, nl, tw);
+    case 384: return fft_ct<384, INV>(a, b, nl, tw);
+    case 576: return fft_ct<576, INV>(a, b, nl, tw);
+    default: return lds_fft(a, b, nl, f, tw, INV);
+    }
+}
+
 // --------------------------------------------------------------------------
 // Generic line pass: load -> FFT -> store, for a table of line groups
 // --------------------------------------------------------------------------
@@ -162,7 +252,7 @@ __global__ __launch_bounds__(kFftThreads) void k_lines(const LineItem *__restric
     extern __shared__ float2 sm[];
     const LineItem it = items[blockIdx.x];
     const ClassFft &cl = classes[it.cls];
-    const FftLen f = op.len(cl);
+    const FftLen &f = op.len(cl);
     const int Ls = f.L + 1;
     float2 *a = sm;
     float2 *b = sm + it.nl * Ls;
@@ -176,12 +266,21 @@ __global__ __launch_bounds__(kFftThreads) void k_lines(const LineItem *__restric
         a[l * Ls + j] = op.load(cl, it.frame, it.line0 + l, j);
     }
     __syncthreads();
-    float2 *r = lds_fft(a, b, it.nl, f, tw + f.tw_off, op.inverse);
+    float2 *r = lds_fft_any<Op::inverse>(a, b, it.nl, f, tw + f.tw_off);
+    double acc = 0.0;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
         int l, j;
         if (Op::col) { l = e % it.nl; j = e / it.nl; }
         else { l = e / f.L; j = e - l * f.L; }
-        op.store(cl, it.frame, it.line0 + l, j, r[l * Ls + j]);
+        if constexpr (Op::rowsum)
+            acc += (double)op.store(cl, it.frame, it.line0 + l, j, r[l * Ls + j]);
+        else
+            op.store(cl, it.frame, it.line0 + l, j, r[l * Ls + j]);
+    }
+    if constexpr (Op::rowsum) {
+        __shared__ double red[kFftThreads / 64];
+        const double tot_sum = block_sum_d_fft(acc, red);
+        if (threadIdx.x == 0) op.gpart[blockIdx.x] = tot_sum;
     }
 }
 
@@ -201,8 +300,9 @@ struct OpHRows {
     int N;
     float2 *Th;
     static constexpr bool col = false;
+    static constexpr bool rowsum = false;
     static constexpr bool inverse = false;
-    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int, int y, int x) const
     {
         return make_float2(x < c.F ? h[(long long)(c.o + y) * N + c.o + x] : 0.f, 0.f);
@@ -219,8 +319,9 @@ struct OpHCols {
     const float2 *Th;
     float2 *Hh;
     static constexpr bool col = true;
+    static constexpr bool rowsum = false;
     static constexpr bool inverse = false;
-    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int, int kx, int y) const
     {
         const int H = c.P / 2 + 1;
@@ -240,8 +341,9 @@ struct OpKRows {
     int s;
     float2 *TS;
     static constexpr bool col = false;
+    static constexpr bool rowsum = false;
     static constexpr bool inverse = false;
-    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int i, int y, int x) const
     {
         const FrameFft &f = fr[i];
@@ -270,8 +372,9 @@ struct OpKCols {
     const float2 *TS;
     float2 *S;
     static constexpr bool col = true;
+    static constexpr bool rowsum = false;
     static constexpr bool inverse = false;
-    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int i, int kx, int y) const
     {
         const int H = c.P / 2 + 1;
@@ -295,8 +398,9 @@ struct OpFwdCols {
     float2 *T;
     const float2 *scene_spec;  // per-frame scene spectra (standalone operator) or NULL
     static constexpr bool col = true;
+    static constexpr bool rowsum = false;
     static constexpr bool inverse = true;
-    __device__ FftLen len(const ClassFft &c) const { return c.fQ; }
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fQ; }
     // scene spectrum at K (any Kx in [0,P)): Gamma w(Ky) w(Kx) + H(K) + sum_k a g_y(Ky) g_x(Kx)
     __device__ float2 scene_hat(const ClassFft &c, int i, int Ky, int Kx) const
     {
@@ -333,14 +437,94 @@ struct OpFwdCols {
     }
 };
 
+// ---- forward spectral product: M_hat_i(k) = sum over the s^2 aliases of
+// S''_i(K) F_i(K), F_i = H + Gamma_i w x w + sum_k a_ik gy_k x gx_k (Eq. 9).
+// One thread per output bin of a class, looping over a chunk of its frames, so
+// the shared spectra of the bin's aliases are read once per chunk. ----
+template <int S>
+__global__ __launch_bounds__(kFftThreads) void k_spec_fwd(const SpecItem *__restrict__ items,
+                                                          const ClassFft *__restrict__ classes,
+                                                          const FrameFft *__restrict__ fr,
+                                                          const int *__restrict__ cls_frames,
+                                                          const float2 *__restrict__ Sp,
+                                                          const float2 *__restrict__ Hh,
+                                                          const float2 *__restrict__ tab,
+                                                          const float *__restrict__ params, int N, int E, int M,
+                                                          float2 *__restrict__ Mh)
+{
+    const SpecItem it = items[blockIdx.x];
+    const ClassFft &c = classes[it.cls];
+    const int P = c.P, Q = c.Q, HQ = Q / 2 + 1;
+    const int bin = it.bin0 + threadIdx.x;
+    if (bin >= Q * HQ) return;
+    const int ky = bin / HQ, kx = bin - ky * HQ;
+    const float2 *t = tab + c.tab_off;
+    float2 hv[S * S], wv[S * S];
+    int Kys[S], Kxs[S];
+    #pragma unroll
+    for (int a = 0; a < S; ++a) {
+        Kys[a] = ky + a * Q;
+        Kxs[a] = kx + a * Q;
+    }
+    #pragma unroll
+    for (int a = 0; a < S; ++a)
+        #pragma unroll
+        for (int b = 0; b < S; ++b) {
+            hv[a * S + b] = half_get(Hh + c.hh_off, P, Kys[a], Kxs[b]);
+            wv[a * S + b] = cmul(t[Kys[a]], t[Kxs[b]]);
+        }
+    for (int f = it.f0; f < it.f0 + it.nf; ++f) {
+        const int i = cls_frames[c.cf_off + f];
+        const FrameFft &fi = fr[i];
+        const float G = params[(long long)N * N + i];
+        const float *ai = params + (long long)N * N + E + (long long)i * M;
+        const float2 *Si = Sp + fi.s_off;
+        float2 acc = make_float2(0.f, 0.f);
+        #pragma unroll
+        for (int a = 0; a < S; ++a)
+            #pragma unroll
+            for (int b = 0; b < S; ++b) {
+                float2 F = cadd(hv[a * S + b], cscale(wv[a * S + b], G));
+                for (int k = 0; k < M; ++k) {
+                    const float2 *tk = t + (long long)(1 + 2 * k) * P;  // [gx | gy]
+                    F = cadd(F, cscale(cmul(tk[P + Kys[a]], tk[Kxs[b]]), ai[k]));
+                }
+                acc = cadd(acc, cmul(half_get(Si, P, Kys[a], Kxs[b]), F));
+            }
+        Mh[fi.r_off + bin] = acc;
+    }
+}
+
+// ---- inverse along ky of M_hat -> rows of the model spectra ----
+struct OpMCols {
+    const FrameFft *fr;
+    const float2 *Mh;
+    float2 *T;
+    static constexpr bool col = true;
+    static constexpr bool rowsum = false;
+    static constexpr bool inverse = true;
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fQ; }
+    __device__ float2 load(const ClassFft &c, int i, int kx, int ky) const
+    {
+        const int H = c.Q / 2 + 1;
+        return Mh[fr[i].r_off + (long long)ky * H + kx];
+    }
+    __device__ void store(const ClassFft &c, int i, int kx, int y, float2 v) const
+    {
+        const int H = c.Q / 2 + 1;
+        if (y < c.n) T[fr[i].t_off + (long long)y * H + kx] = v;
+    }
+};
+
 // ---- pass F: forward along ky of the rho row spectra -> rho_hat[Q][Q/2+1] ----
 struct OpRhoCols {
     const FrameFft *fr;
     const float2 *T2;
     float2 *Rh;
     static constexpr bool col = true;
+    static constexpr bool rowsum = false;
     static constexpr bool inverse = false;
-    __device__ FftLen len(const ClassFft &c) const { return c.fQ; }
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fQ; }
     __device__ float2 load(const ClassFft &c, int i, int kx, int y) const
     {
         const int H = c.Q / 2 + 1;
@@ -360,8 +544,9 @@ struct OpAdjCols {
     const float2 *Rh;
     float2 *T3;
     static constexpr bool col = true;
+    static constexpr bool rowsum = false;
     static constexpr bool inverse = true;
-    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int i, int Kx, int Ky) const
     {
         const FrameFft &f = fr[i];
@@ -383,18 +568,22 @@ struct OpAdjRows {
     const FrameFft *fr;
     const float2 *T3;
     float *g;
+    double *gpart;  // one partial sum of g per work group
     static constexpr bool col = false;
+    static constexpr bool rowsum = true;  // per-group sum of g: the frame sums for Gamma
     static constexpr bool inverse = true;
-    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int i, int y, int Kx) const
     {
         const int P = c.P, H = P / 2 + 1;
         const float2 *row = T3 + fr[i].t3_off + (long long)y * H;
         return Kx < H ? row[Kx] : conjf2(row[P - Kx]);
     }
-    __device__ void store(const ClassFft &c, int i, int y, int x, float2 v) const
+    __device__ float store(const ClassFft &c, int i, int y, int x, float2 v) const
     {
-        if (x < c.F) g[fr[i].fine_off + (long long)y * c.F + x] = v.x;
+        if (x >= c.F) return 0.f;
+        g[fr[i].fine_off + (long long)y * c.F + x] = v.x;
+        return v.x;
     }
 };
 
@@ -404,8 +593,9 @@ struct OpResidRows {
     const float *resid;
     float2 *T2;
     static constexpr bool col = false;
+    static constexpr bool rowsum = false;
     static constexpr bool inverse = false;
-    __device__ FftLen len(const ClassFft &c) const { return c.fQ; }
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fQ; }
     __device__ float2 load(const ClassFft &c, int i, int y, int x) const
     {
         return make_float2(x < c.n ? resid[fr[i].data_off + (long long)y * c.n + x] : 0.f, 0.f);
@@ -423,8 +613,9 @@ struct OpSceneRows {
     const float *scene;
     float2 *T3;
     static constexpr bool col = false;
+    static constexpr bool rowsum = false;
     static constexpr bool inverse = false;
-    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int i, int y, int x) const
     {
         return make_float2(x < c.F ? scene[fr[i].fine_off + (long long)y * c.F + x] : 0.f, 0.f);
@@ -440,8 +631,9 @@ struct OpSceneCols {  // every column is read and written by the same work group
     const FrameFft *fr;
     float2 *T3;
     static constexpr bool col = true;
+    static constexpr bool rowsum = false;
     static constexpr bool inverse = false;
-    __device__ FftLen len(const ClassFft &c) const { return c.fP; }
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int i, int kx, int y) const
     {
         const int H = c.P / 2 + 1;
@@ -470,7 +662,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
     const LineItem it = items[blockIdx.x];
     const ClassFft &c = classes[it.cls];
     const FrameFft &f = fr[it.frame];
-    const FftLen fl = c.fQ;
+    const FftLen &fl = c.fQ;
     const int Q = c.Q, H = Q / 2 + 1, n = c.n, Ls = Q + 1;
     float2 *a = sm;
     float2 *b = sm + it.nl * Ls;
@@ -481,7 +673,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
         a[l * Ls + kx] = kx < H ? row[kx] : conjf2(row[Q - kx]);
     }
     __syncthreads();
-    float2 *r = lds_fft(a, b, it.nl, fl, tw + fl.tw_off, true);
+    float2 *r = lds_fft_any<true>(a, b, it.nl, fl, tw + fl.tw_off);
     float2 *o = (r == a) ? b : a;
     double chi = 0.0;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
@@ -506,7 +698,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
     if (threadIdx.x == 0 && part_chi) part_chi[blockIdx.x] = tchi;
     if (model) return;
     __syncthreads();
-    float2 *q = lds_fft(o, r, it.nl, fl, tw + fl.tw_off, false);
+    float2 *q = lds_fft_any<false>(o, r, it.nl, fl, tw + fl.tw_off);
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
         const int l = e / Q, kx = e - l * Q;
         if (kx < H) T2[f.t_off + (long long)(it.line0 + l) * H + kx] = q[l * Ls + kx];
@@ -577,25 +769,40 @@ hipError_t fft_spectra(hipStream_t st, const FftPlanDev &d, const float *params,
     e = run_lines(st, d.hcols, d.classes, d.tw, OpHCols{d.Th, d.Hh});
     if (e != hipSuccess) return e;
     if (M > 0) {
-        hipLaunchKernelGGL(k_tables, dim3(d.n_classes, 4), dim3(256), 0, st, d.classes, d.tw, params, N, E, M,
+        hipLaunchKernelGGL(k_tables, dim3(d.n_classes, 16), dim3(256), 0, st, d.classes, d.tw, params, N, E, M,
                            sigma, d.tab);
         e = hipGetLastError();
     }
     return e;
 }
 
-hipError_t fft_forward(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,
-                       const float *data, const float *invvar, double *part_chi, float *model)
+hipError_t fft_spec_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s)
 {
-    hipError_t e = run_lines(st, d.fcols, d.classes, d.tw,
-                             OpFwdCols{d.frames, d.S, d.Hh, d.tab, params, N, E, M, s, d.T, nullptr});
-    if (e != hipSuccess) return e;
-    if (d.frows.n_items > 0) {
-        hipLaunchKernelGGL(k_fwd_rows, dim3(d.frows.n_items), dim3(kFftThreads), d.frows.lds_bytes, st,
-                           d.frows.items, d.classes, d.frames, d.tw, d.T, data, invvar, d.T2, model, part_chi);
-        e = hipGetLastError();
-    }
-    return e;
+    if (d.n_spec <= 0) return hipSuccess;
+    if (s == 1)
+        hipLaunchKernelGGL(k_spec_fwd<1>, dim3(d.n_spec), dim3(kFftThreads), 0, st, d.spec, d.classes, d.frames,
+                           d.cls_frames, d.S, d.Hh, d.tab, params, N, E, M, d.Rh);
+    else if (s == 2)
+        hipLaunchKernelGGL(k_spec_fwd<2>, dim3(d.n_spec), dim3(kFftThreads), 0, st, d.spec, d.classes, d.frames,
+                           d.cls_frames, d.S, d.Hh, d.tab, params, N, E, M, d.Rh);
+    else
+        hipLaunchKernelGGL(k_spec_fwd<3>, dim3(d.n_spec), dim3(kFftThreads), 0, st, d.spec, d.classes, d.frames,
+                           d.cls_frames, d.S, d.Hh, d.tab, params, N, E, M, d.Rh);
+    return hipGetLastError();
+}
+
+hipError_t fft_model_cols(hipStream_t st, const FftPlanDev &d)
+{
+    return run_lines(st, d.fcols, d.classes, d.tw, OpMCols{d.frames, d.Rh, d.T});
+}
+
+hipError_t fft_model_rows(hipStream_t st, const FftPlanDev &d, const float *data, const float *invvar,
+                          double *part_chi, float *model)
+{
+    if (d.frows.n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fwd_rows, dim3(d.frows.n_items), dim3(kFftThreads), d.frows.lds_bytes, st, d.frows.items,
+                       d.classes, d.frames, d.tw, d.T, data, invvar, d.T2, model, part_chi);
+    return hipGetLastError();
 }
 
 hipError_t fft_scene_model(hipStream_t st, const FftPlanDev &d, const float *scene, int s, float *model)
@@ -622,13 +829,27 @@ hipError_t fft_resid_rows(hipStream_t st, const FftPlanDev &d, const float *resi
     return run_lines(st, d.rrows, d.classes, d.tw, OpResidRows{d.frames, resid, d.T2});
 }
 
+hipError_t fft_rho_cols(hipStream_t st, const FftPlanDev &d)
+{
+    return run_lines(st, d.rcols, d.classes, d.tw, OpRhoCols{d.frames, d.T2, d.Rh});
+}
+
+hipError_t fft_adj_cols(hipStream_t st, const FftPlanDev &d)
+{
+    return run_lines(st, d.acols, d.classes, d.tw, OpAdjCols{d.frames, d.S, d.Rh, d.T3});
+}
+
+hipError_t fft_adj_rows(hipStream_t st, const FftPlanDev &d, float *g)
+{
+    return run_lines(st, d.arows, d.classes, d.tw, OpAdjRows{d.frames, d.T3, g, d.gpart});
+}
+
 hipError_t fft_adjoint(hipStream_t st, const FftPlanDev &d, float *g)
 {
-    hipError_t e = run_lines(st, d.rcols, d.classes, d.tw, OpRhoCols{d.frames, d.T2, d.Rh});
-    if (e != hipSuccess) return e;
-    e = run_lines(st, d.acols, d.classes, d.tw, OpAdjCols{d.frames, d.S, d.Rh, d.T3});
-    if (e != hipSuccess) return e;
-    return run_lines(st, d.arows, d.classes, d.tw, OpAdjRows{d.frames, d.T3, g});
+    hipError_t e = fft_rho_cols(st, d);
+    if (e == hipSuccess) e = fft_adj_cols(st, d);
+    if (e == hipSuccess) e = fft_adj_rows(st, d, g);
+    return e;
 }
 
 }  // namespace starred

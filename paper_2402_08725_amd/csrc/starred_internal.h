@@ -70,13 +70,17 @@ hipError_t launch_adj_direct(hipStream_t st, int s, const FrameDev *fr, const It
                              int n_items, int Ar_max, int Bpad_max, const float *rho,
                              const float *ka, float *g);
 hipError_t launch_frame_sums(hipStream_t st, const FrameDev *fr, int E, int N, int M, float sigma,
-                             const float *params, const float *g, double *fsum);
+                             const float *params, const float *g, double *fsum, bool with_gamma);
 hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, const float *g,
-                             const float *prior, float *grad_h);
+                             const float *prior, float *grad_h, float *part);
+int finalize_h_chunks(int E);
 hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const double *part_chi,
                                  int n_l1, const double *part_l1, double lambda,
                                  const double *fsum, const float *params, int N,
-                                 float *grad, double *loss);
+                                 float *grad, double *loss, const int *gcsr_off = nullptr,
+                                 const int *gcsr_item = nullptr, const double *gpart = nullptr,
+                                 int *tick = nullptr);
+hipError_t launch_copy_probe(hipStream_t st, const float *src, float *dst, long long n);
 
 hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, float *coeffs,
                               float *z, const float *W, int w_stride, float lam, float *c_a,
@@ -115,7 +119,7 @@ hipError_t launch_psf_sum(hipStream_t st, int S, int N, const float *params, con
                           const float *prior, float *grad, double *part_eta);
 hipError_t launch_psf_finalize_small(hipStream_t st, int S, int n_chi, const double *part_chi, int n_l1,
                                      const double *part_l1, int n_eta, const double *part_eta, float *grad,
-                                     double *loss);
+                                     double *loss, int *tick = nullptr);
 int psf_sum_blocks(int N);
 size_t psf_fwd_lds(int n, int s);
 size_t psf_adj_lds(int n, int N);

@@ -420,14 +420,15 @@ constexpr int kSumThreads = 256;
 
 __global__ __launch_bounds__(kSumThreads) void k_frame_sums(
     const FrameDev *__restrict__ frames, int E, int frame0, int N, int M, float sigma,
-    const float *__restrict__ params, const float *__restrict__ g, double *__restrict__ fsum)
+    const float *__restrict__ params, const float *__restrict__ g, double *__restrict__ fsum, int yofs)
 {
     __shared__ double red[kSumThreads / 64];
     const int i = frame0 + blockIdx.x;
+    const int by = blockIdx.y + yofs;  // yofs = 1: the frame sums of g come from elsewhere
     const FrameDev fr = frames[i];
     const float *gi = g + fr.fine_off;
     const int stride = 1 + 3 * M;
-    if (blockIdx.y == 0) {
+    if (by == 0) {
         double acc = 0.0;
         const int tot = fr.F * fr.F;
         for (int p = threadIdx.x; p < tot; p += kSumThreads) acc += (double)gi[p];
@@ -435,7 +436,7 @@ __global__ __launch_bounds__(kSumThreads) void k_frame_sums(
         if (threadIdx.x == 0) fsum[(long long)i * stride] = s;
         return;
     }
-    const int k = blockIdx.y - 1;
+    const int k = by - 1;
     const float *c = params + (long long)N * N + E + (long long)E * M;
     const float cx = c[2 * k], cy = c[2 * k + 1];
     const float inv2s2 = 1.0f / (2.0f * sigma * sigma);
@@ -468,11 +469,13 @@ __global__ __launch_bounds__(kSumThreads) void k_frame_sums(
 }
 
 hipError_t launch_frame_sums(hipStream_t st, const FrameDev *fr, int E, int N, int M, float sigma,
-                             const float *params, const float *g, double *fsum)
+                             const float *params, const float *g, double *fsum, bool with_gamma)
 {
     if (E <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_frame_sums, dim3(E, 1 + M), dim3(kSumThreads), 0, st, fr, E, 0, N, M, sigma,
-                       params, g, fsum);
+    const int yofs = with_gamma ? 0 : 1;
+    if (1 + M - yofs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_frame_sums, dim3(E, 1 + M - yofs), dim3(kSumThreads), 0, st, fr, E, 0, N, M, sigma,
+                       params, g, fsum, yofs);
     return hipGetLastError();
 }
 
@@ -480,7 +483,7 @@ hipError_t launch_frame_sums_one(hipStream_t st, const FrameDev *fr, int E, int 
                                  const float *params, const float *g, double *fsum)
 {
     hipLaunchKernelGGL(k_frame_sums, dim3(1, 1 + M), dim3(kSumThreads), 0, st, fr, E, i, N, M, sigma,
-                       params, g, fsum);
+                       params, g, fsum, 0);
     return hipGetLastError();
 }
 
@@ -488,27 +491,46 @@ hipError_t launch_frame_sums_one(hipStream_t st, const FrameDev *fr, int E, int 
 // dL/dh = Phi z + sum over frames covering the pixel of g_i (frame order)
 // --------------------------------------------------------------------------
 
-__global__ void k_finalize_h(const FrameDev *__restrict__ frames, int E, int N,
-                             const float *__restrict__ g, const float *__restrict__ prior,
-                             float *__restrict__ grad_h)
+constexpr int kFinChunk = 16;  // frames summed by one thread of k_finalize_h_part
+
+// Two-stage cross-frame sum (frame order within a chunk, then chunk order):
+// part[c][Y,X] = sum over frames of chunk c covering (Y,X) of g_i(Y - o_i, X - o_i)
+__global__ void k_finalize_h_part(const FrameDev *__restrict__ frames, int E, int N,
+                                  const float *__restrict__ g, float *__restrict__ part)
 {
     const int pix = blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= N * N) return;
     const int Y = pix / N, X = pix % N;
-    float acc = prior ? prior[pix] : 0.f;
-    for (int i = 0; i < E; ++i) {
+    const int i0 = blockIdx.y * kFinChunk, i1 = min(E, i0 + kFinChunk);
+    float acc = 0.f;
+    for (int i = i0; i < i1; ++i) {
         const int o = frames[i].o, F = frames[i].F;
         const int y = Y - o, x = X - o;
         if (y >= 0 && y < F && x >= 0 && x < F) acc += g[frames[i].fine_off + (long long)y * F + x];
     }
+    part[(long long)blockIdx.y * N * N + pix] = acc;
+}
+
+// dL/dh = Phi z + sum of the chunk partials
+__global__ void k_finalize_h_sum(int nchunk, int N, const float *__restrict__ part,
+                                 const float *__restrict__ prior, float *__restrict__ grad_h)
+{
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= N * N) return;
+    float acc = prior ? prior[pix] : 0.f;
+    for (int c = 0; c < nchunk; ++c) acc += part[(long long)c * N * N + pix];
     grad_h[pix] = acc;
 }
 
+int finalize_h_chunks(int E) { return (E + kFinChunk - 1) / kFinChunk; }
+
 hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, const float *g,
-                             const float *prior, float *grad_h)
+                             const float *prior, float *grad_h, float *part)
 {
-    hipLaunchKernelGGL(k_finalize_h, dim3((N * N + 255) / 256), dim3(256), 0, st, fr, E, N, g, prior,
-                       grad_h);
+    const int nb = (N * N + 255) / 256;
+    const int nc = finalize_h_chunks(E);
+    hipLaunchKernelGGL(k_finalize_h_part, dim3(nb, nc), dim3(256), 0, st, fr, E, N, g, part);
+    hipLaunchKernelGGL(k_finalize_h_sum, dim3(nb), dim3(256), 0, st, nc, N, part, prior, grad_h);
     return hipGetLastError();
 }
 
@@ -519,8 +541,11 @@ constexpr int kFinThreads = 256;
 __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
     int E, int M, int n_chi, const double *__restrict__ part_chi, int n_l1,
     const double *__restrict__ part_l1, const double *__restrict__ fsum,
-    const float *__restrict__ params, int N, float *__restrict__ grad, double *__restrict__ loss)
+    const float *__restrict__ params, int N, float *__restrict__ grad, double *__restrict__ loss,
+    const int *__restrict__ gcsr_off, const int *__restrict__ gcsr_item, const double *__restrict__ gpart,
+    int *__restrict__ tick)
 {
+    if (tick && threadIdx.x == 0) *tick += 1;  // the Adam step that follows reads it
     __shared__ double red[kFinThreads / 64];
     double a = 0.0;
     for (int i = threadIdx.x; i < n_chi; i += kFinThreads) a += part_chi[i];
@@ -539,25 +564,34 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
     float *gG = grad + NN, *ga = gG + E, *gc = ga + (long long)E * M;
     const float *pa = params + NN + E;
     for (int i = threadIdx.x; i < E; i += kFinThreads) {
-        gG[i] = (float)fsum[(long long)i * stride];
+        if (gcsr_off) {
+            double acc = 0.0;
+            for (int q = gcsr_off[i]; q < gcsr_off[i + 1]; ++q) acc += gpart[gcsr_item[q]];
+            gG[i] = (float)acc;
+        } else {
+            gG[i] = (float)fsum[(long long)i * stride];
+        }
         for (int k = 0; k < M; ++k) ga[(long long)i * M + k] = (float)fsum[(long long)i * stride + 1 + k];
     }
-    for (int q = threadIdx.x; q < 2 * M; q += kFinThreads) {
+    // dL/dc_k = sum_i a_ik <g_i, dr_k/dc>: frames strided over the threads, then a fixed tree
+    for (int q = 0; q < 2 * M; ++q) {
         const int k = q >> 1, axis = q & 1;
         double acc = 0.0;
-        for (int i = 0; i < E; ++i)
+        for (int i = threadIdx.x; i < E; i += kFinThreads)
             acc += (double)pa[(long long)i * M + k] * fsum[(long long)i * stride + 1 + (1 + axis) * M + k];
-        gc[q] = (float)acc;
+        const double tot = block_sum_d<kFinThreads>(acc, red);
+        if (threadIdx.x == 0) gc[q] = (float)tot;
     }
 }
 
 hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const double *part_chi,
                                  int n_l1, const double *part_l1, double,
                                  const double *fsum, const float *params, int N,
-                                 float *grad, double *loss)
+                                 float *grad, double *loss, const int *gcsr_off, const int *gcsr_item,
+                                 const double *gpart, int *tick)
 {
     hipLaunchKernelGGL(k_finalize_small, dim3(1), dim3(kFinThreads), 0, st, E, M, n_chi, part_chi,
-                       n_l1, part_l1, fsum, params, N, grad, loss);
+                       n_l1, part_l1, fsum, params, N, grad, loss, gcsr_off, gcsr_item, gpart, tick);
     return hipGetLastError();
 }
 
@@ -738,9 +772,22 @@ hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, floa
 // --------------------------------------------------------------------------
 
 // The step number lives on the device (d_t) so that a captured graph can run
-// consecutive steps: k_adam_tick advances it, k_adam reads it.
-__global__ void k_adam_tick(int *d_t) { *d_t += 1; }
+// consecutive steps: the final reduction kernel of the step advances it, k_adam
+// reads it.
 __global__ void k_set_int(int *d_t, int v) { *d_t = v; }
+
+// plain device copy, used to calibrate memory-traffic counters
+__global__ void k_copy_probe(const float4 *__restrict__ a, float4 *__restrict__ b, long long n4)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (long long)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+hipError_t launch_copy_probe(hipStream_t st, const float *src, float *dst, long long n)
+{
+    hipLaunchKernelGGL(k_copy_probe, dim3(2048), dim3(256), 0, st, (const float4 *)src, (float4 *)dst, n / 4);
+    return hipGetLastError();
+}
 
 __global__ void k_adam(long long P, long long e0, long long e1, long long e2, float lr0, float lr1,
                        float lr2, float lr3, float *__restrict__ params,
@@ -773,7 +820,6 @@ hipError_t launch_adam(hipStream_t st, long long P, const long long *seg_end, co
                        float beta2, float eps)
 {
     const int nb = (int)((P + 255) / 256);
-    hipLaunchKernelGGL(k_adam_tick, dim3(1), dim3(1), 0, st, d_t);
     hipLaunchKernelGGL(k_adam, dim3(nb), dim3(256), 0, st, P, seg_end[0], seg_end[1], seg_end[2],
                        lr[0], lr[1], lr[2], lr[3], params, grad, m, v, beta1, beta2, eps, d_t);
     return hipGetLastError();

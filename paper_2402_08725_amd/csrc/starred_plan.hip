@@ -79,6 +79,7 @@ struct starred_plan {
     float *d_z = nullptr, *d_ca = nullptr, *d_cb = nullptr, *d_tmp = nullptr, *d_prior = nullptr;
     float *d_grad = nullptr;
     float *d_wzero = nullptr;
+    float *d_hpart = nullptr;
     std::vector<void *> owned;
 
     // FFT path
@@ -328,6 +329,7 @@ static int build_deconv(starred_plan *p)
     if ((rc = p->alloc(&p->d_cb, NN))) return rc;
     if ((rc = p->alloc(&p->d_tmp, NN))) return rc;
     if ((rc = p->alloc(&p->d_prior, NN))) return rc;
+    if ((rc = p->alloc(&p->d_hpart, (size_t)finalize_h_chunks(E) * NN))) return rc;
     if ((rc = p->alloc(&p->d_grad, p->nparams))) return rc;
     if ((rc = p->alloc(&p->d_wzero, (size_t)p->J * NN))) return rc;
     HIP_TRY(hipMemset(p->d_wzero, 0, sizeof(float) * p->J * NN));
@@ -412,6 +414,14 @@ static int build_fft(starred_plan *p)
         c.tab_off = tb;
         tb += (long long)(1 + 2 * M) * c.P;
     }
+    // class-ordered frame list
+    std::vector<int> cls_frames;
+    for (int c = 0; c < (int)p->cls.size(); ++c) {
+        p->cls[c].cf_off = (int)cls_frames.size();
+        for (int i = 0; i < E; ++i)
+            if (fcls[i] == c) cls_frames.push_back(i);
+        p->cls[c].ncf = (int)cls_frames.size() - p->cls[c].cf_off;
+    }
     p->ffr.resize(E);
     long long so = 0, to = 0, ro = 0, t3o = 0;
     for (int i = 0; i < E; ++i) {
@@ -465,12 +475,35 @@ static int build_fft(starred_plan *p)
             }
             tabh[c.tab_off + K] = make_float2((float)acc.real(), (float)acc.imag());
         }
+    // forward spectral product items: 256 bins x a chunk of frames, longest first
+    {
+        std::vector<SpecItem> sp;
+        for (int c = 0; c < (int)p->cls.size(); ++c) {
+            const ClassFft &cl = p->cls[c];
+            const int nbins = cl.Q * (cl.Q / 2 + 1);
+            const int nbb = (nbins + kFftThreads - 1) / kFftThreads;
+            // enough frame chunks to give every compute unit several groups
+            int fch = std::max(1, std::min(8, (int)((long long)nbb * cl.ncf / 1024)));
+            for (int f0 = 0; f0 < cl.ncf; f0 += fch)
+                for (int bb = 0; bb < nbb; ++bb)
+                    sp.push_back(SpecItem{c, f0, std::min(fch, cl.ncf - f0), bb * kFftThreads});
+        }
+        std::stable_sort(sp.begin(), sp.end(), [&](const SpecItem &a, const SpecItem &b) {
+            return p->cls[a.cls].P > p->cls[b.cls].P;
+        });
+        d.n_spec = (int)sp.size();
+        if ((rc = p->alloc(&d.spec, sp.size()))) return rc;
+        if ((rc = p->alloc(&d.cls_frames, cls_frames.size()))) return rc;
+        if (!sp.empty()) HIP_TRY(hipMemcpy(d.spec, sp.data(), sizeof(SpecItem) * sp.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(d.cls_frames, cls_frames.data(), sizeof(int) * cls_frames.size(), hipMemcpyHostToDevice));
+    }
     HIP_TRY(hipMemcpy(d.classes, p->cls.data(), sizeof(ClassFft) * p->cls.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d.frames, p->ffr.data(), sizeof(FrameFft) * E, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d.tw, tw.data(), sizeof(float2) * tw_total, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d.tab, tabh.data(), sizeof(float2) * tb, hipMemcpyHostToDevice));
 
     // line passes: groups of lines of one frame (or class), longest transforms first
+    std::vector<LineItem> last_items;
     auto make_pass = [&](LinePass &lp, bool per_class, auto lines_of, auto len_of) -> int {
         struct G { int L; LineItem it; };
         std::vector<G> g;
@@ -495,6 +528,7 @@ static int build_fft(starred_plan *p)
         std::stable_sort(g.begin(), g.end(), [](const G &a, const G &b) { return a.L > b.L; });
         std::vector<LineItem> items;
         for (auto &x : g) items.push_back(x.it);
+        last_items = items;
         lp.n_items = (int)items.size();
         lp.lds_bytes = (size_t)2 * maxL * sizeof(float2);
         int rc2 = p->alloc(&lp.items, items.size());
@@ -517,6 +551,19 @@ static int build_fft(starred_plan *p)
     if ((rc = make_pass(d.rcols, false, [](const ClassFft &c) { return c.Q / 2 + 1; }, LQ))) return rc;
     if ((rc = make_pass(d.acols, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
     if ((rc = make_pass(d.arows, false, [](const ClassFft &c) { return c.F; }, LP))) return rc;
+    {
+        std::vector<int> off(E + 1, 0), item;
+        for (const LineItem &li : last_items) off[li.frame + 1]++;
+        for (int i = 0; i < E; ++i) off[i + 1] += off[i];
+        item.resize(last_items.size());
+        std::vector<int> fill(off.begin(), off.end() - 1);
+        for (int q = 0; q < (int)last_items.size(); ++q) item[fill[last_items[q].frame]++] = q;
+        if ((rc = p->alloc(&d.gpart, std::max<size_t>(1, last_items.size())))) return rc;
+        if ((rc = p->alloc(&d.gcsr_off, E + 1))) return rc;
+        if ((rc = p->alloc(&d.gcsr_item, std::max<size_t>(1, item.size())))) return rc;
+        HIP_TRY(hipMemcpy(d.gcsr_off, off.data(), sizeof(int) * (E + 1), hipMemcpyHostToDevice));
+        if (!item.empty()) HIP_TRY(hipMemcpy(d.gcsr_item, item.data(), sizeof(int) * item.size(), hipMemcpyHostToDevice));
+    }
     if ((rc = make_pass(d.srows, false, [](const ClassFft &c) { return c.F; }, LP))) return rc;
     if ((rc = make_pass(d.scols, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
     if ((rc = p->alloc(&p->d_part_chi_fft, std::max(1, d.frows.n_items)))) return rc;
@@ -554,7 +601,7 @@ static int build_psf(starred_plan *p)
     return STARRED_OK;
 }
 
-static int loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out);
+static int loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out, int *tick = nullptr);
 static int autotune(starred_plan *p);
 
 int starred_plan_create(const starred_desc *desc, void *stream, starred_plan **plan_out)
@@ -732,7 +779,7 @@ static int starlet_branch(starred_plan *p, const float *img, bool want_grad, int
     return STARRED_OK;
 }
 
-static int loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out)
+static int loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out, int *tick)
 {
     const bool fft = (p->algo == STARRED_CONV_FFT);
     hipEvent_t e0;
@@ -747,8 +794,15 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         HIP_TRY(fft_spectra(p->st, p->fd, params, p->N, p->E, p->M, p->sigma));
         p->prof_stop(STARRED_STAGE_SPECTRA, e0);
         e0 = p->prof_start();
-        HIP_TRY(fft_forward(p->st, p->fd, params, p->N, p->E, p->M, p->s, p->data, p->invvar,
-                            p->d_part_chi_fft, nullptr));
+        hipEvent_t e1 = p->prof_start();
+        HIP_TRY(fft_spec_fwd(p->st, p->fd, params, p->N, p->E, p->M, p->s));
+        p->prof_stop(STARRED_STAGE_FFT_SPEC, e1);
+        e1 = p->prof_start();
+        HIP_TRY(fft_model_cols(p->st, p->fd));
+        p->prof_stop(STARRED_STAGE_FFT_MCOLS, e1);
+        e1 = p->prof_start();
+        HIP_TRY(fft_model_rows(p->st, p->fd, p->data, p->invvar, p->d_part_chi_fft, nullptr));
+        p->prof_stop(STARRED_STAGE_FFT_MROWS, e1);
         p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
         n_chi = p->fd.frows.n_items;
         part_chi = p->d_part_chi_fft;
@@ -765,21 +819,30 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     }
     if (grad) {
         e0 = p->prof_start();
-        if (fft)
-            HIP_TRY(fft_adjoint(p->st, p->fd, p->d_g));
-        else
+        if (fft) {
+            hipEvent_t e1 = p->prof_start();
+            HIP_TRY(fft_rho_cols(p->st, p->fd));
+            p->prof_stop(STARRED_STAGE_FFT_RCOLS, e1);
+            e1 = p->prof_start();
+            HIP_TRY(fft_adj_cols(p->st, p->fd));
+            p->prof_stop(STARRED_STAGE_FFT_ACOLS, e1);
+            e1 = p->prof_start();
+            HIP_TRY(fft_adj_rows(p->st, p->fd, p->d_g));
+            p->prof_stop(STARRED_STAGE_FFT_AROWS, e1);
+        } else
             HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ar_max,
                                       p->Bpad_max, p->d_rho, p->d_ka, p->d_g));
         p->prof_stop(STARRED_STAGE_CONV_ADJ, e0);
         e0 = p->prof_start();
-        HIP_TRY(launch_frame_sums(p->st, p->d_fr, p->E, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum));
+        HIP_TRY(launch_frame_sums(p->st, p->d_fr, p->E, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum, !fft));
         p->prof_stop(STARRED_STAGE_GRAD_SUMS, e0);
     }
     HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
     e0 = p->prof_start();
-    if (grad) HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad));
+    if (grad) HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad, p->d_hpart));
     HIP_TRY(launch_finalize_small(p->st, p->E, p->M, n_chi, part_chi, n_l1, p->d_part_l1, p->lam, p->d_fsum,
-                                  params, p->N, grad, loss_out));
+                                  params, p->N, grad, loss_out, fft && grad ? p->fd.gcsr_off : nullptr,
+                                  p->fd.gcsr_item, p->fd.gpart, tick));
     p->prof_stop(STARRED_STAGE_FINALIZE, e0);
     return STARRED_OK;
 }
@@ -832,7 +895,7 @@ static int autotune(starred_plan *p)
     return rc;
 }
 
-static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out)
+static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out, int *tick = nullptr)
 {
     const int S = p->E, n = p->psf_n, N = p->N;
     const long long NN = (long long)N * N;
@@ -857,7 +920,7 @@ static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad,
     HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
     e0 = p->prof_start();
     HIP_TRY(launch_psf_finalize_small(p->st, S, S, p->d_part_chi, n_l1, p->d_part_l1, psf_sum_blocks(N),
-                                      p->d_part_eta, grad, loss_out));
+                                      p->d_part_eta, grad, loss_out, tick));
     p->prof_stop(STARRED_STAGE_FINALIZE, e0);
     (void)NN;
     return STARRED_OK;
@@ -971,7 +1034,7 @@ int starred_loss_grad_plain(starred_plan *p, const float *params, float *grad, d
                                (float)p->lam, p->d_ca, p->d_cb, p->d_tmp, p->d_part_l1, &n_l1));
     if (grad) {
         HIP_TRY(launch_starlet_adj(p->st, p->N, p->J, p->d_z, p->d_prior, p->d_ca, p->d_cb, p->d_tmp));
-        HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad));
+        HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad, p->d_hpart));
     }
     HIP_TRY(launch_finalize_small(p->st, p->E, p->M, p->n_pchi, p->d_pchi, n_l1, p->d_part_l1, p->lam, p->d_fsum,
                                   params, p->N, grad, loss_out));
@@ -1044,8 +1107,8 @@ int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
     // the caller's step number is not the next one
     if (t != p->next_t) HIP_TRY(launch_set_step(p->st, p->d_t, t - 1));
     auto body = [&]() -> int {
-        int rc = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, p->d_grad, loss_out)
-                                          : loss_grad_impl(p, params, p->d_grad, loss_out);
+        int rc = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t)
+                                          : loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t);
         if (rc) return rc;
         const long long NN = (long long)p->N * p->N;
         long long seg[3] = {NN, NN + p->E, NN + p->E + (long long)p->E * p->M};
@@ -1085,6 +1148,13 @@ int starred_set_graph_mode(starred_plan *p, int32_t enable)
     if (enable && !p->st) return fail(STARRED_EUNSUPPORTED, "graph capture needs a non-default stream");
     if (!enable) p->drop_graphs();
     p->graph_mode = enable != 0;
+    return STARRED_OK;
+}
+
+int starred_copy_probe(starred_plan *p, const float *src, float *dst, int64_t n)
+{
+    if (!p || !src || !dst || n < 0 || (n % 4)) return fail(STARRED_EINVAL, "bad copy probe arguments");
+    HIP_TRY(launch_copy_probe(p->st, src, dst, n));
     return STARRED_OK;
 }
 

@@ -337,8 +337,10 @@ __global__ __launch_bounds__(kPsfSumThreads) void k_psf_sum(int S, int N, const 
 __global__ __launch_bounds__(256) void k_psf_finalize_small(int S, int n_chi, const double *__restrict__ part_chi,
                                                             int n_l1, const double *__restrict__ part_l1,
                                                             int n_eta, const double *__restrict__ part_eta,
-                                                            float *__restrict__ grad, double *__restrict__ loss)
+                                                            float *__restrict__ grad, double *__restrict__ loss,
+                                                            int *__restrict__ tick)
 {
+    if (tick && threadIdx.x == 0) *tick += 1;  // the Adam step that follows reads it
     __shared__ double red[4];
     double a = 0.0;
     for (int i = threadIdx.x; i < n_chi; i += 256) a += part_chi[i];
@@ -398,10 +400,10 @@ hipError_t launch_psf_sum(hipStream_t st, int S, int N, const float *params, con
 
 hipError_t launch_psf_finalize_small(hipStream_t st, int S, int n_chi, const double *part_chi, int n_l1,
                                      const double *part_l1, int n_eta, const double *part_eta, float *grad,
-                                     double *loss)
+                                     double *loss, int *tick)
 {
     hipLaunchKernelGGL(k_psf_finalize_small, dim3(1), dim3(256), 0, st, S, n_chi, part_chi, n_l1, part_l1, n_eta,
-                       part_eta, grad, loss);
+                       part_eta, grad, loss, tick);
     return hipGetLastError();
 }
 

@@ -25,10 +25,10 @@ EXPORTED = [
     "starred_convolve_subsample", "starred_convolve_subsample_adj", "starred_starlet_fwd",
     "starred_starlet_adj", "starred_loss_grad", "starred_step", "starred_set_graph_mode",
     "starred_conv_algo", "starred_last_error", "starred_abi_version", "starred_set_profiling",
-    "starred_profile_read", "starred_psf_model", "starred_loss_grad_plain",
+    "starred_profile_read", "starred_psf_model", "starred_loss_grad_plain", "starred_copy_probe",
 ]
 STAGES = ["render", "conv_fwd", "conv_adj", "grad_sums", "starlet", "finalize", "adam", "spectra",
-          "graph"]
+          "graph", "fft_spec", "fft_mcols", "fft_mrows", "fft_rcols", "fft_acols", "fft_arows"]
 
 
 class Desc(ctypes.Structure):
@@ -81,6 +81,7 @@ def lib():
         L.starred_profile_read.argtypes = [vp, vp, vp]
         L.starred_psf_model.argtypes = [vp, vp, vp]
         L.starred_loss_grad_plain.argtypes = [vp, vp, vp, vp]
+        L.starred_copy_probe.argtypes = [vp, vp, vp, ctypes.c_int64]
         _lib = L
     return _lib
 
@@ -258,6 +259,10 @@ class Plan:
         _check(lib().starred_profile_read(self._h, ctypes.c_void_p(ms.ctypes.data),
                                           ctypes.c_void_p(cnt.ctypes.data)))
         return {name: {"ms": float(ms[i]), "count": int(cnt[i])} for i, name in enumerate(STAGES)}
+
+    def copy_probe(self, src, dst):
+        """Plain device copy (memory-counter calibration)."""
+        self._call(lib().starred_copy_probe, _ptr(src), _ptr(dst), int(src.numel()))
 
     def set_graph_mode(self, enable: bool):
         _check(lib().starred_set_graph_mode(self._h, int(bool(enable))))
