@@ -195,8 +195,9 @@ enum {
     STARRED_STAGE_FFT_MCOLS,    /* ... inverse along the first axis of the model spectra */
     STARRED_STAGE_FFT_MROWS,    /* ... inverse rows, residual, chi-square, forward rows of rho */
     STARRED_STAGE_FFT_RCOLS,    /* FFT path, inside CONV_ADJ: forward columns of rho */
-    STARRED_STAGE_FFT_ACOLS,    /* ... kernel-spectrum product and inverse columns */
-    STARRED_STAGE_FFT_AROWS,    /* ... inverse rows of the adjoint images and their sums */
+    STARRED_STAGE_FFT_ACOLS,    /* ... kernel-spectrum products, their sum over frames and the
+                                   per-frame dot products for Gamma, a and c */
+    STARRED_STAGE_FFT_AROWS,    /* ... inverse transform of the summed spectra (dL/dh) */
     STARRED_NUM_STAGES
 };
 int starred_set_profiling(starred_plan *plan, int32_t enable);

@@ -9,6 +9,8 @@ namespace starred {
 
 constexpr int kFftThreads = 256;
 constexpr int kFftTargetElems = 2048;  // complex elements per work group and buffer
+constexpr int kAdjBins = 4;            // spectral adjoint: bins per thread
+constexpr int kAdjFrames = 4;          // spectral adjoint: frames held in registers at once
 
 // A 1-D transform length L = product of radices (4, 2, 3, 5) and the offset of
 // its twiddle table e^{-2 pi i m / L}, m < L.
@@ -30,7 +32,10 @@ struct ClassFft {
     float sscale;       // 1 / (s^2 Q^2)
     int cf_off;         // first entry of this class in the class-ordered frame list
     int ncf;            // number of frames of the class
-    int pad;
+    int ngch;           // frame chunks of the frequency-domain adjoint
+    int gfch;           // frames per chunk
+    long long gp_off;   // [ngch][P][P/2+1] summed adjoint spectra of each chunk
+    long long hc_off;   // [F][F] the class's contribution to dL/dh (its window)
 };
 
 struct FrameFft {
@@ -82,6 +87,15 @@ struct FftPlanDev {
     // for each frame, the list of its groups (CSR)
     double *gpart = nullptr;
     int *gcsr_off = nullptr, *gcsr_item = nullptr;
+    // frequency-domain adjoint
+    int n_frames = 0;
+    SpecItem *aspec = nullptr;
+    int n_aspec = 0;
+    int maxpb = 0;           // per-wave partial slots per frame
+    double *apart = nullptr; // [E][maxpb][1 + 3M]
+    float2 *Gp = nullptr;
+    float *hcls = nullptr;
+    LinePass gcols, grows;
 };
 
 // Deterministic block sum of one double per thread (kFftThreads); thread 0 holds it.
@@ -113,6 +127,9 @@ hipError_t fft_adj_cols(hipStream_t st, const FftPlanDev &d);
 hipError_t fft_adj_rows(hipStream_t st, const FftPlanDev &d, float *g);
 hipError_t fft_resid_rows(hipStream_t st, const FftPlanDev &d, const float *resid);
 hipError_t fft_adjoint(hipStream_t st, const FftPlanDev &d, float *g);
+hipError_t fft_spec_adj(hipStream_t st, const FftPlanDev &d, int M, double *fsum);
+hipError_t fft_grad_h_inverse(hipStream_t st, const FftPlanDev &d);
+hipError_t fft_finalize_h(hipStream_t st, const FftPlanDev &d, int N, const float *prior, float *grad_h);
 hipError_t fft_scene_model(hipStream_t st, const FftPlanDev &d, const float *scene, int s, float *model);
 
 }  // namespace starred

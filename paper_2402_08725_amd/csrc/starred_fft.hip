@@ -412,7 +412,7 @@ struct OpFwdCols {
         v = cadd(v, cscale(cmul(t[Ky], t[Kx]), G));
         const float *a = params + (long long)N * N + E + (long long)i * M;
         for (int k = 0; k < M; ++k) {
-            const float2 *tk = t + (long long)(1 + 2 * k) * P;  // [gx | gy]
+            const float2 *tk = t + (long long)(1 + 4 * k) * P;  // [gx | gy | dgx | dgy]
             v = cadd(v, cscale(cmul(tk[P + Ky], tk[Kx]), a[k]));
         }
         return v;
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_fwd(const SpecItem *__rest
             for (int b = 0; b < S; ++b) {
                 float2 F = cadd(hv[a * S + b], cscale(wv[a * S + b], G));
                 for (int k = 0; k < M; ++k) {
-                    const float2 *tk = t + (long long)(1 + 2 * k) * P;  // [gx | gy]
+                    const float2 *tk = t + (long long)(1 + 4 * k) * P;  // [gx | gy | dgx | dgy]
                     F = cadd(F, cscale(cmul(tk[P + Kys[a]], tk[Kxs[b]]), ai[k]));
                 }
                 acc = cadd(acc, cmul(half_get(Si, P, Kys[a], Kxs[b]), F));
@@ -706,8 +706,9 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
 }
 
 // ---- per-eval tables: window indicator and point-source factors ----
-// tab[c]: [w (P) | for each source k: gx (P), gy (P)], the 1-D DFTs of the
-// window indicator and of g(x + o - c) over the frame (r = g(dx) g(dy), Eq. 9).
+// tab[c]: [w (P) | for each source k: gx, gy, dgx, dgy (P each)], the 1-D DFTs
+// over the frame of the window indicator, of g(x + o - c) (r = g(dx) g(dy),
+// Eq. 9) and of g(x + o - c)(x + o - c)/sigma^2 (its derivative in c).
 __global__ void k_tables(const ClassFft *__restrict__ classes, const float2 *__restrict__ tw,
                          const float *__restrict__ params, int N, int E, int M, float sigma,
                          float2 *__restrict__ tab)
@@ -717,20 +718,22 @@ __global__ void k_tables(const ClassFft *__restrict__ classes, const float2 *__r
     const float2 *twP = tw + c.fP.tw_off;
     float2 *t = tab + c.tab_off;
     const float *cc = params + (long long)N * N + E + (long long)E * M;
-    const float inv2s2 = 1.0f / (2.0f * sigma * sigma);
+    const float inv2s2 = 1.0f / (2.0f * sigma * sigma), invs2 = 1.0f / (sigma * sigma);
     const float norm = 1.0f / (2.50662827463100050f * sigma);  // 1/(sqrt(2 pi) sigma)
-    const int nent = (1 + 2 * M) * P;
+    const int nent = (1 + 4 * M) * P;
     for (int e = threadIdx.x + blockIdx.y * blockDim.x; e < nent; e += blockDim.x * gridDim.y) {
         const int which = e / P, K = e - which * P;
         if (which == 0) continue;  // the window factor is static, written at plan creation
-        const int k = (which - 1) / 2, part = (which - 1) % 2;
-        const float ctr = cc[2 * k + part];
+        const int k = (which - 1) / 4, part = (which - 1) % 4;
+        const float ctr = cc[2 * k + (part & 1)];
+        const bool deriv = part >= 2;
         const int lo = max(0, (int)ceilf(ctr - c.o - kGaussRadius));
         const int hi = min(c.F - 1, (int)floorf(ctr - c.o + kGaussRadius));
         float2 acc = make_float2(0.f, 0.f);
         for (int x = lo; x <= hi; ++x) {
             const float d = (float)(x + c.o) - ctr;
-            const float g = norm * expf(-d * d * inv2s2);
+            float g = norm * expf(-d * d * inv2s2);
+            if (deriv) g *= d * invs2;
             const float2 w = twP[(int)(((long long)K * x) % P)];
             acc.x += g * w.x;
             acc.y += g * w.y;
@@ -739,6 +742,171 @@ __global__ void k_tables(const ClassFft *__restrict__ classes, const float2 *__r
     }
 }
 
+
+// ---- adjoint in the frequency domain ----
+// For bin K of a class's half spectrum and each frame i of a chunk:
+//   G_i(K) = conj(S''_i(K)) rho_hat_i(K mod Q),
+// summed over the chunk (the spectrum of the chunk's contribution to dL/dh), and
+// the frame's dot products <g_i, x> = sum over the full spectrum of G_i conj(X_hat)
+// (Parseval; half spectrum with weight 2 off the Kx = 0 and P/2 columns) for x the
+// window indicator (dGamma_i), r_k (da_ik) and r_k (X - c_k)/sigma^2 (dc_k, x and y),
+// whose spectra are products of the 1-D tables. Each wave reduces its bins; the
+// per-wave partials are summed per frame by k_fsum_parts.
+__global__ __launch_bounds__(kFftThreads) void k_spec_adj(const SpecItem *__restrict__ items,
+                                                          const ClassFft *__restrict__ classes,
+                                                          const FrameFft *__restrict__ fr,
+                                                          const int *__restrict__ cls_frames,
+                                                          const float2 *__restrict__ Sp,
+                                                          const float2 *__restrict__ Rh,
+                                                          const float2 *__restrict__ tab, int M, int maxpb,
+                                                          float2 *__restrict__ Gp, double *__restrict__ part)
+{
+    constexpr int B = kAdjBins;     // bins per thread (strided by the block size)
+    constexpr int FC = kAdjFrames;  // frames per chunk held in registers
+    const SpecItem it = items[blockIdx.x];
+    const ClassFft &c = classes[it.cls];
+    const int P = c.P, Q = c.Q, HP = P / 2 + 1, nbins = P * HP;
+    const float2 *t = tab + c.tab_off;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int pb = (it.bin0 / (kFftThreads * B)) * (kFftThreads / 64) + wave;  // this wave's partial slot
+    const int Q3 = 1 + 3 * M;
+    int Ky[B], Kx[B], rq[B];
+    float wgt[B];
+    #pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int bin = it.bin0 + b * kFftThreads + threadIdx.x;
+        const bool valid = bin < nbins;
+        Ky[b] = valid ? bin / HP : 0;
+        Kx[b] = valid ? bin - Ky[b] * HP : 0;
+        wgt[b] = valid ? ((Kx[b] == 0 || 2 * Kx[b] == P) ? 1.f : 2.f) : 0.f;
+        rq[b] = valid ? bin : -1;
+    }
+    float2 gs[B];
+    #pragma unroll
+    for (int b = 0; b < B; ++b) gs[b] = make_float2(0.f, 0.f);
+    for (int f0 = it.f0; f0 < it.f0 + it.nf; f0 += FC) {
+        const int nfc = min(FC, it.f0 + it.nf - f0);
+        float2 G[FC][B];
+        int fid[FC];
+        #pragma unroll
+        for (int f = 0; f < FC; ++f) {
+            fid[f] = f < nfc ? cls_frames[c.cf_off + f0 + f] : -1;
+            #pragma unroll
+            for (int b = 0; b < B; ++b) {
+                G[f][b] = make_float2(0.f, 0.f);
+                if (f < nfc && rq[b] >= 0) {
+                    const FrameFft &fi = fr[fid[f]];
+                    G[f][b] = cmulc(half_get(Rh + fi.r_off, Q, Ky[b] % Q, Kx[b] % Q), Sp[fi.s_off + rq[b]]);
+                }
+                gs[b] = cadd(gs[b], G[f][b]);
+            }
+        }
+        // Parseval dot products of every frame of the chunk with each table spectrum
+        for (int q = 0; q < Q3; ++q) {
+            const float2 *ty = t, *tx = t;
+            if (q > 0) {
+                const int k = (q - 1) % M, kind = (q - 1) / M;  // 0: r_k, 1: d/dcx, 2: d/dcy
+                const float2 *tk = t + (long long)(1 + 4 * k) * P;
+                ty = tk + (kind == 2 ? 3 * P : P);
+                tx = tk + (kind == 1 ? 2 * P : 0);
+            }
+            float2 X[B];
+            #pragma unroll
+            for (int b = 0; b < B; ++b) X[b] = cmul(ty[Ky[b]], tx[Kx[b]]);
+            #pragma unroll
+            for (int f = 0; f < FC; ++f) {
+                if (f >= nfc) break;
+                float v = 0.f;
+                #pragma unroll
+                for (int b = 0; b < B; ++b) v += wgt[b] * (G[f][b].x * X[b].x + G[f][b].y * X[b].y);
+                double dv = (double)v;
+                #pragma unroll
+                for (int off = 32; off > 0; off >>= 1) dv += __shfl_xor(dv, off, 64);
+                if (lane == 0) part[((long long)fid[f] * maxpb + pb) * Q3 + q] = dv;
+            }
+        }
+    }
+    #pragma unroll
+    for (int b = 0; b < B; ++b)
+        if (rq[b] >= 0) Gp[c.gp_off + (long long)(it.f0 / c.gfch) * nbins + rq[b]] = gs[b];
+}
+
+// per-frame sums of the per-wave partials -> fsum[i][q] (fixed order)
+__global__ __launch_bounds__(kFftThreads) void k_fsum_parts(const ClassFft *__restrict__ classes,
+                                                            const FrameFft *__restrict__ fr, int M, int maxpb,
+                                                            const double *__restrict__ part, double *__restrict__ fsum)
+{
+    __shared__ double red[kFftThreads / 64];
+    const int i = blockIdx.x;
+    const ClassFft &c = classes[fr[i].cls];
+    const int per_block = kFftThreads * kAdjBins;
+    const int npb = ((c.P * (c.P / 2 + 1) + per_block - 1) / per_block) * (kFftThreads / 64);
+    const int Q3 = 1 + 3 * M;
+    for (int q = 0; q < Q3; ++q) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < npb; b += blockDim.x) acc += part[((long long)i * maxpb + b) * Q3 + q];
+        const double tot = block_sum_d_fft(acc, red);
+        if (threadIdx.x == 0) fsum[(long long)i * Q3 + q] = tot;
+    }
+}
+
+// ---- dL/dh of each class: inverse columns of the summed spectra, crop rows < F ----
+struct OpGCols {
+    const float2 *Gp;
+    float2 *Th;
+    static constexpr bool col = true;
+    static constexpr bool rowsum = false;
+    static constexpr bool inverse = true;
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fP; }
+    __device__ float2 load(const ClassFft &c, int, int Kx, int Ky) const
+    {
+        const int HP = c.P / 2 + 1;
+        const long long stride = (long long)c.P * HP;
+        float2 acc = make_float2(0.f, 0.f);
+        for (int ch = 0; ch < c.ngch; ++ch) acc = cadd(acc, Gp[c.gp_off + ch * stride + (long long)Ky * HP + Kx]);
+        return acc;
+    }
+    __device__ void store(const ClassFft &c, int, int Kx, int y, float2 v) const
+    {
+        const int H = c.P / 2 + 1;
+        if (y < c.F) Th[c.th_off + (long long)y * H + Kx] = v;
+    }
+};
+
+struct OpGRows {
+    const float2 *Th;
+    float *hcls;
+    static constexpr bool col = false;
+    static constexpr bool rowsum = false;
+    static constexpr bool inverse = true;
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fP; }
+    __device__ float2 load(const ClassFft &c, int, int y, int Kx) const
+    {
+        const int P = c.P, H = P / 2 + 1;
+        const float2 *row = Th + c.th_off + (long long)y * H;
+        return Kx < H ? row[Kx] : conjf2(row[P - Kx]);
+    }
+    __device__ void store(const ClassFft &c, int, int y, int x, float2 v) const
+    {
+        if (x < c.F) hcls[c.hc_off + (long long)y * c.F + x] = v.x;
+    }
+};
+
+// dL/dh = prior + the window contributions of the classes (class order)
+__global__ void k_finalize_h_classes(const ClassFft *__restrict__ classes, int ncls, int N,
+                                     const float *__restrict__ hcls, const float *__restrict__ prior,
+                                     float *__restrict__ grad_h)
+{
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= N * N) return;
+    const int Y = pix / N, X = pix % N;
+    float acc = prior ? prior[pix] : 0.f;
+    for (int c = 0; c < ncls; ++c) {
+        const int y = Y - classes[c].o, x = X - classes[c].o, F = classes[c].F;
+        if (y >= 0 && y < F && x >= 0 && x < F) acc += hcls[classes[c].hc_off + (long long)y * F + x];
+    }
+    grad_h[pix] = acc;
+}
 
 // --------------------------------------------------------------------------
 // launchers
@@ -842,6 +1010,33 @@ hipError_t fft_adj_cols(hipStream_t st, const FftPlanDev &d)
 hipError_t fft_adj_rows(hipStream_t st, const FftPlanDev &d, float *g)
 {
     return run_lines(st, d.arows, d.classes, d.tw, OpAdjRows{d.frames, d.T3, g, d.gpart});
+}
+
+hipError_t fft_spec_adj(hipStream_t st, const FftPlanDev &d, int M, double *fsum)
+{
+    if (d.n_aspec > 0) {
+        hipLaunchKernelGGL(k_spec_adj, dim3(d.n_aspec), dim3(kFftThreads), 0, st, d.aspec, d.classes, d.frames,
+                           d.cls_frames, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_fsum_parts, dim3(d.n_frames), dim3(kFftThreads), 0, st, d.classes, d.frames, M, d.maxpb,
+                       d.apart, fsum);
+    return hipGetLastError();
+}
+
+hipError_t fft_grad_h_inverse(hipStream_t st, const FftPlanDev &d)
+{
+    hipError_t e = run_lines(st, d.gcols, d.classes, d.tw, OpGCols{d.Gp, d.Th});
+    if (e != hipSuccess) return e;
+    return run_lines(st, d.grows, d.classes, d.tw, OpGRows{d.Th, d.hcls});
+}
+
+hipError_t fft_finalize_h(hipStream_t st, const FftPlanDev &d, int N, const float *prior, float *grad_h)
+{
+    hipLaunchKernelGGL(k_finalize_h_classes, dim3((N * N + 255) / 256), dim3(256), 0, st, d.classes, d.n_classes, N,
+                       d.hcls, prior, grad_h);
+    return hipGetLastError();
 }
 
 hipError_t fft_adjoint(hipStream_t st, const FftPlanDev &d, float *g)

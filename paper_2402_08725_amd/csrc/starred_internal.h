@@ -88,6 +88,7 @@ hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, fl
 hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, float *out,
                               float *v_a, float *v_b, float *tmp);
 
+
 hipError_t launch_adam(hipStream_t st, long long P, const long long *seg_end, const float *lr,
                        float *params, const float *grad, float *m, float *v, int *d_t, float beta1,
                        float beta2, float eps);

@@ -412,7 +412,7 @@ static int build_fft(starred_plan *p)
         c.hh_off = hh;
         hh += (long long)c.P * HP;
         c.tab_off = tb;
-        tb += (long long)(1 + 2 * M) * c.P;
+        tb += (long long)(1 + 4 * M) * c.P;
     }
     // class-ordered frame list
     std::vector<int> cls_frames;
@@ -497,6 +497,40 @@ static int build_fft(starred_plan *p)
         if (!sp.empty()) HIP_TRY(hipMemcpy(d.spec, sp.data(), sizeof(SpecItem) * sp.size(), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(d.cls_frames, cls_frames.data(), sizeof(int) * cls_frames.size(), hipMemcpyHostToDevice));
     }
+    // frequency-domain adjoint: items over the P half-spectrum bins x frame chunks
+    {
+        std::vector<SpecItem> sp;
+        long long gp = 0, hc = 0;
+        int maxpb = 0;
+        for (int c = 0; c < (int)p->cls.size(); ++c) {
+            ClassFft &cl = p->cls[c];
+            const int nbins = cl.P * (cl.P / 2 + 1);
+            const int per_block = kFftThreads * kAdjBins;
+            const int nbb = (nbins + per_block - 1) / per_block;
+            const int want_chunks = std::max(1, 768 / std::max(1, nbb));
+            cl.gfch = std::max(1, std::min(32, (cl.ncf + want_chunks - 1) / want_chunks));
+            cl.ngch = (cl.ncf + cl.gfch - 1) / cl.gfch;
+            cl.gp_off = gp;
+            gp += (long long)cl.ngch * nbins;
+            cl.hc_off = hc;
+            hc += (long long)cl.F * cl.F;
+            maxpb = std::max(maxpb, nbb * (kFftThreads / 64));
+            for (int f0 = 0; f0 < cl.ncf; f0 += cl.gfch)
+                for (int bb = 0; bb < nbb; ++bb)
+                    sp.push_back(SpecItem{c, f0, std::min(cl.gfch, cl.ncf - f0), bb * per_block});
+        }
+        std::stable_sort(sp.begin(), sp.end(), [&](const SpecItem &a, const SpecItem &b) {
+            return p->cls[a.cls].P > p->cls[b.cls].P;
+        });
+        d.n_frames = E;
+        d.n_aspec = (int)sp.size();
+        d.maxpb = maxpb;
+        if ((rc = p->alloc(&d.aspec, sp.size()))) return rc;
+        if ((rc = p->alloc(&d.apart, (size_t)E * maxpb * (1 + 3 * M)))) return rc;
+        if ((rc = p->alloc(&d.Gp, gp))) return rc;
+        if ((rc = p->alloc(&d.hcls, hc))) return rc;
+        if (!sp.empty()) HIP_TRY(hipMemcpy(d.aspec, sp.data(), sizeof(SpecItem) * sp.size(), hipMemcpyHostToDevice));
+    }
     HIP_TRY(hipMemcpy(d.classes, p->cls.data(), sizeof(ClassFft) * p->cls.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d.frames, p->ffr.data(), sizeof(FrameFft) * E, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d.tw, tw.data(), sizeof(float2) * tw_total, hipMemcpyHostToDevice));
@@ -566,6 +600,8 @@ static int build_fft(starred_plan *p)
     }
     if ((rc = make_pass(d.srows, false, [](const ClassFft &c) { return c.F; }, LP))) return rc;
     if ((rc = make_pass(d.scols, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
+    if ((rc = make_pass(d.gcols, true, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
+    if ((rc = make_pass(d.grows, true, [](const ClassFft &c) { return c.F; }, LP))) return rc;
     if ((rc = p->alloc(&p->d_part_chi_fft, std::max(1, d.frows.n_items)))) return rc;
     p->fft_ready = true;
     return STARRED_OK;
@@ -820,29 +856,38 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     if (grad) {
         e0 = p->prof_start();
         if (fft) {
+            // frequency domain: the frames' adjoint spectra are summed per shape class
+            // before one inverse transform, and the per-frame dot products for Gamma, a
+            // and c are taken there (Parseval)
             hipEvent_t e1 = p->prof_start();
             HIP_TRY(fft_rho_cols(p->st, p->fd));
             p->prof_stop(STARRED_STAGE_FFT_RCOLS, e1);
             e1 = p->prof_start();
-            HIP_TRY(fft_adj_cols(p->st, p->fd));
+            HIP_TRY(fft_spec_adj(p->st, p->fd, p->M, p->d_fsum));
             p->prof_stop(STARRED_STAGE_FFT_ACOLS, e1);
             e1 = p->prof_start();
-            HIP_TRY(fft_adj_rows(p->st, p->fd, p->d_g));
+            HIP_TRY(fft_grad_h_inverse(p->st, p->fd));
             p->prof_stop(STARRED_STAGE_FFT_AROWS, e1);
         } else
             HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ar_max,
                                       p->Bpad_max, p->d_rho, p->d_ka, p->d_g));
         p->prof_stop(STARRED_STAGE_CONV_ADJ, e0);
-        e0 = p->prof_start();
-        HIP_TRY(launch_frame_sums(p->st, p->d_fr, p->E, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum, !fft));
-        p->prof_stop(STARRED_STAGE_GRAD_SUMS, e0);
+        if (!fft) {
+            e0 = p->prof_start();
+            HIP_TRY(launch_frame_sums(p->st, p->d_fr, p->E, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum, true));
+            p->prof_stop(STARRED_STAGE_GRAD_SUMS, e0);
+        }
     }
     HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
     e0 = p->prof_start();
-    if (grad) HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad, p->d_hpart));
+    if (grad) {
+        if (fft)
+            HIP_TRY(fft_finalize_h(p->st, p->fd, p->N, p->d_prior, grad));
+        else
+            HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad, p->d_hpart));
+    }
     HIP_TRY(launch_finalize_small(p->st, p->E, p->M, n_chi, part_chi, n_l1, p->d_part_l1, p->lam, p->d_fsum,
-                                  params, p->N, grad, loss_out, fft && grad ? p->fd.gcsr_off : nullptr,
-                                  p->fd.gcsr_item, p->fd.gpart, tick));
+                                  params, p->N, grad, loss_out, nullptr, nullptr, nullptr, tick));
     p->prof_stop(STARRED_STAGE_FINALIZE, e0);
     return STARRED_OK;
 }

@@ -444,3 +444,81 @@ def test_graph_mode_psf():
         plan.loss_grad(p, grad_out=grad, loss_out=loss)
         torch.cuda.synchronize()
         assert torch.equal(loss, le) and torch.equal(grad, ge), rep
+
+
+# --------------------------------------------------------------------------- #
+# Supernova (ragged) and crowded-field workloads                               #
+# --------------------------------------------------------------------------- #
+
+BIG_CASES = [
+    # every stamp size of the supernova workload, 10 epochs
+    ("cfg4_sizes", lambda: synth.make_deconv(4, E=10)),
+    # crowded field shape with 30 sources and 8 scales, 2 epochs at half the side
+    ("cfg5_shape", lambda: _cfg5_half(2)),
+]
+
+
+def _cfg5_half(E):
+    prob = synth.make_deconv(5, E=E)
+    # same kernels, sources and scales on a 128^2-data (256^2-grid) crop of the field
+    N = 256
+    h = prob.h.reshape(512, 512)[128:384, 128:384]
+    c = prob.c.reshape(-1, 2) - 128.0
+    c = np.clip(c, 8, N - 9)
+    return synth.DeconvProblem(**{**prob.__dict__, "n": np.full(E, 128, np.int32), "N": N,
+                                  "h": synth.f32(h).ravel(), "c": synth.f32(c).ravel()})
+
+
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+@pytest.mark.parametrize("name,make", BIG_CASES, ids=[c[0] for c in BIG_CASES])
+def test_loss_grad_parity_large_shapes(name, make, algo):
+    prob = make()
+    d, w, rng = _data(prob, seed=9)
+    plan = _plan(prob, d, w, algo)
+    p = synth.eval_point(prob, "near", rng)
+    _compare_loss_grad(prob, d, w, p, plan, f"{name}/{ALGO_ID[algo]}")
+
+
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+def test_cfg4_full_size_sampled_frames_and_properties(algo):
+    """1000 ragged epochs in one plan: per-frame model parity on one frame of each
+    stamp size, the adjoint identity and exact central differences at full size."""
+    st = _st()
+    prob = synth.make_deconv(4)
+    rng = np.random.default_rng(10)
+    scene = synth.f32(rng.standard_normal(prob.fine_size) * 50)
+    plan = st.Plan.for_problem(prob, conv_algo=algo)
+    plan.set_frames(np.zeros(prob.data_size), np.ones(prob.data_size), prob.kernels, prob.W)
+    model = plan.convolve_subsample(scene).cpu().numpy().astype(np.float64)
+    offs_d = np.concatenate([[0], np.cumsum(prob.n.astype(np.int64) ** 2)])
+    offs_f = np.concatenate([[0], np.cumsum((prob.s * prob.n.astype(np.int64)) ** 2)])
+    offs_k = np.concatenate([[0], np.cumsum(prob.K.astype(np.int64) ** 2)])
+    for side in sorted(set(prob.n.tolist())):
+        i = int(np.nonzero(prob.n == side)[0][0])
+        ref = ora.conv_sub([side], [prob.K[i]], prob.s, prob.kernels[offs_k[i]:offs_k[i + 1]],
+                           scene[offs_f[i]:offs_f[i + 1]])
+        got = model[offs_d[i]:offs_d[i + 1]]
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        _say(f"cfg4 full frame {i} (n={side}): max rel err {err:.2e}")
+        assert err <= 1e-5
+    resid = synth.f32(rng.standard_normal(prob.data_size))
+    adj = plan.convolve_subsample_adj(resid).cpu().numpy().astype(np.float64)
+    lhs, rhs = np.dot(model, resid), np.dot(scene, adj)
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(model) * np.linalg.norm(resid)
+    # loss + gradient at full size: chi^2 is quadratic in h, so central differences are exact
+    d = synth.f32(model + rng.normal(0, 10, model.shape))
+    w = np.full(prob.data_size, 0.01)
+    plan.set_frames(d, w, prob.kernels, prob.W)
+    plan0 = st.Plan.for_problem(prob, conv_algo=algo, lam=0.0)
+    plan0.set_frames(d, w, prob.kernels, prob.W)
+    p = synth.eval_point(prob, "near", rng)
+    _, g = plan0.loss_grad(p)
+    g = g.cpu().numpy().astype(np.float64)
+    NN = prob.N ** 2
+    delta = np.zeros(prob.n_params)
+    delta[:NN] = rng.standard_normal(NN)
+    pp, pm = synth.f32(p + delta), synth.f32(p - delta)
+    fd = plan0.loss_grad(pp, want_grad=False)[0][2].item() - plan0.loss_grad(pm, want_grad=False)[0][2].item()
+    an = float(np.dot(g, pp - pm))
+    _say(f"cfg4 full: directional difference {fd:.8e} vs gradient {an:.8e}")
+    assert abs(fd - an) <= 1e-4 * abs(an)
