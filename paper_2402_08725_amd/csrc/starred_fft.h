@@ -11,6 +11,7 @@ constexpr int kFftThreads = 256;
 constexpr int kFftTargetElems = 2048;  // complex elements per work group and buffer
 constexpr int kAdjBins = 4;            // spectral adjoint: bins per thread
 constexpr int kAdjFrames = 4;          // spectral adjoint: frames held in registers at once
+constexpr int kAdjQB = 8;              // spectral adjoint: dot products reduced per LDS pass
 
 // A 1-D transform length L = product of radices (4, 2, 3, 5) and the offset of
 // its twiddle table e^{-2 pi i m / L}, m < L.

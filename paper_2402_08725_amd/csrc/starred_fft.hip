@@ -441,7 +441,9 @@ struct OpFwdCols {
 // S''_i(K) F_i(K), F_i = H + Gamma_i w x w + sum_k a_ik gy_k x gx_k (Eq. 9).
 // One thread per output bin of a class, looping over a chunk of its frames, so
 // the shared spectra of the bin's aliases are read once per chunk. ----
-template <int S>
+// MS > 0: the point-source spectra of the bin's aliases (M <= MS) are formed once
+// per work item and kept in registers; MS = 0 reads the tables for every frame.
+template <int S, int MS>
 __global__ __launch_bounds__(kFftThreads) void k_spec_fwd(const SpecItem *__restrict__ items,
                                                           const ClassFft *__restrict__ classes,
                                                           const FrameFft *__restrict__ fr,
@@ -473,21 +475,44 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_fwd(const SpecItem *__rest
             hv[a * S + b] = half_get(Hh + c.hh_off, P, Kys[a], Kxs[b]);
             wv[a * S + b] = cmul(t[Kys[a]], t[Kxs[b]]);
         }
+    constexpr int MR = MS > 0 ? MS : 1;
+    float2 rk[S * S][MR];
+    if (MS > 0) {
+        #pragma unroll
+        for (int a = 0; a < S; ++a)
+            #pragma unroll
+            for (int b = 0; b < S; ++b)
+                #pragma unroll
+                for (int k = 0; k < MR; ++k) {
+                    const float2 *tk = t + (long long)(1 + 4 * k) * P;  // [gx | gy | dgx | dgy]
+                    rk[a * S + b][k] = k < M ? cmul(tk[P + Kys[a]], tk[Kxs[b]]) : make_float2(0.f, 0.f);
+                }
+    }
     for (int f = it.f0; f < it.f0 + it.nf; ++f) {
         const int i = cls_frames[c.cf_off + f];
         const FrameFft &fi = fr[i];
         const float G = params[(long long)N * N + i];
         const float *ai = params + (long long)N * N + E + (long long)i * M;
         const float2 *Si = Sp + fi.s_off;
+        float av[MR];
+        if (MS > 0) {
+            #pragma unroll
+            for (int k = 0; k < MR; ++k) av[k] = k < M ? ai[k] : 0.f;
+        }
         float2 acc = make_float2(0.f, 0.f);
         #pragma unroll
         for (int a = 0; a < S; ++a)
             #pragma unroll
             for (int b = 0; b < S; ++b) {
                 float2 F = cadd(hv[a * S + b], cscale(wv[a * S + b], G));
-                for (int k = 0; k < M; ++k) {
-                    const float2 *tk = t + (long long)(1 + 4 * k) * P;  // [gx | gy | dgx | dgy]
-                    F = cadd(F, cscale(cmul(tk[P + Kys[a]], tk[Kxs[b]]), ai[k]));
+                if (MS > 0) {
+                    #pragma unroll
+                    for (int k = 0; k < MR; ++k) F = cadd(F, cscale(rk[a * S + b][k], av[k]));
+                } else {
+                    for (int k = 0; k < M; ++k) {
+                        const float2 *tk = t + (long long)(1 + 4 * k) * P;
+                        F = cadd(F, cscale(cmul(tk[P + Kys[a]], tk[Kxs[b]]), ai[k]));
+                    }
                 }
                 acc = cadd(acc, cmul(half_get(Si, P, Kys[a], Kxs[b]), F));
             }
@@ -750,8 +775,8 @@ __global__ void k_tables(const ClassFft *__restrict__ classes, const float2 *__r
 // the frame's dot products <g_i, x> = sum over the full spectrum of G_i conj(X_hat)
 // (Parseval; half spectrum with weight 2 off the Kx = 0 and P/2 columns) for x the
 // window indicator (dGamma_i), r_k (da_ik) and r_k (X - c_k)/sigma^2 (dc_k, x and y),
-// whose spectra are products of the 1-D tables. Each wave reduces its bins; the
-// per-wave partials are summed per frame by k_fsum_parts.
+// whose spectra are products of the 1-D tables. Each block reduces its bins
+// through LDS; the per-block partials are summed per frame by k_fsum_parts.
 __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const SpecItem *__restrict__ items,
                                                           const ClassFft *__restrict__ classes,
                                                           const FrameFft *__restrict__ fr,
@@ -767,8 +792,8 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const SpecItem *__rest
     const ClassFft &c = classes[it.cls];
     const int P = c.P, Q = c.Q, HP = P / 2 + 1, nbins = P * HP;
     const float2 *t = tab + c.tab_off;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int pb = (it.bin0 / (kFftThreads * B)) * (kFftThreads / 64) + wave;  // this wave's partial slot
+    __shared__ float red[kAdjFrames * kAdjQB * kFftThreads];
+    const int pb = it.bin0 / (kFftThreads * B);  // this block's partial slot
     const int Q3 = 1 + 3 * M;
     int Ky[B], Kx[B], rq[B];
     float wgt[B];
@@ -801,29 +826,41 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const SpecItem *__rest
                 gs[b] = cadd(gs[b], G[f][b]);
             }
         }
-        // Parseval dot products of every frame of the chunk with each table spectrum
-        for (int q = 0; q < Q3; ++q) {
-            const float2 *ty = t, *tx = t;
-            if (q > 0) {
-                const int k = (q - 1) % M, kind = (q - 1) / M;  // 0: r_k, 1: d/dcx, 2: d/dcy
-                const float2 *tk = t + (long long)(1 + 4 * k) * P;
-                ty = tk + (kind == 2 ? 3 * P : P);
-                tx = tk + (kind == 1 ? 2 * P : 0);
-            }
-            float2 X[B];
-            #pragma unroll
-            for (int b = 0; b < B; ++b) X[b] = cmul(ty[Ky[b]], tx[Kx[b]]);
-            #pragma unroll
-            for (int f = 0; f < FC; ++f) {
-                if (f >= nfc) break;
-                float v = 0.f;
+        // Parseval dot products of every frame of the chunk with each table spectrum,
+        // reduced over the block through LDS in groups of kAdjQB quantities
+        for (int q0 = 0; q0 < Q3; q0 += kAdjQB) {
+            const int nq = min(kAdjQB, Q3 - q0);
+            for (int qq = 0; qq < nq; ++qq) {
+                const int q = q0 + qq;
+                const float2 *ty = t, *tx = t;
+                if (q > 0) {
+                    const int k = (q - 1) % M, kind = (q - 1) / M;  // 0: r_k, 1: d/dcx, 2: d/dcy
+                    const float2 *tk = t + (long long)(1 + 4 * k) * P;
+                    ty = tk + (kind == 2 ? 3 * P : P);
+                    tx = tk + (kind == 1 ? 2 * P : 0);
+                }
+                float2 X[B];
                 #pragma unroll
-                for (int b = 0; b < B; ++b) v += wgt[b] * (G[f][b].x * X[b].x + G[f][b].y * X[b].y);
-                double dv = (double)v;
+                for (int b = 0; b < B; ++b) X[b] = cmul(ty[Ky[b]], tx[Kx[b]]);
                 #pragma unroll
-                for (int off = 32; off > 0; off >>= 1) dv += __shfl_xor(dv, off, 64);
-                if (lane == 0) part[((long long)fid[f] * maxpb + pb) * Q3 + q] = dv;
+                for (int f = 0; f < FC; ++f) {
+                    float v = 0.f;
+                    #pragma unroll
+                    for (int b = 0; b < B; ++b) v += wgt[b] * (G[f][b].x * X[b].x + G[f][b].y * X[b].y);
+                    red[(f * kAdjQB + qq) * kFftThreads + threadIdx.x] = v;
+                }
             }
+            __syncthreads();
+            for (int pr = threadIdx.x; pr < FC * nq; pr += kFftThreads) {
+                const int f = pr / nq, qq = pr - f * nq;
+                if (f < nfc) {
+                    const float *rr = red + (f * kAdjQB + qq) * kFftThreads;
+                    double acc = 0.0;
+                    for (int u = 0; u < kFftThreads; ++u) acc += (double)rr[u];
+                    part[((long long)fid[f] * maxpb + pb) * Q3 + q0 + qq] = acc;
+                }
+            }
+            __syncthreads();
         }
     }
     #pragma unroll
@@ -831,7 +868,7 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const SpecItem *__rest
         if (rq[b] >= 0) Gp[c.gp_off + (long long)(it.f0 / c.gfch) * nbins + rq[b]] = gs[b];
 }
 
-// per-frame sums of the per-wave partials -> fsum[i][q] (fixed order)
+// per-frame sums of the per-block partials -> fsum[i][q] (fixed order)
 __global__ __launch_bounds__(kFftThreads) void k_fsum_parts(const ClassFft *__restrict__ classes,
                                                             const FrameFft *__restrict__ fr, int M, int maxpb,
                                                             const double *__restrict__ part, double *__restrict__ fsum)
@@ -840,7 +877,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fsum_parts(const ClassFft *__re
     const int i = blockIdx.x;
     const ClassFft &c = classes[fr[i].cls];
     const int per_block = kFftThreads * kAdjBins;
-    const int npb = ((c.P * (c.P / 2 + 1) + per_block - 1) / per_block) * (kFftThreads / 64);
+    const int npb = (c.P * (c.P / 2 + 1) + per_block - 1) / per_block;
     const int Q3 = 1 + 3 * M;
     for (int q = 0; q < Q3; ++q) {
         double acc = 0.0;
@@ -947,15 +984,17 @@ hipError_t fft_spectra(hipStream_t st, const FftPlanDev &d, const float *params,
 hipError_t fft_spec_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s)
 {
     if (d.n_spec <= 0) return hipSuccess;
-    if (s == 1)
-        hipLaunchKernelGGL(k_spec_fwd<1>, dim3(d.n_spec), dim3(kFftThreads), 0, st, d.spec, d.classes, d.frames,
-                           d.cls_frames, d.S, d.Hh, d.tab, params, N, E, M, d.Rh);
-    else if (s == 2)
-        hipLaunchKernelGGL(k_spec_fwd<2>, dim3(d.n_spec), dim3(kFftThreads), 0, st, d.spec, d.classes, d.frames,
-                           d.cls_frames, d.S, d.Hh, d.tab, params, N, E, M, d.Rh);
-    else
-        hipLaunchKernelGGL(k_spec_fwd<3>, dim3(d.n_spec), dim3(kFftThreads), 0, st, d.spec, d.classes, d.frames,
-                           d.cls_frames, d.S, d.Hh, d.tab, params, N, E, M, d.Rh);
+#define SPEC_FWD(SS, MS)                                                                                     \
+    hipLaunchKernelGGL((k_spec_fwd<SS, MS>), dim3(d.n_spec), dim3(kFftThreads), 0, st, d.spec, d.classes,     \
+                       d.frames, d.cls_frames, d.S, d.Hh, d.tab, params, N, E, M, d.Rh)
+    if (s == 1) {
+        if (M <= 16) SPEC_FWD(1, 16); else SPEC_FWD(1, 0);
+    } else if (s == 2) {
+        if (M <= 4) SPEC_FWD(2, 4); else if (M <= 8) SPEC_FWD(2, 8); else SPEC_FWD(2, 0);
+    } else {
+        if (M <= 2) SPEC_FWD(3, 2); else SPEC_FWD(3, 0);
+    }
+#undef SPEC_FWD
     return hipGetLastError();
 }
 

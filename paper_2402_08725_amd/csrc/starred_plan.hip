@@ -514,7 +514,7 @@ static int build_fft(starred_plan *p)
             gp += (long long)cl.ngch * nbins;
             cl.hc_off = hc;
             hc += (long long)cl.F * cl.F;
-            maxpb = std::max(maxpb, nbb * (kFftThreads / 64));
+            maxpb = std::max(maxpb, nbb);
             for (int f0 = 0; f0 < cl.ncf; f0 += cl.gfch)
                 for (int bb = 0; bb < nbb; ++bb)
                     sp.push_back(SpecItem{c, f0, std::min(cl.gfch, cl.ncf - f0), bb * per_block});
