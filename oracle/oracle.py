@@ -41,7 +41,8 @@ def lib():
         _lib.ora_sigma_from_fwhm.argtypes = [ctypes.c_double]
         for name in ["ora_render_scene", "ora_conv_sub", "ora_conv_sub_adj", "ora_starlet_fwd",
                      "ora_starlet_adj", "ora_loss_grad", "ora_forward_model", "ora_moffat",
-                     "ora_psf_render", "ora_psf_model", "ora_psf_loss_grad", "ora_adam_step"]:
+                     "ora_psf_render", "ora_psf_model", "ora_psf_loss_grad", "ora_adam_step",
+                     "ora_noise_variance"]:
             getattr(_lib, name).restype = None
         _lib.ora_num_threads.restype = ctypes.c_int
         _lib.ora_frame_offsets.restype = ctypes.c_int
@@ -186,6 +187,14 @@ def psf_loss_grad(prob, data, invvar, params, want_grad=True, sgn_override=None,
                             ctypes.c_double(prob.fwhm), _d(data), _d(invvar), _d(Wv), _d(params),
                             _d(grad), _d(loss), so.ctypes.data_as(_B) if so is not None else None)
     return loss, grad
+
+
+def noise_variance(n1, K1, s, N, J, kernel1, sigma2_data):
+    """Exact per-pixel variance (J x N x N) of Phi^T S_1^T C_up^-1 delta_d (Sec. 2.3)."""
+    kernel1, sigma2_data = _f64(kernel1), _f64(sigma2_data)
+    out = np.zeros(J * N * N)
+    lib().ora_noise_variance(n1, K1, s, N, J, _d(kernel1), _d(sigma2_data), _d(out))
+    return out
 
 
 def adam_step(params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):

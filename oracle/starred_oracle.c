@@ -679,6 +679,45 @@ void ora_psf_loss_grad(int S, int n, int ssub, int N, int J, int w_stride, doubl
 }
 
 /* ------------------------------------------------------------------------- */
+/* Noise propagated to the starlet coefficients (Sec. 2.3, App. B)           */
+/* ------------------------------------------------------------------------- */
+
+/* Exact variance maps of W's Monte Carlo estimate. White noise delta_d on the
+ * fine window of frame 1 with diagonal covariance C_up (the data-pixel variance
+ * sigma2_data replicated over each s x s block) is propagated as
+ * Phi^T S_1^T C_up^-1 delta_d. Its coefficient (j, X) has variance
+ *   Var_j(X) = sum_y [Phi^T S_1^T]_{(j,X), y}^2 / sigma_up^2(y),
+ * accumulated here column by column: for every fine pixel y, the image
+ * S_1^T e_y (the correlation of a unit impulse with the kernel) is placed in the
+ * window of h and transformed. var_out: J x N x N. */
+void ora_noise_variance(int n1, int K1, int s, int N, int J, const double *kernel1,
+                        const double *sigma2_data, double *var_out)
+{
+    int F = s * n1, o = (N - F) / 2;
+    long NN = (long)N * N;
+    double *e = (double *)calloc((size_t)F * F, sizeof(double));
+    double *g = (double *)malloc(sizeof(double) * F * F);
+    double *img = (double *)calloc(NN, sizeof(double));
+    double *co = (double *)malloc(sizeof(double) * J * NN);
+    for (long q = 0; q < J * NN; ++q) var_out[q] = 0.0;
+    for (int y = 0; y < F; ++y)
+        for (int x = 0; x < F; ++x) {
+            e[(long)y * F + x] = 1.0;
+            corr_same(e, F, kernel1, K1, g);
+            e[(long)y * F + x] = 0.0;
+            for (int yy = 0; yy < F; ++yy)
+                for (int xx = 0; xx < F; ++xx) img[(long)(yy + o) * N + xx + o] = g[(long)yy * F + xx];
+            ora_starlet_fwd(N, J, img, co);
+            double s2 = sigma2_data[(long)(y / s) * n1 + (x / s)];
+            for (long q = 0; q < J * NN; ++q) var_out[q] += co[q] * co[q] / s2;
+        }
+    free(e);
+    free(g);
+    free(img);
+    free(co);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Adam update (Kingma & Ba 2015), the optimiser step of the gradient-based   */
 /* fit (Sec. 2.4). lr is per element.                                         */
 /* ------------------------------------------------------------------------- */

@@ -442,3 +442,64 @@ def test_planted_source_recovery_noiseless_cfg1():
     x = res.x * scale
     assert np.abs(x[E * M:] - pt[free][E * M:]).max() < 1e-3
     assert np.abs(x[:E * M] / pt[free][:E * M] - 1).max() < 1e-5
+
+
+# --------------------------------------------------------------------------- #
+# Noise propagated to the starlet coefficients (Sec. 2.3, App. B)              #
+# --------------------------------------------------------------------------- #
+
+def test_noise_variance_delta_kernel_is_starlet_row_norms():
+    """With a unit-impulse kernel and s = 1 the propagated map is Phi^T C^-1 d, so the
+    variance is the squared row norms of Phi^T weighted by 1/sigma^2: built here from
+    scipy.ndimage mirror filtering of unit impulses, independently of the oracle."""
+    N, J = 12, 3
+    k = np.zeros((1, 1))
+    k[0, 0] = 1.0
+    sig2 = RNG.uniform(0.5, 2.0, N * N)
+    got = ora.noise_variance(N, 1, 1, N, J, k.ravel(), sig2).reshape(J, N * N)
+    ref = np.zeros((J, N * N))
+    for yx in range(N * N):
+        e = np.zeros((N, N))
+        e.flat[yx] = 1.0
+        c = e
+        planes = []
+        for j in range(J - 1):
+            cn = _h_smooth_scipy(c, j)
+            planes.append(c - cn)
+            c = cn
+        planes.append(c)
+        for j in range(J):
+            ref[j] += planes[j].ravel() ** 2 / sig2[yx]
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-15)
+
+
+def test_noise_variance_matches_monte_carlo():
+    """Brute-force Monte Carlo of the definition with numpy draws: within 4 standard
+    errors of the variance estimate."""
+    n1, K1, s, J = 6, 5, 2, 3
+    N = 16
+    rng = np.random.default_rng(3)
+    k = rng.uniform(0, 1, (K1, K1))
+    k /= k.sum()
+    sig2 = rng.uniform(1.0, 4.0, n1 * n1)
+    var = ora.noise_variance(n1, K1, s, N, J, k.ravel(), sig2).reshape(J, N, N)
+    F = s * n1
+    o = (N - F) // 2
+    up = np.repeat(np.repeat(sig2.reshape(n1, n1), s, 0), s, 1)
+    R = 4000
+    acc = np.zeros((J, N, N))
+    for _ in range(R):
+        dd = rng.standard_normal((F, F)) * np.sqrt(up)
+        g = scipy.signal.correlate2d(dd / up, k, mode="same")    # S^T (odd K: centre floor(K/2))
+        img = np.zeros((N, N))
+        img[o:o + F, o:o + F] = g
+        c = img
+        for j in range(J - 1):
+            cn = _h_smooth_scipy(c, j)
+            acc[j] += (c - cn) ** 2
+            c = cn
+        acc[J - 1] += c ** 2
+    mc = acc / R
+    inside = var > 1e-12 * var.max()
+    rel = np.abs(mc[inside] - var[inside]) / var[inside]
+    assert np.median(rel) < 4 * np.sqrt(2.0 / R)
