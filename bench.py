@@ -160,7 +160,12 @@ def main():
     plan.set_profiling(False)
     stage_ms = {k: v_["ms"] / max(v_["count"], 1) for k, v_ in prof.items() if v_["count"]}
 
-    roof = roofline(prob, plan, stage_ms)
+    # ---- device time of each stage's launches alone (back to back, HIP events) ----
+    timed = (["fft_fused", "fft_spec", "fft_mcols", "fft_mrows", "fft_rcols", "fft_acols", "fft_fsum", "fft_arows",
+              "spectra", "starlet"] if plan.conv_algo == 2 else ["render", "conv_fwd", "conv_adj", "grad_sums",
+                                                                "starlet"])
+    kernel_ms = {k: plan.time_stage(x, k, reps=50) for k in timed}
+    roof = roofline(prob, plan, kernel_ms)
     out = {
         "metric": "loss+grad evals/s (epoch-pixels/s), fused vs plain, grad rel err <=1e-4",
         "value": value, "unit": "epoch-px/s", "n_gpus": 1, "steps": args.steps,
@@ -179,6 +184,7 @@ def main():
                             "plain_epoch_px_per_s": plain_eps * prob.data_size,
                             "speedup": fused_eps / plain_eps} if plain_eps else None),
         "stage_ms_per_step": {k: round(v_, 4) for k, v_ in stage_ms.items()},
+        "stage_device_ms": {k: round(v_, 4) for k, v_ in kernel_ms.items()},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
@@ -187,7 +193,8 @@ def main():
 
 
 def roofline(prob, plan, stage_ms):
-    """Roofline of the dominant kernel, from its measured average duration."""
+    """Roofline of the dominant kernel, from its average device duration (its
+    launches timed back to back with HIP events on the plan's stream)."""
     if plan.conv_algo == 1:
         fwd_ms = stage_ms["conv_fwd"]
         flops = conv_flops(prob)
@@ -198,7 +205,7 @@ def roofline(prob, plan, stage_ms):
                 "avg_launch_ms": round(fwd_ms, 4), "algorithmic_flops": flops}
     # FFT path: every pass is a memory-bound launch; take the slowest one
     alg = fft_kernel_bytes(prob)
-    name = max(alg, key=lambda k: stage_ms.get(k, 0.0))
+    name = max((k for k in alg if k in stage_ms), key=lambda k: stage_ms[k])
     ms = stage_ms[name]
     by = alg[name]
     achieved = by / (ms * 1e-3) / 1e9
@@ -210,12 +217,15 @@ def roofline(prob, plan, stage_ms):
 
 
 FFT_KERNEL_NAMES = {
+    "fft_fused": "k_frame_fwd (one-launch forward per frame: spectral product, inverse 2-D transform, "
+                 "residual, chi-square, forward 2-D transform of rho)",
     "fft_spec": "k_spec_fwd (spectral product and alias fold)",
     "fft_mcols": "k_lines<OpMCols> (inverse columns of the model spectra)",
     "fft_mrows": "k_fwd_rows (inverse rows, residual, chi-square, rho row spectra)",
     "fft_rcols": "k_lines<OpRhoCols> (forward columns of rho)",
-    "fft_acols": "k_spec_adj (adjoint spectral products, frame sums, Parseval dot products)",
+    "fft_acols": "k_spec_adj (adjoint spectral products summed over frames, Parseval dot products)",
     "fft_arows": "k_lines<OpGCols/OpGRows> (inverse transform of the summed adjoint spectra)",
+    "fft_fsum": "k_adj_sums (sum of the frame-chunk spectra; per-frame sums of the block dot products)",
 }
 
 
@@ -245,6 +255,7 @@ def fft_kernel_bytes(prob):
     """Algorithmic bytes of each FFT-path launch for the whole batch: what each
     pass must read and write once (complex64 spectra, FP32 images)."""
     tot = {k: 0 for k in FFT_KERNEL_NAMES}
+    fused_classes = set()
     for n, K in zip(prob.n, prob.K):
         n = int(n)
         F = prob.s * n
@@ -252,32 +263,60 @@ def fft_kernel_bytes(prob):
         Q = P // prob.s
         HP, HQ = P // 2 + 1, Q // 2 + 1
         s2 = prob.s * prob.s
+        tot["fft_acols"] += 8 * (P * HP + Q * HQ)      # kernel spectrum and rho_hat read once
+        if _fused(Q, n, P, prob.M):
+            # kernel spectrum, data and weights in, rho_hat out; the class's h spectrum once
+            tot["fft_fused"] += 8 * P * HP + 8 * n * n + 8 * Q * HQ
+            if (n, int(K)) not in fused_classes:
+                fused_classes.add((n, int(K)))
+                tot["fft_fused"] += 8 * P * HP
+            continue
         tot["fft_spec"] += 8 * (s2 * Q * HQ + Q * HQ)
         tot["fft_mcols"] += 8 * (Q * HQ + n * HQ)
         tot["fft_mrows"] += 8 * (2 * n * HQ) + 8 * n * n
         tot["fft_rcols"] += 8 * (n * HQ + Q * HQ)
-        tot["fft_acols"] += 8 * (P * HP + Q * HQ)      # kernel spectrum and rho_hat read once
-    for F_, P_, nch in _classes(prob):
+    Q3 = 1 + 3 * prob.M
+    npb = {int(P_): nrr for _, P_, _, nrr in _classes(prob)}
+    for n, K in zip(prob.n, prob.K):
+        P = _good(prob.s * int(n) + int(K) // 2, prob.s)
+        tot["fft_fsum"] += 8 * (npb[P] * Q3 + Q3)       # block partials in, frame sums out
+    for F_, P_, nch, _ in _classes(prob):
         HP_ = P_ // 2 + 1
         tot["fft_acols"] += 8 * nch * P_ * HP_          # summed spectra of each frame chunk
-        tot["fft_arows"] += 8 * (nch * P_ * HP_ + F_ * HP_) + 4 * F_ * F_
+        tot["fft_fsum"] += 8 * (nch + 1) * P_ * HP_     # chunk spectra in, their sum out
+        tot["fft_arows"] += 8 * (P_ * HP_ + 2 * F_ * HP_) + 4 * F_ * F_
     return {k: float(v) for k, v in tot.items()}
 
 
+def _fused(Q, n, P, M):
+    """Whether frames of this shape take the one-launch forward: its two LDS planes of
+    max(Q/2+1, n) lines of Q+1 complex values, the Q twiddles and the (1+4M) P table
+    values fit in 150 KiB."""
+    return (2 * max(Q // 2 + 1, n) * (Q + 1) + Q + (1 + 4 * M) * P) * 8 <= 150 * 1024
+
+
+ADJ_FRAMES = 2  # frames per work group of the frequency-domain adjoint (kAdjFrames)
+
+
 def _classes(prob):
-    """(F, P, number of frame chunks) of each shape class, as the plan groups them."""
+    """(F, P, frame chunks, row ranges) of each shape class, as the plan groups them
+    for the frequency-domain adjoint (chunks of ADJ_FRAMES frames, about 512 work groups)."""
     out = {}
     for n, K in zip(prob.n, prob.K):
         key = (int(n), int(K))
         out[key] = out.get(key, 0) + 1
+    nchunks = sum((ncf + ADJ_FRAMES - 1) // ADJ_FRAMES for ncf in out.values())
     res = []
     for (n, K), ncf in out.items():
         F = prob.s * n
         P = _good(F + K // 2, prob.s)
-        nbb = (P * (P // 2 + 1) + 1023) // 1024
-        want = max(1, 768 // max(1, nbb))
-        gfch = max(1, min(32, (ncf + want - 1) // want))
-        res.append((F, P, (ncf + gfch - 1) // gfch))
+        HP = P // 2 + 1
+        CX = 64 if HP <= 64 else (128 if HP <= 128 else 256)
+        RG = 256 // CX
+        want = max(1, (512 + nchunks - 1) // nchunks)
+        arr = (P + want - 1) // want
+        arr = min(64, max(4 * RG, ((arr + RG - 1) // RG) * RG))
+        res.append((F, P, (ncf + ADJ_FRAMES - 1) // ADJ_FRAMES, (P + arr - 1) // arr))
     return res
 
 

@@ -173,11 +173,21 @@ int starred_step(starred_plan *plan, float *params, float *m, float *v, int32_t 
  * timing reports one STARRED_STAGE_GRAPH interval per call. */
 int starred_set_graph_mode(starred_plan *plan, int32_t enable);
 
+/* FFT algorithm, loss and gradient: frames whose Q x Q model and residual
+ * spectra fit in LDS (Q = P/s, see the FFT notes of starred_plan_create) run the
+ * forward of Eqs. 8 and 10 in one launch with a work group per frame; with
+ * enable = 0 every frame takes the batched line passes instead (same results up
+ * to rounding order). Default 1. Drops captured graphs. */
+int starred_set_fft_fused(starred_plan *plan, int32_t enable);
+
 /* Which convolution algorithm the plan runs (STARRED_CONV_DIRECT or _FFT). */
 int starred_conv_algo(const starred_plan *plan);
 
 /* Stage timing, for measurement. While enabled, loss_grad and step record a
- * pair of HIP events on the plan's stream around each stage below.
+ * pair of HIP events on the plan's stream around each stage below, and each
+ * call first runs a short idle kernel (about 1 ms) on that stream, so that the
+ * call's launches are queued before they run and an interval holds device
+ * time only, not host launch gaps.
  * starred_profile_read synchronises the stream, returns per stage the summed
  * milliseconds (ms_out[STARRED_NUM_STAGES]) and the number of timed launches
  * (count_out[STARRED_NUM_STAGES]; either pointer may be NULL), then resets. */
@@ -198,10 +208,28 @@ enum {
     STARRED_STAGE_FFT_ACOLS,    /* ... kernel-spectrum products, their sum over frames and the
                                    per-frame dot products for Gamma, a and c */
     STARRED_STAGE_FFT_AROWS,    /* ... inverse transform of the summed spectra (dL/dh) */
+    STARRED_STAGE_FFT_FSUM,     /* ... sums of the frame-chunk spectra and of the per-block
+                                   dot products per frame */
+    STARRED_STAGE_FFT_FUSED,    /* FFT path, inside CONV_FWD: one-launch forward of the frames
+                                   whose spectra fit in LDS (product, both 2-D transforms,
+                                   residual, chi-square) */
     STARRED_NUM_STAGES
 };
 int starred_set_profiling(starred_plan *plan, int32_t enable);
 int starred_profile_read(starred_plan *plan, double *ms_out, int64_t *count_out);
+
+/* Measurement aid: the device time of one stage's launches alone. Runs one
+ * loss+gradient evaluation at params (device, num_params floats) so that every
+ * buffer the stage reads holds real data, then launches the stage reps times back
+ * to back between two HIP events on the plan's stream (after a short idle lead-in,
+ * so that the launches are queued ahead of the device) and writes the average
+ * milliseconds per repetition to *ms_out (host). Blocks until done. Stages:
+ * deconvolution mode, FFT algorithm: SPECTRA, FFT_FUSED, FFT_SPEC, FFT_MCOLS,
+ * FFT_MROWS, FFT_RCOLS, FFT_ACOLS, FFT_FSUM, FFT_AROWS; direct algorithm: RENDER, CONV_FWD,
+ * CONV_ADJ, GRAD_SUMS; both: STARLET. Other stages, PSF mode: STARRED_EUNSUPPORTED.
+ * The plan's internal work buffers are left in an unspecified state (the next
+ * evaluation recomputes them); caller-owned memory is not touched. */
+int starred_time_stage(starred_plan *plan, const float *params, int32_t stage, int32_t reps, double *ms_out);
 
 /* Measurement aid: a plain device copy of n floats (n a multiple of 4) from src to
  * dst on the plan's stream; its memory-counter readings calibrate the ones of the

@@ -9,9 +9,17 @@ namespace starred {
 
 constexpr int kFftThreads = 256;
 constexpr int kFftTargetElems = 2048;  // complex elements per work group and buffer
-constexpr int kAdjBins = 4;            // spectral adjoint: bins per thread
-constexpr int kAdjFrames = 4;          // spectral adjoint: frames held in registers at once
-constexpr int kAdjQB = 8;              // spectral adjoint: dot products reduced per LDS pass
+constexpr int kFusedThreads = 1024;     // one-launch forward: threads per frame
+constexpr size_t kFusedLdsMax = 150 * 1024;  // one-launch forward: LDS of its two Q x (Q+1) planes
+constexpr int kFwdFrames = 4;          // spectral product: frames whose loads are issued together
+constexpr int kAdjFrames = 2;          // spectral adjoint: frames of a work group (a chunk)
+constexpr int kAdjSB = 4;              // spectral adjoint: sources per pass over the rows
+constexpr int kAdjBlocks = 512;        // spectral adjoint: work groups aimed at per launch
+constexpr int kAdjMinRows = 4;         // spectral adjoint: fewest rows per thread
+constexpr int kAdjMaxRows = 64;        // spectral adjoint: most rows per work group
+// spectral adjoint: column lanes of a work group (64, 128 or 256, a divisor of its
+// threads), the smallest that covers the P/2+1 columns
+__host__ __device__ inline int adj_lanes(int HP) { return HP <= 64 ? 64 : (HP <= 128 ? 128 : 256); }
 
 // A 1-D transform length L = product of radices (4, 2, 3, 5) and the offset of
 // its twiddle table e^{-2 pi i m / L}, m < L.
@@ -35,8 +43,12 @@ struct ClassFft {
     int ncf;            // number of frames of the class
     int ngch;           // frame chunks of the frequency-domain adjoint
     int gfch;           // frames per chunk
-    long long gp_off;   // [ngch][P][P/2+1] summed adjoint spectra of each chunk
+    long long gp_off;   // [ngch][P][P/2+1] summed adjoint spectra of each chunk (total in chunk 0)
     long long hc_off;   // [F][F] the class's contribution to dL/dh (its window)
+    int fused;          // frames of this class take the one-launch forward (spectra fit in LDS)
+    int arr;            // spectral adjoint: rows of the half spectrum per work group
+    int nrr;            // spectral adjoint: row ranges (per-frame partial slots)
+    int pad;
 };
 
 struct FrameFft {
@@ -92,14 +104,24 @@ struct FftPlanDev {
     int n_frames = 0;
     SpecItem *aspec = nullptr;
     int n_aspec = 0;
-    int maxpb = 0;           // per-wave partial slots per frame
+    int maxpb = 0;           // per-frame partial slots (largest nrr)
+    long long total_bins = 0;  // sum over classes of P (P/2 + 1)
     double *apart = nullptr; // [E][maxpb][1 + 3M]
     float2 *Gp = nullptr;
     float *hcls = nullptr;
     LinePass gcols, grows;
+    // loss+gradient forward: frames of fused classes in one launch (a work group
+    // per frame); the line passes below cover the remaining frames
+    SpecItem *spec_lg = nullptr;
+    int n_spec_lg = 0;
+    int *fused = nullptr;
+    int n_fused = 0;
+    size_t fused_lds = 0;
+    LinePass fcols_lg, frows_lg, rcols_lg;
 };
 
-// Deterministic block sum of one double per thread (kFftThreads); thread 0 holds it.
+// Deterministic block sum of one double per thread (NT threads); thread 0 holds it.
+template <int NT = kFftThreads>
 __device__ __forceinline__ double block_sum_d_fft(double v, double *sh)
 {
     #pragma unroll
@@ -110,7 +132,7 @@ __device__ __forceinline__ double block_sum_d_fft(double v, double *sh)
     double r = 0.0;
     if (threadIdx.x == 0) {
         #pragma unroll
-        for (int i = 0; i < kFftThreads / 64; ++i) r += sh[i];
+        for (int i = 0; i < NT / 64; ++i) r += sh[i];
     }
     __syncthreads();
     return r;
@@ -119,7 +141,8 @@ __device__ __forceinline__ double block_sum_d_fft(double v, double *sh)
 hipError_t fft_prep_kernels(hipStream_t st, const FftPlanDev &d, const float *psf, int s);
 hipError_t fft_spectra(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M,
                        float sigma);
-hipError_t fft_spec_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s);
+hipError_t fft_spec_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,
+                        bool lg = false);
 hipError_t fft_model_cols(hipStream_t st, const FftPlanDev &d);
 hipError_t fft_model_rows(hipStream_t st, const FftPlanDev &d, const float *data, const float *invvar,
                           double *part_chi, float *model);
@@ -128,9 +151,22 @@ hipError_t fft_adj_cols(hipStream_t st, const FftPlanDev &d);
 hipError_t fft_adj_rows(hipStream_t st, const FftPlanDev &d, float *g);
 hipError_t fft_resid_rows(hipStream_t st, const FftPlanDev &d, const float *resid);
 hipError_t fft_adjoint(hipStream_t st, const FftPlanDev &d, float *g);
-hipError_t fft_spec_adj(hipStream_t st, const FftPlanDev &d, int M, double *fsum);
+hipError_t fft_spec_adj(hipStream_t st, const FftPlanDev &d, int M);
+hipError_t fft_adj_sums(hipStream_t st, const FftPlanDev &d, int M, double *fsum);
+// bytes of LDS the one-launch forward needs for a class: two planes of
+// max(Q/2+1, n) lines of Q+1 values, the Q twiddles and the (1+4M) P table values
+inline size_t fused_lds_bytes(int Q, int n, int P, int M)
+{
+    const int rows = (Q / 2 + 1) > n ? (Q / 2 + 1) : n;
+    return ((size_t)2 * rows * (Q + 1) + Q + (size_t)(1 + 4 * M) * P) * 8;
+}
+hipError_t fft_fused_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,
+                         const float *data, const float *invvar, double *part_chi);
+hipError_t fft_model_cols_lg(hipStream_t st, const FftPlanDev &d);
+hipError_t fft_model_rows_lg(hipStream_t st, const FftPlanDev &d, const float *data, const float *invvar,
+                             double *part_chi);
+hipError_t fft_rho_cols_lg(hipStream_t st, const FftPlanDev &d);
 hipError_t fft_grad_h_inverse(hipStream_t st, const FftPlanDev &d);
-hipError_t fft_finalize_h(hipStream_t st, const FftPlanDev &d, int N, const float *prior, float *grad_h);
 hipError_t fft_scene_model(hipStream_t st, const FftPlanDev &d, const float *scene, int s, float *model);
 
 }  // namespace starred

@@ -286,12 +286,17 @@ __global__ __launch_bounds__(kFftThreads) void k_lines(const LineItem *__restric
 
 // Half-spectrum access with Hermitian symmetry: X is [P][P/2+1]; returns X(ky, kx)
 // for any kx in [0, P).
+// Branch-free (selects, one unconditional load) so that the loads of several
+// calls can be in flight together.
 __device__ __forceinline__ float2 half_get(const float2 *__restrict__ X, int P, int ky, int kx)
 {
     const int H = P / 2 + 1;
-    if (kx < H) return X[(long long)ky * H + kx];
-    const int ky2 = ky == 0 ? 0 : P - ky;
-    return conjf2(X[(long long)ky2 * H + (P - kx)]);
+    const bool lo = kx < H;
+    const int ry = lo ? ky : (ky == 0 ? 0 : P - ky);
+    const int rx = lo ? kx : P - kx;
+    float2 v = X[(long long)ry * H + rx];
+    v.y = lo ? v.y : -v.y;
+    return v;
 }
 
 // ---- pass A: rows of the h window of each class (real -> half spectrum) ----
@@ -488,35 +493,55 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_fwd(const SpecItem *__rest
                     rk[a * S + b][k] = k < M ? cmul(tk[P + Kys[a]], tk[Kxs[b]]) : make_float2(0.f, 0.f);
                 }
     }
-    for (int f = it.f0; f < it.f0 + it.nf; ++f) {
-        const int i = cls_frames[c.cf_off + f];
-        const FrameFft &fi = fr[i];
-        const float G = params[(long long)N * N + i];
-        const float *ai = params + (long long)N * N + E + (long long)i * M;
-        const float2 *Si = Sp + fi.s_off;
-        float av[MR];
-        if (MS > 0) {
-            #pragma unroll
-            for (int k = 0; k < MR; ++k) av[k] = k < M ? ai[k] : 0.f;
-        }
-        float2 acc = make_float2(0.f, 0.f);
+    // frames in groups of kFwdFrames: every load of a group is issued before its
+    // arithmetic, so one memory round trip serves several frames
+    constexpr int FG = kFwdFrames;
+    for (int f0 = it.f0; f0 < it.f0 + it.nf; f0 += FG) {
+        const int nfg = min(FG, it.f0 + it.nf - f0);
+        float2 sv[FG][S * S];
+        float Gv[FG], av[FG][MR];
+        long long roff[FG];
         #pragma unroll
-        for (int a = 0; a < S; ++a)
-            #pragma unroll
-            for (int b = 0; b < S; ++b) {
-                float2 F = cadd(hv[a * S + b], cscale(wv[a * S + b], G));
-                if (MS > 0) {
+        for (int u = 0; u < FG; ++u) {
+            if (u < nfg) {
+                const int i = cls_frames[c.cf_off + f0 + u];
+                const FrameFft &fi = fr[i];
+                roff[u] = fi.r_off;
+                Gv[u] = params[(long long)N * N + i];
+                const float *ai = params + (long long)N * N + E + (long long)i * M;
+                #pragma unroll
+                for (int k = 0; k < MR; ++k) av[u][k] = (MS > 0 && k < M) ? ai[k] : 0.f;
+                #pragma unroll
+                for (int a = 0; a < S; ++a)
                     #pragma unroll
-                    for (int k = 0; k < MR; ++k) F = cadd(F, cscale(rk[a * S + b][k], av[k]));
-                } else {
-                    for (int k = 0; k < M; ++k) {
-                        const float2 *tk = t + (long long)(1 + 4 * k) * P;
-                        F = cadd(F, cscale(cmul(tk[P + Kys[a]], tk[Kxs[b]]), ai[k]));
-                    }
-                }
-                acc = cadd(acc, cmul(half_get(Si, P, Kys[a], Kxs[b]), F));
+                    for (int b = 0; b < S; ++b) sv[u][a * S + b] = half_get(Sp + fi.s_off, P, Kys[a], Kxs[b]);
             }
-        Mh[fi.r_off + bin] = acc;
+        }
+        #pragma unroll
+        for (int u = 0; u < FG; ++u) {
+            if (u < nfg) {
+                float2 acc = make_float2(0.f, 0.f);
+                #pragma unroll
+                for (int a = 0; a < S; ++a)
+                    #pragma unroll
+                    for (int b = 0; b < S; ++b) {
+                        float2 F = cadd(hv[a * S + b], cscale(wv[a * S + b], Gv[u]));
+                        if (MS > 0) {
+                            #pragma unroll
+                            for (int k = 0; k < MR; ++k) F = cadd(F, cscale(rk[a * S + b][k], av[u][k]));
+                        } else {
+                            const int i = cls_frames[c.cf_off + f0 + u];
+                            const float *ai = params + (long long)N * N + E + (long long)i * M;
+                            for (int k = 0; k < M; ++k) {
+                                const float2 *tk = t + (long long)(1 + 4 * k) * P;
+                                F = cadd(F, cscale(cmul(tk[P + Kys[a]], tk[Kxs[b]]), ai[k]));
+                            }
+                        }
+                        acc = cadd(acc, cmul(sv[u][a * S + b], F));
+                    }
+                Mh[roff[u] + bin] = acc;
+            }
+        }
     }
 }
 
@@ -730,6 +755,120 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
     }
 }
 
+// ---- one-launch forward of a frame whose Q-grid spectra fit in LDS ----
+// A work group per frame runs the whole forward of the loss in LDS: the
+// spectral product and alias fold into the Q x (Q/2+1) model spectrum (stored
+// column-major), the inverse transform along ky, the Hermitian rows and the
+// inverse along x (the model m, Eq. 8), the weighted residual rho and its
+// chi-square partial (Eq. 10), then the forward transforms of rho along x and
+// along y, and writes rho_hat [Q][Q/2+1] to memory for the adjoint. Two LDS
+// planes of max(Q/2+1, n) lines of stride Q+1 alternate as FFT source and
+// scratch; the Q-point twiddles and the class's factor tables sit behind them.
+template <int S>
+__global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restrict__ frames,
+                                                             const ClassFft *__restrict__ classes,
+                                                             const FrameFft *__restrict__ fr,
+                                                             const float2 *__restrict__ tw,
+                                                             const float2 *__restrict__ Sp,
+                                                             const float2 *__restrict__ Hh,
+                                                             const float2 *__restrict__ tab,
+                                                             const float *__restrict__ params, int N, int E, int M,
+                                                             const float *__restrict__ data,
+                                                             const float *__restrict__ invvar,
+                                                             float2 *__restrict__ Rh, double *__restrict__ part_chi)
+{
+    extern __shared__ float2 sm[];
+    __shared__ double red[kFusedThreads / 64];
+    const int i = frames[blockIdx.x];
+    const FrameFft &f = fr[i];
+    const ClassFft &c = classes[f.cls];
+    const FftLen &fl = c.fQ;
+    const float2 *twQ = tw + fl.tw_off;
+    const int P = c.P, Q = c.Q, HQ = Q / 2 + 1, n = c.n, Ls = Q + 1;
+    const int rows = HQ > n ? HQ : n;
+    float2 *A = sm, *B = sm + rows * Ls;
+    float2 *twl = sm + 2 * rows * Ls;
+    float2 *t = twl + Q;
+    {
+        const float2 *tg = tab + c.tab_off;
+        const int nt = (1 + 4 * M) * P;
+        for (int e = threadIdx.x; e < Q; e += blockDim.x) twl[e] = twQ[e];
+        for (int e = threadIdx.x; e < nt; e += blockDim.x) t[e] = tg[e];
+    }
+    twQ = twl;
+    const float2 *Si = Sp + f.s_off;
+    const float2 *Hc = Hh + c.hh_off;
+    const float G = params[(long long)N * N + i];
+    const float *ai = params + (long long)N * N + E + (long long)i * M;
+    __syncthreads();
+
+    // lanes over columns kx, row groups over ky (no index divisions in the loops)
+    const int CXF = HQ <= 64 ? 64 : 128, RGF = kFusedThreads / CXF;
+    const int Q0L = Q <= 64 ? 64 : 128;  // lanes along a row of Q values
+    const int lane = threadIdx.x % CXF, rg = threadIdx.x / CXF;
+    // model spectrum, column-major: A[kx][ky]
+    if (lane < HQ) {
+        const int kx = lane;
+        float2 wxG[S];
+        #pragma unroll
+        for (int b = 0; b < S; ++b) wxG[b] = cscale(t[kx + b * Q], G);
+        for (int ky = rg; ky < Q; ky += RGF) {
+            float2 acc = make_float2(0.f, 0.f);
+            #pragma unroll
+            for (int a = 0; a < S; ++a) {
+                const int Ky = ky + a * Q;
+                const float2 wy = t[Ky];
+                #pragma unroll
+                for (int b = 0; b < S; ++b) {
+                    const int Kx = kx + b * Q;
+                    float2 F = cadd(half_get(Hc, P, Ky, Kx), cmul(wy, wxG[b]));
+                    for (int k = 0; k < M; ++k) {
+                        const float2 *tk = t + (1 + 4 * k) * P;  // [gx | gy | dgx | dgy]
+                        F = cadd(F, cscale(cmul(tk[P + Ky], tk[Kx]), ai[k]));
+                    }
+                    acc = cadd(acc, cmul(half_get(Si, P, Ky, Kx), F));
+                }
+            }
+            A[kx * Ls + ky] = acc;
+        }
+    }
+    __syncthreads();
+    float2 *r = lds_fft_any<true>(A, B, HQ, fl, twQ);  // along ky
+    float2 *o = (r == A) ? B : A;
+    // Hermitian rows y < n of the column results
+    for (int y = threadIdx.x / Q0L; y < n; y += kFusedThreads / Q0L)
+        for (int kx = threadIdx.x % Q0L; kx < Q; kx += Q0L)
+            o[y * Ls + kx] = kx < HQ ? r[kx * Ls + y] : conjf2(r[(Q - kx) * Ls + y]);
+    __syncthreads();
+    r = lds_fft_any<true>(o, r, n, fl, twQ);  // along x: model in the real parts
+    o = (r == A) ? B : A;
+    double chi = 0.0;
+    for (int y = threadIdx.x / Q0L; y < n; y += kFusedThreads / Q0L)
+        for (int x = threadIdx.x % Q0L; x < Q; x += Q0L) {
+            float v = 0.f;
+            if (x < n) {
+                const long long idx = f.data_off + (long long)y * n + x;
+                const float res = r[y * Ls + x].x - data[idx];
+                const float w = invvar[idx];
+                v = w * res;
+                chi += 0.5 * (double)w * (double)res * (double)res;
+            }
+            o[y * Ls + x] = make_float2(v, 0.f);
+        }
+    const double tchi = block_sum_d_fft<kFusedThreads>(chi, red);  // synchronises
+    if (threadIdx.x == 0) part_chi[blockIdx.x] = tchi;
+    r = lds_fft_any<false>(o, r, n, fl, twQ);  // rho along x
+    o = (r == A) ? B : A;
+    // column-major half spectrum, zero rows y >= n
+    if (lane < HQ)
+        for (int y = rg; y < Q; y += RGF) o[lane * Ls + y] = y < n ? r[y * Ls + lane] : make_float2(0.f, 0.f);
+    __syncthreads();
+    r = lds_fft_any<false>(o, r, HQ, fl, twQ);  // along y
+    float2 *R = Rh + f.r_off;
+    if (lane < HQ)
+        for (int ky = rg; ky < Q; ky += RGF) R[ky * HQ + lane] = r[lane * Ls + ky];
+}
+
 // ---- per-eval tables: window indicator and point-source factors ----
 // tab[c]: [w (P) | for each source k: gx, gy, dgx, dgy (P each)], the 1-D DFTs
 // over the frame of the window indicator, of g(x + o - c) (r = g(dx) g(dy),
@@ -774,9 +913,15 @@ __global__ void k_tables(const ClassFft *__restrict__ classes, const float2 *__r
 // summed over the chunk (the spectrum of the chunk's contribution to dL/dh), and
 // the frame's dot products <g_i, x> = sum over the full spectrum of G_i conj(X_hat)
 // (Parseval; half spectrum with weight 2 off the Kx = 0 and P/2 columns) for x the
-// window indicator (dGamma_i), r_k (da_ik) and r_k (X - c_k)/sigma^2 (dc_k, x and y),
-// whose spectra are products of the 1-D tables. Each block reduces its bins
-// through LDS; the per-block partials are summed per frame by k_fsum_parts.
+// window indicator (dGamma_i), r_k (da_ik) and r_k (X - c_k)/sigma^2 (dc_k, x and y).
+// Those spectra are products ty(Ky) tx(Kx) of 1-D tables, so each dot product is
+//   sum_Kx wgt(Kx) Re( conj(tx(Kx)) V_ty(Kx) ),  V_ty(Kx) = sum_Ky G(Ky, Kx) conj(ty(Ky)),
+// with one column sum V per y-table (window, gy_k, dgy_k). A block takes kAdjFrames
+// frames and a range of rows; a thread owns columns Kx (lanes) and every RG-th row
+// of the range, accumulates V over its rows, folds it with the x-tables, and the
+// block reduces the dot products once per group of kAdjSB sources through LDS.
+// The per-block partials are summed per frame (and the chunk spectra over chunks)
+// by k_adj_sums.
 __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const SpecItem *__restrict__ items,
                                                           const ClassFft *__restrict__ classes,
                                                           const FrameFft *__restrict__ fr,
@@ -786,105 +931,172 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const SpecItem *__rest
                                                           const float2 *__restrict__ tab, int M, int maxpb,
                                                           float2 *__restrict__ Gp, double *__restrict__ part)
 {
-    constexpr int B = kAdjBins;     // bins per thread (strided by the block size)
-    constexpr int FC = kAdjFrames;  // frames per chunk held in registers
+    constexpr int FC = kAdjFrames, SB = kAdjSB, NY = 1 + 2 * SB, NQ = 1 + 3 * SB;
+    constexpr int kRow = kFftThreads + 8;  // padded LDS rows of per-thread partials
+    static_assert(FC * NQ <= 2 * 32, "two reduction passes of 32 quantities");
+    __shared__ float red[32 * kRow];
     const SpecItem it = items[blockIdx.x];
     const ClassFft &c = classes[it.cls];
     const int P = c.P, Q = c.Q, HP = P / 2 + 1, nbins = P * HP;
+    const int y0 = it.bin0, y1 = min(P, y0 + c.arr), pb = y0 / c.arr;
+    // lanes over columns, row groups over rows
+    const int CX = adj_lanes(HP), RG = kFftThreads / CX;
+    const int lane = threadIdx.x % CX, rg = threadIdx.x / CX;
     const float2 *t = tab + c.tab_off;
-    __shared__ float red[kAdjFrames * kAdjQB * kFftThreads];
-    const int pb = it.bin0 / (kFftThreads * B);  // this block's partial slot
     const int Q3 = 1 + 3 * M;
-    int Ky[B], Kx[B], rq[B];
-    float wgt[B];
+    int fid[FC];
+    const float2 *Sf[FC];
+    const float2 *Rf[FC];
     #pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const int bin = it.bin0 + b * kFftThreads + threadIdx.x;
-        const bool valid = bin < nbins;
-        Ky[b] = valid ? bin / HP : 0;
-        Kx[b] = valid ? bin - Ky[b] * HP : 0;
-        wgt[b] = valid ? ((Kx[b] == 0 || 2 * Kx[b] == P) ? 1.f : 2.f) : 0.f;
-        rq[b] = valid ? bin : -1;
+    for (int f = 0; f < FC; ++f) {
+        fid[f] = f < it.nf ? cls_frames[c.cf_off + it.f0 + f] : -1;
+        Sf[f] = f < it.nf ? Sp + fr[fid[f]].s_off : Sp;
+        Rf[f] = f < it.nf ? Rh + fr[fid[f]].r_off : Rh;
     }
-    float2 gs[B];
-    #pragma unroll
-    for (int b = 0; b < B; ++b) gs[b] = make_float2(0.f, 0.f);
-    for (int f0 = it.f0; f0 < it.f0 + it.nf; f0 += FC) {
-        const int nfc = min(FC, it.f0 + it.nf - f0);
-        float2 G[FC][B];
-        int fid[FC];
-        #pragma unroll
-        for (int f = 0; f < FC; ++f) {
-            fid[f] = f < nfc ? cls_frames[c.cf_off + f0 + f] : -1;
-            #pragma unroll
-            for (int b = 0; b < B; ++b) {
-                G[f][b] = make_float2(0.f, 0.f);
-                if (f < nfc && rq[b] >= 0) {
-                    const FrameFft &fi = fr[fid[f]];
-                    G[f][b] = cmulc(half_get(Rh + fi.r_off, Q, Ky[b] % Q, Kx[b] % Q), Sp[fi.s_off + rq[b]]);
-                }
-                gs[b] = cadd(gs[b], G[f][b]);
-            }
+    float2 *gout = Gp + c.gp_off + (long long)(it.f0 / c.gfch) * nbins;
+    const int HQ = Q / 2 + 1, nr = y1 - y0;
+    __shared__ float2 tys[NY * kAdjMaxRows];  // y-tables of the block's rows
+    for (int k0 = 0; k0 < max(M, 1); k0 += SB) {
+        const int nk = min(SB, M - k0);  // sources of this group (may be 0 when M = 0)
+        const bool first = (k0 == 0);
+        // y-tables of this group for the block's rows: window, gy_k, dgy_k
+        for (int e = threadIdx.x; e < NY * nr; e += kFftThreads) {
+            const int u = e / nr, r = e - u * nr, Ky = y0 + r;
+            float2 v = make_float2(0.f, 0.f);
+            if (u == 0) v = t[Ky];
+            else if (u <= SB) { if (u - 1 < nk) v = t[(1 + 4 * (k0 + u - 1)) * P + P + Ky]; }
+            else if (u - 1 - SB < nk) v = t[(1 + 4 * (k0 + u - 1 - SB)) * P + 3 * P + Ky];
+            tys[u * kAdjMaxRows + r] = v;
         }
-        // Parseval dot products of every frame of the chunk with each table spectrum,
-        // reduced over the block through LDS in groups of kAdjQB quantities
-        for (int q0 = 0; q0 < Q3; q0 += kAdjQB) {
-            const int nq = min(kAdjQB, Q3 - q0);
-            for (int qq = 0; qq < nq; ++qq) {
-                const int q = q0 + qq;
-                const float2 *ty = t, *tx = t;
-                if (q > 0) {
-                    const int k = (q - 1) % M, kind = (q - 1) / M;  // 0: r_k, 1: d/dcx, 2: d/dcy
-                    const float2 *tk = t + (long long)(1 + 4 * k) * P;
-                    ty = tk + (kind == 2 ? 3 * P : P);
-                    tx = tk + (kind == 1 ? 2 * P : 0);
-                }
-                float2 X[B];
+        __syncthreads();
+        float dot[FC][NQ];
+        #pragma unroll
+        for (int f = 0; f < FC; ++f)
+            #pragma unroll
+            for (int q = 0; q < NQ; ++q) dot[f][q] = 0.f;
+        for (int Kx = lane; Kx < HP; Kx += CX) {
+            float2 V[FC][NY];
+            #pragma unroll
+            for (int f = 0; f < FC; ++f)
                 #pragma unroll
-                for (int b = 0; b < B; ++b) X[b] = cmul(ty[Ky[b]], tx[Kx[b]]);
+                for (int u = 0; u < NY; ++u) V[f][u] = make_float2(0.f, 0.f);
+            // rho_hat is indexed by K mod Q (Kx < P/2 + 1 <= 2Q, so one subtraction)
+            const int kxq = Kx >= Q ? Kx - Q : Kx;
+            const bool lo = kxq < HQ;
+            const int rx = lo ? kxq : Q - kxq;
+            const float cj = lo ? 1.f : -1.f;
+            int ryq = (y0 + rg) % Q;
+            for (int Ky = y0 + rg; Ky < y1; Ky += RG) {
+                float2 ty[NY];
+                #pragma unroll
+                for (int u = 0; u < NY; ++u) ty[u] = tys[u * kAdjMaxRows + (Ky - y0)];
+                const long long bin = (long long)Ky * HP + Kx;
+                const int ridx = (lo ? ryq : (ryq == 0 ? 0 : Q - ryq)) * HQ + rx;
+                ryq += RG;
+                if (ryq >= Q) ryq -= Q;
+                float2 gsum = make_float2(0.f, 0.f);
                 #pragma unroll
                 for (int f = 0; f < FC; ++f) {
-                    float v = 0.f;
-                    #pragma unroll
-                    for (int b = 0; b < B; ++b) v += wgt[b] * (G[f][b].x * X[b].x + G[f][b].y * X[b].y);
-                    red[(f * kAdjQB + qq) * kFftThreads + threadIdx.x] = v;
+                    if (f < it.nf) {
+                        float2 rv = Rf[f][ridx];
+                        rv.y *= cj;
+                        const float2 G = cmulc(rv, Sf[f][bin]);
+                        gsum = cadd(gsum, G);
+                        #pragma unroll
+                        for (int u = 0; u < NY; ++u) V[f][u] = cadd(V[f][u], cmulc(G, ty[u]));
+                    }
+                }
+                if (first) gout[bin] = gsum;
+            }
+            // fold with the x-tables of this column
+            const float wgt = (Kx == 0 || 2 * Kx == P) ? 1.f : 2.f;
+            float2 tx[1 + 2 * SB];
+            tx[0] = t[Kx];
+            #pragma unroll
+            for (int k = 0; k < SB; ++k) {
+                const float2 *tk = t + (1 + 4 * (k0 + k)) * P;
+                tx[1 + k] = k < nk ? tk[Kx] : make_float2(0.f, 0.f);           // gx_k
+                tx[1 + SB + k] = k < nk ? tk[2 * P + Kx] : make_float2(0.f, 0.f);  // dgx_k
+            }
+            #pragma unroll
+            for (int f = 0; f < FC; ++f) {
+                // Re(conj(tx) V) = tx.x V.x + tx.y V.y
+                dot[f][0] += wgt * (tx[0].x * V[f][0].x + tx[0].y * V[f][0].y);
+                #pragma unroll
+                for (int k = 0; k < SB; ++k) {
+                    const float2 vy = V[f][1 + k], vdy = V[f][1 + SB + k];
+                    dot[f][1 + k] += wgt * (tx[1 + k].x * vy.x + tx[1 + k].y * vy.y);                  // da
+                    dot[f][1 + SB + k] += wgt * (tx[1 + SB + k].x * vy.x + tx[1 + SB + k].y * vy.y);   // dcx
+                    dot[f][1 + 2 * SB + k] += wgt * (tx[1 + k].x * vdy.x + tx[1 + k].y * vdy.y);       // dcy
                 }
             }
+        }
+        // block reduction of FC x NQ quantities in passes of 32 rows
+        for (int p0 = 0; p0 < FC * NQ; p0 += 32) {
+            #pragma unroll
+            for (int v = 0; v < FC * NQ; ++v)
+                if (v >= p0 && v < p0 + 32) red[(v - p0) * kRow + threadIdx.x] = dot[v / NQ][v % NQ];
             __syncthreads();
-            for (int pr = threadIdx.x; pr < FC * nq; pr += kFftThreads) {
-                const int f = pr / nq, qq = pr - f * nq;
-                if (f < nfc) {
-                    const float *rr = red + (f * kAdjQB + qq) * kFftThreads;
-                    double acc = 0.0;
-                    for (int u = 0; u < kFftThreads; ++u) acc += (double)rr[u];
-                    part[((long long)fid[f] * maxpb + pb) * Q3 + q0 + qq] = acc;
-                }
+            const int pr = threadIdx.x >> 3, j = threadIdx.x & 7, v = p0 + pr;
+            double acc = 0.0;
+            if (v < FC * NQ) {
+                const float *rr = red + pr * kRow;
+                #pragma unroll 8
+                for (int u = j; u < kFftThreads; u += 8) acc += (double)rr[u];
+            }
+            acc += __shfl_xor(acc, 1, 8);
+            acc += __shfl_xor(acc, 2, 8);
+            acc += __shfl_xor(acc, 4, 8);
+            if (j == 0 && v < FC * NQ) {
+                const int f = v / NQ, ql = v % NQ;
+                // local quantity -> global index: window, da_k, dcx_k, dcy_k
+                int q = -1;
+                if (ql == 0) q = first ? 0 : -1;
+                else if (ql <= SB) q = (ql - 1 < nk) ? 1 + k0 + (ql - 1) : -1;
+                else if (ql <= 2 * SB) q = (ql - 1 - SB < nk) ? 1 + M + k0 + (ql - 1 - SB) : -1;
+                else q = (ql - 1 - 2 * SB < nk) ? 1 + 2 * M + k0 + (ql - 1 - 2 * SB) : -1;
+                if (f < it.nf && q >= 0) part[((long long)fid[f] * maxpb + pb) * Q3 + q] = acc;
             }
             __syncthreads();
         }
     }
-    #pragma unroll
-    for (int b = 0; b < B; ++b)
-        if (rq[b] >= 0) Gp[c.gp_off + (long long)(it.f0 / c.gfch) * nbins + rq[b]] = gs[b];
 }
 
-// per-frame sums of the per-block partials -> fsum[i][q] (fixed order)
-__global__ __launch_bounds__(kFftThreads) void k_fsum_parts(const ClassFft *__restrict__ classes,
-                                                            const FrameFft *__restrict__ fr, int M, int maxpb,
-                                                            const double *__restrict__ part, double *__restrict__ fsum)
+// Two independent reductions in one launch, each in a fixed order:
+//  blocks [0, gblocks): the frame-chunk spectra of each class summed into the
+//    first chunk's slot (every thread owns one bin of one class);
+//  the remaining blocks: per-frame sums of the per-block dot products,
+//    fsum[i][q], one thread per (frame, quantity).
+__global__ void k_adj_sums(const ClassFft *__restrict__ classes, int ncls, int gblocks,
+                           const FrameFft *__restrict__ fr, int E, int M, int maxpb,
+                           float2 *__restrict__ Gp, const double *__restrict__ part, double *__restrict__ fsum)
 {
-    __shared__ double red[kFftThreads / 64];
-    const int i = blockIdx.x;
-    const ClassFft &c = classes[fr[i].cls];
-    const int per_block = kFftThreads * kAdjBins;
-    const int npb = (c.P * (c.P / 2 + 1) + per_block - 1) / per_block;
-    const int Q3 = 1 + 3 * M;
-    for (int q = 0; q < Q3; ++q) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < npb; b += blockDim.x) acc += part[((long long)i * maxpb + b) * Q3 + q];
-        const double tot = block_sum_d_fft(acc, red);
-        if (threadIdx.x == 0) fsum[(long long)i * Q3 + q] = tot;
+    if ((int)blockIdx.x < gblocks) {
+        int g = blockIdx.x * blockDim.x + threadIdx.x;
+        for (int ci = 0; ci < ncls; ++ci) {
+            const ClassFft &c = classes[ci];
+            const int nbins = c.P * (c.P / 2 + 1);
+            if (g < nbins) {
+                float2 *gp = Gp + c.gp_off + g;
+                float2 acc = gp[0];
+                for (int ch = 1; ch < c.ngch; ++ch) acc = cadd(acc, gp[(long long)ch * nbins]);
+                gp[0] = acc;
+                return;
+            }
+            g -= nbins;
+        }
+        return;
     }
+    const int Q3 = 1 + 3 * M;
+    const int idx = (blockIdx.x - gblocks) * blockDim.x + threadIdx.x;
+    if (idx >= E * Q3) return;
+    const int i = idx / Q3, q = idx - i * Q3;
+    const int npb = classes[fr[i].cls].nrr;
+    const double *pp = part + (long long)i * maxpb * Q3 + q;
+    double acc = 0.0;
+    #pragma unroll 8
+    for (int b = 0; b < npb; ++b) acc += pp[(long long)b * Q3];
+    fsum[idx] = acc;
 }
 
 // ---- dL/dh of each class: inverse columns of the summed spectra, crop rows < F ----
@@ -897,11 +1109,7 @@ struct OpGCols {
     __device__ const FftLen &len(const ClassFft &c) const { return c.fP; }
     __device__ float2 load(const ClassFft &c, int, int Kx, int Ky) const
     {
-        const int HP = c.P / 2 + 1;
-        const long long stride = (long long)c.P * HP;
-        float2 acc = make_float2(0.f, 0.f);
-        for (int ch = 0; ch < c.ngch; ++ch) acc = cadd(acc, Gp[c.gp_off + ch * stride + (long long)Ky * HP + Kx]);
-        return acc;
+        return Gp[c.gp_off + (long long)Ky * (c.P / 2 + 1) + Kx];  // chunk sum, in the first slot
     }
     __device__ void store(const ClassFft &c, int, int Kx, int y, float2 v) const
     {
@@ -928,22 +1136,6 @@ struct OpGRows {
         if (x < c.F) hcls[c.hc_off + (long long)y * c.F + x] = v.x;
     }
 };
-
-// dL/dh = prior + the window contributions of the classes (class order)
-__global__ void k_finalize_h_classes(const ClassFft *__restrict__ classes, int ncls, int N,
-                                     const float *__restrict__ hcls, const float *__restrict__ prior,
-                                     float *__restrict__ grad_h)
-{
-    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= N * N) return;
-    const int Y = pix / N, X = pix % N;
-    float acc = prior ? prior[pix] : 0.f;
-    for (int c = 0; c < ncls; ++c) {
-        const int y = Y - classes[c].o, x = X - classes[c].o, F = classes[c].F;
-        if (y >= 0 && y < F && x >= 0 && x < F) acc += hcls[classes[c].hc_off + (long long)y * F + x];
-    }
-    grad_h[pix] = acc;
-}
 
 // --------------------------------------------------------------------------
 // launchers
@@ -981,11 +1173,14 @@ hipError_t fft_spectra(hipStream_t st, const FftPlanDev &d, const float *params,
     return e;
 }
 
-hipError_t fft_spec_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s)
+hipError_t fft_spec_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,
+                        bool lg)
 {
-    if (d.n_spec <= 0) return hipSuccess;
+    const int ns = lg ? d.n_spec_lg : d.n_spec;
+    const SpecItem *items = lg ? d.spec_lg : d.spec;
+    if (ns <= 0) return hipSuccess;
 #define SPEC_FWD(SS, MS)                                                                                     \
-    hipLaunchKernelGGL((k_spec_fwd<SS, MS>), dim3(d.n_spec), dim3(kFftThreads), 0, st, d.spec, d.classes,     \
+    hipLaunchKernelGGL((k_spec_fwd<SS, MS>), dim3(ns), dim3(kFftThreads), 0, st, items, d.classes,            \
                        d.frames, d.cls_frames, d.S, d.Hh, d.tab, params, N, E, M, d.Rh)
     if (s == 1) {
         if (M <= 16) SPEC_FWD(1, 16); else SPEC_FWD(1, 0);
@@ -1036,6 +1231,39 @@ hipError_t fft_resid_rows(hipStream_t st, const FftPlanDev &d, const float *resi
     return run_lines(st, d.rrows, d.classes, d.tw, OpResidRows{d.frames, resid, d.T2});
 }
 
+hipError_t fft_fused_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,
+                         const float *data, const float *invvar, double *part_chi)
+{
+    if (d.n_fused <= 0) return hipSuccess;
+#define FUSED_FWD(SS)                                                                                             \
+    hipLaunchKernelGGL(k_frame_fwd<SS>, dim3(d.n_fused), dim3(kFusedThreads), d.fused_lds, st, d.fused, d.classes, \
+                       d.frames, d.tw, d.S, d.Hh, d.tab, params, N, E, M, data, invvar, d.Rh, part_chi)
+    if (s == 1) FUSED_FWD(1);
+    else if (s == 2) FUSED_FWD(2);
+    else FUSED_FWD(3);
+#undef FUSED_FWD
+    return hipGetLastError();
+}
+
+hipError_t fft_model_cols_lg(hipStream_t st, const FftPlanDev &d)
+{
+    return run_lines(st, d.fcols_lg, d.classes, d.tw, OpMCols{d.frames, d.Rh, d.T});
+}
+
+hipError_t fft_model_rows_lg(hipStream_t st, const FftPlanDev &d, const float *data, const float *invvar,
+                             double *part_chi)
+{
+    if (d.frows_lg.n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fwd_rows, dim3(d.frows_lg.n_items), dim3(kFftThreads), d.frows_lg.lds_bytes, st,
+                       d.frows_lg.items, d.classes, d.frames, d.tw, d.T, data, invvar, d.T2, nullptr, part_chi);
+    return hipGetLastError();
+}
+
+hipError_t fft_rho_cols_lg(hipStream_t st, const FftPlanDev &d)
+{
+    return run_lines(st, d.rcols_lg, d.classes, d.tw, OpRhoCols{d.frames, d.T2, d.Rh});
+}
+
 hipError_t fft_rho_cols(hipStream_t st, const FftPlanDev &d)
 {
     return run_lines(st, d.rcols, d.classes, d.tw, OpRhoCols{d.frames, d.T2, d.Rh});
@@ -1051,16 +1279,21 @@ hipError_t fft_adj_rows(hipStream_t st, const FftPlanDev &d, float *g)
     return run_lines(st, d.arows, d.classes, d.tw, OpAdjRows{d.frames, d.T3, g, d.gpart});
 }
 
-hipError_t fft_spec_adj(hipStream_t st, const FftPlanDev &d, int M, double *fsum)
+hipError_t fft_spec_adj(hipStream_t st, const FftPlanDev &d, int M)
 {
-    if (d.n_aspec > 0) {
-        hipLaunchKernelGGL(k_spec_adj, dim3(d.n_aspec), dim3(kFftThreads), 0, st, d.aspec, d.classes, d.frames,
-                           d.cls_frames, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_fsum_parts, dim3(d.n_frames), dim3(kFftThreads), 0, st, d.classes, d.frames, M, d.maxpb,
-                       d.apart, fsum);
+    if (d.n_aspec == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spec_adj, dim3(d.n_aspec), dim3(kFftThreads), 0, st, d.aspec, d.classes, d.frames,
+                       d.cls_frames, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart);
+    return hipGetLastError();
+}
+
+hipError_t fft_adj_sums(hipStream_t st, const FftPlanDev &d, int M, double *fsum)
+{
+    const int gblocks = (int)((d.total_bins + 255) / 256);
+    const int fblocks = (d.n_frames * (1 + 3 * M) + 255) / 256;
+    if (gblocks + fblocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_sums, dim3(gblocks + fblocks), dim3(256), 0, st, d.classes, d.n_classes, gblocks,
+                       d.frames, d.n_frames, M, d.maxpb, d.Gp, d.apart, fsum);
     return hipGetLastError();
 }
 
@@ -1069,13 +1302,6 @@ hipError_t fft_grad_h_inverse(hipStream_t st, const FftPlanDev &d)
     hipError_t e = run_lines(st, d.gcols, d.classes, d.tw, OpGCols{d.Gp, d.Th});
     if (e != hipSuccess) return e;
     return run_lines(st, d.grows, d.classes, d.tw, OpGRows{d.Th, d.hcls});
-}
-
-hipError_t fft_finalize_h(hipStream_t st, const FftPlanDev &d, int N, const float *prior, float *grad_h)
-{
-    hipLaunchKernelGGL(k_finalize_h_classes, dim3((N * N + 255) / 256), dim3(256), 0, st, d.classes, d.n_classes, N,
-                       d.hcls, prior, grad_h);
-    return hipGetLastError();
 }
 
 hipError_t fft_adjoint(hipStream_t st, const FftPlanDev &d, float *g)

@@ -74,13 +74,18 @@ hipError_t launch_frame_sums(hipStream_t st, const FrameDev *fr, int E, int N, i
 hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, const float *g,
                              const float *prior, float *grad_h, float *part);
 int finalize_h_chunks(int E);
+struct ClassFft;
+// With classes (FFT path), the launch also writes dL/dh = prior + the classes'
+// window contributions hcls.
 hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const double *part_chi,
                                  int n_l1, const double *part_l1, double lambda,
                                  const double *fsum, const float *params, int N,
                                  float *grad, double *loss, const int *gcsr_off = nullptr,
                                  const int *gcsr_item = nullptr, const double *gpart = nullptr,
-                                 int *tick = nullptr);
+                                 int *tick = nullptr, const ClassFft *classes = nullptr, int ncls = 0,
+                                 const float *hcls = nullptr, const float *prior = nullptr);
 hipError_t launch_copy_probe(hipStream_t st, const float *src, float *dst, long long n);
+hipError_t launch_idle(hipStream_t st, int iters);
 
 hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, float *coeffs,
                               float *z, const float *W, int w_stride, float lam, float *c_a,

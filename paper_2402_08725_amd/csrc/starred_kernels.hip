@@ -5,6 +5,7 @@
 // chi-square and L1 global sums and the small per-frame dot products are
 // reduced in FP64 with fixed (deterministic) trees. No floating-point atomics.
 #include "starred_internal.h"
+#include "starred_fft.h"
 
 #include <hip/hip_runtime.h>
 
@@ -536,33 +537,68 @@ hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, c
 
 // loss[0] = sum chi partials, loss[1] = sum L1 partials, loss[2] = total;
 // grad Gamma, a, c from the per-frame sums (frames summed in order).
-constexpr int kFinThreads = 256;
+// Block 0 does these small reductions, one wave per reduced quantity (lanes
+// stride the items, then a fixed shuffle tree), so none waits for another.
+// When classes is given, blocks 1.. assemble dL/dh of the FFT path: the prior
+// gradient plus the window contribution of every shape class, in class order.
+constexpr int kFinThreads = 1024;
 
 __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
     int E, int M, int n_chi, const double *__restrict__ part_chi, int n_l1,
     const double *__restrict__ part_l1, const double *__restrict__ fsum,
     const float *__restrict__ params, int N, float *__restrict__ grad, double *__restrict__ loss,
     const int *__restrict__ gcsr_off, const int *__restrict__ gcsr_item, const double *__restrict__ gpart,
-    int *__restrict__ tick)
+    int *__restrict__ tick, const ClassFft *__restrict__ classes, int ncls, const float *__restrict__ hcls,
+    const float *__restrict__ prior)
 {
+    const long long NN = (long long)N * N;
+    if (blockIdx.x > 0) {
+        const long long pix = (long long)(blockIdx.x - 1) * kFinThreads + threadIdx.x;
+        if (pix >= NN) return;
+        const int Y = (int)(pix / N), X = (int)(pix % N);
+        float acc = prior ? prior[pix] : 0.f;
+        for (int ci = 0; ci < ncls; ++ci) {
+            const ClassFft &c = classes[ci];
+            const int y = Y - c.o, x = X - c.o, F = c.F;
+            if (y >= 0 && y < F && x >= 0 && x < F) acc += hcls[c.hc_off + (long long)y * F + x];
+        }
+        grad[pix] = acc;
+        return;
+    }
     if (tick && threadIdx.x == 0) *tick += 1;  // the Adam step that follows reads it
-    __shared__ double red[kFinThreads / 64];
-    double a = 0.0;
-    for (int i = threadIdx.x; i < n_chi; i += kFinThreads) a += part_chi[i];
-    const double chi = block_sum_d<kFinThreads>(a, red);
-    double b = 0.0;
-    for (int i = threadIdx.x; i < n_l1; i += kFinThreads) b += part_l1[i];
-    const double l1 = block_sum_d<kFinThreads>(b, red);
+    __shared__ double sums[2];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int NW = kFinThreads / 64;
+    const int stride = 1 + 3 * M;
+    const float *pa = params + NN + E;
+    const int nred = 2 + (grad ? 2 * M : 0);
+    for (int r = wv; r < nred; r += NW) {
+        double acc = 0.0;
+        if (r == 0) {
+            for (int i = lane; i < n_chi; i += 64) acc += part_chi[i];
+        } else if (r == 1) {
+            for (int i = lane; i < n_l1; i += 64) acc += part_l1[i];
+        } else {
+            // dL/dc_k = sum_i a_ik <g_i, dr_k/dc>
+            const int q = r - 2, k = q >> 1, axis = q & 1;
+            for (int i = lane; i < E; i += 64)
+                acc += (double)pa[(long long)i * M + k] * fsum[(long long)i * stride + 1 + (1 + axis) * M + k];
+        }
+        #pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) {
+            if (r < 2) sums[r] = acc;
+            else grad[NN + E + (long long)E * M + (r - 2)] = (float)acc;
+        }
+    }
+    __syncthreads();
     if (threadIdx.x == 0 && loss) {
-        loss[0] = chi;
-        loss[1] = l1;
-        loss[2] = chi + l1;
+        loss[0] = sums[0];
+        loss[1] = sums[1];
+        loss[2] = sums[0] + sums[1];
     }
     if (!grad) return;
-    const long long NN = (long long)N * N;
-    const int stride = 1 + 3 * M;
-    float *gG = grad + NN, *ga = gG + E, *gc = ga + (long long)E * M;
-    const float *pa = params + NN + E;
+    float *gG = grad + NN, *ga = gG + E;
     for (int i = threadIdx.x; i < E; i += kFinThreads) {
         if (gcsr_off) {
             double acc = 0.0;
@@ -571,16 +607,10 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
         } else {
             gG[i] = (float)fsum[(long long)i * stride];
         }
-        for (int k = 0; k < M; ++k) ga[(long long)i * M + k] = (float)fsum[(long long)i * stride + 1 + k];
     }
-    // dL/dc_k = sum_i a_ik <g_i, dr_k/dc>: frames strided over the threads, then a fixed tree
-    for (int q = 0; q < 2 * M; ++q) {
-        const int k = q >> 1, axis = q & 1;
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < E; i += kFinThreads)
-            acc += (double)pa[(long long)i * M + k] * fsum[(long long)i * stride + 1 + (1 + axis) * M + k];
-        const double tot = block_sum_d<kFinThreads>(acc, red);
-        if (threadIdx.x == 0) gc[q] = (float)tot;
+    for (long long e = threadIdx.x; e < (long long)E * M; e += kFinThreads) {
+        const long long i = e / M, k = e - i * M;
+        ga[e] = (float)fsum[i * stride + 1 + k];
     }
 }
 
@@ -588,10 +618,14 @@ hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const 
                                  int n_l1, const double *part_l1, double,
                                  const double *fsum, const float *params, int N,
                                  float *grad, double *loss, const int *gcsr_off, const int *gcsr_item,
-                                 const double *gpart, int *tick)
+                                 const double *gpart, int *tick, const ClassFft *classes, int ncls,
+                                 const float *hcls, const float *prior)
 {
-    hipLaunchKernelGGL(k_finalize_small, dim3(1), dim3(kFinThreads), 0, st, E, M, n_chi, part_chi,
-                       n_l1, part_l1, fsum, params, N, grad, loss, gcsr_off, gcsr_item, gpart, tick);
+    const long long NN = (long long)N * N;
+    const int hblocks = (classes && grad) ? (int)((NN + kFinThreads - 1) / kFinThreads) : 0;
+    hipLaunchKernelGGL(k_finalize_small, dim3(1 + hblocks), dim3(kFinThreads), 0, st, E, M, n_chi, part_chi,
+                       n_l1, part_l1, fsum, params, N, grad, loss, gcsr_off, gcsr_item, gpart, tick, classes, ncls,
+                       hcls, prior);
     return hipGetLastError();
 }
 
@@ -781,6 +815,19 @@ __global__ void k_copy_probe(const float4 *__restrict__ a, float4 *__restrict__ 
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (long long)gridDim.x * blockDim.x)
         b[i] = a[i];
+}
+
+// Idle lead-in for stage timing: one wave sleeps for a fixed number of
+// s_sleep periods (about 3.4 us each at 2.4 GHz) and exits.
+__global__ void k_idle(int iters)
+{
+    for (int i = 0; i < iters; ++i) __builtin_amdgcn_s_sleep(127);
+}
+
+hipError_t launch_idle(hipStream_t st, int iters)
+{
+    hipLaunchKernelGGL(k_idle, dim3(1), dim3(64), 0, st, iters);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy_probe(hipStream_t st, const float *src, float *dst, long long n)

@@ -35,6 +35,9 @@ int fail_hip(hipError_t e, const char *where)
     return e == hipErrorOutOfMemory ? STARRED_ENOMEM : STARRED_EHIP;
 }
 
+// s_sleep periods of the idle lead-in that stage timing puts before each call
+constexpr int kProfIdleIters = 300;
+
 #define HIP_TRY(expr)                                     \
     do {                                                  \
         hipError_t _e = (expr);                           \
@@ -84,6 +87,7 @@ struct starred_plan {
 
     // FFT path
     bool fft_ready = false;
+    bool fft_fused = true;
     FftPlanDev fd;
     std::vector<ClassFft> cls;
     std::vector<FrameFft> ffr;
@@ -414,6 +418,8 @@ static int build_fft(starred_plan *p)
         c.tab_off = tb;
         tb += (long long)(1 + 4 * M) * c.P;
     }
+    // classes whose Q-grid planes fit in LDS take the one-launch forward
+    for (auto &c : p->cls) c.fused = fused_lds_bytes(c.Q, c.n, c.P, p->M) <= kFusedLdsMax ? 1 : 0;
     // class-ordered frame list
     std::vector<int> cls_frames;
     for (int c = 0; c < (int)p->cls.size(); ++c) {
@@ -476,10 +482,12 @@ static int build_fft(starred_plan *p)
             tabh[c.tab_off + K] = make_float2((float)acc.real(), (float)acc.imag());
         }
     // forward spectral product items: 256 bins x a chunk of frames, longest first
-    {
+    // (every class, and for the loss the classes without the one-launch forward)
+    for (int lg = 0; lg < 2; ++lg) {
         std::vector<SpecItem> sp;
         for (int c = 0; c < (int)p->cls.size(); ++c) {
             const ClassFft &cl = p->cls[c];
+            if (lg && cl.fused) continue;
             const int nbins = cl.Q * (cl.Q / 2 + 1);
             const int nbb = (nbins + kFftThreads - 1) / kFftThreads;
             // enough frame chunks to give every compute unit several groups
@@ -491,33 +499,58 @@ static int build_fft(starred_plan *p)
         std::stable_sort(sp.begin(), sp.end(), [&](const SpecItem &a, const SpecItem &b) {
             return p->cls[a.cls].P > p->cls[b.cls].P;
         });
-        d.n_spec = (int)sp.size();
-        if ((rc = p->alloc(&d.spec, sp.size()))) return rc;
-        if ((rc = p->alloc(&d.cls_frames, cls_frames.size()))) return rc;
-        if (!sp.empty()) HIP_TRY(hipMemcpy(d.spec, sp.data(), sizeof(SpecItem) * sp.size(), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(d.cls_frames, cls_frames.data(), sizeof(int) * cls_frames.size(), hipMemcpyHostToDevice));
+        int &ns = lg ? d.n_spec_lg : d.n_spec;
+        SpecItem *&dst = lg ? d.spec_lg : d.spec;
+        ns = (int)sp.size();
+        if ((rc = p->alloc(&dst, sp.size()))) return rc;
+        if (!sp.empty()) HIP_TRY(hipMemcpy(dst, sp.data(), sizeof(SpecItem) * sp.size(), hipMemcpyHostToDevice));
     }
-    // frequency-domain adjoint: items over the P half-spectrum bins x frame chunks
+    if ((rc = p->alloc(&d.cls_frames, cls_frames.size()))) return rc;
+    HIP_TRY(hipMemcpy(d.cls_frames, cls_frames.data(), sizeof(int) * cls_frames.size(), hipMemcpyHostToDevice));
+    // frames of the one-launch forward, largest transforms first
+    {
+        std::vector<int> fu;
+        size_t lds = 0;
+        for (int i = 0; i < E; ++i)
+            if (p->cls[fcls[i]].fused) {
+                fu.push_back(i);
+                const ClassFft &cl = p->cls[fcls[i]];
+                lds = std::max(lds, fused_lds_bytes(cl.Q, cl.n, cl.P, M));
+            }
+        std::stable_sort(fu.begin(), fu.end(), [&](int a, int b) { return p->cls[fcls[a]].Q > p->cls[fcls[b]].Q; });
+        d.n_fused = (int)fu.size();
+        d.fused_lds = lds;
+        if ((rc = p->alloc(&d.fused, std::max<size_t>(1, fu.size())))) return rc;
+        if (!fu.empty()) HIP_TRY(hipMemcpy(d.fused, fu.data(), sizeof(int) * fu.size(), hipMemcpyHostToDevice));
+    }
+    // frequency-domain adjoint: items over chunks of kAdjFrames frames x ranges of
+    // rows of the P half spectrum, about kAdjBlocks of them per launch
     {
         std::vector<SpecItem> sp;
         long long gp = 0, hc = 0;
-        int maxpb = 0;
+        int maxpb = 0, nchunks = 0;
+        for (const ClassFft &cl : p->cls) nchunks += (cl.ncf + kAdjFrames - 1) / kAdjFrames;
         for (int c = 0; c < (int)p->cls.size(); ++c) {
             ClassFft &cl = p->cls[c];
-            const int nbins = cl.P * (cl.P / 2 + 1);
-            const int per_block = kFftThreads * kAdjBins;
-            const int nbb = (nbins + per_block - 1) / per_block;
-            const int want_chunks = std::max(1, 768 / std::max(1, nbb));
-            cl.gfch = std::max(1, std::min(32, (cl.ncf + want_chunks - 1) / want_chunks));
-            cl.ngch = (cl.ncf + cl.gfch - 1) / cl.gfch;
+            const int HP = cl.P / 2 + 1, nbins = cl.P * HP;
+            const int CX = adj_lanes(HP), RG = kFftThreads / CX;
+            cl.gfch = kAdjFrames;
+            cl.ngch = (cl.ncf + kAdjFrames - 1) / kAdjFrames;
+            const int want = std::max(1, (kAdjBlocks + nchunks - 1) / std::max(1, nchunks));
+            int arr = (cl.P + want - 1) / want;
+            // at least kAdjMinRows rows per thread; a multiple of the row groups
+            arr = std::max(kAdjMinRows * RG, ((arr + RG - 1) / RG) * RG);
+            arr = std::min(arr, kAdjMaxRows);  // RG divides kAdjMaxRows
+            cl.arr = arr;
+            cl.nrr = (cl.P + arr - 1) / arr;
             cl.gp_off = gp;
             gp += (long long)cl.ngch * nbins;
             cl.hc_off = hc;
             hc += (long long)cl.F * cl.F;
-            maxpb = std::max(maxpb, nbb);
-            for (int f0 = 0; f0 < cl.ncf; f0 += cl.gfch)
-                for (int bb = 0; bb < nbb; ++bb)
-                    sp.push_back(SpecItem{c, f0, std::min(cl.gfch, cl.ncf - f0), bb * per_block});
+            maxpb = std::max(maxpb, cl.nrr);
+            for (int f0 = 0; f0 < cl.ncf; f0 += kAdjFrames)
+                for (int r = 0; r < cl.nrr; ++r)
+                    sp.push_back(SpecItem{c, f0, std::min(kAdjFrames, cl.ncf - f0), r * arr});
         }
         std::stable_sort(sp.begin(), sp.end(), [&](const SpecItem &a, const SpecItem &b) {
             return p->cls[a.cls].P > p->cls[b.cls].P;
@@ -525,6 +558,8 @@ static int build_fft(starred_plan *p)
         d.n_frames = E;
         d.n_aspec = (int)sp.size();
         d.maxpb = maxpb;
+        d.total_bins = 0;
+        for (const ClassFft &cl : p->cls) d.total_bins += (long long)cl.P * (cl.P / 2 + 1);
         if ((rc = p->alloc(&d.aspec, sp.size()))) return rc;
         if ((rc = p->alloc(&d.apart, (size_t)E * maxpb * (1 + 3 * M)))) return rc;
         if ((rc = p->alloc(&d.Gp, gp))) return rc;
@@ -538,18 +573,21 @@ static int build_fft(starred_plan *p)
 
     // line passes: groups of lines of one frame (or class), longest transforms first
     std::vector<LineItem> last_items;
-    auto make_pass = [&](LinePass &lp, bool per_class, auto lines_of, auto len_of) -> int {
+    auto make_pass = [&](LinePass &lp, bool per_class, auto lines_of, auto len_of, bool skip_fused = false) -> int {
         struct G { int L; LineItem it; };
         std::vector<G> g;
         const int nunits = per_class ? (int)p->cls.size() : E;
+        auto skip = [&](int u) { return skip_fused && !per_class && p->cls[fcls[u]].fused; };
         long long total_lines = 0;
-        for (int u = 0; u < nunits; ++u) total_lines += lines_of(p->cls[per_class ? u : fcls[u]]);
+        for (int u = 0; u < nunits; ++u)
+            if (!skip(u)) total_lines += lines_of(p->cls[per_class ? u : fcls[u]]);
         // lines per work group: about kFftTargetElems elements, fewer when the
         // pass is small so that every compute unit gets work
         const long long want_groups = 1024;
         const int cap = (int)std::max(1LL, total_lines / want_groups);
         int maxL = 1;
         for (int u = 0; u < nunits; ++u) {
+            if (skip(u)) continue;
             const int c = per_class ? u : fcls[u];
             const ClassFft &cl = p->cls[c];
             const int L = len_of(cl);
@@ -583,6 +621,9 @@ static int build_fft(starred_plan *p)
     if ((rc = make_pass(d.frows, false, [](const ClassFft &c) { return c.n; }, LQ))) return rc;
     if ((rc = make_pass(d.rrows, false, [](const ClassFft &c) { return c.n; }, LQ))) return rc;
     if ((rc = make_pass(d.rcols, false, [](const ClassFft &c) { return c.Q / 2 + 1; }, LQ))) return rc;
+    if ((rc = make_pass(d.fcols_lg, false, [](const ClassFft &c) { return c.Q / 2 + 1; }, LQ, true))) return rc;
+    if ((rc = make_pass(d.frows_lg, false, [](const ClassFft &c) { return c.n; }, LQ, true))) return rc;
+    if ((rc = make_pass(d.rcols_lg, false, [](const ClassFft &c) { return c.Q / 2 + 1; }, LQ, true))) return rc;
     if ((rc = make_pass(d.acols, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
     if ((rc = make_pass(d.arows, false, [](const ClassFft &c) { return c.F; }, LP))) return rc;
     {
@@ -602,7 +643,8 @@ static int build_fft(starred_plan *p)
     if ((rc = make_pass(d.scols, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
     if ((rc = make_pass(d.gcols, true, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
     if ((rc = make_pass(d.grows, true, [](const ClassFft &c) { return c.F; }, LP))) return rc;
-    if ((rc = p->alloc(&p->d_part_chi_fft, std::max(1, d.frows.n_items)))) return rc;
+    if ((rc = p->alloc(&p->d_part_chi_fft, std::max(1, std::max(d.frows.n_items, d.frows_lg.n_items + d.n_fused)))))
+        return rc;
     p->fft_ready = true;
     return STARRED_OK;
 }
@@ -825,22 +867,33 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     int n_l1 = 0;
     int rc = starlet_branch(p, params, grad != nullptr, &n_l1);
     if (rc) return rc;
+    const bool fused = fft && p->fft_fused && p->fd.n_fused > 0;
     if (fft) {
         e0 = p->prof_start();
         HIP_TRY(fft_spectra(p->st, p->fd, params, p->N, p->E, p->M, p->sigma));
         p->prof_stop(STARRED_STAGE_SPECTRA, e0);
         e0 = p->prof_start();
-        hipEvent_t e1 = p->prof_start();
-        HIP_TRY(fft_spec_fwd(p->st, p->fd, params, p->N, p->E, p->M, p->s));
+        hipEvent_t e1;
+        // chi-square partials: the line-pass frames' row groups, then one per fused frame
+        const int n_rows = fused ? p->fd.frows_lg.n_items : p->fd.frows.n_items;
+        if (fused) {
+            e1 = p->prof_start();
+            HIP_TRY(fft_fused_fwd(p->st, p->fd, params, p->N, p->E, p->M, p->s, p->data, p->invvar,
+                                  p->d_part_chi_fft + n_rows));
+            p->prof_stop(STARRED_STAGE_FFT_FUSED, e1);
+        }
+        e1 = p->prof_start();
+        HIP_TRY(fft_spec_fwd(p->st, p->fd, params, p->N, p->E, p->M, p->s, fused));
         p->prof_stop(STARRED_STAGE_FFT_SPEC, e1);
         e1 = p->prof_start();
-        HIP_TRY(fft_model_cols(p->st, p->fd));
+        HIP_TRY(fused ? fft_model_cols_lg(p->st, p->fd) : fft_model_cols(p->st, p->fd));
         p->prof_stop(STARRED_STAGE_FFT_MCOLS, e1);
         e1 = p->prof_start();
-        HIP_TRY(fft_model_rows(p->st, p->fd, p->data, p->invvar, p->d_part_chi_fft, nullptr));
+        HIP_TRY(fused ? fft_model_rows_lg(p->st, p->fd, p->data, p->invvar, p->d_part_chi_fft)
+                      : fft_model_rows(p->st, p->fd, p->data, p->invvar, p->d_part_chi_fft, nullptr));
         p->prof_stop(STARRED_STAGE_FFT_MROWS, e1);
         p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
-        n_chi = p->fd.frows.n_items;
+        n_chi = n_rows + (fused ? p->fd.n_fused : 0);
         part_chi = p->d_part_chi_fft;
     } else {
         e0 = p->prof_start();
@@ -860,11 +913,14 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
             // before one inverse transform, and the per-frame dot products for Gamma, a
             // and c are taken there (Parseval)
             hipEvent_t e1 = p->prof_start();
-            HIP_TRY(fft_rho_cols(p->st, p->fd));
+            HIP_TRY(fused ? fft_rho_cols_lg(p->st, p->fd) : fft_rho_cols(p->st, p->fd));
             p->prof_stop(STARRED_STAGE_FFT_RCOLS, e1);
             e1 = p->prof_start();
-            HIP_TRY(fft_spec_adj(p->st, p->fd, p->M, p->d_fsum));
+            HIP_TRY(fft_spec_adj(p->st, p->fd, p->M));
             p->prof_stop(STARRED_STAGE_FFT_ACOLS, e1);
+            e1 = p->prof_start();
+            HIP_TRY(fft_adj_sums(p->st, p->fd, p->M, p->d_fsum));
+            p->prof_stop(STARRED_STAGE_FFT_FSUM, e1);
             e1 = p->prof_start();
             HIP_TRY(fft_grad_h_inverse(p->st, p->fd));
             p->prof_stop(STARRED_STAGE_FFT_AROWS, e1);
@@ -880,14 +936,12 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     }
     HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
     e0 = p->prof_start();
-    if (grad) {
-        if (fft)
-            HIP_TRY(fft_finalize_h(p->st, p->fd, p->N, p->d_prior, grad));
-        else
-            HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad, p->d_hpart));
-    }
+    // FFT path: dL/dh from the classes' window contributions in the same launch
+    if (grad && !fft)
+        HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad, p->d_hpart));
     HIP_TRY(launch_finalize_small(p->st, p->E, p->M, n_chi, part_chi, n_l1, p->d_part_l1, p->lam, p->d_fsum,
-                                  params, p->N, grad, loss_out, nullptr, nullptr, nullptr, tick));
+                                  params, p->N, grad, loss_out, nullptr, nullptr, nullptr, tick,
+                                  fft ? p->fd.classes : nullptr, p->fd.n_classes, p->fd.hcls, p->d_prior));
     p->prof_stop(STARRED_STAGE_FINALIZE, e0);
     return STARRED_OK;
 }
@@ -1133,6 +1187,7 @@ int starred_loss_grad(starred_plan *p, const float *params, float *grad, double 
 {
     if (!p || !params || !loss_out) return fail(STARRED_EINVAL, "NULL argument");
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
+    if (p->prof_on) HIP_TRY(launch_idle(p->st, kProfIdleIters));
     auto body = [&]() -> int {
         return (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, grad, loss_out)
                                          : loss_grad_impl(p, params, grad, loss_out);
@@ -1151,6 +1206,7 @@ int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
     // the device step counter is advanced inside the step; resynchronise it when
     // the caller's step number is not the next one
     if (t != p->next_t) HIP_TRY(launch_set_step(p->st, p->d_t, t - 1));
+    if (p->prof_on) HIP_TRY(launch_idle(p->st, kProfIdleIters));
     auto body = [&]() -> int {
         int rc = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t)
                                           : loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t);
@@ -1187,6 +1243,14 @@ int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
     return STARRED_OK;
 }
 
+int starred_set_fft_fused(starred_plan *p, int32_t enable)
+{
+    if (!p) return fail(STARRED_EINVAL, "plan is NULL");
+    p->drop_graphs();
+    p->fft_fused = enable != 0;
+    return STARRED_OK;
+}
+
 int starred_set_graph_mode(starred_plan *p, int32_t enable)
 {
     if (!p) return fail(STARRED_EINVAL, "plan is NULL");
@@ -1194,6 +1258,113 @@ int starred_set_graph_mode(starred_plan *p, int32_t enable)
     if (!enable) p->drop_graphs();
     p->graph_mode = enable != 0;
     return STARRED_OK;
+}
+
+int starred_time_stage(starred_plan *p, const float *params, int32_t stage, int32_t reps, double *ms_out)
+{
+    if (!p || !params || !ms_out) return fail(STARRED_EINVAL, "NULL argument");
+    if (reps < 1) return fail(STARRED_EINVAL, "reps must be >= 1");
+    if (p->mode != STARRED_DECONV) return fail(STARRED_EUNSUPPORTED, "stage timing needs deconvolution mode");
+    if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
+    const bool fft = (p->algo == STARRED_CONV_FFT);
+    const bool fused = fft && p->fft_fused && p->fd.n_fused > 0;
+    int n_l1 = 0;
+    auto launch = [&]() -> int {
+        switch (stage) {
+        case STARRED_STAGE_STARLET:
+            HIP_TRY(launch_starlet_fwd(p->st, p->N, p->J, params, nullptr, p->d_z, p->W, p->w_stride, (float)p->lam,
+                                       p->d_ca, p->d_cb, p->d_tmp, p->d_part_l1, &n_l1));
+            HIP_TRY(launch_starlet_adj(p->st, p->N, p->J, p->d_z, p->d_prior, p->d_ca, p->d_cb, p->d_tmp));
+            return STARRED_OK;
+        case STARRED_STAGE_SPECTRA:
+            if (!fft) break;
+            HIP_TRY(fft_spectra(p->st, p->fd, params, p->N, p->E, p->M, p->sigma));
+            return STARRED_OK;
+        case STARRED_STAGE_FFT_FUSED:
+            if (!fft) break;
+            HIP_TRY(fft_fused_fwd(p->st, p->fd, params, p->N, p->E, p->M, p->s, p->data, p->invvar,
+                                  p->d_part_chi_fft + p->fd.frows_lg.n_items));
+            return STARRED_OK;
+        case STARRED_STAGE_FFT_SPEC:
+            if (!fft) break;
+            HIP_TRY(fft_spec_fwd(p->st, p->fd, params, p->N, p->E, p->M, p->s, fused));
+            return STARRED_OK;
+        case STARRED_STAGE_FFT_MCOLS:
+            if (!fft) break;
+            HIP_TRY(fused ? fft_model_cols_lg(p->st, p->fd) : fft_model_cols(p->st, p->fd));
+            return STARRED_OK;
+        case STARRED_STAGE_FFT_MROWS:
+            if (!fft) break;
+            HIP_TRY(fused ? fft_model_rows_lg(p->st, p->fd, p->data, p->invvar, p->d_part_chi_fft)
+                          : fft_model_rows(p->st, p->fd, p->data, p->invvar, p->d_part_chi_fft, nullptr));
+            return STARRED_OK;
+        case STARRED_STAGE_FFT_RCOLS:
+            if (!fft) break;
+            HIP_TRY(fused ? fft_rho_cols_lg(p->st, p->fd) : fft_rho_cols(p->st, p->fd));
+            return STARRED_OK;
+        case STARRED_STAGE_FFT_ACOLS:
+            if (!fft) break;
+            HIP_TRY(fft_spec_adj(p->st, p->fd, p->M));
+            return STARRED_OK;
+        case STARRED_STAGE_FFT_FSUM:
+            if (!fft) break;
+            HIP_TRY(fft_adj_sums(p->st, p->fd, p->M, p->d_fsum));
+            return STARRED_OK;
+        case STARRED_STAGE_FFT_AROWS:
+            if (!fft) break;
+            HIP_TRY(fft_grad_h_inverse(p->st, p->fd));
+            return STARRED_OK;
+        case STARRED_STAGE_RENDER:
+            if (fft) break;
+            HIP_TRY(launch_render(p->st, p->d_fr, p->E, p->Fmax, p->N, p->M, p->sigma, params, p->d_scene));
+            return STARRED_OK;
+        case STARRED_STAGE_CONV_FWD:
+            if (fft) break;
+            HIP_TRY(launch_fwd_direct(p->st, p->s, p->d_fr, p->d_fwd_items, (int)p->fwd_items.size(), p->Tmax,
+                                      p->d_scene, p->d_kf, p->data, p->invvar, p->d_rho, p->d_part_chi));
+            return STARRED_OK;
+        case STARRED_STAGE_CONV_ADJ:
+            if (fft) break;
+            HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ar_max,
+                                      p->Bpad_max, p->d_rho, p->d_ka, p->d_g));
+            return STARRED_OK;
+        case STARRED_STAGE_GRAD_SUMS:
+            if (fft) break;
+            HIP_TRY(launch_frame_sums(p->st, p->d_fr, p->E, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum, true));
+            return STARRED_OK;
+        default:
+            break;
+        }
+        return fail(STARRED_EUNSUPPORTED, "stage cannot be timed alone with this plan's algorithm");
+    };
+    if (stage < 0 || stage >= STARRED_NUM_STAGES) return fail(STARRED_EINVAL, "unknown stage");
+    const bool prof = p->prof_on;
+    p->prof_on = false;
+    int rc = STARRED_OK;
+    double *loss = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    rc = dev_alloc(&loss, 3);
+    if (!rc && hipEventCreate(&a) != hipSuccess) rc = fail(STARRED_EHIP, "hipEventCreate");
+    if (!rc && hipEventCreate(&b) != hipSuccess) rc = fail(STARRED_EHIP, "hipEventCreate");
+    if (!rc) rc = loss_grad_impl(p, params, p->d_grad, loss);
+    if (!rc) rc = launch(); // rejects unsupported stages before any timing
+    if (!rc) {
+        hipError_t e = launch_idle(p->st, kProfIdleIters);
+        if (e == hipSuccess) e = hipEventRecord(a, p->st);
+        for (int r = 0; r < reps && e == hipSuccess && !rc; ++r) rc = launch();
+        if (e == hipSuccess && !rc) e = hipEventRecord(b, p->st);
+        if (e == hipSuccess && !rc) e = hipEventSynchronize(b);
+        float ms = 0.f;
+        if (e == hipSuccess && !rc) e = hipEventElapsedTime(&ms, a, b);
+        if (e != hipSuccess && !rc) rc = fail_hip(e, "stage timing");
+        if (!rc) *ms_out = (double)ms / reps;
+    }
+    if (hipStreamSynchronize(p->st) != hipSuccess && !rc) rc = fail(STARRED_EHIP, "stage timing synchronisation");
+    p->prof_on = prof;
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (loss) (void)hipFree(loss);
+    return rc;
 }
 
 int starred_copy_probe(starred_plan *p, const float *src, float *dst, int64_t n)

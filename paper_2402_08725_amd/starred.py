@@ -28,7 +28,8 @@ EXPORTED = [
     "starred_profile_read", "starred_psf_model", "starred_loss_grad_plain", "starred_copy_probe",
 ]
 STAGES = ["render", "conv_fwd", "conv_adj", "grad_sums", "starlet", "finalize", "adam", "spectra",
-          "graph", "fft_spec", "fft_mcols", "fft_mrows", "fft_rcols", "fft_acols", "fft_arows"]
+          "graph", "fft_spec", "fft_mcols", "fft_mrows", "fft_rcols", "fft_acols", "fft_arows",
+          "fft_fsum", "fft_fused"]
 
 
 class Desc(ctypes.Structure):
@@ -75,6 +76,7 @@ def lib():
         L.starred_loss_grad.argtypes = [vp, vp, vp, vp]
         L.starred_step.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(AdamHP), vp]
         L.starred_set_graph_mode.argtypes = [vp, i32]
+        L.starred_set_fft_fused.argtypes = [vp, i32]
         L.starred_conv_algo.argtypes = [vp]
         L.starred_last_error.restype = ctypes.c_char_p
         L.starred_set_profiling.argtypes = [vp, i32]
@@ -82,6 +84,7 @@ def lib():
         L.starred_psf_model.argtypes = [vp, vp, vp]
         L.starred_loss_grad_plain.argtypes = [vp, vp, vp, vp]
         L.starred_copy_probe.argtypes = [vp, vp, vp, ctypes.c_int64]
+        L.starred_time_stage.argtypes = [vp, vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
         _lib = L
     return _lib
 
@@ -260,9 +263,21 @@ class Plan:
                                           ctypes.c_void_p(cnt.ctypes.data)))
         return {name: {"ms": float(ms[i]), "count": int(cnt[i])} for i, name in enumerate(STAGES)}
 
+    def time_stage(self, params, stage: str, reps: int = 50) -> float:
+        """Average device milliseconds of one stage's launches run back to back."""
+        params = _f32(params, self.device)
+        ms = ctypes.c_double(0.0)
+        self._call(lib().starred_time_stage, _ptr(params), ctypes.c_int32(STAGES.index(stage)),
+                   ctypes.c_int32(int(reps)), ctypes.byref(ms))
+        return ms.value
+
     def copy_probe(self, src, dst):
         """Plain device copy (memory-counter calibration)."""
         self._call(lib().starred_copy_probe, _ptr(src), _ptr(dst), int(src.numel()))
+
+    def set_fft_fused(self, enable: bool):
+        """FFT path: one-launch forward for frames whose spectra fit in LDS (default on)."""
+        _check(lib().starred_set_fft_fused(self._h, 1 if enable else 0))
 
     def set_graph_mode(self, enable: bool):
         _check(lib().starred_set_graph_mode(self._h, int(bool(enable))))

@@ -88,4 +88,5 @@ def test_null_plan_arguments_are_rejected():
     L = _lib()
     assert L.starred_plan_destroy(None) == -1
     assert L.starred_loss_grad(None, None, None, None) == -1
+    assert L.starred_time_stage(None, None, 0, 1, None) == -1
     assert L.starred_set_frames(None, None, None, None, None) == -1

@@ -145,6 +145,32 @@ def _compare_loss_grad(prob, d, w, p, plan, label, loss_tol=1e-6, grad_tol=1e-4)
     return loss, grad
 
 
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+def test_stage_timing_leaves_results_unchanged(algo):
+    """Timing a stage alone re-runs its launches on the plan's buffers; the next
+    evaluation must still give bit-identical results, and stages of the other
+    algorithm are refused."""
+    st = _st()
+    prob = synth.make_deconv(2, E=6)
+    d, w, rng = _data(prob, seed=5)
+    plan = _plan(prob, d, w, algo=algo)
+    p = torch.as_tensor(synth.eval_point(prob, "near", rng), dtype=torch.float32, device="cuda")
+    l0, g0 = plan.loss_grad(p)
+    own = (["spectra", "fft_fused", "fft_spec", "fft_mcols", "fft_mrows", "fft_rcols", "fft_acols", "fft_fsum",
+            "fft_arows", "starlet"] if algo == 2 else ["render", "conv_fwd", "conv_adj", "grad_sums", "starlet"])
+    for stage in own:
+        ms = plan.time_stage(p, stage, reps=3)
+        _say(f"{ALGO_ID[algo]} {stage}: {ms * 1e3:.1f} us")
+        assert 0.0 <= ms < 1e3
+    other = "conv_fwd" if algo == 2 else "fft_acols"
+    with pytest.raises(st.StarredError):
+        plan.time_stage(p, other, reps=1)
+    with pytest.raises(st.StarredError):
+        plan.time_stage(p, "adam", reps=1)
+    l1, g1 = plan.loss_grad(p)
+    assert torch.equal(l0, l1) and torch.equal(g0, g1)
+
+
 LG_CASES = [
     ("cfg1", lambda: synth.make_deconv(1)),
     ("cfg2_E6", lambda: synth.make_deconv(2, E=6)),
@@ -164,6 +190,23 @@ def test_loss_grad_parity(name, make, point, algo):
     plan = _plan(prob, d, w, algo)
     p = synth.eval_point(prob, point, rng)
     _compare_loss_grad(prob, d, w, p, plan, f"{name}/{point}/{ALGO_ID[algo]}")
+
+
+@pytest.mark.parametrize("name,make", [LG_CASES[1], LG_CASES[2], LG_CASES[3]], ids=["cfg2_E6", "cfg4_mini",
+                                                                                   "small_s3"])
+def test_fft_line_passes_without_the_fused_forward(name, make):
+    """The FFT forward through the batched line passes (the path of frames too large
+    for the one-launch forward) on shapes that would otherwise take the one-launch
+    kernel: both must match the oracle."""
+    prob = make()
+    d, w, rng = _data(prob, seed=13)
+    plan = _plan(prob, d, w, algo=2)
+    p = synth.eval_point(prob, "near", rng)
+    _, g_fused = _compare_loss_grad(prob, d, w, p, plan, f"{name}/fused")
+    plan.set_fft_fused(False)
+    _, g_lines = _compare_loss_grad(prob, d, w, p, plan, f"{name}/line passes")
+    plan.set_fft_fused(True)
+    assert parity.rel_err(g_fused, g_lines) <= 1e-4
 
 
 def test_loss_grad_cfg2_full_size_both_algorithms_and_autotune():
@@ -200,11 +243,12 @@ def test_forward_only_matches_and_is_deterministic():
     assert torch.equal(l1, l3)
 
 
-def test_autograd_function_and_directional_differences():
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+def test_autograd_function_and_directional_differences(algo):
     st = _st()
     prob = synth.make_deconv(1)
     d, w, rng = _data(prob, seed=4)
-    plan = st.Plan.for_problem(prob, lam=0.0)
+    plan = st.Plan.for_problem(prob, lam=0.0, conv_algo=algo)
     plan.set_frames(d, w, prob.kernels, prob.W)
     p0 = synth.eval_point(prob, "near", rng)
     x = torch.tensor(p0, dtype=torch.float32, device="cuda", requires_grad=True)
@@ -225,7 +269,9 @@ def test_autograd_function_and_directional_differences():
         dp = synth.f32(p0 + eps * delta) - synth.f32(p0 - eps * delta)
         fd = (lp - lm)
         an = float(np.dot(g.cpu().numpy().astype(np.float64), dp))
-        tol = 1e-3 if block == "c" else 1e-4
+        # the loss values differ in their FP32 model rounding (more steps through the
+        # transforms on the FFT path), which the difference of two losses exposes
+        tol = 1e-3 if block == "c" else (1e-4 if algo == 1 else 3e-4)
         _say(f"fd {block}: fd {fd:.6e} analytic {an:.6e}")
         assert abs(fd - an) <= tol * abs(an) + 1e-9, block
 
