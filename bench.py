@@ -99,6 +99,12 @@ def main():
     prob = synth.make_deconv(cfg)
     algo = {"auto": st.CONV_AUTO, "direct": st.CONV_DIRECT, "fft": st.CONV_FFT}[args.algo]
     plan = st.Plan.for_problem(prob, conv_algo=algo)
+    # the whole run on the plan's stream: no cross-stream ordering per call
+    with torch.cuda.stream(plan.stream):
+        _run(args, prob, plan, torch, st, synth)
+
+
+def _run(args, prob, plan, torch, st, synth):
     _make_inputs(prob, plan, torch)
     rng = np.random.default_rng(1)
     p0 = synth.eval_point(prob, "init", rng)

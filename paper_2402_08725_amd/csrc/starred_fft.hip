@@ -21,6 +21,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace starred {
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
@@ -244,12 +246,24 @@ __device__ __forceinline__ float2 *lds_fft_any(float2 *a, float2 *b, int nl, con
 // Generic line pass: load -> FFT -> store, for a table of line groups
 // --------------------------------------------------------------------------
 
+// Ops may carry extra work groups behind their line groups (Op::extra, run_extra)
+template <class Op, class = void>
+struct has_extra : std::false_type {};
+template <class Op>
+struct has_extra<Op, std::void_t<decltype(Op::extra)>> : std::true_type {};
+
 template <class Op>
 __global__ __launch_bounds__(kFftThreads) void k_lines(const LineItem *__restrict__ items,
                                                        const ClassFft *__restrict__ classes,
                                                        const float2 *__restrict__ tw, Op op)
 {
     extern __shared__ float2 sm[];
+    if constexpr (has_extra<Op>::value) {
+        if ((int)blockIdx.x >= op.n_items) {
+            op.run_extra(blockIdx.x - op.n_items, classes, tw);
+            return;
+        }
+    }
     const LineItem it = items[blockIdx.x];
     const ClassFft &cl = classes[it.cls];
     const FftLen &f = op.len(cl);
@@ -300,10 +314,24 @@ __device__ __forceinline__ float2 half_get(const float2 *__restrict__ X, int P, 
 }
 
 // ---- pass A: rows of the h window of each class (real -> half spectrum) ----
+// Its launch carries kTabBlocks extra work groups per class (when M > 0) that
+// compute the per-evaluation factor tables (k_tables' work) alongside.
+constexpr int kTabBlocks = 16;
+__device__ void tables_part(const ClassFft &c, const float2 *__restrict__ tw, const float *__restrict__ params,
+                            int N, int E, int M, float sigma, float2 *__restrict__ tab, int e0, int estep);
 struct OpHRows {
     const float *h;
     int N;
     float2 *Th;
+    int n_items, E, M;
+    float sigma;
+    float2 *tab;
+    static constexpr bool extra = true;
+    __device__ void run_extra(int xb, const ClassFft *classes, const float2 *tw) const
+    {
+        tables_part(classes[xb / kTabBlocks], tw, h, N, E, M, sigma, tab,
+                    threadIdx.x + (xb % kTabBlocks) * blockDim.x, blockDim.x * kTabBlocks);
+    }
     static constexpr bool col = false;
     static constexpr bool rowsum = false;
     static constexpr bool inverse = false;
@@ -873,11 +901,9 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
 // tab[c]: [w (P) | for each source k: gx, gy, dgx, dgy (P each)], the 1-D DFTs
 // over the frame of the window indicator, of g(x + o - c) (r = g(dx) g(dy),
 // Eq. 9) and of g(x + o - c)(x + o - c)/sigma^2 (its derivative in c).
-__global__ void k_tables(const ClassFft *__restrict__ classes, const float2 *__restrict__ tw,
-                         const float *__restrict__ params, int N, int E, int M, float sigma,
-                         float2 *__restrict__ tab)
+__device__ void tables_part(const ClassFft &c, const float2 *__restrict__ tw, const float *__restrict__ params,
+                            int N, int E, int M, float sigma, float2 *__restrict__ tab, int e0, int estep)
 {
-    const ClassFft &c = classes[blockIdx.x];
     const int P = c.P;
     const float2 *twP = tw + c.fP.tw_off;
     float2 *t = tab + c.tab_off;
@@ -885,7 +911,7 @@ __global__ void k_tables(const ClassFft *__restrict__ classes, const float2 *__r
     const float inv2s2 = 1.0f / (2.0f * sigma * sigma), invs2 = 1.0f / (sigma * sigma);
     const float norm = 1.0f / (2.50662827463100050f * sigma);  // 1/(sqrt(2 pi) sigma)
     const int nent = (1 + 4 * M) * P;
-    for (int e = threadIdx.x + blockIdx.y * blockDim.x; e < nent; e += blockDim.x * gridDim.y) {
+    for (int e = e0; e < nent; e += estep) {
         const int which = e / P, K = e - which * P;
         if (which == 0) continue;  // the window factor is static, written at plan creation
         const int k = (which - 1) / 4, part = (which - 1) % 4;
@@ -905,7 +931,6 @@ __global__ void k_tables(const ClassFft *__restrict__ classes, const float2 *__r
         t[e] = acc;
     }
 }
-
 
 // ---- adjoint in the frequency domain ----
 // For bin K of a class's half spectrum and each frame i of a chunk:
@@ -1161,16 +1186,15 @@ hipError_t fft_prep_kernels(hipStream_t st, const FftPlanDev &d, const float *ps
 hipError_t fft_spectra(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M,
                        float sigma)
 {
-    hipError_t e = run_lines(st, d.hrows, d.classes, d.tw, OpHRows{params, N, d.Th});
+    // rows of the h windows, with the factor tables in extra work groups
+    const int extra = M > 0 ? d.n_classes * kTabBlocks : 0;
+    const OpHRows op{params, N, d.Th, d.hrows.n_items, E, M, sigma, d.tab};
+    if (d.hrows.n_items + extra > 0)
+        hipLaunchKernelGGL((k_lines<OpHRows>), dim3(d.hrows.n_items + extra), dim3(kFftThreads),
+                           d.hrows.lds_bytes, st, d.hrows.items, d.classes, d.tw, op);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = run_lines(st, d.hcols, d.classes, d.tw, OpHCols{d.Th, d.Hh});
-    if (e != hipSuccess) return e;
-    if (M > 0) {
-        hipLaunchKernelGGL(k_tables, dim3(d.n_classes, 16), dim3(256), 0, st, d.classes, d.tw, params, N, E, M,
-                           sigma, d.tab);
-        e = hipGetLastError();
-    }
-    return e;
+    return run_lines(st, d.hcols, d.classes, d.tw, OpHCols{d.Th, d.Hh});
 }
 
 hipError_t fft_spec_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,

@@ -87,6 +87,8 @@ hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const 
 hipError_t launch_copy_probe(hipStream_t st, const float *src, float *dst, long long n);
 hipError_t launch_idle(hipStream_t st, int iters);
 
+// partial L1 slots the forward transform writes for an N x N image and J planes
+int starlet_l1_slots(int N, int J);
 hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, float *coeffs,
                               float *z, const float *W, int w_stride, float lam, float *c_a,
                               float *c_b, float *tmp, double *part_l1, int *n_l1);

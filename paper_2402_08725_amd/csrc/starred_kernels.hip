@@ -9,6 +9,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace starred {
 
 // --------------------------------------------------------------------------
@@ -637,35 +639,47 @@ hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const 
 __constant__ float kB3[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
 constexpr int kStarThreads = 256;
 
-__global__ void k_star_row(const float *__restrict__ in, float *__restrict__ out, int N, int d)
-{
-    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= N * N) return;
-    const int y = pix / N, x = pix % N;
-    const float *row = in + (long long)y * N;
-    float acc = 0.f;
-    #pragma unroll
-    for (int t = -2; t <= 2; ++t) acc = fmaf(kB3[t + 2], row[mirror_idx(x + t * d, N)], acc);
-    out[pix] = acc;
-}
-
 __device__ __forceinline__ float sgnf(float v) { return (float)((v > 0.f) - (v < 0.f)); }
 
-// c_next = C_j tmp; alpha_j = c_j - c_next; optionally also the coarse plane.
-__global__ __launch_bounds__(kStarThreads) void k_star_col(
-    const float *__restrict__ cj, const float *__restrict__ tmp, float *__restrict__ cnext,
-    float *__restrict__ coeffs, float *__restrict__ z, const float *__restrict__ W, int w_stride,
-    float lam, int N, int d, int j, int last, double *__restrict__ part_l1)
+// One smoothing level j (spacing d = 2^j) of the forward transform per launch,
+// on kStarTile x kStarTile output tiles: the row filter R_j is applied to every
+// (virtual) row the column taps of the tile reach and kept in LDS, then the
+// column filter C_j gives c_{j+1}; alpha_j = c_j - c_{j+1}, with the weighted L1
+// term and its subgradient (and, on the last level, the coarse plane as well).
+// Virtual row v maps to image row mirror(v); 2d < N keeps one reflection enough.
+constexpr int kStarTile = 16;
+static_assert(kStarTile * kStarTile == kStarThreads, "one output pixel per thread");
+
+__global__ __launch_bounds__(kStarThreads) void k_star_level(
+    const float *__restrict__ cj, float *__restrict__ cnext, float *__restrict__ coeffs, float *__restrict__ z,
+    const float *__restrict__ W, int w_stride, float lam, int N, int d, int j, int last,
+    double *__restrict__ part_l1)
 {
+    extern __shared__ float tmp[];  // (kStarTile + 4d) rows x kStarTile
     __shared__ double red[kStarThreads / 64];
-    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    const int x0 = blockIdx.x * kStarTile, y0 = blockIdx.y * kStarTile;
+    const int R = kStarTile + 4 * d, vy0 = y0 - 2 * d;
+    const int vmax = min(y0 + kStarTile, N) - 1 + 2 * d;  // last virtual row a tap reaches
+    for (int e = threadIdx.x; e < R * kStarTile; e += kStarThreads) {
+        const int r = e / kStarTile, x = x0 + (e % kStarTile);
+        float acc = 0.f;
+        if (x < N && vy0 + r <= vmax) {
+            const float *row = cj + (long long)mirror_idx(vy0 + r, N) * N;
+            #pragma unroll
+            for (int t = -2; t <= 2; ++t) acc = fmaf(kB3[t + 2], row[mirror_idx(x + t * d, N)], acc);
+        }
+        tmp[e] = acc;
+    }
+    __syncthreads();
+    const int yl = threadIdx.x / kStarTile, xl = threadIdx.x % kStarTile;
+    const int y = y0 + yl, x = x0 + xl;
     const long long NN = (long long)N * N;
     double l1 = 0.0;
-    if (pix < N * N) {
-        const int y = pix / N, x = pix % N;
+    if (y < N && x < N) {
+        const long long pix = (long long)y * N + x;
         float acc = 0.f;
         #pragma unroll
-        for (int t = -2; t <= 2; ++t) acc = fmaf(kB3[t + 2], tmp[(long long)mirror_idx(y + t * d, N) * N + x], acc);
+        for (int t = -2; t <= 2; ++t) acc = fmaf(kB3[t + 2], tmp[(yl + 2 * d + t * d) * kStarTile + xl], acc);
         cnext[pix] = acc;
         const float al = cj[pix] - acc;
         const float wj = w_stride ? W[j * NN + pix] : W[j];
@@ -680,7 +694,16 @@ __global__ __launch_bounds__(kStarThreads) void k_star_col(
         }
     }
     const double s = block_sum_d<kStarThreads>(l1, red);
-    if (threadIdx.x == 0 && part_l1) part_l1[blockIdx.x] = s;
+    if (threadIdx.x == 0 && part_l1) part_l1[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+static int star_tiles(int N) { return (N + kStarTile - 1) / kStarTile; }
+
+int starlet_l1_slots(int N, int J)
+{
+    const int plane = (int)(((long long)N * N + kStarThreads - 1) / kStarThreads);
+    const int tiles = star_tiles(N) * star_tiles(N);
+    return std::max(1, J - 1) * std::max(plane, tiles);
 }
 
 // J == 1: the only plane is the image itself.
@@ -704,7 +727,7 @@ __global__ __launch_bounds__(kStarThreads) void k_star_plane(
 
 hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, float *coeffs,
                               float *z, const float *W, int w_stride, float lam, float *c_a,
-                              float *c_b, float *tmp, double *part_l1, int *n_l1)
+                              float *c_b, float *, double *part_l1, int *n_l1)
 {
     const int nb = (N * N + kStarThreads - 1) / kStarThreads;
     if (J == 1) {
@@ -713,16 +736,18 @@ hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, fl
         if (n_l1) *n_l1 = nb;
         return hipGetLastError();
     }
+    const int nt = star_tiles(N);
     const float *cur = img;
     for (int j = 0; j < J - 1; ++j) {
         float *nxt = (j % 2 == 0) ? c_a : c_b;
-        hipLaunchKernelGGL(k_star_row, dim3(nb), dim3(kStarThreads), 0, st, cur, tmp, N, 1 << j);
-        hipLaunchKernelGGL(k_star_col, dim3(nb), dim3(kStarThreads), 0, st, cur, tmp, nxt, coeffs, z,
-                           W, w_stride, lam, N, 1 << j, j, (int)(j == J - 2),
-                           part_l1 ? part_l1 + (long long)j * nb : nullptr);
+        const int d = 1 << j;
+        const size_t lds = sizeof(float) * (size_t)(kStarTile + 4 * d) * kStarTile;
+        hipLaunchKernelGGL(k_star_level, dim3(nt, nt), dim3(kStarThreads), lds, st, cur, nxt, coeffs, z, W,
+                           w_stride, lam, N, d, j, (int)(j == J - 2),
+                           part_l1 ? part_l1 + (long long)j * nt * nt : nullptr);
         cur = nxt;
     }
-    if (n_l1) *n_l1 = (J - 1) * nb;
+    if (n_l1) *n_l1 = (J - 1) * nt * nt;
     return hipGetLastError();
 }
 
@@ -756,24 +781,47 @@ __device__ __forceinline__ float mirrorT_gather(const float *__restrict__ u, lon
     return acc;
 }
 
-// tmp = C_j^T (v - z_j)   (columns)
-__global__ void k_star_colT(const float *__restrict__ v, const float *__restrict__ zj,
-                            float *__restrict__ tmp, int N, int d)
+// One level of the adjoint per launch on output tiles: u = v - z_j, the
+// column transpose C_j^T u on the tile's rows for every column the row
+// transpose reaches (kept in LDS), then vout = z_j + R_j^T of it.
+__global__ __launch_bounds__(kStarThreads) void k_star_levelT(const float *__restrict__ v,
+                                                              const float *__restrict__ zj,
+                                                              float *__restrict__ vout, int N, int d)
 {
-    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= N * N) return;
-    const int y = pix / N, x = pix % N;
-    tmp[pix] = mirrorT_gather(v + x, N, y, N, d, zj + x, true);
-}
-
-// vout = z_j + R_j^T tmp   (rows)
-__global__ void k_star_rowT(const float *__restrict__ tmp, const float *__restrict__ zj,
-                            float *__restrict__ vout, int N, int d)
-{
-    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= N * N) return;
-    const int y = pix / N, x = pix % N;
-    vout[pix] = zj[pix] + mirrorT_gather(tmp + (long long)y * N, 1, x, N, d, nullptr, false);
+    extern __shared__ float tmp[];  // kStarTile rows x (kStarTile + 4d) columns
+    const int x0 = blockIdx.x * kStarTile, y0 = blockIdx.y * kStarTile;
+    const int C = kStarTile + 4 * d, cx0 = x0 - 2 * d;
+    for (int e = threadIdx.x; e < kStarTile * C; e += kStarThreads) {
+        const int yl = e / C, c = e - yl * C;
+        const int y = y0 + yl, xc = cx0 + c;
+        float acc = 0.f;
+        if (y < N && xc >= 0 && xc < N) acc = mirrorT_gather(v + xc, N, y, N, d, zj + xc, true);
+        tmp[e] = acc;
+    }
+    __syncthreads();
+    const int yl = threadIdx.x / kStarTile, xl = threadIdx.x % kStarTile;
+    const int y = y0 + yl, x = x0 + xl;
+    if (y >= N || x >= N) return;
+    // the row transpose gathers tmp at every column xc with mirror(xc + t d) == x;
+    // all of them lie in [x0 - 2d, x0 + kStarTile + 2d)
+    const float *row = tmp + yl * C - cx0;  // indexed by image column
+    float acc = 0.f;
+    #pragma unroll
+    for (int t = -2; t <= 2; ++t) {
+        const float w = kB3[t + 2];
+        int xc = x - t * d;
+        if (xc >= 0 && xc < N) acc = fmaf(w, row[xc], acc);
+        if (x > 0) {
+            xc = -x - t * d;
+            if (xc >= 0 && xc < N) acc = fmaf(w, row[xc], acc);
+        }
+        if (x < N - 1) {
+            xc = 2 * (N - 1) - x - t * d;
+            if (xc >= 0 && xc < N) acc = fmaf(w, row[xc], acc);
+        }
+    }
+    const long long pix = (long long)y * N + x;
+    vout[pix] = zj[pix] + acc;
 }
 
 __global__ void k_copy(const float *__restrict__ a, float *__restrict__ b, long long n)
@@ -783,7 +831,7 @@ __global__ void k_copy(const float *__restrict__ a, float *__restrict__ b, long 
 }
 
 hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, float *out,
-                              float *v_a, float *v_b, float *tmp)
+                              float *v_a, float *v_b, float *)
 {
     const long long NN = (long long)N * N;
     const int nb = (int)((NN + kStarThreads - 1) / kStarThreads);
@@ -791,11 +839,13 @@ hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, floa
         hipLaunchKernelGGL(k_copy, dim3(nb), dim3(kStarThreads), 0, st, z, out, NN);
         return hipGetLastError();
     }
+    const int nt = star_tiles(N);
     const float *v = z + (J - 1) * NN;
     for (int j = J - 2; j >= 0; --j) {
         float *vn = (j == 0) ? out : ((j % 2 == 0) ? v_a : v_b);
-        hipLaunchKernelGGL(k_star_colT, dim3(nb), dim3(kStarThreads), 0, st, v, z + j * NN, tmp, N, 1 << j);
-        hipLaunchKernelGGL(k_star_rowT, dim3(nb), dim3(kStarThreads), 0, st, tmp, z + j * NN, vn, N, 1 << j);
+        const int d = 1 << j;
+        const size_t lds = sizeof(float) * (size_t)kStarTile * (kStarTile + 4 * d);
+        hipLaunchKernelGGL(k_star_levelT, dim3(nt, nt), dim3(kStarThreads), lds, st, v, z + j * NN, vn, N, d);
         v = vn;
     }
     return hipGetLastError();

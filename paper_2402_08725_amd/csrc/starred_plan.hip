@@ -319,14 +319,13 @@ static int build_deconv(starred_plan *p)
     HIP_TRY(hipMemcpy(p->d_adj_items, p->adj_items.data(), sizeof(Item) * p->adj_items.size(), hipMemcpyHostToDevice));
 
     const long long NN = (long long)p->N * p->N;
-    const int nb_star = (int)((NN + 255) / 256);
     if ((rc = p->alloc(&p->d_kf, p->nkf))) return rc;
     if ((rc = p->alloc(&p->d_ka, p->nka))) return rc;
     if ((rc = p->alloc(&p->d_scene, p->nfine))) return rc;
     if ((rc = p->alloc(&p->d_rho, p->ndata))) return rc;
     if ((rc = p->alloc(&p->d_g, p->nfine))) return rc;
     if ((rc = p->alloc(&p->d_part_chi, p->fwd_items.size()))) return rc;
-    if ((rc = p->alloc(&p->d_part_l1, (size_t)std::max(1, p->J - 1) * nb_star))) return rc;
+    if ((rc = p->alloc(&p->d_part_l1, (size_t)starlet_l1_slots(p->N, p->J)))) return rc;
     if ((rc = p->alloc(&p->d_fsum, (size_t)E * (1 + 3 * p->M)))) return rc;
     if ((rc = p->alloc(&p->d_z, (size_t)p->J * NN))) return rc;
     if ((rc = p->alloc(&p->d_ca, NN))) return rc;
@@ -657,7 +656,6 @@ static int build_psf(starred_plan *p)
     p->ndata = (long long)S * n * n;
     p->nfine = (long long)N * N;
     const long long NN = (long long)N * N;
-    const int nb_star = (int)((NN + 255) / 256);
     if (psf_fwd_lds(n, p->s) > kMaxLds || psf_adj_lds(n, N) > kMaxLds)
         return fail(STARRED_EUNSUPPORTED, "PSF grid too large for one work group");
     int rc;
@@ -667,7 +665,7 @@ static int build_psf(starred_plan *p)
     if ((rc = p->alloc(&p->d_gstar, (size_t)S * NN))) return rc;
     if ((rc = p->alloc(&p->d_part_chi, S))) return rc;
     if ((rc = p->alloc(&p->d_part_eta, (size_t)psf_sum_blocks(N) * 5))) return rc;
-    if ((rc = p->alloc(&p->d_part_l1, (size_t)std::max(1, p->J - 1) * nb_star))) return rc;
+    if ((rc = p->alloc(&p->d_part_l1, (size_t)starlet_l1_slots(p->N, p->J)))) return rc;
     if ((rc = p->alloc(&p->d_z, (size_t)p->J * NN))) return rc;
     if ((rc = p->alloc(&p->d_ca, NN))) return rc;
     if ((rc = p->alloc(&p->d_cb, NN))) return rc;
@@ -1170,6 +1168,12 @@ static int run_graph(starred_plan *p, int slot, const std::vector<uintptr_t> &ke
         if (e != hipSuccess) {
             (void)hipGraphDestroy(graph);
             return fail_hip(e, "hipGraphInstantiate");
+        }
+        e = hipGraphUpload(exec, p->st);  // device-side set-up once, not at every launch
+        if (e != hipSuccess) {
+            (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(graph);
+            return fail_hip(e, "hipGraphUpload");
         }
         g.g = graph;
         g.x = exec;

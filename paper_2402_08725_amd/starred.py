@@ -167,11 +167,16 @@ class Plan:
 
     # -- stream ordering with PyTorch's current stream --
     def _call(self, fn, *args):
+        # order the plan's stream after the caller's and back; nothing to do when the
+        # caller already works on the plan's stream (torch.cuda.stream(plan.stream))
         cur = torch.cuda.current_stream(self.device)
-        self.stream.wait_stream(cur)
+        same = cur.cuda_stream == self.stream.cuda_stream
+        if not same:
+            self.stream.wait_stream(cur)
         with torch.cuda.device(self.device):
             rc = fn(self._h, *args)
-        cur.wait_stream(self.stream)
+        if not same:
+            cur.wait_stream(self.stream)
         _check(rc)
 
     @property
@@ -243,13 +248,7 @@ class Plan:
             hp.lr[i] = float(lr[i])
         hp.beta1, hp.beta2, hp.eps = beta1, beta2, eps
         loss = loss_out if loss_out is not None else torch.empty(3, dtype=torch.float64, device=self.device)
-        cur = torch.cuda.current_stream(self.device)
-        self.stream.wait_stream(cur)
-        with torch.cuda.device(self.device):
-            rc = lib().starred_step(self._h, _ptr(params), _ptr(m), _ptr(v), int(t), ctypes.byref(hp),
-                                    _ptr(loss))
-        cur.wait_stream(self.stream)
-        _check(rc)
+        self._call(lib().starred_step, _ptr(params), _ptr(m), _ptr(v), int(t), ctypes.byref(hp), _ptr(loss))
         return loss
 
     def set_profiling(self, enable: bool):
