@@ -139,8 +139,9 @@ __device__ __forceinline__ double block_sum_d_fft(double v, double *sh)
 }
 
 hipError_t fft_prep_kernels(hipStream_t st, const FftPlanDev &d, const float *psf, int s);
+// tick: a step counter the launch advances (the first launch of a fused step), or null
 hipError_t fft_spectra(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M,
-                       float sigma);
+                       float sigma, int *tick = nullptr);
 hipError_t fft_spec_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,
                         bool lg = false);
 hipError_t fft_model_cols(hipStream_t st, const FftPlanDev &d);

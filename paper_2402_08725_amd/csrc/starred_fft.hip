@@ -259,6 +259,7 @@ __global__ __launch_bounds__(kFftThreads) void k_lines(const LineItem *__restric
 {
     extern __shared__ float2 sm[];
     if constexpr (has_extra<Op>::value) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && op.tick) *op.tick += 1;
         if ((int)blockIdx.x >= op.n_items) {
             op.run_extra(blockIdx.x - op.n_items, classes, tw);
             return;
@@ -326,6 +327,7 @@ struct OpHRows {
     int n_items, E, M;
     float sigma;
     float2 *tab;
+    int *tick;  // optimiser step counter advanced by the launch (null: none)
     static constexpr bool extra = true;
     __device__ void run_extra(int xb, const ClassFft *classes, const float2 *tw) const
     {
@@ -792,7 +794,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
 // along y, and writes rho_hat [Q][Q/2+1] to memory for the adjoint. Two LDS
 // planes of max(Q/2+1, n) lines of stride Q+1 alternate as FFT source and
 // scratch; the Q-point twiddles and the class's factor tables sit behind them.
-template <int S>
+template <int S, int MS>
 __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restrict__ frames,
                                                              const ClassFft *__restrict__ classes,
                                                              const FrameFft *__restrict__ fr,
@@ -835,24 +837,43 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
     const int Q0L = Q <= 64 ? 64 : 128;  // lanes along a row of Q values
     const int lane = threadIdx.x % CXF, rg = threadIdx.x / CXF;
     // model spectrum, column-major: A[kx][ky]
+    // (with MS > 0 sources at most, the column factors a_k gx_k(Kx) stay in registers)
+    constexpr int MR = MS > 0 ? MS : 1;
     if (lane < HQ) {
         const int kx = lane;
-        float2 wxG[S];
+        float2 wxG[S], px[S][MR];
         #pragma unroll
-        for (int b = 0; b < S; ++b) wxG[b] = cscale(t[kx + b * Q], G);
+        for (int b = 0; b < S; ++b) {
+            wxG[b] = cscale(t[kx + b * Q], G);
+            #pragma unroll
+            for (int k = 0; k < MR; ++k)
+                px[b][k] = (MS > 0 && k < M) ? cscale(t[(1 + 4 * k) * P + kx + b * Q], ai[k]) : make_float2(0.f, 0.f);
+        }
         for (int ky = rg; ky < Q; ky += RGF) {
             float2 acc = make_float2(0.f, 0.f);
             #pragma unroll
             for (int a = 0; a < S; ++a) {
                 const int Ky = ky + a * Q;
                 const float2 wy = t[Ky];
+                float2 gy[MR];
+                #pragma unroll
+                for (int k = 0; k < MR; ++k)
+                    gy[k] = (MS > 0 && k < M) ? t[(1 + 4 * k) * P + P + Ky] : make_float2(0.f, 0.f);
                 #pragma unroll
                 for (int b = 0; b < S; ++b) {
                     const int Kx = kx + b * Q;
                     float2 F = cadd(half_get(Hc, P, Ky, Kx), cmul(wy, wxG[b]));
-                    for (int k = 0; k < M; ++k) {
-                        const float2 *tk = t + (1 + 4 * k) * P;  // [gx | gy | dgx | dgy]
-                        F = cadd(F, cscale(cmul(tk[P + Ky], tk[Kx]), ai[k]));
+                    if (MS > 0) {
+                        #pragma unroll
+                        for (int k = 0; k < MR; ++k) {
+                            F.x = fmaf(gy[k].x, px[b][k].x, fmaf(-gy[k].y, px[b][k].y, F.x));
+                            F.y = fmaf(gy[k].x, px[b][k].y, fmaf(gy[k].y, px[b][k].x, F.y));
+                        }
+                    } else {
+                        for (int k = 0; k < M; ++k) {
+                            const float2 *tk = t + (1 + 4 * k) * P;  // [gx | gy | dgx | dgy]
+                            F = cadd(F, cscale(cmul(tk[P + Ky], tk[Kx]), ai[k]));
+                        }
                     }
                     acc = cadd(acc, cmul(half_get(Si, P, Ky, Kx), F));
                 }
@@ -1184,11 +1205,11 @@ hipError_t fft_prep_kernels(hipStream_t st, const FftPlanDev &d, const float *ps
 }
 
 hipError_t fft_spectra(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M,
-                       float sigma)
+                       float sigma, int *tick)
 {
     // rows of the h windows, with the factor tables in extra work groups
     const int extra = M > 0 ? d.n_classes * kTabBlocks : 0;
-    const OpHRows op{params, N, d.Th, d.hrows.n_items, E, M, sigma, d.tab};
+    const OpHRows op{params, N, d.Th, d.hrows.n_items, E, M, sigma, d.tab, tick};
     if (d.hrows.n_items + extra > 0)
         hipLaunchKernelGGL((k_lines<OpHRows>), dim3(d.hrows.n_items + extra), dim3(kFftThreads),
                            d.hrows.lds_bytes, st, d.hrows.items, d.classes, d.tw, op);
@@ -1259,12 +1280,17 @@ hipError_t fft_fused_fwd(hipStream_t st, const FftPlanDev &d, const float *param
                          const float *data, const float *invvar, double *part_chi)
 {
     if (d.n_fused <= 0) return hipSuccess;
-#define FUSED_FWD(SS)                                                                                             \
-    hipLaunchKernelGGL(k_frame_fwd<SS>, dim3(d.n_fused), dim3(kFusedThreads), d.fused_lds, st, d.fused, d.classes, \
-                       d.frames, d.tw, d.S, d.Hh, d.tab, params, N, E, M, data, invvar, d.Rh, part_chi)
-    if (s == 1) FUSED_FWD(1);
-    else if (s == 2) FUSED_FWD(2);
-    else FUSED_FWD(3);
+#define FUSED_FWD(SS, MS)                                                                                     \
+    hipLaunchKernelGGL((k_frame_fwd<SS, MS>), dim3(d.n_fused), dim3(kFusedThreads), d.fused_lds, st, d.fused,    \
+                       d.classes, d.frames, d.tw, d.S, d.Hh, d.tab, params, N, E, M, data, invvar, d.Rh, part_chi)
+#define FUSED_FWD_M(SS)                       \
+    if (M <= 4) FUSED_FWD(SS, 4);             \
+    else if (M <= 8) FUSED_FWD(SS, 8);        \
+    else FUSED_FWD(SS, 0)
+    if (s == 1) { FUSED_FWD_M(1); }
+    else if (s == 2) { FUSED_FWD_M(2); }
+    else { FUSED_FWD_M(3); }
+#undef FUSED_FWD_M
 #undef FUSED_FWD
     return hipGetLastError();
 }

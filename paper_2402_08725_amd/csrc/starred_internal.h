@@ -74,6 +74,23 @@ hipError_t launch_frame_sums(hipStream_t st, const FrameDev *fr, int E, int N, i
 hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, const float *g,
                              const float *prior, float *grad_h, float *part);
 int finalize_h_chunks(int E);
+// Adam update of one parameter (bias-corrected moments, per-block learning rate).
+__device__ __forceinline__ void adam_update(float &param, float &m, float &v, float g, float lr, float beta1,
+                                            float beta2, float bc1, float bc2, float eps)
+{
+    m = beta1 * m + (1.f - beta1) * g;
+    v = beta2 * v + (1.f - beta2) * g * g;
+    param -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
+}
+
+// Adam state for an update fused into the final reduction launch (params null: none).
+struct AdamDev {
+    float *params = nullptr, *m = nullptr, *v = nullptr;
+    const int *d_t = nullptr;
+    float lr[4] = {0.f, 0.f, 0.f, 0.f};
+    float beta1 = 0.f, beta2 = 0.f, eps = 0.f;
+};
+
 struct ClassFft;
 // With classes (FFT path), the launch also writes dL/dh = prior + the classes'
 // window contributions hcls.
@@ -83,7 +100,8 @@ hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const 
                                  float *grad, double *loss, const int *gcsr_off = nullptr,
                                  const int *gcsr_item = nullptr, const double *gpart = nullptr,
                                  int *tick = nullptr, const ClassFft *classes = nullptr, int ncls = 0,
-                                 const float *hcls = nullptr, const float *prior = nullptr);
+                                 const float *hcls = nullptr, const float *prior = nullptr,
+                                 const AdamDev &adam = AdamDev());
 hipError_t launch_copy_probe(hipStream_t st, const float *src, float *dst, long long n);
 hipError_t launch_idle(hipStream_t st, int iters);
 

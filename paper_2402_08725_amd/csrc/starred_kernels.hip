@@ -551,9 +551,16 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
     const float *__restrict__ params, int N, float *__restrict__ grad, double *__restrict__ loss,
     const int *__restrict__ gcsr_off, const int *__restrict__ gcsr_item, const double *__restrict__ gpart,
     int *__restrict__ tick, const ClassFft *__restrict__ classes, int ncls, const float *__restrict__ hcls,
-    const float *__restrict__ prior)
+    const float *__restrict__ prior, AdamDev adam)
 {
     const long long NN = (long long)N * N;
+    // step mode: the Adam update of every parameter follows its gradient here
+    float bc1 = 1.f, bc2 = 1.f;
+    if (adam.params) {
+        const float t = (float)(*adam.d_t);
+        bc1 = 1.f - powf(adam.beta1, t);
+        bc2 = 1.f - powf(adam.beta2, t);
+    }
     if (blockIdx.x > 0) {
         const long long pix = (long long)(blockIdx.x - 1) * kFinThreads + threadIdx.x;
         if (pix >= NN) return;
@@ -565,6 +572,13 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
             if (y >= 0 && y < F && x >= 0 && x < F) acc += hcls[c.hc_off + (long long)y * F + x];
         }
         grad[pix] = acc;
+        if (adam.params) {
+            float pi = adam.params[pix], mi = adam.m[pix], vi = adam.v[pix];
+            adam_update(pi, mi, vi, acc, adam.lr[0], adam.beta1, adam.beta2, bc1, bc2, adam.eps);
+            adam.m[pix] = mi;
+            adam.v[pix] = vi;
+            adam.params[pix] = pi;
+        }
         return;
     }
     if (tick && threadIdx.x == 0) *tick += 1;  // the Adam step that follows reads it
@@ -614,6 +628,19 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
         const long long i = e / M, k = e - i * M;
         ga[e] = (float)fsum[i * stride + 1 + k];
     }
+    if (!adam.params) return;
+    // Gamma, a and c after their gradients (written above by this block) are final;
+    // the a values read for dL/dc were taken before this point
+    __syncthreads();
+    const long long e1 = NN + E, e2 = e1 + (long long)E * M, e3 = e2 + 2LL * M;
+    for (long long e = NN + threadIdx.x; e < e3; e += kFinThreads) {
+        const float lr = e < e1 ? adam.lr[1] : (e < e2 ? adam.lr[2] : adam.lr[3]);
+        float pi = adam.params[e], mi = adam.m[e], vi = adam.v[e];
+        adam_update(pi, mi, vi, grad[e], lr, adam.beta1, adam.beta2, bc1, bc2, adam.eps);
+        adam.m[e] = mi;
+        adam.v[e] = vi;
+        adam.params[e] = pi;
+    }
 }
 
 hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const double *part_chi,
@@ -621,13 +648,15 @@ hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const 
                                  const double *fsum, const float *params, int N,
                                  float *grad, double *loss, const int *gcsr_off, const int *gcsr_item,
                                  const double *gpart, int *tick, const ClassFft *classes, int ncls,
-                                 const float *hcls, const float *prior)
+                                 const float *hcls, const float *prior, const AdamDev &adam)
 {
     const long long NN = (long long)N * N;
     const int hblocks = (classes && grad) ? (int)((NN + kFinThreads - 1) / kFinThreads) : 0;
+    // a fused Adam update needs the h blocks (FFT path) and the gradient
+    if (adam.params && (!hblocks || !grad)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_finalize_small, dim3(1 + hblocks), dim3(kFinThreads), 0, st, E, M, n_chi, part_chi,
                        n_l1, part_l1, fsum, params, N, grad, loss, gcsr_off, gcsr_item, gpart, tick, classes, ncls,
-                       hcls, prior);
+                       hcls, prior, adam);
     return hipGetLastError();
 }
 
@@ -898,12 +927,11 @@ __global__ void k_adam(long long P, long long e0, long long e1, long long e2, fl
     const float bc1 = 1.f - powf(beta1, t);
     const float bc2 = 1.f - powf(beta2, t);
     const float lr = i < e0 ? lr0 : (i < e1 ? lr1 : (i < e2 ? lr2 : lr3));
-    const float g = grad[i];
-    const float mi = beta1 * m[i] + (1.f - beta1) * g;
-    const float vi = beta2 * v[i] + (1.f - beta2) * g * g;
+    float pi = params[i], mi = m[i], vi = v[i];
+    adam_update(pi, mi, vi, grad[i], lr, beta1, beta2, bc1, bc2, eps);
     m[i] = mi;
     v[i] = vi;
-    params[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    params[i] = pi;
 }
 
 hipError_t launch_set_step(hipStream_t st, int *d_t, int value)

@@ -677,7 +677,8 @@ static int build_psf(starred_plan *p)
     return STARRED_OK;
 }
 
-static int loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out, int *tick = nullptr);
+static int loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out, int *tick = nullptr,
+                          const AdamDev *adam = nullptr);
 static int autotune(starred_plan *p);
 
 int starred_plan_create(const starred_desc *desc, void *stream, starred_plan **plan_out)
@@ -855,7 +856,10 @@ static int starlet_branch(starred_plan *p, const float *img, bool want_grad, int
     return STARRED_OK;
 }
 
-static int loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out, int *tick)
+// tick: the device step counter a step advances; adam (FFT path only): the
+// update fused into the final launch, which the counter then feeds.
+static int loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out, int *tick,
+                          const AdamDev *adam)
 {
     const bool fft = (p->algo == STARRED_CONV_FFT);
     hipEvent_t e0;
@@ -868,7 +872,8 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     const bool fused = fft && p->fft_fused && p->fd.n_fused > 0;
     if (fft) {
         e0 = p->prof_start();
-        HIP_TRY(fft_spectra(p->st, p->fd, params, p->N, p->E, p->M, p->sigma));
+        // with the fused update the counter advances in the first launch of the step
+        HIP_TRY(fft_spectra(p->st, p->fd, params, p->N, p->E, p->M, p->sigma, adam ? tick : nullptr));
         p->prof_stop(STARRED_STAGE_SPECTRA, e0);
         e0 = p->prof_start();
         hipEvent_t e1;
@@ -938,8 +943,9 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     if (grad && !fft)
         HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad, p->d_hpart));
     HIP_TRY(launch_finalize_small(p->st, p->E, p->M, n_chi, part_chi, n_l1, p->d_part_l1, p->lam, p->d_fsum,
-                                  params, p->N, grad, loss_out, nullptr, nullptr, nullptr, tick,
-                                  fft ? p->fd.classes : nullptr, p->fd.n_classes, p->fd.hcls, p->d_prior));
+                                  params, p->N, grad, loss_out, nullptr, nullptr, nullptr,
+                                  (fft && adam) ? nullptr : tick, fft ? p->fd.classes : nullptr, p->fd.n_classes,
+                                  p->fd.hcls, p->d_prior, (fft && adam) ? *adam : AdamDev()));
     p->prof_stop(STARRED_STAGE_FINALIZE, e0);
     return STARRED_OK;
 }
@@ -1211,10 +1217,23 @@ int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
     // the caller's step number is not the next one
     if (t != p->next_t) HIP_TRY(launch_set_step(p->st, p->d_t, t - 1));
     if (p->prof_on) HIP_TRY(launch_idle(p->st, kProfIdleIters));
+    // FFT path: the update runs inside the final reduction launch
+    const bool fused_adam = p->mode == STARRED_DECONV && p->algo == STARRED_CONV_FFT;
+    AdamDev ad;
+    ad.params = params;
+    ad.m = m;
+    ad.v = v;
+    ad.d_t = p->d_t;
+    for (int k = 0; k < 4; ++k) ad.lr[k] = hp->lr[k];
+    ad.beta1 = hp->beta1;
+    ad.beta2 = hp->beta2;
+    ad.eps = hp->eps;
     auto body = [&]() -> int {
         int rc = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t)
-                                          : loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t);
+                                          : loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t,
+                                                           fused_adam ? &ad : nullptr);
         if (rc) return rc;
+        if (fused_adam) return STARRED_OK;
         const long long NN = (long long)p->N * p->N;
         long long seg[3] = {NN, NN + p->E, NN + p->E + (long long)p->E * p->M};
         if (p->mode == STARRED_PSF) {

@@ -276,14 +276,17 @@ def test_autograd_function_and_directional_differences(algo):
         assert abs(fd - an) <= tol * abs(an) + 1e-9, block
 
 
-def test_adam_200_steps_against_oracle():
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+def test_adam_200_steps_against_oracle(algo):
+    """Direct path: separate update launch; FFT path: update fused into the final
+    reduction launch, step counter advanced by the first launch."""
     st = _st()
     prob = synth.make_deconv(1)
     d, w, rng = _data(prob, seed=5)
     p0 = synth.eval_point(prob, "init", rng)
     lrv = prob.lr_vector()
     lr4 = [prob.adam_lr[k] for k in ("h", "Gamma", "a", "c")]
-    plan = _plan(prob, d, w)
+    plan = _plan(prob, d, w, algo=algo)
     x = torch.tensor(p0, dtype=torch.float32, device="cuda")
     m = torch.zeros_like(x)
     v = torch.zeros_like(x)
@@ -308,22 +311,26 @@ def test_adam_200_steps_against_oracle():
     assert np.abs(cdev - cora).max() <= 0.01
 
 
-def test_adam_single_step_well_conditioned_entries():
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+@pytest.mark.parametrize("t", [1, 7])
+def test_adam_single_step_well_conditioned_entries(algo, t):
+    """One update at step number t (t = 7 without the six before it: the device
+    counter is resynchronised), both update paths."""
     st = _st()
     prob = synth.make_deconv(2, E=4)
     d, w, rng = _data(prob, seed=6)
     p0 = synth.eval_point(prob, "near", rng)
     lrv = prob.lr_vector()
     lr4 = [prob.adam_lr[k] for k in ("h", "Gamma", "a", "c")]
-    plan = _plan(prob, d, w)
+    plan = _plan(prob, d, w, algo=algo)
     x = torch.tensor(p0, dtype=torch.float32, device="cuda")
     m = torch.zeros_like(x)
     v = torch.zeros_like(x)
-    plan.step(x, m, v, 1, lr4)
+    plan.step(x, m, v, t, lr4)
     po = p0.copy()
     _, go = ora.loss_grad(prob, d, w, po)
     mo, vo = np.zeros_like(po), np.zeros_like(po)
-    ora.adam_step(po, go, mo, vo, 1, lrv)
+    ora.adam_step(po, go, mo, vo, t, lrv)
     good = np.abs(go) > 1e-3 * np.abs(go).max()
     xf = x.cpu().numpy().astype(np.float64)
     err = np.abs(xf - po)[good] / np.maximum(np.abs(po[good]), lrv[good])
