@@ -285,11 +285,12 @@ def fft_kernel_bytes(prob):
     npb = {int(P_): nrr for _, P_, _, nrr in _classes(prob)}
     for n, K in zip(prob.n, prob.K):
         P = _good(prob.s * int(n) + int(K) // 2, prob.s)
-        tot["fft_fsum"] += 8 * (npb[P] * Q3 + Q3)       # block partials in, frame sums out
+        tot["fft_fsum"] += 8 * (npb[P] * Q3 + Q3)       # block dot-product partials in, frame sums out
     for F_, P_, nch, _ in _classes(prob):
         HP_ = P_ // 2 + 1
-        tot["fft_acols"] += 8 * nch * P_ * HP_          # summed spectra of each frame chunk
-        tot["fft_fsum"] += 8 * (nch + 1) * P_ * HP_     # chunk spectra in, their sum out
+        # the class's summed adjoint spectrum leaves once (the frame-chunk partial
+        # spectra and their re-read are the implementation's, not the algorithm's)
+        tot["fft_acols"] += 8 * P_ * HP_
         tot["fft_arows"] += 8 * (P_ * HP_ + 2 * F_ * HP_) + 4 * F_ * F_
     return {k: float(v) for k, v in tot.items()}
 

@@ -218,6 +218,26 @@ enum {
 int starred_set_profiling(starred_plan *plan, int32_t enable);
 int starred_profile_read(starred_plan *plan, double *ms_out, int64_t *count_out);
 
+/* Sec. 2.3 and App. B: the starlet weights W by noise propagation (Monte Carlo).
+ * Deconvolution mode, after starred_set_frames. For n_real realizations, white
+ * noise is drawn on the fine grid of frame `frame` (side s n_f) with the variance
+ * of its data pixel replicated over each s x s block (C_up: sigma2_data, device,
+ * n_f^2 values, > 0; the caller chooses the map, e.g. the frame's own or that of
+ * the co-added data), weighted by C_up^-1, correlated with the frame's bound
+ * kernel (S^T), placed in the frame's window of the N x N grid and transformed
+ * (Phi^T). W_out (device) receives the standard deviation over the realizations
+ * (mean removed, divided by n_real) of every coefficient, J x N x N
+ * (per_pixel = 1), or of all coefficients of each scale, J values (per_pixel = 0);
+ * these are the W inputs of set_frames with w_pixel_stride 1 or 0.
+ * normals: device array [n_real][(s n_f)^2] of standard normal draws, or NULL to
+ * draw them on the device: draw k of realization r is the Box-Muller value of
+ * Philox4x32-10 with counter (k/4, r, 0, 0) and key (seed low, seed high), words
+ * mapped to ((w >> 8) + 1/2) / 2^24, pairs (0,1) and (2,3), cosine then sine.
+ * n_real >= 2. The plan allocates its working memory on the first call (kept
+ * until destroy); the call synchronises the plan's stream. */
+int starred_noise_weights(starred_plan *plan, int32_t frame, const float *sigma2_data, int32_t n_real,
+                          uint64_t seed, const float *normals, int32_t per_pixel, float *W_out);
+
 /* Measurement aid: the device time of one stage's launches alone. Runs one
  * loss+gradient evaluation at params (device, num_params floats) so that every
  * buffer the stage reads holds real data, then launches the stage reps times back

@@ -42,8 +42,11 @@ def lib():
         for name in ["ora_render_scene", "ora_conv_sub", "ora_conv_sub_adj", "ora_starlet_fwd",
                      "ora_starlet_adj", "ora_loss_grad", "ora_forward_model", "ora_moffat",
                      "ora_psf_render", "ora_psf_model", "ora_psf_loss_grad", "ora_adam_step",
-                     "ora_noise_variance"]:
+                     "ora_noise_variance", "ora_noise_weights_mc"]:
             getattr(_lib, name).restype = None
+        _lib.ora_philox4x32_10.restype = None
+        _lib.ora_normal.restype = ctypes.c_double
+        _lib.ora_normal.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
         _lib.ora_num_threads.restype = ctypes.c_int
         _lib.ora_frame_offsets.restype = ctypes.c_int
         del v
@@ -194,6 +197,31 @@ def noise_variance(n1, K1, s, N, J, kernel1, sigma2_data):
     kernel1, sigma2_data = _f64(kernel1), _f64(sigma2_data)
     out = np.zeros(J * N * N)
     lib().ora_noise_variance(n1, K1, s, N, J, _d(kernel1), _d(sigma2_data), _d(out))
+    return out
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 of a 4-word counter and a 2-word key (four uint32 words)."""
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    out = (ctypes.c_uint32 * 4)()
+    lib().ora_philox4x32_10(c, k, out)
+    return [int(x) for x in out]
+
+
+def normal(seed, real, idx):
+    """Standard normal draw idx of realization real (Philox4x32-10 + Box-Muller)."""
+    return float(lib().ora_normal(ctypes.c_uint64(seed), ctypes.c_uint32(real), ctypes.c_uint32(idx)))
+
+
+def noise_weights_mc(n1, K1, s, N, J, kernel1, sigma2_data, R, normals=None, seed=0, per_pixel=True):
+    """Monte Carlo W (Sec. 2.3): J x N x N (per_pixel) or J values."""
+    kernel1, sigma2_data = _f64(kernel1), _f64(sigma2_data)
+    out = np.zeros(J * N * N if per_pixel else J)
+    nz = None if normals is None else _f64(normals)
+    lib().ora_noise_weights_mc(n1, K1, s, N, J, _d(kernel1), _d(sigma2_data), int(R),
+                               _d(nz) if nz is not None else None, ctypes.c_uint64(seed),
+                               1 if per_pixel else 0, _d(out))
     return out
 
 

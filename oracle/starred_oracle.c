@@ -33,6 +33,7 @@
  *     centre floor(N/2) rotated by phi.
  */
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -712,6 +713,113 @@ void ora_noise_variance(int n1, int K1, int s, int N, int J, const double *kerne
             for (long q = 0; q < J * NN; ++q) var_out[q] += co[q] * co[q] / s2;
         }
     free(e);
+    free(g);
+    free(img);
+    free(co);
+}
+
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of the
+ * multiply-hi/lo bijection on a 4-word counter with a 2-word key, the key
+ * bumped by the Weyl constants between rounds. */
+void ora_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* Standard normal draw number `idx` of realization `real` (the draw convention
+ * shared with the device generator): Philox4x32-10 of counter (idx/4, real, 0, 0)
+ * and key (seed low, seed high) gives four words; each is mapped to
+ * u = (word >> 8) + 1/2) / 2^24 in (0, 1), and Box-Muller turns the pairs
+ * (u0, u1), (u2, u3) into (r cos, r sin) with r = sqrt(-2 ln u_first) and angle
+ * 2 pi u_second. */
+double ora_normal(uint64_t seed, uint32_t real, uint32_t idx)
+{
+    const uint32_t ctr[4] = {idx / 4u, real, 0u, 0u};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    ora_philox4x32_10(ctr, key, w);
+    const int pair = (int)(idx % 4u) / 2, second = (int)(idx % 2u);
+    const double u1 = ((double)(w[2 * pair] >> 8) + 0.5) / 16777216.0;
+    const double u2 = ((double)(w[2 * pair + 1] >> 8) + 0.5) / 16777216.0;
+    const double r = sqrt(-2.0 * log(u1));
+    const double ang = 6.283185307179586476925286766559 * u2;  /* 2 pi */
+    return second ? r * sin(ang) : r * cos(ang);
+}
+
+/* Monte Carlo estimate of W (Sec. 2.3): for each realization r < R the white
+ * noise delta_d on frame f's fine window (variance sigma2_data of the data pixel
+ * replicated over its s x s block) is weighted by C_up^-1, correlated with the
+ * frame's kernel (S^T), placed in the window of h and transformed; W is the
+ * standard deviation (mean removed, divided by R) of each coefficient over the
+ * realizations (per_pixel: J x N x N) or of all coefficients of each scale over
+ * the realizations (J values). normals: R x F^2 standard normal draws, or NULL
+ * for the Philox draws of ora_normal(seed, r, pixel). */
+void ora_noise_weights_mc(int n1, int K1, int s, int N, int J, const double *kernel1, const double *sigma2_data,
+                          int R, const double *normals, uint64_t seed, int per_pixel, double *W_out)
+{
+    int F = s * n1, o = (N - F) / 2;
+    long NN = (long)N * N;
+    double *s1 = (double *)calloc((size_t)J * NN, sizeof(double));
+    double *s2 = (double *)calloc((size_t)J * NN, sizeof(double));
+    double *dl = (double *)malloc(sizeof(double) * F * F);
+    double *g = (double *)malloc(sizeof(double) * F * F);
+    double *img = (double *)calloc(NN, sizeof(double));
+    double *co = (double *)malloc(sizeof(double) * J * NN);
+    for (int r = 0; r < R; ++r) {
+        for (int y = 0; y < F; ++y)
+            for (int x = 0; x < F; ++x) {
+                const long i = (long)y * F + x;
+                const double z = normals ? normals[(long)r * F * F + i] : ora_normal(seed, (uint32_t)r, (uint32_t)i);
+                const double s2u = sigma2_data[(long)(y / s) * n1 + (x / s)];
+                dl[i] = sqrt(s2u) * z / s2u; /* C_up^-1 delta_d, delta_d = sigma_up z */
+            }
+        corr_same(dl, F, kernel1, K1, g);
+        for (int yy = 0; yy < F; ++yy)
+            for (int xx = 0; xx < F; ++xx) img[(long)(yy + o) * N + xx + o] = g[(long)yy * F + xx];
+        ora_starlet_fwd(N, J, img, co);
+        for (long q = 0; q < J * NN; ++q) {
+            s1[q] += co[q];
+            s2[q] += co[q] * co[q];
+        }
+    }
+    for (int j = 0; j < J; ++j) {
+        if (per_pixel) {
+            for (long q = 0; q < NN; ++q) {
+                const double m = s1[j * NN + q] / R, v = s2[j * NN + q] / R - m * m;
+                W_out[j * NN + q] = sqrt(v > 0.0 ? v : 0.0);
+            }
+        } else {
+            double a = 0.0, b = 0.0;
+            for (long q = 0; q < NN; ++q) {
+                a += s1[j * NN + q];
+                b += s2[j * NN + q];
+            }
+            const double cnt = (double)R * (double)NN, m = a / cnt, v = b / cnt - m * m;
+            W_out[j] = sqrt(v > 0.0 ? v : 0.0);
+        }
+    }
+    free(s1);
+    free(s2);
+    free(dl);
     free(g);
     free(img);
     free(co);

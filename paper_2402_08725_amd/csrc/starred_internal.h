@@ -110,6 +110,8 @@ int starlet_l1_slots(int N, int J);
 hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, float *coeffs,
                               float *z, const float *W, int w_stride, float lam, float *c_a,
                               float *c_b, float *tmp, double *part_l1, int *n_l1);
+hipError_t launch_starlet_fwd_batch(hipStream_t st, int N, int J, int B, const float *img, float *coeffs,
+                                    float *c_a, float *c_b, const float *wzero);
 hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, float *out,
                               float *v_a, float *v_b, float *tmp);
 
@@ -130,6 +132,20 @@ hipError_t launch_plain_frame_ops(hipStream_t st, int op, const FrameDev *fr, in
                                   double *part);
 hipError_t launch_frame_sums_one(hipStream_t st, const FrameDev *fr, int E, int i, int N, int M, float sigma,
                                  const float *params, const float *g, double *fsum);
+
+// noise propagation (starred_noise.hip)
+// delta[b][y][x] = z / sigma_up(y, x), z = normals[r0 + b] or the device Philox draws
+hipError_t launch_noise_draw(hipStream_t st, int B, int nb, int r0, int n, int s, const float *sigma2_data,
+                             const float *normals, unsigned long long seed, float *delta);
+// img[b] = zero N x N with g[b] (F x F) at offset o
+hipError_t launch_noise_embed(hipStream_t st, int B, int F, int N, int o, const float *g, float *img);
+// s1 += sum_b c, s2 += sum_b c^2 over the first nb of B coefficient sets (each count floats)
+hipError_t launch_noise_moments(hipStream_t st, int nb, long long count, const float *coeffs, double *s1,
+                                double *s2);
+// W from the moments of R realizations: per pixel (count = J N^2) or per scale (J values)
+hipError_t launch_noise_finish(hipStream_t st, int J, long long NN, int R, int per_pixel, const double *s1,
+                               const double *s2, float *W);
+hipError_t launch_fill_d(hipStream_t st, double *p, long long n);
 
 // PSF mode (starred_psf.hip)
 hipError_t launch_psf_render(hipStream_t st, int N, const float *params, float *s_out);

@@ -554,6 +554,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
     const float *__restrict__ prior, AdamDev adam)
 {
     const long long NN = (long long)N * N;
+    const int stride = 1 + 3 * M;
+    auto fs = [&](long long i, int q) -> double { return fsum[i * stride + q]; };
     // step mode: the Adam update of every parameter follows its gradient here
     float bc1 = 1.f, bc2 = 1.f;
     if (adam.params) {
@@ -585,7 +587,6 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
     __shared__ double sums[2];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     constexpr int NW = kFinThreads / 64;
-    const int stride = 1 + 3 * M;
     const float *pa = params + NN + E;
     const int nred = 2 + (grad ? 2 * M : 0);
     for (int r = wv; r < nred; r += NW) {
@@ -598,7 +599,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
             // dL/dc_k = sum_i a_ik <g_i, dr_k/dc>
             const int q = r - 2, k = q >> 1, axis = q & 1;
             for (int i = lane; i < E; i += 64)
-                acc += (double)pa[(long long)i * M + k] * fsum[(long long)i * stride + 1 + (1 + axis) * M + k];
+                acc += (double)pa[(long long)i * M + k] * fs(i, 1 + (1 + axis) * M + k);
         }
         #pragma unroll
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -621,12 +622,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
             for (int q = gcsr_off[i]; q < gcsr_off[i + 1]; ++q) acc += gpart[gcsr_item[q]];
             gG[i] = (float)acc;
         } else {
-            gG[i] = (float)fsum[(long long)i * stride];
+            gG[i] = (float)fs(i, 0);
         }
     }
     for (long long e = threadIdx.x; e < (long long)E * M; e += kFinThreads) {
         const long long i = e / M, k = e - i * M;
-        ga[e] = (float)fsum[i * stride + 1 + k];
+        ga[e] = (float)fs(i, 1 + (int)k);
     }
     if (!adam.params) return;
     // Gamma, a and c after their gradients (written above by this block) are final;
@@ -682,10 +683,14 @@ static_assert(kStarTile * kStarTile == kStarThreads, "one output pixel per threa
 __global__ __launch_bounds__(kStarThreads) void k_star_level(
     const float *__restrict__ cj, float *__restrict__ cnext, float *__restrict__ coeffs, float *__restrict__ z,
     const float *__restrict__ W, int w_stride, float lam, int N, int d, int j, int last,
-    double *__restrict__ part_l1)
+    double *__restrict__ part_l1, long long img_stride, long long co_stride)
 {
     extern __shared__ float tmp[];  // (kStarTile + 4d) rows x kStarTile
     __shared__ double red[kStarThreads / 64];
+    // a batch of images along blockIdx.z (the transform alone: no z, no L1)
+    cj += blockIdx.z * img_stride;
+    cnext += blockIdx.z * img_stride;
+    if (coeffs) coeffs += blockIdx.z * co_stride;
     const int x0 = blockIdx.x * kStarTile, y0 = blockIdx.y * kStarTile;
     const int R = kStarTile + 4 * d, vy0 = y0 - 2 * d;
     const int vmax = min(y0 + kStarTile, N) - 1 + 2 * d;  // last virtual row a tap reaches
@@ -773,7 +778,7 @@ hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, fl
         const size_t lds = sizeof(float) * (size_t)(kStarTile + 4 * d) * kStarTile;
         hipLaunchKernelGGL(k_star_level, dim3(nt, nt), dim3(kStarThreads), lds, st, cur, nxt, coeffs, z, W,
                            w_stride, lam, N, d, j, (int)(j == J - 2),
-                           part_l1 ? part_l1 + (long long)j * nt * nt : nullptr);
+                           part_l1 ? part_l1 + (long long)j * nt * nt : nullptr, 0LL, 0LL);
         cur = nxt;
     }
     if (n_l1) *n_l1 = (J - 1) * nt * nt;
@@ -857,6 +862,25 @@ __global__ void k_copy(const float *__restrict__ a, float *__restrict__ b, long 
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = a[i];
+}
+
+// Coefficients of B images (img [B][N][N] -> coeffs [B][J][N][N]); c_a and c_b
+// hold B images each. J = 1 is not handled here (the coefficients are the image).
+hipError_t launch_starlet_fwd_batch(hipStream_t st, int N, int J, int B, const float *img, float *coeffs,
+                                    float *c_a, float *c_b, const float *wzero)
+{
+    const long long NN = (long long)N * N;
+    const int nt = star_tiles(N);
+    const float *cur = img;
+    for (int j = 0; j < J - 1; ++j) {
+        float *nxt = (j % 2 == 0) ? c_a : c_b;
+        const int d = 1 << j;
+        const size_t lds = sizeof(float) * (size_t)(kStarTile + 4 * d) * kStarTile;
+        hipLaunchKernelGGL(k_star_level, dim3(nt, nt, B), dim3(kStarThreads), lds, st, cur, nxt, coeffs,
+                           nullptr, wzero, 0, 0.f, N, d, j, (int)(j == J - 2), nullptr, NN, (long long)J * NN);
+        cur = nxt;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, float *out,

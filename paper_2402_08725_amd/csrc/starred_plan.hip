@@ -37,6 +37,8 @@ int fail_hip(hipError_t e, const char *where)
 
 // s_sleep periods of the idle lead-in that stage timing puts before each call
 constexpr int kProfIdleIters = 300;
+// noise propagation: realizations per batch
+constexpr int kNoiseBatch = 32;
 
 #define HIP_TRY(expr)                                     \
     do {                                                  \
@@ -84,6 +86,13 @@ struct starred_plan {
     float *d_wzero = nullptr;
     float *d_hpart = nullptr;
     std::vector<void *> owned;
+    // noise propagation: an s = 1 plan applying S_f^T to a batch of noise fields
+    starred_plan *noise_aux = nullptr;
+    int noise_frame = -1, noise_B = 0;
+    float *nz_kern = nullptr, *nz_zero = nullptr, *nz_one = nullptr, *nz_w = nullptr;
+    float *nz_delta = nullptr, *nz_g = nullptr, *nz_img = nullptr, *nz_ca = nullptr, *nz_cb = nullptr;
+    float *nz_coef = nullptr;
+    double *nz_s1 = nullptr, *nz_s2 = nullptr;
 
     // FFT path
     bool fft_ready = false;
@@ -179,7 +188,8 @@ struct starred_plan {
         return STARRED_OK;
     }
 
-    ~starred_plan()
+    ~starred_plan();
+    void destroy_members()
     {
         drop_graphs();
         if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -745,6 +755,12 @@ int starred_plan_create(const starred_desc *desc, void *stream, starred_plan **p
     return STARRED_OK;
 }
 
+starred_plan::~starred_plan()
+{
+    if (noise_aux) (void)starred_plan_destroy(noise_aux);
+    destroy_members();
+}
+
 int starred_plan_destroy(starred_plan *p)
 {
     if (!p) return fail(STARRED_EINVAL, "plan is NULL");
@@ -1280,6 +1296,86 @@ int starred_set_graph_mode(starred_plan *p, int32_t enable)
     if (enable && !p->st) return fail(STARRED_EUNSUPPORTED, "graph capture needs a non-default stream");
     if (!enable) p->drop_graphs();
     p->graph_mode = enable != 0;
+    return STARRED_OK;
+}
+
+int starred_noise_weights(starred_plan *p, int32_t frame, const float *sigma2_data, int32_t n_real, uint64_t seed,
+                          const float *normals, int32_t per_pixel, float *W_out)
+{
+    if (!p || !sigma2_data || !W_out) return fail(STARRED_EINVAL, "NULL argument");
+    if (p->mode != STARRED_DECONV) return fail(STARRED_EUNSUPPORTED, "noise propagation needs deconvolution mode");
+    if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
+    if (frame < 0 || frame >= p->E) return fail(STARRED_EINVAL, "frame out of range");
+    if (n_real < 2) return fail(STARRED_EINVAL, "n_real must be >= 2");
+    const int n = p->n[frame], K = p->K[frame], s = p->s, F = s * n, N = p->N, J = p->J;
+    const int o = (N - F) / 2;
+    const long long FF = (long long)F * F, NN = (long long)N * N;
+    const int B = std::min(n_real, kNoiseBatch);
+    if (!p->noise_aux || p->noise_frame != frame || p->noise_B < B) {
+        if (p->noise_aux) {
+            (void)starred_plan_destroy(p->noise_aux);
+            p->noise_aux = nullptr;
+        }
+        // S_f^T on the fine grid = the adjoint of an s = 1 plan with B copies of the frame
+        std::vector<int32_t> sides(B, F), ks(B, K);
+        starred_desc d{};
+        d.mode = STARRED_DECONV;
+        d.n_frames = B;
+        d.side_host = sides.data();
+        d.ksize_host = ks.data();
+        d.subsample = 1;
+        d.grid_side = N;
+        d.n_sources = 0;
+        d.n_scales = J;
+        d.w_pixel_stride = 0;
+        d.conv_algo = STARRED_CONV_FFT;
+        d.lambda = 0.0;
+        d.gauss_fwhm = p->fwhm;
+        int rc = starred_plan_create(&d, p->st, &p->noise_aux);
+        if (rc) return rc;
+        p->noise_frame = frame;
+        p->noise_B = B;
+        const long long kk = (long long)K * K;
+        if ((rc = p->alloc(&p->nz_kern, (size_t)B * kk))) return rc;
+        if ((rc = p->alloc(&p->nz_zero, (size_t)B * FF))) return rc;
+        if ((rc = p->alloc(&p->nz_one, (size_t)B * FF))) return rc;
+        if ((rc = p->alloc(&p->nz_w, (size_t)J))) return rc;
+        if ((rc = p->alloc(&p->nz_delta, (size_t)B * FF))) return rc;
+        if ((rc = p->alloc(&p->nz_g, (size_t)B * FF))) return rc;
+        if ((rc = p->alloc(&p->nz_img, (size_t)B * NN))) return rc;
+        if ((rc = p->alloc(&p->nz_ca, (size_t)B * NN))) return rc;
+        if ((rc = p->alloc(&p->nz_cb, (size_t)B * NN))) return rc;
+        if ((rc = p->alloc(&p->nz_coef, (size_t)B * J * NN))) return rc;
+        if ((rc = p->alloc(&p->nz_s1, (size_t)J * NN))) return rc;
+        if ((rc = p->alloc(&p->nz_s2, (size_t)J * NN))) return rc;
+        const float *kf = p->psf_bound + p->fr[frame].kern_off;
+        for (int b = 0; b < B; ++b)
+            HIP_TRY(hipMemcpyAsync(p->nz_kern + b * kk, kf, sizeof(float) * kk, hipMemcpyDeviceToDevice, p->st));
+        HIP_TRY(launch_fill(p->st, p->nz_zero, (long long)B * FF, 0.f));
+        HIP_TRY(launch_fill(p->st, p->nz_one, (long long)B * FF, 1.f));
+        HIP_TRY(launch_fill(p->st, p->nz_w, J, 0.f));
+        rc = starred_set_frames(p->noise_aux, p->nz_zero, p->nz_one, p->nz_kern, p->nz_w);
+        if (rc) return rc;
+    }
+    HIP_TRY(launch_fill_d(p->st, p->nz_s1, (long long)J * NN));
+    HIP_TRY(launch_fill_d(p->st, p->nz_s2, (long long)J * NN));
+    for (int r0 = 0; r0 < n_real; r0 += B) {
+        const int nb = std::min(B, n_real - r0);
+        HIP_TRY(launch_noise_draw(p->st, B, nb, r0, n, s, sigma2_data, normals, (unsigned long long)seed,
+                                  p->nz_delta));
+        int rc = starred_convolve_subsample_adj(p->noise_aux, p->nz_delta, p->nz_g);
+        if (rc) return rc;
+        HIP_TRY(launch_noise_embed(p->st, B, F, N, o, p->nz_g, p->nz_img));
+        if (J == 1) {
+            HIP_TRY(hipMemcpyAsync(p->nz_coef, p->nz_img, sizeof(float) * B * NN, hipMemcpyDeviceToDevice, p->st));
+        } else {
+            HIP_TRY(launch_starlet_fwd_batch(p->st, N, J, nb, p->nz_img, p->nz_coef, p->nz_ca, p->nz_cb,
+                                             p->d_wzero));
+        }
+        HIP_TRY(launch_noise_moments(p->st, nb, (long long)J * NN, p->nz_coef, p->nz_s1, p->nz_s2));
+    }
+    HIP_TRY(launch_noise_finish(p->st, J, NN, n_real, per_pixel, p->nz_s1, p->nz_s2, W_out));
+    HIP_TRY(hipStreamSynchronize(p->st));
     return STARRED_OK;
 }
 

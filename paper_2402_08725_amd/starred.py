@@ -85,6 +85,7 @@ def lib():
         L.starred_loss_grad_plain.argtypes = [vp, vp, vp, vp]
         L.starred_copy_probe.argtypes = [vp, vp, vp, ctypes.c_int64]
         L.starred_time_stage.argtypes = [vp, vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
+        L.starred_noise_weights.argtypes = [vp, i32, vp, i32, ctypes.c_uint64, vp, i32, vp]
         _lib = L
     return _lib
 
@@ -261,6 +262,16 @@ class Plan:
         _check(lib().starred_profile_read(self._h, ctypes.c_void_p(ms.ctypes.data),
                                           ctypes.c_void_p(cnt.ctypes.data)))
         return {name: {"ms": float(ms[i]), "count": int(cnt[i])} for i, name in enumerate(STAGES)}
+
+    def noise_weights(self, sigma2_data, n_real, seed=0, normals=None, per_pixel=True, frame=0):
+        """W by Monte Carlo noise propagation (Sec. 2.3): J x N x N (per_pixel) or J values."""
+        sig = _f32(sigma2_data, self.device)
+        nz = _f32(normals, self.device) if normals is not None else None
+        out = torch.empty(self.J * self.N * self.N if per_pixel else self.J, dtype=torch.float32,
+                          device=self.device)
+        self._call(lib().starred_noise_weights, ctypes.c_int32(frame), _ptr(sig), ctypes.c_int32(int(n_real)),
+                   ctypes.c_uint64(int(seed)), _ptr(nz), ctypes.c_int32(1 if per_pixel else 0), _ptr(out))
+        return out
 
     def time_stage(self, params, stage: str, reps: int = 50) -> float:
         """Average device milliseconds of one stage's launches run back to back."""

@@ -156,8 +156,8 @@ def test_stage_timing_leaves_results_unchanged(algo):
     plan = _plan(prob, d, w, algo=algo)
     p = torch.as_tensor(synth.eval_point(prob, "near", rng), dtype=torch.float32, device="cuda")
     l0, g0 = plan.loss_grad(p)
-    own = (["spectra", "fft_fused", "fft_spec", "fft_mcols", "fft_mrows", "fft_rcols", "fft_acols", "fft_fsum",
-            "fft_arows", "starlet"] if algo == 2 else ["render", "conv_fwd", "conv_adj", "grad_sums", "starlet"])
+    own = (["spectra", "fft_fused", "fft_spec", "fft_mcols", "fft_mrows", "fft_rcols", "fft_acols",
+            "fft_fsum", "fft_arows", "starlet"] if algo == 2 else ["render", "conv_fwd", "conv_adj", "grad_sums", "starlet"])
     for stage in own:
         ms = plan.time_stage(p, stage, reps=3)
         _say(f"{ALGO_ID[algo]} {stage}: {ms * 1e3:.1f} us")
@@ -575,3 +575,84 @@ def test_cfg4_full_size_sampled_frames_and_properties(algo):
     an = float(np.dot(g, pp - pm))
     _say(f"cfg4 full: directional difference {fd:.8e} vs gradient {an:.8e}")
     assert abs(fd - an) <= 1e-4 * abs(an)
+
+
+# --------------------------------------------------------------------------- #
+# Noise propagation to the starlet coefficients (Sec. 2.3, App. B)             #
+# --------------------------------------------------------------------------- #
+
+def _noise_case():
+    # cfg1 shapes: frame 0 of 32^2 data, s = 2, 64^2 kernel, 64^2 grid, J = 3
+    prob = synth.make_deconv(1)
+    d, w, rng = _data(prob, seed=31)
+    plan = _plan(prob, d, w, algo=2)
+    n0, K0 = int(prob.n[0]), int(prob.K[0])
+    k0 = np.asarray(prob.kernels[:K0 * K0], np.float64)
+    sig2 = 1.0 / np.asarray(w[:n0 * n0], np.float64)  # the frame's own noise map
+    return prob, plan, n0, K0, k0, sig2
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("per_pixel", [True, False], ids=["per_pixel", "per_scale"])
+def test_noise_weights_with_given_draws_match_oracle(per_pixel):
+    """Caller-supplied normal draws: the device pipeline (weighting, S^T through an s = 1
+    FFT plan, embedding, batched starlet, FP64 moments) against the oracle's Monte Carlo
+    on the same draws; 40 realizations = one full and one partial batch."""
+    prob, plan, n0, K0, k0, sig2 = _noise_case()
+    R = 40
+    F = prob.s * n0
+    z = np.random.default_rng(32).standard_normal((R, F * F)).astype(np.float32)
+    got = plan.noise_weights(sig2, R, normals=z, per_pixel=per_pixel).cpu().numpy()
+    ref = ora.noise_weights_mc(n0, K0, prob.s, prob.N, prob.J, k0, sig2, R, normals=z.astype(np.float64),
+                               per_pixel=per_pixel)
+    err = _rel(got, ref)
+    _say(f"noise W given draws ({'pixel' if per_pixel else 'scale'}): rel err {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_noise_weights_device_philox_draws_match_oracle_generator():
+    """Device-drawn noise (Philox4x32-10 + Box-Muller on the GPU) against the oracle's
+    own implementation of the same generator: the same draws, hence the same W."""
+    prob, plan, n0, K0, k0, sig2 = _noise_case()
+    R, seed = 40, 0xC0FFEE1234
+    got = plan.noise_weights(sig2, R, seed=seed).cpu().numpy()
+    ref = ora.noise_weights_mc(n0, K0, prob.s, prob.N, prob.J, k0, sig2, R, seed=seed, per_pixel=True)
+    err = _rel(got, ref)
+    _say(f"noise W device Philox: rel err {err:.2e}")
+    assert err <= 1e-4
+    again = plan.noise_weights(sig2, R, seed=seed).cpu().numpy()
+    assert np.array_equal(got, again)
+    other = plan.noise_weights(sig2, R, seed=seed + 1).cpu().numpy()
+    assert not np.array_equal(got, other)
+
+
+def test_noise_weights_converge_to_exact_variance():
+    """Many device realizations against the exact variance of the propagated noise
+    (sum over fine pixels of squared impulse responses): median relative error of W^2
+    within 4 standard errors of a variance estimate from R draws."""
+    st = _st()
+    prob = synth.make_small_deconv(107, 2, [12, 12], [9, 9], 2, 32, 1, 4)
+    d, w, rng = _data(prob, seed=33)
+    plan = _plan(prob, d, w, algo=2)
+    n0, K0 = int(prob.n[0]), int(prob.K[0])
+    k0 = np.asarray(prob.kernels[:K0 * K0], np.float64)
+    sig2 = np.random.default_rng(34).uniform(1.0, 4.0, n0 * n0)
+    R = 4000
+    Wd = plan.noise_weights(sig2, R, seed=7).cpu().numpy().reshape(prob.J, prob.N, prob.N).astype(np.float64)
+    var = ora.noise_variance(n0, K0, prob.s, prob.N, prob.J, k0, sig2).reshape(prob.J, prob.N, prob.N)
+    inside = var > 1e-10 * var.max()
+    rel = np.abs(Wd[inside] ** 2 - var[inside]) / var[inside]
+    _say(f"noise W vs exact variance: median rel {np.median(rel):.3e} (bound {4 * np.sqrt(2 / R):.3e})")
+    assert np.median(rel) < 4 * np.sqrt(2.0 / R)
+
+
+def test_noise_weights_argument_errors():
+    st = _st()
+    prob, plan, n0, K0, k0, sig2 = _noise_case()
+    with pytest.raises(st.StarredError):
+        plan.noise_weights(sig2, 1)
+    with pytest.raises(st.StarredError):
+        plan.noise_weights(sig2, 10, frame=prob.E)

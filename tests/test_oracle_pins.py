@@ -503,3 +503,94 @@ def test_noise_variance_matches_monte_carlo():
     inside = var > 1e-12 * var.max()
     rel = np.abs(mc[inside] - var[inside]) / var[inside]
     assert np.median(rel) < 4 * np.sqrt(2.0 / R)
+
+
+def test_philox_known_answers():
+    """Philox4x32-10 against the published known-answer vectors of its authors'
+    reference implementation (zero, all-ones and pi-digit counters and keys)."""
+    assert ora.philox4x32_10([0, 0, 0, 0], [0, 0]) == [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]
+    assert ora.philox4x32_10([0xffffffff] * 4, [0xffffffff] * 2) == [0x408f276d, 0x41c83b0e, 0xa20bc7c6,
+                                                                    0x6d5451fd]
+    assert ora.philox4x32_10([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344], [0xa4093822, 0x299f31d0]) == \
+        [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]
+
+
+def test_normal_draws_follow_box_muller_of_philox_words():
+    """The draw convention: words of Philox(counter (i/4, r, 0, 0), key (seed lo, seed hi))
+    mapped to (w >> 8 + 1/2)/2^24, paired (0,1), (2,3) by Box-Muller; and the draws are
+    standard normal (moments within 5 standard errors over 40000 draws)."""
+    seed = 0x1234567890AB
+    w = ora.philox4x32_10([3, 7, 0, 0], [seed & 0xFFFFFFFF, seed >> 32])
+    u = [((x >> 8) + 0.5) / 2.0 ** 24 for x in w]
+    r0, r1 = np.sqrt(-2 * np.log(u[0])), np.sqrt(-2 * np.log(u[2]))
+    want = [r0 * np.cos(2 * np.pi * u[1]), r0 * np.sin(2 * np.pi * u[1]),
+            r1 * np.cos(2 * np.pi * u[3]), r1 * np.sin(2 * np.pi * u[3])]
+    got = [ora.normal(seed, 7, 12 + k) for k in range(4)]
+    np.testing.assert_allclose(got, want, rtol=1e-14, atol=1e-14)
+    z = np.array([ora.normal(seed, r, i) for r in range(10) for i in range(4000)])
+    n = z.size
+    assert abs(z.mean()) < 5 / np.sqrt(n)
+    assert abs(z.var() - 1) < 5 * np.sqrt(2 / n)
+    assert abs((z ** 3).mean()) < 5 * np.sqrt(15 / n)
+    assert abs((z ** 4).mean() - 3) < 5 * np.sqrt(96 / n)
+
+
+def test_noise_weights_mc_given_draws_match_numpy_pipeline():
+    """The Monte Carlo W with caller draws against the same steps assembled from
+    scipy/numpy (correlate2d for S^T, scipy mirror filtering for the starlet)."""
+    n1, K1, s, J, N, R = 5, 4, 2, 3, 14, 6
+    rng = np.random.default_rng(21)
+    k = rng.uniform(0, 1, (K1, K1))
+    sig2 = rng.uniform(0.5, 3.0, n1 * n1)
+    F = s * n1
+    o = (N - F) // 2
+    z = rng.standard_normal((R, F * F))
+    got = ora.noise_weights_mc(n1, K1, s, N, J, k.ravel(), sig2, R, normals=z, per_pixel=True).reshape(J, N, N)
+    got_sc = ora.noise_weights_mc(n1, K1, s, N, J, k.ravel(), sig2, R, normals=z, per_pixel=False)
+    up = np.repeat(np.repeat(sig2.reshape(n1, n1), s, 0), s, 1)
+    # 'same' correlation with centre floor(K/2) for an even kernel: pad and slice
+    c = K1 // 2
+    co = np.zeros((R, J, N, N))
+    for r in range(R):
+        dl = z[r].reshape(F, F) * np.sqrt(up) / up
+        full = np.zeros((F, F))
+        for u in range(K1):
+            for v in range(K1):
+                sh = np.zeros((F, F))
+                dy, dx = u - c, v - c
+                ys, yd = (slice(dy, F), slice(0, F - dy)) if dy >= 0 else (slice(0, F + dy), slice(-dy, F))
+                xs, xd = (slice(dx, F), slice(0, F - dx)) if dx >= 0 else (slice(0, F + dx), slice(-dx, F))
+                sh[yd, xd] = dl[ys, xs]
+                full += k[u, v] * sh
+        img = np.zeros((N, N))
+        img[o:o + F, o:o + F] = full
+        cc = img
+        for j in range(J - 1):
+            cn = _h_smooth_scipy(cc, j)
+            co[r, j] = cc - cn
+            cc = cn
+        co[r, J - 1] = cc
+    ref = co.std(axis=0)
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-13)
+    ref_sc = np.array([co[:, j].std() for j in range(J)])
+    np.testing.assert_allclose(got_sc, ref_sc, rtol=1e-10)
+
+
+def test_noise_weights_mc_with_philox_draws_converge_to_exact_variance():
+    """Philox-drawn Monte Carlo W^2 against the exact variance (the sum over fine
+    pixels of the squared propagated impulse responses): median relative error within
+    4 standard errors of a variance estimate from R draws."""
+    n1, K1, s, J, N, R = 6, 5, 2, 3, 16, 3000
+    rng = np.random.default_rng(22)
+    k = rng.uniform(0, 1, (K1, K1))
+    k /= k.sum()
+    sig2 = rng.uniform(1.0, 4.0, n1 * n1)
+    var = ora.noise_variance(n1, K1, s, N, J, k.ravel(), sig2).reshape(J, N, N)
+    W = ora.noise_weights_mc(n1, K1, s, N, J, k.ravel(), sig2, R, seed=99, per_pixel=True).reshape(J, N, N)
+    inside = var > 1e-12 * var.max()
+    rel = np.abs(W[inside] ** 2 - var[inside]) / var[inside]
+    assert np.median(rel) < 4 * np.sqrt(2.0 / R)
+    Wsc = ora.noise_weights_mc(n1, K1, s, N, J, k.ravel(), sig2, R, seed=99, per_pixel=False)
+    # per scale: pooled second moment over the plane (the mean is zero in expectation)
+    for j in range(J):
+        assert abs(Wsc[j] ** 2 - var[j].mean()) / var[j].mean() < 6 * np.sqrt(2.0 / (R * 4))
