@@ -173,6 +173,23 @@ int starred_step(starred_plan *plan, float *params, float *m, float *v, int32_t 
  * timing reports one STARRED_STAGE_GRAPH interval per call. */
 int starred_set_graph_mode(starred_plan *plan, int32_t enable);
 
+/* Eq. 11, third term: lambda_pts ||W (.) Phi^T sum_k <a_k> r_k||_1 with <a_k> the
+ * mean over the epochs of a_ik and r_k rendered on the N x N grid of h. 0 (the
+ * default) leaves the term out. Deconvolution mode; lambda_pts >= 0. Its gradient
+ * reaches every a_ik (through <a_k>) and c_k. Drops captured graphs. */
+int starred_set_lambda_pts(starred_plan *plan, double lambda_pts);
+
+/* The image that term regularises: P_out (device, N x N) = sum_k <a_k> r_k at
+ * params (r_k within 8 fine pixels of c_k, as in the scene). */
+int starred_pts_image(starred_plan *plan, const float *params, float *P_out);
+
+/* App. C: the estimate of lambda_pts at params (device, num_params floats),
+ *   lambda (||W (.) Phi^T f||_1 - ||W (.) Phi^T h||_1) / sum_k <a_k> ||W (.) Phi^T r_k||_1,
+ * f = <Gamma> + h + sum_k <a_k> r_k the epoch average of the scene on the N x N grid,
+ * W the bound weights. Writes the value to *lambda_pts_out (host) and synchronises
+ * the plan's stream. Deconvolution mode with n_sources >= 1; set_frames first. */
+int starred_estimate_lambda_pts(starred_plan *plan, const float *params, double *lambda_pts_out);
+
 /* FFT algorithm, loss and gradient: frames whose Q x Q model and residual
  * spectra fit in LDS (Q = P/s, see the FFT notes of starred_plan_create) run the
  * forward of Eqs. 8 and 10 in one launch with a work group per frame; with

@@ -42,9 +42,10 @@ def lib():
         for name in ["ora_render_scene", "ora_conv_sub", "ora_conv_sub_adj", "ora_starlet_fwd",
                      "ora_starlet_adj", "ora_loss_grad", "ora_forward_model", "ora_moffat",
                      "ora_psf_render", "ora_psf_model", "ora_psf_loss_grad", "ora_adam_step",
-                     "ora_noise_variance", "ora_noise_weights_mc"]:
+                     "ora_noise_variance", "ora_noise_weights_mc", "ora_pts_term"]:
             getattr(_lib, name).restype = None
         _lib.ora_philox4x32_10.restype = None
+        _lib.ora_lambda_pts_estimate.restype = ctypes.c_double
         _lib.ora_normal.restype = ctypes.c_double
         _lib.ora_normal.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
         _lib.ora_num_threads.restype = ctypes.c_int
@@ -133,8 +134,10 @@ def forward_model(prob, params):
     return out
 
 
-def loss_grad(prob, data, invvar, params, want_grad=True, sgn_override=None, lam=None, W=None):
-    """Deconvolution loss (Eqs. 10-11) and gradient. Returns (loss[3], grad|None)."""
+def loss_grad(prob, data, invvar, params, want_grad=True, sgn_override=None, lam=None, W=None, lam_pts=0.0,
+              sgn_override_pts=None):
+    """Deconvolution loss (Eqs. 10-11, the point-source term when lam_pts != 0) and
+    gradient. Returns (loss[3], grad|None)."""
     frame_offsets(prob.n, prob.s, prob.N)
     n, K = _i32(prob.n), _i32(prob.K)
     data, invvar, params = _f64(data), _f64(invvar), _f64(params)
@@ -151,7 +154,34 @@ def loss_grad(prob, data, invvar, params, want_grad=True, sgn_override=None, lam
                         ctypes.c_double(prob.fwhm), _d(data), _d(invvar), _d(kernels), _d(Wv),
                         _d(params), _d(grad), _d(loss),
                         so.ctypes.data_as(_B) if so is not None else None)
+    if lam_pts:
+        sp = None if sgn_override_pts is None else np.ascontiguousarray(sgn_override_pts, dtype=np.int8)
+        lib().ora_pts_term(prob.E, prob.N, prob.M, prob.J, prob.w_stride, ctypes.c_double(lam_pts),
+                           ctypes.c_double(prob.fwhm), _d(Wv), _d(params), _d(grad), _d(loss),
+                           sp.ctypes.data_as(_B) if sp is not None else None)
     return loss, grad
+
+
+def pts_image(prob, params):
+    """P = sum_k <a_k> r_k on the N x N grid (Eq. 11, third term), via numpy."""
+    N, E, M = prob.N, prob.E, prob.M
+    p = _f64(params)
+    a = p[N * N + E:N * N + E + E * M].reshape(E, M).mean(axis=0)
+    c = p[N * N + E + E * M:].reshape(M, 2)
+    sig = sigma_from_fwhm(prob.fwhm)
+    Y, X = np.mgrid[0:N, 0:N].astype(np.float64)
+    img = np.zeros((N, N))
+    for k in range(M):
+        img += a[k] * np.exp(-((X - c[k, 0]) ** 2 + (Y - c[k, 1]) ** 2) / (2 * sig * sig)) / (2 * np.pi * sig * sig)
+    return img.ravel()
+
+
+def lambda_pts_estimate(prob, params, lam=None, W=None):
+    """App. C estimate of lambda_pts at params."""
+    Wv = _f64(prob.W if W is None else W)
+    return float(lib().ora_lambda_pts_estimate(prob.E, prob.N, prob.M, prob.J, prob.w_stride,
+                                               ctypes.c_double(prob.lam if lam is None else lam),
+                                               ctypes.c_double(prob.fwhm), _d(Wv), _d(_f64(params))))
 
 
 def moffat(N, eta, want_grad=False):

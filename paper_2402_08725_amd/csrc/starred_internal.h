@@ -93,7 +93,8 @@ struct AdamDev {
 
 struct ClassFft;
 // With classes (FFT path), the launch also writes dL/dh = prior + the classes'
-// window contributions hcls.
+// window contributions hcls. pts (3M, or null): the point-source prior's
+// additions to dL/da_ik (every i) and dL/dc_k.
 hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const double *part_chi,
                                  int n_l1, const double *part_l1, double lambda,
                                  const double *fsum, const float *params, int N,
@@ -101,7 +102,7 @@ hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const 
                                  const int *gcsr_item = nullptr, const double *gpart = nullptr,
                                  int *tick = nullptr, const ClassFft *classes = nullptr, int ncls = 0,
                                  const float *hcls = nullptr, const float *prior = nullptr,
-                                 const AdamDev &adam = AdamDev());
+                                 const AdamDev &adam = AdamDev(), const double *pts = nullptr);
 hipError_t launch_copy_probe(hipStream_t st, const float *src, float *dst, long long n);
 hipError_t launch_idle(hipStream_t st, int iters);
 
@@ -110,6 +111,18 @@ int starlet_l1_slots(int N, int J);
 hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, float *coeffs,
                               float *z, const float *W, int w_stride, float lam, float *c_a,
                               float *c_b, float *tmp, double *part_l1, int *n_l1);
+hipError_t launch_starlet_prior(hipStream_t st, int N, int J, int B, const float *img, float *z, const float *W,
+                                int w_stride, float lam0, float lam1, float *c_a, float *c_b, double *part_l1,
+                                int *n_l1);
+hipError_t launch_starlet_adj_batch(hipStream_t st, int N, int J, int B, const float *z, float *out, float *v_a,
+                                    float *v_b);
+hipError_t launch_pts_render(hipStream_t st, int N, int E, int M, float sigma, const float *params, float *h_out,
+                             float *P_out);
+hipError_t launch_pts_dots(hipStream_t st, int N, int E, int M, float sigma, const float *params, const float *q,
+                           double *pts);
+hipError_t launch_pts_images(hipStream_t st, int N, int E, int M, float sigma, const float *params, float *out);
+hipError_t launch_pts_sums(hipStream_t st, int B, int n, const double *part, int N, int E, int M, const float *params,
+                           double *out);
 hipError_t launch_starlet_fwd_batch(hipStream_t st, int N, int J, int B, const float *img, float *coeffs,
                                     float *c_a, float *c_b, const float *wzero);
 hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, float *out,

@@ -551,7 +551,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
     const float *__restrict__ params, int N, float *__restrict__ grad, double *__restrict__ loss,
     const int *__restrict__ gcsr_off, const int *__restrict__ gcsr_item, const double *__restrict__ gpart,
     int *__restrict__ tick, const ClassFft *__restrict__ classes, int ncls, const float *__restrict__ hcls,
-    const float *__restrict__ prior, AdamDev adam)
+    const float *__restrict__ prior, AdamDev adam, const double *__restrict__ pts)
 {
     const long long NN = (long long)N * N;
     const int stride = 1 + 3 * M;
@@ -605,7 +605,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
         if (lane == 0) {
             if (r < 2) sums[r] = acc;
-            else grad[NN + E + (long long)E * M + (r - 2)] = (float)acc;
+            else {
+                // plus the point-source prior's share (pts[3k+1+axis])
+                const int q = r - 2;
+                if (pts) acc += pts[3 * (q >> 1) + 1 + (q & 1)];
+                grad[NN + E + (long long)E * M + q] = (float)acc;
+            }
         }
     }
     __syncthreads();
@@ -627,7 +632,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
     }
     for (long long e = threadIdx.x; e < (long long)E * M; e += kFinThreads) {
         const long long i = e / M, k = e - i * M;
-        ga[e] = (float)fs(i, 1 + (int)k);
+        ga[e] = (float)(fs(i, 1 + (int)k) + (pts ? pts[3 * k] : 0.0));
     }
     if (!adam.params) return;
     // Gamma, a and c after their gradients (written above by this block) are final;
@@ -649,7 +654,7 @@ hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const 
                                  const double *fsum, const float *params, int N,
                                  float *grad, double *loss, const int *gcsr_off, const int *gcsr_item,
                                  const double *gpart, int *tick, const ClassFft *classes, int ncls,
-                                 const float *hcls, const float *prior, const AdamDev &adam)
+                                 const float *hcls, const float *prior, const AdamDev &adam, const double *pts)
 {
     const long long NN = (long long)N * N;
     const int hblocks = (classes && grad) ? (int)((NN + kFinThreads - 1) / kFinThreads) : 0;
@@ -657,7 +662,7 @@ hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const 
     if (adam.params && (!hblocks || !grad)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_finalize_small, dim3(1 + hblocks), dim3(kFinThreads), 0, st, E, M, n_chi, part_chi,
                        n_l1, part_l1, fsum, params, N, grad, loss, gcsr_off, gcsr_item, gpart, tick, classes, ncls,
-                       hcls, prior, adam);
+                       hcls, prior, adam, pts);
     return hipGetLastError();
 }
 
@@ -683,14 +688,18 @@ static_assert(kStarTile * kStarTile == kStarThreads, "one output pixel per threa
 __global__ __launch_bounds__(kStarThreads) void k_star_level(
     const float *__restrict__ cj, float *__restrict__ cnext, float *__restrict__ coeffs, float *__restrict__ z,
     const float *__restrict__ W, int w_stride, float lam, int N, int d, int j, int last,
-    double *__restrict__ part_l1, long long img_stride, long long co_stride)
+    double *__restrict__ part_l1, long long img_stride, long long co_stride, float lam1, long long l1_stride)
 {
     extern __shared__ float tmp[];  // (kStarTile + 4d) rows x kStarTile
     __shared__ double red[kStarThreads / 64];
-    // a batch of images along blockIdx.z (the transform alone: no z, no L1)
+    // a batch of images along blockIdx.z: image b's planes, subgradient and L1
+    // partials sit b strides further; image 1 takes the weight lam1
     cj += blockIdx.z * img_stride;
     cnext += blockIdx.z * img_stride;
     if (coeffs) coeffs += blockIdx.z * co_stride;
+    if (z) z += blockIdx.z * co_stride;
+    if (part_l1) part_l1 += blockIdx.z * l1_stride;
+    if (blockIdx.z == 1) lam = lam1;
     const int x0 = blockIdx.x * kStarTile, y0 = blockIdx.y * kStarTile;
     const int R = kStarTile + 4 * d, vy0 = y0 - 2 * d;
     const int vmax = min(y0 + kStarTile, N) - 1 + 2 * d;  // last virtual row a tap reaches
@@ -778,7 +787,7 @@ hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, fl
         const size_t lds = sizeof(float) * (size_t)(kStarTile + 4 * d) * kStarTile;
         hipLaunchKernelGGL(k_star_level, dim3(nt, nt), dim3(kStarThreads), lds, st, cur, nxt, coeffs, z, W,
                            w_stride, lam, N, d, j, (int)(j == J - 2),
-                           part_l1 ? part_l1 + (long long)j * nt * nt : nullptr, 0LL, 0LL);
+                           part_l1 ? part_l1 + (long long)j * nt * nt : nullptr, 0LL, 0LL, lam, 0LL);
         cur = nxt;
     }
     if (n_l1) *n_l1 = (J - 1) * nt * nt;
@@ -820,9 +829,15 @@ __device__ __forceinline__ float mirrorT_gather(const float *__restrict__ u, lon
 // transpose reaches (kept in LDS), then vout = z_j + R_j^T of it.
 __global__ __launch_bounds__(kStarThreads) void k_star_levelT(const float *__restrict__ v,
                                                               const float *__restrict__ zj,
-                                                              float *__restrict__ vout, int N, int d)
+                                                              float *__restrict__ vout, int N, int d,
+                                                              long long v_stride, long long out_stride,
+                                                              long long z_stride)
 {
     extern __shared__ float tmp[];  // kStarTile rows x (kStarTile + 4d) columns
+    // a batch of images along blockIdx.z
+    v += blockIdx.z * v_stride;
+    vout += blockIdx.z * out_stride;
+    zj += blockIdx.z * z_stride;
     const int x0 = blockIdx.x * kStarTile, y0 = blockIdx.y * kStarTile;
     const int C = kStarTile + 4 * d, cx0 = x0 - 2 * d;
     for (int e = threadIdx.x; e < kStarTile * C; e += kStarThreads) {
@@ -864,6 +879,42 @@ __global__ void k_copy(const float *__restrict__ a, float *__restrict__ b, long 
     if (i < n) b[i] = a[i];
 }
 
+// The prior of B (1 or 2) images img [B][N][N] at once: subgradients z [B][J][N][N]
+// and L1 partials (image b's at part_l1 + b (J-1) tiles), image 0 weighted by
+// lam0 and image 1 by lam1; c_a and c_b hold B images each.
+hipError_t launch_starlet_prior(hipStream_t st, int N, int J, int B, const float *img, float *z, const float *W,
+                                int w_stride, float lam0, float lam1, float *c_a, float *c_b, double *part_l1,
+                                int *n_l1)
+{
+    const long long NN = (long long)N * N;
+    if (J == 1) {
+        int nl = 0;
+        for (int b = 0; b < B; ++b) {
+            hipError_t e = launch_starlet_fwd(st, N, J, img + b * NN, nullptr, z ? z + b * NN : nullptr, W, w_stride,
+                                              b ? lam1 : lam0, c_a, c_b, nullptr, part_l1 ? part_l1 + nl : nullptr,
+                                              n_l1);
+            if (e != hipSuccess) return e;
+            nl += n_l1 ? *n_l1 : 0;
+        }
+        if (n_l1) *n_l1 = nl;
+        return hipSuccess;
+    }
+    const int nt = star_tiles(N);
+    const long long l1s = (long long)(J - 1) * nt * nt;
+    const float *cur = img;
+    for (int j = 0; j < J - 1; ++j) {
+        float *nxt = (j % 2 == 0) ? c_a : c_b;
+        const int d = 1 << j;
+        const size_t lds = sizeof(float) * (size_t)(kStarTile + 4 * d) * kStarTile;
+        hipLaunchKernelGGL(k_star_level, dim3(nt, nt, B), dim3(kStarThreads), lds, st, cur, nxt, nullptr, z, W,
+                           w_stride, lam0, N, d, j, (int)(j == J - 2),
+                           part_l1 ? part_l1 + (long long)j * nt * nt : nullptr, NN, (long long)J * NN, lam1, l1s);
+        cur = nxt;
+    }
+    if (n_l1) *n_l1 = (int)(B * l1s);
+    return hipGetLastError();
+}
+
 // Coefficients of B images (img [B][N][N] -> coeffs [B][J][N][N]); c_a and c_b
 // hold B images each. J = 1 is not handled here (the coefficients are the image).
 hipError_t launch_starlet_fwd_batch(hipStream_t st, int N, int J, int B, const float *img, float *coeffs,
@@ -877,7 +928,8 @@ hipError_t launch_starlet_fwd_batch(hipStream_t st, int N, int J, int B, const f
         const int d = 1 << j;
         const size_t lds = sizeof(float) * (size_t)(kStarTile + 4 * d) * kStarTile;
         hipLaunchKernelGGL(k_star_level, dim3(nt, nt, B), dim3(kStarThreads), lds, st, cur, nxt, coeffs,
-                           nullptr, wzero, 0, 0.f, N, d, j, (int)(j == J - 2), nullptr, NN, (long long)J * NN);
+                           nullptr, wzero, 0, 0.f, N, d, j, (int)(j == J - 2), nullptr, NN, (long long)J * NN,
+                           0.f, 0LL);
         cur = nxt;
     }
     return hipGetLastError();
@@ -898,9 +950,189 @@ hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, floa
         float *vn = (j == 0) ? out : ((j % 2 == 0) ? v_a : v_b);
         const int d = 1 << j;
         const size_t lds = sizeof(float) * (size_t)kStarTile * (kStarTile + 4 * d);
-        hipLaunchKernelGGL(k_star_levelT, dim3(nt, nt), dim3(kStarThreads), lds, st, v, z + j * NN, vn, N, d);
+        hipLaunchKernelGGL(k_star_levelT, dim3(nt, nt), dim3(kStarThreads), lds, st, v, z + j * NN, vn, N, d, 0LL,
+                           0LL, 0LL);
         v = vn;
     }
+    return hipGetLastError();
+}
+
+// Adjoint of B images at once: z [B][J][N][N] -> out [B][N][N]; v_a, v_b hold B images.
+hipError_t launch_starlet_adj_batch(hipStream_t st, int N, int J, int B, const float *z, float *out, float *v_a,
+                                    float *v_b)
+{
+    const long long NN = (long long)N * N;
+    if (J == 1) {
+        for (int b = 0; b < B; ++b) {
+            hipError_t e = launch_starlet_adj(st, N, J, z + b * NN, out + b * NN, v_a, v_b, nullptr);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    const int nt = star_tiles(N);
+    const float *v = z + (J - 1) * NN;
+    for (int j = J - 2; j >= 0; --j) {
+        float *vn = (j == 0) ? out : ((j % 2 == 0) ? v_a : v_b);
+        const int d = 1 << j;
+        const size_t lds = sizeof(float) * (size_t)kStarTile * (kStarTile + 4 * d);
+        // the first level reads plane J-1 of each image's z: stride J N^2 for it, N^2 after
+        hipLaunchKernelGGL(k_star_levelT, dim3(nt, nt, B), dim3(kStarThreads), lds, st, v, z + j * NN, vn, N, d,
+                           (j == J - 2) ? (long long)J * NN : NN, NN, (long long)J * NN);
+        v = vn;
+    }
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Eq. 11, third term: the point-source image P = sum_k <a_k> r_k on the h grid
+// (r_k within +-kGaussRadius of c_k, as in the scene) and the dot products that
+// carry its prior's gradient to a and c.
+// --------------------------------------------------------------------------
+
+// P_out = P and, when h_out is given, h_out = h (copied); <a_k> per work group
+__global__ __launch_bounds__(256) void k_pts_render(int N, int E, int M, float sigma, const float *__restrict__ params,
+                                                     float *__restrict__ h_out, float *__restrict__ P_out)
+{
+    extern __shared__ float am[];  // <a_k>
+    const long long NN = (long long)N * N;
+    const float *a = params + NN + E, *c = a + (long long)E * M;
+    for (int k = threadIdx.x; k < M; k += blockDim.x) {
+        double acc = 0.0;
+        for (int i = 0; i < E; ++i) acc += a[(long long)i * M + k];
+        am[k] = (float)(acc / E);
+    }
+    __syncthreads();
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= NN) return;
+    const int Y = (int)(pix / N), X = (int)(pix % N);
+    const float inv2s2 = 1.0f / (2.0f * sigma * sigma), norm = 1.0f / (6.28318530717958647692f * sigma * sigma);
+    float v = 0.f;
+    for (int k = 0; k < M; ++k) {
+        const float dx = (float)X - c[2 * k], dy = (float)Y - c[2 * k + 1];
+        if (fabsf(dx) <= kGaussRadius && fabsf(dy) <= kGaussRadius) v += am[k] * norm * expf(-(dx * dx + dy * dy) * inv2s2);
+    }
+    if (h_out) h_out[pix] = params[pix];
+    P_out[pix] = v;
+}
+
+hipError_t launch_pts_render(hipStream_t st, int N, int E, int M, float sigma, const float *params, float *h_out,
+                             float *P_out)
+{
+    const long long NN = (long long)N * N;
+    hipLaunchKernelGGL(k_pts_render, dim3((unsigned)((NN + 255) / 256)), dim3(256), sizeof(float) * (M > 0 ? M : 1),
+                       st, N, E, M, sigma, params, h_out, P_out);
+    return hipGetLastError();
+}
+
+// one work group per source k over the +-kGaussRadius window of r_k, with q = Phi z_P:
+// pts[3k] = <q, r_k> / E (added to every dL/da_ik), pts[3k+1..2] = <a_k> <q, dr_k/dc_k>
+__global__ __launch_bounds__(256) void k_pts_dots(int N, int E, int M, float sigma, const float *__restrict__ params,
+                                                   const float *__restrict__ q, double *__restrict__ pts)
+{
+    __shared__ double red[256 / 64];
+    const int k = blockIdx.x;
+    const long long NN = (long long)N * N;
+    const float *a = params + NN + E, *c = a + (long long)E * M;
+    const float cx = c[2 * k], cy = c[2 * k + 1];
+    const int x0 = max(0, (int)ceilf(cx - kGaussRadius)), x1 = min(N - 1, (int)floorf(cx + kGaussRadius));
+    const int y0 = max(0, (int)ceilf(cy - kGaussRadius)), y1 = min(N - 1, (int)floorf(cy + kGaussRadius));
+    const int w = max(0, x1 - x0 + 1), h = max(0, y1 - y0 + 1);
+    const double inv2s2 = 1.0 / (2.0 * (double)sigma * sigma), invs2 = 1.0 / ((double)sigma * sigma);
+    const double norm = 1.0 / (6.283185307179586477 * (double)sigma * sigma);
+    double sa = 0.0, sx = 0.0, sy = 0.0;
+    for (int e = threadIdx.x; e < w * h; e += blockDim.x) {
+        const int Y = y0 + e / w, X = x0 + e % w;
+        const double dx = (double)X - cx, dy = (double)Y - cy;
+        const double r = norm * exp(-(dx * dx + dy * dy) * inv2s2);
+        const double qv = q[(long long)Y * N + X];
+        sa += qv * r;
+        sx += qv * r * dx * invs2;
+        sy += qv * r * dy * invs2;
+    }
+    sa = block_sum_d<256>(sa, red);
+    sx = block_sum_d<256>(sx, red);
+    sy = block_sum_d<256>(sy, red);
+    if (threadIdx.x == 0) {
+        double am = 0.0;
+        for (int i = 0; i < E; ++i) am += a[(long long)i * M + k];
+        am /= E;
+        pts[3 * k] = sa / E;
+        pts[3 * k + 1] = am * sx;
+        pts[3 * k + 2] = am * sy;
+    }
+}
+
+hipError_t launch_pts_dots(hipStream_t st, int N, int E, int M, float sigma, const float *params, const float *q,
+                           double *pts)
+{
+    if (M <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pts_dots, dim3(M), dim3(256), 0, st, N, E, M, sigma, params, q, pts);
+    return hipGetLastError();
+}
+
+// App. C images: out[0] = <Gamma> + h + sum_k <a_k> r_k (the epoch average of the
+// scene on the h grid), out[1] = h, out[2 + k] = r_k; <a_k>, <Gamma> per work group
+__global__ __launch_bounds__(256) void k_pts_images(int N, int E, int M, float sigma, const float *__restrict__ params,
+                                                     float *__restrict__ out)
+{
+    extern __shared__ float am[];  // <a_k>, then <Gamma>
+    const long long NN = (long long)N * N;
+    const float *G = params + NN, *a = G + E, *c = a + (long long)E * M;
+    for (int k = threadIdx.x; k <= M; k += blockDim.x) {
+        double acc = 0.0;
+        for (int i = 0; i < E; ++i) acc += (k < M) ? a[(long long)i * M + k] : G[i];
+        am[k] = (float)(acc / E);
+    }
+    __syncthreads();
+    const long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= NN) return;
+    const int Y = (int)(pix / N), X = (int)(pix % N);
+    const float inv2s2 = 1.0f / (2.0f * sigma * sigma), norm = 1.0f / (6.28318530717958647692f * sigma * sigma);
+    float f = am[M] + params[pix];
+    for (int k = 0; k < M; ++k) {
+        const float dx = (float)X - c[2 * k], dy = (float)Y - c[2 * k + 1];
+        float r = 0.f;
+        if (fabsf(dx) <= kGaussRadius && fabsf(dy) <= kGaussRadius) r = norm * expf(-(dx * dx + dy * dy) * inv2s2);
+        out[(2 + k) * NN + pix] = r;
+        f += am[k] * r;
+    }
+    out[pix] = f;
+    out[NN + pix] = params[pix];
+}
+
+hipError_t launch_pts_images(hipStream_t st, int N, int E, int M, float sigma, const float *params, float *out)
+{
+    const long long NN = (long long)N * N;
+    hipLaunchKernelGGL(k_pts_images, dim3((unsigned)((NN + 255) / 256)), dim3(256), sizeof(float) * (M + 1), st, N,
+                       E, M, sigma, params, out);
+    return hipGetLastError();
+}
+
+// sums[b] = sum of the n partials of image b (fixed order); am[k] = <a_k>
+__global__ __launch_bounds__(256) void k_pts_sums(int B, int n, const double *__restrict__ part, int N, int E, int M,
+                                                   const float *__restrict__ params, double *__restrict__ out)
+{
+    __shared__ double red[256 / 64];
+    const int b = blockIdx.x;
+    if (b < B) {
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < n; i += 256) acc += part[(long long)b * n + i];
+        acc = block_sum_d<256>(acc, red);
+        if (threadIdx.x == 0) out[b] = acc;
+        return;
+    }
+    const int k = b - B;
+    const float *a = params + (long long)N * N + E;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < E; i += 256) acc += a[(long long)i * M + k];
+    acc = block_sum_d<256>(acc, red);
+    if (threadIdx.x == 0) out[b] = acc / E;
+}
+
+hipError_t launch_pts_sums(hipStream_t st, int B, int n, const double *part, int N, int E, int M, const float *params,
+                           double *out)
+{
+    hipLaunchKernelGGL(k_pts_sums, dim3(B + M), dim3(256), 0, st, B, n, part, N, E, M, params, out);
     return hipGetLastError();
 }
 

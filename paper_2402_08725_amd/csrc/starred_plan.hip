@@ -82,6 +82,13 @@ struct starred_plan {
     float *d_scene = nullptr, *d_rho = nullptr, *d_g = nullptr;
     double *d_part_chi = nullptr, *d_part_l1 = nullptr, *d_fsum = nullptr;
     float *d_z = nullptr, *d_ca = nullptr, *d_cb = nullptr, *d_tmp = nullptr, *d_prior = nullptr;
+    // Eq. 11, third term: weight, [h | P] images, shares of dL/da and dL/dc (3M)
+    double lam_pts = 0.0;
+    float *d_pair = nullptr;
+    double *d_pts = nullptr;
+    // its App. C estimate: images [f | h | r_k], L1 partials, norms and <a_k>
+    float *est_img = nullptr;
+    double *est_part = nullptr, *est_out = nullptr;
     float *d_grad = nullptr;
     float *d_wzero = nullptr;
     float *d_hpart = nullptr;
@@ -335,13 +342,16 @@ static int build_deconv(starred_plan *p)
     if ((rc = p->alloc(&p->d_rho, p->ndata))) return rc;
     if ((rc = p->alloc(&p->d_g, p->nfine))) return rc;
     if ((rc = p->alloc(&p->d_part_chi, p->fwd_items.size()))) return rc;
-    if ((rc = p->alloc(&p->d_part_l1, (size_t)starlet_l1_slots(p->N, p->J)))) return rc;
+    if ((rc = p->alloc(&p->d_part_l1, (size_t)2 * starlet_l1_slots(p->N, p->J)))) return rc;
     if ((rc = p->alloc(&p->d_fsum, (size_t)E * (1 + 3 * p->M)))) return rc;
-    if ((rc = p->alloc(&p->d_z, (size_t)p->J * NN))) return rc;
-    if ((rc = p->alloc(&p->d_ca, NN))) return rc;
-    if ((rc = p->alloc(&p->d_cb, NN))) return rc;
+    // two images (h and the point-source image P of Eq. 11) for the prior buffers
+    if ((rc = p->alloc(&p->d_z, (size_t)2 * p->J * NN))) return rc;
+    if ((rc = p->alloc(&p->d_ca, 2 * NN))) return rc;
+    if ((rc = p->alloc(&p->d_cb, 2 * NN))) return rc;
+    if ((rc = p->alloc(&p->d_pair, 2 * NN))) return rc;
+    if ((rc = p->alloc(&p->d_pts, (size_t)3 * std::max(1, p->M)))) return rc;
     if ((rc = p->alloc(&p->d_tmp, NN))) return rc;
-    if ((rc = p->alloc(&p->d_prior, NN))) return rc;
+    if ((rc = p->alloc(&p->d_prior, 2 * NN))) return rc;
     if ((rc = p->alloc(&p->d_hpart, (size_t)finalize_h_chunks(E) * NN))) return rc;
     if ((rc = p->alloc(&p->d_grad, p->nparams))) return rc;
     if ((rc = p->alloc(&p->d_wzero, (size_t)p->J * NN))) return rc;
@@ -859,14 +869,38 @@ int starred_starlet_adj(starred_plan *p, const float *coeffs, float *img)
 // Starlet transform, L1 term, subgradient and adjoint of the image part of
 // params (h, or b in PSF mode) on the second stream: fork from st, join with
 // ev_join (the caller waits on it before the final reductions).
+// The prior terms on stream st: lambda ||W (.) Phi^T img||_1 with its gradient
+// Phi z in d_prior and, when lambda_pts != 0 (deconvolution), the point-source
+// term of Eq. 11 transformed together with h (a batch of two images): its
+// gradient's shares of dL/da and dL/dc land in d_pts.
+static int prior_launches(starred_plan *p, hipStream_t st, const float *img, bool want_grad, int *n_l1)
+{
+    if (p->mode == STARRED_DECONV && p->lam_pts != 0.0) {
+        const long long NN = (long long)p->N * p->N;
+        HIP_TRY(launch_pts_render(st, p->N, p->E, p->M, p->sigma, img, p->d_pair, p->d_pair + NN));
+        HIP_TRY(launch_starlet_prior(st, p->N, p->J, 2, p->d_pair, want_grad ? p->d_z : nullptr, p->W, p->w_stride,
+                                     (float)p->lam, (float)p->lam_pts, p->d_ca, p->d_cb, p->d_part_l1, n_l1));
+        if (want_grad) {
+            HIP_TRY(launch_starlet_adj_batch(st, p->N, p->J, 2, p->d_z, p->d_prior, p->d_ca, p->d_cb));
+            HIP_TRY(launch_pts_dots(st, p->N, p->E, p->M, p->sigma, img, p->d_prior + NN, p->d_pts));
+        }
+        return STARRED_OK;
+    }
+    HIP_TRY(launch_starlet_fwd(st, p->N, p->J, img, nullptr, want_grad ? p->d_z : nullptr, p->W, p->w_stride,
+                               (float)p->lam, p->d_ca, p->d_cb, p->d_tmp, p->d_part_l1, n_l1));
+    if (want_grad) HIP_TRY(launch_starlet_adj(st, p->N, p->J, p->d_z, p->d_prior, p->d_ca, p->d_cb, p->d_tmp));
+    return STARRED_OK;
+}
+
+// The prior on the second stream: fork from st, join with ev_join (the caller
+// waits on it before the final reductions).
 static int starlet_branch(starred_plan *p, const float *img, bool want_grad, int *n_l1)
 {
     HIP_TRY(hipEventRecord(p->ev_fork, p->st));
     HIP_TRY(hipStreamWaitEvent(p->st2, p->ev_fork, 0));
     hipEvent_t e0 = p->prof_start(p->st2);
-    HIP_TRY(launch_starlet_fwd(p->st2, p->N, p->J, img, nullptr, want_grad ? p->d_z : nullptr, p->W, p->w_stride,
-                               (float)p->lam, p->d_ca, p->d_cb, p->d_tmp, p->d_part_l1, n_l1));
-    if (want_grad) HIP_TRY(launch_starlet_adj(p->st2, p->N, p->J, p->d_z, p->d_prior, p->d_ca, p->d_cb, p->d_tmp));
+    int rc = prior_launches(p, p->st2, img, want_grad, n_l1);
+    if (rc) return rc;
     p->prof_stop(STARRED_STAGE_STARLET, e0, p->st2);
     HIP_TRY(hipEventRecord(p->ev_join, p->st2));
     return STARRED_OK;
@@ -961,7 +995,8 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     HIP_TRY(launch_finalize_small(p->st, p->E, p->M, n_chi, part_chi, n_l1, p->d_part_l1, p->lam, p->d_fsum,
                                   params, p->N, grad, loss_out, nullptr, nullptr, nullptr,
                                   (fft && adam) ? nullptr : tick, fft ? p->fd.classes : nullptr, p->fd.n_classes,
-                                  p->fd.hcls, p->d_prior, (fft && adam) ? *adam : AdamDev()));
+                                  p->fd.hcls, p->d_prior, (fft && adam) ? *adam : AdamDev(),
+                                  (p->lam_pts != 0.0 && grad) ? p->d_pts : nullptr));
     p->prof_stop(STARRED_STAGE_FINALIZE, e0);
     return STARRED_OK;
 }
@@ -1149,14 +1184,12 @@ int starred_loss_grad_plain(starred_plan *p, const float *params, float *grad, d
         }
     }
     int n_l1 = 0;
-    HIP_TRY(launch_starlet_fwd(p->st, p->N, p->J, params, nullptr, grad ? p->d_z : nullptr, p->W, p->w_stride,
-                               (float)p->lam, p->d_ca, p->d_cb, p->d_tmp, p->d_part_l1, &n_l1));
-    if (grad) {
-        HIP_TRY(launch_starlet_adj(p->st, p->N, p->J, p->d_z, p->d_prior, p->d_ca, p->d_cb, p->d_tmp));
-        HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad, p->d_hpart));
-    }
+    int rc = prior_launches(p, p->st, params, grad != nullptr, &n_l1);
+    if (rc) return rc;
+    if (grad) HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad, p->d_hpart));
     HIP_TRY(launch_finalize_small(p->st, p->E, p->M, p->n_pchi, p->d_pchi, n_l1, p->d_part_l1, p->lam, p->d_fsum,
-                                  params, p->N, grad, loss_out));
+                                  params, p->N, grad, loss_out, nullptr, nullptr, nullptr, nullptr, nullptr, 0,
+                                  nullptr, nullptr, AdamDev(), (p->lam_pts != 0.0 && grad) ? p->d_pts : nullptr));
     return STARRED_OK;
 }
 
@@ -1287,6 +1320,54 @@ int starred_set_fft_fused(starred_plan *p, int32_t enable)
     if (!p) return fail(STARRED_EINVAL, "plan is NULL");
     p->drop_graphs();
     p->fft_fused = enable != 0;
+    return STARRED_OK;
+}
+
+int starred_set_lambda_pts(starred_plan *p, double lambda_pts)
+{
+    if (!p) return fail(STARRED_EINVAL, "plan is NULL");
+    if (p->mode != STARRED_DECONV) return fail(STARRED_EUNSUPPORTED, "the point-source prior is a deconvolution term");
+    if (!(lambda_pts >= 0.0)) return fail(STARRED_EINVAL, "lambda_pts must be >= 0");
+    p->drop_graphs();
+    p->lam_pts = lambda_pts;
+    return STARRED_OK;
+}
+
+int starred_pts_image(starred_plan *p, const float *params, float *P_out)
+{
+    if (!p || !params || !P_out) return fail(STARRED_EINVAL, "NULL argument");
+    if (p->mode != STARRED_DECONV) return fail(STARRED_EUNSUPPORTED, "the point-source prior is a deconvolution term");
+    HIP_TRY(launch_pts_render(p->st, p->N, p->E, p->M, p->sigma, params, nullptr, P_out));
+    return STARRED_OK;
+}
+
+int starred_estimate_lambda_pts(starred_plan *p, const float *params, double *lambda_pts_out)
+{
+    if (!p || !params || !lambda_pts_out) return fail(STARRED_EINVAL, "NULL argument");
+    if (p->mode != STARRED_DECONV) return fail(STARRED_EUNSUPPORTED, "the point-source prior is a deconvolution term");
+    if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
+    if (p->M < 1) return fail(STARRED_EUNSUPPORTED, "no point sources");
+    const long long NN = (long long)p->N * p->N;
+    const int B = p->M + 2, slots = starlet_l1_slots(p->N, p->J);
+    if (!p->est_img) {
+        int rc = p->alloc(&p->est_img, (size_t)B * NN);
+        if (!rc) rc = p->alloc(&p->est_part, (size_t)B * slots);
+        if (!rc) rc = p->alloc(&p->est_out, (size_t)B + p->M);
+        if (rc) return rc;
+    }
+    HIP_TRY(launch_fill_d(p->st, p->est_part, (long long)B * slots));
+    HIP_TRY(launch_pts_images(p->st, p->N, p->E, p->M, p->sigma, params, p->est_img));
+    for (int b = 0; b < B; ++b)
+        HIP_TRY(launch_starlet_fwd(p->st, p->N, p->J, p->est_img + b * NN, nullptr, nullptr, p->W, p->w_stride, 1.f,
+                                   p->d_ca, p->d_cb, p->d_tmp, p->est_part + (long long)b * slots, nullptr));
+    HIP_TRY(launch_pts_sums(p->st, B, slots, p->est_part, p->N, p->E, p->M, params, p->est_out));
+    std::vector<double> h(B + p->M);
+    HIP_TRY(hipMemcpyAsync(h.data(), p->est_out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, p->st));
+    HIP_TRY(hipStreamSynchronize(p->st));
+    double den = 0.0;
+    for (int k = 0; k < p->M; ++k) den += h[B + k] * h[2 + k];
+    if (!(den != 0.0)) return fail(STARRED_EINVAL, "the point sources' norms sum to zero");
+    *lambda_pts_out = p->lam * (h[0] - h[1]) / den;
     return STARRED_OK;
 }
 

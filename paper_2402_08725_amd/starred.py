@@ -86,6 +86,9 @@ def lib():
         L.starred_copy_probe.argtypes = [vp, vp, vp, ctypes.c_int64]
         L.starred_time_stage.argtypes = [vp, vp, i32, i32, ctypes.POINTER(ctypes.c_double)]
         L.starred_noise_weights.argtypes = [vp, i32, vp, i32, ctypes.c_uint64, vp, i32, vp]
+        L.starred_set_lambda_pts.argtypes = [vp, ctypes.c_double]
+        L.starred_pts_image.argtypes = [vp, vp, vp]
+        L.starred_estimate_lambda_pts.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
         _lib = L
     return _lib
 
@@ -284,6 +287,24 @@ class Plan:
     def copy_probe(self, src, dst):
         """Plain device copy (memory-counter calibration)."""
         self._call(lib().starred_copy_probe, _ptr(src), _ptr(dst), int(src.numel()))
+
+    def set_lambda_pts(self, lambda_pts: float):
+        """Weight of the point-source prior (Eq. 11, third term); 0 leaves it out."""
+        _check(lib().starred_set_lambda_pts(self._h, ctypes.c_double(float(lambda_pts))))
+
+    def pts_image(self, params):
+        """P = sum_k <a_k> r_k on the N x N grid (Eq. 11, third term)."""
+        params = _f32(params, self.device)
+        out = torch.empty(self.N * self.N, dtype=torch.float32, device=self.device)
+        self._call(lib().starred_pts_image, _ptr(params), _ptr(out))
+        return out
+
+    def estimate_lambda_pts(self, params) -> float:
+        """App. C estimate of lambda_pts at params."""
+        params = _f32(params, self.device)
+        out = ctypes.c_double(0.0)
+        self._call(lib().starred_estimate_lambda_pts, _ptr(params), ctypes.byref(out))
+        return out.value
 
     def set_fft_fused(self, enable: bool):
         """FFT path: one-launch forward for frames whose spectra fit in LDS (default on)."""

@@ -90,4 +90,7 @@ def test_null_plan_arguments_are_rejected():
     assert L.starred_loss_grad(None, None, None, None) == -1
     assert L.starred_time_stage(None, None, 0, 1, None) == -1
     assert L.starred_noise_weights(None, 0, None, 10, 0, None, 1, None) == -1
+    assert L.starred_set_lambda_pts(None, ctypes.c_double(1.0)) == -1
+    assert L.starred_estimate_lambda_pts(None, None, None) == -1
+    assert L.starred_pts_image(None, None, None) == -1
     assert L.starred_set_frames(None, None, None, None, None) == -1

@@ -656,3 +656,70 @@ def test_noise_weights_argument_errors():
         plan.noise_weights(sig2, 1)
     with pytest.raises(st.StarredError):
         plan.noise_weights(sig2, 10, frame=prob.E)
+
+
+# --------------------------------------------------------------------------- #
+# Point-source prior (Eq. 11, third term) and its App. C estimate              #
+# --------------------------------------------------------------------------- #
+
+def _compare_with_pts(prob, d, w, p, plan, lam_pts, label, plain=False):
+    NN = prob.N * prob.N
+    if plain:
+        loss, grad = plan.loss_grad_plain(p)
+    else:
+        loss, grad = plan.loss_grad(p)
+    loss = loss.cpu().numpy()
+    grad = grad.cpu().numpy().astype(np.float64)
+    so_h, n1 = parity.tie_override(prob.N, prob.J, p[:NN], plan.starlet_fwd(p[:NN]).cpu().numpy())
+    alpha_P = plan.starlet_fwd(plan.pts_image(p)).cpu().numpy()
+    so_P, n2 = parity.tie_override(prob.N, prob.J, ora.pts_image(prob, p), alpha_P)
+    lo, go = ora.loss_grad(prob, d, w, p, sgn_override=so_h, lam_pts=lam_pts, sgn_override_pts=so_P)
+    rl = abs(loss[2] - lo[2]) / abs(lo[2])
+    blocks = {k: parity.rel_err(parity.deconv_blocks(prob, grad)[k], v)
+              for k, v in parity.deconv_blocks(prob, go).items() if np.linalg.norm(v) > 0}
+    _say(f"{label}: loss rel {rl:.2e} (l1 {abs(loss[1]-lo[1])/abs(lo[1]):.2e}); grad {blocks}; ties {n1}+{n2}")
+    assert rl <= 1e-6
+    assert parity.rel_err(grad, go) <= 1e-4
+    for k, v in blocks.items():
+        assert v <= 1e-4, (k, v)
+
+
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+@pytest.mark.parametrize("name,make", [LG_CASES[0], LG_CASES[1], LG_CASES[3]], ids=["cfg1", "cfg2_E6", "small_s3"])
+def test_loss_grad_with_point_source_prior(name, make, algo):
+    prob = make()
+    d, w, rng = _data(prob, seed=41)
+    plan = _plan(prob, d, w, algo=algo)
+    p = synth.eval_point(prob, "near", rng)
+    lam_pts = 0.6 * prob.lam
+    plan.set_lambda_pts(lam_pts)
+    _compare_with_pts(prob, d, w, p, plan, lam_pts, f"{name}/{ALGO_ID[algo]}/pts")
+    # graph replay of the same evaluation
+    plan.set_graph_mode(True)
+    _compare_with_pts(prob, d, w, p, plan, lam_pts, f"{name}/{ALGO_ID[algo]}/pts graph")
+    plan.set_graph_mode(False)
+    # and off again: back to the two-term loss
+    plan.set_lambda_pts(0.0)
+    _compare_loss_grad(prob, d, w, p, plan, f"{name}/{ALGO_ID[algo]}/pts off")
+
+
+def test_plain_baseline_with_point_source_prior():
+    prob = synth.make_deconv(2, E=6)
+    d, w, rng = _data(prob, seed=42)
+    plan = _plan(prob, d, w)
+    p = synth.eval_point(prob, "near", rng)
+    plan.set_lambda_pts(1.3)
+    _compare_with_pts(prob, d, w, p, plan, 1.3, "plain/pts", plain=True)
+
+
+@pytest.mark.parametrize("name,make", [LG_CASES[0], LG_CASES[1]], ids=["cfg1", "cfg2_E6"])
+def test_lambda_pts_estimate_matches_oracle(name, make):
+    prob = make()
+    d, w, rng = _data(prob, seed=43)
+    plan = _plan(prob, d, w)
+    for point in ("init", "near"):
+        p = synth.eval_point(prob, point, rng)
+        got = plan.estimate_lambda_pts(p)
+        ref = ora.lambda_pts_estimate(prob, p)
+        _say(f"{name}/{point}: lambda_pts estimate {got:.6g} oracle {ref:.6g}")
+        assert got == pytest.approx(ref, rel=1e-4)

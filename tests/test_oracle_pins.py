@@ -594,3 +594,98 @@ def test_noise_weights_mc_with_philox_draws_converge_to_exact_variance():
     # per scale: pooled second moment over the plane (the mean is zero in expectation)
     for j in range(J):
         assert abs(Wsc[j] ** 2 - var[j].mean()) / var[j].mean() < 6 * np.sqrt(2.0 / (R * 4))
+
+
+# --------------------------------------------------------------------------- #
+# Point-source prior (Eq. 11, third term) and its App. C estimate              #
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("w_stride", [0, 1])
+def test_pts_term_is_linear_in_a_along_sign_preserving_directions(w_stride):
+    """For fixed c the term is lam_pts ||W (.) Phi^T sum_k <a_k> r_k||_1: piecewise linear in
+    a. Along a direction that keeps every coefficient's sign its change is exactly the
+    gradient's dot product; the gradient is the same for every epoch of a source."""
+    prob, d, w, p = _small_problem_with_data(seed=14, w_stride=w_stride)
+    lam_pts = 1.7
+    NN, E, M = prob.N ** 2, prob.E, prob.M
+    _, g_all = ora.loss_grad(prob, d, w, p, lam_pts=lam_pts)
+    _, g0 = ora.loss_grad(prob, d, w, p)
+    g = g_all - g0
+    assert np.all(g[:NN + E] == 0.0)
+    ga = g[NN + E:NN + E + E * M].reshape(E, M)
+    np.testing.assert_allclose(ga, np.broadcast_to(ga[0], ga.shape), rtol=1e-12)
+    rng = np.random.default_rng(5)
+    L3 = lambda q: (ora.loss_grad(prob, d, w, q, want_grad=False, lam_pts=lam_pts)[0][1]
+                    - ora.loss_grad(prob, d, w, q, want_grad=False)[0][1])
+    for _ in range(3):
+        delta = np.zeros(prob.n_params)
+        delta[NN + E:NN + E + E * M] = rng.standard_normal(E * M)
+        alpha = ora.starlet_fwd(prob.N, prob.J, ora.pts_image(prob, p))
+        # the direction's change of P is linear in delta (c fixed)
+        dP = ora.pts_image(prob, p + delta) - ora.pts_image(prob, p)
+        dalpha = ora.starlet_fwd(prob.N, prob.J, dP)
+        eps = 0.5 * np.min(np.abs(alpha) / np.maximum(np.abs(dalpha), 1e-300))
+        fd = (L3(p + eps * delta) - L3(p - eps * delta)) / (2 * eps)
+        assert fd == pytest.approx(np.dot(g, delta), rel=1e-7)
+
+
+def test_pts_term_position_gradient_by_central_differences():
+    prob, d, w, p = _small_problem_with_data(seed=15)
+    lam_pts = 2.3
+    NN, E, M = prob.N ** 2, prob.E, prob.M
+    _, g_all = ora.loss_grad(prob, d, w, p, lam_pts=lam_pts)
+    _, g0 = ora.loss_grad(prob, d, w, p)
+    g = g_all - g0
+    L3 = lambda q: (ora.loss_grad(prob, d, w, q, want_grad=False, lam_pts=lam_pts)[0][1]
+                    - ora.loss_grad(prob, d, w, q, want_grad=False)[0][1])
+    for j in range(NN + E + E * M, prob.n_params):
+        h = 1e-6
+        pp, pm = p.copy(), p.copy()
+        pp[j] += h
+        pm[j] -= h
+        fd = (L3(pp) - L3(pm)) / (2 * h)
+        assert fd == pytest.approx(g[j], rel=1e-5, abs=1e-9 * np.abs(g).max())
+
+
+def test_pts_term_single_plane_closed_form():
+    """J = 1 (the transform is the identity), one source: the term is
+    lam_pts W_0 |<a>| sum_X r(X), r the sampled Gaussian, positive everywhere."""
+    prob = synth.make_small_deconv(seed=16, E=4, sides=[8], K=[5], s=2, N=24, M=1, J=1)
+    rng = np.random.default_rng(6)
+    m = ora.forward_model(prob, prob.params_true)
+    d, w = synth.add_noise(m, rng)
+    p = synth.eval_point(prob, "near", rng)
+    lam_pts = 0.9
+    l_all, _ = ora.loss_grad(prob, d, w, p, want_grad=False, lam_pts=lam_pts)
+    l_0, _ = ora.loss_grad(prob, d, w, p, want_grad=False)
+    NN, E = prob.N ** 2, prob.E
+    amean = p[NN + E:NN + 2 * E].mean()
+    cx, cy = p[NN + 2 * E:NN + 2 * E + 2]
+    sig = ora.sigma_from_fwhm(prob.fwhm)
+    Y, X = np.mgrid[0:prob.N, 0:prob.N].astype(np.float64)
+    rsum = np.sum(np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2 * sig ** 2)) / (2 * np.pi * sig ** 2))
+    assert l_all[1] - l_0[1] == pytest.approx(lam_pts * prob.W[0] * abs(amean) * rsum, rel=1e-12)
+
+
+def test_lambda_pts_estimate_special_cases():
+    """App. C: with h = 0 and Gamma = 0 the averaged image is sum_k <a_k> r_k, so for one
+    source (or sources whose starlet supports do not meet) the estimate is lambda itself,
+    and the triangle inequality bounds it by lambda in general."""
+    prob = synth.make_small_deconv(seed=17, E=3, sides=[12], K=[7], s=2, N=48, M=1, J=3)
+    p = prob.params_true.astype(np.float64).copy()
+    NN, E, M = prob.N ** 2, prob.E, prob.M
+    p[:NN + E] = 0.0
+    p[NN + E:NN + E + E * M] = np.abs(p[NN + E:NN + E + E * M]) + 1.0
+    assert ora.lambda_pts_estimate(prob, p, lam=2.5) == pytest.approx(2.5, rel=1e-12)
+    prob2 = synth.make_small_deconv(seed=18, E=3, sides=[12], K=[7], s=2, N=48, M=3, J=3)
+    p2 = prob2.params_true.astype(np.float64).copy()
+    p2[:NN + E] = 0.0
+    p2[NN + E:NN + E + E * 3] = np.abs(p2[NN + E:NN + E + E * 3]) + 1.0
+    est = ora.lambda_pts_estimate(prob2, p2, lam=2.5)
+    assert 0.0 < est <= 2.5 * (1 + 1e-12)
+    # far-apart sources: the planes' supports (J = 2: +-4 px around +-8 px Gaussian tails) do not meet
+    p3 = p2.copy()
+    p3[NN + E + E * 3:] = [6.0, 6.0, 41.0, 6.0, 24.0, 41.0]
+    prob3 = synth.DeconvProblem(**{**prob2.__dict__, "J": 2, "W": prob2.W[:2]})
+    est3 = ora.lambda_pts_estimate(prob3, p3, lam=2.5)
+    assert est3 == pytest.approx(2.5, rel=1e-6)
