@@ -86,12 +86,19 @@ typedef struct {
     double gauss_fwhm;
 } starred_desc;
 
-/* Adam hyper-parameters; lr is given per parameter block:
+/* Optimiser hyper-parameters; lr is given per parameter block:
  *   deconvolution: lr[0] h, lr[1] Gamma, lr[2] a, lr[3] c
- *   PSF mode:      lr[0] eta_M, lr[1] b, lr[2] a, lr[3] c */
+ *   PSF mode:      lr[0] eta_M, lr[1] b, lr[2] a, lr[3] c
+ * rule: STARRED_ADAM (Kingma & Ba: v tracks g^2) or STARRED_ADABELIEF (Zhuang et
+ * al.: v tracks (g - m)^2 + eps_root, m the updated first moment); both use the
+ * bias corrections 1 - beta^t and the step lr m_hat / (sqrt(v_hat) + eps).
+ * A zero-initialised struct's rule is Adam (eps_root is then unused). */
+enum { STARRED_ADAM = 0, STARRED_ADABELIEF = 1 };
 typedef struct {
     float lr[4];
     float beta1, beta2, eps;
+    int32_t rule;
+    float eps_root;
 } starred_adam;
 
 /* Create a plan: validates the description, builds the frame tables and the
@@ -158,8 +165,8 @@ int starred_loss_grad(starred_plan *plan, const float *params, float *grad, doub
  * starred_set_frames must stay valid (they are re-read on the first call). */
 int starred_loss_grad_plain(starred_plan *plan, const float *params, float *grad, double *loss_out);
 
-/* One optimiser step: loss_grad at params, then the Adam update (Kingma & Ba)
- * of params, m and v in place, t = step number starting at 1. The plan keeps
+/* One optimiser step: loss_grad at params, then the update (hp->rule: Adam or
+ * AdaBelief) of params, m and v in place, t = step number starting at 1. The plan keeps
  * the gradient in its own scratch. loss_out as above (may be NULL). */
 int starred_step(starred_plan *plan, float *params, float *m, float *v, int32_t t,
                  const starred_adam *hp, double *loss_out);

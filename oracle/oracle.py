@@ -42,7 +42,7 @@ def lib():
         for name in ["ora_render_scene", "ora_conv_sub", "ora_conv_sub_adj", "ora_starlet_fwd",
                      "ora_starlet_adj", "ora_loss_grad", "ora_forward_model", "ora_moffat",
                      "ora_psf_render", "ora_psf_model", "ora_psf_loss_grad", "ora_adam_step",
-                     "ora_noise_variance", "ora_noise_weights_mc", "ora_pts_term"]:
+                     "ora_noise_variance", "ora_noise_weights_mc", "ora_pts_term", "ora_adabelief_step"]:
             getattr(_lib, name).restype = None
         _lib.ora_philox4x32_10.restype = None
         _lib.ora_lambda_pts_estimate.restype = ctypes.c_double
@@ -262,3 +262,13 @@ def adam_step(params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     lr = _f64(np.broadcast_to(lr, params.shape))
     lib().ora_adam_step(ctypes.c_long(params.size), _d(params), _d(grad), _d(m), _d(v), t, _d(lr),
                         ctypes.c_double(beta1), ctypes.c_double(beta2), ctypes.c_double(eps))
+
+
+def adabelief_step(params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-16, eps_root=1e-16):
+    """In-place AdaBelief update of float64 arrays (params, m, v)."""
+    assert params.dtype == np.float64 and m.dtype == np.float64 and v.dtype == np.float64
+    grad = _f64(grad)
+    lr = _f64(np.broadcast_to(lr, params.shape))
+    lib().ora_adabelief_step(ctypes.c_long(params.size), _d(params), _d(grad), _d(m), _d(v), t, _d(lr),
+                             ctypes.c_double(beta1), ctypes.c_double(beta2), ctypes.c_double(eps),
+                             ctypes.c_double(eps_root))

@@ -948,6 +948,22 @@ void ora_adam_step(long P, double *params, const double *grad, double *m, double
     }
 }
 
+/* AdaBelief (Zhuang et al., NeurIPS 2020): the second moment tracks the squared
+ * deviation of the gradient from the updated first moment, plus eps_root; the
+ * bias corrections and the step are Adam's. lr per parameter. */
+void ora_adabelief_step(long P, double *params, const double *grad, double *m, double *v, int t,
+                        const double *lr, double beta1, double beta2, double eps, double eps_root)
+{
+    double bc1 = 1.0 - pow(beta1, t);
+    double bc2 = 1.0 - pow(beta2, t);
+    for (long p = 0; p < P; ++p) {
+        m[p] = beta1 * m[p] + (1.0 - beta1) * grad[p];
+        const double d = grad[p] - m[p];
+        v[p] = beta2 * v[p] + (1.0 - beta2) * d * d + eps_root;
+        params[p] -= lr[p] * (m[p] / bc1) / (sqrt(v[p] / bc2) + eps);
+    }
+}
+
 int ora_num_threads(void)
 {
 #ifdef _OPENMP

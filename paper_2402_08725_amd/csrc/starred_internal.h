@@ -74,21 +74,31 @@ hipError_t launch_frame_sums(hipStream_t st, const FrameDev *fr, int E, int N, i
 hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, const float *g,
                              const float *prior, float *grad_h, float *part);
 int finalize_h_chunks(int E);
-// Adam update of one parameter (bias-corrected moments, per-block learning rate).
+// Update of one parameter (bias-corrected moments, per-block learning rate):
+// Adam (v tracks g^2) or, with belief, AdaBelief (v tracks (g - m)^2 + eps_root
+// with the updated m).
 __device__ __forceinline__ void adam_update(float &param, float &m, float &v, float g, float lr, float beta1,
-                                            float beta2, float bc1, float bc2, float eps)
+                                            float beta2, float bc1, float bc2, float eps, bool belief = false,
+                                            float eps_root = 0.f)
 {
     m = beta1 * m + (1.f - beta1) * g;
-    v = beta2 * v + (1.f - beta2) * g * g;
+    if (belief) {
+        const float dg = g - m;
+        v = beta2 * v + (1.f - beta2) * dg * dg + eps_root;
+    } else {
+        v = beta2 * v + (1.f - beta2) * g * g;
+    }
     param -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
 }
 
-// Adam state for an update fused into the final reduction launch (params null: none).
+// Optimiser state for an update fused into the final reduction launch (params null: none).
 struct AdamDev {
     float *params = nullptr, *m = nullptr, *v = nullptr;
     const int *d_t = nullptr;
     float lr[4] = {0.f, 0.f, 0.f, 0.f};
     float beta1 = 0.f, beta2 = 0.f, eps = 0.f;
+    int rule = 0;
+    float eps_root = 0.f;
 };
 
 struct ClassFft;
@@ -131,7 +141,7 @@ hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, floa
 
 hipError_t launch_adam(hipStream_t st, long long P, const long long *seg_end, const float *lr,
                        float *params, const float *grad, float *m, float *v, int *d_t, float beta1,
-                       float beta2, float eps);
+                       float beta2, float eps, int rule = 0, float eps_root = 0.f);
 hipError_t launch_set_step(hipStream_t st, int *d_t, int value);
 
 hipError_t launch_fill(hipStream_t st, float *p, long long n, float v);

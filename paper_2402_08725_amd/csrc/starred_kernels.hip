@@ -576,7 +576,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
         grad[pix] = acc;
         if (adam.params) {
             float pi = adam.params[pix], mi = adam.m[pix], vi = adam.v[pix];
-            adam_update(pi, mi, vi, acc, adam.lr[0], adam.beta1, adam.beta2, bc1, bc2, adam.eps);
+            adam_update(pi, mi, vi, acc, adam.lr[0], adam.beta1, adam.beta2, bc1, bc2, adam.eps, adam.rule == 1,
+                        adam.eps_root);
             adam.m[pix] = mi;
             adam.v[pix] = vi;
             adam.params[pix] = pi;
@@ -642,7 +643,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(
     for (long long e = NN + threadIdx.x; e < e3; e += kFinThreads) {
         const float lr = e < e1 ? adam.lr[1] : (e < e2 ? adam.lr[2] : adam.lr[3]);
         float pi = adam.params[e], mi = adam.m[e], vi = adam.v[e];
-        adam_update(pi, mi, vi, grad[e], lr, adam.beta1, adam.beta2, bc1, bc2, adam.eps);
+        adam_update(pi, mi, vi, grad[e], lr, adam.beta1, adam.beta2, bc1, bc2, adam.eps, adam.rule == 1,
+                    adam.eps_root);
         adam.m[e] = mi;
         adam.v[e] = vi;
         adam.params[e] = pi;
@@ -1175,7 +1177,7 @@ __global__ void k_adam(long long P, long long e0, long long e1, long long e2, fl
                        float lr2, float lr3, float *__restrict__ params,
                        const float *__restrict__ grad, float *__restrict__ m,
                        float *__restrict__ v, float beta1, float beta2, float eps,
-                       const int *__restrict__ d_t)
+                       const int *__restrict__ d_t, int rule, float eps_root)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
@@ -1184,7 +1186,7 @@ __global__ void k_adam(long long P, long long e0, long long e1, long long e2, fl
     const float bc2 = 1.f - powf(beta2, t);
     const float lr = i < e0 ? lr0 : (i < e1 ? lr1 : (i < e2 ? lr2 : lr3));
     float pi = params[i], mi = m[i], vi = v[i];
-    adam_update(pi, mi, vi, grad[i], lr, beta1, beta2, bc1, bc2, eps);
+    adam_update(pi, mi, vi, grad[i], lr, beta1, beta2, bc1, bc2, eps, rule == 1, eps_root);
     m[i] = mi;
     v[i] = vi;
     params[i] = pi;
@@ -1198,11 +1200,11 @@ hipError_t launch_set_step(hipStream_t st, int *d_t, int value)
 
 hipError_t launch_adam(hipStream_t st, long long P, const long long *seg_end, const float *lr,
                        float *params, const float *grad, float *m, float *v, int *d_t, float beta1,
-                       float beta2, float eps)
+                       float beta2, float eps, int rule, float eps_root)
 {
     const int nb = (int)((P + 255) / 256);
     hipLaunchKernelGGL(k_adam, dim3(nb), dim3(256), 0, st, P, seg_end[0], seg_end[1], seg_end[2],
-                       lr[0], lr[1], lr[2], lr[3], params, grad, m, v, beta1, beta2, eps, d_t);
+                       lr[0], lr[1], lr[2], lr[3], params, grad, m, v, beta1, beta2, eps, d_t, rule, eps_root);
     return hipGetLastError();
 }
 

@@ -1261,6 +1261,7 @@ int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
 {
     if (!p || !params || !m || !v || !hp) return fail(STARRED_EINVAL, "NULL argument");
     if (t < 1) return fail(STARRED_EINVAL, "t must be >= 1");
+    if (hp->rule != STARRED_ADAM && hp->rule != STARRED_ADABELIEF) return fail(STARRED_EINVAL, "unknown update rule");
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
     // the device step counter is advanced inside the step; resynchronise it when
     // the caller's step number is not the next one
@@ -1277,6 +1278,8 @@ int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
     ad.beta1 = hp->beta1;
     ad.beta2 = hp->beta2;
     ad.eps = hp->eps;
+    ad.rule = hp->rule;
+    ad.eps_root = hp->eps_root;
     auto body = [&]() -> int {
         int rc = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t)
                                           : loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t,
@@ -1292,7 +1295,7 @@ int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
         }
         hipEvent_t e0 = p->prof_start();
         HIP_TRY(launch_adam(p->st, p->nparams, seg, hp->lr, params, p->d_grad, m, v, p->d_t, hp->beta1, hp->beta2,
-                            hp->eps));
+                            hp->eps, hp->rule, hp->eps_root));
         p->prof_stop(STARRED_STAGE_ADAM, e0);
         return STARRED_OK;
     };
@@ -1300,11 +1303,13 @@ int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
     if (!p->graph_mode) {
         rc = body();
     } else {
-        uint32_t hb[7];
+        uint32_t hb[9];
         memcpy(hb, hp->lr, sizeof(float) * 4);
         memcpy(hb + 4, &hp->beta1, sizeof(float));
         memcpy(hb + 5, &hp->beta2, sizeof(float));
         memcpy(hb + 6, &hp->eps, sizeof(float));
+        memcpy(hb + 7, &hp->rule, sizeof(int32_t));
+        memcpy(hb + 8, &hp->eps_root, sizeof(float));
         std::vector<uintptr_t> key = {(uintptr_t)params, (uintptr_t)m, (uintptr_t)v, (uintptr_t)loss_out,
                                       (uintptr_t)p->algo};
         for (uint32_t x : hb) key.push_back(x);

@@ -42,9 +42,12 @@ class Desc(ctypes.Structure):
     ]
 
 
+ADAM, ADABELIEF = 0, 1
+
+
 class AdamHP(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float * 4), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
-                ("eps", ctypes.c_float)]
+                ("eps", ctypes.c_float), ("rule", ctypes.c_int32), ("eps_root", ctypes.c_float)]
 
 
 class StarredError(RuntimeError):
@@ -245,12 +248,15 @@ class Plan:
         self._call(lib().starred_loss_grad_plain, _ptr(params), _ptr(grad), _ptr(loss))
         return loss, grad
 
-    def step(self, params, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, loss_out=None):
-        """One Adam step in place on (params, m, v); returns the loss at the old params."""
+    def step(self, params, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, loss_out=None, rule=ADAM,
+             eps_root=0.0):
+        """One optimiser step (Adam or AdaBelief) in place on (params, m, v); returns the
+        loss at the old params."""
         hp = AdamHP()
         for i in range(4):
             hp.lr[i] = float(lr[i])
         hp.beta1, hp.beta2, hp.eps = beta1, beta2, eps
+        hp.rule, hp.eps_root = int(rule), float(eps_root)
         loss = loss_out if loss_out is not None else torch.empty(3, dtype=torch.float64, device=self.device)
         self._call(lib().starred_step, _ptr(params), _ptr(m), _ptr(v), int(t), ctypes.byref(hp), _ptr(loss))
         return loss

@@ -723,3 +723,43 @@ def test_lambda_pts_estimate_matches_oracle(name, make):
         ref = ora.lambda_pts_estimate(prob, p)
         _say(f"{name}/{point}: lambda_pts estimate {got:.6g} oracle {ref:.6g}")
         assert got == pytest.approx(ref, rel=1e-4)
+
+
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+def test_adabelief_steps_against_oracle(algo):
+    """The AdaBelief rule (the optimiser of the paper's fits) through the same step: a
+    single step on well-conditioned entries, then 50 steps against the oracle's
+    trajectory (graph mode, so the rule is part of the captured update)."""
+    st = _st()
+    prob = synth.make_deconv(1)
+    d, w, rng = _data(prob, seed=44)
+    p0 = synth.eval_point(prob, "near", rng)
+    lrv = prob.lr_vector()
+    lr4 = [prob.adam_lr[k] for k in ("h", "Gamma", "a", "c")]
+    plan = _plan(prob, d, w, algo=algo)
+    x = torch.tensor(p0, dtype=torch.float32, device="cuda")
+    m = torch.zeros_like(x)
+    v = torch.zeros_like(x)
+    kw = dict(rule=st.ADABELIEF, eps=1e-16, eps_root=1e-16)
+    plan.step(x, m, v, 1, lr4, **kw)
+    po = p0.copy()
+    mo, vo = np.zeros_like(po), np.zeros_like(po)
+    _, go = ora.loss_grad(prob, d, w, po)
+    ora.adabelief_step(po, go, mo, vo, 1, lrv, eps=1e-16, eps_root=1e-16)
+    good = np.abs(go) > 1e-3 * np.abs(go).max()
+    xf = x.cpu().numpy().astype(np.float64)
+    err = np.abs(xf - po)[good] / np.maximum(np.abs(po[good]), lrv[good])
+    _say(f"adabelief single step: {good.sum()} entries, max rel err {err.max():.2e}")
+    assert err.max() <= 1e-5
+    plan.set_graph_mode(True)
+    for t in range(2, 51):
+        plan.step(x, m, v, t, lr4, **kw)
+        _, go = ora.loss_grad(prob, d, w, po)
+        ora.adabelief_step(po, go, mo, vo, t, lrv, eps=1e-16, eps_root=1e-16)
+    plan.set_graph_mode(False)
+    lg = plan.loss_grad(x)[0].cpu().numpy()
+    lo, _ = ora.loss_grad(prob, d, w, po, want_grad=False)
+    cdev = x.cpu().numpy().astype(np.float64)[-2 * prob.M:]
+    _say(f"adabelief 50: loss dev {lg[2]:.6e} oracle {lo[2]:.6e}; c dev {cdev} oracle {po[-2 * prob.M:]}")
+    assert abs(lg[2] - lo[2]) / abs(lo[2]) <= 1e-3
+    assert np.abs(cdev - po[-2 * prob.M:]).max() <= 0.01

@@ -689,3 +689,30 @@ def test_lambda_pts_estimate_special_cases():
     prob3 = synth.DeconvProblem(**{**prob2.__dict__, "J": 2, "W": prob2.W[:2]})
     est3 = ora.lambda_pts_estimate(prob3, p3, lam=2.5)
     assert est3 == pytest.approx(2.5, rel=1e-6)
+
+
+def test_adabelief_first_step_and_constant_gradient_closed_forms():
+    """AdaBelief: after one step from zero moments m_hat = g and
+    v_hat = beta1^2 g^2 + eps_root / (1 - beta2); under a constant gradient
+    m_t = (1 - beta1^t) g and g - m_t = beta1^t g, so v_t is a geometric sum of those
+    squares plus eps_root."""
+    rng = np.random.default_rng(7)
+    g = rng.standard_normal(50)
+    lr, b1, b2, eps, er = 0.01, 0.9, 0.999, 1e-16, 1e-16
+    p = np.zeros(50)
+    m, v = np.zeros(50), np.zeros(50)
+    ora.adabelief_step(p, g, m, v, 1, lr, b1, b2, eps, er)
+    want = -lr * g / (np.sqrt(b1 ** 2 * g ** 2 + er / (1 - b2)) + eps)
+    np.testing.assert_allclose(p, want, rtol=1e-12)
+    np.testing.assert_allclose(m, (1 - b1) * g, rtol=1e-15)
+    # constant gradient for many steps: the recursions have closed forms
+    p = np.zeros(50)
+    m, v = np.zeros(50), np.zeros(50)
+    T = 60
+    for t in range(1, T + 1):
+        ora.adabelief_step(p, g, m, v, t, lr, b1, b2, eps, er)
+    mt = (1 - b1 ** T) * g
+    # v_T = sum_t b2^(T-t) [(1-b2) (b1^t g)^2 + er]
+    vt = sum(b2 ** (T - t) * ((1 - b2) * (b1 ** t * g) ** 2 + er) for t in range(1, T + 1))
+    np.testing.assert_allclose(m, mt, rtol=1e-12)
+    np.testing.assert_allclose(v, vt, rtol=1e-10)
