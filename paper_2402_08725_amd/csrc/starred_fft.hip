@@ -884,33 +884,65 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
     __syncthreads();
     float2 *r = lds_fft_any<true>(A, B, HQ, fl, twQ);  // along ky
     float2 *o = (r == A) ? B : A;
-    // Hermitian rows y < n of the column results
-    for (int y = threadIdx.x / Q0L; y < n; y += kFusedThreads / Q0L)
-        for (int kx = threadIdx.x % Q0L; kx < Q; kx += Q0L)
-            o[y * Ls + kx] = kx < HQ ? r[kx * Ls + y] : conjf2(r[(Q - kx) * Ls + y]);
+    // Rows in pairs (two real rows per complex transform): the inverse of
+    // Z = X_2p + i X_2p+1, X_y the Hermitian rows of the column results, is
+    // x_2p + i x_2p+1; a missing second row (odd n) is zero.
+    const int n2 = (n + 1) / 2;
+    for (int yp = threadIdx.x / Q0L; yp < n2; yp += kFusedThreads / Q0L) {
+        const int ya = 2 * yp, yb = 2 * yp + 1;
+        for (int kx = threadIdx.x % Q0L; kx < Q; kx += Q0L) {
+            const bool lo = kx < HQ;
+            const int col = lo ? kx : Q - kx;
+            float2 xa = r[col * Ls + ya];
+            float2 xb = yb < n ? r[col * Ls + yb] : make_float2(0.f, 0.f);
+            if (!lo) {
+                xa.y = -xa.y;
+                xb.y = -xb.y;
+            }
+            o[yp * Ls + kx] = make_float2(xa.x - xb.y, xa.y + xb.x);  // xa + i xb
+        }
+    }
     __syncthreads();
-    r = lds_fft_any<true>(o, r, n, fl, twQ);  // along x: model in the real parts
+    r = lds_fft_any<true>(o, r, n2, fl, twQ);  // along x: model rows 2p, 2p+1 in the real, imaginary parts
     o = (r == A) ? B : A;
     double chi = 0.0;
-    for (int y = threadIdx.x / Q0L; y < n; y += kFusedThreads / Q0L)
+    for (int yp = threadIdx.x / Q0L; yp < n2; yp += kFusedThreads / Q0L)
         for (int x = threadIdx.x % Q0L; x < Q; x += Q0L) {
-            float v = 0.f;
+            float va = 0.f, vb = 0.f;
             if (x < n) {
-                const long long idx = f.data_off + (long long)y * n + x;
-                const float res = r[y * Ls + x].x - data[idx];
-                const float w = invvar[idx];
-                v = w * res;
-                chi += 0.5 * (double)w * (double)res * (double)res;
+                const float2 mv = r[yp * Ls + x];
+                const long long ia = f.data_off + (long long)(2 * yp) * n + x;
+                const float ra = mv.x - data[ia], wa = invvar[ia];
+                va = wa * ra;
+                chi += 0.5 * (double)wa * (double)ra * (double)ra;
+                if (2 * yp + 1 < n) {
+                    const long long ib = ia + n;
+                    const float rb = mv.y - data[ib], wb = invvar[ib];
+                    vb = wb * rb;
+                    chi += 0.5 * (double)wb * (double)rb * (double)rb;
+                }
             }
-            o[y * Ls + x] = make_float2(v, 0.f);
+            o[yp * Ls + x] = make_float2(va, vb);  // rho rows 2p + i (2p+1)
         }
     const double tchi = block_sum_d_fft<kFusedThreads>(chi, red);  // synchronises
     if (threadIdx.x == 0) part_chi[blockIdx.x] = tchi;
-    r = lds_fft_any<false>(o, r, n, fl, twQ);  // rho along x
+    r = lds_fft_any<false>(o, r, n2, fl, twQ);  // rho pairs along x
     o = (r == A) ? B : A;
-    // column-major half spectrum, zero rows y >= n
-    if (lane < HQ)
-        for (int y = rg; y < Q; y += RGF) o[lane * Ls + y] = y < n ? r[y * Ls + lane] : make_float2(0.f, 0.f);
+    // split each pair's spectrum Z into the two rows' (Hermitian) spectra,
+    // R_a = (Z(k) + conj Z(-k)) / 2 and R_b = (Z(k) - conj Z(-k)) / 2i, and lay the
+    // half spectra out column-major with zero rows y >= n
+    if (lane < HQ) {
+        const int km = lane == 0 ? 0 : Q - lane;
+        for (int y = rg; y < Q; y += RGF) {
+            float2 v = make_float2(0.f, 0.f);
+            if (y < n) {
+                const float2 z = r[(y >> 1) * Ls + lane], zm = r[(y >> 1) * Ls + km];
+                v = (y & 1) ? make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x))
+                            : make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+            }
+            o[lane * Ls + y] = v;
+        }
+    }
     __syncthreads();
     r = lds_fft_any<false>(o, r, HQ, fl, twQ);  // along y
     float2 *R = Rh + f.r_off;
