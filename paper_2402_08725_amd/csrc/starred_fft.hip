@@ -841,19 +841,27 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
     constexpr int MR = MS > 0 ? MS : 1;
     if (lane < HQ) {
         const int kx = lane;
+        const int HP = P / 2 + 1;
         float2 wxG[S], px[S][MR];
+        // half-spectrum access of the column aliases Kx_b (Hermitian fold for Kx >= P/2+1)
+        bool lob[S];
+        int rxb[S];
         #pragma unroll
         for (int b = 0; b < S; ++b) {
-            wxG[b] = cscale(t[kx + b * Q], G);
+            const int Kx = kx + b * Q;
+            lob[b] = Kx < HP;
+            rxb[b] = lob[b] ? Kx : P - Kx;
+            wxG[b] = cscale(t[Kx], G);
             #pragma unroll
             for (int k = 0; k < MR; ++k)
-                px[b][k] = (MS > 0 && k < M) ? cscale(t[(1 + 4 * k) * P + kx + b * Q], ai[k]) : make_float2(0.f, 0.f);
+                px[b][k] = (MS > 0 && k < M) ? cscale(t[(1 + 4 * k) * P + Kx], ai[k]) : make_float2(0.f, 0.f);
         }
         for (int ky = rg; ky < Q; ky += RGF) {
             float2 acc = make_float2(0.f, 0.f);
             #pragma unroll
             for (int a = 0; a < S; ++a) {
                 const int Ky = ky + a * Q;
+                const int rlo = Ky * HP, rhi = (Ky == 0 ? 0 : P - Ky) * HP;
                 const float2 wy = t[Ky];
                 float2 gy[MR];
                 #pragma unroll
@@ -862,7 +870,13 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
                 #pragma unroll
                 for (int b = 0; b < S; ++b) {
                     const int Kx = kx + b * Q;
-                    float2 F = cadd(half_get(Hc, P, Ky, Kx), cmul(wy, wxG[b]));
+                    const int hidx = (lob[b] ? rlo : rhi) + rxb[b];
+                    float2 hv = Hc[hidx], sv = Si[hidx];
+                    if (!lob[b]) {
+                        hv.y = -hv.y;
+                        sv.y = -sv.y;
+                    }
+                    float2 F = cadd(hv, cmul(wy, wxG[b]));
                     if (MS > 0) {
                         #pragma unroll
                         for (int k = 0; k < MR; ++k) {
@@ -875,7 +889,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
                             F = cadd(F, cscale(cmul(tk[P + Ky], tk[Kx]), ai[k]));
                         }
                     }
-                    acc = cadd(acc, cmul(half_get(Si, P, Ky, Kx), F));
+                    acc = cadd(acc, cmul(sv, F));
                 }
             }
             A[kx * Ls + ky] = acc;
@@ -1064,6 +1078,7 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const SpecItem *__rest
             const int rx = lo ? kxq : Q - kxq;
             const float cj = lo ? 1.f : -1.f;
             int ryq = (y0 + rg) % Q;
+            #pragma unroll 3
             for (int Ky = y0 + rg; Ky < y1; Ky += RG) {
                 float2 ty[NY];
                 #pragma unroll
@@ -1157,6 +1172,7 @@ __global__ void k_adj_sums(const ClassFft *__restrict__ classes, int ncls, int g
             if (g < nbins) {
                 float2 *gp = Gp + c.gp_off + g;
                 float2 acc = gp[0];
+                #pragma unroll 8
                 for (int ch = 1; ch < c.ngch; ++ch) acc = cadd(acc, gp[(long long)ch * nbins]);
                 gp[0] = acc;
                 return;
