@@ -76,8 +76,8 @@ def cpu_baseline(prob_name, budget_s=12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--algo", default="auto", choices=["auto", "direct", "fft"])
     ap.add_argument("--no-cpu-baseline", action="store_true")

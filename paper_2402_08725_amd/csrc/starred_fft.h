@@ -154,6 +154,12 @@ hipError_t fft_resid_rows(hipStream_t st, const FftPlanDev &d, const float *resi
 hipError_t fft_adjoint(hipStream_t st, const FftPlanDev &d, float *g);
 hipError_t fft_spec_adj(hipStream_t st, const FftPlanDev &d, int M);
 hipError_t fft_adj_sums(hipStream_t st, const FftPlanDev &d, int M, double *fsum);
+struct FinalArgs;
+// dL/dh of the classes: the column inverse alone, and (one class whose window
+// is the whole grid) the row inverse that also writes dL/dh, updates h and does
+// the evaluation's small reductions in an extra work group
+hipError_t fft_grad_h_cols(hipStream_t st, const FftPlanDev &d);
+hipError_t fft_grad_h_rows_final(hipStream_t st, const FftPlanDev &d, const float *prior, const FinalArgs &fin);
 // bytes of LDS the one-launch forward needs for a class: two planes of
 // max(Q/2+1, n) lines of Q+1 values, the Q twiddles and the (1+4M) P table values
 inline size_t fused_lds_bytes(int Q, int n, int P, int M)

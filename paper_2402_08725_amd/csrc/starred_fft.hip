@@ -18,6 +18,7 @@
 // fuse the spectral products, the Hermitian extensions, the crops and the
 // residual / chi-square epilogue.
 #include "starred_fft.h"
+#include "starred_finalize.h"
 
 #include <hip/hip_runtime.h>
 
@@ -1231,6 +1232,40 @@ struct OpGRows {
     }
 };
 
+// dL/dh of a single class whose window is the whole grid, written by the inverse
+// rows themselves: the prior's gradient plus the row value, and the update of h
+// in a step; one extra work group does the evaluation's small reductions.
+struct OpGRowsFin {
+    const float2 *Th;
+    const float *prior;
+    FinalArgs fin;
+    int n_items;
+    int *tick;  // the line launch's own counter hook: unused (null)
+    static constexpr bool extra = true;
+    static constexpr bool col = false;
+    static constexpr bool rowsum = false;
+    static constexpr bool inverse = true;
+    __device__ void run_extra(int xb, const ClassFft *, const float2 *) const
+    {
+        if (xb == 0) finalize_small_body<kFftThreads>(fin);
+    }
+    __device__ const FftLen &len(const ClassFft &c) const { return c.fP; }
+    __device__ float2 load(const ClassFft &c, int, int y, int Kx) const
+    {
+        const int P = c.P, H = P / 2 + 1;
+        const float2 *row = Th + c.th_off + (long long)y * H;
+        return Kx < H ? row[Kx] : conjf2(row[P - Kx]);
+    }
+    __device__ void store(const ClassFft &c, int, int y, int x, float2 v) const
+    {
+        if (x >= c.F) return;
+        const long long pix = (long long)y * fin.N + x;
+        float bc1, bc2;
+        adam_bias(fin.adam, bc1, bc2);
+        finalize_h_pixel(fin.adam, bc1, bc2, pix, (prior ? prior[pix] : 0.f) + v.x, fin.grad);
+    }
+};
+
 // --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
@@ -1392,6 +1427,19 @@ hipError_t fft_adj_sums(hipStream_t st, const FftPlanDev &d, int M, double *fsum
     if (gblocks + fblocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_adj_sums, dim3(gblocks + fblocks), dim3(256), 0, st, d.classes, d.n_classes, gblocks,
                        d.frames, d.n_frames, M, d.maxpb, d.Gp, d.apart, fsum);
+    return hipGetLastError();
+}
+
+hipError_t fft_grad_h_cols(hipStream_t st, const FftPlanDev &d)
+{
+    return run_lines(st, d.gcols, d.classes, d.tw, OpGCols{d.Gp, d.Th});
+}
+
+hipError_t fft_grad_h_rows_final(hipStream_t st, const FftPlanDev &d, const float *prior, const FinalArgs &fin)
+{
+    const OpGRowsFin op{d.Th, prior, fin, d.grows.n_items, nullptr};
+    hipLaunchKernelGGL((k_lines<OpGRowsFin>), dim3(d.grows.n_items + 1), dim3(kFftThreads), d.grows.lds_bytes, st,
+                       d.grows.items, d.classes, d.tw, op);
     return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 // reduced in FP64 with fixed (deterministic) trees. No floating-point atomics.
 #include "starred_internal.h"
 #include "starred_fft.h"
+#include "starred_finalize.h"
 
 #include <hip/hip_runtime.h>
 
@@ -537,118 +538,33 @@ hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, c
     return hipGetLastError();
 }
 
-// loss[0] = sum chi partials, loss[1] = sum L1 partials, loss[2] = total;
-// grad Gamma, a, c from the per-frame sums (frames summed in order).
-// Block 0 does these small reductions, one wave per reduced quantity (lanes
-// stride the items, then a fixed shuffle tree), so none waits for another.
-// When classes is given, blocks 1.. assemble dL/dh of the FFT path: the prior
-// gradient plus the window contribution of every shape class, in class order.
+// Block 0: the small reductions and updates (finalize_small_body). When classes
+// is given, blocks 1.. assemble dL/dh of the FFT path: the prior gradient plus the
+// window contribution of every shape class, in class order (and update h).
 constexpr int kFinThreads = 1024;
 
-__global__ __launch_bounds__(kFinThreads) void k_finalize_small(
-    int E, int M, int n_chi, const double *__restrict__ part_chi, int n_l1,
-    const double *__restrict__ part_l1, const double *__restrict__ fsum,
-    const float *__restrict__ params, int N, float *__restrict__ grad, double *__restrict__ loss,
-    const int *__restrict__ gcsr_off, const int *__restrict__ gcsr_item, const double *__restrict__ gpart,
-    int *__restrict__ tick, const ClassFft *__restrict__ classes, int ncls, const float *__restrict__ hcls,
-    const float *__restrict__ prior, AdamDev adam, const double *__restrict__ pts)
+__global__ __launch_bounds__(kFinThreads) void k_finalize_small(FinalArgs fa, const ClassFft *__restrict__ classes,
+                                                                int ncls, const float *__restrict__ hcls,
+                                                                const float *__restrict__ prior)
 {
-    const long long NN = (long long)N * N;
-    const int stride = 1 + 3 * M;
-    auto fs = [&](long long i, int q) -> double { return fsum[i * stride + q]; };
-    // step mode: the Adam update of every parameter follows its gradient here
-    float bc1 = 1.f, bc2 = 1.f;
-    if (adam.params) {
-        const float t = (float)(*adam.d_t);
-        bc1 = 1.f - powf(adam.beta1, t);
-        bc2 = 1.f - powf(adam.beta2, t);
-    }
-    if (blockIdx.x > 0) {
-        const long long pix = (long long)(blockIdx.x - 1) * kFinThreads + threadIdx.x;
-        if (pix >= NN) return;
-        const int Y = (int)(pix / N), X = (int)(pix % N);
-        float acc = prior ? prior[pix] : 0.f;
-        for (int ci = 0; ci < ncls; ++ci) {
-            const ClassFft &c = classes[ci];
-            const int y = Y - c.o, x = X - c.o, F = c.F;
-            if (y >= 0 && y < F && x >= 0 && x < F) acc += hcls[c.hc_off + (long long)y * F + x];
-        }
-        grad[pix] = acc;
-        if (adam.params) {
-            float pi = adam.params[pix], mi = adam.m[pix], vi = adam.v[pix];
-            adam_update(pi, mi, vi, acc, adam.lr[0], adam.beta1, adam.beta2, bc1, bc2, adam.eps, adam.rule == 1,
-                        adam.eps_root);
-            adam.m[pix] = mi;
-            adam.v[pix] = vi;
-            adam.params[pix] = pi;
-        }
+    if (blockIdx.x == 0) {
+        finalize_small_body<kFinThreads>(fa);
         return;
     }
-    if (tick && threadIdx.x == 0) *tick += 1;  // the Adam step that follows reads it
-    __shared__ double sums[2];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    constexpr int NW = kFinThreads / 64;
-    const float *pa = params + NN + E;
-    const int nred = 2 + (grad ? 2 * M : 0);
-    for (int r = wv; r < nred; r += NW) {
-        double acc = 0.0;
-        if (r == 0) {
-            for (int i = lane; i < n_chi; i += 64) acc += part_chi[i];
-        } else if (r == 1) {
-            for (int i = lane; i < n_l1; i += 64) acc += part_l1[i];
-        } else {
-            // dL/dc_k = sum_i a_ik <g_i, dr_k/dc>
-            const int q = r - 2, k = q >> 1, axis = q & 1;
-            for (int i = lane; i < E; i += 64)
-                acc += (double)pa[(long long)i * M + k] * fs(i, 1 + (1 + axis) * M + k);
-        }
-        #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (lane == 0) {
-            if (r < 2) sums[r] = acc;
-            else {
-                // plus the point-source prior's share (pts[3k+1+axis])
-                const int q = r - 2;
-                if (pts) acc += pts[3 * (q >> 1) + 1 + (q & 1)];
-                grad[NN + E + (long long)E * M + q] = (float)acc;
-            }
-        }
+    const int N = fa.N;
+    const long long NN = (long long)N * N;
+    const long long pix = (long long)(blockIdx.x - 1) * kFinThreads + threadIdx.x;
+    if (pix >= NN) return;
+    float bc1, bc2;
+    adam_bias(fa.adam, bc1, bc2);
+    const int Y = (int)(pix / N), X = (int)(pix % N);
+    float acc = prior ? prior[pix] : 0.f;
+    for (int ci = 0; ci < ncls; ++ci) {
+        const ClassFft &c = classes[ci];
+        const int y = Y - c.o, x = X - c.o, F = c.F;
+        if (y >= 0 && y < F && x >= 0 && x < F) acc += hcls[c.hc_off + (long long)y * F + x];
     }
-    __syncthreads();
-    if (threadIdx.x == 0 && loss) {
-        loss[0] = sums[0];
-        loss[1] = sums[1];
-        loss[2] = sums[0] + sums[1];
-    }
-    if (!grad) return;
-    float *gG = grad + NN, *ga = gG + E;
-    for (int i = threadIdx.x; i < E; i += kFinThreads) {
-        if (gcsr_off) {
-            double acc = 0.0;
-            for (int q = gcsr_off[i]; q < gcsr_off[i + 1]; ++q) acc += gpart[gcsr_item[q]];
-            gG[i] = (float)acc;
-        } else {
-            gG[i] = (float)fs(i, 0);
-        }
-    }
-    for (long long e = threadIdx.x; e < (long long)E * M; e += kFinThreads) {
-        const long long i = e / M, k = e - i * M;
-        ga[e] = (float)(fs(i, 1 + (int)k) + (pts ? pts[3 * k] : 0.0));
-    }
-    if (!adam.params) return;
-    // Gamma, a and c after their gradients (written above by this block) are final;
-    // the a values read for dL/dc were taken before this point
-    __syncthreads();
-    const long long e1 = NN + E, e2 = e1 + (long long)E * M, e3 = e2 + 2LL * M;
-    for (long long e = NN + threadIdx.x; e < e3; e += kFinThreads) {
-        const float lr = e < e1 ? adam.lr[1] : (e < e2 ? adam.lr[2] : adam.lr[3]);
-        float pi = adam.params[e], mi = adam.m[e], vi = adam.v[e];
-        adam_update(pi, mi, vi, grad[e], lr, adam.beta1, adam.beta2, bc1, bc2, adam.eps, adam.rule == 1,
-                    adam.eps_root);
-        adam.m[e] = mi;
-        adam.v[e] = vi;
-        adam.params[e] = pi;
-    }
+    finalize_h_pixel(fa.adam, bc1, bc2, pix, acc, fa.grad);
 }
 
 hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const double *part_chi,
@@ -662,9 +578,25 @@ hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const 
     const int hblocks = (classes && grad) ? (int)((NN + kFinThreads - 1) / kFinThreads) : 0;
     // a fused Adam update needs the h blocks (FFT path) and the gradient
     if (adam.params && (!hblocks || !grad)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_finalize_small, dim3(1 + hblocks), dim3(kFinThreads), 0, st, E, M, n_chi, part_chi,
-                       n_l1, part_l1, fsum, params, N, grad, loss, gcsr_off, gcsr_item, gpart, tick, classes, ncls,
-                       hcls, prior, adam, pts);
+    FinalArgs fa;
+    fa.E = E;
+    fa.M = M;
+    fa.N = N;
+    fa.n_chi = n_chi;
+    fa.n_l1 = n_l1;
+    fa.part_chi = part_chi;
+    fa.part_l1 = part_l1;
+    fa.fsum = fsum;
+    fa.params = params;
+    fa.grad = grad;
+    fa.loss = loss;
+    fa.gcsr_off = gcsr_off;
+    fa.gcsr_item = gcsr_item;
+    fa.gpart = gpart;
+    fa.tick = tick;
+    fa.adam = adam;
+    fa.pts = pts;
+    hipLaunchKernelGGL(k_finalize_small, dim3(1 + hblocks), dim3(kFinThreads), 0, st, fa, classes, ncls, hcls, prior);
     return hipGetLastError();
 }
 

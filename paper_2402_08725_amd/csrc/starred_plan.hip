@@ -2,6 +2,7 @@
 // work lists, scratch ownership and the launch sequences of loss_grad / step.
 #include "starred.h"
 #include "starred_fft.h"
+#include "starred_finalize.h"
 #include "starred_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -920,6 +921,9 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     int rc = starlet_branch(p, params, grad != nullptr, &n_l1);
     if (rc) return rc;
     const bool fused = fft && p->fft_fused && p->fd.n_fused > 0;
+    // one class covering the whole grid: the row inverse of dL/dh carries the final
+    // reductions and the update (one launch fewer)
+    const bool fin_rows = fft && grad && p->fd.n_classes == 1 && p->cls[0].F == p->N;
     if (fft) {
         e0 = p->prof_start();
         // with the fused update the counter advances in the first launch of the step
@@ -975,7 +979,7 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
             HIP_TRY(fft_adj_sums(p->st, p->fd, p->M, p->d_fsum));
             p->prof_stop(STARRED_STAGE_FFT_FSUM, e1);
             e1 = p->prof_start();
-            HIP_TRY(fft_grad_h_inverse(p->st, p->fd));
+            HIP_TRY(fin_rows ? fft_grad_h_cols(p->st, p->fd) : fft_grad_h_inverse(p->st, p->fd));
             p->prof_stop(STARRED_STAGE_FFT_AROWS, e1);
         } else
             HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ar_max,
@@ -989,6 +993,26 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     }
     HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
     e0 = p->prof_start();
+    if (fin_rows) {
+        FinalArgs fa;
+        fa.E = p->E;
+        fa.M = p->M;
+        fa.N = p->N;
+        fa.n_chi = n_chi;
+        fa.n_l1 = n_l1;
+        fa.part_chi = part_chi;
+        fa.part_l1 = p->d_part_l1;
+        fa.fsum = p->d_fsum;
+        fa.params = params;
+        fa.grad = grad;
+        fa.loss = loss_out;
+        fa.tick = adam ? nullptr : tick;
+        if (adam) fa.adam = *adam;
+        fa.pts = p->lam_pts != 0.0 ? p->d_pts : nullptr;
+        HIP_TRY(fft_grad_h_rows_final(p->st, p->fd, p->d_prior, fa));
+        p->prof_stop(STARRED_STAGE_FINALIZE, e0);
+        return STARRED_OK;
+    }
     // FFT path: dL/dh from the classes' window contributions in the same launch
     if (grad && !fft)
         HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad, p->d_hpart));
