@@ -171,6 +171,37 @@ int starred_loss_grad_plain(starred_plan *plan, const float *params, float *grad
 int starred_step(starred_plan *plan, float *params, float *m, float *v, int32_t t,
                  const starred_adam *hp, double *loss_out);
 
+/* L-BFGS (limited-memory BFGS, Nocedal & Wright Alg. 7.4-7.5), the quasi-Newton
+ * method of the paper's PSF fits, on the plan's loss. A state holds the history
+ * of the last m pairs (s, y) ([m][num_params] floats each, allocated here), the
+ * gradient at the current point and the loss there. Optional box bounds lo, hi
+ * (device, num_params floats each, referenced, may be NULL): every trial point is
+ * clipped into the box (a projected search, not the Cauchy-point machinery of
+ * L-BFGS-B). Each iteration: direction d = -H g by the two-loop recursion
+ * (steepest descent when the history is empty or d is not a descent direction),
+ * backtracking from step 1 (1/|g| without history) by halves until the Armijo
+ * condition f(x_t) <= f(x) + 1e-4 g^T (x_t - x) holds (at most 40 trials; none
+ * ends the run), then the full gradient at the accepted point and the new pair
+ * (kept when s^T y > 1e-12 y^T y). The vector work runs in kernels; the accept
+ * decisions read each trial's loss on the host (the calls synchronise). */
+/* The two-loop recursion alone (Nocedal & Wright Alg. 7.4): d_out = -H grad for the
+ * `count` newest pairs of the caller's ring buffers S, Y ([m][num_params] floats,
+ * device, newest pair at slot `newest`, older ones before it modulo m) and
+ * H_0 = gamma I, gamma = s^T y / y^T y of the newest pair; count = 0: -grad.
+ * count <= min(m, 1024). One launch on the plan's stream. */
+int starred_lbfgs_direction(starred_plan *plan, const float *grad, const float *S, const float *Y, int32_t m,
+                            int32_t count, int32_t newest, float *d_out);
+
+typedef struct starred_lbfgs starred_lbfgs;
+int starred_lbfgs_create(starred_plan *plan, int32_t m, const float *lo, const float *hi, starred_lbfgs **state_out);
+int starred_lbfgs_destroy(starred_lbfgs *state);
+/* Forget the history and the stored gradient (call after changing x elsewhere). */
+int starred_lbfgs_reset(starred_lbfgs *state);
+/* n_iter iterations from x (device, num_params floats, updated in place; it must
+ * not change between calls except here, else reset first). *loss_out (host): the
+ * loss at the final x; *n_evals_out (host, may be NULL): loss evaluations used. */
+int starred_lbfgs_run(starred_lbfgs *state, float *x, int32_t n_iter, double *loss_out, int32_t *n_evals_out);
+
 /* Graph mode. When enabled, starred_loss_grad and starred_step capture their
  * launch sequence into a HIP graph on the first call and replay it while the
  * argument pointers (and, for step, the Adam hyper-parameters) stay the same;

@@ -42,7 +42,8 @@ def lib():
         for name in ["ora_render_scene", "ora_conv_sub", "ora_conv_sub_adj", "ora_starlet_fwd",
                      "ora_starlet_adj", "ora_loss_grad", "ora_forward_model", "ora_moffat",
                      "ora_psf_render", "ora_psf_model", "ora_psf_loss_grad", "ora_adam_step",
-                     "ora_noise_variance", "ora_noise_weights_mc", "ora_pts_term", "ora_adabelief_step"]:
+                     "ora_noise_variance", "ora_noise_weights_mc", "ora_pts_term", "ora_adabelief_step",
+                     "ora_lbfgs_direction"]:
             getattr(_lib, name).restype = None
         _lib.ora_philox4x32_10.restype = None
         _lib.ora_lambda_pts_estimate.restype = ctypes.c_double
@@ -272,3 +273,13 @@ def adabelief_step(params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-16,
     lib().ora_adabelief_step(ctypes.c_long(params.size), _d(params), _d(grad), _d(m), _d(v), t, _d(lr),
                              ctypes.c_double(beta1), ctypes.c_double(beta2), ctypes.c_double(eps),
                              ctypes.c_double(eps_root))
+
+
+def lbfgs_direction(g, S, Y, count, newest):
+    """L-BFGS two-loop recursion: d = -H g from the ring buffers S, Y ([m][n])."""
+    g = _f64(g)
+    S, Y = _f64(S), _f64(Y)
+    m, n = S.shape
+    d = np.zeros(n)
+    lib().ora_lbfgs_direction(ctypes.c_long(n), _d(g), _d(S), _d(Y), m, count, newest, _d(d))
+    return d

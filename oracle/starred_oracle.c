@@ -964,6 +964,55 @@ void ora_adabelief_step(long P, double *params, const double *grad, double *m, d
     }
 }
 
+/* L-BFGS two-loop recursion (Nocedal & Wright, Numerical Optimization, Alg. 7.4):
+ * d = -H g for the inverse-Hessian approximation built from the `count` newest
+ * pairs (s_i, y_i) of the ring buffers S, Y ([m][n], newest at slot `newest`,
+ * older ones before it modulo m) and H_0 = gamma I, gamma = s^T y / y^T y of the
+ * newest pair. count = 0 gives d = -g. */
+void ora_lbfgs_direction(long n, const double *g, const double *S, const double *Y, int m, int count, int newest,
+                         double *d)
+{
+    double *q = (double *)malloc(sizeof(double) * n);
+    double *alpha = (double *)malloc(sizeof(double) * (m > 0 ? m : 1));
+    for (long p = 0; p < n; ++p) q[p] = g[p];
+    for (int c = 0; c < count; ++c) {
+        const int i = ((newest - c) % m + m) % m;
+        const double *s = S + (long)i * n, *y = Y + (long)i * n;
+        double sy = 0.0, sq = 0.0;
+        for (long p = 0; p < n; ++p) {
+            sy += s[p] * y[p];
+            sq += s[p] * q[p];
+        }
+        alpha[c] = sq / sy;
+        for (long p = 0; p < n; ++p) q[p] -= alpha[c] * y[p];
+    }
+    double gamma = 1.0;
+    if (count > 0) {
+        const double *s = S + (long)newest * n, *y = Y + (long)newest * n;
+        double sy = 0.0, yy = 0.0;
+        for (long p = 0; p < n; ++p) {
+            sy += s[p] * y[p];
+            yy += y[p] * y[p];
+        }
+        gamma = sy / yy;
+    }
+    for (long p = 0; p < n; ++p) q[p] *= gamma;
+    for (int c = count - 1; c >= 0; --c) {
+        const int i = ((newest - c) % m + m) % m;
+        const double *s = S + (long)i * n, *y = Y + (long)i * n;
+        double sy = 0.0, yr = 0.0;
+        for (long p = 0; p < n; ++p) {
+            sy += s[p] * y[p];
+            yr += y[p] * q[p];
+        }
+        const double beta = yr / sy;
+        for (long p = 0; p < n; ++p) q[p] += s[p] * (alpha[c] - beta);
+    }
+    for (long p = 0; p < n; ++p) d[p] = -q[p];
+    free(q);
+    free(alpha);
+}
+
 int ora_num_threads(void)
 {
 #ifdef _OPENMP

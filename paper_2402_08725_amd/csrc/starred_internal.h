@@ -170,6 +170,15 @@ hipError_t launch_noise_finish(hipStream_t st, int J, long long NN, int R, int p
                                const double *s2, float *W);
 hipError_t launch_fill_d(hipStream_t st, double *p, long long n);
 
+// L-BFGS vector kernels (starred_opt.hip)
+hipError_t launch_lbfgs_direction(hipStream_t st, long long n, const float *g, const float *S, const float *Y, int m,
+                                  int count, int newest, float *d, double *alpha_scratch);
+hipError_t launch_trial_point(hipStream_t st, long long n, const float *x, const float *d, float step, const float *lo,
+                              const float *hi, float *xt);
+hipError_t launch_dots(hipStream_t st, long long n, const float *a, const float *b, const float *c, double *out);
+hipError_t launch_history(hipStream_t st, long long n, const float *xn, float *xo, const float *gn, float *go,
+                          float *s, float *y, int store);
+
 // PSF mode (starred_psf.hip)
 hipError_t launch_psf_render(hipStream_t st, int N, const float *params, float *s_out);
 hipError_t launch_psf_render64(hipStream_t st, int N, const float *params, double *s64);

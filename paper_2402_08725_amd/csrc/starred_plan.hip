@@ -87,6 +87,7 @@ struct starred_plan {
     double lam_pts = 0.0;
     float *d_pair = nullptr;
     double *d_pts = nullptr;
+    double *d_lbfgs_alpha = nullptr;  // two-loop coefficients of starred_lbfgs_direction
     // its App. C estimate: images [f | h | r_k], L1 partials, norms and <a_k>
     float *est_img = nullptr;
     double *est_part = nullptr, *est_out = nullptr;
@@ -1486,6 +1487,174 @@ int starred_noise_weights(starred_plan *p, int32_t frame, const float *sigma2_da
     }
     HIP_TRY(launch_noise_finish(p->st, J, NN, n_real, per_pixel, p->nz_s1, p->nz_s2, W_out));
     HIP_TRY(hipStreamSynchronize(p->st));
+    return STARRED_OK;
+}
+
+// ---------------------------------------------------------------------------
+// L-BFGS (Nocedal & Wright Alg. 7.4 and 7.5) with a backtracking Armijo search
+// on projected trial points; the vector work runs in kernels, the control flow
+// (accept / halve) on the host from the loss values.
+// ---------------------------------------------------------------------------
+extern "C++" {
+struct starred_lbfgs {
+    starred_plan *p = nullptr;
+    int m = 0;
+    long long n = 0;
+    const float *lo = nullptr, *hi = nullptr;
+    float *S = nullptr, *Y = nullptr, *g = nullptr, *gn = nullptr, *d = nullptr, *xt = nullptr;
+    double *alpha = nullptr, *dots = nullptr, *loss = nullptr;
+    int count = 0, newest = -1;
+    bool have_g = false;
+    double f = 0.0;
+    std::vector<void *> owned;
+    ~starred_lbfgs()
+    {
+        for (void *q : owned) (void)hipFree(q);
+    }
+    template <typename T>
+    int alloc(T **q, size_t cnt)
+    {
+        int rc = dev_alloc(q, cnt);
+        if (rc == STARRED_OK) owned.push_back((void *)*q);
+        return rc;
+    }
+};
+}  // extern "C++"
+
+int starred_lbfgs_direction(starred_plan *p, const float *grad, const float *S, const float *Y, int32_t m,
+                            int32_t count, int32_t newest, float *d_out)
+{
+    if (!p || !grad || !d_out || (count > 0 && (!S || !Y))) return fail(STARRED_EINVAL, "NULL argument");
+    if (m < 1 || count < 0 || count > m || (count > 0 && (newest < 0 || newest >= m)))
+        return fail(STARRED_EINVAL, "history indices out of range");
+    if (!p->d_lbfgs_alpha) {
+        int rc = p->alloc(&p->d_lbfgs_alpha, 1024);
+        if (rc) return rc;
+    }
+    if (count > 1024) return fail(STARRED_EINVAL, "history longer than 1024");
+    HIP_TRY(launch_lbfgs_direction(p->st, p->nparams, grad, S, Y, m, count, count > 0 ? newest : 0, d_out,
+                                   p->d_lbfgs_alpha));
+    return STARRED_OK;
+}
+
+int starred_lbfgs_create(starred_plan *p, int32_t m, const float *lo, const float *hi, starred_lbfgs **out)
+{
+    if (!p || !out) return fail(STARRED_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (m < 1) return fail(STARRED_EINVAL, "history length must be >= 1");
+    starred_lbfgs *L = new starred_lbfgs();
+    L->p = p;
+    L->m = m;
+    L->n = p->nparams;
+    L->lo = lo;
+    L->hi = hi;
+    int rc = L->alloc(&L->S, (size_t)m * L->n);
+    if (!rc) rc = L->alloc(&L->Y, (size_t)m * L->n);
+    if (!rc) rc = L->alloc(&L->g, (size_t)L->n);
+    if (!rc) rc = L->alloc(&L->gn, (size_t)L->n);
+    if (!rc) rc = L->alloc(&L->d, (size_t)L->n);
+    if (!rc) rc = L->alloc(&L->xt, (size_t)L->n);
+    if (!rc) rc = L->alloc(&L->alpha, (size_t)m);
+    if (!rc) rc = L->alloc(&L->dots, 2);
+    if (!rc) rc = L->alloc(&L->loss, 3);
+    if (rc) {
+        delete L;
+        return rc;
+    }
+    *out = L;
+    return STARRED_OK;
+}
+
+int starred_lbfgs_destroy(starred_lbfgs *L)
+{
+    if (!L) return fail(STARRED_EINVAL, "state is NULL");
+    if (L->p && L->p->st) (void)hipStreamSynchronize(L->p->st);
+    delete L;
+    return STARRED_OK;
+}
+
+int starred_lbfgs_reset(starred_lbfgs *L)
+{
+    if (!L) return fail(STARRED_EINVAL, "state is NULL");
+    L->count = 0;
+    L->newest = -1;
+    L->have_g = false;
+    return STARRED_OK;
+}
+
+static int read_doubles(starred_plan *p, const double *dev, double *host, int k)
+{
+    HIP_TRY(hipMemcpyAsync(host, dev, sizeof(double) * k, hipMemcpyDeviceToHost, p->st));
+    HIP_TRY(hipStreamSynchronize(p->st));
+    return STARRED_OK;
+}
+
+int starred_lbfgs_run(starred_lbfgs *L, float *x, int32_t n_iter, double *loss_out, int32_t *n_evals_out)
+{
+    if (!L || !x) return fail(STARRED_EINVAL, "NULL argument");
+    starred_plan *p = L->p;
+    if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
+    const long long n = L->n;
+    int evals = 0, rc;
+    double h[3];
+    auto evaluate = [&](const float *at, float *grad_out) -> int {
+        int r = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, at, grad_out, L->loss)
+                                         : loss_grad_impl(p, at, grad_out, L->loss);
+        if (r) return r;
+        ++evals;
+        return read_doubles(p, L->loss, h, 3);
+    };
+    if (!L->have_g) {
+        if ((rc = evaluate(x, L->g))) return rc;
+        L->f = h[2];
+        L->have_g = true;
+    }
+    for (int it = 0; it < n_iter; ++it) {
+        HIP_TRY(launch_lbfgs_direction(p->st, n, L->g, L->S, L->Y, L->m, L->count, L->newest, L->d, L->alpha));
+        HIP_TRY(launch_dots(p->st, n, L->g, L->d, nullptr, L->dots));
+        double gd[2];
+        if ((rc = read_doubles(p, L->dots, gd, 2))) return rc;
+        if (!(gd[0] < 0.0)) {
+            // not a descent direction: forget the history, steepest descent
+            L->count = 0;
+            L->newest = -1;
+            HIP_TRY(launch_lbfgs_direction(p->st, n, L->g, L->S, L->Y, L->m, 0, 0, L->d, L->alpha));
+        }
+        double step = L->count == 0 ? 1.0 / std::max(1.0, std::sqrt(gd[1])) : 1.0;
+        bool ok = false;
+        for (int ls = 0; ls < 40; ++ls) {
+            HIP_TRY(launch_trial_point(p->st, n, x, L->d, (float)step, L->lo, L->hi, L->xt));
+            if ((rc = evaluate(L->xt, nullptr))) return rc;
+            const double ft = h[2];
+            HIP_TRY(launch_dots(p->st, n, L->g, L->xt, x, L->dots));  // g^T (xt - x)
+            double dec[2];
+            if ((rc = read_doubles(p, L->dots, dec, 2))) return rc;
+            if (ft <= L->f + 1e-4 * dec[0] && dec[0] < 0.0) {
+                ok = true;
+                break;
+            }
+            step *= 0.5;
+        }
+        if (!ok) break;  // no decrease along the direction: converged to rounding
+        if ((rc = evaluate(L->xt, L->gn))) return rc;
+        L->f = h[2];
+        // history slot for (s, y); x <- xt, g <- gn
+        const int slot = (L->newest + 1) % L->m;
+        HIP_TRY(launch_history(p->st, n, L->xt, x, L->gn, L->g, L->S + (long long)slot * n, L->Y + (long long)slot * n,
+                               1));
+        HIP_TRY(launch_dots(p->st, n, L->S + (long long)slot * n, L->Y + (long long)slot * n, nullptr, L->dots));
+        double sy[2];
+        if ((rc = read_doubles(p, L->dots, sy, 2))) return rc;
+        if (sy[0] > 1e-12 * sy[1]) {
+            L->newest = slot;
+            L->count = std::min(L->count + 1, L->m);
+        } else {
+            // no positive curvature: the pair is dropped (its slot held the oldest pair)
+            L->count = std::min(L->count, L->m - 1);
+        }
+    }
+    if (loss_out) *loss_out = L->f;
+    if (n_evals_out) *n_evals_out = evals;
     return STARRED_OK;
 }
 

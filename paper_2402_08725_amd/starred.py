@@ -91,6 +91,11 @@ def lib():
         L.starred_noise_weights.argtypes = [vp, i32, vp, i32, ctypes.c_uint64, vp, i32, vp]
         L.starred_set_lambda_pts.argtypes = [vp, ctypes.c_double]
         L.starred_pts_image.argtypes = [vp, vp, vp]
+        L.starred_lbfgs_direction.argtypes = [vp, vp, vp, vp, i32, i32, i32, vp]
+        L.starred_lbfgs_create.argtypes = [vp, i32, vp, vp, ctypes.POINTER(vp)]
+        L.starred_lbfgs_destroy.argtypes = [vp]
+        L.starred_lbfgs_reset.argtypes = [vp]
+        L.starred_lbfgs_run.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
         L.starred_estimate_lambda_pts.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
         _lib = L
     return _lib
@@ -312,6 +317,19 @@ class Plan:
         self._call(lib().starred_estimate_lambda_pts, _ptr(params), ctypes.byref(out))
         return out.value
 
+    def lbfgs_direction(self, grad, S, Y, count, newest):
+        """d = -H grad by the two-loop recursion over the ring buffers S, Y ([m][n])."""
+        g = _f32(grad, self.device)
+        S, Y = _f32(S, self.device), _f32(Y, self.device)
+        d = torch.empty_like(g)
+        self._call(lib().starred_lbfgs_direction, _ptr(g), _ptr(S), _ptr(Y), int(S.shape[0]), int(count),
+                   int(newest), _ptr(d))
+        return d
+
+    def lbfgs(self, m=10, lo=None, hi=None):
+        """An L-BFGS state on this plan's loss (optional box bounds)."""
+        return LBFGS(self, m, lo, hi)
+
     def set_fft_fused(self, enable: bool):
         """FFT path: one-launch forward for frames whose spectra fit in LDS (default on)."""
         _check(lib().starred_set_fft_fused(self._h, 1 if enable else 0))
@@ -339,3 +357,34 @@ class StarredLoss(torch.autograd.Function):
 
 def starred_loss(params, plan):
     return StarredLoss.apply(params, plan)
+
+
+class LBFGS:
+    """L-BFGS iterations on a plan's loss (state and history on the device)."""
+
+    def __init__(self, plan, m=10, lo=None, hi=None):
+        self.plan = plan
+        self._lo = _f32(lo, plan.device) if lo is not None else None
+        self._hi = _f32(hi, plan.device) if hi is not None else None
+        h = ctypes.c_void_p()
+        _check(lib().starred_lbfgs_create(plan._h, int(m), _ptr(self._lo), _ptr(self._hi), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, x, n_iter):
+        """n_iter iterations in place on x (float32 device tensor); returns (loss, evaluations)."""
+        loss = ctypes.c_double(0.0)
+        ev = ctypes.c_int32(0)
+        self.plan._call(lambda _, *a: lib().starred_lbfgs_run(self._h, *a), _ptr(x), int(n_iter),
+                        ctypes.byref(loss), ctypes.byref(ev))
+        return loss.value, ev.value
+
+    def reset(self):
+        _check(lib().starred_lbfgs_reset(self._h))
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().starred_lbfgs_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass

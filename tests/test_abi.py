@@ -93,4 +93,8 @@ def test_null_plan_arguments_are_rejected():
     assert L.starred_set_lambda_pts(None, ctypes.c_double(1.0)) == -1
     assert L.starred_estimate_lambda_pts(None, None, None) == -1
     assert L.starred_pts_image(None, None, None) == -1
+    assert L.starred_lbfgs_create(None, 10, None, None, None) == -1
+    assert L.starred_lbfgs_direction(None, None, None, None, 1, 0, 0, None) == -1
+    assert L.starred_lbfgs_run(None, None, 1, None, None) == -1
+    assert L.starred_lbfgs_destroy(None) == -1
     assert L.starred_set_frames(None, None, None, None, None) == -1

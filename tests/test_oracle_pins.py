@@ -716,3 +716,36 @@ def test_adabelief_first_step_and_constant_gradient_closed_forms():
     vt = sum(b2 ** (T - t) * ((1 - b2) * (b1 ** t * g) ** 2 + er) for t in range(1, T + 1))
     np.testing.assert_allclose(m, mt, rtol=1e-12)
     np.testing.assert_allclose(v, vt, rtol=1e-10)
+
+
+def test_lbfgs_two_loop_equals_the_bfgs_inverse_hessian_product():
+    """The two-loop recursion over a ring buffer against the textbook matrix form:
+    H_0 = gamma I, H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T for the stored
+    pairs oldest to newest, d = -H g."""
+    rng = np.random.default_rng(23)
+    n, m = 12, 5
+    A = rng.standard_normal((n, n))
+    A = A @ A.T + n * np.eye(n)  # SPD, so that s^T y > 0
+    S = np.zeros((m, n))
+    Y = np.zeros((m, n))
+    newest = -1
+    pairs = []
+    for k in range(8):  # more pairs than slots: the ring wraps
+        s = rng.standard_normal(n)
+        y = A @ s
+        newest = (newest + 1) % m
+        S[newest], Y[newest] = s, y
+        pairs.append((s, y))
+    count = m
+    g = rng.standard_normal(n)
+    got = ora.lbfgs_direction(g, S, Y, count, newest)
+    kept = pairs[-count:]
+    s_n, y_n = kept[-1]
+    H = (s_n @ y_n) / (y_n @ y_n) * np.eye(n)
+    for s, y in kept:
+        rho = 1.0 / (y @ s)
+        V = np.eye(n) - rho * np.outer(y, s)
+        H = V.T @ H @ V + rho * np.outer(s, s)
+    np.testing.assert_allclose(got, -H @ g, rtol=1e-10, atol=1e-12)
+    # no history: steepest descent
+    np.testing.assert_array_equal(ora.lbfgs_direction(g, S, Y, 0, newest), -g)
