@@ -1092,11 +1092,14 @@ static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad,
         e0 = p->prof_start();
         HIP_TRY(launch_psf_adj(p->st, S, n, p->s, N, p->sigma, params, p->d_rho, p->d_gstar));
         p->prof_stop(STARRED_STAGE_CONV_ADJ, e0);
+    }
+    // the sums read the prior's gradient: the starlet branch joins first
+    HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
+    if (grad) {
         e0 = p->prof_start();
         HIP_TRY(launch_psf_sum(p->st, S, N, params, p->d_gstar, p->d_prior, grad, p->d_part_eta));
         p->prof_stop(STARRED_STAGE_GRAD_SUMS, e0);
     }
-    HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
     e0 = p->prof_start();
     HIP_TRY(launch_psf_finalize_small(p->st, S, S, p->d_part_chi, n_l1, p->d_part_l1, psf_sum_blocks(N),
                                       p->d_part_eta, grad, loss_out, tick));
@@ -1670,10 +1673,7 @@ int starred_time_stage(starred_plan *p, const float *params, int32_t stage, int3
     auto launch = [&]() -> int {
         switch (stage) {
         case STARRED_STAGE_STARLET:
-            HIP_TRY(launch_starlet_fwd(p->st, p->N, p->J, params, nullptr, p->d_z, p->W, p->w_stride, (float)p->lam,
-                                       p->d_ca, p->d_cb, p->d_tmp, p->d_part_l1, &n_l1));
-            HIP_TRY(launch_starlet_adj(p->st, p->N, p->J, p->d_z, p->d_prior, p->d_ca, p->d_cb, p->d_tmp));
-            return STARRED_OK;
+            return prior_launches(p, p->st, params, true, &n_l1);
         case STARRED_STAGE_SPECTRA:
             if (!fft) break;
             HIP_TRY(fft_spectra(p->st, p->fd, params, p->N, p->E, p->M, p->sigma));
