@@ -115,17 +115,17 @@ def _run(args, prob, plan, torch, st, synth):
     grad = torch.empty_like(x)
     lr4 = [prob.adam_lr[k] for k in ("h", "Gamma", "a", "c")]
 
-    # ---- timed region: optimiser steps, each one captured graph replay ----
+    # ---- timed region: optimiser steps (captured graphs of several steps each) ----
     plan.set_graph_mode(not args.no_graph)
     t = 0
-    for _ in range(args.warmup):
-        t += 1
-        plan.step(x, m, v, t, lr4, loss_out=loss)
+    if args.warmup:
+        plan.steps(x, m, v, t + 1, lr4, args.warmup, loss_out=loss)
+        t += args.warmup
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        t += 1
-        plan.step(x, m, v, t, lr4, loss_out=loss)
+    # the K timed steps as one fit (starred_steps: several steps per graph launch)
+    plan.steps(x, m, v, t + 1, lr4, args.steps, loss_out=loss)
+    t += args.steps
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms = el * 1e3 / args.steps

@@ -171,6 +171,13 @@ int starred_loss_grad_plain(starred_plan *plan, const float *params, float *grad
 int starred_step(starred_plan *plan, float *params, float *m, float *v, int32_t t,
                  const starred_adam *hp, double *loss_out);
 
+/* n_steps >= 1 consecutive optimiser steps, the same as starred_step with t, t+1,
+ * ..., t+n_steps-1 (bitwise: the same launches in the same order); in graph mode
+ * several steps share one graph launch. loss_out holds the last step's loss. The
+ * paper's fits run hundreds of such steps (Sec. 2.4). */
+int starred_steps(starred_plan *plan, float *params, float *m, float *v, int32_t t,
+                  const starred_adam *hp, int32_t n_steps, double *loss_out);
+
 /* L-BFGS (limited-memory BFGS, Nocedal & Wright Alg. 7.4-7.5), the quasi-Newton
  * method of the paper's PSF fits, on the plan's loss. A state holds the history
  * of the last m pairs (s, y) ([m][num_params] floats each, allocated here), the

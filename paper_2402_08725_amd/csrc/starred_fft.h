@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "starred_dense.h"
 #include "starred_internal.h"
 
 namespace starred {
@@ -140,8 +141,9 @@ __device__ __forceinline__ double block_sum_d_fft(double v, double *sh)
 
 hipError_t fft_prep_kernels(hipStream_t st, const FftPlanDev &d, const float *psf, int s);
 // tick: a step counter the launch advances (the first launch of a fused step), or null
+// pa, pb: passes of the starlet prior carried by the row and column launches (or null)
 hipError_t fft_spectra(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M,
-                       float sigma, int *tick = nullptr);
+                       float sigma, int *tick = nullptr, DensePiece *pa = nullptr, DensePiece *pb = nullptr);
 hipError_t fft_spec_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,
                         bool lg = false);
 hipError_t fft_model_cols(hipStream_t st, const FftPlanDev &d);
@@ -158,8 +160,10 @@ struct FinalArgs;
 // dL/dh of the classes: the column inverse alone, and (one class whose window
 // is the whole grid) the row inverse that also writes dL/dh, updates h and does
 // the evaluation's small reductions in an extra work group
-hipError_t fft_grad_h_cols(hipStream_t st, const FftPlanDev &d);
-hipError_t fft_grad_h_rows_final(hipStream_t st, const FftPlanDev &d, const float *prior, const FinalArgs &fin);
+hipError_t fft_grad_h_cols(hipStream_t st, const FftPlanDev &d, DensePiece *pd = nullptr);
+// psum (or null): the composite-filter prior's planes after pass D1, summed per pixel instead of reading prior
+hipError_t fft_grad_h_rows_final(hipStream_t st, const FftPlanDev &d, const float *prior, const FinalArgs &fin,
+                                 const DenseStar *psum = nullptr);
 // bytes of LDS the one-launch forward needs for a class: two planes of
 // max(Q/2+1, n) lines of Q+1 values, the Q twiddles and the (1+4M) P table values
 inline size_t fused_lds_bytes(int Q, int n, int P, int M)
@@ -168,12 +172,12 @@ inline size_t fused_lds_bytes(int Q, int n, int P, int M)
     return ((size_t)2 * rows * (Q + 1) + Q + (size_t)(1 + 4 * M) * P) * 8;
 }
 hipError_t fft_fused_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,
-                         const float *data, const float *invvar, double *part_chi);
+                         const float *data, const float *invvar, double *part_chi, DensePiece *pc = nullptr);
 hipError_t fft_model_cols_lg(hipStream_t st, const FftPlanDev &d);
 hipError_t fft_model_rows_lg(hipStream_t st, const FftPlanDev &d, const float *data, const float *invvar,
                              double *part_chi);
 hipError_t fft_rho_cols_lg(hipStream_t st, const FftPlanDev &d);
-hipError_t fft_grad_h_inverse(hipStream_t st, const FftPlanDev &d);
+hipError_t fft_grad_h_inverse(hipStream_t st, const FftPlanDev &d, DensePiece *pd = nullptr);
 hipError_t fft_scene_model(hipStream_t st, const FftPlanDev &d, const float *scene, int s, float *model);
 
 }  // namespace starred

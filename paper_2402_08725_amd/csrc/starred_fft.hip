@@ -22,6 +22,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 namespace starred {
@@ -256,9 +257,14 @@ struct has_extra<Op, std::void_t<decltype(Op::extra)>> : std::true_type {};
 template <class Op>
 __global__ __launch_bounds__(kFftThreads) void k_lines(const LineItem *__restrict__ items,
                                                        const ClassFft *__restrict__ classes,
-                                                       const float2 *__restrict__ tw, Op op)
+                                                       const float2 *__restrict__ tw, Op op, DensePiece dp)
 {
     extern __shared__ float2 sm[];
+    {
+        // a starlet-prior job carried by this launch (work groups after the line groups and extras)
+        __shared__ double dred[kFftThreads / 64];
+        if (dense_piece_run(dp, sm, dred)) return;
+    }
     if constexpr (has_extra<Op>::value) {
         if (blockIdx.x == 0 && threadIdx.x == 0 && op.tick) *op.tick += 1;
         if ((int)blockIdx.x >= op.n_items) {
@@ -806,10 +812,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
                                                              const float *__restrict__ params, int N, int E, int M,
                                                              const float *__restrict__ data,
                                                              const float *__restrict__ invvar,
-                                                             float2 *__restrict__ Rh, double *__restrict__ part_chi)
+                                                             float2 *__restrict__ Rh, double *__restrict__ part_chi,
+                                                             DensePiece dp)
 {
     extern __shared__ float2 sm[];
     __shared__ double red[kFusedThreads / 64];
+    if (dense_piece_run(dp, sm, red)) return;  // a starlet-prior job carried by this launch
     const int i = frames[blockIdx.x];
     const FrameFft &f = fr[i];
     const ClassFft &c = classes[f.cls];
@@ -821,21 +829,49 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
     float2 *twl = sm + 2 * rows * Ls;
     float2 *t = twl + Q;
     {
+        // the twiddles and the tables: all of a thread's loads issued before its LDS writes
         const float2 *tg = tab + c.tab_off;
         const int nt = (1 + 4 * M) * P;
+        constexpr int kTabBatch = 4;
         for (int e = threadIdx.x; e < Q; e += blockDim.x) twl[e] = twQ[e];
-        for (int e = threadIdx.x; e < nt; e += blockDim.x) t[e] = tg[e];
+        for (int e0 = threadIdx.x; e0 < nt; e0 += kTabBatch * kFusedThreads) {
+            float2 v[kTabBatch];
+            #pragma unroll
+            for (int u = 0; u < kTabBatch; ++u) v[u] = tg[min(e0 + u * kFusedThreads, nt - 1)];
+            #pragma unroll
+            for (int u = 0; u < kTabBatch; ++u)
+                if (e0 + u * kFusedThreads < nt) t[e0 + u * kFusedThreads] = v[u];
+        }
     }
     twQ = twl;
     const float2 *Si = Sp + f.s_off;
     const float2 *Hc = Hh + c.hh_off;
     const float G = params[(long long)N * N + i];
     const float *ai = params + (long long)N * N + E + (long long)i * M;
-    __syncthreads();
 
     // lanes over columns kx, row groups over ky (no index divisions in the loops)
     const int CXF = HQ <= 64 ? 64 : 128, RGF = kFusedThreads / CXF;
     const int Q0L = Q <= 64 ? 64 : 128;  // lanes along a row of Q values
+    // this thread's data and weights for the residual (its first kPreRows row pairs),
+    // loaded now so that they arrive during the transforms
+    constexpr int kPreRows = S <= 2 ? 4 : 0;  // (s = 3 keeps its registers for the aliases)
+    const int n2 = (n + 1) / 2;
+    float pre[kPreRows > 0 ? kPreRows : 1][4];
+    {
+        const int x = threadIdx.x % Q0L;
+        #pragma unroll
+        for (int k = 0; k < kPreRows; ++k) {
+            const int yp = threadIdx.x / Q0L + k * (kFusedThreads / Q0L);
+            const bool va = x < n && yp < n2, vb = va && 2 * yp + 1 < n;
+            const long long ia = f.data_off + (long long)(va ? 2 * yp : 0) * n + (va ? x : 0);
+            const long long ib = vb ? ia + n : ia;
+            pre[k][0] = data[ia];
+            pre[k][1] = invvar[ia];
+            pre[k][2] = data[ib];
+            pre[k][3] = invvar[ib];
+        }
+    }
+    __syncthreads();
     const int lane = threadIdx.x % CXF, rg = threadIdx.x / CXF;
     // model spectrum, column-major: A[kx][ky]
     // (with MS > 0 sources at most, the column factors a_k gx_k(Kx) stay in registers)
@@ -902,7 +938,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
     // Rows in pairs (two real rows per complex transform): the inverse of
     // Z = X_2p + i X_2p+1, X_y the Hermitian rows of the column results, is
     // x_2p + i x_2p+1; a missing second row (odd n) is zero.
-    const int n2 = (n + 1) / 2;
     for (int yp = threadIdx.x / Q0L; yp < n2; yp += kFusedThreads / Q0L) {
         const int ya = 2 * yp, yb = 2 * yp + 1;
         for (int kx = threadIdx.x % Q0L; kx < Q; kx += Q0L) {
@@ -921,18 +956,36 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
     r = lds_fft_any<true>(o, r, n2, fl, twQ);  // along x: model rows 2p, 2p+1 in the real, imaginary parts
     o = (r == A) ? B : A;
     double chi = 0.0;
-    for (int yp = threadIdx.x / Q0L; yp < n2; yp += kFusedThreads / Q0L)
+    for (int k = 0, yp = threadIdx.x / Q0L; yp < n2; ++k, yp += kFusedThreads / Q0L)
         for (int x = threadIdx.x % Q0L; x < Q; x += Q0L) {
             float va = 0.f, vb = 0.f;
             if (x < n) {
                 const float2 mv = r[yp * Ls + x];
                 const long long ia = f.data_off + (long long)(2 * yp) * n + x;
-                const float ra = mv.x - data[ia], wa = invvar[ia];
+                // prefetched for the first kPreRows row pairs of the first column sweep
+                const bool have = k < kPreRows && x < Q0L;
+                float da = 0.f, wa = 0.f, db = 0.f, wb = 0.f;
+                #pragma unroll
+                for (int kk = 0; kk < kPreRows; ++kk)
+                    if (kk == k) {
+                        da = pre[kk][0];
+                        wa = pre[kk][1];
+                        db = pre[kk][2];
+                        wb = pre[kk][3];
+                    }
+                if (!have) {
+                    da = data[ia];
+                    wa = invvar[ia];
+                    if (2 * yp + 1 < n) {
+                        db = data[ia + n];
+                        wb = invvar[ia + n];
+                    }
+                }
+                const float ra = mv.x - da;
                 va = wa * ra;
                 chi += 0.5 * (double)wa * (double)ra * (double)ra;
                 if (2 * yp + 1 < n) {
-                    const long long ib = ia + n;
-                    const float rb = mv.y - data[ib], wb = invvar[ib];
+                    const float rb = mv.y - db;
                     vb = wb * rb;
                     chi += 0.5 * (double)wb * (double)rb * (double)rb;
                 }
@@ -1241,6 +1294,7 @@ struct OpGRowsFin {
     FinalArgs fin;
     int n_items;
     int *tick;  // the line launch's own counter hook: unused (null)
+    DenseStar psum;  // with psum.U set, the prior's gradient is summed from its per-level planes here
     static constexpr bool extra = true;
     static constexpr bool col = false;
     static constexpr bool rowsum = false;
@@ -1262,7 +1316,8 @@ struct OpGRowsFin {
         const long long pix = (long long)y * fin.N + x;
         float bc1, bc2;
         adam_bias(fin.adam, bc1, bc2);
-        finalize_h_pixel(fin.adam, bc1, bc2, pix, (prior ? prior[pix] : 0.f) + v.x, fin.grad);
+        const float pg = psum.U ? (float)dense_prior_at(psum, 0, pix) : (prior ? prior[pix] : 0.f);
+        finalize_h_pixel(fin.adam, bc1, bc2, pix, pg + v.x, fin.grad);
     }
 };
 
@@ -1270,13 +1325,30 @@ struct OpGRowsFin {
 // launchers
 // --------------------------------------------------------------------------
 
+// LDS bytes a carried prior pass needs
+static size_t piece_lds(const DensePiece &p)
+{
+    if (p.pass < 0) return 0;
+    if (p.pass == 0 || p.pass == 2) return sizeof(double) * (size_t)p.d.rx * (p.d.N + 2 * DenseStar::bw(p.d.J - 1));
+    return p.pass == 3 ? dense_lds_d(p.d.J) : dense_lds_y(p.d.J);
+}
+
+// n_main work groups of line groups (and extras), then the carried pass's jobs
 template <class Op>
 static hipError_t run_lines(hipStream_t st, const LinePass &lp, const ClassFft *classes, const float2 *tw,
-                            const Op &op)
+                            const Op &op, int n_main = -1, DensePiece *piece = nullptr)
 {
-    if (lp.n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_lines<Op>), dim3(lp.n_items), dim3(kFftThreads), lp.lds_bytes, st, lp.items,
-                       classes, tw, op);
+    if (n_main < 0) n_main = lp.n_items;
+    DensePiece dp;
+    size_t lds = lp.lds_bytes;
+    if (piece && piece->pass >= 0) {
+        dp = *piece;
+        dp.first = n_main;
+        lds = std::max(lds, piece_lds(dp));
+    }
+    const int grid = n_main + (dp.pass >= 0 ? dp.jobs : 0);
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_lines<Op>), dim3(grid), dim3(kFftThreads), lds, st, lp.items, classes, tw, op, dp);
     return hipGetLastError();
 }
 
@@ -1288,17 +1360,14 @@ hipError_t fft_prep_kernels(hipStream_t st, const FftPlanDev &d, const float *ps
 }
 
 hipError_t fft_spectra(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M,
-                       float sigma, int *tick)
+                       float sigma, int *tick, DensePiece *pa, DensePiece *pb)
 {
     // rows of the h windows, with the factor tables in extra work groups
     const int extra = M > 0 ? d.n_classes * kTabBlocks : 0;
     const OpHRows op{params, N, d.Th, d.hrows.n_items, E, M, sigma, d.tab, tick};
-    if (d.hrows.n_items + extra > 0)
-        hipLaunchKernelGGL((k_lines<OpHRows>), dim3(d.hrows.n_items + extra), dim3(kFftThreads),
-                           d.hrows.lds_bytes, st, d.hrows.items, d.classes, d.tw, op);
-    hipError_t e = hipGetLastError();
+    hipError_t e = run_lines(st, d.hrows, d.classes, d.tw, op, d.hrows.n_items + extra, pa);
     if (e != hipSuccess) return e;
-    return run_lines(st, d.hcols, d.classes, d.tw, OpHCols{d.Th, d.Hh});
+    return run_lines(st, d.hcols, d.classes, d.tw, OpHCols{d.Th, d.Hh}, -1, pb);
 }
 
 hipError_t fft_spec_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,
@@ -1360,12 +1429,20 @@ hipError_t fft_resid_rows(hipStream_t st, const FftPlanDev &d, const float *resi
 }
 
 hipError_t fft_fused_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,
-                         const float *data, const float *invvar, double *part_chi)
+                         const float *data, const float *invvar, double *part_chi, DensePiece *pc)
 {
     if (d.n_fused <= 0) return hipSuccess;
+    DensePiece dp;
+    size_t lds = d.fused_lds;
+    if (pc && pc->pass >= 0) {
+        dp = *pc;
+        dp.first = d.n_fused;
+        lds = std::max(lds, piece_lds(dp));
+    }
+    const int grid = d.n_fused + (dp.pass >= 0 ? dp.jobs : 0);
 #define FUSED_FWD(SS, MS)                                                                                     \
-    hipLaunchKernelGGL((k_frame_fwd<SS, MS>), dim3(d.n_fused), dim3(kFusedThreads), d.fused_lds, st, d.fused,    \
-                       d.classes, d.frames, d.tw, d.S, d.Hh, d.tab, params, N, E, M, data, invvar, d.Rh, part_chi)
+    hipLaunchKernelGGL((k_frame_fwd<SS, MS>), dim3(grid), dim3(kFusedThreads), lds, st, d.fused, d.classes,      \
+                       d.frames, d.tw, d.S, d.Hh, d.tab, params, N, E, M, data, invvar, d.Rh, part_chi, dp)
 #define FUSED_FWD_M(SS)                       \
     if (M <= 4) FUSED_FWD(SS, 4);             \
     else if (M <= 8) FUSED_FWD(SS, 8);        \
@@ -1430,22 +1507,21 @@ hipError_t fft_adj_sums(hipStream_t st, const FftPlanDev &d, int M, double *fsum
     return hipGetLastError();
 }
 
-hipError_t fft_grad_h_cols(hipStream_t st, const FftPlanDev &d)
+hipError_t fft_grad_h_cols(hipStream_t st, const FftPlanDev &d, DensePiece *pd)
 {
-    return run_lines(st, d.gcols, d.classes, d.tw, OpGCols{d.Gp, d.Th});
+    return run_lines(st, d.gcols, d.classes, d.tw, OpGCols{d.Gp, d.Th}, -1, pd);
 }
 
-hipError_t fft_grad_h_rows_final(hipStream_t st, const FftPlanDev &d, const float *prior, const FinalArgs &fin)
+hipError_t fft_grad_h_rows_final(hipStream_t st, const FftPlanDev &d, const float *prior, const FinalArgs &fin,
+                                 const DenseStar *psum)
 {
-    const OpGRowsFin op{d.Th, prior, fin, d.grows.n_items, nullptr};
-    hipLaunchKernelGGL((k_lines<OpGRowsFin>), dim3(d.grows.n_items + 1), dim3(kFftThreads), d.grows.lds_bytes, st,
-                       d.grows.items, d.classes, d.tw, op);
-    return hipGetLastError();
+    const OpGRowsFin op{d.Th, prior, fin, d.grows.n_items, nullptr, psum ? *psum : DenseStar()};
+    return run_lines(st, d.grows, d.classes, d.tw, op, d.grows.n_items + 1);
 }
 
-hipError_t fft_grad_h_inverse(hipStream_t st, const FftPlanDev &d)
+hipError_t fft_grad_h_inverse(hipStream_t st, const FftPlanDev &d, DensePiece *pd)
 {
-    hipError_t e = run_lines(st, d.gcols, d.classes, d.tw, OpGCols{d.Gp, d.Th});
+    hipError_t e = run_lines(st, d.gcols, d.classes, d.tw, OpGCols{d.Gp, d.Th}, -1, pd);
     if (e != hipSuccess) return e;
     return run_lines(st, d.grows, d.classes, d.tw, OpGRows{d.Th, d.hcls});
 }

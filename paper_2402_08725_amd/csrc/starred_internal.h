@@ -124,6 +124,24 @@ hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, fl
 hipError_t launch_starlet_prior(hipStream_t st, int N, int J, int B, const float *img, float *z, const float *W,
                                 int w_stride, float lam0, float lam1, float *c_a, float *c_b, double *part_l1,
                                 int *n_l1);
+// Starlet prior through the per-scale composite filters (starred_starlet.hip)
+struct DenseStar;
+constexpr int kDenseMaxN = 256;
+constexpr size_t kDenseMaxLds = 128 * 1024;
+bool dense_fits(int N, int J);  // images and scale counts the composite filters handle
+int dense_rows_per_job(int N);
+int dense_rows_for(int N, int threads);  // rows per x-pass job for work groups of `threads`
+int dense_num_taps(int J);
+void dense_taps(int J, double *out);  // host: the composite filters of levels 1 .. J-1
+size_t dense_lds_x(int N, int J);
+size_t dense_lds_y(int J);
+size_t dense_lds_d(int J);
+// L1 partials (part_l1, if set) and, with out set, the subgradient's image
+hipError_t launch_dense_prior(hipStream_t st, const DenseStar &d);
+// coefficients alpha [B][J][N][N] of d.img
+hipError_t launch_dense_coeffs(hipStream_t st, const DenseStar &d, float *coeffs);
+// out = Phi zin
+hipError_t launch_dense_adjoint(hipStream_t st, const DenseStar &d);
 hipError_t launch_starlet_adj_batch(hipStream_t st, int N, int J, int B, const float *z, float *out, float *v_a,
                                     float *v_b);
 hipError_t launch_pts_render(hipStream_t st, int N, int E, int M, float sigma, const float *params, float *h_out,

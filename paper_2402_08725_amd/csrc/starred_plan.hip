@@ -1,6 +1,7 @@
 // Host side of the C ABI (include/starred.h): plan validation, frame tables,
 // work lists, scratch ownership and the launch sequences of loss_grad / step.
 #include "starred.h"
+#include "starred_dense.h"
 #include "starred_fft.h"
 #include "starred_finalize.h"
 #include "starred_internal.h"
@@ -93,6 +94,11 @@ struct starred_plan {
     double *est_part = nullptr, *est_out = nullptr;
     float *d_grad = nullptr;
     float *d_wzero = nullptr;
+    // the prior through the per-scale composite filters (when they fit): taps and
+    // the row-filtered, smoothed and adjoint planes, for up to dense_b images
+    bool dense = false;
+    int dense_b = 0;
+    double *d_dense_taps = nullptr, *d_dense_T = nullptr, *d_dense_C = nullptr, *d_dense_U = nullptr;
     float *d_hpart = nullptr;
     std::vector<void *> owned;
     // noise propagation: an s = 1 plan applying S_f^T to a batch of noise fields
@@ -136,14 +142,14 @@ struct starred_plan {
     int *d_t = nullptr;
     int next_t = -1;  // step number the device counter will produce next (-1: unknown)
 
-    // captured graphs (slot 0: loss_grad, slot 1: step)
+    // captured graphs (slot 0: loss_grad, slot 1: step, slot 2: kStepsPerGraph steps)
     bool graph_mode = false;
     struct GraphSlot {
         bool valid = false;
         hipGraph_t g = nullptr;
         hipGraphExec_t x = nullptr;
         std::vector<uintptr_t> key;
-    } gs[2];
+    } gs[3];
 
     // stage timing
     bool prof_on = false;
@@ -259,6 +265,48 @@ static int validate(const starred_desc *d)
     return STARRED_OK;
 }
 
+// The composite-filter prior: taps and planes for up to B images, when the
+// grid and the scale count fit it (else the prior runs the cascade).
+static int dense_setup(starred_plan *p, int B)
+{
+    p->dense = dense_fits(p->N, p->J);
+    if (!p->dense) return STARRED_OK;
+    p->dense_b = B;
+    const size_t planes = (size_t)B * p->J * p->N * p->N;
+    int rc;
+    if ((rc = p->alloc(&p->d_dense_taps, (size_t)dense_num_taps(p->J)))) return rc;
+    if ((rc = p->alloc(&p->d_dense_T, planes))) return rc;
+    if ((rc = p->alloc(&p->d_dense_C, planes))) return rc;
+    if ((rc = p->alloc(&p->d_dense_U, planes))) return rc;
+    std::vector<double> taps(dense_num_taps(p->J));
+    dense_taps(p->J, taps.data());
+    HIP_TRY(hipMemcpy(p->d_dense_taps, taps.data(), sizeof(double) * taps.size(), hipMemcpyHostToDevice));
+    return STARRED_OK;
+}
+
+static DenseStar dense_desc(const starred_plan *p, int B, const float *img)
+{
+    DenseStar d;
+    d.N = p->N;
+    d.J = p->J;
+    d.B = B;
+    d.rx = dense_rows_per_job(p->N);
+    d.taps = p->d_dense_taps;
+    d.img = img;
+    d.T = p->d_dense_T;
+    d.C = p->d_dense_C;
+    d.U = p->d_dense_U;
+    d.W = p->W;
+    d.w_stride = p->w_stride;
+    d.lam0 = d.lam1 = (float)p->lam;
+    return d;
+}
+
+static size_t dense_l1_slots(const starred_plan *p)
+{
+    return p->dense ? (size_t)dense_desc(p, p->dense_b, nullptr).l1_slots() : 0;
+}
+
 static int build_deconv(starred_plan *p)
 {
     const int s = p->s, E = p->E;
@@ -344,7 +392,9 @@ static int build_deconv(starred_plan *p)
     if ((rc = p->alloc(&p->d_rho, p->ndata))) return rc;
     if ((rc = p->alloc(&p->d_g, p->nfine))) return rc;
     if ((rc = p->alloc(&p->d_part_chi, p->fwd_items.size()))) return rc;
-    if ((rc = p->alloc(&p->d_part_l1, (size_t)2 * starlet_l1_slots(p->N, p->J)))) return rc;
+    if ((rc = dense_setup(p, 2))) return rc;
+    if ((rc = p->alloc(&p->d_part_l1, std::max((size_t)2 * starlet_l1_slots(p->N, p->J), dense_l1_slots(p)))))
+        return rc;
     if ((rc = p->alloc(&p->d_fsum, (size_t)E * (1 + 3 * p->M)))) return rc;
     // two images (h and the point-source image P of Eq. 11) for the prior buffers
     if ((rc = p->alloc(&p->d_z, (size_t)2 * p->J * NN))) return rc;
@@ -687,7 +737,8 @@ static int build_psf(starred_plan *p)
     if ((rc = p->alloc(&p->d_gstar, (size_t)S * NN))) return rc;
     if ((rc = p->alloc(&p->d_part_chi, S))) return rc;
     if ((rc = p->alloc(&p->d_part_eta, (size_t)psf_sum_blocks(N) * 5))) return rc;
-    if ((rc = p->alloc(&p->d_part_l1, (size_t)starlet_l1_slots(p->N, p->J)))) return rc;
+    if ((rc = dense_setup(p, 1))) return rc;
+    if ((rc = p->alloc(&p->d_part_l1, std::max((size_t)starlet_l1_slots(p->N, p->J), dense_l1_slots(p))))) return rc;
     if ((rc = p->alloc(&p->d_z, (size_t)p->J * NN))) return rc;
     if ((rc = p->alloc(&p->d_ca, NN))) return rc;
     if ((rc = p->alloc(&p->d_cb, NN))) return rc;
@@ -855,6 +906,10 @@ int starred_convolve_subsample_adj(starred_plan *p, const float *resid, float *g
 int starred_starlet_fwd(starred_plan *p, const float *img, float *coeffs)
 {
     if (!p || !img || !coeffs) return fail(STARRED_EINVAL, "NULL argument");
+    if (p->dense) {
+        HIP_TRY(launch_dense_coeffs(p->st, dense_desc(p, 1, img), coeffs));
+        return STARRED_OK;
+    }
     // the transform alone: zero weights, no L1 partials, no subgradient
     HIP_TRY(launch_starlet_fwd(p->st, p->N, p->J, img, coeffs, nullptr, p->d_wzero, 0, 0.f,
                                p->d_ca, p->d_cb, p->d_tmp, nullptr, nullptr));
@@ -864,6 +919,13 @@ int starred_starlet_fwd(starred_plan *p, const float *img, float *coeffs)
 int starred_starlet_adj(starred_plan *p, const float *coeffs, float *img)
 {
     if (!p || !coeffs || !img) return fail(STARRED_EINVAL, "NULL argument");
+    if (p->dense) {
+        DenseStar d = dense_desc(p, 1, nullptr);
+        d.zin = coeffs;
+        d.out = img;
+        HIP_TRY(launch_dense_adjoint(p->st, d));
+        return STARRED_OK;
+    }
     HIP_TRY(launch_starlet_adj(p->st, p->N, p->J, coeffs, img, p->d_ca, p->d_cb, p->d_tmp));
     return STARRED_OK;
 }
@@ -877,6 +939,23 @@ int starred_starlet_adj(starred_plan *p, const float *coeffs, float *img)
 // gradient's shares of dL/da and dL/dc land in d_pts.
 static int prior_launches(starred_plan *p, hipStream_t st, const float *img, bool want_grad, int *n_l1)
 {
+    if (p->dense) {
+        // every scale from the image(s) directly: four passes over all scales
+        const bool pts = p->mode == STARRED_DECONV && p->lam_pts != 0.0;
+        const long long NN = (long long)p->N * p->N;
+        if (pts) HIP_TRY(launch_pts_render(st, p->N, p->E, p->M, p->sigma, img, nullptr, p->d_pair + NN));
+        DenseStar d = dense_desc(p, pts ? 2 : 1, img);
+        if (pts) {
+            d.img1 = p->d_pair + NN;  // the point-source image
+            d.lam1 = (float)p->lam_pts;
+        }
+        d.part_l1 = p->d_part_l1;
+        d.out = want_grad ? p->d_prior : nullptr;
+        HIP_TRY(launch_dense_prior(st, d));
+        *n_l1 = d.l1_slots();
+        if (pts && want_grad) HIP_TRY(launch_pts_dots(st, p->N, p->E, p->M, p->sigma, img, p->d_prior + NN, p->d_pts));
+        return STARRED_OK;
+    }
     if (p->mode == STARRED_DECONV && p->lam_pts != 0.0) {
         const long long NN = (long long)p->N * p->N;
         HIP_TRY(launch_pts_render(st, p->N, p->E, p->M, p->sigma, img, p->d_pair, p->d_pair + NN));
@@ -917,18 +996,49 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     hipEvent_t e0;
     int n_chi;
     const double *part_chi;
-    // the starlet prior depends on h only: it runs on the forked stream
     int n_l1 = 0;
-    int rc = starlet_branch(p, params, grad != nullptr, &n_l1);
-    if (rc) return rc;
     const bool fused = fft && p->fft_fused && p->fd.n_fused > 0;
     // one class covering the whole grid: the row inverse of dL/dh carries the final
     // reductions and the update (one launch fewer)
     const bool fin_rows = fft && grad && p->fd.n_classes == 1 && p->cls[0].F == p->N;
+    // The starlet prior depends on h only. With the composite filters, the
+    // one-launch forward and (for the gradient) the row inverse above, its passes
+    // ride in the step's own launches as extra work groups (A: the h-row launch,
+    // B: the h-column launch, C with z and the L1 share: the forward, D1 with each
+    // level's adjoint term: the dL/dh column launch; the row inverse sums the
+    // terms per pixel); otherwise, and with the point-source term, the prior runs
+    // on the forked stream.
+    const bool pts = p->lam_pts != 0.0;
+    const bool ride = fused && p->dense && !pts && (!grad || fin_rows);
+    DensePiece pa, pb, pc, pd;
+    DenseStar dd;
+    if (ride) {
+        dd = dense_desc(p, 1, params);
+        dd.part_l1 = p->d_part_l1;
+        dd.out = grad ? p->d_prior : nullptr;  // (pass C builds U_j only when set)
+        pa.d = pb.d = pd.d = dd;
+        pc.d = dd;
+        pc.d.rx = dense_rows_for(p->N, kFusedThreads);  // the forward's work groups are wider
+        pa.pass = 0;
+        pa.jobs = pa.d.jobs_a();
+        pb.pass = 1;
+        pb.jobs = pb.d.jobs_b();
+        pc.pass = 2;
+        pc.jobs = pc.d.jobs_c();
+        if (grad) {
+            pd.pass = 4;  // each level's term into its own plane; the h-row inverse sums them
+            pd.jobs = pd.d.jobs_d1();
+        }
+        n_l1 = pc.d.l1_slots();
+    } else {
+        int rc = starlet_branch(p, params, grad != nullptr, &n_l1);
+        if (rc) return rc;
+    }
     if (fft) {
         e0 = p->prof_start();
         // with the fused update the counter advances in the first launch of the step
-        HIP_TRY(fft_spectra(p->st, p->fd, params, p->N, p->E, p->M, p->sigma, adam ? tick : nullptr));
+        HIP_TRY(fft_spectra(p->st, p->fd, params, p->N, p->E, p->M, p->sigma, adam ? tick : nullptr,
+                            ride ? &pa : nullptr, ride ? &pb : nullptr));
         p->prof_stop(STARRED_STAGE_SPECTRA, e0);
         e0 = p->prof_start();
         hipEvent_t e1;
@@ -937,7 +1047,7 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         if (fused) {
             e1 = p->prof_start();
             HIP_TRY(fft_fused_fwd(p->st, p->fd, params, p->N, p->E, p->M, p->s, p->data, p->invvar,
-                                  p->d_part_chi_fft + n_rows));
+                                  p->d_part_chi_fft + n_rows, ride ? &pc : nullptr));
             p->prof_stop(STARRED_STAGE_FFT_FUSED, e1);
         }
         e1 = p->prof_start();
@@ -980,8 +1090,10 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
             HIP_TRY(fft_adj_sums(p->st, p->fd, p->M, p->d_fsum));
             p->prof_stop(STARRED_STAGE_FFT_FSUM, e1);
             e1 = p->prof_start();
-            HIP_TRY(fin_rows ? fft_grad_h_cols(p->st, p->fd) : fft_grad_h_inverse(p->st, p->fd));
+            HIP_TRY(fin_rows ? fft_grad_h_cols(p->st, p->fd, ride ? &pd : nullptr)
+                             : fft_grad_h_inverse(p->st, p->fd, ride ? &pd : nullptr));
             p->prof_stop(STARRED_STAGE_FFT_AROWS, e1);
+
         } else
             HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ar_max,
                                       p->Bpad_max, p->d_rho, p->d_ka, p->d_g));
@@ -992,7 +1104,7 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
             p->prof_stop(STARRED_STAGE_GRAD_SUMS, e0);
         }
     }
-    HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
+    if (!ride) HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
     e0 = p->prof_start();
     if (fin_rows) {
         FinalArgs fa;
@@ -1010,7 +1122,7 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         fa.tick = adam ? nullptr : tick;
         if (adam) fa.adam = *adam;
         fa.pts = p->lam_pts != 0.0 ? p->d_pts : nullptr;
-        HIP_TRY(fft_grad_h_rows_final(p->st, p->fd, p->d_prior, fa));
+        HIP_TRY(fft_grad_h_rows_final(p->st, p->fd, p->d_prior, fa, ride ? &dd : nullptr));
         p->prof_stop(STARRED_STAGE_FINALIZE, e0);
         return STARRED_OK;
     }
@@ -1284,11 +1396,17 @@ int starred_loss_grad(starred_plan *p, const float *params, float *grad, double 
     return run_graph(p, 0, key, body);
 }
 
-int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
-                 const starred_adam *hp, double *loss_out)
+// Steps a graph replay of starred_steps covers (the device-side gap between two
+// graph launches is paid once per kStepsPerGraph steps).
+constexpr int kStepsPerGraph = 8;
+
+// n consecutive optimiser steps from step number t
+static int run_steps(starred_plan *p, float *params, float *m, float *v, int32_t t, const starred_adam *hp,
+                     int32_t n, double *loss_out)
 {
     if (!p || !params || !m || !v || !hp) return fail(STARRED_EINVAL, "NULL argument");
     if (t < 1) return fail(STARRED_EINVAL, "t must be >= 1");
+    if (n < 1) return fail(STARRED_EINVAL, "the number of steps must be >= 1");
     if (hp->rule != STARRED_ADAM && hp->rule != STARRED_ADABELIEF) return fail(STARRED_EINVAL, "unknown update rule");
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
     // the device step counter is advanced inside the step; resynchronise it when
@@ -1308,7 +1426,7 @@ int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
     ad.eps = hp->eps;
     ad.rule = hp->rule;
     ad.eps_root = hp->eps_root;
-    auto body = [&]() -> int {
+    auto one = [&]() -> int {
         int rc = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t)
                                           : loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t,
                                                            fused_adam ? &ad : nullptr);
@@ -1327,9 +1445,11 @@ int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
         p->prof_stop(STARRED_STAGE_ADAM, e0);
         return STARRED_OK;
     };
-    int rc;
     if (!p->graph_mode) {
-        rc = body();
+        for (int i = 0; i < n; ++i) {
+            int rc = one();
+            if (rc) return rc;
+        }
     } else {
         uint32_t hb[9];
         memcpy(hb, hp->lr, sizeof(float) * 4);
@@ -1341,11 +1461,38 @@ int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
         std::vector<uintptr_t> key = {(uintptr_t)params, (uintptr_t)m, (uintptr_t)v, (uintptr_t)loss_out,
                                       (uintptr_t)p->algo};
         for (uint32_t x : hb) key.push_back(x);
-        rc = run_graph(p, 1, key, body);
+        // whole groups of steps as one graph, the rest one step per graph
+        int left = n;
+        while (left >= kStepsPerGraph) {
+            int rc = run_graph(p, 2, key, [&]() -> int {
+                for (int i = 0; i < kStepsPerGraph; ++i) {
+                    int rc2 = one();
+                    if (rc2) return rc2;
+                }
+                return STARRED_OK;
+            });
+            if (rc) return rc;
+            left -= kStepsPerGraph;
+        }
+        for (; left > 0; --left) {
+            int rc = run_graph(p, 1, key, one);
+            if (rc) return rc;
+        }
     }
-    if (rc) return rc;
-    p->next_t = t + 1;
+    p->next_t = t + n;
     return STARRED_OK;
+}
+
+int starred_step(starred_plan *p, float *params, float *m, float *v, int32_t t,
+                 const starred_adam *hp, double *loss_out)
+{
+    return run_steps(p, params, m, v, t, hp, 1, loss_out);
+}
+
+int starred_steps(starred_plan *p, float *params, float *m, float *v, int32_t t, const starred_adam *hp,
+                  int32_t n_steps, double *loss_out)
+{
+    return run_steps(p, params, m, v, t, hp, n_steps, loss_out);
 }
 
 int starred_set_fft_fused(starred_plan *p, int32_t enable)

@@ -23,7 +23,7 @@ EXPORTED = [
     "starred_plan_create", "starred_plan_destroy", "starred_num_params", "starred_num_data",
     "starred_num_scene", "starred_set_frames", "starred_render_scene",
     "starred_convolve_subsample", "starred_convolve_subsample_adj", "starred_starlet_fwd",
-    "starred_starlet_adj", "starred_loss_grad", "starred_step", "starred_set_graph_mode",
+    "starred_starlet_adj", "starred_loss_grad", "starred_step", "starred_steps", "starred_set_graph_mode",
     "starred_conv_algo", "starred_last_error", "starred_abi_version", "starred_set_profiling",
     "starred_profile_read", "starred_psf_model", "starred_loss_grad_plain", "starred_copy_probe",
 ]
@@ -78,6 +78,7 @@ def lib():
             getattr(L, f).argtypes = [vp, vp, vp]
         L.starred_loss_grad.argtypes = [vp, vp, vp, vp]
         L.starred_step.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(AdamHP), vp]
+        L.starred_steps.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(AdamHP), i32, vp]
         L.starred_set_graph_mode.argtypes = [vp, i32]
         L.starred_set_fft_fused.argtypes = [vp, i32]
         L.starred_conv_algo.argtypes = [vp]
@@ -264,6 +265,20 @@ class Plan:
         hp.rule, hp.eps_root = int(rule), float(eps_root)
         loss = loss_out if loss_out is not None else torch.empty(3, dtype=torch.float64, device=self.device)
         self._call(lib().starred_step, _ptr(params), _ptr(m), _ptr(v), int(t), ctypes.byref(hp), _ptr(loss))
+        return loss
+
+    def steps(self, params, m, v, t, lr, n, beta1=0.9, beta2=0.999, eps=1e-8, loss_out=None, rule=ADAM,
+              eps_root=0.0):
+        """n consecutive optimiser steps t .. t+n-1 (several per graph launch in graph mode);
+        returns the last step's loss."""
+        hp = AdamHP()
+        for i in range(4):
+            hp.lr[i] = float(lr[i])
+        hp.beta1, hp.beta2, hp.eps = beta1, beta2, eps
+        hp.rule, hp.eps_root = int(rule), float(eps_root)
+        loss = loss_out if loss_out is not None else torch.empty(3, dtype=torch.float64, device=self.device)
+        self._call(lib().starred_steps, _ptr(params), _ptr(m), _ptr(v), int(t), ctypes.byref(hp), int(n),
+                   _ptr(loss))
         return loss
 
     def set_profiling(self, enable: bool):

@@ -98,3 +98,4 @@ def test_null_plan_arguments_are_rejected():
     assert L.starred_lbfgs_run(None, None, 1, None, None) == -1
     assert L.starred_lbfgs_destroy(None) == -1
     assert L.starred_set_frames(None, None, None, None, None) == -1
+    assert L.starred_steps(None, None, None, None, 1, None, 1, None) == -1

@@ -314,6 +314,37 @@ def test_adam_200_steps_against_oracle(algo):
 
 
 @pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+@pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
+def test_steps_equal_repeated_single_steps(algo, graph):
+    """starred_steps(n) runs the same launches as n calls of starred_step (several
+    steps per graph launch in graph mode, then single-step graphs for the rest):
+    bitwise the same parameters, moments and last loss, also across the boundary
+    between two calls (the device step counter carries on)."""
+    prob = synth.make_deconv(2, E=6)
+    d, w, rng = _data(prob, seed=21)
+    p0 = synth.eval_point(prob, "init", rng)
+    lr4 = [prob.adam_lr[k] for k in ("h", "Gamma", "a", "c")]
+    runs = []
+    for many in (False, True):
+        plan = _plan(prob, d, w, algo=algo)
+        plan.set_graph_mode(graph)
+        x = torch.tensor(p0, dtype=torch.float32, device="cuda")
+        m = torch.zeros_like(x)
+        v = torch.zeros_like(x)
+        loss = torch.empty(3, dtype=torch.float64, device="cuda")
+        if many:
+            plan.steps(x, m, v, 1, lr4, 11, loss_out=loss)   # one 8-step graph and 3 single steps
+            plan.steps(x, m, v, 12, lr4, 9, loss_out=loss)
+        else:
+            for t in range(1, 21):
+                plan.step(x, m, v, t, lr4, loss_out=loss)
+        torch.cuda.synchronize()
+        runs.append((x.clone(), m.clone(), v.clone(), loss.clone()))
+    for a, b in zip(*runs):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
 @pytest.mark.parametrize("t", [1, 7])
 def test_adam_single_step_well_conditioned_entries(algo, t):
     """One update at step number t (t = 7 without the six before it: the device

@@ -228,6 +228,57 @@ def test_starlet_adjoint_identity(N, J):
     assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
 
 
+def _composite_filter(j):
+    """Level j's smoothing as one filter: the holed B3 filters of levels < j convolved."""
+    a = np.array([1.0])
+    for l in range(j):
+        h = np.zeros(4 * 2 ** l + 1)
+        h[:: 2 ** l] = np.array([1, 4, 6, 4, 1]) / 16.0
+        a = np.convolve(a, h)
+    return a
+
+
+def _mirror_operator(N, a):
+    """N x N matrix of filter a applied to the whole-sample symmetric extension."""
+    bw = (len(a) - 1) // 2
+    M = np.zeros((N, N))
+    for x in range(N):
+        for t in range(-bw, bw + 1):
+            i = abs(x + t)
+            i = 2 * (N - 1) - i if i > N - 1 else i
+            M[x, i] += a[t + bw]
+    return M
+
+
+@pytest.mark.parametrize("N,J", [(16, 4), (33, 5), (64, 6), (20, 3)])
+def test_starlet_composite_filter_forms(N, J):
+    """The forms the device prior evaluates: every scale directly from the image
+    through the composite filter on the symmetric extension, c_j = M_j x M_j^T,
+    and the subgradient's image sum_j M_j^T (z_j - z_{j-1}) M_j evaluated as
+    D^-1 M_j (D Y D) M_j^T D^-1 with D = diag(2, 1, ..., 1, 2)."""
+    img = RNG.standard_normal((N, N))
+    z = RNG.standard_normal((J, N, N))
+    Ms = [np.eye(N)] + [_mirror_operator(N, _composite_filter(j)) for j in range(1, J)]
+    c = [M @ img @ M.T for M in Ms]
+    alpha = [c[j] - c[j + 1] for j in range(J - 1)] + [c[J - 1]]
+    got = ora.starlet_fwd(N, J, img.ravel()).reshape(J, N, N)
+    np.testing.assert_allclose(np.array(alpha), got, rtol=0, atol=1e-12)
+    dvec = np.ones(N)
+    dvec[0] = dvec[-1] = 2.0
+    D = np.diag(dvec)
+    g = np.zeros((N, N))
+    for j in range(J):
+        Y = z[j] - (z[j - 1] if j else 0.0)
+        assert np.abs(Ms[j] @ D - (Ms[j] @ D).T).max() == 0.0
+        g += np.linalg.inv(D) @ Ms[j] @ (D @ Y @ D) @ Ms[j].T @ np.linalg.inv(D)
+    np.testing.assert_allclose(g, ora.starlet_adj(N, J, z.ravel()).reshape(N, N), rtol=0, atol=1e-11)
+    # the taps are dyadic: exact in FP64 (and FP32) at every level used here
+    for j in range(1, J):
+        a = _composite_filter(j)
+        assert len(a) == 2 * (2 ** (j + 1) - 2) + 1
+        assert np.all(a * 16.0 ** j == np.round(a * 16.0 ** j))
+
+
 # --------------------------------------------------------------------------- #
 # Gradient of the deconvolution loss (Eqs. 10-11)                              #
 # --------------------------------------------------------------------------- #
