@@ -886,3 +886,73 @@ def test_lbfgs_psf_mode():
     f, ev = plan.lbfgs(m=6).run(x, 20)
     _say(f"lbfgs psf: {l0:.6e} -> {f:.6e} in {ev} evaluations")
     assert f < l0
+
+
+def test_pipeline_psf_fits_then_joint_deconvolution():
+    """The paper's two-stage workflow (f3's pipeline): per-epoch PSF reconstruction
+    from star stamps (PSF mode, L-BFGS), the fitted narrow PSFs s_i rendered on the
+    device (starred_render_scene) as the deconvolution kernels, then the joint
+    deconvolution (Adam steps, starred_steps). The data are made with the true
+    PSFs; the fit with the reconstructed kernels must land close to the one with
+    the true kernels."""
+    st = _st()
+    E, s, n_star, M, J = 3, 2, 16, 2, 3
+    K = s * n_star
+    kern_true, kern_fit = [], []
+    for e in range(E):
+        pp = synth.make_psf(cfg=3, rep=e, S=6, n=n_star, s=s, J=3)
+        rng = np.random.default_rng(300 + e)
+        d, w = synth.add_noise(ora.psf_model(pp, pp.params_true), rng, sigma_bg=pp.sigma_bg, poisson=False)
+        plan = st.Plan.for_psf(pp)
+        plan.set_frames(d, w, None, pp.W)
+        NN = pp.N ** 2
+        # a start as from the data: Moffat within a few per cent, amplitudes within 5 %,
+        # positions within 0.2 px, no pixel grid
+        x0 = synth.psf_eval_point(pp, "near", rng)
+        x0[5:5 + NN] = 0.0
+        truth = torch.tensor(pp.params_true, dtype=torch.float32, device="cuda")
+        ft = plan.loss_grad(truth)[0][2].item()
+        kern_true.append(plan.render_scene(truth).cpu().numpy().astype(np.float64))
+        # stage 1: the Moffat, amplitudes and positions by L-BFGS with the pixel grid
+        # b held at zero (a box with lo = hi there; A, widths > 0, beta > 1, a >= 0)
+        lo = np.full(pp.n_params, -np.inf, np.float32)
+        hi = np.full(pp.n_params, np.inf, np.float32)
+        lo[[0, 1, 2]] = 1e-6
+        lo[4], hi[4] = 1.05, 20.0
+        lo[5:5 + NN] = hi[5:5 + NN] = 0.0
+        lo[5 + NN:5 + NN + pp.S] = 0.0
+        x = torch.tensor(np.clip(x0, lo, hi), dtype=torch.float32, device="cuda")
+        f0 = plan.loss_grad(x)[0][2].item()
+        f1, ev = plan.lbfgs(m=10, lo=lo, hi=hi).run(x, 100)
+        err1 = np.abs(plan.render_scene(x).cpu().numpy() - kern_true[-1]).sum() / np.abs(kern_true[-1]).sum()
+        # stage 2: everything, b included, by AdaBelief steps (per-block rates)
+        m = torch.zeros_like(x)
+        v = torch.zeros_like(x)
+        lr4 = [1e-4, 1e-7, 1e-4 * float(np.median(pp.a)), 1e-3]
+        f2 = plan.steps(x, m, v, 1, lr4, 600, rule=st.ADABELIEF, eps=1e-16, eps_root=1e-16)[2].item()
+        kern_fit.append(plan.render_scene(x).cpu().numpy().astype(np.float64))
+        err = np.abs(kern_fit[-1] - kern_true[-1]).sum() / np.abs(kern_true[-1]).sum()
+        _say(f"pipeline psf {e}: loss {f0:.4e} -> {f1:.4e} (L-BFGS, {ev} evals, kernel L1 error {err1:.2e}) "
+             f"-> {f2:.4e} (AdaBelief; at the truth {ft:.4e}), kernel L1 error {err:.2e}")
+        assert f1 < f0 and f2 < f1 and err < 0.3
+    dp = synth.make_small_deconv(311, E, [n_star], [K], s, K, M, J)
+    dp.kernels = synth.f32(np.concatenate([k.ravel() for k in kern_true]))
+    d, w, rng = _data(dp, seed=312)  # the data: true kernels
+    p0 = synth.eval_point(dp, "init", rng)
+    lr4 = [0.5, 0.05, 20.0, 0.01]  # the workloads' Adam rates for h, Gamma, a, c
+    fits = []
+    for kern in (kern_true, kern_fit):
+        plan = st.Plan.for_problem(dp)
+        plan.set_frames(d, w, synth.f32(np.concatenate([k.ravel() for k in kern])), dp.W)
+        x = torch.tensor(p0, dtype=torch.float32, device="cuda")
+        m = torch.zeros_like(x)
+        v = torch.zeros_like(x)
+        loss = plan.steps(x, m, v, 1, lr4, 400)
+        fits.append((x.cpu().numpy().astype(np.float64), plan.loss_grad(x)[0].cpu().numpy()))
+    (xt, lt), (xf, lf) = fits
+    at, af = dp.unpack(xt)[2], dp.unpack(xf)[2]
+    rel = np.abs(af - at) / np.abs(at)
+    _say(f"pipeline deconv: chi2/2 true kernels {lt[0]:.4e}, fitted kernels {lf[0]:.4e}; "
+         f"point amplitudes rel diff median {np.median(rel):.3e} max {rel.max():.3e}")
+    assert lf[0] <= 5.0 * lt[0]
+    assert np.median(rel) <= 0.15
