@@ -850,7 +850,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
     const float *ai = params + (long long)N * N + E + (long long)i * M;
 
     // lanes over columns kx, row groups over ky (no index divisions in the loops)
-    const int CXF = HQ <= 64 ? 64 : 128, RGF = kFusedThreads / CXF;
+    // (threads packed over the HQ columns: column lane = tid % HQ, row group tid / HQ)
+    const int RGF = kFusedThreads / HQ;
     const int Q0L = Q <= 64 ? 64 : 128;  // lanes along a row of Q values
     // this thread's data and weights for the residual (its first kPreRows row pairs),
     // loaded now so that they arrive during the transforms
@@ -872,11 +873,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
         }
     }
     __syncthreads();
-    const int lane = threadIdx.x % CXF, rg = threadIdx.x / CXF;
+    const int lane = threadIdx.x % HQ, rg = threadIdx.x / HQ;
+    const bool colw = rg < RGF;  // this thread works in the column-wise loops
     // model spectrum, column-major: A[kx][ky]
     // (with MS > 0 sources at most, the column factors a_k gx_k(Kx) stay in registers)
     constexpr int MR = MS > 0 ? MS : 1;
-    if (lane < HQ) {
+    if (colw) {
         const int kx = lane;
         const int HP = P / 2 + 1;
         float2 wxG[S], px[S][MR];
@@ -999,7 +1001,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
     // split each pair's spectrum Z into the two rows' (Hermitian) spectra,
     // R_a = (Z(k) + conj Z(-k)) / 2 and R_b = (Z(k) - conj Z(-k)) / 2i, and lay the
     // half spectra out column-major with zero rows y >= n
-    if (lane < HQ) {
+    if (colw) {
         const int km = lane == 0 ? 0 : Q - lane;
         for (int y = rg; y < Q; y += RGF) {
             float2 v = make_float2(0.f, 0.f);
@@ -1014,7 +1016,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
     __syncthreads();
     r = lds_fft_any<false>(o, r, HQ, fl, twQ);  // along y
     float2 *R = Rh + f.r_off;
-    if (lane < HQ)
+    if (colw)
         for (int ky = rg; ky < Q; ky += RGF) R[ky * HQ + lane] = r[lane * Ls + ky];
 }
 
