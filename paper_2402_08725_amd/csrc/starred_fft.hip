@@ -42,10 +42,10 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 
 // radix-R DFT of v in place; sign -1 forward (e^{-i}), +1 inverse
 template <int R>
-__device__ __forceinline__ void dft_small(float2 (&v)[5], bool inv);
+__device__ __forceinline__ void dft_small(float2 (&v)[8], bool inv);
 
 template <>
-__device__ __forceinline__ void dft_small<2>(float2 (&v)[5], bool)
+__device__ __forceinline__ void dft_small<2>(float2 (&v)[8], bool)
 {
     const float2 a = v[0], b = v[1];
     v[0] = cadd(a, b);
@@ -53,7 +53,7 @@ __device__ __forceinline__ void dft_small<2>(float2 (&v)[5], bool)
 }
 
 template <>
-__device__ __forceinline__ void dft_small<4>(float2 (&v)[5], bool inv)
+__device__ __forceinline__ void dft_small<4>(float2 (&v)[8], bool inv)
 {
     const float2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
     const float2 b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
@@ -66,7 +66,7 @@ __device__ __forceinline__ void dft_small<4>(float2 (&v)[5], bool inv)
 }
 
 template <>
-__device__ __forceinline__ void dft_small<3>(float2 (&v)[5], bool inv)
+__device__ __forceinline__ void dft_small<3>(float2 (&v)[8], bool inv)
 {
     const float c1 = -0.5f;
     const float s1 = inv ? 0.86602540378443865f : -0.86602540378443865f;
@@ -81,7 +81,7 @@ __device__ __forceinline__ void dft_small<3>(float2 (&v)[5], bool inv)
 }
 
 template <>
-__device__ __forceinline__ void dft_small<5>(float2 (&v)[5], bool inv)
+__device__ __forceinline__ void dft_small<5>(float2 (&v)[8], bool inv)
 {
     const float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
     const float sg = inv ? 1.f : -1.f;
@@ -102,6 +102,32 @@ __device__ __forceinline__ void dft_small<5>(float2 (&v)[5], bool inv)
     v[3] = csub(m2, iu2);
 }
 
+// radix 8 as two radix-4 transforms of the sums and the twiddled differences
+// of the pairs (n, n+4): even outputs from the sums, odd ones from the differences
+template <>
+__device__ __forceinline__ void dft_small<8>(float2 (&v)[8], bool inv)
+{
+    const float h = 0.70710678118654752f;
+    float2 e[8], o[8];
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        e[k] = cadd(v[k], v[k + 4]);
+        o[k] = csub(v[k], v[k + 4]);
+    }
+    // o[n] *= W8^n, W8 = e^{-i pi/4} (forward) or e^{+i pi/4} (inverse)
+    const float2 b1 = o[1], b2 = o[2], b3 = o[3];
+    o[1] = inv ? make_float2(h * (b1.x - b1.y), h * (b1.x + b1.y)) : make_float2(h * (b1.x + b1.y), h * (b1.y - b1.x));
+    o[2] = inv ? make_float2(-b2.y, b2.x) : make_float2(b2.y, -b2.x);
+    o[3] = inv ? make_float2(-h * (b3.x + b3.y), h * (b3.x - b3.y)) : make_float2(h * (b3.y - b3.x), -h * (b3.x + b3.y));
+    dft_small<4>(e, inv);
+    dft_small<4>(o, inv);
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[2 * k] = e[k];
+        v[2 * k + 1] = o[k];
+    }
+}
+
 template <int R>
 __device__ __forceinline__ void stockham_stage(const float2 *__restrict__ src, float2 *__restrict__ dst,
                                                int nl, int L, int Ls, int Ns, const float2 *__restrict__ tw,
@@ -114,7 +140,7 @@ __device__ __forceinline__ void stockham_stage(const float2 *__restrict__ src, f
         const float2 *in = src + l * Ls;
         float2 *out = dst + l * Ls;
         const int k = j % Ns;
-        float2 v[5];
+        float2 v[8];
         #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = in[j + r * LR];
         if (Ns > 1) {
@@ -159,6 +185,7 @@ __device__ float2 *lds_fft(float2 *a, float2 *b, int nl, const FftLen &f, const 
 constexpr int ct_nrad(int L)
 {
     int n = 0;
+    while (L % 8 == 0) { L /= 8; ++n; }
     while (L % 4 == 0) { L /= 4; ++n; }
     while (L % 2 == 0) { L /= 2; ++n; }
     while (L % 3 == 0) { L /= 3; ++n; }
@@ -168,6 +195,7 @@ constexpr int ct_nrad(int L)
 constexpr int ct_rad(int L, int i)
 {
     int k = 0;
+    while (L % 8 == 0) { if (k++ == i) return 8; L /= 8; }
     while (L % 4 == 0) { if (k++ == i) return 4; L /= 4; }
     while (L % 2 == 0) { if (k++ == i) return 2; L /= 2; }
     while (L % 3 == 0) { if (k++ == i) return 3; L /= 3; }
@@ -191,7 +219,7 @@ __device__ __forceinline__ void stage_ct(const float2 *__restrict__ src, float2 
         const float2 *in = src + l * Ls;
         float2 *out = dst + l * Ls;
         const int k = j % NS;
-        float2 v[5];
+        float2 v[8];
         #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = in[j + r * LR];
         if (NS > 1) {
