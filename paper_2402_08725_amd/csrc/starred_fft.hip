@@ -1022,8 +1022,18 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
             }
             o[yp * Ls + x] = make_float2(va, vb);  // rho rows 2p + i (2p+1)
         }
-    const double tchi = block_sum_d_fft<kFusedThreads>(chi, red);  // synchronises
-    if (threadIdx.x == 0) part_chi[blockIdx.x] = tchi;
+    // the frame's chi-square: wave sums in LDS across the barrier the transform needs
+    // anyway, then thread 0 adds them (in wave order) while the others transform
+    #pragma unroll
+    for (int off = 32; off > 0; off >>= 1) chi += __shfl_xor(chi, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = chi;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tchi = 0.0;
+        #pragma unroll
+        for (int w = 0; w < kFusedThreads / 64; ++w) tchi += red[w];
+        part_chi[blockIdx.x] = tchi;
+    }
     r = lds_fft_any<false>(o, r, n2, fl, twQ);  // rho pairs along x
     o = (r == A) ? B : A;
     // split each pair's spectrum Z into the two rows' (Hermitian) spectra,
