@@ -1130,14 +1130,14 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const SpecItem *__rest
     const int lane = threadIdx.x % CX, rg = threadIdx.x / CX;
     const float2 *t = tab + c.tab_off;
     const int Q3 = 1 + 3 * M;
+    // spectra of the chunk's frames (a missing frame reads frame 0's slot and is zeroed)
     int fid[FC];
-    const float2 *Sf[FC];
-    const float2 *Rf[FC];
+    long long soff[FC], roff[FC];
     #pragma unroll
     for (int f = 0; f < FC; ++f) {
         fid[f] = f < it.nf ? cls_frames[c.cf_off + it.f0 + f] : -1;
-        Sf[f] = f < it.nf ? Sp + fr[fid[f]].s_off : Sp;
-        Rf[f] = f < it.nf ? Rh + fr[fid[f]].r_off : Rh;
+        soff[f] = f < it.nf ? fr[fid[f]].s_off : 0;
+        roff[f] = f < it.nf ? fr[fid[f]].r_off : 0;
     }
     float2 *gout = Gp + c.gp_off + (long long)(it.f0 / c.gfch) * nbins;
     const int HQ = Q / 2 + 1, nr = y1 - y0;
@@ -1172,28 +1172,46 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const SpecItem *__rest
             const int rx = lo ? kxq : Q - kxq;
             const float cj = lo ? 1.f : -1.f;
             int ryq = (y0 + rg) % Q;
-            #pragma unroll 3
-            for (int Ky = y0 + rg; Ky < y1; Ky += RG) {
-                float2 ty[NY];
+            // kAdjRB rows of this thread at a time: every load of the batch is issued
+            // before the first is used (a row group is whole waves, so the row tests are uniform)
+            for (int Kb = y0 + rg; Kb < y1; Kb += kAdjRB * RG) {
+                float2 sv[kAdjRB][FC], rv[kAdjRB][FC];
                 #pragma unroll
-                for (int u = 0; u < NY; ++u) ty[u] = tys[u * kAdjMaxRows + (Ky - y0)];
-                const long long bin = (long long)Ky * HP + Kx;
-                const int ridx = (lo ? ryq : (ryq == 0 ? 0 : Q - ryq)) * HQ + rx;
-                ryq += RG;
-                if (ryq >= Q) ryq -= Q;
-                float2 gsum = make_float2(0.f, 0.f);
+                for (int b = 0; b < kAdjRB; ++b) {
+                    const int Ky = min(Kb + b * RG, y1 - 1);  // rows past the range reload a valid bin
+                    const long long bin = (long long)Ky * HP + Kx;
+                    const int ridx = (lo ? ryq : (ryq == 0 ? 0 : Q - ryq)) * HQ + rx;
+                    ryq += RG;
+                    if (ryq >= Q) ryq -= Q;
+                    #pragma unroll
+                    for (int f = 0; f < FC; ++f) {
+                        sv[b][f] = Sp[soff[f] + bin];
+                        rv[b][f] = Rh[roff[f] + ridx];
+                    }
+                }
                 #pragma unroll
-                for (int f = 0; f < FC; ++f) {
-                    if (f < it.nf) {
-                        float2 rv = Rf[f][ridx];
-                        rv.y *= cj;
-                        const float2 G = cmulc(rv, Sf[f][bin]);
+                for (int b = 0; b < kAdjRB; ++b) {
+                    const int Ky = Kb + b * RG;
+                    if (Ky >= y1) break;
+                    float2 ty[NY];
+                    #pragma unroll
+                    for (int u = 0; u < NY; ++u) ty[u] = tys[u * kAdjMaxRows + (Ky - y0)];
+                    float2 gsum = make_float2(0.f, 0.f);
+                    #pragma unroll
+                    for (int f = 0; f < FC; ++f) {
+                        // a missing frame's product is scaled to zero (a branch here would let
+                        // the compiler sink the loads above back to their use)
+                        const float on = f < it.nf ? 1.f : 0.f;
+                        float2 r = rv[b][f];
+                        r.x *= on;
+                        r.y *= cj * on;
+                        const float2 G = cmulc(r, sv[b][f]);
                         gsum = cadd(gsum, G);
                         #pragma unroll
                         for (int u = 0; u < NY; ++u) V[f][u] = cadd(V[f][u], cmulc(G, ty[u]));
                     }
+                    if (first) gout[(long long)Ky * HP + Kx] = gsum;
                 }
-                if (first) gout[bin] = gsum;
             }
             // fold with the x-tables of this column
             const float wgt = (Kx == 0 || 2 * Kx == P) ? 1.f : 2.f;
