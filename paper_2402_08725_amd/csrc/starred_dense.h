@@ -34,7 +34,7 @@ constexpr int kDenseThreads = 256;
 struct DenseStar {
     int N = 0, J = 0, B = 0;
     int rx = 1;                  // rows per x-pass job
-    const double *taps = nullptr;  // levels 1 .. J-1 one after the other (2 bw(j) + 1 taps each)
+    const double *taps = nullptr;  // levels 1 .. J-1 one after the other (plen(j) entries each)
     const float *img = nullptr;  // image 0 (N x N)
     const float *img1 = nullptr; // image 1 (N x N), when B = 2
     double *T = nullptr;         // [B][J][N][N]: plane j >= 1 = x M_j^T, then (pass D1) D^-1 (M_j U_j) D^-1
@@ -47,9 +47,13 @@ struct DenseStar {
     float *out = nullptr;        // [B][N][N]
     double *part_l1 = nullptr;   // [B][J][rows jobs]
 
-    // half width of level j's composite filter, 2^{j+1} - 2, and the offset of its taps
-    __host__ __device__ static int bw(int j) { return (2 << j) - 2; }
-    __host__ __device__ static int toff(int j) { return (4 << j) - 8 - 3 * (j - 1); }
+    // half width of level j's composite filter, 2^{j+1} - 2; its 2 bw + 1 taps
+    // zero-padded to plen(j), a multiple of 16 (the filter loops read whole blocks
+    // of 16), at offset toff(j)
+    __host__ __device__ static constexpr int bw(int j) { return (2 << j) - 2; }
+    __host__ __device__ static constexpr int plen(int j) { return (2 * bw(j) + 1 + 15) & ~15; }
+    // sum of plen(l) for l < j: 16 for level 1, 2^{l+2} for l >= 2
+    __host__ __device__ static constexpr int toff(int j) { return j >= 2 ? (4 << j) : 0; }
     __host__ __device__ int xjobs() const { return (N + rx - 1) / rx; }
     __host__ __device__ int tiles() const { return (N + kDenseTile - 1) / kDenseTile; }
     __host__ __device__ int jobs_a() const { return B * (J - 1) * xjobs(); }
@@ -90,12 +94,13 @@ __device__ __forceinline__ double dense_block_sum(double v, double *sh)
 }
 
 // sum_t a[t] s[t stride] (taps uniform across the work group, s in LDS), in
-// blocks of 16 taps so that each block's loads are in flight together
+// whole blocks of 16 taps whose loads are in flight together: the taps past nt
+// are the level's zero padding, against staged samples (or the staging's zero
+// tail), so they add exact zeros
 __device__ __forceinline__ double dense_dot(const double *a, const double *s, int stride, int nt)
 {
     double acc = 0.0;
-    int t = 0;
-    for (; t + 16 <= nt; t += 16) {
+    for (int t = 0; t < nt; t += 16) {
         double av[16], sv[16];
         #pragma unroll
         for (int u = 0; u < 16; ++u) {
@@ -105,15 +110,16 @@ __device__ __forceinline__ double dense_dot(const double *a, const double *s, in
         #pragma unroll
         for (int u = 0; u < 16; ++u) acc = fma(av[u], sv[u], acc);
     }
-    for (; t < nt; ++t) acc = fma(a[t], s[t * stride], acc);
     return acc;
 }
 
 // Stages n values through LDS with kDenseBatch independent loads in flight per
-// thread; load(e) is only called with e < n.
+// thread, then nz zeros after them; load(e) is only called with e < n.
 constexpr int kDenseBatch = 8;
+constexpr int kDenseXTail = 16;       // zeros after an x-pass job's rows
+constexpr int kDenseYTail = 15 * 16;  // zero rows after a y-pass strip (16 wide)
 template <class Load>
-__device__ __forceinline__ void dense_stage(double *lds, int n, Load load)
+__device__ __forceinline__ void dense_stage(double *lds, int n, int nz, Load load)
 {
     for (int base = threadIdx.x; base < n; base += kDenseBatch * blockDim.x) {
         double v[kDenseBatch];
@@ -125,6 +131,7 @@ __device__ __forceinline__ void dense_stage(double *lds, int n, Load load)
             if (e < n) lds[e] = v[u];
         }
     }
+    for (int e = threadIdx.x; e < nz; e += blockDim.x) lds[n + e] = 0.0;
 }
 
 // Rows y0 .. y0+ny-1, filtered along x by level j's composite filter through
@@ -133,7 +140,7 @@ template <class Src, class Dst>
 __device__ __forceinline__ void dense_xpass(const DenseStar &d, int j, int y0, int ny, double *lds, Src src, Dst dst)
 {
     const int N = d.N, bw = d.bw(j), L = N + 2 * bw, nt = 2 * bw + 1;
-    dense_stage(lds, ny * L, [&](int e) {
+    dense_stage(lds, ny * L, kDenseXTail, [&](int e) {
         const int r = e / L, i = e - r * L - bw;
         return src(y0 + r, dmirror(i, N));
     });
@@ -163,7 +170,7 @@ template <class Src>
 __device__ __forceinline__ void dense_ystage(const DenseStar &d, int j, int y0, int x0, double *lds, Src src)
 {
     const int R = kDenseTile + 2 * d.bw(j);
-    dense_stage(lds, R * kDenseTile, [&](int e) { return dense_strip_at(d, j, y0, x0, e, src); });
+    dense_stage(lds, R * kDenseTile, kDenseYTail, [&](int e) { return dense_strip_at(d, j, y0, x0, e, src); });
 }
 
 // Level j's filter along y at output (y0 + ty, x0 + tx) from a staged strip.
@@ -270,7 +277,7 @@ __device__ __forceinline__ void dense_job_d(const DenseStar &d, int job, double 
     // every level's strip in one batched staging pass (levels one after the other)
     int total = 0;
     for (int j = 1; j < d.J; ++j) total += (kDenseTile + 2 * d.bw(j)) * kDenseTile;
-    dense_stage(lds, total, [&](int e) {
+    dense_stage(lds, total, kDenseYTail, [&](int e) {
         int j = 1, off = 0;
         while (e >= off + (kDenseTile + 2 * d.bw(j)) * kDenseTile) off += (kDenseTile + 2 * d.bw(j++)) * kDenseTile;
         const double *U = d.U + d.plane(b, j);

@@ -1387,7 +1387,7 @@ struct OpGRowsFin {
 static size_t piece_lds(const DensePiece &p)
 {
     if (p.pass < 0) return 0;
-    if (p.pass == 0 || p.pass == 2) return sizeof(double) * (size_t)p.d.rx * (p.d.N + 2 * DenseStar::bw(p.d.J - 1));
+    if (p.pass == 0 || p.pass == 2) return dense_lds_xr(p.d.N, p.d.J, p.d.rx);
     return p.pass == 3 ? dense_lds_d(p.d.J) : dense_lds_y(p.d.J);
 }
 

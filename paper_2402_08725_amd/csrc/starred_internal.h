@@ -134,6 +134,7 @@ int dense_rows_for(int N, int threads);  // rows per x-pass job for work groups 
 int dense_num_taps(int J);
 void dense_taps(int J, double *out);  // host: the composite filters of levels 1 .. J-1
 size_t dense_lds_x(int N, int J);
+size_t dense_lds_xr(int N, int J, int rx);  // rx rows per job
 size_t dense_lds_y(int J);
 size_t dense_lds_d(int J);
 // L1 partials (part_l1, if set) and, with out set, the subgradient's image

@@ -46,17 +46,21 @@ __global__ void k_dense_coeffs(DenseStar d, float *coeffs)
     coeffs[e] = (float)dense_alpha(d, b, j, (int)(pix / d.N), (int)(pix % d.N));
 }
 
-size_t dense_lds_x(int N, int J)
+size_t dense_lds_xr(int N, int J, int rx)
 {
-    const int rx = dense_rows_per_job(N);
-    return sizeof(double) * (size_t)rx * (N + 2 * DenseStar::bw(J - 1));
+    return sizeof(double) * ((size_t)rx * (N + 2 * DenseStar::bw(J - 1)) + kDenseXTail);
 }
 
-size_t dense_lds_y(int J) { return sizeof(double) * kDenseTile * (size_t)(kDenseTile + 2 * DenseStar::bw(J - 1)); }
+size_t dense_lds_x(int N, int J) { return dense_lds_xr(N, J, dense_rows_per_job(N)); }
+
+size_t dense_lds_y(int J)
+{
+    return sizeof(double) * (kDenseTile * (size_t)(kDenseTile + 2 * DenseStar::bw(J - 1)) + kDenseYTail);
+}
 
 size_t dense_lds_d(int J)
 {
-    size_t n = 0;
+    size_t n = kDenseYTail;
     for (int j = 1; j < J; ++j) n += (size_t)(kDenseTile + 2 * DenseStar::bw(j)) * kDenseTile;
     return sizeof(double) * n;
 }
@@ -84,7 +88,7 @@ void dense_taps(int J, double *out)
         for (size_t i = 0; i < a.size(); ++i)
             for (int t = 0; t < 5; ++t) n[i + t * d] += a[i] * h[t];
         a.swap(n);
-        for (size_t i = 0; i < a.size(); ++i) out[DenseStar::toff(j) + i] = a[i];
+        for (int i = 0; i < DenseStar::plen(j); ++i) out[DenseStar::toff(j) + i] = i < (int)a.size() ? a[i] : 0.0;
     }
 }
 
