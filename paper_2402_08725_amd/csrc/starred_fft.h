@@ -19,6 +19,9 @@ constexpr int kAdjBlocks = 512;        // spectral adjoint: work groups aimed at
 constexpr int kAdjMinRows = 4;         // spectral adjoint: fewest rows per thread
 constexpr int kAdjMaxRows = 64;        // spectral adjoint: most rows per work group
 constexpr int kAdjRB = 3;              // spectral adjoint: rows of a thread whose loads are issued together
+constexpr int kSumBins = 64;           // chunk-spectrum sums: bins of a work group
+constexpr int kSumParts = 4;           // chunk-spectrum sums: runs of chunks per bin (threads)
+constexpr int kSumBatch = 16;          // chunk-spectrum sums: loads of a run in flight together
 // spectral adjoint: column lanes of a work group (64, 128 or 256, a divisor of its
 // threads), the smallest that covers the P/2+1 columns
 __host__ __device__ inline int adj_lanes(int HP) { return HP <= 64 ? 64 : (HP <= 128 ? 128 : 256); }

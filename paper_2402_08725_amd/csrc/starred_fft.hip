@@ -1269,27 +1269,51 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const SpecItem *__rest
 
 // Two independent reductions in one launch, each in a fixed order:
 //  blocks [0, gblocks): the frame-chunk spectra of each class summed into the
-//    first chunk's slot (every thread owns one bin of one class);
+//    first chunk's slot: a block takes kSumBins consecutive bins and kSumParts
+//    threads per bin, each summing its own run of consecutive chunks (every load
+//    of the run in flight together), the runs then added in order;
 //  the remaining blocks: per-frame sums of the per-block dot products,
 //    fsum[i][q], one thread per (frame, quantity).
-__global__ void k_adj_sums(const ClassFft *__restrict__ classes, int ncls, int gblocks,
-                           const FrameFft *__restrict__ fr, int E, int M, int maxpb,
-                           float2 *__restrict__ Gp, const double *__restrict__ part, double *__restrict__ fsum)
+__global__ __launch_bounds__(256) void k_adj_sums(const ClassFft *__restrict__ classes, int ncls, int gblocks,
+                                                  const FrameFft *__restrict__ fr, int E, int M, int maxpb,
+                                                  float2 *__restrict__ Gp, const double *__restrict__ part,
+                                                  double *__restrict__ fsum)
 {
+    static_assert(kSumBins * kSumParts == 256, "one thread per (bin, run)");
     if ((int)blockIdx.x < gblocks) {
-        int g = blockIdx.x * blockDim.x + threadIdx.x;
+        __shared__ float2 runs[kSumParts][kSumBins];
+        const int lane = threadIdx.x % kSumBins, q = threadIdx.x / kSumBins;
+        int g = blockIdx.x * kSumBins + lane;
+        float2 *gp = nullptr;
+        int ngch = 0;
+        long long nbins = 0;
         for (int ci = 0; ci < ncls; ++ci) {
             const ClassFft &c = classes[ci];
-            const int nbins = c.P * (c.P / 2 + 1);
-            if (g < nbins) {
-                float2 *gp = Gp + c.gp_off + g;
-                float2 acc = gp[0];
-                #pragma unroll 8
-                for (int ch = 1; ch < c.ngch; ++ch) acc = cadd(acc, gp[(long long)ch * nbins]);
-                gp[0] = acc;
-                return;
+            const int nb = c.P * (c.P / 2 + 1);
+            if (g < nb) {
+                gp = Gp + c.gp_off + g;
+                ngch = c.ngch;
+                nbins = nb;
+                break;
             }
-            g -= nbins;
+            g -= nb;
+        }
+        float2 acc = make_float2(0.f, 0.f);
+        const int per = (ngch + kSumParts - 1) / kSumParts, c0 = q * per, c1 = min(ngch, c0 + per);
+        for (int b0 = c0; b0 < c1; b0 += kSumBatch) {
+            float2 v[kSumBatch];
+            #pragma unroll
+            for (int u = 0; u < kSumBatch; ++u) v[u] = gp[(long long)min(b0 + u, c1 - 1) * nbins];
+            #pragma unroll
+            for (int u = 0; u < kSumBatch; ++u)
+                if (b0 + u < c1) acc = cadd(acc, v[u]);
+        }
+        runs[q][lane] = acc;
+        __syncthreads();
+        if (q == 0 && gp) {
+            #pragma unroll
+            for (int r = 1; r < kSumParts; ++r) acc = cadd(acc, runs[r][lane]);
+            gp[0] = acc;
         }
         return;
     }
@@ -1557,7 +1581,7 @@ hipError_t fft_spec_adj(hipStream_t st, const FftPlanDev &d, int M)
 
 hipError_t fft_adj_sums(hipStream_t st, const FftPlanDev &d, int M, double *fsum)
 {
-    const int gblocks = (int)((d.total_bins + 255) / 256);
+    const int gblocks = (int)((d.total_bins + kSumBins - 1) / kSumBins);
     const int fblocks = (d.n_frames * (1 + 3 * M) + 255) / 256;
     if (gblocks + fblocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_adj_sums, dim3(gblocks + fblocks), dim3(256), 0, st, d.classes, d.n_classes, gblocks,
