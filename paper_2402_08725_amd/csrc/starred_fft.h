@@ -84,6 +84,23 @@ struct SpecItem {
     int bin0;
 };
 
+// A work group of the frequency-domain adjoint: a chunk of frames and a range of
+// rows of one class, with everything the group needs resolved on the host (so
+// its loads depend on this item alone).
+struct AdjItem {
+    int cls;
+    int nf;                      // frames in the chunk
+    int y0, y1;                  // rows [y0, y1) of the P x (P/2+1) half spectrum
+    int P, Q;
+    int pb;                      // row range index (the per-frame partial slot)
+    int pad;
+    int fid[kAdjFrames];         // frame indices (-1 past nf)
+    long long soff[kAdjFrames];  // kernel spectra S'' (frame 0's slot past nf)
+    long long roff[kAdjFrames];  // rho_hat (frame 0's slot past nf)
+    long long tab_off;           // the class's factor tables
+    long long gout;              // the chunk's slot in the chunk spectra
+};
+
 struct LinePass {
     LineItem *items = nullptr;  // device
     int n_items = 0;
@@ -107,7 +124,7 @@ struct FftPlanDev {
     int *gcsr_off = nullptr, *gcsr_item = nullptr;
     // frequency-domain adjoint
     int n_frames = 0;
-    SpecItem *aspec = nullptr;
+    AdjItem *aspec = nullptr;
     int n_aspec = 0;
     int maxpb = 0;           // per-frame partial slots (largest nrr)
     long long total_bins = 0;  // sum over classes of P (P/2 + 1)

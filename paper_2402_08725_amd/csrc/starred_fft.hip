@@ -1108,10 +1108,7 @@ __device__ void tables_part(const ClassFft &c, const float2 *__restrict__ tw, co
 // block reduces the dot products once per group of kAdjSB sources through LDS.
 // The per-block partials are summed per frame (and the chunk spectra over chunks)
 // by k_adj_sums.
-__global__ __launch_bounds__(kFftThreads) void k_spec_adj(const SpecItem *__restrict__ items,
-                                                          const ClassFft *__restrict__ classes,
-                                                          const FrameFft *__restrict__ fr,
-                                                          const int *__restrict__ cls_frames,
+__global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restrict__ items,
                                                           const float2 *__restrict__ Sp,
                                                           const float2 *__restrict__ Rh,
                                                           const float2 *__restrict__ tab, int M, int maxpb,
@@ -1121,25 +1118,24 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const SpecItem *__rest
     constexpr int kRow = kFftThreads + 8;  // padded LDS rows of per-thread partials
     static_assert(FC * NQ <= 2 * 32, "two reduction passes of 32 quantities");
     __shared__ float red[32 * kRow];
-    const SpecItem it = items[blockIdx.x];
-    const ClassFft &c = classes[it.cls];
-    const int P = c.P, Q = c.Q, HP = P / 2 + 1, nbins = P * HP;
-    const int y0 = it.bin0, y1 = min(P, y0 + c.arr), pb = y0 / c.arr;
+    const AdjItem &it = items[blockIdx.x];
+    const int P = it.P, Q = it.Q, HP = P / 2 + 1;
+    const int y0 = it.y0, y1 = it.y1, pb = it.pb;
     // lanes over columns, row groups over rows
     const int CX = adj_lanes(HP), RG = kFftThreads / CX;
     const int lane = threadIdx.x % CX, rg = threadIdx.x / CX;
-    const float2 *t = tab + c.tab_off;
+    const float2 *t = tab + it.tab_off;
     const int Q3 = 1 + 3 * M;
     // spectra of the chunk's frames (a missing frame reads frame 0's slot and is zeroed)
     int fid[FC];
     long long soff[FC], roff[FC];
     #pragma unroll
     for (int f = 0; f < FC; ++f) {
-        fid[f] = f < it.nf ? cls_frames[c.cf_off + it.f0 + f] : -1;
-        soff[f] = f < it.nf ? fr[fid[f]].s_off : 0;
-        roff[f] = f < it.nf ? fr[fid[f]].r_off : 0;
+        fid[f] = it.fid[f];
+        soff[f] = it.soff[f];
+        roff[f] = it.roff[f];
     }
-    float2 *gout = Gp + c.gp_off + (long long)(it.f0 / c.gfch) * nbins;
+    float2 *gout = Gp + it.gout;
     const int HQ = Q / 2 + 1, nr = y1 - y0;
     __shared__ float2 tys[NY * kAdjMaxRows];  // y-tables of the block's rows
     for (int k0 = 0; k0 < max(M, 1); k0 += SB) {
@@ -1574,8 +1570,8 @@ hipError_t fft_adj_rows(hipStream_t st, const FftPlanDev &d, float *g)
 hipError_t fft_spec_adj(hipStream_t st, const FftPlanDev &d, int M)
 {
     if (d.n_aspec == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spec_adj, dim3(d.n_aspec), dim3(kFftThreads), 0, st, d.aspec, d.classes, d.frames,
-                       d.cls_frames, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart);
+    hipLaunchKernelGGL(k_spec_adj, dim3(d.n_aspec), dim3(kFftThreads), 0, st, d.aspec, d.S, d.Rh, d.tab, M,
+                       d.maxpb, d.Gp, d.apart);
     return hipGetLastError();
 }
 

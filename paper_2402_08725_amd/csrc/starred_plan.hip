@@ -597,7 +597,7 @@ static int build_fft(starred_plan *p)
     // frequency-domain adjoint: items over chunks of kAdjFrames frames x ranges of
     // rows of the P half spectrum, about kAdjBlocks of them per launch
     {
-        std::vector<SpecItem> sp;
+        std::vector<AdjItem> sp;
         long long gp = 0, hc = 0;
         int maxpb = 0, nchunks = 0;
         for (const ClassFft &cl : p->cls) nchunks += (cl.ncf + kAdjFrames - 1) / kAdjFrames;
@@ -620,10 +620,27 @@ static int build_fft(starred_plan *p)
             hc += (long long)cl.F * cl.F;
             maxpb = std::max(maxpb, cl.nrr);
             for (int f0 = 0; f0 < cl.ncf; f0 += kAdjFrames)
-                for (int r = 0; r < cl.nrr; ++r)
-                    sp.push_back(SpecItem{c, f0, std::min(kAdjFrames, cl.ncf - f0), r * arr});
+                for (int r = 0; r < cl.nrr; ++r) {
+                    AdjItem it{};
+                    it.cls = c;
+                    it.nf = std::min(kAdjFrames, cl.ncf - f0);
+                    it.y0 = r * arr;
+                    it.y1 = std::min(cl.P, it.y0 + arr);
+                    it.P = cl.P;
+                    it.Q = cl.Q;
+                    it.pb = r;
+                    for (int f = 0; f < kAdjFrames; ++f) {
+                        const int fi = f < it.nf ? cls_frames[cl.cf_off + f0 + f] : -1;
+                        it.fid[f] = fi;
+                        it.soff[f] = fi >= 0 ? p->ffr[fi].s_off : 0;
+                        it.roff[f] = fi >= 0 ? p->ffr[fi].r_off : 0;
+                    }
+                    it.tab_off = cl.tab_off;
+                    it.gout = cl.gp_off + (long long)(f0 / cl.gfch) * nbins;
+                    sp.push_back(it);
+                }
         }
-        std::stable_sort(sp.begin(), sp.end(), [&](const SpecItem &a, const SpecItem &b) {
+        std::stable_sort(sp.begin(), sp.end(), [&](const AdjItem &a, const AdjItem &b) {
             return p->cls[a.cls].P > p->cls[b.cls].P;
         });
         d.n_frames = E;
@@ -635,7 +652,7 @@ static int build_fft(starred_plan *p)
         if ((rc = p->alloc(&d.apart, (size_t)E * maxpb * (1 + 3 * M)))) return rc;
         if ((rc = p->alloc(&d.Gp, gp))) return rc;
         if ((rc = p->alloc(&d.hcls, hc))) return rc;
-        if (!sp.empty()) HIP_TRY(hipMemcpy(d.aspec, sp.data(), sizeof(SpecItem) * sp.size(), hipMemcpyHostToDevice));
+        if (!sp.empty()) HIP_TRY(hipMemcpy(d.aspec, sp.data(), sizeof(AdjItem) * sp.size(), hipMemcpyHostToDevice));
     }
     HIP_TRY(hipMemcpy(d.classes, p->cls.data(), sizeof(ClassFft) * p->cls.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d.frames, p->ffr.data(), sizeof(FrameFft) * E, hipMemcpyHostToDevice));
