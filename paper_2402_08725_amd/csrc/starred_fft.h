@@ -84,6 +84,20 @@ struct SpecItem {
     int bin0;
 };
 
+// A work group of the one-launch forward: its frame with the offsets it reads,
+// resolved on the host (the class record itself is only needed for the
+// transforms' factor tables, later).
+struct FusedItem {
+    int frame, cls;
+    int P, Q, n, pad;     // sizes
+    long long tw_off;     // the Q-point twiddles
+    long long s_off;      // kernel spectrum S''
+    long long data_off;   // data and inverse variances
+    long long r_off;      // rho_hat (output)
+    long long tab_off;    // the class's factor tables
+    long long hh_off;     // the class's spectrum of h
+};
+
 // A work group of the frequency-domain adjoint: a chunk of frames and a range of
 // rows of one class, with everything the group needs resolved on the host (so
 // its loads depend on this item alone).
@@ -136,7 +150,7 @@ struct FftPlanDev {
     // per frame); the line passes below cover the remaining frames
     SpecItem *spec_lg = nullptr;
     int n_spec_lg = 0;
-    int *fused = nullptr;
+    FusedItem *fused = nullptr;
     int n_fused = 0;
     size_t fused_lds = 0;
     LinePass fcols_lg, frows_lg, rcols_lg;

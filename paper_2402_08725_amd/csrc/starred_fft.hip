@@ -830,9 +830,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
 // planes of max(Q/2+1, n) lines of stride Q+1 alternate as FFT source and
 // scratch; the Q-point twiddles and the class's factor tables sit behind them.
 template <int S, int MS>
-__global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restrict__ frames,
+__global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const FusedItem *__restrict__ items,
                                                              const ClassFft *__restrict__ classes,
-                                                             const FrameFft *__restrict__ fr,
                                                              const float2 *__restrict__ tw,
                                                              const float2 *__restrict__ Sp,
                                                              const float2 *__restrict__ Hh,
@@ -846,19 +845,18 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
     extern __shared__ float2 sm[];
     __shared__ double red[kFusedThreads / 64];
     if (dense_piece_run(dp, sm, red)) return;  // a starlet-prior job carried by this launch
-    const int i = frames[blockIdx.x];
-    const FrameFft &f = fr[i];
-    const ClassFft &c = classes[f.cls];
-    const FftLen &fl = c.fQ;
-    const float2 *twQ = tw + fl.tw_off;
-    const int P = c.P, Q = c.Q, HQ = Q / 2 + 1, n = c.n, Ls = Q + 1;
+    const FusedItem &f = items[blockIdx.x];
+    const int i = f.frame;
+    const FftLen &fl = classes[f.cls].fQ;
+    const float2 *twQ = tw + f.tw_off;
+    const int P = f.P, Q = f.Q, HQ = Q / 2 + 1, n = f.n, Ls = Q + 1;
     const int rows = HQ > n ? HQ : n;
     float2 *A = sm, *B = sm + rows * Ls;
     float2 *twl = sm + 2 * rows * Ls;
     float2 *t = twl + Q;
     {
         // the twiddles and the tables: all of a thread's loads issued before its LDS writes
-        const float2 *tg = tab + c.tab_off;
+        const float2 *tg = tab + f.tab_off;
         const int nt = (1 + 4 * M) * P;
         constexpr int kTabBatch = 4;
         for (int e = threadIdx.x; e < Q; e += blockDim.x) twl[e] = twQ[e];
@@ -873,7 +871,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const int *__restri
     }
     twQ = twl;
     const float2 *Si = Sp + f.s_off;
-    const float2 *Hc = Hh + c.hh_off;
+    const float2 *Hc = Hh + f.hh_off;
     const float G = params[(long long)N * N + i];
     const float *ai = params + (long long)N * N + E + (long long)i * M;
 
@@ -1520,7 +1518,7 @@ hipError_t fft_fused_fwd(hipStream_t st, const FftPlanDev &d, const float *param
     const int grid = d.n_fused + (dp.pass >= 0 ? dp.jobs : 0);
 #define FUSED_FWD(SS, MS)                                                                                     \
     hipLaunchKernelGGL((k_frame_fwd<SS, MS>), dim3(grid), dim3(kFusedThreads), lds, st, d.fused, d.classes,      \
-                       d.frames, d.tw, d.S, d.Hh, d.tab, params, N, E, M, data, invvar, d.Rh, part_chi, dp)
+                       d.tw, d.S, d.Hh, d.tab, params, N, E, M, data, invvar, d.Rh, part_chi, dp)
 #define FUSED_FWD_M(SS)                       \
     if (M <= 4) FUSED_FWD(SS, 4);             \
     else if (M <= 8) FUSED_FWD(SS, 8);        \

@@ -580,19 +580,37 @@ static int build_fft(starred_plan *p)
     HIP_TRY(hipMemcpy(d.cls_frames, cls_frames.data(), sizeof(int) * cls_frames.size(), hipMemcpyHostToDevice));
     // frames of the one-launch forward, largest transforms first
     {
-        std::vector<int> fu;
+        std::vector<int> fi;
         size_t lds = 0;
         for (int i = 0; i < E; ++i)
             if (p->cls[fcls[i]].fused) {
-                fu.push_back(i);
+                fi.push_back(i);
                 const ClassFft &cl = p->cls[fcls[i]];
                 lds = std::max(lds, fused_lds_bytes(cl.Q, cl.n, cl.P, M));
             }
-        std::stable_sort(fu.begin(), fu.end(), [&](int a, int b) { return p->cls[fcls[a]].Q > p->cls[fcls[b]].Q; });
+        std::stable_sort(fi.begin(), fi.end(), [&](int a, int b) { return p->cls[fcls[a]].Q > p->cls[fcls[b]].Q; });
+        std::vector<FusedItem> fu;
+        for (int i : fi) {
+            const ClassFft &cl = p->cls[fcls[i]];
+            const FrameFft &f = p->ffr[i];
+            FusedItem it{};
+            it.frame = i;
+            it.cls = fcls[i];
+            it.P = cl.P;
+            it.Q = cl.Q;
+            it.n = cl.n;
+            it.tw_off = cl.fQ.tw_off;
+            it.s_off = f.s_off;
+            it.data_off = f.data_off;
+            it.r_off = f.r_off;
+            it.tab_off = cl.tab_off;
+            it.hh_off = cl.hh_off;
+            fu.push_back(it);
+        }
         d.n_fused = (int)fu.size();
         d.fused_lds = lds;
         if ((rc = p->alloc(&d.fused, std::max<size_t>(1, fu.size())))) return rc;
-        if (!fu.empty()) HIP_TRY(hipMemcpy(d.fused, fu.data(), sizeof(int) * fu.size(), hipMemcpyHostToDevice));
+        if (!fu.empty()) HIP_TRY(hipMemcpy(d.fused, fu.data(), sizeof(FusedItem) * fu.size(), hipMemcpyHostToDevice));
     }
     // frequency-domain adjoint: items over chunks of kAdjFrames frames x ranges of
     // rows of the P half spectrum, about kAdjBlocks of them per launch
