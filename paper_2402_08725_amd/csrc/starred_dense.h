@@ -113,6 +113,62 @@ __device__ __forceinline__ double dense_dot(const double *a, const double *s, in
     return acc;
 }
 
+// The composite taps of the levels up to kDenseConstLevels, built at compile time
+// (a_j = a_{j-1} * h_{j-1}, h_l the B3 kernel (1 4 6 4 1)/16 with holes 2^l). Each tap
+// is a dyadic rational with at most 20 significant bits, so it is an exact FP64
+// instruction literal: the filter loops of these levels load no taps at all (a tap
+// read from memory costs a dependent round trip per block of 16 taps).
+constexpr int kDenseConstLevels = 5;
+struct DenseConstTaps {
+    double v[DenseStar::toff(kDenseConstLevels + 1)];
+};
+constexpr DenseConstTaps dense_const_taps()
+{
+    constexpr int kLen = 2 * DenseStar::bw(kDenseConstLevels) + 1;
+    DenseConstTaps t{};
+    double a[kLen] = {}, n[kLen] = {};
+    const double h[5] = {1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16};
+    int len = 1;
+    a[0] = 1.0;
+    for (int j = 1; j <= kDenseConstLevels; ++j) {
+        const int d = 1 << (j - 1), nl = len + 4 * d;
+        for (int i = 0; i < nl; ++i) n[i] = 0.0;
+        for (int i = 0; i < len; ++i)
+            for (int k = 0; k < 5; ++k) n[i + k * d] += a[i] * h[k];
+        for (int i = 0; i < nl; ++i) {
+            a[i] = n[i];
+            t.v[DenseStar::toff(j) + i] = n[i];
+        }
+        len = nl;
+    }
+    return t;
+}
+constexpr DenseConstTaps kDenseConstTaps = dense_const_taps();
+
+// Level LV's filter, sum_t a[t] s[t stride], with literal taps (four interleaved sums)
+template <int LV>
+__device__ __forceinline__ double dense_dot_lv(const double *s, int stride)
+{
+    constexpr int nt = 2 * DenseStar::bw(LV) + 1, off = DenseStar::toff(LV);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    #pragma unroll
+    for (int t = 0; t < nt; ++t) acc[t & 3] = fma(kDenseConstTaps.v[off + t], s[t * stride], acc[t & 3]);
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// Level j's filter: literal taps up to kDenseConstLevels, the padded table beyond
+__device__ __forceinline__ double dense_dot_level(const DenseStar &d, int j, const double *s, int stride)
+{
+    switch (j) {
+    case 1: return dense_dot_lv<1>(s, stride);
+    case 2: return dense_dot_lv<2>(s, stride);
+    case 3: return dense_dot_lv<3>(s, stride);
+    case 4: return dense_dot_lv<4>(s, stride);
+    case 5: return dense_dot_lv<5>(s, stride);
+    default: return dense_dot(d.taps + d.toff(j), s, stride, 2 * d.bw(j) + 1);
+    }
+}
+
 // Stages n values through LDS with kDenseBatch independent loads in flight per
 // thread, then nz zeros after them; load(e) is only called with e < n.
 constexpr int kDenseBatch = 8;
@@ -139,16 +195,15 @@ __device__ __forceinline__ void dense_stage(double *lds, int n, int nz, Load loa
 template <class Src, class Dst>
 __device__ __forceinline__ void dense_xpass(const DenseStar &d, int j, int y0, int ny, double *lds, Src src, Dst dst)
 {
-    const int N = d.N, bw = d.bw(j), L = N + 2 * bw, nt = 2 * bw + 1;
+    const int N = d.N, bw = d.bw(j), L = N + 2 * bw;
     dense_stage(lds, ny * L, kDenseXTail, [&](int e) {
         const int r = e / L, i = e - r * L - bw;
         return src(y0 + r, dmirror(i, N));
     });
     __syncthreads();
-    const double *a = d.taps + d.toff(j);
     for (int o = threadIdx.x; o < ny * N; o += blockDim.x) {
         const int r = o / N, x = o - r * N;
-        dst(y0 + r, x, dense_dot(a, lds + r * L + x, 1, nt));
+        dst(y0 + r, x, dense_dot_level(d, j, lds + r * L + x, 1));
     }
 }
 
@@ -177,7 +232,7 @@ __device__ __forceinline__ void dense_ystage(const DenseStar &d, int j, int y0, 
 
 __device__ __forceinline__ double dense_ysum(const DenseStar &d, int j, const double *lds, int ty, int tx)
 {
-    return dense_dot(d.taps + d.toff(j), lds + ty * kDenseTile + tx, kDenseTile, 2 * d.bw(j) + 1);
+    return dense_dot_level(d, j, lds + ty * kDenseTile + tx, kDenseTile);
 }
 
 // ---- pass A: T_j = x M_j^T ----
