@@ -192,6 +192,17 @@ def test_loss_grad_parity(name, make, point, algo):
     _compare_loss_grad(prob, d, w, p, plan, f"{name}/{point}/{ALGO_ID[algo]}")
 
 
+@pytest.mark.parametrize("E", [1, 3, 5])
+def test_loss_grad_parity_few_epochs_fft(E):
+    """The frequency-domain adjoint with fewer frame chunks than the chunk sums' runs per
+    bin (1 or 2 chunks), and a last chunk holding a single frame (odd E)."""
+    prob = synth.make_deconv(2, E=E)
+    d, w, rng = _data(prob, seed=40 + E)
+    plan = _plan(prob, d, w, 2)
+    p = synth.eval_point(prob, "near", rng)
+    _compare_loss_grad(prob, d, w, p, plan, f"cfg2_E{E}/fft")
+
+
 @pytest.mark.parametrize("name,make", [LG_CASES[1], LG_CASES[2], LG_CASES[3]], ids=["cfg2_E6", "cfg4_mini",
                                                                                    "small_s3"])
 def test_fft_line_passes_without_the_fused_forward(name, make):
