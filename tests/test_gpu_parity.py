@@ -194,6 +194,18 @@ def test_loss_grad_parity(name, make, point, algo):
     _compare_loss_grad(prob, d, w, p, plan, f"{name}/{point}/{ALGO_ID[algo]}")
 
 
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+def test_loss_grad_parity_seven_scales(algo):
+    """Seven starlet scales on a 128 grid: the prior's level-6 filters come from the
+    padded tap table (levels 1-5 are compiled in), inside the step's launches on the
+    FFT path."""
+    prob = synth.make_small_deconv(211, 3, [64, 64, 64], [31, 25, 31], 2, 128, 2, 7)
+    d, w, rng = _data(prob, seed=211)
+    plan = _plan(prob, d, w, algo)
+    p = synth.eval_point(prob, "near", rng)
+    _compare_loss_grad(prob, d, w, p, plan, f"J7/{ALGO_ID[algo]}")
+
+
 @pytest.mark.parametrize("E", [1, 3, 5])
 def test_loss_grad_parity_few_epochs_fft(E):
     """The frequency-domain adjoint with fewer frame chunks than the chunk sums' runs per
