@@ -635,6 +635,49 @@ def test_cfg4_full_size_sampled_frames_and_properties(algo):
     assert abs(fd - an) <= 1e-4 * abs(an)
 
 
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+def test_cfg5_full_size_sampled_frame_and_properties(algo):
+    """The large field at full size (12 epochs of 256^2 data, 512^2 grid, 128^2 kernels,
+    30 sources, 8 scales): model parity on one whole frame, the adjoint identity, and
+    exact central differences of the loss along h (chi^2 is quadratic in h)."""
+    st = _st()
+    prob = synth.make_deconv(5)
+    rng = np.random.default_rng(12)
+    scene = synth.f32(rng.standard_normal(prob.fine_size) * 50)
+    plan = st.Plan.for_problem(prob, conv_algo=algo)
+    plan.set_frames(np.zeros(prob.data_size), np.ones(prob.data_size), prob.kernels, prob.W)
+    model = plan.convolve_subsample(scene).cpu().numpy().astype(np.float64)
+    n0, K0, F0 = int(prob.n[0]), int(prob.K[0]), prob.s * int(prob.n[0])
+    i = prob.E - 1  # the last frame
+    ref = ora.conv_sub([n0], [K0], prob.s, prob.kernels[i * K0 * K0:(i + 1) * K0 * K0],
+                       scene[i * F0 * F0:(i + 1) * F0 * F0])
+    got = model[i * n0 * n0:(i + 1) * n0 * n0]
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _say(f"cfg5 full frame {i}: max rel err {err:.2e}")
+    assert err <= 1e-5
+    resid = synth.f32(rng.standard_normal(prob.data_size))
+    adj = plan.convolve_subsample_adj(resid).cpu().numpy().astype(np.float64)
+    lhs, rhs = np.dot(model, resid), np.dot(scene, adj)
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(model) * np.linalg.norm(resid)
+    d = synth.f32(model + rng.normal(0, 10, model.shape))
+    w = np.full(prob.data_size, 0.01)
+    plan0 = st.Plan.for_problem(prob, conv_algo=algo, lam=0.0)
+    plan0.set_frames(d, w, prob.kernels, prob.W)
+    p = synth.eval_point(prob, "near", rng)
+    _, g = plan0.loss_grad(p)
+    g = g.cpu().numpy().astype(np.float64)
+    NN = prob.N ** 2
+    delta = np.zeros(prob.n_params)
+    # a long step: the difference is exact at any length (quadratic), and the FP32
+    # rounding of the two losses (~1 at this size) must stay far below it
+    delta[:NN] = 30.0 * rng.standard_normal(NN)
+    pp, pm = synth.f32(p + delta), synth.f32(p - delta)
+    fd = plan0.loss_grad(pp, want_grad=False)[0][2].item() - plan0.loss_grad(pm, want_grad=False)[0][2].item()
+    an = float(np.dot(g, pp - pm))
+    _say(f"cfg5 full: directional difference {fd:.8e} vs gradient {an:.8e}")
+    assert abs(fd - an) <= 1e-4 * abs(an)
+
+
 # --------------------------------------------------------------------------- #
 # Noise propagation to the starlet coefficients (Sec. 2.3, App. B)             #
 # --------------------------------------------------------------------------- #
