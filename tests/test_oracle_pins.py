@@ -800,3 +800,102 @@ def test_lbfgs_two_loop_equals_the_bfgs_inverse_hessian_product():
     np.testing.assert_allclose(got, -H @ g, rtol=1e-10, atol=1e-12)
     # no history: steepest descent
     np.testing.assert_array_equal(ora.lbfgs_direction(g, S, Y, 0, newest), -g)
+
+
+def _gauss_sampled(N, cx, cy, fwhm):
+    # unit-integral Gaussian point-sampled at pixel centres, written out here
+    sig = fwhm / (2.0 * np.sqrt(2.0 * np.log(2.0)))
+    Y, X = np.mgrid[0:N, 0:N].astype(np.float64)
+    return np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / (2 * sig * sig)) / (2 * np.pi * sig * sig)
+
+
+@pytest.mark.parametrize("w_stride", [0, 1])
+def test_lambda_pts_estimate_single_plane_with_h_and_gamma(w_stride):
+    """App. C with h != 0 and Gamma != 0: at J = 1 the transform is the identity, so
+    every norm is a plain weighted L1 sum of an image, and the estimate is
+    lambda (sum W |<Gamma> + h + sum_k <a_k> r_k| - sum W |h|) / sum_k <a_k> sum W r_k.
+    A dropped h norm, h counted twice in the averaged scene, or <Gamma> left out of it
+    (or replaced by the sum or by one epoch's value) each move the value far from this."""
+    prob = synth.make_small_deconv(seed=31, E=5, sides=[10], K=[5], s=2, N=40, M=2, J=1,
+                                   w_stride=w_stride)
+    rng = np.random.default_rng(31)
+    NN, E, M, N = prob.N ** 2, prob.E, prob.M, prob.N
+    p = prob.params_true.astype(np.float64).copy()
+    p[:NN] = synth.f32(rng.normal(0.0, 20.0, NN) + 15.0)           # signed h
+    p[NN:NN + E] = synth.f32(rng.uniform(-30.0, 60.0, E))           # unequal Gamma
+    p[NN + E:NN + E + E * M] = synth.f32(rng.uniform(500.0, 3000.0, E * M))
+    p[NN + E + E * M:] = synth.f32(rng.uniform(8.0, 31.0, 2 * M))
+    lam = 2.5
+    Wv = prob.W if w_stride else synth.f32([1.3])  # (the generator leaves the coarse plane at 0)
+    est = ora.lambda_pts_estimate(prob, p, lam=lam, W=Wv)
+    W = Wv.reshape(-1, N, N)[0] if w_stride else Wv[0]
+    h = p[:NN].reshape(N, N)
+    gmean = p[NN:NN + E].mean()
+    amean = p[NN + E:NN + E + E * M].reshape(E, M).mean(axis=0)
+    c = p[NN + E + E * M:].reshape(M, 2)
+    r = [_gauss_sampled(N, c[k, 0], c[k, 1], prob.fwhm) for k in range(M)]
+    P = sum(amean[k] * r[k] for k in range(M))
+    den = sum(amean[k] * np.sum(W * np.abs(r[k])) for k in range(M))
+    want = lam * (np.sum(W * np.abs(gmean + h + P)) - np.sum(W * np.abs(h))) / den
+    assert est == pytest.approx(want, rel=1e-12)
+    # the readings a slip would produce are all far from it
+    wrong = {
+        "h norm dropped": lam * np.sum(W * np.abs(gmean + h + P)) / den,
+        "h twice": lam * (np.sum(W * np.abs(gmean + 2 * h + P)) - np.sum(W * np.abs(h))) / den,
+        "Gamma left out": lam * (np.sum(W * np.abs(h + P)) - np.sum(W * np.abs(h))) / den,
+        "Gamma summed": lam * (np.sum(W * np.abs(E * gmean + h + P)) - np.sum(W * np.abs(h))) / den,
+    }
+    for name, v in wrong.items():
+        assert abs(v - want) > 1e-3 * abs(want), name
+
+
+def test_lambda_pts_estimate_h_proportional_to_point_image():
+    """App. C at any J: with Gamma = 0 and h = beta P, P = <a> r for one source, the
+    averaged scene is (1 + beta) P, so the numerator is (1 + beta - beta) lambda
+    ||W Phi^T P||_1 and the estimate is lambda exactly (the norms are positively
+    homogeneous). Dropping the h norm gives (1 + beta) lambda; counting h twice gives
+    (1 + beta) lambda too; both fail."""
+    prob = synth.make_small_deconv(seed=32, E=4, sides=[12], K=[7], s=2, N=48, M=1, J=4)
+    NN, E, M, N = prob.N ** 2, prob.E, prob.M, prob.N
+    p = prob.params_true.astype(np.float64).copy()
+    p[NN:NN + E] = 0.0
+    p[NN + E:NN + E + E * M] = synth.f32([800.0, 1200.0, 950.0, 1450.0])
+    p[NN + E + E * M:] = synth.f32([22.3, 25.6])
+    for beta in (0.5, 3.0):
+        pp = p.copy()
+        pp[:NN] = beta * ora.pts_image(prob, pp)
+        est = ora.lambda_pts_estimate(prob, pp, lam=1.7)
+        assert est == pytest.approx(1.7, rel=1e-9), beta
+
+
+def test_lambda_pts_estimate_gamma_reaches_the_coarse_plane_only():
+    """App. C, multi-scale: a constant has zero detail planes and a constant coarse
+    plane, so with W_{J-1} = 0 the estimate does not depend on <Gamma>, and with
+    W_{J-1} = w the shift of the numerator is exactly what <Gamma> adds to the coarse
+    plane's weighted L1 sum, which is plain arithmetic when that plane keeps one sign."""
+    prob = synth.make_small_deconv(seed=33, E=4, sides=[12], K=[7], s=2, N=48, M=1, J=3)
+    NN, E, M, N, J = prob.N ** 2, prob.E, prob.M, prob.N, prob.J
+    p = prob.params_true.astype(np.float64).copy()
+    p[NN + E:NN + E + E * M] = synth.f32([800.0, 1200.0, 950.0, 1450.0])
+    p[NN + E + E * M:] = synth.f32([22.3, 25.6])
+    p[:NN] = np.abs(p[:NN]) + 1.0  # positive h: a positive coarse plane
+    g0 = p.copy()
+    g0[NN:NN + E] = 0.0
+    g1 = p.copy()
+    g1[NN:NN + E] = synth.f32([4.0, 10.0, -2.0, 12.0])  # mean 6
+    W0 = prob.W.copy()
+    W0[J - 1] = 0.0
+    e0 = ora.lambda_pts_estimate(prob, g0, lam=2.0, W=W0)
+    e1 = ora.lambda_pts_estimate(prob, g1, lam=2.0, W=W0)
+    assert e1 == pytest.approx(e0, rel=1e-12)
+    Wc = W0.copy()
+    Wc[J - 1] = 0.7
+    f0 = ora.lambda_pts_estimate(prob, g0, lam=2.0, W=Wc)
+    f1 = ora.lambda_pts_estimate(prob, g1, lam=2.0, W=Wc)
+    cx, cy = synth.f32([22.3, 25.6])
+    r = _gauss_sampled(N, cx, cy, prob.fwhm)
+    coarse = ora.starlet_fwd(N, J, r).reshape(J, N, N)[J - 1]
+    det = ora.starlet_fwd(N, J, r).reshape(J, N, N)[:J - 1]
+    amean = np.mean([800.0, 1200.0, 950.0, 1450.0])
+    den = amean * (np.sum(W0[:J - 1, None, None] * np.abs(det)) + 0.7 * np.sum(np.abs(coarse)))
+    assert f1 - f0 == pytest.approx(2.0 * 0.7 * 6.0 * NN / den, rel=1e-9)
