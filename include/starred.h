@@ -245,6 +245,22 @@ int starred_set_fft_fused(starred_plan *plan, int32_t enable);
 /* Which convolution algorithm the plan runs (STARRED_CONV_DIRECT or _FFT). */
 int starred_conv_algo(const starred_plan *plan);
 
+/* Shape classes of a deconvolution plan: the frames that share a (data side,
+ * kernel side) pair. For each, the convolution algorithm it runs and, on the FFT
+ * algorithm, the transform lengths P (fine grid) and Q = P/s (data grid) and
+ * whether its forward is the one-launch form (fused = 1) or the batched line
+ * passes (0). starred_num_classes returns the count (>= 0) or a negative status;
+ * starred_get_class_info fills *out for class c in [0, count). */
+typedef struct {
+    int32_t n, K, n_frames;
+    int32_t algo;
+    int32_t P, Q;
+    int32_t fused;
+    int32_t pad;
+} starred_class_info;
+int starred_num_classes(const starred_plan *plan);
+int starred_get_class_info(const starred_plan *plan, int32_t c, starred_class_info *out);
+
 /* Stage timing, for measurement. While enabled, loss_grad and step record a
  * pair of HIP events on the plan's stream around each stage below, and each
  * call first runs a short idle kernel (about 1 ms) on that stream, so that the

@@ -43,7 +43,7 @@ def lib():
                      "ora_starlet_adj", "ora_loss_grad", "ora_forward_model", "ora_moffat",
                      "ora_psf_render", "ora_psf_model", "ora_psf_loss_grad", "ora_adam_step",
                      "ora_noise_variance", "ora_noise_weights_mc", "ora_pts_term", "ora_adabelief_step",
-                     "ora_lbfgs_direction"]:
+                     "ora_lbfgs_direction", "ora_set_num_threads"]:
             getattr(_lib, name).restype = None
         _lib.ora_philox4x32_10.restype = None
         _lib.ora_lambda_pts_estimate.restype = ctypes.c_double
@@ -69,6 +69,11 @@ def _f64(a):
 
 def num_threads() -> int:
     return lib().ora_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's frame loops (n <= 0: every processor)."""
+    lib().ora_set_num_threads(int(n))
 
 
 def sigma_from_fwhm(fwhm: float) -> float:

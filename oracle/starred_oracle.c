@@ -1021,3 +1021,13 @@ int ora_num_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count of the frame loops (n <= 0: every processor). */
+void ora_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}

@@ -873,12 +873,37 @@ int64_t starred_num_data(const starred_plan *p) { return p ? p->ndata : -1; }
 int64_t starred_num_scene(const starred_plan *p) { return p ? p->nfine : -1; }
 int starred_conv_algo(const starred_plan *p) { return p ? p->algo : STARRED_EINVAL; }
 
+int starred_num_classes(const starred_plan *p)
+{
+    if (!p) return fail(STARRED_EINVAL, "plan is NULL");
+    return p->mode == STARRED_DECONV ? (int)p->cls.size() : 0;
+}
+
+int starred_get_class_info(const starred_plan *p, int32_t c, starred_class_info *out)
+{
+    if (!p || !out) return fail(STARRED_EINVAL, "NULL argument");
+    if (p->mode != STARRED_DECONV || c < 0 || c >= (int)p->cls.size()) return fail(STARRED_EINVAL, "no such class");
+    const ClassFft &cl = p->cls[c];
+    memset(out, 0, sizeof *out);
+    out->n = cl.n;
+    out->K = cl.K;
+    out->n_frames = cl.ncf;
+    out->algo = p->algo;
+    out->P = cl.P;
+    out->Q = cl.Q;
+    out->fused = (p->algo == STARRED_CONV_FFT && p->fft_fused) ? cl.fused : 0;
+    return STARRED_OK;
+}
+
 int starred_set_frames(starred_plan *p, const float *data, const float *inv_var, const float *psf,
                        const float *W)
 {
     if (!p) return fail(STARRED_EINVAL, "plan is NULL");
     if (!data || !inv_var || !W) return fail(STARRED_EINVAL, "data, inv_var and W must be non-NULL");
     if (p->mode == STARRED_DECONV && !psf) return fail(STARRED_EINVAL, "psf kernels are required in deconvolution mode");
+    // captured graphs hold the bound pointers as kernel arguments: re-capture
+    // after any re-bind
+    p->drop_graphs();
     p->data = data;
     p->invvar = inv_var;
     p->W = W;

@@ -32,6 +32,12 @@ STAGES = ["render", "conv_fwd", "conv_adj", "grad_sums", "starlet", "finalize", 
           "fft_fsum", "fft_fused"]
 
 
+class ClassInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("K", ctypes.c_int32), ("n_frames", ctypes.c_int32),
+                ("algo", ctypes.c_int32), ("P", ctypes.c_int32), ("Q", ctypes.c_int32),
+                ("fused", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 class Desc(ctypes.Structure):
     _fields_ = [
         ("mode", ctypes.c_int32), ("n_frames", ctypes.c_int32),
@@ -82,6 +88,8 @@ def lib():
         L.starred_set_graph_mode.argtypes = [vp, i32]
         L.starred_set_fft_fused.argtypes = [vp, i32]
         L.starred_conv_algo.argtypes = [vp]
+        L.starred_num_classes.argtypes = [vp]
+        L.starred_get_class_info.argtypes = [vp, i32, ctypes.POINTER(ClassInfo)]
         L.starred_last_error.restype = ctypes.c_char_p
         L.starred_set_profiling.argtypes = [vp, i32]
         L.starred_profile_read.argtypes = [vp, vp, vp]
@@ -196,10 +204,27 @@ class Plan:
     def conv_algo(self):
         return lib().starred_conv_algo(self._h)
 
+    def classes(self):
+        """Shape classes: dicts of n, K, n_frames, algo, P, Q, fused."""
+        nc = lib().starred_num_classes(self._h)
+        _check(min(nc, 0))
+        out = []
+        for c in range(nc):
+            ci = ClassInfo()
+            _check(lib().starred_get_class_info(self._h, c, ctypes.byref(ci)))
+            out.append({k: getattr(ci, k) for k, _ in ClassInfo._fields_ if k != "pad"})
+        return out
+
+    def fused_classes(self):
+        """(n, K) of the classes whose forward is the one-launch form."""
+        return {(c["n"], c["K"]) for c in self.classes() if c["algo"] == CONV_FFT and c["fused"]}
+
     def set_frames(self, data, invvar, psf, W):
         t = [_f32(x, self.device) if x is not None else None for x in (data, invvar, psf, W)]
-        self._bound = tuple(t)  # keep the memory alive while the plan references it
         self._call(lib().starred_set_frames, *[_ptr(x) for x in t])
+        # keep the memory alive while the plan references it (the old arrays stay bound
+        # when the call fails)
+        self._bound = tuple(t)
 
     def render_scene(self, params):
         params = _f32(params, self.device)

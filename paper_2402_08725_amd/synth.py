@@ -266,6 +266,27 @@ def make_deconv(cfg: int, rep: int = 0, E: int | None = None, sizes=None,
         c=f32(c).ravel(), W=W, adam_lr=adam_lr)
 
 
+def subset(prob: DeconvProblem, frames) -> DeconvProblem:
+    """The same workload restricted to some of its frames (inputs sliced, nothing
+    computed): kernels, Gamma and a of those frames; h, c and W unchanged."""
+    idx = np.asarray(frames, dtype=np.int64)
+    koff = np.concatenate([[0], np.cumsum(prob.K.astype(np.int64) ** 2)])
+    kern = np.concatenate([prob.kernels[koff[i]:koff[i + 1]] for i in idx])
+    a = prob.a.reshape(prob.E, prob.M)[idx].ravel()
+    return DeconvProblem(
+        name=f"{prob.name}[{len(idx)} frames]", E=len(idx), n=prob.n[idx].copy(), K=prob.K[idx].copy(),
+        s=prob.s, N=prob.N, M=prob.M, J=prob.J, lam=prob.lam, kernels=kern, h=prob.h, Gamma=prob.Gamma[idx].copy(),
+        a=a, c=prob.c, W=prob.W, w_stride=prob.w_stride, fwhm=prob.fwhm, sigma_bg=prob.sigma_bg,
+        adam_lr=dict(prob.adam_lr))
+
+
+def subset_params(prob: DeconvProblem, params: np.ndarray, frames) -> np.ndarray:
+    """A parameter vector of prob restricted to some frames (see subset)."""
+    idx = np.asarray(frames, dtype=np.int64)
+    h, G, a, c = prob.unpack(np.asarray(params))
+    return np.concatenate([h, G[idx], a.reshape(prob.E, prob.M)[idx].ravel(), c])
+
+
 def make_small_deconv(seed: int, E: int, sides, K, s: int, N: int, M: int, J: int,
                       lam: float = 3.0, w_stride: int = 0) -> DeconvProblem:
     """A small random deconvolution instance for property and parity tests:

@@ -542,6 +542,33 @@ def test_graph_replays_match_eager(algo):
         assert torch.equal(mg, me) and torch.equal(vg, ve), t
 
 
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+def test_graph_replay_after_rebinding_frames(algo):
+    """A captured graph holds the bound data pointers: after set_frames with new data
+    (new device arrays), a replay must read the new data, as an eager call does."""
+    st = _st()
+    prob = synth.make_deconv(2, E=6)
+    d, w, rng = _data(prob, seed=18)
+    p = torch.tensor(synth.eval_point(prob, "near", rng), dtype=torch.float32, device="cuda")
+    plan = _plan(prob, d, w, algo)
+    plan.set_graph_mode(True)
+    loss = torch.empty(3, dtype=torch.float64, device="cuda")
+    grad = torch.empty(prob.n_params, dtype=torch.float32, device="cuda")
+    plan.loss_grad(p, grad_out=grad, loss_out=loss)  # captured with the first data
+    torch.cuda.synchronize()
+    l_first = loss.clone()
+    d2 = synth.f32(d + rng.normal(0.0, 30.0, d.shape))
+    plan.set_frames(d2, w, prob.kernels, prob.W)
+    _ = (torch.randn(1000, device="cuda") * 2).sum().item()  # the old arrays' memory gets reused
+    plan.loss_grad(p, grad_out=grad, loss_out=loss)
+    torch.cuda.synchronize()
+    eager = _plan(prob, d2, w, algo)
+    le, ge = eager.loss_grad(p)
+    torch.cuda.synchronize()
+    assert not torch.equal(loss, l_first)
+    assert torch.equal(loss, le) and torch.equal(grad, ge)
+
+
 def test_graph_mode_psf():
     prob, d, w, rng, plan = _psf_setup(dict(S=4, n=16, s=3, J=4), 44)
     p = torch.tensor(synth.psf_eval_point(prob, "near", rng), dtype=torch.float32, device="cuda")
