@@ -334,6 +334,21 @@ int starred_time_stage(starred_plan *plan, const float *params, int32_t stage, i
  * library's kernels. */
 int starred_copy_probe(starred_plan *plan, const float *src, float *dst, int64_t n);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, hosts that forbid allocation): the starlet transform of
+ * starred_starlet_fwd without a plan. img (N x N) and coeffs (J planes of N^2) are
+ * the caller's device arrays; the two working planes of the cascade live in one
+ * fixed device array of the library (2 x 512 x 512 floats plus 16, about 2 MiB,
+ * held on each device it runs on until the process ends), so the call allocates
+ * nothing. Limits: 2 <= N <= 512, 1 <= J <= 16, 2^(J-1) <= N-1; larger requests
+ * return STARRED_EINVAL. Enqueues on stream (a hipStream_t, NULL = default) without
+ * synchronising. Every call on a device shares that device's working array, so
+ * calls that may overlap on one device (different streams or host threads without
+ * ordering) race; calls on one stream are ordered and safe. Coefficients equal
+ * starred_starlet_fwd's up to rounding (that call may evaluate the scales by
+ * composite filters in FP64). */
+int starred_starlet_fwd_noalloc(int32_t N, int32_t J, const float *img, float *coeffs, void *stream);
+
 const char *starred_last_error(void);
 int starred_abi_version(void);
 

@@ -63,6 +63,9 @@ int dev_alloc(T **p, size_t count)
 
 }  // namespace
 
+// the calling thread's last error, for the entry points of other files
+int starred_set_error(int code, const char *msg) { return fail(code, msg); }
+
 struct starred_plan {
     int mode = 0, E = 0, s = 1, N = 0, M = 0, J = 1, w_stride = 0, algo = STARRED_CONV_DIRECT;
     double lam = 0.0, fwhm = 2.0;

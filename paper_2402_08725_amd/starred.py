@@ -106,6 +106,7 @@ def lib():
         L.starred_lbfgs_reset.argtypes = [vp]
         L.starred_lbfgs_run.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
         L.starred_estimate_lambda_pts.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
+        L.starred_starlet_fwd_noalloc.argtypes = [i32, i32, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -376,6 +377,16 @@ class Plan:
 
     def set_graph_mode(self, enable: bool):
         _check(lib().starred_set_graph_mode(self._h, int(bool(enable))))
+
+
+def starlet_fwd_noalloc(N, J, img, out):
+    """Phi^T of img (N x N, float32 device tensor) into out (J N^2), without a plan and
+    without allocating device memory (the library's fixed working array)."""
+    stream = torch.cuda.current_stream(img.device)
+    with torch.cuda.device(img.device):
+        _check(lib().starred_starlet_fwd_noalloc(int(N), int(J), _ptr(img), _ptr(out),
+                                                 ctypes.c_void_p(stream.cuda_stream)))
+    return out
 
 
 class StarredLoss(torch.autograd.Function):
