@@ -43,7 +43,8 @@ def lib():
                      "ora_starlet_adj", "ora_loss_grad", "ora_forward_model", "ora_moffat",
                      "ora_psf_render", "ora_psf_model", "ora_psf_loss_grad", "ora_adam_step",
                      "ora_noise_variance", "ora_noise_weights_mc", "ora_pts_term", "ora_adabelief_step",
-                     "ora_lbfgs_direction", "ora_set_num_threads"]:
+                     "ora_lbfgs_direction", "ora_set_num_threads", "ora_render_scene_xf",
+                     "ora_loss_grad_xf"]:
             getattr(_lib, name).restype = None
         _lib.ora_philox4x32_10.restype = None
         _lib.ora_lambda_pts_estimate.restype = ctypes.c_double
@@ -288,3 +289,31 @@ def lbfgs_direction(g, S, Y, count, newest):
     d = np.zeros(n)
     lib().ora_lbfgs_direction(ctypes.c_long(n), _d(g), _d(S), _d(Y), m, count, newest, _d(d))
     return d
+
+
+def render_scene_xf(n, s, N, M, fwhm, params, xf):
+    """Scenes under per-frame transforms xf (E x 3: dx, dy, theta)."""
+    n = _i32(n)
+    params, xf = _f64(params), _f64(xf)
+    out = np.zeros(int(np.sum((s * n.astype(np.int64)) ** 2)))
+    lib().ora_render_scene_xf(len(n), n.ctypes.data_as(_I), s, N, M, ctypes.c_double(fwhm), _d(params), _d(xf),
+                              _d(out))
+    return out
+
+
+def loss_grad_xf(prob, data, invvar, params, xf, want_grad=True, sgn_override=None, lam=None, W=None):
+    """Loss and gradient with per-frame transforms; returns (loss, grad, dL/dxf)."""
+    frame_offsets(prob.n, prob.s, prob.N)
+    n, K = _i32(prob.n), _i32(prob.K)
+    params, xf = _f64(params), _f64(xf)
+    Wv = _f64(prob.W if W is None else W)
+    loss = np.zeros(3)
+    grad = np.zeros(prob.n_params) if want_grad else None
+    gxf = np.zeros(3 * prob.E) if want_grad else None
+    sp = None if sgn_override is None else np.ascontiguousarray(sgn_override, dtype=np.int8)
+    lib().ora_loss_grad_xf(prob.E, n.ctypes.data_as(_I), K.ctypes.data_as(_I), prob.s, prob.N, prob.M, prob.J,
+                           prob.w_stride, ctypes.c_double(prob.lam if lam is None else lam),
+                           ctypes.c_double(prob.fwhm), _d(_f64(data)), _d(_f64(invvar)), _d(_f64(prob.kernels)),
+                           _d(Wv), _d(params), _d(xf), _d(grad), _d(gxf), _d(loss),
+                           sp.ctypes.data_as(_B) if sp is not None else None)
+    return loss, grad, gxf

@@ -1031,3 +1031,173 @@ void ora_set_num_threads(int n)
     (void)n;
 #endif
 }
+
+/* ------------------------------------------------------------------------- */
+/* Per-frame shifts and rotations (Conclusion: all epochs processed together  */
+/* while modelling shifts and rotations between frames; Sec. 4.1: per-epoch   */
+/* dithering offsets recovered by the fit).                                   */
+/* Frame i with transform t_i = (dx_i, dy_i, theta_i) observes the scene at   */
+/*   u_i(X) = R(theta_i) (X - C) + C + (dx_i, dy_i),  C = ((N-1)/2, (N-1)/2), */
+/* X a fine pixel of its window in grid coordinates, R the counter-clockwise  */
+/* rotation [[cos, -sin], [sin, cos]]. The extended channel is read there by  */
+/* bilinear interpolation of h (zero outside the grid); point source k adds   */
+/* a_ik r(u_i(X) - c_k).  t_i = 0 gives Eq. (9) exactly.                      */
+/* ------------------------------------------------------------------------- */
+
+static double h_at(const double *h, int N, long X, long Y)
+{
+    if (X < 0 || X >= N || Y < 0 || Y >= N) return 0.0;
+    return h[Y * N + X];
+}
+
+/* bilinear interpolation of h at (ux, uy) and its two partial derivatives */
+static double bilerp(const double *h, int N, double ux, double uy, double *dx_out, double *dy_out)
+{
+    const double fx = floor(ux), fy = floor(uy);
+    const long X0 = (long)fx, Y0 = (long)fy;
+    const double tx = ux - fx, ty = uy - fy;
+    const double h00 = h_at(h, N, X0, Y0), h10 = h_at(h, N, X0 + 1, Y0);
+    const double h01 = h_at(h, N, X0, Y0 + 1), h11 = h_at(h, N, X0 + 1, Y0 + 1);
+    if (dx_out) *dx_out = (1.0 - ty) * (h10 - h00) + ty * (h11 - h01);
+    if (dy_out) *dy_out = (1.0 - tx) * (h01 - h00) + tx * (h11 - h10);
+    return (1.0 - tx) * (1.0 - ty) * h00 + tx * (1.0 - ty) * h10 + (1.0 - tx) * ty * h01 + tx * ty * h11;
+}
+
+static void frame_map(int N, const double *t, double X, double Y, double *ux, double *uy)
+{
+    const double C = 0.5 * (N - 1), cs = cos(t[2]), sn = sin(t[2]);
+    const double vx = X - C, vy = Y - C;
+    *ux = cs * vx - sn * vy + C + t[0];
+    *uy = sn * vx + cs * vy + C + t[1];
+}
+
+/* scene of every frame under its transform (xf: E x 3 = dx, dy, theta) */
+void ora_render_scene_xf(int E, const int *n, int s, int N, int M, double fwhm, const double *params,
+                         const double *xf, double *scene)
+{
+    const double *h = params;
+    const double *Gam = params + (long)N * N;
+    const double *a = Gam + E;
+    const double *c = a + (long)E * M;
+    const double sigma = ora_sigma_from_fwhm(fwhm);
+    int *o = (int *)malloc(sizeof(int) * (E > 0 ? E : 1));
+    ora_frame_offsets(E, n, s, N, o);
+    for (int i = 0; i < E; ++i) {
+        const int F = s * n[i];
+        double *f = scene + fine_offset(E, n, s, i);
+        for (int y = 0; y < F; ++y)
+            for (int x = 0; x < F; ++x) {
+                double ux, uy;
+                frame_map(N, xf + 3 * i, x + o[i], y + o[i], &ux, &uy);
+                double v = Gam[i] + bilerp(h, N, ux, uy, NULL, NULL);
+                for (int k = 0; k < M; ++k)
+                    v += a[(long)i * M + k] * gauss2(ux - c[2 * k], uy - c[2 * k + 1], sigma);
+                f[(long)y * F + x] = v;
+            }
+    }
+    free(o);
+}
+
+/* Loss and gradient with per-frame transforms (Eqs. 9-11 with the scene above).
+ * grad: [h | Gamma | a | c] as ora_loss_grad; gxf (E x 3, may be NULL): dL/d(dx_i,
+ * dy_i, theta_i). The h block's data term is the literal transpose of the
+ * interpolation: every frame pixel scatters its g onto the four pixels it read. */
+void ora_loss_grad_xf(int E, const int *n, const int *K, int s, int N, int M, int J, int w_stride, double lambda,
+                      double fwhm, const double *data, const double *invvar, const double *kernels, const double *W,
+                      const double *params, const double *xf, double *grad, double *gxf, double *loss,
+                      const signed char *sgn_override)
+{
+    const long NN = (long)N * N;
+    const long nfine = fine_offset(E, n, s, E);
+    const long ndata = data_offset(n, E);
+    const double sigma = ora_sigma_from_fwhm(fwhm), s2 = sigma * sigma;
+    int *o = (int *)malloc(sizeof(int) * (E > 0 ? E : 1));
+    ora_frame_offsets(E, n, s, N, o);
+    double *scene = (double *)malloc(sizeof(double) * (nfine > 0 ? nfine : 1));
+    double *model = (double *)malloc(sizeof(double) * (ndata > 0 ? ndata : 1));
+    double *rho = (double *)malloc(sizeof(double) * (ndata > 0 ? ndata : 1));
+    ora_render_scene_xf(E, n, s, N, M, fwhm, params, xf, scene);
+    ora_conv_sub(E, n, K, s, kernels, scene, model);
+    double chi = 0.0;
+    for (long p = 0; p < ndata; ++p) {
+        const double r = model[p] - data[p];
+        rho[p] = invvar[p] * r;
+        chi += 0.5 * invvar[p] * r * r;
+    }
+    double *alpha = (double *)malloc(sizeof(double) * J * NN);
+    double *z = (double *)malloc(sizeof(double) * J * NN);
+    ora_starlet_fwd(N, J, params, alpha);
+    const double l1 = l1_prior(N, J, alpha, W, w_stride, lambda, sgn_override, z);
+    loss[0] = chi;
+    loss[1] = l1;
+    loss[2] = chi + l1;
+    if (grad) {
+        const double *h = params;
+        const double *a = params + NN + E;
+        const double *c = a + (long)E * M;
+        double *gh = grad, *gG = grad + NN, *ga = gG + E, *gc = ga + (long)E * M;
+        double *gscene = (double *)malloc(sizeof(double) * (nfine > 0 ? nfine : 1));
+        ora_conv_sub_adj(E, n, K, s, kernels, rho, gscene);
+        for (long p = 0; p < NN; ++p) gh[p] = 0.0;
+        for (long q = 0; q < 2L * M; ++q) gc[q] = 0.0;
+        for (int i = 0; i < E; ++i) {
+            const int F = s * n[i];
+            const double *g = gscene + fine_offset(E, n, s, i);
+            const double *t = xf + 3 * i;
+            const double cs = cos(t[2]), sn = sin(t[2]), C = 0.5 * (N - 1);
+            double sG = 0.0, gdx = 0.0, gdy = 0.0, gth = 0.0;
+            for (int k = 0; k < M; ++k) ga[(long)i * M + k] = 0.0;
+            for (int y = 0; y < F; ++y)
+                for (int x = 0; x < F; ++x) {
+                    const double gv = g[(long)y * F + x];
+                    const double X = x + o[i], Y = y + o[i];
+                    double ux, uy, hx, hy;
+                    frame_map(N, t, X, Y, &ux, &uy);
+                    bilerp(h, N, ux, uy, &hx, &hy);
+                    sG += gv;
+                    /* transpose of the interpolation */
+                    const double fx = floor(ux), fy = floor(uy);
+                    const long X0 = (long)fx, Y0 = (long)fy;
+                    const double tx = ux - fx, ty = uy - fy;
+                    const double wts[4] = {(1 - tx) * (1 - ty), tx * (1 - ty), (1 - tx) * ty, tx * ty};
+                    const long xs[4] = {X0, X0 + 1, X0, X0 + 1}, ys[4] = {Y0, Y0, Y0 + 1, Y0 + 1};
+                    for (int q = 0; q < 4; ++q)
+                        if (xs[q] >= 0 && xs[q] < N && ys[q] >= 0 && ys[q] < N) gh[ys[q] * N + xs[q]] += gv * wts[q];
+                    /* d scene / d u at this pixel */
+                    double dux = hx, duy = hy;
+                    for (int k = 0; k < M; ++k) {
+                        const double ex = ux - c[2 * k], ey = uy - c[2 * k + 1];
+                        const double r = gauss2(ex, ey, sigma);
+                        const double aik = a[(long)i * M + k];
+                        ga[(long)i * M + k] += gv * r;
+                        gc[2 * k] += gv * aik * r * ex / s2;       /* d r(u - c)/d c = r (u - c)/sigma^2 */
+                        gc[2 * k + 1] += gv * aik * r * ey / s2;
+                        dux -= aik * r * ex / s2;
+                        duy -= aik * r * ey / s2;
+                    }
+                    /* u = R (X - C) + C + d:  du/dd = I,  du/dtheta = R'(theta) (X - C) */
+                    const double vx = X - C, vy = Y - C;
+                    gdx += gv * dux;
+                    gdy += gv * duy;
+                    gth += gv * (dux * (-sn * vx - cs * vy) + duy * (cs * vx - sn * vy));
+                }
+            gG[i] = sG;
+            if (gxf) {
+                gxf[3 * i] = gdx;
+                gxf[3 * i + 1] = gdy;
+                gxf[3 * i + 2] = gth;
+            }
+        }
+        double *pz = (double *)malloc(sizeof(double) * NN);
+        ora_starlet_adj(N, J, z, pz);
+        for (long p = 0; p < NN; ++p) gh[p] += pz[p];
+        free(pz);
+        free(gscene);
+    }
+    free(alpha);
+    free(z);
+    free(scene);
+    free(model);
+    free(rho);
+    free(o);
+}

@@ -899,3 +899,115 @@ def test_lambda_pts_estimate_gamma_reaches_the_coarse_plane_only():
     amean = np.mean([800.0, 1200.0, 950.0, 1450.0])
     den = amean * (np.sum(W0[:J - 1, None, None] * np.abs(det)) + 0.7 * np.sum(np.abs(coarse)))
     assert f1 - f0 == pytest.approx(2.0 * 0.7 * 6.0 * NN / den, rel=1e-9)
+
+
+# --------------------------------------------------------------------------- #
+# Per-frame shifts and rotations (Conclusion; Sec. 4.1 dithering offsets)      #
+# --------------------------------------------------------------------------- #
+
+def _xf_case(seed=51, M=2, J=3):
+    prob = synth.make_small_deconv(seed=seed, E=3, sides=[10, 12, 8], K=[5, 7, 4], s=2, N=32, M=M, J=J)
+    rng = np.random.default_rng(seed)
+    p = prob.params_true.astype(np.float64).copy()
+    p[:prob.N ** 2] += synth.f32(rng.normal(0, 4.0, prob.N ** 2))
+    return prob, rng, p
+
+
+def test_transforms_identity_is_eq9():
+    """t_i = 0 for every frame: the scene, loss and gradient are those of Eq. (9)."""
+    prob, rng, p = _xf_case()
+    d, w = synth.add_noise(ora.forward_model(prob, prob.params_true), rng)
+    xf = np.zeros(3 * prob.E)
+    s0 = ora.render_scene(prob.n, prob.s, prob.N, prob.M, prob.fwhm, p)
+    s1 = ora.render_scene_xf(prob.n, prob.s, prob.N, prob.M, prob.fwhm, p, xf)
+    np.testing.assert_array_equal(s1, s0)
+    l0, g0 = ora.loss_grad(prob, d, w, p)
+    l1, g1, _ = ora.loss_grad_xf(prob, d, w, p, xf)
+    np.testing.assert_allclose(l1, l0, rtol=1e-13)
+    np.testing.assert_allclose(g1, g0, rtol=1e-11, atol=1e-11 * np.abs(g0).max())
+
+
+def test_transforms_integer_shift_is_an_index_shift():
+    """An integer shift d = (2, -1) with no rotation reads h at (X + 2, Y - 1): the same
+    scene as an untransformed frame over h shifted by those indices (zero filled) with
+    the sources moved by -d."""
+    prob, rng, p = _xf_case(M=1)
+    N, E = prob.N, prob.E
+    xf = np.tile([2.0, -1.0, 0.0], E)
+    got = ora.render_scene_xf(prob.n, prob.s, N, prob.M, prob.fwhm, p, xf)
+    h = p[:N * N].reshape(N, N)
+    hs = np.zeros_like(h)
+    hs[1:, :N - 2] = h[:N - 1, 2:]          # hs[Y, X] = h[Y - 1, X + 2]
+    q = p.copy()
+    q[:N * N] = hs.ravel()
+    q[N * N + E + E * prob.M:] = p[N * N + E + E * prob.M:] - np.tile([2.0, -1.0], prob.M)
+    want = ora.render_scene(prob.n, prob.s, N, prob.M, prob.fwhm, q)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+def test_transforms_quarter_turn_is_an_index_rotation():
+    """theta = pi/2 about the grid centre (N even, so the centre is a half-integer
+    point) maps grid points onto grid points: frame pixel (X, Y) reads h at
+    (N-1-Y, X), i.e. the scene is a rotated copy of h, and a source at c reads as
+    one at the rotated-back position."""
+    prob, rng, p = _xf_case(M=1)
+    N, E = prob.N, prob.E
+    xf = np.tile([0.0, 0.0, np.pi / 2], E)
+    got = ora.render_scene_xf(prob.n, prob.s, N, prob.M, prob.fwhm, p, xf)
+    h = p[:N * N].reshape(N, N)
+    Y, X = np.mgrid[0:N, 0:N]
+    hr = h[X, N - 1 - Y]                     # hr[Y, X] = h[uy = X, ux = N-1-Y]
+    q = p.copy()
+    q[:N * N] = hr.ravel()
+    cx, cy = p[N * N + E + E * prob.M:]
+    C = (N - 1) / 2
+    # u = R(X - C) + C equals c where X = R^T (c - C) + C
+    q[N * N + E + E * prob.M:] = [C + (cy - C), C - (cx - C)]
+    want = ora.render_scene(prob.n, prob.s, N, prob.M, prob.fwhm, q)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-11 * np.abs(want).max())
+
+
+def test_transforms_interpolation_transpose_by_homogeneity():
+    """With Gamma = a = 0, d = 0, w = 1 and lambda = 0 the loss is (1/2)|A h|^2 with A
+    the frames' D S W_i stacked, so <h, dL/dh> = |A h|^2 = 2 L exactly when the h block
+    holds the true transpose of the interpolation (a wrong scatter weight, index or
+    sign breaks it)."""
+    prob, rng, p = _xf_case(M=1)
+    N, E = prob.N, prob.E
+    p[N * N:] = 0.0
+    p[N * N + E + E * prob.M:] = [10.0, 12.0]
+    xf = np.concatenate([[0.37, -1.61, 0.3], [-2.2, 0.85, -0.7], [1.1, 0.4, 2.5]])
+    zero, one = np.zeros(prob.data_size), np.ones(prob.data_size)
+    loss, g, _ = ora.loss_grad_xf(prob, zero, one, p, xf, lam=0.0)
+    assert float(np.dot(p[:N * N], g[:N * N])) == pytest.approx(2.0 * loss[0], rel=1e-12)
+
+
+def test_transforms_gradients_by_central_differences():
+    """dL/dc, dL/dd_i, dL/dtheta_i (and dL/dh) against FP64 central differences of
+    the loss (lambda = 0 keeps it smooth; the bilinear interpolation is smooth away
+    from pixel boundaries, which a step of 1e-6 px does not cross here)."""
+    prob, rng, p = _xf_case(M=2)
+    N, E, M = prob.N, prob.E, prob.M
+    d, w = synth.add_noise(ora.forward_model(prob, prob.params_true), rng)
+    xf = np.concatenate([[0.37, -1.61, 0.3], [-2.2, 0.85, -0.7], [1.1, 0.4, 2.5]])
+    _, g, gx = ora.loss_grad_xf(prob, d, w, p, xf, lam=0.0)
+
+    def L(pp, xx):
+        return ora.loss_grad_xf(prob, d, w, pp, xx, want_grad=False, lam=0.0)[0][2]
+    eps = 1e-6
+    for j in range(3 * E):
+        e = np.zeros(3 * E)
+        e[j] = eps
+        fd = (L(p, xf + e) - L(p, xf - e)) / (2 * eps)
+        assert fd == pytest.approx(gx[j], rel=2e-5, abs=1e-6 * np.abs(gx).max()), j
+    off = N * N + E + E * M
+    for j in range(2 * M):
+        e = np.zeros_like(p)
+        e[off + j] = eps
+        fd = (L(p + e, xf) - L(p - e, xf)) / (2 * eps)
+        assert fd == pytest.approx(g[off + j], rel=2e-5, abs=1e-6 * np.abs(g[off:]).max()), j
+    # h: the loss is quadratic in h, so a long central difference is exact
+    dh = np.zeros_like(p)
+    dh[:N * N] = rng.standard_normal(N * N)
+    fd = (L(p + dh, xf) - L(p - dh, xf)) / 2.0
+    assert fd == pytest.approx(float(np.dot(g[:N * N], dh[:N * N])), rel=1e-9)
