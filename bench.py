@@ -77,12 +77,15 @@ def _make_inputs(prob, plan, seed=0):
 # window of dL/dh written once (4 F^2). Passes that only move the transforms'
 # intermediate spectra have no algorithmic bytes of their own.
 
-def fft_kernel_bytes(prob, fused_classes):
+def fft_kernel_bytes(prob, fused_classes, keep=None):
     """Algorithmic bytes per launch of each FFT-path kernel for the whole batch.
-    fused_classes: set of (n, K) whose frames take the one-launch forward."""
+    fused_classes: set of (n, K) whose frames take the one-launch forward; keep: mask of
+    the frames on the FFT algorithm (all when None)."""
     tot = {k: 0.0 for k in FFT_KERNEL_NAMES}
     classes = set()
-    for n, K in zip(prob.n.tolist(), prob.K.tolist()):
+    for i, (n, K) in enumerate(zip(prob.n.tolist(), prob.K.tolist())):
+        if keep is not None and not keep[i]:
+            continue
         classes.add((n, K))
         if (n, K) in fused_classes:
             tot["fft_fused"] += 8 * n * n + 4 * K * K + 4 * n * n
@@ -111,29 +114,39 @@ FFT_KERNEL_NAMES = {
 }
 
 
-def direct_flops(prob):
-    """Algorithmic FP32 flops of one forward launch of the fused S_i + D kernel:
-    2 n_i^2 (K_i + s - 1)^2 per frame (a multiply and an add per tap)."""
+def direct_flops(prob, sel=None):
+    """Algorithmic FP32 flops of one launch of the fused S_i + D kernel (or of its
+    adjoint, which applies the same taps): 2 n_i^2 (K_i + s - 1)^2 per frame (a
+    multiply and an add per tap), over the frames sel (all when None)."""
     n = prob.n.astype(np.int64)
     Kp = prob.K.astype(np.int64) + prob.s - 1
-    return float(np.sum(2 * n * n * Kp * Kp))
+    f = 2 * n * n * Kp * Kp
+    return float(np.sum(f if sel is None else f[sel]))
 
 
 def roofline(prob, plan, stage_ms):
     """Roofline of the dominant kernel of a step: its algorithmic bytes (or flops) per
     launch over its average in-step duration (HIP events around each launch on the
-    plan's stream, from the profiled steps)."""
-    if plan.conv_algo == 1:
-        ms = stage_ms["conv_fwd"]
-        flops = direct_flops(prob)
+    plan's stream, from the profiled steps). Frames of classes on the direct
+    algorithm count for the direct kernels, the others for the FFT kernels."""
+    cls = plan.classes()
+    direct = {(c["n"], c["K"]) for c in cls if c["algo"] == 1}
+    fused = {(c["n"], c["K"]) for c in cls if c["algo"] == 2 and c["fused"]}
+    cand = [k for k in list(FFT_KERNEL_NAMES) + ["direct_fwd", "direct_adj"] if k in stage_ms]
+    name = max(cand, key=lambda k: stage_ms[k])
+    if name in ("direct_fwd", "direct_adj"):
+        ms = stage_ms[name]
+        sel = np.array([(n, K) in direct for n, K in zip(prob.n.tolist(), prob.K.tolist())])
+        flops = direct_flops(prob, sel)
         achieved = flops / (ms * 1e-3) / 1e12
-        return {"bound": "alu", "kernel": "k_fwd_direct (fused S_i + D + residual + chi2)",
+        kern = ("k_fwd_direct (fused S_i + D + residual + chi2)" if name == "direct_fwd"
+                else "k_adj_direct (S_i^T D^T, s^2 phase correlations)")
+        return {"bound": "alu", "kernel": kern, "stage": name,
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
                 "avg_launch_ms": round(ms, 4), "algorithmic_flops": flops}
-    alg = fft_kernel_bytes(prob, plan.fused_classes())
-    cand = [k for k in FFT_KERNEL_NAMES if k in stage_ms]
-    name = max(cand, key=lambda k: stage_ms[k])
+    keep = np.array([(n, K) not in direct for n, K in zip(prob.n.tolist(), prob.K.tolist())])
+    alg = fft_kernel_bytes(prob, fused, keep)
     ms = stage_ms[name]
     by = alg[name]
     achieved = by / (ms * 1e-3) / 1e9
@@ -366,7 +379,7 @@ def _run(args, prob, plan, torch, st, synth):
         "capture_steps": capture,
         "step_ms": {k: (round(v_, 5) if isinstance(v_, float) else v_) for k, v_ in step_stats.items()},
         "fine_epoch_px_per_s": args.steps / el * prob.fine_size,
-        "autotune_s": round(tune_s, 3),
+        "autotune": autotune_summary(plan, tune_s),
         "fused_vs_plain": {
             "fused_loss_grad_ms": {k: (round(v_, 5) if isinstance(v_, float) else v_) for k, v_ in fused.items()},
             "fused_epoch_px_per_s": prob.data_size / (fused_ms * 1e-3),
@@ -380,6 +393,20 @@ def _run(args, prob, plan, torch, st, synth):
                              "frac": round(b_alg / (step_stats["median"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
     }
     return out
+
+
+def autotune_summary(plan, tune_s):
+    """The autotuner's choices per shape class and the time it took (excluded from the
+    timed steps; reported as the counterpart of a compile step)."""
+    info = plan.autotune_info()
+    names = {0: "direct", 1: "fft-fused", 2: "fft-lines"}
+    cls = []
+    for c in plan.classes():
+        choice = "direct" if c["algo"] == 1 else ("fft-fused" if c["fused"] else "fft-lines")
+        cls.append({"n": c["n"], "K": c["K"], "frames": c["n_frames"], "P": c["P"], "choice": choice,
+                    "tried_ms": {names[k]: round(v, 4) for k, v in enumerate(c["tune_ms"]) if v >= 0}})
+    return {"tune_ms": round(info["wall_ms"], 2), "cached": info["cached"], "set_frames_s": round(tune_s, 3),
+            "adj_blocks": info["adj_blocks"], "line_groups": info["line_groups"], "classes": cls}
 
 
 def step_alg_bytes(prob, W):

@@ -257,9 +257,50 @@ typedef struct {
     int32_t P, Q;
     int32_t fused;
     int32_t pad;
+    double tune_ms[3];  /* autotuner: ms per loss+gradient evaluation of the whole plan with
+                           this class on the direct algorithm, the FFT one-launch forward,
+                           the FFT line passes (-1: not tried) */
 } starred_class_info;
 int starred_num_classes(const starred_plan *plan);
 int starred_get_class_info(const starred_plan *plan, int32_t c, starred_class_info *out);
+
+/* The autotuner (STARRED_CONV_AUTO, run by starred_set_frames): each shape class
+ * gets the direct algorithm, the FFT algorithm with the one-launch forward or the
+ * FFT algorithm with the line passes, by coordinate descent over the classes (most
+ * costly first), each candidate timed as whole loss+gradient evaluations on the
+ * plan's stream; then the launch shapes of the FFT path (work groups aimed at by
+ * the spectral adjoint and by the line passes). Decisions are cached per process
+ * by the plan's shapes (subsampling, grid, sources, scales and the multiset of
+ * (n_i, K_i)) and device, so a second plan of the same shapes reuses them.
+ * starred_autotune_info reports the host milliseconds of the tuning that made the
+ * plan's decision (0 when none ran; with a cached decision, the time of the tuning
+ * that filled the cache), whether the decision came from the cache, and the launch
+ * shapes in use (any pointer may be NULL). */
+int starred_autotune_info(const starred_plan *plan, double *wall_ms_out, int32_t *cached_out,
+                          int32_t *adj_blocks_out, int32_t *line_groups_out);
+
+/* Per-frame shifts and rotations (the joint processing of epochs that differ by a
+ * shift and a rotation, as in the paper's conclusions; the per-epoch dithering
+ * offsets of its supernova application). xf: device array [n_frames][3] =
+ * (dx_i, dy_i, theta_i), referenced, not copied. Frame i then observes the scene
+ * at u = R(theta_i)(X - C) + C + (dx_i, dy_i) for its fine pixel at grid position X,
+ * C = ((N-1)/2, (N-1)/2), R the counter-clockwise rotation: h is read there by
+ * bilinear interpolation (zero outside the grid) and point source k contributes
+ * a_ik r(u - c_k); t_i = 0 is Eq. 9. The data term's gradient in h is the exact
+ * transpose of that interpolation. grad_xf (device [n_frames][3], or NULL):
+ * loss_grad also writes dL/d(dx_i, dy_i, theta_i) there, so that offsets can be
+ * fitted. Frames with transforms run the direct algorithm: setting them moves every
+ * class onto it (EUNSUPPORTED when the kernels exceed its tiles); xf = NULL clears
+ * them and restores the previous choices. Drops captured graphs. The plain baseline
+ * does not support them. */
+int starred_set_frame_transforms(starred_plan *plan, const float *xf, float *grad_xf);
+
+/* Force the algorithm of shape class c: STARRED_CONV_DIRECT, or STARRED_CONV_FFT with
+ * the one-launch forward (fused = 1, where it fits) or the line passes (fused = 0).
+ * Frames of different classes may run different algorithms in one evaluation; the
+ * results agree up to rounding. Drops captured graphs. EUNSUPPORTED when the class's
+ * kernels do not fit the direct path's tiles. */
+int starred_set_class_algo(starred_plan *plan, int32_t c, int32_t algo, int32_t fused);
 
 /* Stage timing, for measurement. While enabled, loss_grad and step record a
  * pair of HIP events on the plan's stream around each stage below, and each
@@ -291,6 +332,9 @@ enum {
     STARRED_STAGE_FFT_FUSED,    /* FFT path, inside CONV_FWD: one-launch forward of the frames
                                    whose spectra fit in LDS (product, both 2-D transforms,
                                    residual, chi-square) */
+    STARRED_STAGE_DIRECT_FWD,   /* the direct algorithm's fused S_i + D forward with the residual
+                                   and chi-square, over the frames of the classes that run it */
+    STARRED_STAGE_DIRECT_ADJ,   /* the direct algorithm's S_i^T D^T over those frames */
     STARRED_NUM_STAGES
 };
 int starred_set_profiling(starred_plan *plan, int32_t enable);

@@ -53,7 +53,7 @@ struct ClassFft {
     int fused;          // frames of this class take the one-launch forward (spectra fit in LDS)
     int arr;            // spectral adjoint: rows of the half spectrum per work group
     int nrr;            // spectral adjoint: row ranges (per-frame partial slots)
-    int pad;
+    int direct;         // the class runs the direct algorithm (the FFT launches skip it)
 };
 
 struct FrameFft {

@@ -1283,6 +1283,7 @@ __global__ __launch_bounds__(256) void k_adj_sums(const ClassFft *__restrict__ c
         long long nbins = 0;
         for (int ci = 0; ci < ncls; ++ci) {
             const ClassFft &c = classes[ci];
+            if (c.direct) continue;  // classes on the direct algorithm have no spectra here
             const int nb = c.P * (c.P / 2 + 1);
             if (g < nb) {
                 gp = Gp + c.gp_off + g;
@@ -1315,6 +1316,7 @@ __global__ __launch_bounds__(256) void k_adj_sums(const ClassFft *__restrict__ c
     const int idx = (blockIdx.x - gblocks) * blockDim.x + threadIdx.x;
     if (idx >= E * Q3) return;
     const int i = idx / Q3, q = idx - i * Q3;
+    if (classes[fr[i].cls].direct) return;  // its sums come from the direct path
     const int npb = classes[fr[i].cls].nrr;
     const double *pp = part + (long long)i * maxpb * Q3 + q;
     double acc = 0.0;

@@ -61,18 +61,30 @@ size_t adj_lds_bytes(int Ar_max, int Bpad_max);
 // ---- kernel launchers (starred_kernels.hip) ----
 hipError_t launch_prep_kernels(hipStream_t st, const FrameDev *fr_dev, const FrameDev *fr_host,
                                int E, int s, const float *psf, float *kf, float *ka);
+// flist (device, nlist frame indices) restricts a launch to those frames; null: every frame
+// xf (device, E x 3 = dx, dy, theta, or null): per-frame transforms of the scene
 hipError_t launch_render(hipStream_t st, const FrameDev *fr, int E, int Fmax, int N, int M,
-                         float sigma, const float *params, float *scene);
+                         float sigma, const float *params, float *scene, const int *flist = nullptr,
+                         int nlist = 0, const float *xf = nullptr);
+// Persistent launches: at most `groups` work groups walk the item list (0: one per item).
 hipError_t launch_fwd_direct(hipStream_t st, int s, const FrameDev *fr, const Item *items,
                              int n_items, int Tmax, const float *scene, const float *kf,
-                             const float *data, const float *invvar, float *out, double *part_chi);
+                             const float *data, const float *invvar, float *out, double *part_chi,
+                             int groups = 0);
 hipError_t launch_adj_direct(hipStream_t st, int s, const FrameDev *fr, const Item *items,
                              int n_items, int Ar_max, int Bpad_max, const float *rho,
-                             const float *ka, float *g);
+                             const float *ka, float *g, int groups = 0);
+// with xf: sums in scene coordinates, and (gxf non-null) dL/d(dx, dy, theta) per frame
 hipError_t launch_frame_sums(hipStream_t st, const FrameDev *fr, int E, int N, int M, float sigma,
-                             const float *params, const float *g, double *fsum, bool with_gamma);
+                             const float *params, const float *g, double *fsum, bool with_gamma,
+                             const int *flist = nullptr, int nlist = 0, const float *xf = nullptr,
+                             float *gxf = nullptr);
 hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, const float *g,
-                             const float *prior, float *grad_h, float *part);
+                             const float *prior, float *grad_h, float *part, const int *flist = nullptr,
+                             int nlist = 0, const float *xf = nullptr);
+// work groups of the direct kernels that fit on the device at once (persistent grid)
+int direct_fwd_groups(int s, int Tmax);
+int direct_adj_groups(int s, int Ar_max, int Bpad_max);
 int finalize_h_chunks(int E);
 // Update of one parameter (bias-corrected moments, per-block learning rate):
 // Adam (v tracks g^2) or, with belief, AdaBelief (v tracks (g - m)^2 + eps_root

@@ -101,10 +101,51 @@ hipError_t launch_prep_kernels(hipStream_t st, const FrameDev *fr_dev, const Fra
 // a1: scene rendering f_i = Gamma_i + h[window_i] + sum_k a_ki r_k   (Eq. 9)
 // --------------------------------------------------------------------------
 
-__global__ void k_render(const FrameDev *__restrict__ frames, int E, int frame0, int N, int M, float sigma,
-                         const float *__restrict__ params, float *__restrict__ scene)
+// Per-frame transform t_i = (dx, dy, theta): the frame pixel at grid position X
+// reads the scene at u = R(theta)(X - C) + C + (dx, dy), C the grid centre.
+struct FrameMap {
+    float cs, sn, C, dx, dy;
+    __device__ FrameMap(const float *xf, int i, int N)
+    {
+        dx = xf[3 * i];
+        dy = xf[3 * i + 1];
+        sincosf(xf[3 * i + 2], &sn, &cs);
+        C = 0.5f * (float)(N - 1);
+    }
+    __device__ void map(float X, float Y, float &ux, float &uy) const
+    {
+        const float vx = X - C, vy = Y - C;
+        ux = cs * vx - sn * vy + C + dx;
+        uy = sn * vx + cs * vy + C + dy;
+    }
+};
+
+__device__ __forceinline__ float h_at(const float *__restrict__ h, int N, int X, int Y)
 {
-    const int i = frame0 + blockIdx.y;
+    return (X >= 0 && X < N && Y >= 0 && Y < N) ? h[(long long)Y * N + X] : 0.f;
+}
+
+// bilinear read of h at (ux, uy) (zero outside the grid) and its partial derivatives
+__device__ __forceinline__ float bilerp(const float *__restrict__ h, int N, float ux, float uy, float *gx,
+                                       float *gy)
+{
+    const float fx = floorf(ux), fy = floorf(uy);
+    const int X0 = (int)fx, Y0 = (int)fy;
+    const float tx = ux - fx, ty = uy - fy;
+    const float h00 = h_at(h, N, X0, Y0), h10 = h_at(h, N, X0 + 1, Y0);
+    const float h01 = h_at(h, N, X0, Y0 + 1), h11 = h_at(h, N, X0 + 1, Y0 + 1);
+    if (gx) {
+        *gx = (1.f - ty) * (h10 - h00) + ty * (h11 - h01);
+        *gy = (1.f - tx) * (h01 - h00) + tx * (h11 - h10);
+    }
+    return (1.f - tx) * (1.f - ty) * h00 + tx * (1.f - ty) * h10 + (1.f - tx) * ty * h01 + tx * ty * h11;
+}
+
+__global__ void k_render(const FrameDev *__restrict__ frames, int E, int frame0, int N, int M, float sigma,
+                         const float *__restrict__ params, float *__restrict__ scene,
+                         const int *__restrict__ flist, const float *__restrict__ xf)
+{
+    const int i = flist ? flist[blockIdx.y] : frame0 + blockIdx.y;
     const FrameDev fr = frames[i];
     const int pix = blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= fr.F * fr.F) return;
@@ -113,11 +154,18 @@ __global__ void k_render(const FrameDev *__restrict__ frames, int E, int frame0,
     const float *h = params;
     const float *a = params + (long long)N * N + E;
     const float *c = a + (long long)E * M;
-    float v = params[(long long)N * N + i] + h[(long long)Y * N + X];
+    float ux = (float)X, uy = (float)Y, v;
+    if (xf) {
+        FrameMap fm(xf, i, N);
+        fm.map((float)X, (float)Y, ux, uy);
+        v = params[(long long)N * N + i] + bilerp(h, N, ux, uy, nullptr, nullptr);
+    } else {
+        v = params[(long long)N * N + i] + h[(long long)Y * N + X];
+    }
     const float inv2s2 = 1.0f / (2.0f * sigma * sigma);
     const float norm = 1.0f / (2.0f * 3.14159265358979f * sigma * sigma);
     for (int k = 0; k < M; ++k) {
-        float dx = (float)X - c[2 * k], dy = (float)Y - c[2 * k + 1];
+        float dx = ux - c[2 * k], dy = uy - c[2 * k + 1];
         if (fabsf(dx) <= (float)kGaussRadius && fabsf(dy) <= (float)kGaussRadius)
             v += a[(long long)i * M + k] * (norm * expf(-(dx * dx + dy * dy) * inv2s2));
     }
@@ -125,11 +173,13 @@ __global__ void k_render(const FrameDev *__restrict__ frames, int E, int frame0,
 }
 
 hipError_t launch_render(hipStream_t st, const FrameDev *fr, int E, int Fmax, int N, int M,
-                         float sigma, const float *params, float *scene)
+                         float sigma, const float *params, float *scene, const int *flist, int nlist,
+                         const float *xf)
 {
-    if (E <= 0) return hipSuccess;
-    dim3 grid((Fmax * Fmax + 255) / 256, E);
-    hipLaunchKernelGGL(k_render, grid, dim3(256), 0, st, fr, E, 0, N, M, sigma, params, scene);
+    const int nf = flist ? nlist : E;
+    if (nf <= 0) return hipSuccess;
+    dim3 grid((Fmax * Fmax + 255) / 256, nf);
+    hipLaunchKernelGGL(k_render, grid, dim3(256), 0, st, fr, E, 0, N, M, sigma, params, scene, flist, xf);
     return hipGetLastError();
 }
 
@@ -137,7 +187,7 @@ hipError_t launch_render_frame(hipStream_t st, const FrameDev *fr, int E, int i,
                                float sigma, const float *params, float *scene)
 {
     dim3 grid((F * F + 255) / 256, 1);
-    hipLaunchKernelGGL(k_render, grid, dim3(256), 0, st, fr, E, i, N, M, sigma, params, scene);
+    hipLaunchKernelGGL(k_render, grid, dim3(256), 0, st, fr, E, i, N, M, sigma, params, scene, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -247,12 +297,14 @@ template <int S, bool RESID>
 __global__ __launch_bounds__(kFwdThreads) void k_fwd_direct(
     const FrameDev *__restrict__ frames, const Item *__restrict__ items,
     const float *__restrict__ scene, const float *__restrict__ kf, const float *__restrict__ data,
-    const float *__restrict__ invvar, float *__restrict__ out, double *__restrict__ part_chi)
+    const float *__restrict__ invvar, float *__restrict__ out, double *__restrict__ part_chi, int n_items)
 {
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
     __shared__ double red[kFwdThreads / 64];
-    const Item it = items[blockIdx.x];
+    // persistent: the grid walks the (longest-first) item list
+    for (int b = blockIdx.x; b < n_items; b += gridDim.x) {
+    const Item it = items[b];
     const FrameDev fr = frames[it.frame];
     const int tid = threadIdx.x;
     constexpr int NTX = kFwdTQ / 4;
@@ -312,25 +364,51 @@ __global__ __launch_bounds__(kFwdThreads) void k_fwd_direct(
         const double tot = block_sum_d<kFwdThreads>(chi, red);
         if (tid == 0) part_chi[it.slot] = tot;
     }
+    }
 }
 
 size_t fwd_lds_bytes(int s, int Tmax) { return (size_t)(s * (kFwdTP - 1) + kFwdCA) * s * (kFwdTQ + Tmax) * 4; }
 
+static int device_cus()
+{
+    static int n = 0;
+    if (n <= 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+    }
+    return n;
+}
+
+int direct_fwd_groups(int s, int Tmax)
+{
+    int per = 0;
+    const size_t lds = fwd_lds_bytes(s, Tmax);
+    hipError_t e = hipErrorInvalidValue;
+    if (s == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_fwd_direct<1, true>, kFwdThreads, lds);
+    if (s == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_fwd_direct<2, true>, kFwdThreads, lds);
+    if (s == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_fwd_direct<3, true>, kFwdThreads, lds);
+    if (e != hipSuccess || per < 1) per = 1;
+    return per * device_cus();
+}
+
 hipError_t launch_fwd_direct(hipStream_t st, int s, const FrameDev *fr, const Item *items,
                              int n_items, int Tmax, const float *scene, const float *kf,
-                             const float *data, const float *invvar, float *out, double *part_chi)
+                             const float *data, const float *invvar, float *out, double *part_chi, int groups)
 {
     if (n_items <= 0) return hipSuccess;
     const size_t lds = fwd_lds_bytes(s, Tmax);
     const bool resid = (part_chi != nullptr);
+    const int grid = (groups > 0 && groups < n_items) ? groups : n_items;
 #define FWD_CASE(SS)                                                                               \
     if (s == SS) {                                                                                 \
         if (resid)                                                                                 \
-            hipLaunchKernelGGL((k_fwd_direct<SS, true>), dim3(n_items), dim3(kFwdThreads), lds, st, \
-                               fr, items, scene, kf, data, invvar, out, part_chi);                 \
+            hipLaunchKernelGGL((k_fwd_direct<SS, true>), dim3(grid), dim3(kFwdThreads), lds, st,    \
+                               fr, items, scene, kf, data, invvar, out, part_chi, n_items);        \
         else                                                                                       \
-            hipLaunchKernelGGL((k_fwd_direct<SS, false>), dim3(n_items), dim3(kFwdThreads), lds,   \
-                               st, fr, items, scene, kf, data, invvar, out, part_chi);             \
+            hipLaunchKernelGGL((k_fwd_direct<SS, false>), dim3(grid), dim3(kFwdThreads), lds,      \
+                               st, fr, items, scene, kf, data, invvar, out, part_chi, n_items);    \
         return hipGetLastError();                                                                  \
     }
     FWD_CASE(1)
@@ -350,11 +428,14 @@ hipError_t launch_fwd_direct(hipStream_t st, int s, const FrameDev *fr, const It
 template <int S>
 __global__ __launch_bounds__(kAdjThreads) void k_adj_direct(
     const FrameDev *__restrict__ frames, const Item *__restrict__ items,
-    const float *__restrict__ rho, const float *__restrict__ ka, float *__restrict__ g)
+    const float *__restrict__ rho, const float *__restrict__ ka, float *__restrict__ g, int n_items)
 {
     extern __shared__ float4 lds4[];
     float *lds = reinterpret_cast<float *>(lds4);
-    const Item it = items[blockIdx.x];
+    // persistent: the grid walks the (longest-first) item list
+    for (int b = blockIdx.x; b < n_items; b += gridDim.x) {
+    if (b != (int)blockIdx.x) __syncthreads();  // the previous item's reads of the tile are done
+    const Item it = items[b];
     const FrameDev fr = frames[it.frame];
     const int tid = threadIdx.x;
     constexpr int NTX = kAdjTQ / 4;
@@ -393,22 +474,36 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_direct(
                 }
             }
         }
+    }
 }
 
 size_t adj_lds_bytes(int Ar_max, int Bpad_max) { return (size_t)(kAdjTP - 1 + Ar_max) * (kAdjTQ + Bpad_max) * 4; }
 
+int direct_adj_groups(int s, int Ar_max, int Bpad_max)
+{
+    int per = 0;
+    const size_t lds = adj_lds_bytes(Ar_max, Bpad_max);
+    hipError_t e = hipErrorInvalidValue;
+    if (s == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_adj_direct<1>, kAdjThreads, lds);
+    if (s == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_adj_direct<2>, kAdjThreads, lds);
+    if (s == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_adj_direct<3>, kAdjThreads, lds);
+    if (e != hipSuccess || per < 1) per = 1;
+    return per * device_cus();
+}
+
 hipError_t launch_adj_direct(hipStream_t st, int s, const FrameDev *fr, const Item *items,
                              int n_items, int Ar_max, int Bpad_max, const float *rho,
-                             const float *ka, float *g)
+                             const float *ka, float *g, int groups)
 {
     if (n_items <= 0) return hipSuccess;
     const size_t lds = adj_lds_bytes(Ar_max, Bpad_max);
+    const int grid = (groups > 0 && groups < n_items) ? groups : n_items;
     if (s == 1)
-        hipLaunchKernelGGL(k_adj_direct<1>, dim3(n_items), dim3(kAdjThreads), lds, st, fr, items, rho, ka, g);
+        hipLaunchKernelGGL(k_adj_direct<1>, dim3(grid), dim3(kAdjThreads), lds, st, fr, items, rho, ka, g, n_items);
     else if (s == 2)
-        hipLaunchKernelGGL(k_adj_direct<2>, dim3(n_items), dim3(kAdjThreads), lds, st, fr, items, rho, ka, g);
+        hipLaunchKernelGGL(k_adj_direct<2>, dim3(grid), dim3(kAdjThreads), lds, st, fr, items, rho, ka, g, n_items);
     else if (s == 3)
-        hipLaunchKernelGGL(k_adj_direct<3>, dim3(n_items), dim3(kAdjThreads), lds, st, fr, items, rho, ka, g);
+        hipLaunchKernelGGL(k_adj_direct<3>, dim3(grid), dim3(kAdjThreads), lds, st, fr, items, rho, ka, g, n_items);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -422,16 +517,114 @@ hipError_t launch_adj_direct(hipStream_t st, int s, const FrameDev *fr, const It
 
 constexpr int kSumThreads = 256;
 
+// Frame sums under a per-frame transform: block 0 dL/dGamma_i; block 1+k the sums of
+// g r_k(u) and g r_k(u) (u - c_k)/sigma^2 (scene coordinates u, so dL/dc_k needs no
+// rotation); block 1+M (when gxf is given) dL/d(dx_i, dy_i, theta_i) from
+// q(X) = grad h(u) - sum_k a_ik r_k(u) (u - c_k)/sigma^2:  <g, q> and
+// <g, q . R'(theta)(X - C)>.
+__device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, int M, float sigma,
+                              const float *__restrict__ params, const float *__restrict__ gi,
+                              double *__restrict__ fsum, const float *__restrict__ xf, float *__restrict__ gxf,
+                              double *red)
+{
+    const int stride = 1 + 3 * M;
+    const int tot = fr.F * fr.F;
+    const float *h = params;
+    const float *a = params + (long long)N * N + E;
+    const float *c = a + (long long)E * M;
+    const float inv2s2 = 1.0f / (2.0f * sigma * sigma);
+    const float invs2 = 1.0f / (sigma * sigma);
+    const float norm = 1.0f / (2.0f * 3.14159265358979f * sigma * sigma);
+    const FrameMap fm(xf, i, N);
+    if (by == 0) {
+        double acc = 0.0;
+        for (int p = threadIdx.x; p < tot; p += kSumThreads) acc += (double)gi[p];
+        const double sm = block_sum_d<kSumThreads>(acc, red);
+        if (threadIdx.x == 0) fsum[(long long)i * stride] = sm;
+        return;
+    }
+    if (by <= M) {
+        const int k = by - 1;
+        const float cx = c[2 * k], cy = c[2 * k + 1];
+        // the source's box |u - c| <= R in frame coordinates: around the preimage of
+        // c, within R sqrt(2) (+1) on each axis
+        const float ex = cx - fm.C - fm.dx, ey = cy - fm.C - fm.dy;
+        const float px = fm.cs * ex + fm.sn * ey + fm.C, py = -fm.sn * ex + fm.cs * ey + fm.C;
+        const float rad = (float)kGaussRadius * 1.4143f + 1.f;
+        const int x_lo = max(fr.o, (int)floorf(px - rad)), x_hi = min(fr.o + fr.F - 1, (int)ceilf(px + rad));
+        const int y_lo = max(fr.o, (int)floorf(py - rad)), y_hi = min(fr.o + fr.F - 1, (int)ceilf(py + rad));
+        const int wx = x_hi - x_lo + 1, wy = y_hi - y_lo + 1;
+        double sa = 0.0, sx = 0.0, sy = 0.0;
+        if (wx > 0 && wy > 0) {
+            for (int e = threadIdx.x; e < wx * wy; e += kSumThreads) {
+                const int Y = y_lo + e / wx, X = x_lo + e % wx;
+                float ux, uy;
+                fm.map((float)X, (float)Y, ux, uy);
+                const float dx = ux - cx, dy = uy - cy;
+                if (fabsf(dx) > (float)kGaussRadius || fabsf(dy) > (float)kGaussRadius) continue;
+                const float r = norm * expf(-(dx * dx + dy * dy) * inv2s2);
+                const float gr = gi[(long long)(Y - fr.o) * fr.F + (X - fr.o)] * r;
+                sa += (double)gr;
+                sx += (double)(gr * dx * invs2);
+                sy += (double)(gr * dy * invs2);
+            }
+        }
+        sa = block_sum_d<kSumThreads>(sa, red);
+        sx = block_sum_d<kSumThreads>(sx, red);
+        sy = block_sum_d<kSumThreads>(sy, red);
+        if (threadIdx.x == 0) {
+            fsum[(long long)i * stride + 1 + k] = sa;
+            fsum[(long long)i * stride + 1 + M + k] = sx;
+            fsum[(long long)i * stride + 1 + 2 * M + k] = sy;
+        }
+        return;
+    }
+    // by == 1 + M: the transform's gradient
+    double gdx = 0.0, gdy = 0.0, gth = 0.0;
+    for (int p = threadIdx.x; p < tot; p += kSumThreads) {
+        const float X = (float)(fr.o + p % fr.F), Y = (float)(fr.o + p / fr.F);
+        float ux, uy, qx, qy;
+        fm.map(X, Y, ux, uy);
+        bilerp(h, N, ux, uy, &qx, &qy);
+        for (int k = 0; k < M; ++k) {
+            const float dx = ux - c[2 * k], dy = uy - c[2 * k + 1];
+            if (fabsf(dx) <= (float)kGaussRadius && fabsf(dy) <= (float)kGaussRadius) {
+                const float ar = a[(long long)i * M + k] * norm * expf(-(dx * dx + dy * dy) * inv2s2) * invs2;
+                qx -= ar * dx;
+                qy -= ar * dy;
+            }
+        }
+        const float gv = gi[p];
+        const float vx = X - fm.C, vy = Y - fm.C;
+        gdx += (double)(gv * qx);
+        gdy += (double)(gv * qy);
+        gth += (double)(gv * (qx * (-fm.sn * vx - fm.cs * vy) + qy * (fm.cs * vx - fm.sn * vy)));
+    }
+    gdx = block_sum_d<kSumThreads>(gdx, red);
+    gdy = block_sum_d<kSumThreads>(gdy, red);
+    gth = block_sum_d<kSumThreads>(gth, red);
+    if (threadIdx.x == 0) {
+        gxf[3 * i] = (float)gdx;
+        gxf[3 * i + 1] = (float)gdy;
+        gxf[3 * i + 2] = (float)gth;
+    }
+}
+
 __global__ __launch_bounds__(kSumThreads) void k_frame_sums(
     const FrameDev *__restrict__ frames, int E, int frame0, int N, int M, float sigma,
-    const float *__restrict__ params, const float *__restrict__ g, double *__restrict__ fsum, int yofs)
+    const float *__restrict__ params, const float *__restrict__ g, double *__restrict__ fsum, int yofs,
+    const int *__restrict__ flist, const float *__restrict__ xf, float *__restrict__ gxf)
 {
     __shared__ double red[kSumThreads / 64];
-    const int i = frame0 + blockIdx.x;
+    const int i = flist ? flist[blockIdx.x] : frame0 + blockIdx.x;
     const int by = blockIdx.y + yofs;  // yofs = 1: the frame sums of g come from elsewhere
     const FrameDev fr = frames[i];
     const float *gi = g + fr.fine_off;
     const int stride = 1 + 3 * M;
+    if (xf) {
+        frame_sums_xf(fr, i, by, E, N, M, sigma, params, gi, fsum, xf, gxf, red);
+        return;
+    }
     if (by == 0) {
         double acc = 0.0;
         const int tot = fr.F * fr.F;
@@ -473,13 +666,16 @@ __global__ __launch_bounds__(kSumThreads) void k_frame_sums(
 }
 
 hipError_t launch_frame_sums(hipStream_t st, const FrameDev *fr, int E, int N, int M, float sigma,
-                             const float *params, const float *g, double *fsum, bool with_gamma)
+                             const float *params, const float *g, double *fsum, bool with_gamma,
+                             const int *flist, int nlist, const float *xf, float *gxf)
 {
-    if (E <= 0) return hipSuccess;
+    const int nf = flist ? nlist : E;
+    if (nf <= 0) return hipSuccess;
     const int yofs = with_gamma ? 0 : 1;
-    if (1 + M - yofs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_frame_sums, dim3(E, 1 + M - yofs), dim3(kSumThreads), 0, st, fr, E, 0, N, M, sigma,
-                       params, g, fsum, yofs);
+    const int ny = 1 + M - yofs + ((xf && gxf) ? 1 : 0);  // + the transform's gradient block
+    if (ny <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_frame_sums, dim3(nf, ny), dim3(kSumThreads), 0, st, fr, E, 0, N, M, sigma,
+                       params, g, fsum, yofs, flist, xf, gxf);
     return hipGetLastError();
 }
 
@@ -487,7 +683,7 @@ hipError_t launch_frame_sums_one(hipStream_t st, const FrameDev *fr, int E, int 
                                  const float *params, const float *g, double *fsum)
 {
     hipLaunchKernelGGL(k_frame_sums, dim3(1, 1 + M), dim3(kSumThreads), 0, st, fr, E, i, N, M, sigma,
-                       params, g, fsum, 0);
+                       params, g, fsum, 0, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -499,15 +695,58 @@ constexpr int kFinChunk = 16;  // frames summed by one thread of k_finalize_h_pa
 
 // Two-stage cross-frame sum (frame order within a chunk, then chunk order):
 // part[c][Y,X] = sum over frames of chunk c covering (Y,X) of g_i(Y - o_i, X - o_i)
+// Transpose of the bilinear read of frame i at grid pixel (PX, PY): the sum of
+// g_i(X) times the weight with which frame pixel X read h there, over the frame
+// pixels whose transformed position lies within one pixel of (PX, PY) on both axes
+// (a gather in a fixed order: the candidates around the preimage of the pixel).
+__device__ float transpose_bilerp(const FrameDev &fr, int i, int N, const float *__restrict__ xf,
+                                  const float *__restrict__ g, int PX, int PY)
+{
+    const FrameMap fm(xf, i, N);
+    const float ex = (float)PX - fm.C - fm.dx, ey = (float)PY - fm.C - fm.dy;
+    const float px = fm.cs * ex + fm.sn * ey + fm.C, py = -fm.sn * ex + fm.cs * ey + fm.C;
+    const int bx = (int)floorf(px), byy = (int)floorf(py);
+    const float *gi = g + fr.fine_off;
+    float acc = 0.f;
+    for (int Y = byy - 2; Y <= byy + 2; ++Y) {
+        const int y = Y - fr.o;
+        if (y < 0 || y >= fr.F) continue;
+        for (int X = bx - 2; X <= bx + 2; ++X) {
+            const int x = X - fr.o;
+            if (x < 0 || x >= fr.F) continue;
+            float ux, uy;
+            fm.map((float)X, (float)Y, ux, uy);
+            // the same corner weights as the read: (1 - t) towards the lower corner
+            const float fx = floorf(ux), fy = floorf(uy);
+            const int X0 = (int)fx, Y0 = (int)fy;
+            if ((PX != X0 && PX != X0 + 1) || (PY != Y0 && PY != Y0 + 1)) continue;
+            const float tx = ux - fx, ty = uy - fy;
+            const float wx = PX == X0 ? 1.f - tx : tx, wy = PY == Y0 ? 1.f - ty : ty;
+            acc += gi[(long long)y * fr.F + x] * (wx * wy);
+        }
+    }
+    return acc;
+}
+
 __global__ void k_finalize_h_part(const FrameDev *__restrict__ frames, int E, int N,
-                                  const float *__restrict__ g, float *__restrict__ part)
+                                  const float *__restrict__ g, float *__restrict__ part,
+                                  const int *__restrict__ flist, const float *__restrict__ xf)
 {
     const int pix = blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= N * N) return;
     const int Y = pix / N, X = pix % N;
     const int i0 = blockIdx.y * kFinChunk, i1 = min(E, i0 + kFinChunk);
     float acc = 0.f;
-    for (int i = i0; i < i1; ++i) {
+    if (xf) {
+        for (int q = i0; q < i1; ++q) {
+            const int i = flist ? flist[q] : q;
+            acc += transpose_bilerp(frames[i], i, N, xf, g, X, Y);
+        }
+        part[(long long)blockIdx.y * N * N + pix] = acc;
+        return;
+    }
+    for (int q = i0; q < i1; ++q) {
+        const int i = flist ? flist[q] : q;
         const int o = frames[i].o, F = frames[i].F;
         const int y = Y - o, x = X - o;
         if (y >= 0 && y < F && x >= 0 && x < F) acc += g[frames[i].fine_off + (long long)y * F + x];
@@ -529,11 +768,13 @@ __global__ void k_finalize_h_sum(int nchunk, int N, const float *__restrict__ pa
 int finalize_h_chunks(int E) { return (E + kFinChunk - 1) / kFinChunk; }
 
 hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, const float *g,
-                             const float *prior, float *grad_h, float *part)
+                             const float *prior, float *grad_h, float *part, const int *flist, int nlist,
+                             const float *xf)
 {
     const int nb = (N * N + 255) / 256;
-    const int nc = finalize_h_chunks(E);
-    hipLaunchKernelGGL(k_finalize_h_part, dim3(nb, nc), dim3(256), 0, st, fr, E, N, g, part);
+    const int nf = flist ? nlist : E;
+    const int nc = finalize_h_chunks(nf);
+    hipLaunchKernelGGL(k_finalize_h_part, dim3(nb, nc), dim3(256), 0, st, fr, nf, N, g, part, flist, xf);
     hipLaunchKernelGGL(k_finalize_h_sum, dim3(nb), dim3(256), 0, st, nc, N, part, prior, grad_h);
     return hipGetLastError();
 }
@@ -561,6 +802,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(FinalArgs fa, co
     float acc = prior ? prior[pix] : 0.f;
     for (int ci = 0; ci < ncls; ++ci) {
         const ClassFft &c = classes[ci];
+        if (c.direct) continue;  // its frames' windows are in prior (the direct path's sum)
         const int y = Y - c.o, x = X - c.o, F = c.F;
         if (y >= 0 && y < F && x >= 0 && x < F) acc += hcls[c.hc_off + (long long)y * F + x];
     }

@@ -9,6 +9,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <chrono>
+#include <mutex>
 #include <cmath>
 #include <complex>
 #include <map>
@@ -118,7 +121,34 @@ struct starred_plan {
     FftPlanDev fd;
     std::vector<ClassFft> cls;
     std::vector<FrameFft> ffr;
-    double *d_part_chi_fft = nullptr;
+    std::vector<int> fcls;        // class of each frame
+    std::vector<int> cls_frames;  // frames in class order
+    std::vector<int> cls_fits;    // per class: the one-launch forward fits in LDS
+    double *d_part_chi_fft = nullptr;  // chi-square partials: FFT groups, then direct tiles
+    int n_fft_chi = 0;
+    // launch shapes of the FFT path: work groups aimed at by the spectral adjoint
+    // and by the line passes (the autotuner may change them)
+    int adj_blocks = kAdjBlocks, line_groups = 1024;
+    // frames of the classes that run the direct algorithm, and their LDS extents
+    std::vector<int> fdir;
+    int *d_fdir = nullptr;
+    int Tdir = 0, Ardir = 0, Bpdir = 0, Fdir = 0;
+    int fwd_groups = 0, adj_groups = 0;  // persistent grids of the direct kernels
+    float *d_hdir = nullptr;  // prior gradient plus the direct frames' windows of dL/dh
+    // per-frame transforms (device E x 3: dx, dy, theta; caller-owned) and the
+    // caller's buffer for their gradient (or null); the class choices before they
+    // were set (restored when they are cleared)
+    const float *xf = nullptr;
+    float *gxf = nullptr;
+    std::vector<int> xf_prev_choice;
+    // autotuner: per class the ms of an evaluation with each choice tried
+    // (direct, FFT one-launch forward, FFT line passes; < 0 = not tried), the
+    // host time it took and whether its decision came from the cache
+    std::vector<std::array<double, 3>> cls_tune;
+    double tune_wall_ms = 0.0;
+    int tune_cached = 0;
+    // work lists (rebuilt with the per-class choices): freed on rebuild
+    std::vector<void *> list_owned;
     // plain per-epoch baseline (s = 1 tables at fine resolution)
     bool plain_ready = false;
     std::vector<FrameDev> frp;
@@ -137,7 +167,6 @@ struct starred_plan {
     double *d_part_eta = nullptr;
     int algo_req = STARRED_CONV_AUTO;
     bool direct_ok = true;
-    double tune_ms[3] = {0, 0, 0};
 
     // starlet branch: a second stream forked from and joined back into st
     hipStream_t st2 = nullptr;
@@ -215,6 +244,7 @@ struct starred_plan {
         if (st2) (void)hipStreamDestroy(st2);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (void *p : owned) (void)hipFree(p);
+        free_lists();
     }
     template <typename T>
     int alloc(T **p, size_t count)
@@ -222,6 +252,18 @@ struct starred_plan {
         int rc = dev_alloc(p, count);
         if (rc == STARRED_OK) owned.push_back((void *)*p);
         return rc;
+    }
+    template <typename T>
+    int alloc_list(T **p, size_t count)
+    {
+        int rc = dev_alloc(p, count);
+        if (rc == STARRED_OK) list_owned.push_back((void *)*p);
+        return rc;
+    }
+    void free_lists()
+    {
+        for (void *q : list_owned) (void)hipFree(q);
+        list_owned.clear();
     }
 };
 
@@ -351,42 +393,9 @@ static int build_deconv(starred_plan *p)
     p->nka = kaoff;
     p->nparams = (long long)p->N * p->N + E + (long long)E * p->M + 2LL * p->M;
 
-    // Work lists: frame-major enumeration fixes the partial-result slots; the
-    // launch order is longest-first (cost ~ folded kernel area) so that ragged
-    // batches balance across the compute units.
-    struct Cost { long long c; Item it; };
-    std::vector<Cost> fw, ad;
-    int slot = 0;
-    for (int i = 0; i < E; ++i) {
-        const FrameDev &f = p->fr[i];
-        for (int p0 = 0; p0 < f.n; p0 += kFwdTP)
-            for (int q0 = 0; q0 < f.n; q0 += kFwdTQ) {
-                Item it{i, p0, q0, slot++};
-                fw.push_back({(long long)f.Kp * s * f.Tpad, it});
-            }
-    }
-    slot = 0;
-    for (int i = 0; i < E; ++i) {
-        const FrameDev &f = p->fr[i];
-        for (int p0 = 0; p0 < f.n; p0 += kAdjTP)
-            for (int q0 = 0; q0 < f.n; q0 += kAdjTQ) {
-                Item it{i, p0, q0, slot++};
-                ad.push_back({(long long)s * s * f.Ar * f.Bpad, it});
-            }
-    }
-    auto by_cost = [](const Cost &a, const Cost &b) { return a.c > b.c; };
-    std::stable_sort(fw.begin(), fw.end(), by_cost);
-    std::stable_sort(ad.begin(), ad.end(), by_cost);
-    for (auto &c : fw) p->fwd_items.push_back(c.it);
-    for (auto &c : ad) p->adj_items.push_back(c.it);
-
     int rc;
     if ((rc = p->alloc(&p->d_fr, E))) return rc;
-    if ((rc = p->alloc(&p->d_fwd_items, p->fwd_items.size()))) return rc;
-    if ((rc = p->alloc(&p->d_adj_items, p->adj_items.size()))) return rc;
     HIP_TRY(hipMemcpy(p->d_fr, p->fr.data(), sizeof(FrameDev) * E, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(p->d_fwd_items, p->fwd_items.data(), sizeof(Item) * p->fwd_items.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(p->d_adj_items, p->adj_items.data(), sizeof(Item) * p->adj_items.size(), hipMemcpyHostToDevice));
 
     const long long NN = (long long)p->N * p->N;
     if ((rc = p->alloc(&p->d_kf, p->nkf))) return rc;
@@ -394,7 +403,6 @@ static int build_deconv(starred_plan *p)
     if ((rc = p->alloc(&p->d_scene, p->nfine))) return rc;
     if ((rc = p->alloc(&p->d_rho, p->ndata))) return rc;
     if ((rc = p->alloc(&p->d_g, p->nfine))) return rc;
-    if ((rc = p->alloc(&p->d_part_chi, p->fwd_items.size()))) return rc;
     if ((rc = dense_setup(p, 2))) return rc;
     if ((rc = p->alloc(&p->d_part_l1, std::max((size_t)2 * starlet_l1_slots(p->N, p->J), dense_l1_slots(p)))))
         return rc;
@@ -408,9 +416,76 @@ static int build_deconv(starred_plan *p)
     if ((rc = p->alloc(&p->d_tmp, NN))) return rc;
     if ((rc = p->alloc(&p->d_prior, 2 * NN))) return rc;
     if ((rc = p->alloc(&p->d_hpart, (size_t)finalize_h_chunks(E) * NN))) return rc;
+    if ((rc = p->alloc(&p->d_hdir, NN))) return rc;
     if ((rc = p->alloc(&p->d_grad, p->nparams))) return rc;
     if ((rc = p->alloc(&p->d_wzero, (size_t)p->J * NN))) return rc;
     HIP_TRY(hipMemset(p->d_wzero, 0, sizeof(float) * p->J * NN));
+    return STARRED_OK;
+}
+
+// The direct path's work lists over the frames of the classes that run it
+// (every frame when the plan has no classes yet): tiles of those frames; the
+// partial-result slots are enumerated frame by frame, the launch order is
+// longest first (cost ~ folded kernel area) so that ragged batches balance
+// across the compute units, and the launches are persistent (a fixed grid that
+// walks the list).
+static int build_direct_lists(starred_plan *p)
+{
+    const int s = p->s, E = p->E;
+    p->fwd_items.clear();
+    p->adj_items.clear();
+    p->fdir.clear();
+    p->Tdir = p->Ardir = p->Bpdir = p->Fdir = 0;
+    for (int i = 0; i < E; ++i)
+        if (p->cls.empty() || p->cls[p->fcls[i]].direct) {
+            const FrameDev &f = p->fr[i];
+            p->fdir.push_back(i);
+            p->Tdir = std::max(p->Tdir, f.Tpad);
+            p->Ardir = std::max(p->Ardir, f.Ar);
+            p->Bpdir = std::max(p->Bpdir, f.Bpad);
+            p->Fdir = std::max(p->Fdir, f.F);
+        }
+    struct Cost { long long c; Item it; };
+    std::vector<Cost> fw, ad;
+    int slot = 0;
+    for (int i : p->fdir) {
+        const FrameDev &f = p->fr[i];
+        for (int p0 = 0; p0 < f.n; p0 += kFwdTP)
+            for (int q0 = 0; q0 < f.n; q0 += kFwdTQ) {
+                Item it{i, p0, q0, slot++};
+                fw.push_back({(long long)f.Kp * s * f.Tpad, it});
+            }
+    }
+    slot = 0;
+    for (int i : p->fdir) {
+        const FrameDev &f = p->fr[i];
+        for (int p0 = 0; p0 < f.n; p0 += kAdjTP)
+            for (int q0 = 0; q0 < f.n; q0 += kAdjTQ) {
+                Item it{i, p0, q0, slot++};
+                ad.push_back({(long long)s * s * f.Ar * f.Bpad, it});
+            }
+    }
+    auto by_cost = [](const Cost &a, const Cost &b) { return a.c > b.c; };
+    std::stable_sort(fw.begin(), fw.end(), by_cost);
+    std::stable_sort(ad.begin(), ad.end(), by_cost);
+    for (auto &c : fw) p->fwd_items.push_back(c.it);
+    for (auto &c : ad) p->adj_items.push_back(c.it);
+    if (!p->fdir.empty()) {
+        p->fwd_groups = direct_fwd_groups(s, p->Tdir);
+        p->adj_groups = direct_adj_groups(s, p->Ardir, p->Bpdir);
+    }
+    int rc;
+    if ((rc = p->alloc_list(&p->d_fwd_items, std::max<size_t>(1, p->fwd_items.size())))) return rc;
+    if ((rc = p->alloc_list(&p->d_adj_items, std::max<size_t>(1, p->adj_items.size())))) return rc;
+    if ((rc = p->alloc_list(&p->d_fdir, std::max<size_t>(1, p->fdir.size())))) return rc;
+    if (!p->fwd_items.empty())
+        HIP_TRY(hipMemcpy(p->d_fwd_items, p->fwd_items.data(), sizeof(Item) * p->fwd_items.size(),
+                          hipMemcpyHostToDevice));
+    if (!p->adj_items.empty())
+        HIP_TRY(hipMemcpy(p->d_adj_items, p->adj_items.data(), sizeof(Item) * p->adj_items.size(),
+                          hipMemcpyHostToDevice));
+    if (!p->fdir.empty())
+        HIP_TRY(hipMemcpy(p->d_fdir, p->fdir.data(), sizeof(int) * p->fdir.size(), hipMemcpyHostToDevice));
     return STARRED_OK;
 }
 
@@ -451,13 +526,19 @@ static FftLen make_len(int L, std::map<int, long long> &tw_offsets, long long &t
     return f;
 }
 
+static int build_fft_lists(starred_plan *p);
+
+// Shape classes, transform lengths, factor tables and the per-frame spectra (fixed
+// for the plan); the work lists, which depend on each class's algorithm and
+// forward form, follow in build_fft_lists.
 static int build_fft(starred_plan *p)
 {
     const int s = p->s, E = p->E;
     std::map<std::pair<int, int>, int> cls_of;  // (n, K) -> class
     std::map<int, long long> tw_off;
     long long tw_total = 0;
-    std::vector<int> fcls(E);
+    std::vector<int> &fcls = p->fcls;
+    fcls.assign(E, 0);
     for (int i = 0; i < E; ++i) {
         auto key = std::make_pair(p->n[i], p->K[i]);
         auto it = cls_of.find(key);
@@ -492,10 +573,16 @@ static int build_fft(starred_plan *p)
         c.tab_off = tb;
         tb += (long long)(1 + 4 * M) * c.P;
     }
-    // classes whose Q-grid planes fit in LDS take the one-launch forward
-    for (auto &c : p->cls) c.fused = fused_lds_bytes(c.Q, c.n, c.P, p->M) <= kFusedLdsMax ? 1 : 0;
+    // classes whose Q-grid planes fit in LDS may take the one-launch forward
+    p->cls_fits.clear();
+    for (auto &c : p->cls) {
+        p->cls_fits.push_back(fused_lds_bytes(c.Q, c.n, c.P, p->M) <= kFusedLdsMax ? 1 : 0);
+        c.fused = p->cls_fits.back();
+        c.direct = 0;
+    }
     // class-ordered frame list
-    std::vector<int> cls_frames;
+    std::vector<int> &cls_frames = p->cls_frames;
+    cls_frames.clear();
     for (int c = 0; c < (int)p->cls.size(); ++c) {
         p->cls[c].cf_off = (int)cls_frames.size();
         for (int i = 0; i < E; ++i)
@@ -522,9 +609,20 @@ static int build_fft(starred_plan *p)
         f.t3_off = t3o;
         t3o += (long long)c.P * HP;
     }
+    // frequency-domain adjoint: chunks of kAdjFrames frames; summed spectra per chunk
+    long long gp = 0, hc = 0;
+    for (ClassFft &cl : p->cls) {
+        cl.gfch = kAdjFrames;
+        cl.ngch = (cl.ncf + kAdjFrames - 1) / kAdjFrames;
+        cl.gp_off = gp;
+        gp += (long long)cl.ngch * cl.P * (cl.P / 2 + 1);
+        cl.hc_off = hc;
+        hc += (long long)cl.F * cl.F;
+    }
     int rc;
     FftPlanDev &d = p->fd;
     d.n_classes = (int)p->cls.size();
+    d.n_frames = E;
     if ((rc = p->alloc(&d.classes, p->cls.size()))) return rc;
     if ((rc = p->alloc(&d.frames, E))) return rc;
     if ((rc = p->alloc(&d.tw, tw_total))) return rc;
@@ -536,6 +634,11 @@ static int build_fft(starred_plan *p)
     if ((rc = p->alloc(&d.Th, th))) return rc;
     if ((rc = p->alloc(&d.Hh, hh))) return rc;
     if ((rc = p->alloc(&d.tab, tb))) return rc;
+    if ((rc = p->alloc(&d.Gp, gp))) return rc;
+    if ((rc = p->alloc(&d.hcls, hc))) return rc;
+    if ((rc = p->alloc(&d.cls_frames, cls_frames.size()))) return rc;
+    HIP_TRY(hipMemcpy(d.cls_frames, cls_frames.data(), sizeof(int) * cls_frames.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.frames, p->ffr.data(), sizeof(FrameFft) * E, hipMemcpyHostToDevice));
 
     // twiddles e^{-2 pi i m / L} rounded from double
     std::vector<float2> tw(tw_total);
@@ -555,13 +658,32 @@ static int build_fft(starred_plan *p)
             }
             tabh[c.tab_off + K] = make_float2((float)acc.real(), (float)acc.imag());
         }
+    HIP_TRY(hipMemcpy(d.tw, tw.data(), sizeof(float2) * tw_total, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d.tab, tabh.data(), sizeof(float2) * tb, hipMemcpyHostToDevice));
+    // the kernel-spectrum passes cover every frame (set_frames prepares both forms)
+    p->fft_ready = true;
+    return build_fft_lists(p);
+}
+
+// The FFT path's work lists for the classes that run it (cls[c].direct == 0), and
+// the direct path's for the frames of the others: rebuilt when the autotuner
+// changes a class's algorithm, its forward form or the launch shapes.
+static int build_fft_lists(starred_plan *p)
+{
+    const int E = p->E, M = p->M;
+    const std::vector<int> &fcls = p->fcls;
+    const std::vector<int> &cls_frames = p->cls_frames;
+    FftPlanDev &d = p->fd;
+    p->free_lists();
+    int rc;
+    auto is_direct = [&](int c) { return p->cls[c].direct != 0; };
     // forward spectral product items: 256 bins x a chunk of frames, longest first
-    // (every class, and for the loss the classes without the one-launch forward)
+    // (every FFT class, and for the loss the classes without the one-launch forward)
     for (int lg = 0; lg < 2; ++lg) {
         std::vector<SpecItem> sp;
         for (int c = 0; c < (int)p->cls.size(); ++c) {
             const ClassFft &cl = p->cls[c];
-            if (lg && cl.fused) continue;
+            if (is_direct(c) || (lg && cl.fused)) continue;
             const int nbins = cl.Q * (cl.Q / 2 + 1);
             const int nbb = (nbins + kFftThreads - 1) / kFftThreads;
             // enough frame chunks to give every compute unit several groups
@@ -576,17 +698,15 @@ static int build_fft(starred_plan *p)
         int &ns = lg ? d.n_spec_lg : d.n_spec;
         SpecItem *&dst = lg ? d.spec_lg : d.spec;
         ns = (int)sp.size();
-        if ((rc = p->alloc(&dst, sp.size()))) return rc;
+        if ((rc = p->alloc_list(&dst, sp.size()))) return rc;
         if (!sp.empty()) HIP_TRY(hipMemcpy(dst, sp.data(), sizeof(SpecItem) * sp.size(), hipMemcpyHostToDevice));
     }
-    if ((rc = p->alloc(&d.cls_frames, cls_frames.size()))) return rc;
-    HIP_TRY(hipMemcpy(d.cls_frames, cls_frames.data(), sizeof(int) * cls_frames.size(), hipMemcpyHostToDevice));
     // frames of the one-launch forward, largest transforms first
     {
         std::vector<int> fi;
         size_t lds = 0;
         for (int i = 0; i < E; ++i)
-            if (p->cls[fcls[i]].fused) {
+            if (!is_direct(fcls[i]) && p->cls[fcls[i]].fused) {
                 fi.push_back(i);
                 const ClassFft &cl = p->cls[fcls[i]];
                 lds = std::max(lds, fused_lds_bytes(cl.Q, cl.n, cl.P, M));
@@ -612,33 +732,29 @@ static int build_fft(starred_plan *p)
         }
         d.n_fused = (int)fu.size();
         d.fused_lds = lds;
-        if ((rc = p->alloc(&d.fused, std::max<size_t>(1, fu.size())))) return rc;
+        if ((rc = p->alloc_list(&d.fused, std::max<size_t>(1, fu.size())))) return rc;
         if (!fu.empty()) HIP_TRY(hipMemcpy(d.fused, fu.data(), sizeof(FusedItem) * fu.size(), hipMemcpyHostToDevice));
     }
     // frequency-domain adjoint: items over chunks of kAdjFrames frames x ranges of
-    // rows of the P half spectrum, about kAdjBlocks of them per launch
+    // rows of the P half spectrum, about p->adj_blocks of them per launch
     {
         std::vector<AdjItem> sp;
-        long long gp = 0, hc = 0;
-        int maxpb = 0, nchunks = 0;
-        for (const ClassFft &cl : p->cls) nchunks += (cl.ncf + kAdjFrames - 1) / kAdjFrames;
+        int maxpb = 1, nchunks = 0;
+        for (int c = 0; c < (int)p->cls.size(); ++c)
+            if (!is_direct(c)) nchunks += p->cls[c].ngch;
         for (int c = 0; c < (int)p->cls.size(); ++c) {
             ClassFft &cl = p->cls[c];
+            cl.arr = cl.nrr = 0;
+            if (is_direct(c)) continue;
             const int HP = cl.P / 2 + 1, nbins = cl.P * HP;
             const int CX = adj_lanes(HP), RG = kFftThreads / CX;
-            cl.gfch = kAdjFrames;
-            cl.ngch = (cl.ncf + kAdjFrames - 1) / kAdjFrames;
-            const int want = std::max(1, (kAdjBlocks + nchunks - 1) / std::max(1, nchunks));
+            const int want = std::max(1, (p->adj_blocks + nchunks - 1) / std::max(1, nchunks));
             int arr = (cl.P + want - 1) / want;
             // at least kAdjMinRows rows per thread; a multiple of the row groups
             arr = std::max(kAdjMinRows * RG, ((arr + RG - 1) / RG) * RG);
             arr = std::min(arr, kAdjMaxRows);  // RG divides kAdjMaxRows
             cl.arr = arr;
             cl.nrr = (cl.P + arr - 1) / arr;
-            cl.gp_off = gp;
-            gp += (long long)cl.ngch * nbins;
-            cl.hc_off = hc;
-            hc += (long long)cl.F * cl.F;
             maxpb = std::max(maxpb, cl.nrr);
             for (int f0 = 0; f0 < cl.ncf; f0 += kAdjFrames)
                 for (int r = 0; r < cl.nrr; ++r) {
@@ -664,35 +780,36 @@ static int build_fft(starred_plan *p)
         std::stable_sort(sp.begin(), sp.end(), [&](const AdjItem &a, const AdjItem &b) {
             return p->cls[a.cls].P > p->cls[b.cls].P;
         });
-        d.n_frames = E;
         d.n_aspec = (int)sp.size();
         d.maxpb = maxpb;
         d.total_bins = 0;
-        for (const ClassFft &cl : p->cls) d.total_bins += (long long)cl.P * (cl.P / 2 + 1);
-        if ((rc = p->alloc(&d.aspec, sp.size()))) return rc;
-        if ((rc = p->alloc(&d.apart, (size_t)E * maxpb * (1 + 3 * M)))) return rc;
-        if ((rc = p->alloc(&d.Gp, gp))) return rc;
-        if ((rc = p->alloc(&d.hcls, hc))) return rc;
+        for (int c = 0; c < (int)p->cls.size(); ++c)
+            if (!is_direct(c)) d.total_bins += (long long)p->cls[c].P * (p->cls[c].P / 2 + 1);
+        if ((rc = p->alloc_list(&d.aspec, std::max<size_t>(1, sp.size())))) return rc;
+        if ((rc = p->alloc_list(&d.apart, (size_t)E * maxpb * (1 + 3 * M) + 1))) return rc;
         if (!sp.empty()) HIP_TRY(hipMemcpy(d.aspec, sp.data(), sizeof(AdjItem) * sp.size(), hipMemcpyHostToDevice));
     }
     HIP_TRY(hipMemcpy(d.classes, p->cls.data(), sizeof(ClassFft) * p->cls.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d.frames, p->ffr.data(), sizeof(FrameFft) * E, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d.tw, tw.data(), sizeof(float2) * tw_total, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d.tab, tabh.data(), sizeof(float2) * tb, hipMemcpyHostToDevice));
 
     // line passes: groups of lines of one frame (or class), longest transforms first
     std::vector<LineItem> last_items;
-    auto make_pass = [&](LinePass &lp, bool per_class, auto lines_of, auto len_of, bool skip_fused = false) -> int {
+    // all: every frame, whatever its class runs (the kernel-spectrum passes of set_frames)
+    auto make_pass = [&](LinePass &lp, bool per_class, auto lines_of, auto len_of, bool skip_fused = false,
+                         bool all = false) -> int {
         struct G { int L; LineItem it; };
         std::vector<G> g;
         const int nunits = per_class ? (int)p->cls.size() : E;
-        auto skip = [&](int u) { return skip_fused && !per_class && p->cls[fcls[u]].fused; };
+        auto skip = [&](int u) {
+            const int c = per_class ? u : fcls[u];
+            if (all) return false;
+            return is_direct(c) || (skip_fused && !per_class && p->cls[c].fused);
+        };
         long long total_lines = 0;
         for (int u = 0; u < nunits; ++u)
             if (!skip(u)) total_lines += lines_of(p->cls[per_class ? u : fcls[u]]);
         // lines per work group: about kFftTargetElems elements, fewer when the
         // pass is small so that every compute unit gets work
-        const long long want_groups = 1024;
+        const long long want_groups = p->line_groups;
         const int cap = (int)std::max(1LL, total_lines / want_groups);
         int maxL = 1;
         for (int u = 0; u < nunits; ++u) {
@@ -712,7 +829,7 @@ static int build_fft(starred_plan *p)
         last_items = items;
         lp.n_items = (int)items.size();
         lp.lds_bytes = (size_t)2 * maxL * sizeof(float2);
-        int rc2 = p->alloc(&lp.items, items.size());
+        int rc2 = p->alloc_list(&lp.items, std::max<size_t>(1, items.size()));
         if (rc2) return rc2;
         if (!items.empty()) {
             hipError_t e = hipMemcpy(lp.items, items.data(), sizeof(LineItem) * items.size(), hipMemcpyHostToDevice);
@@ -724,8 +841,8 @@ static int build_fft(starred_plan *p)
     auto LQ = [](const ClassFft &c) { return c.Q; };
     if ((rc = make_pass(d.hrows, true, [](const ClassFft &c) { return c.F; }, LP))) return rc;
     if ((rc = make_pass(d.hcols, true, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
-    if ((rc = make_pass(d.krows, false, [](const ClassFft &c) { return c.P; }, LP))) return rc;
-    if ((rc = make_pass(d.kcols, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
+    if ((rc = make_pass(d.krows, false, [](const ClassFft &c) { return c.P; }, LP, false, true))) return rc;
+    if ((rc = make_pass(d.kcols, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP, false, true))) return rc;
     if ((rc = make_pass(d.fcols, false, [](const ClassFft &c) { return c.Q / 2 + 1; }, LQ))) return rc;
     if ((rc = make_pass(d.frows, false, [](const ClassFft &c) { return c.n; }, LQ))) return rc;
     if ((rc = make_pass(d.rrows, false, [](const ClassFft &c) { return c.n; }, LQ))) return rc;
@@ -742,9 +859,9 @@ static int build_fft(starred_plan *p)
         item.resize(last_items.size());
         std::vector<int> fill(off.begin(), off.end() - 1);
         for (int q = 0; q < (int)last_items.size(); ++q) item[fill[last_items[q].frame]++] = q;
-        if ((rc = p->alloc(&d.gpart, std::max<size_t>(1, last_items.size())))) return rc;
-        if ((rc = p->alloc(&d.gcsr_off, E + 1))) return rc;
-        if ((rc = p->alloc(&d.gcsr_item, std::max<size_t>(1, item.size())))) return rc;
+        if ((rc = p->alloc_list(&d.gpart, std::max<size_t>(1, last_items.size())))) return rc;
+        if ((rc = p->alloc_list(&d.gcsr_off, E + 1))) return rc;
+        if ((rc = p->alloc_list(&d.gcsr_item, std::max<size_t>(1, item.size())))) return rc;
         HIP_TRY(hipMemcpy(d.gcsr_off, off.data(), sizeof(int) * (E + 1), hipMemcpyHostToDevice));
         if (!item.empty()) HIP_TRY(hipMemcpy(d.gcsr_item, item.data(), sizeof(int) * item.size(), hipMemcpyHostToDevice));
     }
@@ -752,9 +869,12 @@ static int build_fft(starred_plan *p)
     if ((rc = make_pass(d.scols, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
     if ((rc = make_pass(d.gcols, true, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
     if ((rc = make_pass(d.grows, true, [](const ClassFft &c) { return c.F; }, LP))) return rc;
-    if ((rc = p->alloc(&p->d_part_chi_fft, std::max(1, std::max(d.frows.n_items, d.frows_lg.n_items + d.n_fused)))))
-        return rc;
-    p->fft_ready = true;
+    // the direct path's lists for the frames of the direct classes
+    if ((rc = build_direct_lists(p))) return rc;
+    // chi-square partials: the FFT line-pass row groups (or, with the one-launch
+    // forward, its row groups and then one per fused frame), then the direct tiles
+    p->n_fft_chi = std::max(d.frows.n_items, d.frows_lg.n_items + d.n_fused);
+    if ((rc = p->alloc_list(&p->d_part_chi_fft, (size_t)p->n_fft_chi + p->fwd_items.size() + 1))) return rc;
     return STARRED_OK;
 }
 
@@ -791,6 +911,38 @@ static int build_psf(starred_plan *p)
 static int loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out, int *tick = nullptr,
                           const AdamDev *adam = nullptr);
 static int autotune(starred_plan *p);
+
+// Per-class algorithm choices: the direct algorithm, the FFT algorithm with the
+// one-launch forward (where it fits), the FFT algorithm with the line passes.
+enum { kChDirect = 0, kChFused = 1, kChLines = 2 };
+
+// Whether the direct kernels' LDS tiles hold the frames of class c.
+static bool class_direct_ok(const starred_plan *p, int c)
+{
+    const FrameDev &f = p->fr[p->cls_frames[p->cls[c].cf_off]];
+    return fwd_lds_bytes(p->s, f.Tpad) <= kMaxLds && adj_lds_bytes(f.Ar, f.Bpad) <= kMaxLds;
+}
+
+static int class_choice(const starred_plan *p, int c)
+{
+    const ClassFft &cl = p->cls[c];
+    return cl.direct ? kChDirect : (cl.fused ? kChFused : kChLines);
+}
+
+// Set every class's algorithm and forward form, then rebuild the work lists.
+static int apply_choices(starred_plan *p, const std::vector<int> &ch)
+{
+    bool any_fft = false;
+    for (int c = 0; c < (int)p->cls.size(); ++c) {
+        ClassFft &cl = p->cls[c];
+        cl.direct = ch[c] == kChDirect ? 1 : 0;
+        cl.fused = (ch[c] == kChFused && p->cls_fits[c]) ? 1 : 0;
+        any_fft = any_fft || !cl.direct;
+    }
+    p->algo = any_fft ? STARRED_CONV_FFT : STARRED_CONV_DIRECT;
+    p->drop_graphs();
+    return build_fft_lists(p);
+}
 
 int starred_plan_create(const starred_desc *desc, void *stream, starred_plan **plan_out)
 {
@@ -837,20 +989,25 @@ int starred_plan_create(const starred_desc *desc, void *stream, starred_plan **p
         return STARRED_OK;
     }
     p->algo_req = desc->conv_algo;
-    p->algo = (desc->conv_algo == STARRED_CONV_FFT) ? STARRED_CONV_FFT : STARRED_CONV_DIRECT;
+    p->algo = STARRED_CONV_FFT;  // every class on the FFT algorithm until told or tuned otherwise
     rc = build_deconv(p);
     if (!rc) rc = build_fft(p);
     if (rc) {
         delete p;
         return rc;
     }
-    p->direct_ok = fwd_lds_bytes(p->s, p->Tmax) <= kMaxLds && adj_lds_bytes(p->Ar_max, p->Bpad_max) <= kMaxLds;
-    if (p->algo == STARRED_CONV_DIRECT && !p->direct_ok) {
-        if (p->algo_req == STARRED_CONV_DIRECT) {
+    p->direct_ok = true;
+    for (int c = 0; c < (int)p->cls.size(); ++c) p->direct_ok = p->direct_ok && class_direct_ok(p, c);
+    if (p->algo_req == STARRED_CONV_DIRECT) {
+        if (!p->direct_ok) {
             delete p;
             return fail(STARRED_EUNSUPPORTED, "kernels too large for the direct path's LDS tiles");
         }
-        p->algo = STARRED_CONV_FFT;
+        rc = apply_choices(p, std::vector<int>(p->cls.size(), kChDirect));
+        if (rc) {
+            delete p;
+            return rc;
+        }
     }
     *plan_out = p;
     return STARRED_OK;
@@ -891,10 +1048,61 @@ int starred_get_class_info(const starred_plan *p, int32_t c, starred_class_info 
     out->n = cl.n;
     out->K = cl.K;
     out->n_frames = cl.ncf;
-    out->algo = p->algo;
+    out->algo = cl.direct ? STARRED_CONV_DIRECT : STARRED_CONV_FFT;
     out->P = cl.P;
     out->Q = cl.Q;
-    out->fused = (p->algo == STARRED_CONV_FFT && p->fft_fused) ? cl.fused : 0;
+    out->fused = (!cl.direct && p->fft_fused) ? cl.fused : 0;
+    for (int k = 0; k < 3; ++k) out->tune_ms[k] = c < (int)p->cls_tune.size() ? p->cls_tune[c][k] : -1.0;
+    return STARRED_OK;
+}
+
+int starred_autotune_info(const starred_plan *p, double *wall_ms_out, int32_t *cached_out, int32_t *adj_blocks_out,
+                          int32_t *line_groups_out)
+{
+    if (!p) return fail(STARRED_EINVAL, "plan is NULL");
+    if (wall_ms_out) *wall_ms_out = p->tune_wall_ms;
+    if (cached_out) *cached_out = p->tune_cached;
+    if (adj_blocks_out) *adj_blocks_out = p->adj_blocks;
+    if (line_groups_out) *line_groups_out = p->line_groups;
+    return STARRED_OK;
+}
+
+int starred_set_class_algo(starred_plan *p, int32_t c, int32_t algo, int32_t fused)
+{
+    if (!p) return fail(STARRED_EINVAL, "plan is NULL");
+    if (p->mode != STARRED_DECONV || c < 0 || c >= (int)p->cls.size()) return fail(STARRED_EINVAL, "no such class");
+    if (algo != STARRED_CONV_DIRECT && algo != STARRED_CONV_FFT) return fail(STARRED_EINVAL, "algo must be DIRECT or FFT");
+    if (algo == STARRED_CONV_DIRECT && !class_direct_ok(p, c))
+        return fail(STARRED_EUNSUPPORTED, "kernels of this class too large for the direct path's LDS tiles");
+    if (algo == STARRED_CONV_FFT && p->xf)
+        return fail(STARRED_EUNSUPPORTED, "frames with per-frame transforms run the direct algorithm");
+    std::vector<int> ch(p->cls.size());
+    for (int k = 0; k < (int)p->cls.size(); ++k) ch[k] = class_choice(p, k);
+    ch[c] = algo == STARRED_CONV_DIRECT ? kChDirect : (fused && p->cls_fits[c] ? kChFused : kChLines);
+    return apply_choices(p, ch);
+}
+
+int starred_set_frame_transforms(starred_plan *p, const float *xf, float *grad_xf)
+{
+    if (!p) return fail(STARRED_EINVAL, "plan is NULL");
+    if (p->mode != STARRED_DECONV) return fail(STARRED_EUNSUPPORTED, "per-frame transforms need deconvolution mode");
+    if (!xf && grad_xf) return fail(STARRED_EINVAL, "grad_xf without transforms");
+    if (xf && !p->direct_ok)
+        return fail(STARRED_EUNSUPPORTED, "per-frame transforms run the direct algorithm, whose tiles these kernels exceed");
+    p->drop_graphs();
+    if (xf && !p->xf) {
+        // every class onto the direct algorithm (the FFT path assumes untransformed windows)
+        p->xf_prev_choice.resize(p->cls.size());
+        for (int c = 0; c < (int)p->cls.size(); ++c) p->xf_prev_choice[c] = class_choice(p, c);
+        int rc = apply_choices(p, std::vector<int>(p->cls.size(), kChDirect));
+        if (rc) return rc;
+    } else if (!xf && p->xf && !p->xf_prev_choice.empty()) {
+        p->xf = nullptr;
+        p->gxf = nullptr;
+        return apply_choices(p, p->xf_prev_choice);
+    }
+    p->xf = xf;
+    p->gxf = xf ? grad_xf : nullptr;
     return STARRED_OK;
 }
 
@@ -922,7 +1130,7 @@ int starred_set_frames(starred_plan *p, const float *data, const float *inv_var,
     if (p->fft_ready) HIP_TRY(fft_prep_kernels(p->st, p->fd, psf, p->s));
     HIP_TRY(hipStreamSynchronize(p->st));
     p->frames_set = true;
-    if (p->algo_req == STARRED_CONV_AUTO && p->direct_ok) return autotune(p);
+    if (p->algo_req == STARRED_CONV_AUTO && !p->xf) return autotune(p);
     return STARRED_OK;
 }
 
@@ -933,7 +1141,7 @@ int starred_render_scene(starred_plan *p, const float *params, float *scene)
         HIP_TRY(launch_psf_render(p->st, p->N, params, scene));
         return STARRED_OK;
     }
-    HIP_TRY(launch_render(p->st, p->d_fr, p->E, p->Fmax, p->N, p->M, p->sigma, params, scene));
+    HIP_TRY(launch_render(p->st, p->d_fr, p->E, p->Fmax, p->N, p->M, p->sigma, params, scene, nullptr, 0, p->xf));
     return STARRED_OK;
 }
 
@@ -942,12 +1150,10 @@ int starred_convolve_subsample(starred_plan *p, const float *scene, float *model
     if (!p || !scene || !model) return fail(STARRED_EINVAL, "NULL argument");
     if (p->mode == STARRED_PSF) return fail(STARRED_EUNSUPPORTED, "deconvolution-mode operator called on a PSF-mode plan");
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
-    if (p->algo == STARRED_CONV_FFT) {
-        HIP_TRY(fft_scene_model(p->st, p->fd, scene, p->s, model));
-        return STARRED_OK;
-    }
-    HIP_TRY(launch_fwd_direct(p->st, p->s, p->d_fr, p->d_fwd_items, (int)p->fwd_items.size(), p->Tmax,
-                              scene, p->d_kf, nullptr, nullptr, model, nullptr));
+    // frames of FFT classes by the transforms, frames of direct classes by the direct kernel
+    if (p->algo == STARRED_CONV_FFT) HIP_TRY(fft_scene_model(p->st, p->fd, scene, p->s, model));
+    HIP_TRY(launch_fwd_direct(p->st, p->s, p->d_fr, p->d_fwd_items, (int)p->fwd_items.size(), p->Tdir,
+                              scene, p->d_kf, nullptr, nullptr, model, nullptr, p->fwd_groups));
     return STARRED_OK;
 }
 
@@ -959,10 +1165,9 @@ int starred_convolve_subsample_adj(starred_plan *p, const float *resid, float *g
     if (p->algo == STARRED_CONV_FFT) {
         HIP_TRY(fft_resid_rows(p->st, p->fd, resid));
         HIP_TRY(fft_adjoint(p->st, p->fd, grad_scene));
-        return STARRED_OK;
     }
-    HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ar_max,
-                              p->Bpad_max, resid, p->d_ka, grad_scene));
+    HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ardir,
+                              p->Bpdir, resid, p->d_ka, grad_scene, p->adj_groups));
     return STARRED_OK;
 }
 
@@ -1055,15 +1260,18 @@ static int starlet_branch(starred_plan *p, const float *img, bool want_grad, int
 static int loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out, int *tick,
                           const AdamDev *adam)
 {
+    // fft: some class runs the FFT algorithm; dir: some frames run the direct one
+    // (both in one evaluation when the classes differ)
     const bool fft = (p->algo == STARRED_CONV_FFT);
+    const bool dir = !p->fdir.empty();
     hipEvent_t e0;
-    int n_chi;
-    const double *part_chi;
+    int n_chi = 0;
+    const double *part_chi = p->d_part_chi_fft;
     int n_l1 = 0;
     const bool fused = fft && p->fft_fused && p->fd.n_fused > 0;
     // one class covering the whole grid: the row inverse of dL/dh carries the final
     // reductions and the update (one launch fewer)
-    const bool fin_rows = fft && grad && p->fd.n_classes == 1 && p->cls[0].F == p->N;
+    const bool fin_rows = fft && !dir && grad && p->fd.n_classes == 1 && p->cls[0].F == p->N;
     // The starlet prior depends on h only. With the composite filters, the
     // one-launch forward and (for the gradient) the row inverse above, its passes
     // ride in the step's own launches as extra work groups (A: the h-row launch,
@@ -1125,17 +1333,22 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         p->prof_stop(STARRED_STAGE_FFT_MROWS, e1);
         p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
         n_chi = n_rows + (fused ? p->fd.n_fused : 0);
-        part_chi = p->d_part_chi_fft;
-    } else {
+    }
+    if (dir) {
+        // the direct classes' frames: their chi-square partials follow the FFT ones
+        const bool all = !fft;
         e0 = p->prof_start();
-        HIP_TRY(launch_render(p->st, p->d_fr, p->E, p->Fmax, p->N, p->M, p->sigma, params, p->d_scene));
+        HIP_TRY(launch_render(p->st, p->d_fr, p->E, p->Fdir, p->N, p->M, p->sigma, params, p->d_scene,
+                              all ? nullptr : p->d_fdir, (int)p->fdir.size(), p->xf));
         p->prof_stop(STARRED_STAGE_RENDER, e0);
         e0 = p->prof_start();
-        HIP_TRY(launch_fwd_direct(p->st, p->s, p->d_fr, p->d_fwd_items, (int)p->fwd_items.size(), p->Tmax,
-                                  p->d_scene, p->d_kf, p->data, p->invvar, p->d_rho, p->d_part_chi));
-        p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
-        n_chi = (int)p->fwd_items.size();
-        part_chi = p->d_part_chi;
+        hipEvent_t e1 = p->prof_start();
+        HIP_TRY(launch_fwd_direct(p->st, p->s, p->d_fr, p->d_fwd_items, (int)p->fwd_items.size(), p->Tdir,
+                                  p->d_scene, p->d_kf, p->data, p->invvar, p->d_rho, p->d_part_chi_fft + n_chi,
+                                  p->fwd_groups));
+        p->prof_stop(STARRED_STAGE_DIRECT_FWD, e1);
+        if (!fft) p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
+        n_chi += (int)p->fwd_items.size();
     }
     if (grad) {
         e0 = p->prof_start();
@@ -1156,14 +1369,18 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
             HIP_TRY(fin_rows ? fft_grad_h_cols(p->st, p->fd, ride ? &pd : nullptr)
                              : fft_grad_h_inverse(p->st, p->fd, ride ? &pd : nullptr));
             p->prof_stop(STARRED_STAGE_FFT_AROWS, e1);
-
-        } else
-            HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ar_max,
-                                      p->Bpad_max, p->d_rho, p->d_ka, p->d_g));
+        }
+        if (dir) {
+            hipEvent_t e1 = p->prof_start();
+            HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ardir,
+                                      p->Bpdir, p->d_rho, p->d_ka, p->d_g, p->adj_groups));
+            p->prof_stop(STARRED_STAGE_DIRECT_ADJ, e1);
+        }
         p->prof_stop(STARRED_STAGE_CONV_ADJ, e0);
-        if (!fft) {
+        if (dir) {
             e0 = p->prof_start();
-            HIP_TRY(launch_frame_sums(p->st, p->d_fr, p->E, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum, true));
+            HIP_TRY(launch_frame_sums(p->st, p->d_fr, p->E, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum, true,
+                                      fft ? p->d_fdir : nullptr, (int)p->fdir.size(), p->xf, p->gxf));
             p->prof_stop(STARRED_STAGE_GRAD_SUMS, e0);
         }
     }
@@ -1189,23 +1406,91 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         p->prof_stop(STARRED_STAGE_FINALIZE, e0);
         return STARRED_OK;
     }
-    // FFT path: dL/dh from the classes' window contributions in the same launch
-    if (grad && !fft)
-        HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, grad, p->d_hpart));
+    // dL/dh: the prior gradient plus the direct frames' windows (directly into grad
+    // when every frame is direct; else into d_hdir, which the final launch adds to
+    // the FFT classes' windows, pixel by pixel in the same launch as the update)
+    if (grad && dir)
+        HIP_TRY(launch_finalize_h(p->st, p->d_fr, p->E, p->N, p->d_g, p->d_prior, fft ? p->d_hdir : grad,
+                                  p->d_hpart, fft ? p->d_fdir : nullptr, (int)p->fdir.size(), p->xf));
     HIP_TRY(launch_finalize_small(p->st, p->E, p->M, n_chi, part_chi, n_l1, p->d_part_l1, p->lam, p->d_fsum,
                                   params, p->N, grad, loss_out, nullptr, nullptr, nullptr,
                                   (fft && adam) ? nullptr : tick, fft ? p->fd.classes : nullptr, p->fd.n_classes,
-                                  p->fd.hcls, p->d_prior, (fft && adam) ? *adam : AdamDev(),
+                                  p->fd.hcls, (fft && dir) ? p->d_hdir : p->d_prior,
+                                  (fft && adam) ? *adam : AdamDev(),
                                   (p->lam_pts != 0.0 && grad) ? p->d_pts : nullptr));
     p->prof_stop(STARRED_STAGE_FINALIZE, e0);
     return STARRED_OK;
 }
 
-// Autotuner: time the direct and the FFT algorithms on this plan's shapes
-// (one warm-up and three timed loss+gradient evaluations each, at h = 0) and
-// keep the faster one.
+// ---- autotuner ----
+// Per-class algorithm and forward form, then the FFT path's launch shapes, chosen
+// by timing whole loss+gradient evaluations (one warm-up, kTuneReps timed) on the
+// plan's stream at h = 0 with the bound data. Coordinate descent over the classes,
+// most costly first; a change is kept when it saves more than 2 %.
+constexpr int kTuneReps = 4;
+constexpr double kTuneGain = 0.98;
+
+struct TuneEntry {
+    std::vector<int> choice;
+    int adj_blocks = kAdjBlocks, line_groups = 1024;
+    std::vector<std::array<double, 3>> tried;  // the timings the decision came from
+    double wall_ms = 0.0;                      // how long that tuning took
+};
+
+static std::mutex g_tune_mu;
+static std::map<std::string, TuneEntry> g_tune_cache;
+
+// The plan's shapes and the device: what the timings depend on.
+static std::string tune_key(const starred_plan *p)
+{
+    std::map<std::pair<int, int>, int> cnt;
+    for (int i = 0; i < p->E; ++i) cnt[{p->n[i], p->K[i]}]++;
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    std::string k = "s" + std::to_string(p->s) + " N" + std::to_string(p->N) + " M" + std::to_string(p->M) + " J" +
+                    std::to_string(p->J) + " w" + std::to_string(p->w_stride) + " cu" + std::to_string(cus) + ":";
+    for (auto &kv : cnt)
+        k += " " + std::to_string(kv.first.first) + "/" + std::to_string(kv.first.second) + "x" +
+             std::to_string(kv.second);
+    return k;
+}
+
+static int time_plan(starred_plan *p, const float *params, double *loss, hipEvent_t a, hipEvent_t b, double *ms)
+{
+    int rc = loss_grad_impl(p, params, p->d_grad, loss);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(a, p->st));
+    for (int r = 0; r < kTuneReps && !rc; ++r) rc = loss_grad_impl(p, params, p->d_grad, loss);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(b, p->st));
+    HIP_TRY(hipEventSynchronize(b));
+    float f = 0.f;
+    HIP_TRY(hipEventElapsedTime(&f, a, b));
+    *ms = (double)f / kTuneReps;
+    return STARRED_OK;
+}
+
 static int autotune(starred_plan *p)
 {
+    const auto t_start = std::chrono::steady_clock::now();
+    const int C = (int)p->cls.size();
+    p->cls_tune.assign(C, {-1.0, -1.0, -1.0});
+    const std::string key = tune_key(p);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            p->adj_blocks = it->second.adj_blocks;
+            p->line_groups = it->second.line_groups;
+            p->tune_cached = 1;
+            p->cls_tune = it->second.tried;
+            p->tune_wall_ms = it->second.wall_ms;
+            const std::vector<int> ch = it->second.choice;
+            return apply_choices(p, ch);
+        }
+    }
+    p->tune_cached = 0;
     float *params = nullptr;
     double *loss = nullptr;
     int rc = dev_alloc(&params, p->nparams);
@@ -1215,37 +1500,89 @@ static int autotune(starred_plan *p)
         (void)hipFree(params);
         return rc;
     }
-    (void)hipMemsetAsync(params, 0, sizeof(float) * p->nparams, p->st);
     const bool prof = p->prof_on;
     p->prof_on = false;
     hipEvent_t a = nullptr, b = nullptr;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
-    double best = 1e300;
-    int best_algo = STARRED_CONV_DIRECT;
-    const int algos[2] = {STARRED_CONV_DIRECT, STARRED_CONV_FFT};
-    for (int ai = 0; ai < 2 && !rc; ++ai) {
-        p->algo = algos[ai];
-        rc = loss_grad_impl(p, params, p->d_grad, loss);
+    // h = 0 (a fill kernel: the tuning's launches may be the first on this stream)
+    if (launch_fill(p->st, params, p->nparams, 0.f) != hipSuccess) rc = fail(STARRED_EHIP, "autotune fill");
+    // start: every class on the FFT algorithm, the one-launch forward where it fits
+    std::vector<int> ch(C);
+    for (int c = 0; c < C; ++c) ch[c] = p->cls_fits[c] ? kChFused : kChLines;
+    double best = 0.0;
+    if (!rc) rc = apply_choices(p, ch);
+    if (!rc) rc = time_plan(p, params, loss, a, b, &best);
+    for (int c = 0; c < C && !rc; ++c) p->cls_tune[c][ch[c]] = best;
+    // classes in order of FFT cost: frames x P^2
+    std::vector<int> order(C);
+    for (int c = 0; c < C; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return (double)p->cls[x].ncf * p->cls[x].P * p->cls[x].P > (double)p->cls[y].ncf * p->cls[y].P * p->cls[y].P;
+    });
+    for (int c : order) {
         if (rc) break;
-        (void)hipEventRecord(a, p->st);
-        for (int r = 0; r < 3 && !rc; ++r) rc = loss_grad_impl(p, params, p->d_grad, loss);
-        (void)hipEventRecord(b, p->st);
-        if (hipEventSynchronize(b) != hipSuccess) rc = fail(STARRED_EHIP, "autotune synchronisation");
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, a, b);
-        p->tune_ms[algos[ai]] = ms / 3.0;
-        if (ms < best) {
-            best = ms;
-            best_algo = algos[ai];
+        for (int alt : {kChDirect, kChFused, kChLines}) {
+            if (alt == ch[c]) continue;
+            if (alt == kChDirect && !class_direct_ok(p, c)) continue;
+            if (alt == kChFused && !p->cls_fits[c]) continue;
+            std::vector<int> t = ch;
+            t[c] = alt;
+            double ms = 0.0;
+            rc = apply_choices(p, t);
+            if (!rc) rc = time_plan(p, params, loss, a, b, &ms);
+            if (rc) break;
+            p->cls_tune[c][alt] = ms;
+            if (ms < kTuneGain * best) {
+                best = ms;
+                ch = t;
+            }
         }
+        if (!rc) p->cls_tune[c][ch[c]] = best;
     }
-    p->algo = best_algo;
+    if (!rc) rc = apply_choices(p, ch);
+    // launch shapes of the FFT path
+    if (!rc && p->algo == STARRED_CONV_FFT) {
+        for (int which = 0; which < 2 && !rc; ++which) {
+            int &knob = which == 0 ? p->adj_blocks : p->line_groups;
+            const int keep = knob;
+            int best_v = keep;
+            const std::vector<int> cands = which == 0 ? std::vector<int>{256, 512, 1024, 2048}
+                                                      : std::vector<int>{512, 1024, 2048};
+            for (int v : cands) {
+                if (v == keep) continue;
+                knob = v;
+                double ms = 0.0;
+                rc = build_fft_lists(p);
+                if (!rc) rc = time_plan(p, params, loss, a, b, &ms);
+                if (rc) break;
+                if (ms < kTuneGain * best) {
+                    best = ms;
+                    best_v = v;
+                }
+            }
+            knob = best_v;
+        }
+        if (!rc) rc = build_fft_lists(p);
+    }
+    p->drop_graphs();
     p->prof_on = prof;
+    (void)hipStreamSynchronize(p->st);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     (void)hipFree(params);
     (void)hipFree(loss);
+    p->tune_wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (!rc) {
+        TuneEntry e;
+        e.choice = ch;
+        e.adj_blocks = p->adj_blocks;
+        e.line_groups = p->line_groups;
+        e.tried = p->cls_tune;
+        e.wall_ms = p->tune_wall_ms;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = e;
+    }
     return rc;
 }
 
@@ -1360,6 +1697,7 @@ static int build_plain(starred_plan *p)
 
 int starred_loss_grad_plain(starred_plan *p, const float *params, float *grad, double *loss_out)
 {
+    if (p && p->xf) return fail(STARRED_EUNSUPPORTED, "the plain baseline has no per-frame transforms");
     if (!p || !params || !loss_out) return fail(STARRED_EINVAL, "NULL argument");
     if (p->mode != STARRED_DECONV) return fail(STARRED_EUNSUPPORTED, "the plain baseline is a deconvolution-mode path");
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
@@ -1922,23 +2260,29 @@ int starred_time_stage(starred_plan *p, const float *params, int32_t stage, int3
             if (!fft) break;
             HIP_TRY(fft_grad_h_inverse(p->st, p->fd));
             return STARRED_OK;
+        // the direct stages over the frames of the direct classes
         case STARRED_STAGE_RENDER:
-            if (fft) break;
-            HIP_TRY(launch_render(p->st, p->d_fr, p->E, p->Fmax, p->N, p->M, p->sigma, params, p->d_scene));
+            if (p->fdir.empty()) break;
+            HIP_TRY(launch_render(p->st, p->d_fr, p->E, p->Fdir, p->N, p->M, p->sigma, params, p->d_scene,
+                                  p->d_fdir, (int)p->fdir.size(), p->xf));
             return STARRED_OK;
         case STARRED_STAGE_CONV_FWD:
-            if (fft) break;
-            HIP_TRY(launch_fwd_direct(p->st, p->s, p->d_fr, p->d_fwd_items, (int)p->fwd_items.size(), p->Tmax,
-                                      p->d_scene, p->d_kf, p->data, p->invvar, p->d_rho, p->d_part_chi));
+        case STARRED_STAGE_DIRECT_FWD:
+            if (p->fdir.empty()) break;
+            HIP_TRY(launch_fwd_direct(p->st, p->s, p->d_fr, p->d_fwd_items, (int)p->fwd_items.size(), p->Tdir,
+                                      p->d_scene, p->d_kf, p->data, p->invvar, p->d_rho, p->d_part_chi_fft,
+                                      p->fwd_groups));
             return STARRED_OK;
         case STARRED_STAGE_CONV_ADJ:
-            if (fft) break;
-            HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ar_max,
-                                      p->Bpad_max, p->d_rho, p->d_ka, p->d_g));
+        case STARRED_STAGE_DIRECT_ADJ:
+            if (p->fdir.empty()) break;
+            HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ardir,
+                                      p->Bpdir, p->d_rho, p->d_ka, p->d_g, p->adj_groups));
             return STARRED_OK;
         case STARRED_STAGE_GRAD_SUMS:
-            if (fft) break;
-            HIP_TRY(launch_frame_sums(p->st, p->d_fr, p->E, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum, true));
+            if (p->fdir.empty()) break;
+            HIP_TRY(launch_frame_sums(p->st, p->d_fr, p->E, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum, true,
+                                      p->d_fdir, (int)p->fdir.size(), p->xf, p->gxf));
             return STARRED_OK;
         default:
             break;

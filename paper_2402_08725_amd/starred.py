@@ -29,13 +29,13 @@ EXPORTED = [
 ]
 STAGES = ["render", "conv_fwd", "conv_adj", "grad_sums", "starlet", "finalize", "adam", "spectra",
           "graph", "fft_spec", "fft_mcols", "fft_mrows", "fft_rcols", "fft_acols", "fft_arows",
-          "fft_fsum", "fft_fused"]
+          "fft_fsum", "fft_fused", "direct_fwd", "direct_adj"]
 
 
 class ClassInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("K", ctypes.c_int32), ("n_frames", ctypes.c_int32),
                 ("algo", ctypes.c_int32), ("P", ctypes.c_int32), ("Q", ctypes.c_int32),
-                ("fused", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("fused", ctypes.c_int32), ("pad", ctypes.c_int32), ("tune_ms", ctypes.c_double * 3)]
 
 
 class Desc(ctypes.Structure):
@@ -90,6 +90,10 @@ def lib():
         L.starred_conv_algo.argtypes = [vp]
         L.starred_num_classes.argtypes = [vp]
         L.starred_get_class_info.argtypes = [vp, i32, ctypes.POINTER(ClassInfo)]
+        L.starred_autotune_info.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32),
+                                            ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.starred_set_class_algo.argtypes = [vp, i32, i32, i32]
+        L.starred_set_frame_transforms.argtypes = [vp, vp, vp]
         L.starred_last_error.restype = ctypes.c_char_p
         L.starred_set_profiling.argtypes = [vp, i32]
         L.starred_profile_read.argtypes = [vp, vp, vp]
@@ -213,8 +217,36 @@ class Plan:
         for c in range(nc):
             ci = ClassInfo()
             _check(lib().starred_get_class_info(self._h, c, ctypes.byref(ci)))
-            out.append({k: getattr(ci, k) for k, _ in ClassInfo._fields_ if k != "pad"})
+            d = {k: getattr(ci, k) for k, _ in ClassInfo._fields_ if k not in ("pad", "tune_ms")}
+            d["tune_ms"] = [float(v) for v in ci.tune_ms]
+            out.append(d)
         return out
+
+    def autotune_info(self):
+        """Host ms of the last autotuning, whether it came from the cache, launch shapes."""
+        ms, cached = ctypes.c_double(0.0), ctypes.c_int32(0)
+        ab, lg = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().starred_autotune_info(self._h, ctypes.byref(ms), ctypes.byref(cached), ctypes.byref(ab),
+                                           ctypes.byref(lg)))
+        return {"wall_ms": ms.value, "cached": bool(cached.value), "adj_blocks": ab.value,
+                "line_groups": lg.value}
+
+    def set_frame_transforms(self, xf, grad_out=None):
+        """Per-frame (dx, dy, theta) transforms (E x 3), or None to clear them; grad_out
+        (float32 device tensor of E x 3) receives dL/d(dx, dy, theta) in loss_grad."""
+        if xf is None:
+            self._xf = None
+            self._call(lib().starred_set_frame_transforms, None, None)
+            return None
+        t = _f32(xf, self.device)
+        g = grad_out if grad_out is not None else torch.zeros(3 * self.E, dtype=torch.float32, device=self.device)
+        self._call(lib().starred_set_frame_transforms, _ptr(t), _ptr(g))
+        self._xf = (t, g)  # referenced by the plan
+        return g
+
+    def set_class_algo(self, c, algo, fused=True):
+        """Force shape class c onto CONV_DIRECT or CONV_FFT (one-launch forward if fused)."""
+        _check(lib().starred_set_class_algo(self._h, int(c), int(algo), 1 if fused else 0))
 
     def fused_classes(self):
         """(n, K) of the classes whose forward is the one-launch form."""

@@ -1051,3 +1051,167 @@ def test_pipeline_psf_fits_then_joint_deconvolution():
          f"point amplitudes rel diff median {np.median(rel):.3e} max {rel.max():.3e}")
     assert lf[0] <= 5.0 * lt[0]
     assert np.median(rel) <= 0.15
+
+
+# --------------------------------------------------------------------------- #
+# Shape classes on different algorithms in one plan; the autotuner             #
+# --------------------------------------------------------------------------- #
+
+# per class of the 10-epoch supernova subset (sides 32..128): direct, FFT one-launch
+# forward, FFT line passes, in a rotation that gives every pattern a class
+MIXES = {
+    "dir-fused-lines": [(1, True), (2, True), (2, False)],
+    "lines-dir-fused": [(2, False), (1, True), (2, True)],
+}
+
+
+def _mixed_plan(prob, d, w, mix):
+    st = _st()
+    plan = st.Plan.for_problem(prob, conv_algo=st.CONV_FFT)
+    plan.set_frames(d, w, prob.kernels, prob.W)
+    cls = plan.classes()
+    for c in range(len(cls)):
+        algo, fused = mix[c % len(mix)]
+        plan.set_class_algo(c, algo, fused)
+    got = plan.classes()
+    assert {c["algo"] for c in got} == {1, 2}, got
+    return plan, got
+
+
+@pytest.mark.parametrize("mix", sorted(MIXES), ids=sorted(MIXES))
+def test_mixed_class_algorithms_loss_grad_and_operators(mix):
+    """Frames of some shape classes on the direct algorithm and the rest on the FFT
+    algorithm (one-launch forward or line passes) in one evaluation: loss, gradient,
+    the operators and their adjoint against the oracle."""
+    prob = synth.make_deconv(4, E=10)
+    d, w, rng = _data(prob, seed=41)
+    plan, cls = _mixed_plan(prob, d, w, MIXES[mix])
+    _say(f"mixed {mix}: " + ", ".join(f"n{c['n']}/K{c['K']}:{'dir' if c['algo'] == 1 else ('fused' if c['fused'] else 'lines')}"
+                                        for c in cls))
+    for point in ("init", "near"):
+        p = synth.eval_point(prob, point, rng)
+        _compare_loss_grad(prob, d, w, p, plan, f"mixed {mix}/{point}")
+    scene = synth.f32(rng.standard_normal(prob.fine_size) * 30)
+    model = plan.convolve_subsample(scene).cpu().numpy().astype(np.float64)
+    ref = ora.conv_sub(prob.n, prob.K, prob.s, prob.kernels, scene)
+    _check_frames(model, ref, prob.n.tolist(), 1e-5)
+    resid = synth.f32(rng.standard_normal(prob.data_size))
+    adj = plan.convolve_subsample_adj(resid).cpu().numpy().astype(np.float64)
+    refa = ora.conv_sub_adj(prob.n, prob.K, prob.s, prob.kernels, resid)
+    _check_frames(adj, refa, (prob.s * prob.n).tolist(), 1e-5)
+
+
+def test_mixed_class_algorithms_graph_steps_match_eager():
+    """Optimiser steps of a mixed plan (the update fused into the final launch):
+    graph replays equal eager steps bit for bit, and equal the all-FFT plan's loss
+    up to rounding."""
+    st = _st()
+    prob = synth.make_deconv(4, E=10)
+    d, w, rng = _data(prob, seed=42)
+    p = torch.tensor(synth.eval_point(prob, "near", rng), dtype=torch.float32, device="cuda")
+    plan_g, _ = _mixed_plan(prob, d, w, MIXES["dir-fused-lines"])
+    plan_e, _ = _mixed_plan(prob, d, w, MIXES["dir-fused-lines"])
+    plan_g.set_graph_mode(True)
+    lr4 = [prob.adam_lr[k] for k in ("h", "Gamma", "a", "c")]
+    xg, xe = p.clone(), p.clone()
+    mg, vg, me, ve = (torch.zeros_like(p) for _ in range(4))
+    lg = torch.empty(3, dtype=torch.float64, device="cuda")
+    for t in range(1, 5):
+        plan_g.step(xg, mg, vg, t, lr4, loss_out=lg)
+        le = plan_e.step(xe, me, ve, t, lr4)
+        torch.cuda.synchronize()
+        _ = (torch.randn(1000, device="cuda") * 2).sum().item()
+        assert torch.equal(lg, le) and torch.equal(xg, xe) and torch.equal(mg, me) and torch.equal(vg, ve), t
+    fft = st.Plan.for_problem(prob, conv_algo=st.CONV_FFT)
+    fft.set_frames(d, w, prob.kernels, prob.W)
+    lf, _ = fft.loss_grad(xe)
+    lm, _ = plan_e.loss_grad(xe)
+    assert abs(lf[2].item() - lm[2].item()) <= 1e-6 * abs(lf[2].item())
+
+
+def test_autotuner_per_class_choices_cache_and_parity():
+    """The automatic choice times each class's alternatives; a second plan of the same
+    shapes takes the cached decision; the tuned plan matches the oracle."""
+    st = _st()
+    prob = synth.make_deconv(4, E=10)
+    d, w, rng = _data(prob, seed=43)
+    plan = st.Plan.for_problem(prob)
+    plan.set_frames(d, w, prob.kernels, prob.W)
+    info = plan.autotune_info()
+    cls = plan.classes()
+    _say(f"autotune: {info}; " + "; ".join(f"n{c['n']}: algo {c['algo']} fused {c['fused']} ms {c['tune_ms']}"
+                                           for c in cls))
+    assert info["wall_ms"] > 0
+    for c in cls:
+        tried = [v for v in c["tune_ms"] if v >= 0]
+        assert len(tried) >= 2, c  # the current choice and at least one alternative
+    plan2 = st.Plan.for_problem(prob)
+    plan2.set_frames(d, w, prob.kernels, prob.W)
+    info2 = plan2.autotune_info()
+    assert info2["cached"] and [c["algo"] for c in plan2.classes()] == [c["algo"] for c in cls]
+    assert info2["adj_blocks"] == info["adj_blocks"] and info2["line_groups"] == info["line_groups"]
+    p = synth.eval_point(prob, "near", rng)
+    _compare_loss_grad(prob, d, w, p, plan, "autotuned cfg4 subset")
+
+
+# --------------------------------------------------------------------------- #
+# Per-frame shifts and rotations                                               #
+# --------------------------------------------------------------------------- #
+
+XF_CASES = {
+    # small ragged frames, two sources, odd and even kernels
+    "small": lambda: synth.make_small_deconv(61, 4, [16, 24, 8, 20], [15, 16, 5, 9], 2, 64, 2, 4),
+    # supernova stamps
+    "cfg4_sizes": lambda: synth.make_deconv(4, E=6),
+}
+
+
+def _xf_for(E, rng, big=False):
+    d = rng.uniform(-2.5, 2.5, (E, 2))
+    th = rng.uniform(-0.6, 0.6, E) if not big else rng.uniform(-np.pi, np.pi, E)
+    return synth.f32(np.column_stack([d, th]).ravel())
+
+
+@pytest.mark.parametrize("name", sorted(XF_CASES), ids=sorted(XF_CASES))
+def test_frame_transforms_parity(name):
+    """Frames shifted and rotated: scenes element by element, loss, every gradient
+    block and dL/d(dx, dy, theta) per frame against the oracle; clearing the transforms
+    gives back the untransformed plan's results."""
+    st = _st()
+    prob = XF_CASES[name]()
+    d, w, rng = _data(prob, seed=62)
+    plan = _plan(prob, d, w, algo=st.CONV_AUTO)
+    p = synth.eval_point(prob, "near", rng)
+    l_plain, g_plain = plan.loss_grad(p)
+    l_plain, g_plain = l_plain.clone(), g_plain.clone()
+    for big in (False, True):
+        xf = _xf_for(prob.E, rng, big)
+        gx = plan.set_frame_transforms(xf)
+        assert all(c["algo"] == st.CONV_DIRECT for c in plan.classes())
+        sc = plan.render_scene(p).cpu().numpy().astype(np.float64)
+        ref = ora.render_scene_xf(prob.n, prob.s, prob.N, prob.M, prob.fwhm, p, xf)
+        _check_frames(sc, ref, (prob.s * prob.n).tolist(), 2e-6)
+        loss, grad = plan.loss_grad(p)
+        torch.cuda.synchronize()
+        loss = loss.cpu().numpy()
+        grad = grad.cpu().numpy().astype(np.float64)
+        gxd = gx.cpu().numpy().astype(np.float64)
+        NN = prob.N ** 2
+        so, nsub = parity.tie_override(prob.N, prob.J, p[:NN], plan.starlet_fwd(p[:NN]).cpu().numpy())
+        lo, go, gxo = ora.loss_grad_xf(prob, d, w, p, xf, sgn_override=so)
+        rl = abs(loss[2] - lo[2]) / abs(lo[2])
+        blocks = {k: parity.rel_err(parity.deconv_blocks(prob, grad)[k], v)
+                  for k, v in parity.deconv_blocks(prob, go).items() if np.linalg.norm(v) > 0}
+        rx = parity.rel_err(gxd, gxo)
+        rxs = [parity.rel_err(gxd[j::3], gxo[j::3]) for j in range(3)]
+        _say(f"xf {name} big={big}: loss rel {rl:.2e}; grad {blocks}; transforms {rx:.2e} {rxs}")
+        assert rl <= 1e-6
+        assert parity.rel_err(grad, go) <= 1e-4
+        for k, v in blocks.items():
+            assert v <= 1e-4, (k, v)
+        for j in range(3):
+            assert rxs[j] <= 1e-4, j
+    plan.set_frame_transforms(None)
+    l2, g2 = plan.loss_grad(p)
+    assert abs(l2[2].item() - l_plain[2].item()) <= 1e-6 * abs(l_plain[2].item())
+    assert parity.rel_err(g2.cpu().numpy(), g_plain.cpu().numpy()) <= 1e-5
