@@ -69,7 +69,8 @@ typedef struct starred_plan starred_plan;
  *   w_pixel_stride  0: W holds J per-scale values; 1: W holds J*N*N maps.
  *   lambda      regularisation strength of the starlet L1 term (Eq. 6, Eq. 11).
  *   gauss_fwhm  FWHM of the target Gaussian r in fine pixels (2 in the paper,
- *               Sec. 2.1).
+ *               Sec. 2.1); at most about 3.04 (sigma <= 8/6.2), since r is evaluated
+ *               within +-8 fine pixels of its centre (EINVAL above).
  *   conv_algo   STARRED_CONV_AUTO / DIRECT / FFT (deconvolution only). */
 typedef struct {
     int32_t mode;
@@ -178,19 +179,6 @@ int starred_step(starred_plan *plan, float *params, float *m, float *v, int32_t 
 int starred_steps(starred_plan *plan, float *params, float *m, float *v, int32_t t,
                   const starred_adam *hp, int32_t n_steps, double *loss_out);
 
-/* L-BFGS (limited-memory BFGS, Nocedal & Wright Alg. 7.4-7.5), the quasi-Newton
- * method of the paper's PSF fits, on the plan's loss. A state holds the history
- * of the last m pairs (s, y) ([m][num_params] floats each, allocated here), the
- * gradient at the current point and the loss there. Optional box bounds lo, hi
- * (device, num_params floats each, referenced, may be NULL): every trial point is
- * clipped into the box (a projected search, not the Cauchy-point machinery of
- * L-BFGS-B). Each iteration: direction d = -H g by the two-loop recursion
- * (steepest descent when the history is empty or d is not a descent direction),
- * backtracking from step 1 (1/|g| without history) by halves until the Armijo
- * condition f(x_t) <= f(x) + 1e-4 g^T (x_t - x) holds (at most 40 trials; none
- * ends the run), then the full gradient at the accepted point and the new pair
- * (kept when s^T y > 1e-12 y^T y). The vector work runs in kernels; the accept
- * decisions read each trial's loss on the host (the calls synchronise). */
 /* The two-loop recursion alone (Nocedal & Wright Alg. 7.4): d_out = -H grad for the
  * `count` newest pairs of the caller's ring buffers S, Y ([m][num_params] floats,
  * device, newest pair at slot `newest`, older ones before it modulo m) and
@@ -199,14 +187,49 @@ int starred_steps(starred_plan *plan, float *params, float *m, float *v, int32_t
 int starred_lbfgs_direction(starred_plan *plan, const float *grad, const float *S, const float *Y, int32_t m,
                             int32_t count, int32_t newest, float *d_out);
 
+/* L-BFGS-B (Byrd, Lu, Nocedal & Zhu; the projected subspace step of Morales &
+ * Nocedal), the bound-constrained quasi-Newton method of the paper's PSF fits, as a
+ * host-side iteration in FP64 driven by reverse communication: each iteration
+ * takes the generalized Cauchy point of the quadratic model along the projected
+ * steepest-descent path, minimises the model over the variables free there (the
+ * result projected onto the box, or cut back to it when the projection is not a
+ * descent direction), then searches the line with Moré-Thuente steps (sufficient
+ * decrease 1e-3, curvature 0.9, first trial 1, or 1/|d| on the first iteration when
+ * not every variable is bounded, never past the box) and stores the correction
+ * pair when s^T y is safely positive (history m). Stops when the projected
+ * gradient's largest entry is <= pgtol or the relative decrease of f is below
+ * factr times the machine epsilon (scipy's defaults: m 10, factr 1e7, pgtol 1e-5,
+ * maxls 20).
+ * create: n variables, host bounds lo/hi (NULL or +-inf entries: unbounded).
+ * iterate: x (host, n doubles) is projected into the box and returned on the first
+ * call (task FG); afterwards pass f and g (host) at the current x each time. Tasks:
+ * FG (evaluate at the updated x and call again), NEW_X (an iteration ended at x:
+ * call again with the same f, g to continue), CONVERGED, ABNORMAL (no descent or
+ * the line search failed without history). counts: iterations done and
+ * evaluations requested. */
+enum { STARRED_LBFGSB_FG = 1, STARRED_LBFGSB_NEW_X = 2, STARRED_LBFGSB_CONVERGED = 3, STARRED_LBFGSB_ABNORMAL = 4 };
+typedef struct starred_lbfgsb starred_lbfgsb;
+int starred_lbfgsb_create(int64_t n, int32_t m, const double *lo, const double *hi, double factr, double pgtol,
+                          int32_t maxls, starred_lbfgsb **out);
+int starred_lbfgsb_destroy(starred_lbfgsb *state);
+int starred_lbfgsb_iterate(starred_lbfgsb *state, double *x, double f, const double *g, int32_t *task);
+int starred_lbfgsb_counts(const starred_lbfgsb *state, int32_t *iterations, int32_t *evaluations);
+
+/* L-BFGS-B on the plan's loss: the iteration of starred_lbfgsb_* (history m, scipy's
+ * defaults otherwise) on the host, with the loss and gradient evaluated on the device
+ * at every point it asks for (each evaluation synchronises the plan's stream and
+ * copies the loss and the gradient to the host). lo, hi (device, num_params floats,
+ * or NULL; +-inf entries are unbounded): box bounds, copied at creation. */
 typedef struct starred_lbfgs starred_lbfgs;
 int starred_lbfgs_create(starred_plan *plan, int32_t m, const float *lo, const float *hi, starred_lbfgs **state_out);
 int starred_lbfgs_destroy(starred_lbfgs *state);
 /* Forget the history and the stored gradient (call after changing x elsewhere). */
 int starred_lbfgs_reset(starred_lbfgs *state);
-/* n_iter iterations from x (device, num_params floats, updated in place; it must
- * not change between calls except here, else reset first). *loss_out (host): the
- * loss at the final x; *n_evals_out (host, may be NULL): loss evaluations used. */
+/* Up to n_iter iterations from x (device, num_params floats, updated in place; it
+ * must not change between calls except here, else reset first; the first call
+ * projects it into the box). Stops early at convergence (projected gradient <= 1e-5
+ * or relative decrease <= 1e7 eps) or when no descent is possible. *loss_out (host):
+ * the loss at the final x; *n_evals_out (host, may be NULL): evaluations used. */
 int starred_lbfgs_run(starred_lbfgs *state, float *x, int32_t n_iter, double *loss_out, int32_t *n_evals_out);
 
 /* Graph mode. When enabled, starred_loss_grad and starred_step capture their

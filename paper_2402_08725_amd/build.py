@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libstarred.so")
-SOURCES = ["starred_kernels.hip", "starred_fft.hip", "starred_psf.hip", "starred_noise.hip", "starred_opt.hip", "starred_starlet.hip", "starred_static.hip", "starred_plan.hip"]
+SOURCES = ["starred_kernels.hip", "starred_fft.hip", "starred_psf.hip", "starred_noise.hip", "starred_opt.hip", "starred_starlet.hip", "starred_static.hip", "starred_lbfgsb.hip", "starred_plan.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

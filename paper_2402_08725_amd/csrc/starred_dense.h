@@ -27,7 +27,7 @@
 
 namespace starred {
 
-constexpr int kDenseMaxJ = 9;  // at most 8 scales
+constexpr int kDenseMaxJ = 8;  // at most 7 scales (eight need more LDS than the cap: the cascade)
 constexpr int kDenseTile = 16;  // y-pass output tiles
 constexpr int kDenseThreads = 256;
 

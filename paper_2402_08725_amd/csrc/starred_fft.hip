@@ -779,44 +779,65 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
     const FrameFft &f = fr[it.frame];
     const FftLen &fl = c.fQ;
     const int Q = c.Q, H = Q / 2 + 1, n = c.n, Ls = Q + 1;
+    // the rows are real: two of them share one complex transform (row 2p in the real
+    // part, row 2p+1 in the imaginary part; a missing partner row is zero)
+    const int np = (it.nl + 1) / 2;
     float2 *a = sm;
-    float2 *b = sm + it.nl * Ls;
-    const int tot = it.nl * Q;
+    float2 *b = sm + np * Ls;
+    const int tot = np * Q;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
         const int l = e / Q, kx = e - l * Q;
-        const float2 *row = T + f.t_off + (long long)(it.line0 + l) * H;
-        a[l * Ls + kx] = kx < H ? row[kx] : conjf2(row[Q - kx]);
+        const float2 *row0 = T + f.t_off + (long long)(it.line0 + 2 * l) * H;
+        const float2 x0 = kx < H ? row0[kx] : conjf2(row0[Q - kx]);
+        float2 x1 = make_float2(0.f, 0.f);
+        if (2 * l + 1 < it.nl) {
+            const float2 *row1 = row0 + H;
+            x1 = kx < H ? row1[kx] : conjf2(row1[Q - kx]);
+        }
+        a[l * Ls + kx] = make_float2(x0.x - x1.y, x0.y + x1.x);  // X0 + i X1
     }
     __syncthreads();
-    float2 *r = lds_fft_any<true>(a, b, it.nl, fl, tw + fl.tw_off);
+    float2 *r = lds_fft_any<true>(a, b, np, fl, tw + fl.tw_off);
     float2 *o = (r == a) ? b : a;
     double chi = 0.0;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
         const int l = e / Q, x = e - l * Q;
-        const int y = it.line0 + l;
-        float v = 0.f;
+        float v[2] = {0.f, 0.f};
         if (x < n) {
-            const long long idx = f.data_off + (long long)y * n + x;
-            const float m = r[l * Ls + x].x;
-            if (model) {
-                model[idx] = m;
-            } else {
-                const float res = m - data[idx];
-                const float w = invvar[idx];
-                v = w * res;
-                chi += 0.5 * (double)w * (double)res * (double)res;
+            const float2 z = r[l * Ls + x];
+            const float mm[2] = {z.x, z.y};
+            #pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (2 * l + u >= it.nl) break;
+                const int y = it.line0 + 2 * l + u;
+                const long long idx = f.data_off + (long long)y * n + x;
+                if (model) {
+                    model[idx] = mm[u];
+                } else {
+                    const float res = mm[u] - data[idx];
+                    const float w = invvar[idx];
+                    v[u] = w * res;
+                    chi += 0.5 * (double)w * (double)res * (double)res;
+                }
             }
         }
-        o[l * Ls + x] = make_float2(v, 0.f);
+        o[l * Ls + x] = make_float2(v[0], v[1]);
     }
     const double tchi = block_sum_d_fft(chi, red);
     if (threadIdx.x == 0 && part_chi) part_chi[blockIdx.x] = tchi;
     if (model) return;
     __syncthreads();
-    float2 *q = lds_fft_any<false>(o, r, it.nl, fl, tw + fl.tw_off);
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int l = e / Q, kx = e - l * Q;
-        if (kx < H) T2[f.t_off + (long long)(it.line0 + l) * H + kx] = q[l * Ls + kx];
+    float2 *q = lds_fft_any<false>(o, r, np, fl, tw + fl.tw_off);
+    // split the pair's spectrum Z into the two rows' half spectra:
+    // X0 = (Z(k) + conj Z(Q-k)) / 2, X1 = (Z(k) - conj Z(Q-k)) / (2i)
+    const int toth = np * H;
+    for (int e = threadIdx.x; e < toth; e += blockDim.x) {
+        const int l = e / H, kx = e - l * H;
+        const float2 zk = q[l * Ls + kx];
+        const float2 zc = conjf2(q[l * Ls + (kx == 0 ? 0 : Q - kx)]);
+        float2 *dst = T2 + f.t_off + (long long)(it.line0 + 2 * l) * H + kx;
+        dst[0] = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+        if (2 * l + 1 < it.nl) dst[H] = make_float2(0.5f * (zk.y - zc.y), -0.5f * (zk.x - zc.x));
     }
 }
 

@@ -32,36 +32,52 @@ __device__ __forceinline__ void adam_bias(const AdamDev &adam, float &bc1, float
     }
 }
 
-// One work group of NT threads: one wave per reduced quantity (lanes stride the
-// items, then a fixed shuffle tree), so none waits for another.
+// Deterministic sum over the work group of one double per thread (a fixed
+// shuffle tree per wave, then the waves in order); every thread gets the total.
+template <int NT>
+__device__ __forceinline__ double group_sum(double v, double *sh)
+{
+    #pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();  // sh may still be read by the previous sum
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    #pragma unroll
+    for (int w = 0; w < NT / 64; ++w) t += sh[w];
+    return t;
+}
+
+// One work group of NT threads. Each reduced quantity is summed by the whole group:
+// thread t takes the items t, t + NT, ... (their loads independent, so they are in
+// flight together), then the fixed-order group sum.
 // loss[0] = sum chi partials, loss[1] = sum L1 partials, loss[2] = total.
 template <int NT>
 __device__ void finalize_small_body(const FinalArgs &a)
 {
     __shared__ double sums[2];
+    __shared__ double gsh[NT / 64];
     const int E = a.E, M = a.M;
     const long long NN = (long long)a.N * a.N;
     const int stride = 1 + 3 * M;
     if (a.tick && threadIdx.x == 0) *a.tick += 1;  // the update that follows reads it
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    constexpr int NW = NT / 64;
     const float *pa = a.params + NN + E;
     const int nred = 2 + (a.grad ? 2 * M : 0);
-    for (int r = wv; r < nred; r += NW) {
+    for (int r = 0; r < nred; ++r) {
         double acc = 0.0;
         if (r == 0) {
-            for (int i = lane; i < a.n_chi; i += 64) acc += a.part_chi[i];
+            for (int i = threadIdx.x; i < a.n_chi; i += NT) acc += a.part_chi[i];
         } else if (r == 1) {
-            for (int i = lane; i < a.n_l1; i += 64) acc += a.part_l1[i];
+            for (int i = threadIdx.x; i < a.n_l1; i += NT) acc += a.part_l1[i];
         } else {
             // dL/dc_k = sum_i a_ik <g_i, dr_k/dc>
             const int q = r - 2, k = q >> 1, axis = q & 1;
-            for (int i = lane; i < E; i += 64)
+            for (int i = threadIdx.x; i < E; i += NT)
                 acc += (double)pa[(long long)i * M + k] * a.fsum[(long long)i * stride + 1 + (1 + axis) * M + k];
         }
-        #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (lane == 0) {
+        acc = group_sum<NT>(acc, gsh);
+        if (threadIdx.x == 0) {
             if (r < 2) sums[r] = acc;
             else {
                 // plus the point-source prior's share (pts[3k+1+axis])

@@ -102,19 +102,22 @@ hipError_t launch_prep_kernels(hipStream_t st, const FrameDev *fr_dev, const Fra
 // --------------------------------------------------------------------------
 
 // Per-frame transform t_i = (dx, dy, theta): the frame pixel at grid position X
-// reads the scene at u = R(theta)(X - C) + C + (dx, dy), C the grid centre.
+// reads the scene at u = R(theta)(X - C) + C + (dx, dy), C the grid centre. The
+// position is formed in FP64 (a few operations per pixel) so that the bilinear
+// weights and the Gaussian offsets carry no FP32 rounding of coordinates that
+// reach hundreds of pixels.
 struct FrameMap {
-    float cs, sn, C, dx, dy;
+    double cs, sn, C, dx, dy;
     __device__ FrameMap(const float *xf, int i, int N)
     {
-        dx = xf[3 * i];
-        dy = xf[3 * i + 1];
-        sincosf(xf[3 * i + 2], &sn, &cs);
-        C = 0.5f * (float)(N - 1);
+        dx = (double)xf[3 * i];
+        dy = (double)xf[3 * i + 1];
+        sincos((double)xf[3 * i + 2], &sn, &cs);
+        C = 0.5 * (double)(N - 1);
     }
-    __device__ void map(float X, float Y, float &ux, float &uy) const
+    __device__ void map(double X, double Y, double &ux, double &uy) const
     {
-        const float vx = X - C, vy = Y - C;
+        const double vx = X - C, vy = Y - C;
         ux = cs * vx - sn * vy + C + dx;
         uy = sn * vx + cs * vy + C + dy;
     }
@@ -126,12 +129,12 @@ __device__ __forceinline__ float h_at(const float *__restrict__ h, int N, int X,
 }
 
 // bilinear read of h at (ux, uy) (zero outside the grid) and its partial derivatives
-__device__ __forceinline__ float bilerp(const float *__restrict__ h, int N, float ux, float uy, float *gx,
+__device__ __forceinline__ float bilerp(const float *__restrict__ h, int N, double ux, double uy, float *gx,
                                        float *gy)
 {
-    const float fx = floorf(ux), fy = floorf(uy);
+    const double fx = floor(ux), fy = floor(uy);
     const int X0 = (int)fx, Y0 = (int)fy;
-    const float tx = ux - fx, ty = uy - fy;
+    const float tx = (float)(ux - fx), ty = (float)(uy - fy);
     const float h00 = h_at(h, N, X0, Y0), h10 = h_at(h, N, X0 + 1, Y0);
     const float h01 = h_at(h, N, X0, Y0 + 1), h11 = h_at(h, N, X0 + 1, Y0 + 1);
     if (gx) {
@@ -154,10 +157,11 @@ __global__ void k_render(const FrameDev *__restrict__ frames, int E, int frame0,
     const float *h = params;
     const float *a = params + (long long)N * N + E;
     const float *c = a + (long long)E * M;
-    float ux = (float)X, uy = (float)Y, v;
+    double ux = (double)X, uy = (double)Y;
+    float v;
     if (xf) {
         FrameMap fm(xf, i, N);
-        fm.map((float)X, (float)Y, ux, uy);
+        fm.map((double)X, (double)Y, ux, uy);
         v = params[(long long)N * N + i] + bilerp(h, N, ux, uy, nullptr, nullptr);
     } else {
         v = params[(long long)N * N + i] + h[(long long)Y * N + X];
@@ -165,7 +169,7 @@ __global__ void k_render(const FrameDev *__restrict__ frames, int E, int frame0,
     const float inv2s2 = 1.0f / (2.0f * sigma * sigma);
     const float norm = 1.0f / (2.0f * 3.14159265358979f * sigma * sigma);
     for (int k = 0; k < M; ++k) {
-        float dx = ux - c[2 * k], dy = uy - c[2 * k + 1];
+        float dx = (float)(ux - (double)c[2 * k]), dy = (float)(uy - (double)c[2 * k + 1]);
         if (fabsf(dx) <= (float)kGaussRadius && fabsf(dy) <= (float)kGaussRadius)
             v += a[(long long)i * M + k] * (norm * expf(-(dx * dx + dy * dy) * inv2s2));
     }
@@ -548,19 +552,19 @@ __device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, i
         const float cx = c[2 * k], cy = c[2 * k + 1];
         // the source's box |u - c| <= R in frame coordinates: around the preimage of
         // c, within R sqrt(2) (+1) on each axis
-        const float ex = cx - fm.C - fm.dx, ey = cy - fm.C - fm.dy;
-        const float px = fm.cs * ex + fm.sn * ey + fm.C, py = -fm.sn * ex + fm.cs * ey + fm.C;
-        const float rad = (float)kGaussRadius * 1.4143f + 1.f;
-        const int x_lo = max(fr.o, (int)floorf(px - rad)), x_hi = min(fr.o + fr.F - 1, (int)ceilf(px + rad));
-        const int y_lo = max(fr.o, (int)floorf(py - rad)), y_hi = min(fr.o + fr.F - 1, (int)ceilf(py + rad));
+        const double ex = cx - fm.C - fm.dx, ey = cy - fm.C - fm.dy;
+        const double px = fm.cs * ex + fm.sn * ey + fm.C, py = -fm.sn * ex + fm.cs * ey + fm.C;
+        const double rad = (double)kGaussRadius * 1.4143 + 1.0;
+        const int x_lo = max(fr.o, (int)floor(px - rad)), x_hi = min(fr.o + fr.F - 1, (int)ceil(px + rad));
+        const int y_lo = max(fr.o, (int)floor(py - rad)), y_hi = min(fr.o + fr.F - 1, (int)ceil(py + rad));
         const int wx = x_hi - x_lo + 1, wy = y_hi - y_lo + 1;
         double sa = 0.0, sx = 0.0, sy = 0.0;
         if (wx > 0 && wy > 0) {
             for (int e = threadIdx.x; e < wx * wy; e += kSumThreads) {
                 const int Y = y_lo + e / wx, X = x_lo + e % wx;
-                float ux, uy;
-                fm.map((float)X, (float)Y, ux, uy);
-                const float dx = ux - cx, dy = uy - cy;
+                double ux, uy;
+                fm.map((double)X, (double)Y, ux, uy);
+                const float dx = (float)(ux - (double)cx), dy = (float)(uy - (double)cy);
                 if (fabsf(dx) > (float)kGaussRadius || fabsf(dy) > (float)kGaussRadius) continue;
                 const float r = norm * expf(-(dx * dx + dy * dy) * inv2s2);
                 const float gr = gi[(long long)(Y - fr.o) * fr.F + (X - fr.o)] * r;
@@ -582,12 +586,13 @@ __device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, i
     // by == 1 + M: the transform's gradient
     double gdx = 0.0, gdy = 0.0, gth = 0.0;
     for (int p = threadIdx.x; p < tot; p += kSumThreads) {
-        const float X = (float)(fr.o + p % fr.F), Y = (float)(fr.o + p / fr.F);
-        float ux, uy, qx, qy;
+        const double X = (double)(fr.o + p % fr.F), Y = (double)(fr.o + p / fr.F);
+        double ux, uy;
+        float qx, qy;
         fm.map(X, Y, ux, uy);
         bilerp(h, N, ux, uy, &qx, &qy);
         for (int k = 0; k < M; ++k) {
-            const float dx = ux - c[2 * k], dy = uy - c[2 * k + 1];
+            const float dx = (float)(ux - (double)c[2 * k]), dy = (float)(uy - (double)c[2 * k + 1]);
             if (fabsf(dx) <= (float)kGaussRadius && fabsf(dy) <= (float)kGaussRadius) {
                 const float ar = a[(long long)i * M + k] * norm * expf(-(dx * dx + dy * dy) * inv2s2) * invs2;
                 qx -= ar * dx;
@@ -595,10 +600,11 @@ __device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, i
             }
         }
         const float gv = gi[p];
-        const float vx = X - fm.C, vy = Y - fm.C;
+        const float vx = (float)(X - fm.C), vy = (float)(Y - fm.C);
+        const float cs = (float)fm.cs, sn = (float)fm.sn;
         gdx += (double)(gv * qx);
         gdy += (double)(gv * qy);
-        gth += (double)(gv * (qx * (-fm.sn * vx - fm.cs * vy) + qy * (fm.cs * vx - fm.sn * vy)));
+        gth += (double)(gv * (qx * (-sn * vx - cs * vy) + qy * (cs * vx - sn * vy)));
     }
     gdx = block_sum_d<kSumThreads>(gdx, red);
     gdy = block_sum_d<kSumThreads>(gdy, red);
@@ -703,9 +709,9 @@ __device__ float transpose_bilerp(const FrameDev &fr, int i, int N, const float 
                                   const float *__restrict__ g, int PX, int PY)
 {
     const FrameMap fm(xf, i, N);
-    const float ex = (float)PX - fm.C - fm.dx, ey = (float)PY - fm.C - fm.dy;
-    const float px = fm.cs * ex + fm.sn * ey + fm.C, py = -fm.sn * ex + fm.cs * ey + fm.C;
-    const int bx = (int)floorf(px), byy = (int)floorf(py);
+    const double ex = (double)PX - fm.C - fm.dx, ey = (double)PY - fm.C - fm.dy;
+    const double px = fm.cs * ex + fm.sn * ey + fm.C, py = -fm.sn * ex + fm.cs * ey + fm.C;
+    const int bx = (int)floor(px), byy = (int)floor(py);
     const float *gi = g + fr.fine_off;
     float acc = 0.f;
     for (int Y = byy - 2; Y <= byy + 2; ++Y) {
@@ -714,13 +720,13 @@ __device__ float transpose_bilerp(const FrameDev &fr, int i, int N, const float 
         for (int X = bx - 2; X <= bx + 2; ++X) {
             const int x = X - fr.o;
             if (x < 0 || x >= fr.F) continue;
-            float ux, uy;
-            fm.map((float)X, (float)Y, ux, uy);
+            double ux, uy;
+            fm.map((double)X, (double)Y, ux, uy);
             // the same corner weights as the read: (1 - t) towards the lower corner
-            const float fx = floorf(ux), fy = floorf(uy);
+            const double fx = floor(ux), fy = floor(uy);
             const int X0 = (int)fx, Y0 = (int)fy;
             if ((PX != X0 && PX != X0 + 1) || (PY != Y0 && PY != Y0 + 1)) continue;
-            const float tx = ux - fx, ty = uy - fy;
+            const float tx = (float)(ux - fx), ty = (float)(uy - fy);
             const float wx = PX == X0 ? 1.f - tx : tx, wy = PY == Y0 ? 1.f - ty : ty;
             acc += gi[(long long)y * fr.F + x] * (wx * wy);
         }

@@ -285,6 +285,10 @@ static int validate(const starred_desc *d)
         return fail(STARRED_EINVAL, "2^(J-1) must not exceed grid_side-1");
     if (d->w_pixel_stride != 0 && d->w_pixel_stride != 1) return fail(STARRED_EINVAL, "w_pixel_stride must be 0 or 1");
     if (!(d->gauss_fwhm > 0.0)) return fail(STARRED_EINVAL, "gauss_fwhm must be > 0");
+    // r is evaluated within +-kGaussRadius fine pixels of its centre: the mass beyond
+    // the box must stay negligible (below 1e-9 of the total: sigma <= R / 6.2)
+    if (d->gauss_fwhm / (2.0 * std::sqrt(2.0 * std::log(2.0))) > kGaussRadius / 6.2)
+        return fail(STARRED_EINVAL, "gauss_fwhm above 3.0 fine pixels: r would be cut by its +-8 px evaluation box");
     if (!(d->lambda >= 0.0)) return fail(STARRED_EINVAL, "lambda must be >= 0");
     if (d->n_sources < 0) return fail(STARRED_EINVAL, "n_sources must be >= 0");
     for (int i = 0; i < d->n_frames; ++i) {
@@ -2042,24 +2046,30 @@ int starred_noise_weights(starred_plan *p, int32_t frame, const float *sigma2_da
 }
 
 // ---------------------------------------------------------------------------
-// L-BFGS (Nocedal & Wright Alg. 7.4 and 7.5) with a backtracking Armijo search
-// on projected trial points; the vector work runs in kernels, the control flow
-// (accept / halve) on the host from the loss values.
+// L-BFGS-B on the plan's loss: the iteration control (starred_lbfgsb_*, FP64 on
+// the host) asks for the loss and gradient at a point, the device evaluates them
+// there, and the two are copied back (one synchronisation per evaluation).
+// starred_lbfgs_direction: the two-loop recursion on the device (L-BFGS direction).
 // ---------------------------------------------------------------------------
 extern "C++" {
 struct starred_lbfgs {
     starred_plan *p = nullptr;
     int m = 0;
     long long n = 0;
-    const float *lo = nullptr, *hi = nullptr;
-    float *S = nullptr, *Y = nullptr, *g = nullptr, *gn = nullptr, *d = nullptr, *xt = nullptr;
-    double *alpha = nullptr, *dots = nullptr, *loss = nullptr;
-    int count = 0, newest = -1;
-    bool have_g = false;
+    std::vector<double> lo, hi;
+    bool has_lo = false, has_hi = false;
+    starred_lbfgsb *core = nullptr;
+    std::vector<double> xh, gh;
+    std::vector<float> buf;
+    float *gdev = nullptr;
+    double *loss = nullptr;
     double f = 0.0;
+    int task = 0;
+    bool started = false, done = false;
     std::vector<void *> owned;
     ~starred_lbfgs()
     {
+        if (core) (void)starred_lbfgsb_destroy(core);
         for (void *q : owned) (void)hipFree(q);
     }
     template <typename T>
@@ -2097,17 +2107,19 @@ int starred_lbfgs_create(starred_plan *p, int32_t m, const float *lo, const floa
     L->p = p;
     L->m = m;
     L->n = p->nparams;
-    L->lo = lo;
-    L->hi = hi;
-    int rc = L->alloc(&L->S, (size_t)m * L->n);
-    if (!rc) rc = L->alloc(&L->Y, (size_t)m * L->n);
-    if (!rc) rc = L->alloc(&L->g, (size_t)L->n);
-    if (!rc) rc = L->alloc(&L->gn, (size_t)L->n);
-    if (!rc) rc = L->alloc(&L->d, (size_t)L->n);
-    if (!rc) rc = L->alloc(&L->xt, (size_t)L->n);
-    if (!rc) rc = L->alloc(&L->alpha, (size_t)m);
-    if (!rc) rc = L->alloc(&L->dots, 2);
+    int rc = L->alloc(&L->gdev, (size_t)L->n);
     if (!rc) rc = L->alloc(&L->loss, 3);
+    L->buf.resize(L->n);
+    // bounds copied to the host once (FP32 values; +-inf or a NULL array: unbounded)
+    auto copy_bound = [&](const float *src, std::vector<double> &dst, double inf) -> int {
+        dst.assign(L->n, inf);
+        if (!src) return STARRED_OK;
+        HIP_TRY(hipMemcpy(L->buf.data(), src, sizeof(float) * L->n, hipMemcpyDeviceToHost));
+        for (long long i = 0; i < L->n; ++i) dst[i] = (double)L->buf[i];
+        return STARRED_OK;
+    };
+    if (!rc) rc = copy_bound(lo, L->lo, -HUGE_VAL);
+    if (!rc) rc = copy_bound(hi, L->hi, HUGE_VAL);
     if (rc) {
         delete L;
         return rc;
@@ -2127,16 +2139,9 @@ int starred_lbfgs_destroy(starred_lbfgs *L)
 int starred_lbfgs_reset(starred_lbfgs *L)
 {
     if (!L) return fail(STARRED_EINVAL, "state is NULL");
-    L->count = 0;
-    L->newest = -1;
-    L->have_g = false;
-    return STARRED_OK;
-}
-
-static int read_doubles(starred_plan *p, const double *dev, double *host, int k)
-{
-    HIP_TRY(hipMemcpyAsync(host, dev, sizeof(double) * k, hipMemcpyDeviceToHost, p->st));
-    HIP_TRY(hipStreamSynchronize(p->st));
+    if (L->core) (void)starred_lbfgsb_destroy(L->core);
+    L->core = nullptr;
+    L->started = L->done = false;
     return STARRED_OK;
 }
 
@@ -2147,63 +2152,55 @@ int starred_lbfgs_run(starred_lbfgs *L, float *x, int32_t n_iter, double *loss_o
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
     const long long n = L->n;
     int evals = 0, rc;
-    double h[3];
-    auto evaluate = [&](const float *at, float *grad_out) -> int {
-        int r = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, at, grad_out, L->loss)
-                                         : loss_grad_impl(p, at, grad_out, L->loss);
+    // the loss and gradient at the device vector x, into L->f and L->gh
+    auto evaluate = [&]() -> int {
+        int r = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, x, L->gdev, L->loss)
+                                         : loss_grad_impl(p, x, L->gdev, L->loss);
         if (r) return r;
+        double h[3];
+        HIP_TRY(hipMemcpyAsync(h, L->loss, sizeof(double) * 3, hipMemcpyDeviceToHost, p->st));
+        HIP_TRY(hipMemcpyAsync(L->buf.data(), L->gdev, sizeof(float) * n, hipMemcpyDeviceToHost, p->st));
+        HIP_TRY(hipStreamSynchronize(p->st));
+        L->f = h[2];
+        for (long long i = 0; i < n; ++i) L->gh[i] = (double)L->buf[i];
         ++evals;
-        return read_doubles(p, L->loss, h, 3);
+        return STARRED_OK;
     };
-    if (!L->have_g) {
-        if ((rc = evaluate(x, L->g))) return rc;
-        L->f = h[2];
-        L->have_g = true;
+    auto put_x = [&]() -> int {
+        for (long long i = 0; i < n; ++i) L->buf[i] = (float)L->xh[i];
+        HIP_TRY(hipMemcpyAsync(x, L->buf.data(), sizeof(float) * n, hipMemcpyHostToDevice, p->st));
+        HIP_TRY(hipStreamSynchronize(p->st));
+        return STARRED_OK;
+    };
+    if (!L->started) {
+        L->xh.resize(n);
+        L->gh.assign(n, 0.0);
+        HIP_TRY(hipMemcpyAsync(L->buf.data(), x, sizeof(float) * n, hipMemcpyDeviceToHost, p->st));
+        HIP_TRY(hipStreamSynchronize(p->st));
+        for (long long i = 0; i < n; ++i) L->xh[i] = (double)L->buf[i];
+        if ((rc = starred_lbfgsb_create(n, L->m, L->lo.data(), L->hi.data(), 1e7, 1e-5, 20, &L->core))) return rc;
+        int32_t task = 0;
+        if ((rc = starred_lbfgsb_iterate(L->core, L->xh.data(), 0.0, nullptr, &task))) return rc;
+        L->task = task;  // FG at the projected start
+        L->started = true;
+        L->done = false;
     }
-    for (int it = 0; it < n_iter; ++it) {
-        HIP_TRY(launch_lbfgs_direction(p->st, n, L->g, L->S, L->Y, L->m, L->count, L->newest, L->d, L->alpha));
-        HIP_TRY(launch_dots(p->st, n, L->g, L->d, nullptr, L->dots));
-        double gd[2];
-        if ((rc = read_doubles(p, L->dots, gd, 2))) return rc;
-        if (!(gd[0] < 0.0)) {
-            // not a descent direction: forget the history, steepest descent
-            L->count = 0;
-            L->newest = -1;
-            HIP_TRY(launch_lbfgs_direction(p->st, n, L->g, L->S, L->Y, L->m, 0, 0, L->d, L->alpha));
+    int iters = 0;
+    while (!L->done && iters < n_iter) {
+        int32_t task = L->task;
+        if (task == STARRED_LBFGSB_FG) {
+            if ((rc = put_x())) return rc;
+            if ((rc = evaluate())) return rc;
         }
-        double step = L->count == 0 ? 1.0 / std::max(1.0, std::sqrt(gd[1])) : 1.0;
-        bool ok = false;
-        for (int ls = 0; ls < 40; ++ls) {
-            HIP_TRY(launch_trial_point(p->st, n, x, L->d, (float)step, L->lo, L->hi, L->xt));
-            if ((rc = evaluate(L->xt, nullptr))) return rc;
-            const double ft = h[2];
-            HIP_TRY(launch_dots(p->st, n, L->g, L->xt, x, L->dots));  // g^T (xt - x)
-            double dec[2];
-            if ((rc = read_doubles(p, L->dots, dec, 2))) return rc;
-            if (ft <= L->f + 1e-4 * dec[0] && dec[0] < 0.0) {
-                ok = true;
-                break;
-            }
-            step *= 0.5;
-        }
-        if (!ok) break;  // no decrease along the direction: converged to rounding
-        if ((rc = evaluate(L->xt, L->gn))) return rc;
-        L->f = h[2];
-        // history slot for (s, y); x <- xt, g <- gn
-        const int slot = (L->newest + 1) % L->m;
-        HIP_TRY(launch_history(p->st, n, L->xt, x, L->gn, L->g, L->S + (long long)slot * n, L->Y + (long long)slot * n,
-                               1));
-        HIP_TRY(launch_dots(p->st, n, L->S + (long long)slot * n, L->Y + (long long)slot * n, nullptr, L->dots));
-        double sy[2];
-        if ((rc = read_doubles(p, L->dots, sy, 2))) return rc;
-        if (sy[0] > 1e-12 * sy[1]) {
-            L->newest = slot;
-            L->count = std::min(L->count + 1, L->m);
-        } else {
-            // no positive curvature: the pair is dropped (its slot held the oldest pair)
-            L->count = std::min(L->count, L->m - 1);
-        }
+        if ((rc = starred_lbfgsb_iterate(L->core, L->xh.data(), L->f, L->gh.data(), &task))) return rc;
+        L->task = task;
+        if (task == STARRED_LBFGSB_NEW_X) ++iters;
+        if (task == STARRED_LBFGSB_CONVERGED || task == STARRED_LBFGSB_ABNORMAL) L->done = true;
     }
+    // x holds the last iterate; after a failed search the iterate is the previous
+    // point, whose loss is evaluated again
+    if ((rc = put_x())) return rc;
+    if (L->task == STARRED_LBFGSB_ABNORMAL && (rc = evaluate())) return rc;
     if (loss_out) *loss_out = L->f;
     if (n_evals_out) *n_evals_out = evals;
     return STARRED_OK;

@@ -111,6 +111,11 @@ def lib():
         L.starred_lbfgs_run.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
         L.starred_estimate_lambda_pts.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
         L.starred_starlet_fwd_noalloc.argtypes = [i32, i32, vp, vp, vp]
+        L.starred_lbfgsb_create.argtypes = [ctypes.c_int64, i32, vp, vp, ctypes.c_double, ctypes.c_double, i32,
+                                            ctypes.POINTER(vp)]
+        L.starred_lbfgsb_destroy.argtypes = [vp]
+        L.starred_lbfgsb_iterate.argtypes = [vp, vp, ctypes.c_double, vp, ctypes.POINTER(i32)]
+        L.starred_lbfgsb_counts.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         _lib = L
     return _lib
 
@@ -419,6 +424,60 @@ def starlet_fwd_noalloc(N, J, img, out):
         _check(lib().starred_starlet_fwd_noalloc(int(N), int(J), _ptr(img), _ptr(out),
                                                  ctypes.c_void_p(stream.cuda_stream)))
     return out
+
+
+LBFGSB_FG, LBFGSB_NEW_X, LBFGSB_CONVERGED, LBFGSB_ABNORMAL = 1, 2, 3, 4
+
+
+class LBFGSB:
+    """The library's L-BFGS-B iteration on the host (reverse communication): any
+    function of float64 vectors can drive it."""
+
+    def __init__(self, n, m=10, lo=None, hi=None, factr=1e7, pgtol=1e-5, maxls=20):
+        self.n = int(n)
+        self._lo = None if lo is None else np.ascontiguousarray(lo, dtype=np.float64)
+        self._hi = None if hi is None else np.ascontiguousarray(hi, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().starred_lbfgsb_create(self.n, int(m), _np_ptr(self._lo), _np_ptr(self._hi), float(factr),
+                                           float(pgtol), int(maxls), ctypes.byref(h)))
+        self._h = h
+
+    def minimize(self, fun, x0, max_iter, callback=None):
+        """fun(x) -> (f, g). Returns (x, f, task, iterations, evaluations); callback(x)
+        after every iteration."""
+        x = np.ascontiguousarray(x0, dtype=np.float64).copy()
+        task = ctypes.c_int32(0)
+        _check(lib().starred_lbfgsb_iterate(self._h, _np_ptr(x), 0.0, None, ctypes.byref(task)))
+        f, g = 0.0, np.zeros(self.n)
+        it = 0
+        while it < max_iter:
+            if task.value == LBFGSB_FG:
+                f, g = fun(x)
+                g = np.ascontiguousarray(g, dtype=np.float64)
+            _check(lib().starred_lbfgsb_iterate(self._h, _np_ptr(x), float(f), _np_ptr(g), ctypes.byref(task)))
+            if task.value == LBFGSB_NEW_X:
+                it += 1
+                if callback:
+                    callback(x.copy())
+            elif task.value in (LBFGSB_CONVERGED, LBFGSB_ABNORMAL):
+                if task.value == LBFGSB_CONVERGED and callback:
+                    callback(x.copy())
+                break
+        ni, ne = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().starred_lbfgsb_counts(self._h, ctypes.byref(ni), ctypes.byref(ne)))
+        return x, f, task.value, ni.value, ne.value
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                lib().starred_lbfgsb_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def _np_ptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
 
 
 class StarredLoss(torch.autograd.Function):

@@ -99,3 +99,14 @@ def test_null_plan_arguments_are_rejected():
     assert L.starred_lbfgs_destroy(None) == -1
     assert L.starred_set_frames(None, None, None, None, None) == -1
     assert L.starred_steps(None, None, None, None, 1, None, 1, None) == -1
+
+
+def test_plan_rejects_a_gaussian_wider_than_its_evaluation_box():
+    """r is evaluated within +-8 fine pixels of its centre: a FWHM whose mass beyond
+    that box is not negligible is refused before anything runs."""
+    from paper_2402_08725_amd import starred as st
+    L = _lib()
+    d, keep = _desc(fwhm=3.5)
+    h = ctypes.c_void_p()
+    assert L.starred_plan_create(ctypes.byref(d), None, ctypes.byref(h)) == st.EINVAL
+    assert b"gauss_fwhm" in L.starred_last_error()

@@ -107,9 +107,10 @@ def test_convolve_subsample_and_adjoint(case, algo):
     assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(got) * np.linalg.norm(resid)
 
 
-# (128, 7) and (256, 8) reach levels 6 and 7, whose composite taps are read from the
-# padded table rather than compiled in
-@pytest.mark.parametrize("N,J", [(48, 4), (64, 3), (128, 6), (33, 5), (128, 7), (256, 8)])
+# (128, 7) reaches level 6, whose composite taps are read from the padded table rather
+# than compiled in; (256, 8) and (300, 5) run the cascade (eight scales, and grids above
+# 256, are beyond the composite filters)
+@pytest.mark.parametrize("N,J", [(48, 4), (64, 3), (128, 6), (33, 5), (128, 7), (256, 8), (300, 5)])
 def test_starlet_forward_and_adjoint(N, J):
     prob = synth.make_small_deconv(7, 1, [N], [5], 1, N, 1, J)
     d, w, rng = _data(prob)
@@ -303,6 +304,9 @@ def test_autograd_function_and_directional_differences(algo):
         assert abs(fd - an) <= tol * abs(an) + 1e-9, block
 
 
+ADAM200_LOSS_BAR = 1e-3
+
+
 @pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
 def test_adam_200_steps_against_oracle(algo):
     """Direct path: separate update launch; FFT path: update fused into the final
@@ -321,20 +325,30 @@ def test_adam_200_steps_against_oracle(algo):
     mo = np.zeros_like(po)
     vo = np.zeros_like(po)
     steps = 200
+    NN = prob.N ** 2
+    nties = 0
     for t in range(1, steps + 1):
         plan.step(x, m, v, t, lr4)
-        _, go = ora.loss_grad(prob, d, w, po)
+        # the oracle's subgradient takes the device's sign on coefficients that are
+        # zero up to rounding (several subgradients are correct there, and Adam's
+        # normalised step would turn an arbitrary choice into a full-lr step)
+        so, nsub = parity.tie_override(prob.N, prob.J, po[:NN], plan.starlet_fwd(po[:NN]).cpu().numpy())
+        nties += nsub
+        _, go = ora.loss_grad(prob, d, w, po, sgn_override=so)
         ora.adam_step(po, go, mo, vo, t, lrv)
     lg = plan.loss_grad(x)[0].cpu().numpy()
     lo, _ = ora.loss_grad(prob, d, w, po, want_grad=False)
     xf = x.cpu().numpy().astype(np.float64)
     cdev = xf[-2 * prob.M:]
     cora = po[-2 * prob.M:]
-    _say(f"adam200: loss dev {lg[2]:.6e} oracle {lo[2]:.6e}; c dev {cdev} oracle {cora}")
-    # Adam divides by sqrt(v): at entries whose gradient is zero up to rounding
-    # an FP32 and an FP64 run take opposite full-lr steps, so the trajectories
-    # separate slowly; the fixed-point parity bars are the tests above.
-    assert abs(lg[2] - lo[2]) / abs(lo[2]) <= 1e-3
+    _say(f"adam200: loss dev {lg[2]:.6e} oracle {lo[2]:.6e} rel {abs(lg[2] - lo[2]) / abs(lo[2]):.2e}; "
+         f"c dev {cdev} oracle {cora}; tied coefficients over the run {nties}")
+    # The bar on the final loss is ADAM200_LOSS_BAR: the oracle's own 200-step final
+    # loss moves by up to 2.4e-4 when its gradients carry relative perturbations of
+    # 1e-6 (the FP32 path's gradient error), because the l1 subgradient turns a
+    # coefficient's zero crossing a step earlier or later into a different path
+    # (tests/test_tolerances.py pins that spread on the CPU).
+    assert abs(lg[2] - lo[2]) / abs(lo[2]) <= ADAM200_LOSS_BAR
     assert np.abs(cdev - cora).max() <= 0.01
 
 
@@ -880,16 +894,19 @@ def test_adabelief_steps_against_oracle(algo):
     _say(f"adabelief single step: {good.sum()} entries, max rel err {err.max():.2e}")
     assert err.max() <= 1e-5
     plan.set_graph_mode(True)
+    NN = prob.N ** 2
     for t in range(2, 51):
         plan.step(x, m, v, t, lr4, **kw)
-        _, go = ora.loss_grad(prob, d, w, po)
+        so, _ = parity.tie_override(prob.N, prob.J, po[:NN], plan.starlet_fwd(po[:NN]).cpu().numpy())
+        _, go = ora.loss_grad(prob, d, w, po, sgn_override=so)
         ora.adabelief_step(po, go, mo, vo, t, lrv, eps=1e-16, eps_root=1e-16)
     plan.set_graph_mode(False)
     lg = plan.loss_grad(x)[0].cpu().numpy()
     lo, _ = ora.loss_grad(prob, d, w, po, want_grad=False)
     cdev = x.cpu().numpy().astype(np.float64)[-2 * prob.M:]
-    _say(f"adabelief 50: loss dev {lg[2]:.6e} oracle {lo[2]:.6e}; c dev {cdev} oracle {po[-2 * prob.M:]}")
-    assert abs(lg[2] - lo[2]) / abs(lo[2]) <= 1e-3
+    _say(f"adabelief 50: loss dev {lg[2]:.6e} oracle {lo[2]:.6e} rel {abs(lg[2] - lo[2]) / abs(lo[2]):.2e}; "
+         f"c dev {cdev} oracle {po[-2 * prob.M:]}")
+    assert abs(lg[2] - lo[2]) / abs(lo[2]) <= 1e-4
     assert np.abs(cdev - po[-2 * prob.M:]).max() <= 0.01
 
 
@@ -926,9 +943,9 @@ def test_lbfgs_direction_matches_oracle_two_loop():
 
 @pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
 def test_lbfgs_iterations_decrease_the_loss(algo):
-    """Iterations never raise the loss, make progress comparable to scipy's L-BFGS-B on
-    the oracle (same start, same history length, 30 iterations, lambda = 0), and the
-    reported loss is the loss at the returned point."""
+    """Iterations never raise the loss, reach scipy's L-BFGS-B on the oracle (same
+    start, same history length, 30 iterations, lambda = 0) to 1e-3, and the reported
+    loss is the loss at the returned point."""
     st = _st()
     prob = synth.make_deconv(1)
     d, w, rng = _data(prob, seed=46)
@@ -948,7 +965,7 @@ def test_lbfgs_iterations_decrease_the_loss(algo):
     res = scipy.optimize.minimize(lambda q: (lambda lg: (lg[0][2], lg[1]))(ora.loss_grad(prob, d, w, q, lam=0.0)),
                                   x0, jac=True, method="L-BFGS-B", options=dict(maxiter=30, maxcor=8))
     _say(f"scipy L-BFGS-B on the oracle, 30 iterations: {res.fun:.6e}")
-    assert losses[-1] <= 1.25 * res.fun
+    assert losses[-1] <= (1 + 1e-3) * res.fun
     assert plan.loss_grad(x)[0][2].item() == pytest.approx(losses[-1], rel=1e-6)
 
 
@@ -1215,3 +1232,106 @@ def test_frame_transforms_parity(name):
     l2, g2 = plan.loss_grad(p)
     assert abs(l2[2].item() - l_plain[2].item()) <= 1e-6 * abs(l_plain[2].item())
     assert parity.rel_err(g2.cpu().numpy(), g_plain.cpu().numpy()) <= 1e-5
+
+
+# --------------------------------------------------------------------------- #
+# L-BFGS-B with device evaluations against scipy's on the oracle               #
+# --------------------------------------------------------------------------- #
+
+def _lbfgsb_tracks(fun_oracle, plan, x0, lo, hi, iters, label):
+    import scipy.optimize
+    xs_s = []
+    res = scipy.optimize.minimize(fun_oracle, x0, jac=True, method="L-BFGS-B", bounds=list(zip(lo, hi)),
+                                  options=dict(maxiter=iters, maxcor=10),
+                                  callback=lambda xk: xs_s.append(np.array(xk, dtype=np.float64)))
+    x = torch.tensor(x0, dtype=torch.float32, device="cuda")
+    opt = plan.lbfgs(m=10, lo=lo.astype(np.float32), hi=hi.astype(np.float32))
+    xs_d, fs_d = [], []
+    for _ in range(iters):
+        f, _ = opt.run(x, 1)
+        xs_d.append(x.cpu().numpy().astype(np.float64))
+        fs_d.append(f)
+    k = min(len(xs_s), len(xs_d))
+    errs = [np.abs(xs_d[i] - xs_s[i]).max() / max(np.abs(xs_s[i]).max(), 1.0) for i in range(k)]
+    _say(f"{label}: iterate differences vs scipy " + " ".join(f"{e:.1e}" for e in errs))
+    _say(f"{label}: loss device {fs_d[-1]:.9e} scipy {res.fun:.9e} after {iters} iterations")
+    return errs, fs_d[-1], res.fun
+
+
+def test_lbfgsb_device_iterates_track_scipy_deconvolution():
+    """cfg1 (4 epochs of 32^2, lambda = 0) with h >= 0 and a_ik >= 0: the device-driven
+    L-BFGS-B follows scipy's L-BFGS-B on the FP64 oracle iterate by iterate. The two
+    evaluate the loss in FP32 and FP64, so the trajectories separate slowly: the first
+    five iterates within 1e-4 of the largest entry, the loss after 20 iterations
+    within 1e-3."""
+    st = _st()
+    prob = synth.make_deconv(1)
+    d, w, rng = _data(prob, seed=83)
+    plan = st.Plan.for_problem(prob, lam=0.0)
+    plan.set_frames(d, w, prob.kernels, prob.W)
+    NN, E, M = prob.N ** 2, prob.E, prob.M
+    lo = np.full(prob.n_params, -np.inf)
+    hi = np.full(prob.n_params, np.inf)
+    lo[:NN] = 0.0
+    lo[NN + E:NN + E + E * M] = 0.0
+    x0 = synth.f32(np.maximum(synth.eval_point(prob, "init", rng), lo))
+
+    def fun(q):
+        loss, g = ora.loss_grad(prob, d, w, q, lam=0.0)
+        return loss[2], g
+    errs, fd, fs = _lbfgsb_tracks(fun, plan, x0, lo, hi, 20, "lbfgsb cfg1")
+    assert max(errs[:5]) <= 1e-4
+    assert abs(fd - fs) <= 1e-3 * abs(fs)
+
+
+def test_lbfgsb_device_iterates_track_scipy_psf():
+    """PSF mode (4 star stamps of 16^2, s = 3) with positive widths, exponent and
+    amplitudes: the same comparison."""
+    st = _st()
+    prob = synth.make_psf(3, S=4, n=16, s=3, J=4)
+    rng = np.random.default_rng(84)
+    m = ora.psf_model(prob, prob.params_true)
+    d, w = synth.add_noise(m, rng, poisson=False)
+    plan = st.Plan.for_psf(prob)
+    plan.set_frames(d, w, None, prob.W)
+    NN, S = prob.N ** 2, prob.S
+    lo = np.full(prob.n_params, -np.inf)
+    hi = np.full(prob.n_params, np.inf)
+    lo[1:3] = 0.5
+    lo[4] = 1.0
+    lo[5 + NN:5 + NN + S] = 0.0
+    x0 = synth.f32(np.maximum(synth.psf_eval_point(prob, "init", rng), lo))
+
+    def fun(q):
+        loss, g = ora.psf_loss_grad(prob, d, w, q)
+        return loss[2], g
+    errs, fd, fs = _lbfgsb_tracks(fun, plan, x0, lo, hi, 20, "lbfgsb psf")
+    assert max(errs[:5]) <= 1e-4
+    assert abs(fd - fs) <= 1e-3 * abs(fs)
+
+
+# --------------------------------------------------------------------------- #
+# Edge cases: no point sources, a single starlet plane, sources at frame edges #
+# --------------------------------------------------------------------------- #
+
+def _edge_case(name):
+    if name == "no_sources":
+        return synth.make_small_deconv(91, 3, [16, 12, 20], [9, 8, 5], 2, 48, 0, 4)
+    if name == "one_plane":
+        prob = synth.make_small_deconv(92, 3, [16, 12, 20], [9, 8, 5], 2, 48, 1, 1)
+        return synth.DeconvProblem(**{**prob.__dict__, "W": synth.f32([2.5])})
+    # sources within 8 px of the windows' edges (and one just outside the smallest
+    # window), where the +-8 px evaluation box of r meets the window crop
+    prob = synth.make_small_deconv(93, 3, [16, 12, 20], [9, 8, 5], 2, 48, 3, 4)
+    return synth.DeconvProblem(**{**prob.__dict__, "c": synth.f32([6.3, 20.7, 44.6, 30.2, 10.8, 13.1])})
+
+
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+@pytest.mark.parametrize("name", ["no_sources", "one_plane", "sources_at_edges"])
+def test_loss_grad_parity_edge_cases(name, algo):
+    prob = _edge_case(name)
+    d, w, rng = _data(prob, seed=94)
+    plan = _plan(prob, d, w, algo)
+    for point in ("init", "near"):
+        p = synth.eval_point(prob, point, rng)
+        _compare_loss_grad(prob, d, w, p, plan, f"edge {name}/{ALGO_ID[algo]}/{point}")
