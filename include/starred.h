@@ -298,9 +298,12 @@ int starred_get_class_info(const starred_plan *plan, int32_t c, starred_class_in
  * starred_autotune_info reports the host milliseconds of the tuning that made the
  * plan's decision (0 when none ran; with a cached decision, the time of the tuning
  * that filled the cache), whether the decision came from the cache, and the launch
- * shapes in use (any pointer may be NULL). */
+ * shapes in use: work groups aimed at by the frequency-domain adjoint and by the
+ * line passes, frames per adjoint chunk, and whether the one-launch forward runs on
+ * a stream of its own (any pointer may be NULL). */
 int starred_autotune_info(const starred_plan *plan, double *wall_ms_out, int32_t *cached_out,
-                          int32_t *adj_blocks_out, int32_t *line_groups_out);
+                          int32_t *adj_blocks_out, int32_t *line_groups_out, int32_t *adj_frames_out,
+                          int32_t *split_forward_out);
 
 /* Per-frame shifts and rotations (the joint processing of epochs that differ by a
  * shift and a rotation, as in the paper's conclusions; the per-epoch dithering
@@ -317,6 +320,18 @@ int starred_autotune_info(const starred_plan *plan, double *wall_ms_out, int32_t
  * them and restores the previous choices. Drops captured graphs. The plain baseline
  * does not support them. */
 int starred_set_frame_transforms(starred_plan *plan, const float *xf, float *grad_xf);
+
+/* Launch shapes of the deconvolution FFT path (what the autotuner chooses; 0 keeps
+ * the current value): adj_frames, frames per chunk of the frequency-domain adjoint
+ * (2 or 4; 8 with at most one point source); adj_blocks, work groups its launch aims
+ * at; line_groups, work groups a line pass aims at; split_forward (-1 keeps it): 1
+ * runs the one-launch forward of the smaller classes on a second stream of the plan,
+ * beside the line passes of the larger ones (forked from and joined back into the
+ * plan's stream, also inside captured graphs), 0 runs everything in order. Results
+ * agree up to rounding for every choice (bitwise for split_forward). Drops captured
+ * graphs. EINVAL for other values. */
+int starred_set_fft_shapes(starred_plan *plan, int32_t adj_frames, int32_t adj_blocks, int32_t line_groups,
+                           int32_t split_forward);
 
 /* Force the algorithm of shape class c: STARRED_CONV_DIRECT, or STARRED_CONV_FFT with
  * the one-launch forward (fused = 1, where it fits) or the line passes (fused = 0).

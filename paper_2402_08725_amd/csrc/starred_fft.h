@@ -13,8 +13,9 @@ constexpr int kFftTargetElems = 2048;  // complex elements per work group and bu
 constexpr int kFusedThreads = 1024;     // one-launch forward: threads per frame
 constexpr size_t kFusedLdsMax = 150 * 1024;  // one-launch forward: LDS of its two Q x (Q+1) planes
 constexpr int kFwdFrames = 4;          // spectral product: frames whose loads are issued together
-constexpr int kAdjFrames = 2;          // spectral adjoint: frames of a work group (a chunk)
-constexpr int kAdjSB = 4;              // spectral adjoint: sources per pass over the rows
+constexpr int kAdjFrames = 2;          // spectral adjoint: frames of a work group (a chunk), default
+constexpr int kAdjMaxFrames = 8;       // spectral adjoint: most frames of a chunk
+constexpr int kAdjSB = 4;              // spectral adjoint: sources per pass over the rows (M > 1)
 constexpr int kAdjBlocks = 512;        // spectral adjoint: work groups aimed at per launch
 constexpr int kAdjMinRows = 4;         // spectral adjoint: fewest rows per thread
 constexpr int kAdjMaxRows = 64;        // spectral adjoint: most rows per work group
@@ -108,9 +109,9 @@ struct AdjItem {
     int P, Q;
     int pb;                      // row range index (the per-frame partial slot)
     int pad;
-    int fid[kAdjFrames];         // frame indices (-1 past nf)
-    long long soff[kAdjFrames];  // kernel spectra S'' (frame 0's slot past nf)
-    long long roff[kAdjFrames];  // rho_hat (frame 0's slot past nf)
+    int fid[kAdjMaxFrames];         // frame indices (-1 past nf)
+    long long soff[kAdjMaxFrames];  // kernel spectra S'' (frame 0's slot past nf)
+    long long roff[kAdjMaxFrames];  // rho_hat (frame 0's slot past nf)
     long long tab_off;           // the class's factor tables
     long long gout;              // the chunk's slot in the chunk spectra
 };
@@ -140,6 +141,7 @@ struct FftPlanDev {
     int n_frames = 0;
     AdjItem *aspec = nullptr;
     int n_aspec = 0;
+    int adj_fc = kAdjFrames;   // frames per chunk of the current items
     int maxpb = 0;           // per-frame partial slots (largest nrr)
     long long total_bins = 0;  // sum over classes of P (P/2 + 1)
     double *apart = nullptr; // [E][maxpb][1 + 3M]

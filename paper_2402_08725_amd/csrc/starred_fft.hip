@@ -785,6 +785,23 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
     float2 *a = sm;
     float2 *b = sm + np * Ls;
     const int tot = np * Q;
+    // the data and weights of this thread's first kRowPre residual elements, loaded
+    // now so that they arrive during the inverse transform
+    constexpr int kRowPre = 4;
+    float pd[kRowPre][2], pw[kRowPre][2];
+    #pragma unroll
+    for (int k = 0; k < kRowPre; ++k) {
+        const int e = threadIdx.x + k * blockDim.x;
+        const int l = e / Q, x = e - l * Q;
+        #pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            // (no loads at all when only the model is written: data may be NULL then)
+            const bool ok = !model && e < tot && x < n && 2 * l + u < it.nl;
+            const long long idx = f.data_off + (long long)(it.line0 + 2 * l + u) * n + x;
+            pd[k][u] = ok ? data[idx] : 0.f;
+            pw[k][u] = ok ? invvar[idx] : 0.f;
+        }
+    }
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
         const int l = e / Q, kx = e - l * Q;
         const float2 *row0 = T + f.t_off + (long long)(it.line0 + 2 * l) * H;
@@ -800,7 +817,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
     float2 *r = lds_fft_any<true>(a, b, np, fl, tw + fl.tw_off);
     float2 *o = (r == a) ? b : a;
     double chi = 0.0;
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    for (int k = 0, e = threadIdx.x; e < tot; ++k, e += blockDim.x) {
         const int l = e / Q, x = e - l * Q;
         float v[2] = {0.f, 0.f};
         if (x < n) {
@@ -814,8 +831,18 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
                 if (model) {
                     model[idx] = mm[u];
                 } else {
-                    const float res = mm[u] - data[idx];
-                    const float w = invvar[idx];
+                    float dv = 0.f, w = 0.f;
+                    #pragma unroll
+                    for (int kk = 0; kk < kRowPre; ++kk)
+                        if (kk == k) {
+                            dv = pd[kk][u];
+                            w = pw[kk][u];
+                        }
+                    if (k >= kRowPre) {
+                        dv = data[idx];
+                        w = invvar[idx];
+                    }
+                    const float res = mm[u] - dv;
                     v[u] = w * res;
                     chi += 0.5 * (double)w * (double)res * (double)res;
                 }
@@ -1121,19 +1148,23 @@ __device__ void tables_part(const ClassFft &c, const float2 *__restrict__ tw, co
 // window indicator (dGamma_i), r_k (da_ik) and r_k (X - c_k)/sigma^2 (dc_k, x and y).
 // Those spectra are products ty(Ky) tx(Kx) of 1-D tables, so each dot product is
 //   sum_Kx wgt(Kx) Re( conj(tx(Kx)) V_ty(Kx) ),  V_ty(Kx) = sum_Ky G(Ky, Kx) conj(ty(Ky)),
-// with one column sum V per y-table (window, gy_k, dgy_k). A block takes kAdjFrames
-// frames and a range of rows; a thread owns columns Kx (lanes) and every RG-th row
+// with one column sum V per y-table (window, gy_k, dgy_k). A block takes FC frames
+// (a chunk) and a range of rows, SB sources per pass (one when M <= 1); a thread owns columns Kx (lanes) and every RG-th row
 // of the range, accumulates V over its rows, folds it with the x-tables, and the
 // block reduces the dot products once per group of kAdjSB sources through LDS.
 // The per-block partials are summed per frame (and the chunk spectra over chunks)
 // by k_adj_sums.
+template <int FC, int SB>
 __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restrict__ items,
                                                           const float2 *__restrict__ Sp,
                                                           const float2 *__restrict__ Rh,
                                                           const float2 *__restrict__ tab, int M, int maxpb,
                                                           float2 *__restrict__ Gp, double *__restrict__ part)
 {
-    constexpr int FC = kAdjFrames, SB = kAdjSB, NY = 1 + 2 * SB, NQ = 1 + 3 * SB;
+    constexpr int NY = 1 + 2 * SB, NQ = 1 + 3 * SB;
+    // rows of a thread whose loads are issued together: about 12-16 loads in flight
+    constexpr int RB = FC >= 8 ? 1 : (FC >= 4 ? 2 : kAdjRB);
+    static_assert(FC <= kAdjMaxFrames, "chunk larger than the work items hold");
     constexpr int kRow = kFftThreads + 8;  // padded LDS rows of per-thread partials
     static_assert(FC * NQ <= 2 * 32, "two reduction passes of 32 quantities");
     __shared__ float red[32 * kRow];
@@ -1187,12 +1218,12 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restr
             const int rx = lo ? kxq : Q - kxq;
             const float cj = lo ? 1.f : -1.f;
             int ryq = (y0 + rg) % Q;
-            // kAdjRB rows of this thread at a time: every load of the batch is issued
+            // RB rows of this thread at a time: every load of the batch is issued
             // before the first is used (a row group is whole waves, so the row tests are uniform)
-            for (int Kb = y0 + rg; Kb < y1; Kb += kAdjRB * RG) {
-                float2 sv[kAdjRB][FC], rv[kAdjRB][FC];
+            for (int Kb = y0 + rg; Kb < y1; Kb += RB * RG) {
+                float2 sv[RB][FC], rv[RB][FC];
                 #pragma unroll
-                for (int b = 0; b < kAdjRB; ++b) {
+                for (int b = 0; b < RB; ++b) {
                     const int Ky = min(Kb + b * RG, y1 - 1);  // rows past the range reload a valid bin
                     const long long bin = (long long)Ky * HP + Kx;
                     const int ridx = (lo ? ryq : (ryq == 0 ? 0 : Q - ryq)) * HQ + rx;
@@ -1205,7 +1236,7 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restr
                     }
                 }
                 #pragma unroll
-                for (int b = 0; b < kAdjRB; ++b) {
+                for (int b = 0; b < RB; ++b) {
                     const int Ky = Kb + b * RG;
                     if (Ky >= y1) break;
                     float2 ty[NY];
@@ -1591,8 +1622,21 @@ hipError_t fft_adj_rows(hipStream_t st, const FftPlanDev &d, float *g)
 hipError_t fft_spec_adj(hipStream_t st, const FftPlanDev &d, int M)
 {
     if (d.n_aspec == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spec_adj, dim3(d.n_aspec), dim3(kFftThreads), 0, st, d.aspec, d.S, d.Rh, d.tab, M,
-                       d.maxpb, d.Gp, d.apart);
+    const dim3 g(d.n_aspec), b(kFftThreads);
+    if (M <= 1) {
+        switch (d.adj_fc) {
+        case 2: hipLaunchKernelGGL((k_spec_adj<2, 1>), g, b, 0, st, d.aspec, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart); break;
+        case 4: hipLaunchKernelGGL((k_spec_adj<4, 1>), g, b, 0, st, d.aspec, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart); break;
+        case 8: hipLaunchKernelGGL((k_spec_adj<8, 1>), g, b, 0, st, d.aspec, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (d.adj_fc) {
+        case 2: hipLaunchKernelGGL((k_spec_adj<2, kAdjSB>), g, b, 0, st, d.aspec, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart); break;
+        case 4: hipLaunchKernelGGL((k_spec_adj<4, kAdjSB>), g, b, 0, st, d.aspec, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
     return hipGetLastError();
 }
 

@@ -128,7 +128,7 @@ struct starred_plan {
     int n_fft_chi = 0;
     // launch shapes of the FFT path: work groups aimed at by the spectral adjoint
     // and by the line passes (the autotuner may change them)
-    int adj_blocks = kAdjBlocks, line_groups = 1024;
+    int adj_blocks = kAdjBlocks, line_groups = 1024, adj_fc = kAdjFrames;
     // frames of the classes that run the direct algorithm, and their LDS extents
     std::vector<int> fdir;
     int *d_fdir = nullptr;
@@ -171,6 +171,11 @@ struct starred_plan {
     // starlet branch: a second stream forked from and joined back into st
     hipStream_t st2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // FFT path: the one-launch forward on a third stream, beside the line passes of
+    // the larger classes (their frames are independent until the adjoint)
+    hipStream_t st3 = nullptr;
+    hipEvent_t ev_fork3 = nullptr, ev_join3 = nullptr;
+    int fwd_split = 1;
     int *d_t = nullptr;
     int next_t = -1;  // step number the device counter will produce next (-1: unknown)
 
@@ -242,6 +247,9 @@ struct starred_plan {
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (st2) (void)hipStreamDestroy(st2);
+        if (ev_fork3) (void)hipEventDestroy(ev_fork3);
+        if (ev_join3) (void)hipEventDestroy(ev_join3);
+        if (st3) (void)hipStreamDestroy(st3);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (void *p : owned) (void)hipFree(p);
         free_lists();
@@ -613,7 +621,8 @@ static int build_fft(starred_plan *p)
         f.t3_off = t3o;
         t3o += (long long)c.P * HP;
     }
-    // frequency-domain adjoint: chunks of kAdjFrames frames; summed spectra per chunk
+    // frequency-domain adjoint: summed spectra per chunk of frames, room for the
+    // smallest chunks (the chunk size is chosen with the work lists)
     long long gp = 0, hc = 0;
     for (ClassFft &cl : p->cls) {
         cl.gfch = kAdjFrames;
@@ -739,11 +748,18 @@ static int build_fft_lists(starred_plan *p)
         if ((rc = p->alloc_list(&d.fused, std::max<size_t>(1, fu.size())))) return rc;
         if (!fu.empty()) HIP_TRY(hipMemcpy(d.fused, fu.data(), sizeof(FusedItem) * fu.size(), hipMemcpyHostToDevice));
     }
-    // frequency-domain adjoint: items over chunks of kAdjFrames frames x ranges of
-    // rows of the P half spectrum, about p->adj_blocks of them per launch
+    // frequency-domain adjoint: items over chunks of p->adj_fc frames x ranges of
+    // rows of the P half spectrum, about p->adj_blocks of them per launch (chunks of
+    // up to 8 frames with one source per pass, up to 4 with four)
     {
+        const int fc = (p->M > 1 && p->adj_fc > 4) ? 4 : p->adj_fc;
+        d.adj_fc = fc;
         std::vector<AdjItem> sp;
         int maxpb = 1, nchunks = 0;
+        for (ClassFft &cl : p->cls) {
+            cl.gfch = fc;
+            cl.ngch = (cl.ncf + fc - 1) / fc;
+        }
         for (int c = 0; c < (int)p->cls.size(); ++c)
             if (!is_direct(c)) nchunks += p->cls[c].ngch;
         for (int c = 0; c < (int)p->cls.size(); ++c) {
@@ -760,17 +776,17 @@ static int build_fft_lists(starred_plan *p)
             cl.arr = arr;
             cl.nrr = (cl.P + arr - 1) / arr;
             maxpb = std::max(maxpb, cl.nrr);
-            for (int f0 = 0; f0 < cl.ncf; f0 += kAdjFrames)
+            for (int f0 = 0; f0 < cl.ncf; f0 += fc)
                 for (int r = 0; r < cl.nrr; ++r) {
                     AdjItem it{};
                     it.cls = c;
-                    it.nf = std::min(kAdjFrames, cl.ncf - f0);
+                    it.nf = std::min(fc, cl.ncf - f0);
                     it.y0 = r * arr;
                     it.y1 = std::min(cl.P, it.y0 + arr);
                     it.P = cl.P;
                     it.Q = cl.Q;
                     it.pb = r;
-                    for (int f = 0; f < kAdjFrames; ++f) {
+                    for (int f = 0; f < kAdjMaxFrames; ++f) {
                         const int fi = f < it.nf ? cls_frames[cl.cf_off + f0 + f] : -1;
                         it.fid[f] = fi;
                         it.soff[f] = fi >= 0 ? p->ffr[fi].s_off : 0;
@@ -970,6 +986,9 @@ int starred_plan_create(const starred_desc *desc, void *stream, starred_plan **p
         hipError_t e = hipStreamCreate(&p->st2);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipStreamCreate(&p->st3);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork3, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join3, hipEventDisableTiming);
         if (e != hipSuccess) {
             delete p;
             return fail_hip(e, "stream/event creation");
@@ -1061,13 +1080,15 @@ int starred_get_class_info(const starred_plan *p, int32_t c, starred_class_info 
 }
 
 int starred_autotune_info(const starred_plan *p, double *wall_ms_out, int32_t *cached_out, int32_t *adj_blocks_out,
-                          int32_t *line_groups_out)
+                          int32_t *line_groups_out, int32_t *adj_frames_out, int32_t *split_forward_out)
 {
+    if (split_forward_out && p) *split_forward_out = p->fwd_split;
     if (!p) return fail(STARRED_EINVAL, "plan is NULL");
     if (wall_ms_out) *wall_ms_out = p->tune_wall_ms;
     if (cached_out) *cached_out = p->tune_cached;
     if (adj_blocks_out) *adj_blocks_out = p->adj_blocks;
     if (line_groups_out) *line_groups_out = p->line_groups;
+    if (adj_frames_out) *adj_frames_out = p->fd.adj_fc;
     return STARRED_OK;
 }
 
@@ -1084,6 +1105,26 @@ int starred_set_class_algo(starred_plan *p, int32_t c, int32_t algo, int32_t fus
     for (int k = 0; k < (int)p->cls.size(); ++k) ch[k] = class_choice(p, k);
     ch[c] = algo == STARRED_CONV_DIRECT ? kChDirect : (fused && p->cls_fits[c] ? kChFused : kChLines);
     return apply_choices(p, ch);
+}
+
+int starred_set_fft_shapes(starred_plan *p, int32_t adj_frames, int32_t adj_blocks, int32_t line_groups,
+                           int32_t split_forward)
+{
+    if (!p) return fail(STARRED_EINVAL, "plan is NULL");
+    if (p->mode != STARRED_DECONV) return fail(STARRED_EUNSUPPORTED, "launch shapes of the deconvolution FFT path");
+    if (adj_frames && adj_frames != 2 && adj_frames != 4 && !(adj_frames == 8 && p->M <= 1))
+        return fail(STARRED_EINVAL, "adj_frames must be 2 or 4 (or 8 with at most one point source)");
+    if (adj_blocks < 0 || adj_blocks > (1 << 20) || line_groups < 0 || line_groups > (1 << 20))
+        return fail(STARRED_EINVAL, "work-group targets must lie in [1, 2^20] (0 keeps the current one)");
+    if (split_forward < -1 || split_forward > 1) return fail(STARRED_EINVAL, "split_forward must be -1, 0 or 1");
+    if (split_forward >= 0) p->fwd_split = split_forward;
+    if (adj_frames) p->adj_fc = adj_frames;
+    if (adj_blocks) p->adj_blocks = adj_blocks;
+    if (line_groups) p->line_groups = line_groups;
+    p->drop_graphs();
+    // taken up by the next list build (binding frames, or a class moving onto the FFT path)
+    if (p->algo != STARRED_CONV_FFT || !p->data || p->cls.empty()) return STARRED_OK;
+    return build_fft_lists(p);
 }
 
 int starred_set_frame_transforms(starred_plan *p, const float *xf, float *grad_xf)
@@ -1273,6 +1314,8 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     const double *part_chi = p->d_part_chi_fft;
     int n_l1 = 0;
     const bool fused = fft && p->fft_fused && p->fd.n_fused > 0;
+    // the one-launch forward beside the line passes when both have frames
+    const bool split = fused && p->fwd_split && p->fd.frows_lg.n_items > 0;
     // one class covering the whole grid: the row inverse of dL/dh carries the final
     // reductions and the update (one launch fewer)
     const bool fin_rows = fft && !dir && grad && p->fd.n_classes == 1 && p->cls[0].F == p->N;
@@ -1320,10 +1363,17 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         // chi-square partials: the line-pass frames' row groups, then one per fused frame
         const int n_rows = fused ? p->fd.frows_lg.n_items : p->fd.frows.n_items;
         if (fused) {
-            e1 = p->prof_start();
-            HIP_TRY(fft_fused_fwd(p->st, p->fd, params, p->N, p->E, p->M, p->s, p->data, p->invvar,
+            hipStream_t sf = p->st;
+            if (split) {
+                HIP_TRY(hipEventRecord(p->ev_fork3, p->st));
+                HIP_TRY(hipStreamWaitEvent(p->st3, p->ev_fork3, 0));
+                sf = p->st3;
+            }
+            e1 = p->prof_start(sf);
+            HIP_TRY(fft_fused_fwd(sf, p->fd, params, p->N, p->E, p->M, p->s, p->data, p->invvar,
                                   p->d_part_chi_fft + n_rows, ride ? &pc : nullptr));
-            p->prof_stop(STARRED_STAGE_FFT_FUSED, e1);
+            p->prof_stop(STARRED_STAGE_FFT_FUSED, e1, sf);
+            if (split) HIP_TRY(hipEventRecord(p->ev_join3, p->st3));
         }
         e1 = p->prof_start();
         HIP_TRY(fft_spec_fwd(p->st, p->fd, params, p->N, p->E, p->M, p->s, fused));
@@ -1363,6 +1413,7 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
             hipEvent_t e1 = p->prof_start();
             HIP_TRY(fused ? fft_rho_cols_lg(p->st, p->fd) : fft_rho_cols(p->st, p->fd));
             p->prof_stop(STARRED_STAGE_FFT_RCOLS, e1);
+            if (split) HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join3, 0));
             e1 = p->prof_start();
             HIP_TRY(fft_spec_adj(p->st, p->fd, p->M));
             p->prof_stop(STARRED_STAGE_FFT_ACOLS, e1);
@@ -1388,6 +1439,7 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
             p->prof_stop(STARRED_STAGE_GRAD_SUMS, e0);
         }
     }
+    if (split && !grad) HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join3, 0));
     if (!ride) HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
     e0 = p->prof_start();
     if (fin_rows) {
@@ -1436,7 +1488,7 @@ constexpr double kTuneGain = 0.98;
 
 struct TuneEntry {
     std::vector<int> choice;
-    int adj_blocks = kAdjBlocks, line_groups = 1024;
+    int adj_blocks = kAdjBlocks, line_groups = 1024, adj_fc = kAdjFrames, fwd_split = 1;
     std::vector<std::array<double, 3>> tried;  // the timings the decision came from
     double wall_ms = 0.0;                      // how long that tuning took
 };
@@ -1487,6 +1539,8 @@ static int autotune(starred_plan *p)
         if (it != g_tune_cache.end()) {
             p->adj_blocks = it->second.adj_blocks;
             p->line_groups = it->second.line_groups;
+            p->adj_fc = it->second.adj_fc;
+            p->fwd_split = it->second.fwd_split;
             p->tune_cached = 1;
             p->cls_tune = it->second.tried;
             p->tune_wall_ms = it->second.wall_ms;
@@ -1545,14 +1599,20 @@ static int autotune(starred_plan *p)
         if (!rc) p->cls_tune[c][ch[c]] = best;
     }
     if (!rc) rc = apply_choices(p, ch);
-    // launch shapes of the FFT path
+    // launch shapes of the FFT path: frames per adjoint chunk, adjoint work groups,
+    // line-pass work groups, the one-launch forward on its own stream or not
     if (!rc && p->algo == STARRED_CONV_FFT) {
-        for (int which = 0; which < 2 && !rc; ++which) {
-            int &knob = which == 0 ? p->adj_blocks : p->line_groups;
+        for (int which = 0; which < 4 && !rc; ++which) {
+            int &knob = which == 0 ? p->adj_fc
+                        : which == 1 ? p->adj_blocks
+                        : which == 2 ? p->line_groups
+                                     : p->fwd_split;
             const int keep = knob;
             int best_v = keep;
-            const std::vector<int> cands = which == 0 ? std::vector<int>{256, 512, 1024, 2048}
-                                                      : std::vector<int>{512, 1024, 2048};
+            const std::vector<int> cands = which == 0   ? (p->M > 1 ? std::vector<int>{2, 4} : std::vector<int>{2, 4, 8})
+                                           : which == 1 ? std::vector<int>{256, 512, 1024, 2048}
+                                           : which == 2 ? std::vector<int>{512, 1024, 2048}
+                                                        : std::vector<int>{0, 1};
             for (int v : cands) {
                 if (v == keep) continue;
                 knob = v;
@@ -1582,6 +1642,8 @@ static int autotune(starred_plan *p)
         e.choice = ch;
         e.adj_blocks = p->adj_blocks;
         e.line_groups = p->line_groups;
+        e.adj_fc = p->adj_fc;
+        e.fwd_split = p->fwd_split;
         e.tried = p->cls_tune;
         e.wall_ms = p->tune_wall_ms;
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -2214,6 +2276,8 @@ int starred_time_stage(starred_plan *p, const float *params, int32_t stage, int3
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
     const bool fft = (p->algo == STARRED_CONV_FFT);
     const bool fused = fft && p->fft_fused && p->fd.n_fused > 0;
+    // the one-launch forward beside the line passes when both have frames
+    const bool split = fused && p->fwd_split && p->fd.frows_lg.n_items > 0;
     int n_l1 = 0;
     auto launch = [&]() -> int {
         switch (stage) {

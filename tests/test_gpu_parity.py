@@ -1146,6 +1146,61 @@ def test_mixed_class_algorithms_graph_steps_match_eager():
     assert abs(lf[2].item() - lm[2].item()) <= 1e-6 * abs(lf[2].item())
 
 
+@pytest.mark.parametrize("case,fcs", [("cfg4_sub", (2, 4, 8)), ("cfg2_E5", (2, 4))])
+def test_fft_adjoint_chunk_sizes(case, fcs):
+    """The frequency-domain adjoint with 2, 4 and 8 frames per chunk (8 only with one
+    point source), including a last chunk that is not full, against the oracle and
+    against each other."""
+    st = _st()
+    prob = synth.make_deconv(4, E=13) if case == "cfg4_sub" else synth.make_deconv(2, E=5)
+    d, w, rng = _data(prob, seed=71)
+    plan = _plan(prob, d, w, algo=st.CONV_FFT)
+    p = synth.eval_point(prob, "near", rng)
+    grads = []
+    for fc in fcs:
+        plan.set_fft_shapes(adj_frames=fc)
+        assert plan.autotune_info()["adj_frames"] == fc
+        _, g = _compare_loss_grad(prob, d, w, p, plan, f"{case}/adj_frames {fc}")
+        grads.append(g)
+    for g in grads[1:]:
+        assert parity.rel_err(g, grads[0]) <= 1e-5
+    with pytest.raises(RuntimeError):
+        plan.set_fft_shapes(adj_frames=3)
+
+
+@pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
+def test_split_forward_is_bitwise_the_same(graph):
+    """The one-launch forward on the plan's second FFT stream, beside the line passes,
+    gives bitwise the results of the in-order launches (loss, gradient and Adam steps,
+    eager or captured), and matches the oracle."""
+    st = _st()
+    prob = synth.make_deconv(4, E=13)
+    d, w, rng = _data(prob, seed=72)
+    plan = _plan(prob, d, w, algo=st.CONV_FFT)
+    cls = plan.classes()
+    assert any(c["fused"] for c in cls) and any(not c["fused"] for c in cls), cls
+    p0 = synth.eval_point(prob, "near", rng)
+    lr4 = [prob.adam_lr[k] for k in ("h", "Gamma", "a", "c")]
+    runs = []
+    for split in (0, 1):
+        plan.set_fft_shapes(split_forward=split)
+        assert plan.autotune_info()["split_forward"] == split
+        plan.set_graph_mode(graph)
+        x = torch.tensor(p0, dtype=torch.float32, device="cuda")
+        m = torch.zeros_like(x)
+        v = torch.zeros_like(x)
+        l, g = plan.loss_grad(x)
+        l, g = l.clone(), g.clone()
+        for t in range(1, 4):
+            plan.step(x, m, v, t, lr4)
+        torch.cuda.synchronize()
+        runs.append((l, g, x.clone(), m.clone(), v.clone()))
+        plan.set_graph_mode(False)
+    for a, b in zip(runs[0], runs[1]):
+        assert torch.equal(a, b)
+    _compare_loss_grad(prob, d, w, p0, plan, "split forward")
+
+
 def test_autotuner_per_class_choices_cache_and_parity():
     """The automatic choice times each class's alternatives; a second plan of the same
     shapes takes the cached decision; the tuned plan matches the oracle."""
@@ -1167,6 +1222,7 @@ def test_autotuner_per_class_choices_cache_and_parity():
     info2 = plan2.autotune_info()
     assert info2["cached"] and [c["algo"] for c in plan2.classes()] == [c["algo"] for c in cls]
     assert info2["adj_blocks"] == info["adj_blocks"] and info2["line_groups"] == info["line_groups"]
+    assert info2["adj_frames"] == info["adj_frames"]
     p = synth.eval_point(prob, "near", rng)
     _compare_loss_grad(prob, d, w, p, plan, "autotuned cfg4 subset")
 
