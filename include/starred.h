@@ -271,8 +271,9 @@ int starred_conv_algo(const starred_plan *plan);
 /* Shape classes of a deconvolution plan: the frames that share a (data side,
  * kernel side) pair. For each, the convolution algorithm it runs and, on the FFT
  * algorithm, the transform lengths P (fine grid) and Q = P/s (data grid) and
- * whether its forward is the one-launch form (fused = 1) or the batched line
- * passes (0). starred_num_classes returns the count (>= 0) or a negative status;
+ * whether its forward is the one-launch form (fused = 1 with two LDS planes, 2 with
+ * one plane transformed in place, for frames whose two planes do not fit) or the
+ * batched line passes (0). starred_num_classes returns the count (>= 0) or a negative status;
  * starred_get_class_info fills *out for class c in [0, count). */
 typedef struct {
     int32_t n, K, n_frames;
@@ -323,8 +324,8 @@ int starred_set_frame_transforms(starred_plan *plan, const float *xf, float *gra
 
 /* Launch shapes of the deconvolution FFT path (what the autotuner chooses; 0 keeps
  * the current value): adj_frames, frames per chunk of the frequency-domain adjoint
- * (2 or 4; 8 with at most one point source); adj_blocks, work groups its launch aims
- * at; line_groups, work groups a line pass aims at; split_forward (-1 keeps it): 1
+ * (2 or 4; 8 with at most one point source; one summed spectrum per chunk goes
+ * through memory); adj_blocks, work groups its launch aims at; line_groups, work groups a line pass aims at; split_forward (-1 keeps it): 1
  * runs the one-launch forward of the smaller classes on a second stream of the plan,
  * beside the line passes of the larger ones (forked from and joined back into the
  * plan's stream, also inside captured graphs), 0 runs everything in order. Results

@@ -90,7 +90,8 @@ struct SpecItem {
 // transforms' factor tables, later).
 struct FusedItem {
     int frame, cls;
-    int P, Q, n, pad;     // sizes
+    int P, Q, n;          // sizes
+    int inplace;          // one LDS plane transformed in place (else two planes)
     long long tw_off;     // the Q-point twiddles
     long long s_off;      // kernel spectrum S''
     long long data_off;   // data and inverse variances
@@ -201,13 +202,23 @@ hipError_t fft_grad_h_cols(hipStream_t st, const FftPlanDev &d, DensePiece *pd =
 // psum (or null): the composite-filter prior's planes after pass D1, summed per pixel instead of reading prior
 hipError_t fft_grad_h_rows_final(hipStream_t st, const FftPlanDev &d, const float *prior, const FinalArgs &fin,
                                  const DenseStar *psum = nullptr);
-// bytes of LDS the one-launch forward needs for a class: two planes of
-// max(Q/2+1, n) lines of Q+1 values, the Q twiddles and the (1+4M) P table values
-inline size_t fused_lds_bytes(int Q, int n, int P, int M)
+// lines of each LDS plane of the one-launch forward: the Q/2+1 columns of the half
+// spectrum, or the (n+1)/2 pairs of real rows (two rows share a complex transform)
+__host__ __device__ inline int fused_plane_lines(int Q, int n)
 {
-    const int rows = (Q / 2 + 1) > n ? (Q / 2 + 1) : n;
-    return ((size_t)2 * rows * (Q + 1) + Q + (size_t)(1 + 4 * M) * P) * 8;
+    const int pairs = (n + 1) / 2;
+    return (Q / 2 + 1) > pairs ? (Q / 2 + 1) : pairs;
 }
+// bytes of LDS the one-launch forward needs for a class: `planes` (two, or one
+// transformed in place) of fused_plane_lines lines of Q+1 values, the Q twiddles
+// and the (1+4M) P table values
+inline size_t fused_lds_bytes(int Q, int n, int P, int M, int planes = 2)
+{
+    const int rows = fused_plane_lines(Q, n);
+    return ((size_t)planes * rows * (Q + 1) + Q + (size_t)(1 + 4 * M) * P) * 8;
+}
+// transform lengths with a single-plane (in-place) form in the one-launch forward
+__host__ __device__ inline bool fft_ip_length(int L) { return L == 128 || L == 144 || L == 160 || L == 192; }
 hipError_t fft_fused_fwd(hipStream_t st, const FftPlanDev &d, const float *params, int N, int E, int M, int s,
                          const float *data, const float *invvar, double *part_chi, DensePiece *pc = nullptr);
 hipError_t fft_model_cols_lg(hipStream_t st, const FftPlanDev &d);

@@ -248,6 +248,69 @@ __device__ __forceinline__ float2 *fft_ct(float2 *a, float2 *b, int nl, const fl
     }
 }
 
+// Single-plane (in-place) transforms for frames whose two planes do not fit in LDS:
+// each stage reads a thread's butterflies into registers, waits for every thread,
+// then writes the results over the same plane. A thread holds at most KB
+// butterflies (lines at most L/2+1, blocks of kFusedThreads threads).
+template <int R, int L, int NS, bool INV>
+__device__ __forceinline__ void stage_ct_ip(float2 *buf, int nl, const float2 *__restrict__ tw)
+{
+    constexpr int LR = L / R, Ls = L + 1, TS = L / (NS * R);
+    constexpr int KB = ((L / 2 + 1) * LR + kFusedThreads - 1) / kFusedThreads;
+    float2 v[KB][8];
+    int dst[KB];
+    #pragma unroll
+    for (int q = 0; q < KB; ++q) {
+        const int b = threadIdx.x + q * kFusedThreads;
+        dst[q] = -1;
+        if (b < nl * LR) {
+            const int l = b / LR, j = b - l * LR;
+            const float2 *in = buf + l * Ls;
+            const int k = j % NS;
+            #pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = in[j + r * LR];
+            if (NS > 1) {
+                #pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const float2 t = tw[r * k * TS];  // r k TS < L
+                    v[q][r] = INV ? cmulc(v[q][r], t) : cmul(v[q][r], t);
+                }
+            }
+            dft_small<R>(v[q], INV);
+            dst[q] = l * Ls + (j / NS) * NS * R + k;
+        }
+    }
+    __syncthreads();
+    #pragma unroll
+    for (int q = 0; q < KB; ++q)
+        if (dst[q] >= 0) {
+            #pragma unroll
+            for (int r = 0; r < R; ++r) buf[dst[q] + r * NS] = v[q][r];
+        }
+    __syncthreads();
+}
+
+template <int L, bool INV, int I = 0>
+__device__ __forceinline__ void fft_ct_ip(float2 *a, int nl, const float2 *__restrict__ tw)
+{
+    if constexpr (I < ct_nrad(L)) {
+        stage_ct_ip<ct_rad(L, I), L, ct_ns(L, I), INV>(a, nl, tw);
+        fft_ct_ip<L, INV, I + 1>(a, nl, tw);
+    }
+}
+
+template <bool INV>
+__device__ __forceinline__ void lds_fft_ip(float2 *a, int nl, const FftLen &f, const float2 *__restrict__ tw)
+{
+    switch (f.L) {  // the lengths fft_ip_length admits
+    case 128: fft_ct_ip<128, INV>(a, nl, tw); break;
+    case 144: fft_ct_ip<144, INV>(a, nl, tw); break;
+    case 160: fft_ct_ip<160, INV>(a, nl, tw); break;
+    case 192: fft_ct_ip<192, INV>(a, nl, tw); break;
+    default: break;
+    }
+}
+
 // Transform dispatch: compile-time bodies for the common lengths, the runtime
 // Stockham loop otherwise.
 template <bool INV>
@@ -270,6 +333,19 @@ __device__ __forceinline__ float2 *lds_fft_any(float2 *a, float2 *b, int nl, con
     case 576: return fft_ct<576, INV>(a, b, nl, tw);
     default: return lds_fft(a, b, nl, f, tw, INV);
     }
+}
+
+// One-launch forward: two planes (a source and a scratch plane; returns the one
+// holding the result) or, when ip, one plane transformed in place.
+template <bool INV>
+__device__ __forceinline__ float2 *lds_fft_plane(float2 *a, float2 *b, int nl, const FftLen &f,
+                                                 const float2 *__restrict__ tw, bool ip)
+{
+    if (ip) {
+        lds_fft_ip<INV>(a, nl, f, tw);
+        return a;
+    }
+    return lds_fft_any<INV>(a, b, nl, f, tw);
 }
 
 // --------------------------------------------------------------------------
@@ -875,7 +951,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fwd_rows(const LineItem *__rest
 // inverse along x (the model m, Eq. 8), the weighted residual rho and its
 // chi-square partial (Eq. 10), then the forward transforms of rho along x and
 // along y, and writes rho_hat [Q][Q/2+1] to memory for the adjoint. Two LDS
-// planes of max(Q/2+1, n) lines of stride Q+1 alternate as FFT source and
+// planes of max(Q/2+1, (n+1)/2) lines of stride Q+1 alternate as FFT source and
 // scratch; the Q-point twiddles and the class's factor tables sit behind them.
 template <int S, int MS>
 __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const FusedItem *__restrict__ items,
@@ -898,9 +974,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const FusedItem *__
     const FftLen &fl = classes[f.cls].fQ;
     const float2 *twQ = tw + f.tw_off;
     const int P = f.P, Q = f.Q, HQ = Q / 2 + 1, n = f.n, Ls = Q + 1;
-    const int rows = HQ > n ? HQ : n;
-    float2 *A = sm, *B = sm + rows * Ls;
-    float2 *twl = sm + 2 * rows * Ls;
+    const int rows = fused_plane_lines(Q, n);
+    // one plane transformed in place (frames whose two planes exceed the LDS), else two
+    // (not with 5-8 sources held in registers: that form keeps its registers for them)
+    const bool ip = MS != 8 && f.inplace != 0;
+    float2 *A = sm, *B = ip ? sm : sm + rows * Ls;
+    float2 *twl = sm + (ip ? 1 : 2) * rows * Ls;
     float2 *t = twl + Q;
     {
         // the twiddles and the tables: all of a thread's loads issued before its LDS writes
@@ -1009,27 +1088,49 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const FusedItem *__
         }
     }
     __syncthreads();
-    float2 *r = lds_fft_any<true>(A, B, HQ, fl, twQ);  // along ky
+    float2 *r = lds_fft_plane<true>(A, B, HQ, fl, twQ, ip);  // along ky
     float2 *o = (r == A) ? B : A;
     // Rows in pairs (two real rows per complex transform): the inverse of
     // Z = X_2p + i X_2p+1, X_y the Hermitian rows of the column results, is
     // x_2p + i x_2p+1; a missing second row (odd n) is zero.
-    for (int yp = threadIdx.x / Q0L; yp < n2; yp += kFusedThreads / Q0L) {
+    auto pair_in = [&](int yp, int kx) {
         const int ya = 2 * yp, yb = 2 * yp + 1;
-        for (int kx = threadIdx.x % Q0L; kx < Q; kx += Q0L) {
-            const bool lo = kx < HQ;
-            const int col = lo ? kx : Q - kx;
-            float2 xa = r[col * Ls + ya];
-            float2 xb = yb < n ? r[col * Ls + yb] : make_float2(0.f, 0.f);
-            if (!lo) {
-                xa.y = -xa.y;
-                xb.y = -xb.y;
-            }
-            o[yp * Ls + kx] = make_float2(xa.x - xb.y, xa.y + xb.x);  // xa + i xb
+        const bool lo = kx < HQ;
+        const int col = lo ? kx : Q - kx;
+        float2 xa = r[col * Ls + ya];
+        float2 xb = yb < n ? r[col * Ls + yb] : make_float2(0.f, 0.f);
+        if (!lo) {
+            xa.y = -xa.y;
+            xb.y = -xb.y;
         }
+        return make_float2(xa.x - xb.y, xa.y + xb.x);  // xa + i xb
+    };
+    if (!ip) {
+        for (int yp = threadIdx.x / Q0L; yp < n2; yp += kFusedThreads / Q0L)
+            for (int kx = threadIdx.x % Q0L; kx < Q; kx += Q0L) o[yp * Ls + kx] = pair_in(yp, kx);
+    } else {
+        // in place: every value read before any is overwritten (Q in (64, 192]: 128
+        // lanes along a row, 8 row pairs per sweep, at most 97 pairs)
+        constexpr int IY = (192 / 2 + 1 + 7) / 8;
+        float2 hold[IY][2];
+        #pragma unroll
+        for (int iy = 0; iy < IY; ++iy)
+            #pragma unroll
+            for (int ix = 0; ix < 2; ++ix) {
+                const int yp = threadIdx.x / 128 + iy * 8, kx = threadIdx.x % 128 + ix * 128;
+                hold[iy][ix] = (yp < n2 && kx < Q) ? pair_in(yp, kx) : make_float2(0.f, 0.f);
+            }
+        __syncthreads();
+        #pragma unroll
+        for (int iy = 0; iy < IY; ++iy)
+            #pragma unroll
+            for (int ix = 0; ix < 2; ++ix) {
+                const int yp = threadIdx.x / 128 + iy * 8, kx = threadIdx.x % 128 + ix * 128;
+                if (yp < n2 && kx < Q) o[yp * Ls + kx] = hold[iy][ix];
+            }
     }
     __syncthreads();
-    r = lds_fft_any<true>(o, r, n2, fl, twQ);  // along x: model rows 2p, 2p+1 in the real, imaginary parts
+    r = lds_fft_plane<true>(o, r, n2, fl, twQ, ip);  // along x: model rows 2p, 2p+1 in the real, imaginary parts
     o = (r == A) ? B : A;
     double chi = 0.0;
     for (int k = 0, yp = threadIdx.x / Q0L; yp < n2; ++k, yp += kFusedThreads / Q0L)
@@ -1080,25 +1181,42 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const FusedItem *__
         for (int w = 0; w < kFusedThreads / 64; ++w) tchi += red[w];
         part_chi[blockIdx.x] = tchi;
     }
-    r = lds_fft_any<false>(o, r, n2, fl, twQ);  // rho pairs along x
+    r = lds_fft_plane<false>(o, r, n2, fl, twQ, ip);  // rho pairs along x
     o = (r == A) ? B : A;
     // split each pair's spectrum Z into the two rows' (Hermitian) spectra,
     // R_a = (Z(k) + conj Z(-k)) / 2 and R_b = (Z(k) - conj Z(-k)) / 2i, and lay the
     // half spectra out column-major with zero rows y >= n
-    if (colw) {
-        const int km = lane == 0 ? 0 : Q - lane;
-        for (int y = rg; y < Q; y += RGF) {
-            float2 v = make_float2(0.f, 0.f);
-            if (y < n) {
-                const float2 z = r[(y >> 1) * Ls + lane], zm = r[(y >> 1) * Ls + km];
-                v = (y & 1) ? make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x))
-                            : make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
-            }
-            o[lane * Ls + y] = v;
+    const int km = lane == 0 ? 0 : Q - lane;
+    auto split_at = [&](int y) {
+        float2 v = make_float2(0.f, 0.f);
+        if (y < n) {
+            const float2 z = r[(y >> 1) * Ls + lane], zm = r[(y >> 1) * Ls + km];
+            v = (y & 1) ? make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x))
+                        : make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+        }
+        return v;
+    };
+    if (!ip) {
+        if (colw)
+            for (int y = rg; y < Q; y += RGF) o[lane * Ls + y] = split_at(y);
+    } else {
+        // in place: at most 192 rows over at least 10 row groups (Q/2+1 <= 97 lanes)
+        constexpr int IS = (192 + 9) / 10;
+        float2 hold[IS];
+        #pragma unroll
+        for (int i2 = 0; i2 < IS; ++i2) {
+            const int y = rg + i2 * RGF;
+            hold[i2] = (colw && y < Q) ? split_at(y) : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int i2 = 0; i2 < IS; ++i2) {
+            const int y = rg + i2 * RGF;
+            if (colw && y < Q) o[lane * Ls + y] = hold[i2];
         }
     }
     __syncthreads();
-    r = lds_fft_any<false>(o, r, HQ, fl, twQ);  // along y
+    r = lds_fft_plane<false>(o, r, HQ, fl, twQ, ip);  // along y
     float2 *R = Rh + f.r_off;
     if (colw)
         for (int ky = rg; ky < Q; ky += RGF) R[ky * HQ + lane] = r[lane * Ls + ky];
@@ -1148,8 +1266,8 @@ __device__ void tables_part(const ClassFft &c, const float2 *__restrict__ tw, co
 // window indicator (dGamma_i), r_k (da_ik) and r_k (X - c_k)/sigma^2 (dc_k, x and y).
 // Those spectra are products ty(Ky) tx(Kx) of 1-D tables, so each dot product is
 //   sum_Kx wgt(Kx) Re( conj(tx(Kx)) V_ty(Kx) ),  V_ty(Kx) = sum_Ky G(Ky, Kx) conj(ty(Ky)),
-// with one column sum V per y-table (window, gy_k, dgy_k). A block takes FC frames
-// (a chunk) and a range of rows, SB sources per pass (one when M <= 1); a thread owns columns Kx (lanes) and every RG-th row
+// with one column sum V per y-table (window, gy_k, dgy_k). A block takes a chunk of
+// FC frames and a range of rows, SB sources per pass (one when M <= 1); a thread owns columns Kx (lanes) and every RG-th row
 // of the range, accumulates V over its rows, folds it with the x-tables, and the
 // block reduces the dot products once per group of kAdjSB sources through LDS.
 // The per-block partials are summed per frame (and the chunk spectra over chunks)
@@ -1166,8 +1284,10 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restr
     constexpr int RB = FC >= 8 ? 1 : (FC >= 4 ? 2 : kAdjRB);
     static_assert(FC <= kAdjMaxFrames, "chunk larger than the work items hold");
     constexpr int kRow = kFftThreads + 8;  // padded LDS rows of per-thread partials
+    // rows of per-thread partials reduced per pass (LDS kept small for occupancy)
+    constexpr int NRED = FC * NQ < 32 ? FC * NQ : 32;
     static_assert(FC * NQ <= 2 * 32, "two reduction passes of 32 quantities");
-    __shared__ float red[32 * kRow];
+    __shared__ float red[NRED * kRow];
     const AdjItem &it = items[blockIdx.x];
     const int P = it.P, Q = it.Q, HP = P / 2 + 1;
     const int y0 = it.y0, y1 = it.y1, pb = it.pb;
@@ -1176,15 +1296,6 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restr
     const int lane = threadIdx.x % CX, rg = threadIdx.x / CX;
     const float2 *t = tab + it.tab_off;
     const int Q3 = 1 + 3 * M;
-    // spectra of the chunk's frames (a missing frame reads frame 0's slot and is zeroed)
-    int fid[FC];
-    long long soff[FC], roff[FC];
-    #pragma unroll
-    for (int f = 0; f < FC; ++f) {
-        fid[f] = it.fid[f];
-        soff[f] = it.soff[f];
-        roff[f] = it.roff[f];
-    }
     float2 *gout = Gp + it.gout;
     const int HQ = Q / 2 + 1, nr = y1 - y0;
     __shared__ float2 tys[NY * kAdjMaxRows];  // y-tables of the block's rows
@@ -1201,6 +1312,15 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restr
             tys[u * kAdjMaxRows + r] = v;
         }
         __syncthreads();
+        // spectra of the chunk's frames (a missing frame reads frame 0's slot and is zeroed)
+        int fid[FC];
+        long long soff[FC], roff[FC];
+        #pragma unroll
+        for (int f = 0; f < FC; ++f) {
+            fid[f] = it.fid[f];
+            soff[f] = it.soff[f];
+            roff[f] = it.roff[f];
+        }
         float dot[FC][NQ];
         #pragma unroll
         for (int f = 0; f < FC; ++f)
@@ -1283,14 +1403,14 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restr
             }
         }
         // block reduction of FC x NQ quantities in passes of 32 rows
-        for (int p0 = 0; p0 < FC * NQ; p0 += 32) {
+        for (int p0 = 0; p0 < FC * NQ; p0 += NRED) {
             #pragma unroll
             for (int v = 0; v < FC * NQ; ++v)
-                if (v >= p0 && v < p0 + 32) red[(v - p0) * kRow + threadIdx.x] = dot[v / NQ][v % NQ];
+                if (v >= p0 && v < p0 + NRED) red[(v - p0) * kRow + threadIdx.x] = dot[v / NQ][v % NQ];
             __syncthreads();
             const int pr = threadIdx.x >> 3, j = threadIdx.x & 7, v = p0 + pr;
             double acc = 0.0;
-            if (v < FC * NQ) {
+            if (pr < NRED && v < FC * NQ) {
                 const float *rr = red + pr * kRow;
                 #pragma unroll 8
                 for (int u = j; u < kFftThreads; u += 8) acc += (double)rr[u];
@@ -1298,7 +1418,7 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restr
             acc += __shfl_xor(acc, 1, 8);
             acc += __shfl_xor(acc, 2, 8);
             acc += __shfl_xor(acc, 4, 8);
-            if (j == 0 && v < FC * NQ) {
+            if (j == 0 && pr < NRED && v < FC * NQ) {
                 const int f = v / NQ, ql = v % NQ;
                 // local quantity -> global index: window, da_k, dcx_k, dcy_k
                 int q = -1;
@@ -1623,20 +1743,24 @@ hipError_t fft_spec_adj(hipStream_t st, const FftPlanDev &d, int M)
 {
     if (d.n_aspec == 0) return hipSuccess;
     const dim3 g(d.n_aspec), b(kFftThreads);
+#define SPEC_ADJ(FC, SB)                                                                               \
+    hipLaunchKernelGGL((k_spec_adj<FC, SB>), g, b, 0, st, d.aspec, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, \
+                       d.apart)
     if (M <= 1) {
         switch (d.adj_fc) {
-        case 2: hipLaunchKernelGGL((k_spec_adj<2, 1>), g, b, 0, st, d.aspec, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart); break;
-        case 4: hipLaunchKernelGGL((k_spec_adj<4, 1>), g, b, 0, st, d.aspec, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart); break;
-        case 8: hipLaunchKernelGGL((k_spec_adj<8, 1>), g, b, 0, st, d.aspec, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart); break;
+        case 2: SPEC_ADJ(2, 1); break;
+        case 4: SPEC_ADJ(4, 1); break;
+        case 8: SPEC_ADJ(8, 1); break;
         default: return hipErrorInvalidValue;
         }
     } else {
         switch (d.adj_fc) {
-        case 2: hipLaunchKernelGGL((k_spec_adj<2, kAdjSB>), g, b, 0, st, d.aspec, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart); break;
-        case 4: hipLaunchKernelGGL((k_spec_adj<4, kAdjSB>), g, b, 0, st, d.aspec, d.S, d.Rh, d.tab, M, d.maxpb, d.Gp, d.apart); break;
+        case 2: SPEC_ADJ(2, kAdjSB); break;
+        case 4: SPEC_ADJ(4, kAdjSB); break;
         default: return hipErrorInvalidValue;
         }
     }
+#undef SPEC_ADJ
     return hipGetLastError();
 }
 

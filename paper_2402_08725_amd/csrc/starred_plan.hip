@@ -123,7 +123,7 @@ struct starred_plan {
     std::vector<FrameFft> ffr;
     std::vector<int> fcls;        // class of each frame
     std::vector<int> cls_frames;  // frames in class order
-    std::vector<int> cls_fits;    // per class: the one-launch forward fits in LDS
+    std::vector<int> cls_fits;    // per class: the one-launch forward fits in LDS (1: two planes, 2: one in place)
     double *d_part_chi_fft = nullptr;  // chi-square partials: FFT groups, then direct tiles
     int n_fft_chi = 0;
     // launch shapes of the FFT path: work groups aimed at by the spectral adjoint
@@ -588,8 +588,14 @@ static int build_fft(starred_plan *p)
     // classes whose Q-grid planes fit in LDS may take the one-launch forward
     p->cls_fits.clear();
     for (auto &c : p->cls) {
-        p->cls_fits.push_back(fused_lds_bytes(c.Q, c.n, c.P, p->M) <= kFusedLdsMax ? 1 : 0);
-        c.fused = p->cls_fits.back();
+        // the one-launch forward: two LDS planes (1), one plane in place (2), or none (0)
+        int fit = 0;
+        if (fused_lds_bytes(c.Q, c.n, c.P, p->M, 2) <= kFusedLdsMax) fit = 1;
+        else if (c.Q > 64 && fft_ip_length(c.Q) && !(p->M > 4 && p->M <= 8) &&
+                 fused_lds_bytes(c.Q, c.n, c.P, p->M, 1) <= kFusedLdsMax)
+            fit = 2;  // (5-8 sources: the source factors take the registers the in-place form needs)
+        p->cls_fits.push_back(fit);
+        c.fused = fit ? 1 : 0;
         c.direct = 0;
     }
     // class-ordered frame list
@@ -722,7 +728,7 @@ static int build_fft_lists(starred_plan *p)
             if (!is_direct(fcls[i]) && p->cls[fcls[i]].fused) {
                 fi.push_back(i);
                 const ClassFft &cl = p->cls[fcls[i]];
-                lds = std::max(lds, fused_lds_bytes(cl.Q, cl.n, cl.P, M));
+                lds = std::max(lds, fused_lds_bytes(cl.Q, cl.n, cl.P, M, p->cls_fits[fcls[i]] == 2 ? 1 : 2));
             }
         std::stable_sort(fi.begin(), fi.end(), [&](int a, int b) { return p->cls[fcls[a]].Q > p->cls[fcls[b]].Q; });
         std::vector<FusedItem> fu;
@@ -735,6 +741,7 @@ static int build_fft_lists(starred_plan *p)
             it.P = cl.P;
             it.Q = cl.Q;
             it.n = cl.n;
+            it.inplace = p->cls_fits[fcls[i]] == 2 ? 1 : 0;
             it.tw_off = cl.fQ.tw_off;
             it.s_off = f.s_off;
             it.data_off = f.data_off;
@@ -752,7 +759,7 @@ static int build_fft_lists(starred_plan *p)
     // rows of the P half spectrum, about p->adj_blocks of them per launch (chunks of
     // up to 8 frames with one source per pass, up to 4 with four)
     {
-        const int fc = (p->M > 1 && p->adj_fc > 4) ? 4 : p->adj_fc;
+        const int fc = p->adj_fc;
         d.adj_fc = fc;
         std::vector<AdjItem> sp;
         int maxpb = 1, nchunks = 0;
@@ -1074,7 +1081,7 @@ int starred_get_class_info(const starred_plan *p, int32_t c, starred_class_info 
     out->algo = cl.direct ? STARRED_CONV_DIRECT : STARRED_CONV_FFT;
     out->P = cl.P;
     out->Q = cl.Q;
-    out->fused = (!cl.direct && p->fft_fused) ? cl.fused : 0;
+    out->fused = (!cl.direct && p->fft_fused && cl.fused) ? p->cls_fits[c] : 0;
     for (int k = 0; k < 3; ++k) out->tune_ms[k] = c < (int)p->cls_tune.size() ? p->cls_tune[c][k] : -1.0;
     return STARRED_OK;
 }
@@ -1107,12 +1114,16 @@ int starred_set_class_algo(starred_plan *p, int32_t c, int32_t algo, int32_t fus
     return apply_choices(p, ch);
 }
 
+// chunk sizes of the frequency-domain adjoint (8 only with at most one point source:
+// four sources per pass need the registers)
+static bool adj_shape_ok(int fc, int M) { return fc == 2 || fc == 4 || (fc == 8 && M <= 1); }
+
 int starred_set_fft_shapes(starred_plan *p, int32_t adj_frames, int32_t adj_blocks, int32_t line_groups,
                            int32_t split_forward)
 {
     if (!p) return fail(STARRED_EINVAL, "plan is NULL");
     if (p->mode != STARRED_DECONV) return fail(STARRED_EUNSUPPORTED, "launch shapes of the deconvolution FFT path");
-    if (adj_frames && adj_frames != 2 && adj_frames != 4 && !(adj_frames == 8 && p->M <= 1))
+    if (adj_frames && !adj_shape_ok(adj_frames, p->M))
         return fail(STARRED_EINVAL, "adj_frames must be 2 or 4 (or 8 with at most one point source)");
     if (adj_blocks < 0 || adj_blocks > (1 << 20) || line_groups < 0 || line_groups > (1 << 20))
         return fail(STARRED_EINVAL, "work-group targets must lie in [1, 2^20] (0 keeps the current one)");
@@ -1483,7 +1494,7 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
 // by timing whole loss+gradient evaluations (one warm-up, kTuneReps timed) on the
 // plan's stream at h = 0 with the bound data. Coordinate descent over the classes,
 // most costly first; a change is kept when it saves more than 2 %.
-constexpr int kTuneReps = 4;
+constexpr int kTuneReps = 8;
 constexpr double kTuneGain = 0.98;
 
 struct TuneEntry {
@@ -1599,20 +1610,34 @@ static int autotune(starred_plan *p)
         if (!rc) p->cls_tune[c][ch[c]] = best;
     }
     if (!rc) rc = apply_choices(p, ch);
-    // launch shapes of the FFT path: frames per adjoint chunk, adjoint work groups,
-    // line-pass work groups, the one-launch forward on its own stream or not
+    // launch shapes of the FFT path: frames per adjoint chunk and adjoint work groups
+    // together (they interact: the chunk count sets the rows per group), then the
+    // line-pass work groups, then the one-launch forward on its own stream or not
     if (!rc && p->algo == STARRED_CONV_FFT) {
-        for (int which = 0; which < 4 && !rc; ++which) {
-            int &knob = which == 0 ? p->adj_fc
-                        : which == 1 ? p->adj_blocks
-                        : which == 2 ? p->line_groups
-                                     : p->fwd_split;
+        const std::vector<int> abs_ = {256, 512, 1024, 2048};
+        const int keep_fc = p->adj_fc, keep_ab = p->adj_blocks;
+        int best_fc = keep_fc, best_ab = keep_ab;
+        for (int fc : {2, 4, 8})
+            for (int ab : abs_) {
+                if (rc || !adj_shape_ok(fc, p->M) || (fc == keep_fc && ab == keep_ab)) continue;
+                p->adj_fc = fc;
+                p->adj_blocks = ab;
+                double ms = 0.0;
+                rc = build_fft_lists(p);
+                if (!rc) rc = time_plan(p, params, loss, a, b, &ms);
+                if (!rc && ms < kTuneGain * best) {
+                    best = ms;
+                    best_fc = fc;
+                    best_ab = ab;
+                }
+            }
+        p->adj_fc = best_fc;
+        p->adj_blocks = best_ab;
+        for (int which = 0; which < 2 && !rc; ++which) {
+            int &knob = which == 0 ? p->line_groups : p->fwd_split;
             const int keep = knob;
             int best_v = keep;
-            const std::vector<int> cands = which == 0   ? (p->M > 1 ? std::vector<int>{2, 4} : std::vector<int>{2, 4, 8})
-                                           : which == 1 ? std::vector<int>{256, 512, 1024, 2048}
-                                           : which == 2 ? std::vector<int>{512, 1024, 2048}
-                                                        : std::vector<int>{0, 1};
+            const std::vector<int> cands = which == 0 ? std::vector<int>{512, 1024, 2048} : std::vector<int>{0, 1};
             for (int v : cands) {
                 if (v == keep) continue;
                 knob = v;

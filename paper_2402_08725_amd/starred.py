@@ -232,7 +232,7 @@ class Plan:
     def autotune_info(self):
         """Host ms of the last autotuning, whether it came from the cache, launch shapes."""
         ms, cached = ctypes.c_double(0.0), ctypes.c_int32(0)
-        ab, lg, af, sf = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        ab, lg, af, sf = (ctypes.c_int32(0) for _ in range(4))
         _check(lib().starred_autotune_info(self._h, ctypes.byref(ms), ctypes.byref(cached), ctypes.byref(ab),
                                            ctypes.byref(lg), ctypes.byref(af), ctypes.byref(sf)))
         return {"wall_ms": ms.value, "cached": bool(cached.value), "adj_blocks": ab.value,

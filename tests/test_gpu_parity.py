@@ -1164,8 +1164,30 @@ def test_fft_adjoint_chunk_sizes(case, fcs):
         grads.append(g)
     for g in grads[1:]:
         assert parity.rel_err(g, grads[0]) <= 1e-5
-    with pytest.raises(RuntimeError):
-        plan.set_fft_shapes(adj_frames=3)
+    for bad in (3, 16) + ((8,) if prob.M > 1 else ()):
+        with pytest.raises(RuntimeError):
+            plan.set_fft_shapes(adj_frames=bad)
+
+
+def test_inplace_one_launch_forward():
+    """Frames whose two LDS planes do not fit (128^2 data, Q = 160) take the one-launch
+    forward with a single plane transformed in place: against the oracle, and against
+    the same class on the line passes."""
+    st = _st()
+    prob = synth.make_deconv(4, E=13)
+    d, w, rng = _data(prob, seed=73)
+    plan = _plan(prob, d, w, algo=st.CONV_FFT)
+    cls = plan.classes()
+    big = [c for c, ci in enumerate(cls) if ci["n"] == 128]
+    assert big and all(cls[c]["fused"] == 2 for c in big), cls
+    assert all(ci["fused"] == 1 for ci in cls if ci["n"] < 128), cls
+    p = synth.eval_point(prob, "near", rng)
+    _, g_ip = _compare_loss_grad(prob, d, w, p, plan, "in-place forward")
+    for c in big:
+        plan.set_class_algo(c, st.CONV_FFT, fused=False)
+    assert all(plan.classes()[c]["fused"] == 0 for c in big)
+    _, g_lines = _compare_loss_grad(prob, d, w, p, plan, "line passes")
+    assert parity.rel_err(g_ip, g_lines) <= 1e-5
 
 
 @pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
@@ -1177,6 +1199,9 @@ def test_split_forward_is_bitwise_the_same(graph):
     prob = synth.make_deconv(4, E=13)
     d, w, rng = _data(prob, seed=72)
     plan = _plan(prob, d, w, algo=st.CONV_FFT)
+    for c, ci in enumerate(plan.classes()):
+        if ci["n"] == 128:  # the largest stamps onto the line passes
+            plan.set_class_algo(c, st.CONV_FFT, fused=False)
     cls = plan.classes()
     assert any(c["fused"] for c in cls) and any(not c["fused"] for c in cls), cls
     p0 = synth.eval_point(prob, "near", rng)
