@@ -13,6 +13,7 @@ constexpr int kFftTargetElems = 2048;  // complex elements per work group and bu
 constexpr int kFusedThreads = 1024;     // one-launch forward: threads per frame
 constexpr size_t kFusedLdsMax = 150 * 1024;  // one-launch forward: LDS of its two Q x (Q+1) planes
 constexpr int kFwdFrames = 4;          // spectral product: frames whose loads are issued together
+constexpr int kProdPairQ = 128;        // one-launch forward: columns of at least this length load two rows at once
 constexpr int kAdjFrames = 2;          // spectral adjoint: frames of a work group (a chunk), default
 constexpr int kAdjMaxFrames = 8;       // spectral adjoint: most frames of a chunk
 constexpr int kAdjSB = 4;              // spectral adjoint: sources per pass over the rows (M > 1)
@@ -52,7 +53,7 @@ struct ClassFft {
     long long gp_off;   // [ngch][P][P/2+1] summed adjoint spectra of each chunk (total in chunk 0)
     long long hc_off;   // [F][F] the class's contribution to dL/dh (its window)
     int fused;          // frames of this class take the one-launch forward (spectra fit in LDS)
-    int arr;            // spectral adjoint: rows of the half spectrum per work group
+    int arr;            // spectral adjoint: row representatives per work group (2s rows each)
     int nrr;            // spectral adjoint: row ranges (per-frame partial slots)
     int direct;         // the class runs the direct algorithm (the FFT launches skip it)
 };
@@ -106,7 +107,7 @@ struct FusedItem {
 struct AdjItem {
     int cls;
     int nf;                      // frames in the chunk
-    int y0, y1;                  // rows [y0, y1) of the P x (P/2+1) half spectrum
+    int y0, y1;                  // representatives [y0, y1) of the rows (y <= Q/2: rows = +-y mod Q)
     int P, Q;
     int pb;                      // row range index (the per-frame partial slot)
     int pad;

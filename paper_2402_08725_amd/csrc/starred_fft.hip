@@ -1048,12 +1048,25 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const FusedItem *__
             for (int k = 0; k < MR; ++k)
                 px[b][k] = (MS > 0 && k < M) ? cscale(t[(1 + 4 * k) * P + Kx], ai[k]) : make_float2(0.f, 0.f);
         }
-        for (int ky = rg; ky < Q; ky += RGF) {
-            float2 acc = make_float2(0.f, 0.f);
+        // the s^2 alias terms of the model spectrum at (kx, ky), from the loaded bins
+        auto load_row = [&](int ky, float2 (&hv)[S][S], float2 (&sv)[S][S]) {
             #pragma unroll
             for (int a = 0; a < S; ++a) {
                 const int Ky = ky + a * Q;
                 const int rlo = Ky * HP, rhi = (Ky == 0 ? 0 : P - Ky) * HP;
+                #pragma unroll
+                for (int b = 0; b < S; ++b) {
+                    const int hidx = (lob[b] ? rlo : rhi) + rxb[b];
+                    hv[a][b] = Hc[hidx];
+                    sv[a][b] = Si[hidx];
+                }
+            }
+        };
+        auto row_sum = [&](int ky, const float2 (&hv)[S][S], const float2 (&sv)[S][S]) {
+            float2 acc = make_float2(0.f, 0.f);
+            #pragma unroll
+            for (int a = 0; a < S; ++a) {
+                const int Ky = ky + a * Q;
                 const float2 wy = t[Ky];
                 float2 gy[MR];
                 #pragma unroll
@@ -1062,13 +1075,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const FusedItem *__
                 #pragma unroll
                 for (int b = 0; b < S; ++b) {
                     const int Kx = kx + b * Q;
-                    const int hidx = (lob[b] ? rlo : rhi) + rxb[b];
-                    float2 hv = Hc[hidx], sv = Si[hidx];
+                    float2 h = hv[a][b], sk = sv[a][b];
                     if (!lob[b]) {
-                        hv.y = -hv.y;
-                        sv.y = -sv.y;
+                        h.y = -h.y;
+                        sk.y = -sk.y;
                     }
-                    float2 F = cadd(hv, cmul(wy, wxG[b]));
+                    float2 F = cadd(h, cmul(wy, wxG[b]));
                     if (MS > 0) {
                         #pragma unroll
                         for (int k = 0; k < MR; ++k) {
@@ -1081,10 +1093,28 @@ __global__ __launch_bounds__(kFusedThreads) void k_frame_fwd(const FusedItem *__
                             F = cadd(F, cscale(cmul(tk[P + Ky], tk[Kx]), ai[k]));
                         }
                     }
-                    acc = cadd(acc, cmul(sv, F));
+                    acc = cadd(acc, cmul(sk, F));
                 }
             }
-            A[kx * Ls + ky] = acc;
+            return acc;
+        };
+        if (S <= 2 && MS != 8 && Q >= kProdPairQ) {
+            // long columns: the loads of two rows in flight together (the loop is a chain
+            // of memory round trips otherwise)
+            for (int ky0 = rg; ky0 < Q; ky0 += 2 * RGF) {
+                const int ky1 = ky0 + RGF;
+                float2 h0[S][S], s0[S][S], h1[S][S], s1[S][S];
+                load_row(ky0, h0, s0);
+                load_row(ky1 < Q ? ky1 : ky0, h1, s1);  // (past the end: row ky0 again, unused)
+                A[kx * Ls + ky0] = row_sum(ky0, h0, s0);
+                if (ky1 < Q) A[kx * Ls + ky1] = row_sum(ky1, h1, s1);
+            }
+        } else {
+            for (int ky = rg; ky < Q; ky += RGF) {
+                float2 h0[S][S], s0[S][S];
+                load_row(ky, h0, s0);
+                A[kx * Ls + ky] = row_sum(ky, h0, s0);
+            }
         }
     }
     __syncthreads();
@@ -1267,7 +1297,8 @@ __device__ void tables_part(const ClassFft &c, const float2 *__restrict__ tw, co
 // Those spectra are products ty(Ky) tx(Kx) of 1-D tables, so each dot product is
 //   sum_Kx wgt(Kx) Re( conj(tx(Kx)) V_ty(Kx) ),  V_ty(Kx) = sum_Ky G(Ky, Kx) conj(ty(Ky)),
 // with one column sum V per y-table (window, gy_k, dgy_k). A block takes a chunk of
-// FC frames and a range of rows, SB sources per pass (one when M <= 1); a thread owns columns Kx (lanes) and every RG-th row
+// FC frames and the rows of a range of representatives y (rows congruent to y or
+// -y modulo Q, see below), SB sources per pass (one when M <= 1); a thread owns columns Kx (lanes) and every RG-th row
 // of the range, accumulates V over its rows, folds it with the x-tables, and the
 // block reduces the dot products once per group of kAdjSB sources through LDS.
 // The per-block partials are summed per frame (and the chunk spectra over chunks)
@@ -1291,24 +1322,41 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restr
     const AdjItem &it = items[blockIdx.x];
     const int P = it.P, Q = it.Q, HP = P / 2 + 1;
     const int y0 = it.y0, y1 = it.y1, pb = it.pb;
+    // The block's rows: for each representative y in [y0, y1) (0 <= y <= Q/2) the rows
+    // Ky = y + aQ and Ky = (Q - y) + aQ, a < s, i.e. every row whose rho_hat row is y or
+    // its mirror Q - y; local row i: representative i / 2s, a = (i % 2s) / 2, mirrored
+    // when i is odd (no mirrored rows for y = 0 and y = Q/2, which are their own
+    // mirrors). So the s^2 reads of each rho_hat value fall in one block.
+    const int S2 = 2 * (P / Q);
+    const int nloc = S2 * (y1 - y0);
+    auto row_of = [&](int li, bool &valid) {
+        const int y = y0 + li / S2, j = li % S2;
+        const bool mir = j & 1;
+        valid = !(mir && (y == 0 || 2 * y == Q));
+        return (mir && valid ? Q - y : y) + (j >> 1) * Q;
+    };
     // lanes over columns, row groups over rows
     const int CX = adj_lanes(HP), RG = kFftThreads / CX;
     const int lane = threadIdx.x % CX, rg = threadIdx.x / CX;
     const float2 *t = tab + it.tab_off;
     const int Q3 = 1 + 3 * M;
     float2 *gout = Gp + it.gout;
-    const int HQ = Q / 2 + 1, nr = y1 - y0;
+    const int HQ = Q / 2 + 1;
     __shared__ float2 tys[NY * kAdjMaxRows];  // y-tables of the block's rows
     for (int k0 = 0; k0 < max(M, 1); k0 += SB) {
         const int nk = min(SB, M - k0);  // sources of this group (may be 0 when M = 0)
         const bool first = (k0 == 0);
         // y-tables of this group for the block's rows: window, gy_k, dgy_k
-        for (int e = threadIdx.x; e < NY * nr; e += kFftThreads) {
-            const int u = e / nr, r = e - u * nr, Ky = y0 + r;
+        for (int e = threadIdx.x; e < NY * nloc; e += kFftThreads) {
+            const int u = e / nloc, r = e - u * nloc;
+            bool valid;
+            const int Ky = row_of(r, valid);
             float2 v = make_float2(0.f, 0.f);
-            if (u == 0) v = t[Ky];
-            else if (u <= SB) { if (u - 1 < nk) v = t[(1 + 4 * (k0 + u - 1)) * P + P + Ky]; }
-            else if (u - 1 - SB < nk) v = t[(1 + 4 * (k0 + u - 1 - SB)) * P + 3 * P + Ky];
+            if (valid) {
+                if (u == 0) v = t[Ky];
+                else if (u <= SB) { if (u - 1 < nk) v = t[(1 + 4 * (k0 + u - 1)) * P + P + Ky]; }
+                else if (u - 1 - SB < nk) v = t[(1 + 4 * (k0 + u - 1 - SB)) * P + 3 * P + Ky];
+            }
             tys[u * kAdjMaxRows + r] = v;
         }
         __syncthreads();
@@ -1337,18 +1385,22 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restr
             const bool lo = kxq < HQ;
             const int rx = lo ? kxq : Q - kxq;
             const float cj = lo ? 1.f : -1.f;
-            int ryq = (y0 + rg) % Q;
             // RB rows of this thread at a time: every load of the batch is issued
             // before the first is used (a row group is whole waves, so the row tests are uniform)
-            for (int Kb = y0 + rg; Kb < y1; Kb += RB * RG) {
+            for (int ib = rg; ib < nloc; ib += RB * RG) {
                 float2 sv[RB][FC], rv[RB][FC];
+                int kyb[RB];
+                bool okb[RB];
                 #pragma unroll
                 for (int b = 0; b < RB; ++b) {
-                    const int Ky = min(Kb + b * RG, y1 - 1);  // rows past the range reload a valid bin
+                    const int li = ib + b * RG;
+                    bool valid;
+                    const int Ky = row_of(li < nloc ? li : ib, valid);  // (past the range: a row loaded again)
+                    okb[b] = valid && li < nloc;  // (an invalid slot still names a row in range)
+                    kyb[b] = Ky;
+                    const int ryq = Ky % Q;
                     const long long bin = (long long)Ky * HP + Kx;
                     const int ridx = (lo ? ryq : (ryq == 0 ? 0 : Q - ryq)) * HQ + rx;
-                    ryq += RG;
-                    if (ryq >= Q) ryq -= Q;
                     #pragma unroll
                     for (int f = 0; f < FC; ++f) {
                         sv[b][f] = Sp[soff[f] + bin];
@@ -1357,11 +1409,11 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restr
                 }
                 #pragma unroll
                 for (int b = 0; b < RB; ++b) {
-                    const int Ky = Kb + b * RG;
-                    if (Ky >= y1) break;
+                    if (!okb[b]) continue;
+                    const int Ky = kyb[b], li = ib + b * RG;
                     float2 ty[NY];
                     #pragma unroll
-                    for (int u = 0; u < NY; ++u) ty[u] = tys[u * kAdjMaxRows + (Ky - y0)];
+                    for (int u = 0; u < NY; ++u) ty[u] = tys[u * kAdjMaxRows + li];
                     float2 gsum = make_float2(0.f, 0.f);
                     #pragma unroll
                     for (int f = 0; f < FC; ++f) {

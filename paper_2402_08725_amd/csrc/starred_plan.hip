@@ -776,12 +776,15 @@ static int build_fft_lists(starred_plan *p)
             const int HP = cl.P / 2 + 1, nbins = cl.P * HP;
             const int CX = adj_lanes(HP), RG = kFftThreads / CX;
             const int want = std::max(1, (p->adj_blocks + nchunks - 1) / std::max(1, nchunks));
-            int arr = (cl.P + want - 1) / want;
-            // at least kAdjMinRows rows per thread; a multiple of the row groups
-            arr = std::max(kAdjMinRows * RG, ((arr + RG - 1) / RG) * RG);
-            arr = std::min(arr, kAdjMaxRows);  // RG divides kAdjMaxRows
+            // a block takes the 2s rows of each of its representatives y <= Q/2 (the rows
+            // congruent to y or -y modulo Q): at least kAdjMinRows rows per thread, at
+            // most kAdjMaxRows rows
+            const int S2 = 2 * (cl.P / cl.Q), nrep = cl.Q / 2 + 1;
+            const int rows = std::max(kAdjMinRows * RG, (cl.P + want - 1) / want);
+            int arr = std::max(1, (rows + S2 - 1) / S2);
+            arr = std::min(arr, kAdjMaxRows / S2);
             cl.arr = arr;
-            cl.nrr = (cl.P + arr - 1) / arr;
+            cl.nrr = (nrep + arr - 1) / arr;
             maxpb = std::max(maxpb, cl.nrr);
             for (int f0 = 0; f0 < cl.ncf; f0 += fc)
                 for (int r = 0; r < cl.nrr; ++r) {
@@ -789,7 +792,7 @@ static int build_fft_lists(starred_plan *p)
                     it.cls = c;
                     it.nf = std::min(fc, cl.ncf - f0);
                     it.y0 = r * arr;
-                    it.y1 = std::min(cl.P, it.y0 + arr);
+                    it.y1 = std::min(nrep, it.y0 + arr);
                     it.P = cl.P;
                     it.Q = cl.Q;
                     it.pb = r;
