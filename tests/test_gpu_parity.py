@@ -1046,7 +1046,8 @@ def test_pipeline_psf_fits_then_joint_deconvolution():
         err = np.abs(kern_fit[-1] - kern_true[-1]).sum() / np.abs(kern_true[-1]).sum()
         _say(f"pipeline psf {e}: loss {f0:.4e} -> {f1:.4e} (L-BFGS, {ev} evals, kernel L1 error {err1:.2e}) "
              f"-> {f2:.4e} (AdaBelief; at the truth {ft:.4e}), kernel L1 error {err:.2e}")
-        assert f1 < f0 and f2 < f1 and err < 0.3
+        # (measured: L-BFGS kernels within 0.06-0.075 in L1, after AdaBelief 0.05-0.11)
+        assert f1 < f0 and f2 < f1 and err1 < 0.12 and err < 0.16
     dp = synth.make_small_deconv(311, E, [n_star], [K], s, K, M, J)
     dp.kernels = synth.f32(np.concatenate([k.ravel() for k in kern_true]))
     d, w, rng = _data(dp, seed=312)  # the data: true kernels
@@ -1066,8 +1067,10 @@ def test_pipeline_psf_fits_then_joint_deconvolution():
     rel = np.abs(af - at) / np.abs(at)
     _say(f"pipeline deconv: chi2/2 true kernels {lt[0]:.4e}, fitted kernels {lf[0]:.4e}; "
          f"point amplitudes rel diff median {np.median(rel):.3e} max {rel.max():.3e}")
-    assert lf[0] <= 5.0 * lt[0]
-    assert np.median(rel) <= 0.15
+    # (measured: chi2 with the fitted kernels within 0.3 % of the true kernels' value,
+    # amplitudes 2.9 % apart in the median, 6.7 % at most)
+    assert lf[0] <= 1.05 * lt[0]
+    assert np.median(rel) <= 0.05 and rel.max() <= 0.12
 
 
 # --------------------------------------------------------------------------- #
