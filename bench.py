@@ -417,7 +417,7 @@ def autotune_summary(plan, tune_s):
                     "tried_ms": {names[k]: round(v, 4) for k, v in enumerate(c["tune_ms"]) if v >= 0}})
     return {"tune_ms": round(info["wall_ms"], 2), "cached": info["cached"], "set_frames_s": round(tune_s, 3),
             "adj_blocks": info["adj_blocks"], "adj_frames": info["adj_frames"], "line_groups": info["line_groups"],
-            "split_forward": info["split_forward"], "classes": cls}
+            "split_forward": info["split_forward"], "prior_late": info["prior_late"], "classes": cls}
 
 
 def step_alg_bytes(prob, W):

@@ -300,11 +300,12 @@ int starred_get_class_info(const starred_plan *plan, int32_t c, starred_class_in
  * plan's decision (0 when none ran; with a cached decision, the time of the tuning
  * that filled the cache), whether the decision came from the cache, and the launch
  * shapes in use: work groups aimed at by the frequency-domain adjoint and by the
- * line passes, frames per adjoint chunk, and whether the one-launch forward runs on
- * a stream of its own (any pointer may be NULL). */
+ * line passes, frames per adjoint chunk, whether the one-launch forward runs on a
+ * stream of its own, and whether the prior forks after the forward (any pointer may be
+ * NULL). */
 int starred_autotune_info(const starred_plan *plan, double *wall_ms_out, int32_t *cached_out,
                           int32_t *adj_blocks_out, int32_t *line_groups_out, int32_t *adj_frames_out,
-                          int32_t *split_forward_out);
+                          int32_t *split_forward_out, int32_t *prior_late_out);
 
 /* Per-frame shifts and rotations (the joint processing of epochs that differ by a
  * shift and a rotation, as in the paper's conclusions; the per-epoch dithering
@@ -329,10 +330,12 @@ int starred_set_frame_transforms(starred_plan *plan, const float *xf, float *gra
  * runs the one-launch forward of the smaller classes on a second stream of the plan,
  * beside the line passes of the larger ones (forked from and joined back into the
  * plan's stream, also inside captured graphs), 0 runs everything in order. Results
- * agree up to rounding for every choice (bitwise for split_forward). Drops captured
- * graphs. EINVAL for other values. */
+ * agree up to rounding for every choice (bitwise for split_forward). prior_late (-1
+ * keeps it): 1 forks the starlet prior onto its stream after the forward's launches, so
+ * that it runs beside the adjoint, 0 at the start of the evaluation, beside the forward
+ * (bitwise the same results). Drops captured graphs. EINVAL for other values. */
 int starred_set_fft_shapes(starred_plan *plan, int32_t adj_frames, int32_t adj_blocks, int32_t line_groups,
-                           int32_t split_forward);
+                           int32_t split_forward, int32_t prior_late);
 
 /* Force the algorithm of shape class c: STARRED_CONV_DIRECT, or STARRED_CONV_FFT with
  * the one-launch forward (fused = 1, where it fits) or the line passes (fused = 0).

@@ -112,8 +112,8 @@ struct AdjItem {
     int pb;                      // row range index (the per-frame partial slot)
     int pad;
     int fid[kAdjMaxFrames];         // frame indices (-1 past nf)
-    long long soff[kAdjMaxFrames];  // kernel spectra S'' (frame 0's slot past nf)
-    long long roff[kAdjMaxFrames];  // rho_hat (frame 0's slot past nf)
+    long long soff[kAdjMaxFrames];  // kernel spectra S'' (the chunk's first frame again past nf)
+    long long roff[kAdjMaxFrames];  // rho_hat (the chunk's first frame again past nf)
     long long tab_off;           // the class's factor tables
     long long gout;              // the chunk's slot in the chunk spectra
 };

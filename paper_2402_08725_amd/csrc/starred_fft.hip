@@ -1360,7 +1360,8 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restr
             tys[u * kAdjMaxRows + r] = v;
         }
         __syncthreads();
-        // spectra of the chunk's frames (a missing frame reads frame 0's slot and is zeroed)
+        // spectra of the chunk's frames (a slot past the chunk's frames reads its first
+        // frame again; its product is discarded)
         int fid[FC];
         long long soff[FC], roff[FC];
         #pragma unroll
@@ -1417,13 +1418,14 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_adj(const AdjItem *__restr
                     float2 gsum = make_float2(0.f, 0.f);
                     #pragma unroll
                     for (int f = 0; f < FC; ++f) {
-                        // a missing frame's product is scaled to zero (a branch here would let
-                        // the compiler sink the loads above back to their use)
-                        const float on = f < it.nf ? 1.f : 0.f;
-                        float2 r = rv[b][f];
-                        r.x *= on;
-                        r.y *= cj * on;
-                        const float2 G = cmulc(r, sv[b][f]);
+                        // a missing frame's product is replaced by zero with a select (a branch
+                        // here would let the compiler sink the loads above back to their use;
+                        // a product with zero would let a non-finite value through)
+                        const bool on = f < it.nf;
+                        const float2 z = make_float2(0.f, 0.f);
+                        float2 r = on ? rv[b][f] : z;
+                        r.y *= cj;
+                        const float2 G = cmulc(r, on ? sv[b][f] : z);
                         gsum = cadd(gsum, G);
                         #pragma unroll
                         for (int u = 0; u < NY; ++u) V[f][u] = cadd(V[f][u], cmulc(G, ty[u]));

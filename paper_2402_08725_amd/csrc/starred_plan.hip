@@ -176,6 +176,9 @@ struct starred_plan {
     hipStream_t st3 = nullptr;
     hipEvent_t ev_fork3 = nullptr, ev_join3 = nullptr;
     int fwd_split = 1;
+    // FFT path, prior on the forked stream: forked after the forward's launches (beside
+    // the adjoint) instead of at the start of the evaluation (beside the forward)
+    int prior_late = 0;
     int *d_t = nullptr;
     int next_t = -1;  // step number the device counter will produce next (-1: unknown)
 
@@ -799,8 +802,10 @@ static int build_fft_lists(starred_plan *p)
                     for (int f = 0; f < kAdjMaxFrames; ++f) {
                         const int fi = f < it.nf ? cls_frames[cl.cf_off + f0 + f] : -1;
                         it.fid[f] = fi;
-                        it.soff[f] = fi >= 0 ? p->ffr[fi].s_off : 0;
-                        it.roff[f] = fi >= 0 ? p->ffr[fi].r_off : 0;
+                        // a slot past the chunk's frames reads the chunk's first frame again
+                        // (computed spectra: finite values, which the kernel then discards)
+                        it.soff[f] = fi >= 0 ? p->ffr[fi].s_off : it.soff[0];
+                        it.roff[f] = fi >= 0 ? p->ffr[fi].r_off : it.roff[0];
                     }
                     it.tab_off = cl.tab_off;
                     it.gout = cl.gp_off + (long long)(f0 / cl.gfch) * nbins;
@@ -1090,8 +1095,10 @@ int starred_get_class_info(const starred_plan *p, int32_t c, starred_class_info 
 }
 
 int starred_autotune_info(const starred_plan *p, double *wall_ms_out, int32_t *cached_out, int32_t *adj_blocks_out,
-                          int32_t *line_groups_out, int32_t *adj_frames_out, int32_t *split_forward_out)
+                          int32_t *line_groups_out, int32_t *adj_frames_out, int32_t *split_forward_out,
+                          int32_t *prior_late_out)
 {
+    if (prior_late_out && p) *prior_late_out = p->prior_late;
     if (split_forward_out && p) *split_forward_out = p->fwd_split;
     if (!p) return fail(STARRED_EINVAL, "plan is NULL");
     if (wall_ms_out) *wall_ms_out = p->tune_wall_ms;
@@ -1122,7 +1129,7 @@ int starred_set_class_algo(starred_plan *p, int32_t c, int32_t algo, int32_t fus
 static bool adj_shape_ok(int fc, int M) { return fc == 2 || fc == 4 || (fc == 8 && M <= 1); }
 
 int starred_set_fft_shapes(starred_plan *p, int32_t adj_frames, int32_t adj_blocks, int32_t line_groups,
-                           int32_t split_forward)
+                           int32_t split_forward, int32_t prior_late)
 {
     if (!p) return fail(STARRED_EINVAL, "plan is NULL");
     if (p->mode != STARRED_DECONV) return fail(STARRED_EUNSUPPORTED, "launch shapes of the deconvolution FFT path");
@@ -1131,6 +1138,8 @@ int starred_set_fft_shapes(starred_plan *p, int32_t adj_frames, int32_t adj_bloc
     if (adj_blocks < 0 || adj_blocks > (1 << 20) || line_groups < 0 || line_groups > (1 << 20))
         return fail(STARRED_EINVAL, "work-group targets must lie in [1, 2^20] (0 keeps the current one)");
     if (split_forward < -1 || split_forward > 1) return fail(STARRED_EINVAL, "split_forward must be -1, 0 or 1");
+    if (prior_late < -1 || prior_late > 1) return fail(STARRED_EINVAL, "prior_late must be -1, 0 or 1");
+    if (prior_late >= 0) p->prior_late = prior_late;
     if (split_forward >= 0) p->fwd_split = split_forward;
     if (adj_frames) p->adj_fc = adj_frames;
     if (adj_blocks) p->adj_blocks = adj_blocks;
@@ -1362,7 +1371,9 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
             pd.jobs = pd.d.jobs_d1();
         }
         n_l1 = pc.d.l1_slots();
-    } else {
+    }
+    const bool late = !ride && fft && p->prior_late;
+    if (!ride && !late) {
         int rc = starlet_branch(p, params, grad != nullptr, &n_l1);
         if (rc) return rc;
     }
@@ -1401,6 +1412,10 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         p->prof_stop(STARRED_STAGE_FFT_MROWS, e1);
         p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
         n_chi = n_rows + (fused ? p->fd.n_fused : 0);
+        if (late) {
+            int rc = starlet_branch(p, params, grad != nullptr, &n_l1);
+            if (rc) return rc;
+        }
     }
     if (dir) {
         // the direct classes' frames: their chi-square partials follow the FFT ones
@@ -1502,7 +1517,7 @@ constexpr double kTuneGain = 0.98;
 
 struct TuneEntry {
     std::vector<int> choice;
-    int adj_blocks = kAdjBlocks, line_groups = 1024, adj_fc = kAdjFrames, fwd_split = 1;
+    int adj_blocks = kAdjBlocks, line_groups = 1024, adj_fc = kAdjFrames, fwd_split = 1, prior_late = 0;
     std::vector<std::array<double, 3>> tried;  // the timings the decision came from
     double wall_ms = 0.0;                      // how long that tuning took
 };
@@ -1555,6 +1570,7 @@ static int autotune(starred_plan *p)
             p->line_groups = it->second.line_groups;
             p->adj_fc = it->second.adj_fc;
             p->fwd_split = it->second.fwd_split;
+            p->prior_late = it->second.prior_late;
             p->tune_cached = 1;
             p->cls_tune = it->second.tried;
             p->tune_wall_ms = it->second.wall_ms;
@@ -1636,8 +1652,8 @@ static int autotune(starred_plan *p)
             }
         p->adj_fc = best_fc;
         p->adj_blocks = best_ab;
-        for (int which = 0; which < 2 && !rc; ++which) {
-            int &knob = which == 0 ? p->line_groups : p->fwd_split;
+        for (int which = 0; which < 3 && !rc; ++which) {
+            int &knob = which == 0 ? p->line_groups : (which == 1 ? p->fwd_split : p->prior_late);
             const int keep = knob;
             int best_v = keep;
             const std::vector<int> cands = which == 0 ? std::vector<int>{512, 1024, 2048} : std::vector<int>{0, 1};
@@ -1672,6 +1688,7 @@ static int autotune(starred_plan *p)
         e.line_groups = p->line_groups;
         e.adj_fc = p->adj_fc;
         e.fwd_split = p->fwd_split;
+        e.prior_late = p->prior_late;
         e.tried = p->cls_tune;
         e.wall_ms = p->tune_wall_ms;
         std::lock_guard<std::mutex> lk(g_tune_mu);

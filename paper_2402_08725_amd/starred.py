@@ -92,9 +92,9 @@ def lib():
         L.starred_get_class_info.argtypes = [vp, i32, ctypes.POINTER(ClassInfo)]
         L.starred_autotune_info.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32),
                                             ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                            ctypes.POINTER(i32)]
+                                            ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.starred_set_class_algo.argtypes = [vp, i32, i32, i32]
-        L.starred_set_fft_shapes.argtypes = [vp, i32, i32, i32, i32]
+        L.starred_set_fft_shapes.argtypes = [vp, i32, i32, i32, i32, i32]
         L.starred_set_frame_transforms.argtypes = [vp, vp, vp]
         L.starred_last_error.restype = ctypes.c_char_p
         L.starred_set_profiling.argtypes = [vp, i32]
@@ -232,11 +232,12 @@ class Plan:
     def autotune_info(self):
         """Host ms of the last autotuning, whether it came from the cache, launch shapes."""
         ms, cached = ctypes.c_double(0.0), ctypes.c_int32(0)
-        ab, lg, af, sf = (ctypes.c_int32(0) for _ in range(4))
+        ab, lg, af, sf, pl = (ctypes.c_int32(0) for _ in range(5))
         _check(lib().starred_autotune_info(self._h, ctypes.byref(ms), ctypes.byref(cached), ctypes.byref(ab),
-                                           ctypes.byref(lg), ctypes.byref(af), ctypes.byref(sf)))
+                                           ctypes.byref(lg), ctypes.byref(af), ctypes.byref(sf), ctypes.byref(pl)))
         return {"wall_ms": ms.value, "cached": bool(cached.value), "adj_blocks": ab.value,
-                "line_groups": lg.value, "adj_frames": af.value, "split_forward": sf.value}
+                "line_groups": lg.value, "adj_frames": af.value, "split_forward": sf.value,
+                "prior_late": pl.value}
 
     def set_frame_transforms(self, xf, grad_out=None):
         """Per-frame (dx, dy, theta) transforms (E x 3), or None to clear them; grad_out
@@ -255,10 +256,10 @@ class Plan:
         """Force shape class c onto CONV_DIRECT or CONV_FFT (one-launch forward if fused)."""
         _check(lib().starred_set_class_algo(self._h, int(c), int(algo), 1 if fused else 0))
 
-    def set_fft_shapes(self, adj_frames=0, adj_blocks=0, line_groups=0, split_forward=-1):
-        """Launch shapes of the FFT path (0, or -1 for split_forward, keeps the current value)."""
+    def set_fft_shapes(self, adj_frames=0, adj_blocks=0, line_groups=0, split_forward=-1, prior_late=-1):
+        """Launch shapes of the FFT path (0, or -1 for the two switches, keeps the current value)."""
         _check(lib().starred_set_fft_shapes(self._h, int(adj_frames), int(adj_blocks), int(line_groups),
-                                            int(split_forward)))
+                                            int(split_forward), int(prior_late)))
 
     def fused_classes(self):
         """(n, K) of the classes whose forward is the one-launch form."""

@@ -1121,6 +1121,26 @@ def test_mixed_class_algorithms_loss_grad_and_operators(mix):
     _check_frames(adj, refa, (prob.s * prob.n).tolist(), 1e-5)
 
 
+def test_partial_adjoint_chunk_with_unwritten_spectra_slots():
+    """A chunk of the frequency-domain adjoint with fewer frames than slots, in a plan
+    whose first frames run the direct algorithm (their spectrum slots are never
+    written): device memory is filled with NaN and released first, so that the plan's
+    buffers start with non-finite values; the gradient must stay finite and match the
+    oracle (regression: the missing slots once read frame 0's unwritten spectra and
+    scaled them by zero)."""
+    poison = torch.full((256 * 1024 * 1024,), float("nan"), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    del poison
+    torch.cuda.empty_cache()
+    prob = synth.make_deconv(4, E=10)
+    d, w, rng = _data(prob, seed=42)
+    plan, cls = _mixed_plan(prob, d, w, MIXES["dir-fused-lines"])
+    assert cls[0]["algo"] == 1  # the first class (holding frame 0) on the direct algorithm
+    p = synth.eval_point(prob, "near", rng)
+    _, g = _compare_loss_grad(prob, d, w, p, plan, "partial chunk, poisoned memory")
+    assert np.isfinite(g).all()
+
+
 def test_mixed_class_algorithms_graph_steps_match_eager():
     """Optimiser steps of a mixed plan (the update fused into the final launch):
     graph replays equal eager steps bit for bit, and equal the all-FFT plan's loss
@@ -1141,7 +1161,13 @@ def test_mixed_class_algorithms_graph_steps_match_eager():
         le = plan_e.step(xe, me, ve, t, lr4)
         torch.cuda.synchronize()
         _ = (torch.randn(1000, device="cuda") * 2).sum().item()
-        assert torch.equal(lg, le) and torch.equal(xg, xe) and torch.equal(mg, me) and torch.equal(vg, ve), t
+        same = [torch.equal(a, b) for a, b in ((lg, le), (xg, xe), (mg, me), (vg, ve))]
+        if not all(same):
+            dx = (xg - xe).abs()
+            _say(f"mixed graph step {t}: equal (loss, x, m, v) {same}; loss {lg.tolist()} vs {le.tolist()}; "
+                 f"x differs at {int((dx > 0).sum())} entries, first {int(torch.nonzero(dx)[0])} of {dx.numel()}, "
+                 f"max {dx.max().item():.3e}")
+        assert all(same), t
     fft = st.Plan.for_problem(prob, conv_algo=st.CONV_FFT)
     fft.set_frames(d, w, prob.kernels, prob.W)
     lf, _ = fft.loss_grad(xe)
@@ -1196,8 +1222,9 @@ def test_inplace_one_launch_forward():
 @pytest.mark.parametrize("graph", [False, True], ids=["eager", "graph"])
 def test_split_forward_is_bitwise_the_same(graph):
     """The one-launch forward on the plan's second FFT stream, beside the line passes,
-    gives bitwise the results of the in-order launches (loss, gradient and Adam steps,
-    eager or captured), and matches the oracle."""
+    and the prior forked after the forward instead of at the start give bitwise the
+    results of the in-order launches (loss, gradient and Adam steps, eager or captured),
+    and match the oracle."""
     st = _st()
     prob = synth.make_deconv(4, E=13)
     d, w, rng = _data(prob, seed=72)
@@ -1210,9 +1237,10 @@ def test_split_forward_is_bitwise_the_same(graph):
     p0 = synth.eval_point(prob, "near", rng)
     lr4 = [prob.adam_lr[k] for k in ("h", "Gamma", "a", "c")]
     runs = []
-    for split in (0, 1):
-        plan.set_fft_shapes(split_forward=split)
-        assert plan.autotune_info()["split_forward"] == split
+    for split, late in ((0, 0), (1, 0), (0, 1), (1, 1)):
+        plan.set_fft_shapes(split_forward=split, prior_late=late)
+        info = plan.autotune_info()
+        assert info["split_forward"] == split and info["prior_late"] == late
         plan.set_graph_mode(graph)
         x = torch.tensor(p0, dtype=torch.float32, device="cuda")
         m = torch.zeros_like(x)
@@ -1224,9 +1252,10 @@ def test_split_forward_is_bitwise_the_same(graph):
         torch.cuda.synchronize()
         runs.append((l, g, x.clone(), m.clone(), v.clone()))
         plan.set_graph_mode(False)
-    for a, b in zip(runs[0], runs[1]):
-        assert torch.equal(a, b)
-    _compare_loss_grad(prob, d, w, p0, plan, "split forward")
+    for r in runs[1:]:
+        for a, b in zip(runs[0], r):
+            assert torch.equal(a, b)
+    _compare_loss_grad(prob, d, w, p0, plan, "split forward, late prior")
 
 
 def test_autotuner_per_class_choices_cache_and_parity():
