@@ -466,6 +466,39 @@ def _extra_workloads(args, torch, st, synth):
                           "step_ms": {k: (round(v_, 5) if isinstance(v_, float) else v_) for k, v_ in ser.items()},
                           "epoch_px_per_s": prob.data_size / (ser["median"] * 1e-3)}
         plan.close()
+    # per-frame shifts and rotations (the lensed-quasar shapes): each frame rendered under
+    # its transform and convolved by the faster of the direct kernels and its own
+    # spectrum (timed at set_frame_transforms), the transforms' gradient written too
+    prob = synth.make_deconv(2)
+    plan = st.Plan.for_problem(prob)
+    with torch.cuda.stream(plan.stream):
+        _make_inputs(prob, plan)
+        rng = np.random.default_rng(7)
+        xf = np.stack([rng.uniform(-2, 2, prob.E), rng.uniform(-2, 2, prob.E), rng.uniform(-0.02, 0.02, prob.E)], 1)
+        xf_d = torch.tensor(xf, dtype=torch.float32, device="cuda")
+        gxf = torch.empty_like(xf_d)
+        plan.set_frame_transforms(xf_d, grad_out=gxf)
+        xalgo, xms = plan.frame_transforms_info()
+        x = torch.tensor(synth.eval_point(prob, "init", np.random.default_rng(1)), dtype=torch.float32, device="cuda")
+        m = torch.zeros_like(x)
+        v = torch.zeros_like(x)
+        loss = torch.empty(3, dtype=torch.float64, device="cuda")
+        lr4 = [prob.adam_lr[k] for k in ("h", "Gamma", "a", "c")]
+        plan.set_graph_mode(True)
+        tt = [0]
+
+        def go_xf():
+            plan.steps(x, m, v, tt[0] + 1, lr4, STEPS_PER_GRAPH, loss_out=loss)
+            tt[0] += STEPS_PER_GRAPH
+        for _ in range(2):
+            go_xf()
+        ser = _pct([s / STEPS_PER_GRAPH for s in _event_series(torch, go_xf, 10, 0.3)])
+    res["cfg2_transforms"] = {"workload": workload_name(prob) + ", per-frame shifts and rotations",
+                              "conv_algo": {1: "direct", 2: "fft"}.get(xalgo, "none"),
+                              "choice_ms_per_eval": {k: round(v_, 4) for k, v_ in xms.items()},
+                              "step_ms": {k: (round(v_, 5) if isinstance(v_, float) else v_) for k, v_ in ser.items()},
+                              "epoch_px_per_s": prob.data_size / (ser["median"] * 1e-3)}
+    plan.close()
     # PSF mode (star stamps): one step = loss, gradient and update of (eta_M, b, a, c)
     pp = synth.make_psf(3)
     plan = st.Plan.for_psf(pp)

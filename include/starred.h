@@ -317,11 +317,21 @@ int starred_autotune_info(const starred_plan *plan, double *wall_ms_out, int32_t
  * a_ik r(u - c_k); t_i = 0 is Eq. 9. The data term's gradient in h is the exact
  * transpose of that interpolation. grad_xf (device [n_frames][3], or NULL):
  * loss_grad also writes dL/d(dx_i, dy_i, theta_i) there, so that offsets can be
- * fitted. Frames with transforms run the direct algorithm: setting them moves every
- * class onto it (EUNSUPPORTED when the kernels exceed its tiles); xf = NULL clears
- * them and restores the previous choices. Drops captured graphs. The plain baseline
- * does not support them. */
-int starred_set_frame_transforms(starred_plan *plan, const float *xf, float *grad_xf);
+ * fitted. Each frame's scene is rendered under its transform; setting transforms
+ * moves every class off the shared class spectra (EUNSUPPORTED when the kernels
+ * exceed the direct tiles), and algo chooses how the rendered frames are convolved:
+ * STARRED_CONV_DIRECT (the direct kernels), STARRED_CONV_FFT (each frame through its
+ * own spectrum: a P-size forward transform of its rendered window, the spectral
+ * product and alias fold, and a P-size inverse in the adjoint), or STARRED_CONV_AUTO
+ * (both timed on the bound data when frames are bound, else the spectra). xf = NULL
+ * clears them and restores the previous choices. Drops captured graphs. The plain
+ * baseline does not support them. */
+int starred_set_frame_transforms(starred_plan *plan, const float *xf, float *grad_xf, int32_t algo);
+/* The convolution chosen for frames with transforms (*algo_out: STARRED_CONV_DIRECT or
+ * STARRED_CONV_FFT, 0 when none are set) and, when STARRED_CONV_AUTO timed it, the
+ * milliseconds per loss+gradient evaluation with each (ms_out[2]: direct, spectra;
+ * -1 when not timed). Either pointer may be NULL. */
+int starred_frame_transforms_info(const starred_plan *plan, int32_t *algo_out, double *ms_out);
 
 /* Launch shapes of the deconvolution FFT path (what the autotuner chooses; 0 keeps
  * the current value): adj_frames, frames per chunk of the frequency-domain adjoint

@@ -158,6 +158,10 @@ struct FftPlanDev {
     int n_fused = 0;
     size_t fused_lds = 0;
     LinePass fcols_lg, frows_lg, rcols_lg;
+    // every frame, whatever its class runs: the per-frame convolution of rendered
+    // scenes (frames with per-frame transforms), and its per-group sums of g
+    LinePass srows_x, scols_x, fcols_x, frows_x, rcols_x, acols_x, arows_x;
+    double *gpart_x = nullptr;
 };
 
 // Deterministic block sum of one double per thread (NT threads); thread 0 holds it.
@@ -228,5 +232,12 @@ hipError_t fft_model_rows_lg(hipStream_t st, const FftPlanDev &d, const float *d
 hipError_t fft_rho_cols_lg(hipStream_t st, const FftPlanDev &d);
 hipError_t fft_grad_h_inverse(hipStream_t st, const FftPlanDev &d, DensePiece *pd = nullptr);
 hipError_t fft_scene_model(hipStream_t st, const FftPlanDev &d, const float *scene, int s, float *model);
+// Frames with per-frame transforms: S_i and D of each frame's rendered scene (fine
+// grid, per-frame layout) through its own spectrum, the weighted residual and its
+// chi-square partials (one per row group of frows_x), rho_hat kept for the adjoint.
+hipError_t fft_xf_forward(hipStream_t st, const FftPlanDev &d, const float *scene, int s, const float *data,
+                          const float *invvar, double *part_chi);
+// ... and D^T S_i^T of those residuals into g (fine grid, per-frame layout).
+hipError_t fft_xf_adjoint(hipStream_t st, const FftPlanDev &d, float *g);
 
 }  // namespace starred

@@ -1727,6 +1727,28 @@ hipError_t fft_scene_model(hipStream_t st, const FftPlanDev &d, const float *sce
     return e;
 }
 
+hipError_t fft_xf_forward(hipStream_t st, const FftPlanDev &d, const float *scene, int s, const float *data,
+                          const float *invvar, double *part_chi)
+{
+    hipError_t e = run_lines(st, d.srows_x, d.classes, d.tw, OpSceneRows{d.frames, scene, d.T3});
+    if (e != hipSuccess) return e;
+    e = run_lines(st, d.scols_x, d.classes, d.tw, OpSceneCols{d.frames, d.T3});
+    if (e != hipSuccess) return e;
+    e = run_lines(st, d.fcols_x, d.classes, d.tw, OpFwdCols{d.frames, d.S, d.Hh, d.tab, nullptr, 0, 0, 0, s, d.T, d.T3});
+    if (e != hipSuccess || d.frows_x.n_items <= 0) return e;
+    hipLaunchKernelGGL(k_fwd_rows, dim3(d.frows_x.n_items), dim3(kFftThreads), d.frows_x.lds_bytes, st,
+                       d.frows_x.items, d.classes, d.frames, d.tw, d.T, data, invvar, d.T2, nullptr, part_chi);
+    return hipGetLastError();
+}
+
+hipError_t fft_xf_adjoint(hipStream_t st, const FftPlanDev &d, float *g)
+{
+    hipError_t e = run_lines(st, d.rcols_x, d.classes, d.tw, OpRhoCols{d.frames, d.T2, d.Rh});
+    if (e == hipSuccess) e = run_lines(st, d.acols_x, d.classes, d.tw, OpAdjCols{d.frames, d.S, d.Rh, d.T3});
+    if (e == hipSuccess) e = run_lines(st, d.arows_x, d.classes, d.tw, OpAdjRows{d.frames, d.T3, g, d.gpart_x});
+    return e;
+}
+
 hipError_t fft_resid_rows(hipStream_t st, const FftPlanDev &d, const float *resid)
 {
     return run_lines(st, d.rrows, d.classes, d.tw, OpResidRows{d.frames, resid, d.T2});

@@ -179,6 +179,10 @@ struct starred_plan {
     // FFT path, prior on the forked stream: forked after the forward's launches (beside
     // the adjoint) instead of at the start of the evaluation (beside the forward)
     int prior_late = 0;
+    // frames with per-frame transforms: convolved through their own spectra (1) or by the
+    // direct kernels (0)
+    int xf_fft = 0;
+    double xf_ms[2] = {-1.0, -1.0};  // timings of that choice: direct, spectra (-1: not timed)
     int *d_t = nullptr;
     int next_t = -1;  // step number the device counter will produce next (-1: unknown)
 
@@ -904,11 +908,20 @@ static int build_fft_lists(starred_plan *p)
     if ((rc = make_pass(d.scols, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
     if ((rc = make_pass(d.gcols, true, [](const ClassFft &c) { return c.P / 2 + 1; }, LP))) return rc;
     if ((rc = make_pass(d.grows, true, [](const ClassFft &c) { return c.F; }, LP))) return rc;
+    // every frame: the per-frame convolution of the rendered scenes (frame transforms)
+    if ((rc = make_pass(d.srows_x, false, [](const ClassFft &c) { return c.F; }, LP, false, true))) return rc;
+    if ((rc = make_pass(d.scols_x, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP, false, true))) return rc;
+    if ((rc = make_pass(d.fcols_x, false, [](const ClassFft &c) { return c.Q / 2 + 1; }, LQ, false, true))) return rc;
+    if ((rc = make_pass(d.frows_x, false, [](const ClassFft &c) { return c.n; }, LQ, false, true))) return rc;
+    if ((rc = make_pass(d.rcols_x, false, [](const ClassFft &c) { return c.Q / 2 + 1; }, LQ, false, true))) return rc;
+    if ((rc = make_pass(d.acols_x, false, [](const ClassFft &c) { return c.P / 2 + 1; }, LP, false, true))) return rc;
+    if ((rc = make_pass(d.arows_x, false, [](const ClassFft &c) { return c.F; }, LP, false, true))) return rc;
+    if ((rc = p->alloc_list(&d.gpart_x, std::max<size_t>(1, (size_t)d.arows_x.n_items)))) return rc;
     // the direct path's lists for the frames of the direct classes
     if ((rc = build_direct_lists(p))) return rc;
     // chi-square partials: the FFT line-pass row groups (or, with the one-launch
     // forward, its row groups and then one per fused frame), then the direct tiles
-    p->n_fft_chi = std::max(d.frows.n_items, d.frows_lg.n_items + d.n_fused);
+    p->n_fft_chi = std::max(std::max(d.frows.n_items, d.frows_lg.n_items + d.n_fused), d.frows_x.n_items);
     if ((rc = p->alloc_list(&p->d_part_chi_fft, (size_t)p->n_fft_chi + p->fwd_items.size() + 1))) return rc;
     return STARRED_OK;
 }
@@ -1150,11 +1163,66 @@ int starred_set_fft_shapes(starred_plan *p, int32_t adj_frames, int32_t adj_bloc
     return build_fft_lists(p);
 }
 
-int starred_set_frame_transforms(starred_plan *p, const float *xf, float *grad_xf)
+static int time_plan(starred_plan *p, const float *params, double *loss, hipEvent_t a, hipEvent_t b, double *ms);
+
+// The convolution of frames with per-frame transforms: the direct kernels or each
+// frame's own spectra; STARRED_CONV_AUTO times both on the bound data (h = 0) when
+// frames are bound, else takes the spectra.
+static int choose_xf_algo(starred_plan *p, int algo)
+{
+    p->xf_ms[0] = p->xf_ms[1] = -1.0;
+    const bool fft_ok = !p->cls.empty() && p->fd.frows_x.n_items > 0 && p->fd.srows_x.n_items > 0;
+    if (algo == STARRED_CONV_FFT && !fft_ok) return fail(STARRED_EUNSUPPORTED, "this plan has no FFT structures");
+    if (algo == STARRED_CONV_DIRECT || !fft_ok) {
+        p->xf_fft = 0;
+        return STARRED_OK;
+    }
+    if (algo == STARRED_CONV_FFT || !p->frames_set) {
+        p->xf_fft = 1;
+        return STARRED_OK;
+    }
+    float *params = nullptr;
+    double *loss = nullptr;
+    int rc = dev_alloc(&params, p->nparams);
+    if (!rc) rc = dev_alloc(&loss, 3);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (!rc && hipEventCreate(&a) != hipSuccess) rc = fail(STARRED_EHIP, "hipEventCreate");
+    if (!rc && hipEventCreate(&b) != hipSuccess) rc = fail(STARRED_EHIP, "hipEventCreate");
+    if (!rc && launch_fill(p->st, params, p->nparams, 0.f) != hipSuccess) rc = fail(STARRED_EHIP, "fill");
+    const bool prof = p->prof_on;
+    p->prof_on = false;
+    for (int v = 0; v < 2 && !rc; ++v) {
+        p->xf_fft = v;
+        rc = time_plan(p, params, loss, a, b, &p->xf_ms[v]);
+    }
+    p->prof_on = prof;
+    if (!rc) p->xf_fft = p->xf_ms[1] < p->xf_ms[0] ? 1 : 0;
+    (void)hipStreamSynchronize(p->st);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (params) (void)hipFree(params);
+    if (loss) (void)hipFree(loss);
+    return rc;
+}
+
+int starred_frame_transforms_info(const starred_plan *p, int32_t *algo_out, double *ms_out)
+{
+    if (!p) return fail(STARRED_EINVAL, "plan is NULL");
+    if (algo_out) *algo_out = !p->xf ? 0 : (p->xf_fft ? STARRED_CONV_FFT : STARRED_CONV_DIRECT);
+    if (ms_out) {
+        ms_out[0] = p->xf_ms[0];
+        ms_out[1] = p->xf_ms[1];
+    }
+    return STARRED_OK;
+}
+
+int starred_set_frame_transforms(starred_plan *p, const float *xf, float *grad_xf, int32_t algo)
 {
     if (!p) return fail(STARRED_EINVAL, "plan is NULL");
     if (p->mode != STARRED_DECONV) return fail(STARRED_EUNSUPPORTED, "per-frame transforms need deconvolution mode");
     if (!xf && grad_xf) return fail(STARRED_EINVAL, "grad_xf without transforms");
+    if (algo != STARRED_CONV_AUTO && algo != STARRED_CONV_DIRECT && algo != STARRED_CONV_FFT)
+        return fail(STARRED_EINVAL, "algo must be STARRED_CONV_AUTO, DIRECT or FFT");
     if (xf && !p->direct_ok)
         return fail(STARRED_EUNSUPPORTED, "per-frame transforms run the direct algorithm, whose tiles these kernels exceed");
     p->drop_graphs();
@@ -1171,7 +1239,10 @@ int starred_set_frame_transforms(starred_plan *p, const float *xf, float *grad_x
     }
     p->xf = xf;
     p->gxf = xf ? grad_xf : nullptr;
-    return STARRED_OK;
+    if (!xf) return STARRED_OK;
+    int rc = choose_xf_algo(p, algo);
+    p->drop_graphs();
+    return rc;
 }
 
 int starred_set_frames(starred_plan *p, const float *data, const float *inv_var, const float *psf,
@@ -1332,6 +1403,9 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     // (both in one evaluation when the classes differ)
     const bool fft = (p->algo == STARRED_CONV_FFT);
     const bool dir = !p->fdir.empty();
+    // per-frame transforms through the frames' own spectra (every class is on the direct
+    // algorithm while transforms are set; only its convolution changes)
+    const bool xf_fft = p->xf && p->xf_fft && !fft;
     hipEvent_t e0;
     int n_chi = 0;
     const double *part_chi = p->d_part_chi_fft;
@@ -1426,12 +1500,19 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         p->prof_stop(STARRED_STAGE_RENDER, e0);
         e0 = p->prof_start();
         hipEvent_t e1 = p->prof_start();
-        HIP_TRY(launch_fwd_direct(p->st, p->s, p->d_fr, p->d_fwd_items, (int)p->fwd_items.size(), p->Tdir,
-                                  p->d_scene, p->d_kf, p->data, p->invvar, p->d_rho, p->d_part_chi_fft + n_chi,
-                                  p->fwd_groups));
+        if (xf_fft) {
+            // transformed frames through their own spectra (every frame: all classes run
+            // this path while transforms are set)
+            HIP_TRY(fft_xf_forward(p->st, p->fd, p->d_scene, p->s, p->data, p->invvar, p->d_part_chi_fft + n_chi));
+            n_chi += p->fd.frows_x.n_items;
+        } else {
+            HIP_TRY(launch_fwd_direct(p->st, p->s, p->d_fr, p->d_fwd_items, (int)p->fwd_items.size(), p->Tdir,
+                                      p->d_scene, p->d_kf, p->data, p->invvar, p->d_rho, p->d_part_chi_fft + n_chi,
+                                      p->fwd_groups));
+            n_chi += (int)p->fwd_items.size();
+        }
         p->prof_stop(STARRED_STAGE_DIRECT_FWD, e1);
         if (!fft) p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
-        n_chi += (int)p->fwd_items.size();
     }
     if (grad) {
         e0 = p->prof_start();
@@ -1456,8 +1537,11 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         }
         if (dir) {
             hipEvent_t e1 = p->prof_start();
-            HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ardir,
-                                      p->Bpdir, p->d_rho, p->d_ka, p->d_g, p->adj_groups));
+            if (xf_fft)
+                HIP_TRY(fft_xf_adjoint(p->st, p->fd, p->d_g));
+            else
+                HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ardir,
+                                          p->Bpdir, p->d_rho, p->d_ka, p->d_g, p->adj_groups));
             p->prof_stop(STARRED_STAGE_DIRECT_ADJ, e1);
         }
         p->prof_stop(STARRED_STAGE_CONV_ADJ, e0);
@@ -2375,6 +2459,10 @@ int starred_time_stage(starred_plan *p, const float *params, int32_t stage, int3
         case STARRED_STAGE_CONV_FWD:
         case STARRED_STAGE_DIRECT_FWD:
             if (p->fdir.empty()) break;
+            if (p->xf && p->xf_fft) {
+                HIP_TRY(fft_xf_forward(p->st, p->fd, p->d_scene, p->s, p->data, p->invvar, p->d_part_chi_fft));
+                return STARRED_OK;
+            }
             HIP_TRY(launch_fwd_direct(p->st, p->s, p->d_fr, p->d_fwd_items, (int)p->fwd_items.size(), p->Tdir,
                                       p->d_scene, p->d_kf, p->data, p->invvar, p->d_rho, p->d_part_chi_fft,
                                       p->fwd_groups));
@@ -2382,6 +2470,10 @@ int starred_time_stage(starred_plan *p, const float *params, int32_t stage, int3
         case STARRED_STAGE_CONV_ADJ:
         case STARRED_STAGE_DIRECT_ADJ:
             if (p->fdir.empty()) break;
+            if (p->xf && p->xf_fft) {
+                HIP_TRY(fft_xf_adjoint(p->st, p->fd, p->d_g));
+                return STARRED_OK;
+            }
             HIP_TRY(launch_adj_direct(p->st, p->s, p->d_fr, p->d_adj_items, (int)p->adj_items.size(), p->Ardir,
                                       p->Bpdir, p->d_rho, p->d_ka, p->d_g, p->adj_groups));
             return STARRED_OK;

@@ -95,7 +95,8 @@ def lib():
                                             ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.starred_set_class_algo.argtypes = [vp, i32, i32, i32]
         L.starred_set_fft_shapes.argtypes = [vp, i32, i32, i32, i32, i32]
-        L.starred_set_frame_transforms.argtypes = [vp, vp, vp]
+        L.starred_set_frame_transforms.argtypes = [vp, vp, vp, i32]
+        L.starred_frame_transforms_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
         L.starred_last_error.restype = ctypes.c_char_p
         L.starred_set_profiling.argtypes = [vp, i32]
         L.starred_profile_read.argtypes = [vp, vp, vp]
@@ -239,18 +240,26 @@ class Plan:
                 "line_groups": lg.value, "adj_frames": af.value, "split_forward": sf.value,
                 "prior_late": pl.value}
 
-    def set_frame_transforms(self, xf, grad_out=None):
+    def set_frame_transforms(self, xf, grad_out=None, algo=CONV_AUTO):
         """Per-frame (dx, dy, theta) transforms (E x 3), or None to clear them; grad_out
-        (float32 device tensor of E x 3) receives dL/d(dx, dy, theta) in loss_grad."""
+        (float32 device tensor of E x 3) receives dL/d(dx, dy, theta) in loss_grad; algo:
+        how the transformed frames are convolved (CONV_AUTO, CONV_DIRECT or CONV_FFT)."""
         if xf is None:
             self._xf = None
-            self._call(lib().starred_set_frame_transforms, None, None)
+            self._call(lib().starred_set_frame_transforms, None, None, ctypes.c_int32(CONV_AUTO))
             return None
         t = _f32(xf, self.device)
         g = grad_out if grad_out is not None else torch.zeros(3 * self.E, dtype=torch.float32, device=self.device)
-        self._call(lib().starred_set_frame_transforms, _ptr(t), _ptr(g))
+        self._call(lib().starred_set_frame_transforms, _ptr(t), _ptr(g), ctypes.c_int32(int(algo)))
         self._xf = (t, g)  # referenced by the plan
         return g
+
+    def frame_transforms_info(self):
+        """(algo, {"direct": ms, "fft": ms}) of the transformed frames' convolution."""
+        a = ctypes.c_int32(0)
+        ms = (ctypes.c_double * 2)()
+        _check(lib().starred_frame_transforms_info(self._h, ctypes.byref(a), ms))
+        return a.value, {"direct": ms[0], "fft": ms[1]}
 
     def set_class_algo(self, c, algo, fused=True):
         """Force shape class c onto CONV_DIRECT or CONV_FFT (one-launch forward if fused)."""

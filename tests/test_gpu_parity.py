@@ -198,11 +198,13 @@ def test_loss_grad_parity(name, make, point, algo):
 @pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
 def test_loss_grad_parity_seven_scales(algo):
     """Seven starlet scales on a 128 grid: the prior's level-6 filters come from the
-    padded tap table (levels 1-5 are compiled in), inside the step's launches on the
-    FFT path."""
-    prob = synth.make_small_deconv(211, 3, [64, 64, 64], [31, 25, 31], 2, 128, 2, 7)
+    padded tap table (levels 1-5 are compiled in); one shape class covering the whole
+    grid, so on the FFT path the prior's passes ride in the evaluation's own launches
+    (with the gradient too)."""
+    prob = synth.make_small_deconv(211, 3, [64, 64, 64], [31, 31, 31], 2, 128, 2, 7)
     d, w, rng = _data(prob, seed=211)
     plan = _plan(prob, d, w, algo)
+    assert len(plan.classes()) == 1
     p = synth.eval_point(prob, "near", rng)
     _compare_loss_grad(prob, d, w, p, plan, f"J7/{ALGO_ID[algo]}")
 
@@ -1302,11 +1304,13 @@ def _xf_for(E, rng, big=False):
     return synth.f32(np.column_stack([d, th]).ravel())
 
 
+@pytest.mark.parametrize("xalgo", [1, 2], ids=["direct", "fft"])
 @pytest.mark.parametrize("name", sorted(XF_CASES), ids=sorted(XF_CASES))
-def test_frame_transforms_parity(name):
-    """Frames shifted and rotated: scenes element by element, loss, every gradient
-    block and dL/d(dx, dy, theta) per frame against the oracle; clearing the transforms
-    gives back the untransformed plan's results."""
+def test_frame_transforms_parity(name, xalgo):
+    """Frames shifted and rotated, convolved by the direct kernels or through each
+    frame's own spectrum: scenes element by element, loss, every gradient block and
+    dL/d(dx, dy, theta) per frame against the oracle; clearing the transforms gives
+    back the untransformed plan's results."""
     st = _st()
     prob = XF_CASES[name]()
     d, w, rng = _data(prob, seed=62)
@@ -1316,8 +1320,9 @@ def test_frame_transforms_parity(name):
     l_plain, g_plain = l_plain.clone(), g_plain.clone()
     for big in (False, True):
         xf = _xf_for(prob.E, rng, big)
-        gx = plan.set_frame_transforms(xf)
+        gx = plan.set_frame_transforms(xf, algo=xalgo)
         assert all(c["algo"] == st.CONV_DIRECT for c in plan.classes())
+        assert plan.frame_transforms_info()[0] == xalgo
         sc = plan.render_scene(p).cpu().numpy().astype(np.float64)
         ref = ora.render_scene_xf(prob.n, prob.s, prob.N, prob.M, prob.fwhm, p, xf)
         _check_frames(sc, ref, (prob.s * prob.n).tolist(), 2e-6)
@@ -1334,7 +1339,8 @@ def test_frame_transforms_parity(name):
                   for k, v in parity.deconv_blocks(prob, go).items() if np.linalg.norm(v) > 0}
         rx = parity.rel_err(gxd, gxo)
         rxs = [parity.rel_err(gxd[j::3], gxo[j::3]) for j in range(3)]
-        _say(f"xf {name} big={big}: loss rel {rl:.2e}; grad {blocks}; transforms {rx:.2e} {rxs}")
+        _say(f"xf {name}/{'fft' if xalgo == 2 else 'direct'} big={big}: loss rel {rl:.2e}; grad {blocks}; "
+             f"transforms {rx:.2e} {rxs}")
         assert rl <= 1e-6
         assert parity.rel_err(grad, go) <= 1e-4
         for k, v in blocks.items():
@@ -1345,6 +1351,40 @@ def test_frame_transforms_parity(name):
     l2, g2 = plan.loss_grad(p)
     assert abs(l2[2].item() - l_plain[2].item()) <= 1e-6 * abs(l_plain[2].item())
     assert parity.rel_err(g2.cpu().numpy(), g_plain.cpu().numpy()) <= 1e-5
+
+
+def test_frame_transforms_auto_choice_and_graph_steps():
+    """With STARRED_CONV_AUTO the plan times both convolutions of the transformed frames
+    and keeps the faster; optimiser steps with transforms replayed from a captured
+    graph equal eager steps bit for bit, on both convolutions."""
+    st = _st()
+    prob = synth.make_deconv(4, E=6)
+    d, w, rng = _data(prob, seed=63)
+    xf = _xf_for(prob.E, rng)
+    p = torch.tensor(synth.eval_point(prob, "near", rng), dtype=torch.float32, device="cuda")
+    lr4 = [prob.adam_lr[k] for k in ("h", "Gamma", "a", "c")]
+    plan = _plan(prob, d, w, algo=st.CONV_AUTO)
+    plan.set_frame_transforms(xf)
+    algo, ms = plan.frame_transforms_info()
+    _say(f"transforms auto: algo {algo}, ms {ms}")
+    assert ms["direct"] > 0 and ms["fft"] > 0
+    assert algo == (st.CONV_FFT if ms["fft"] < ms["direct"] else st.CONV_DIRECT)
+    for xalgo in (st.CONV_DIRECT, st.CONV_FFT):
+        runs = []
+        for graph in (False, True):
+            pl = _plan(prob, d, w, algo=st.CONV_AUTO)
+            gx = pl.set_frame_transforms(xf, algo=xalgo)
+            pl.set_graph_mode(graph)
+            x = p.clone()
+            m = torch.zeros_like(p)
+            v = torch.zeros_like(p)
+            for t in range(1, 4):
+                loss = pl.step(x, m, v, t, lr4)
+                torch.cuda.synchronize()
+                _ = (torch.randn(1000, device="cuda") * 2).sum().item()
+            runs.append((loss.clone(), x.clone(), m.clone(), v.clone(), gx.clone()))
+        for a, b in zip(*runs):
+            assert torch.equal(a, b), xalgo
 
 
 # --------------------------------------------------------------------------- #
