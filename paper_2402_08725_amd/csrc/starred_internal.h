@@ -170,9 +170,11 @@ hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, floa
                               float *v_a, float *v_b, float *tmp);
 
 
+// gadd (or null): added to grad over [ga0, ga1) before the update and written back
 hipError_t launch_adam(hipStream_t st, long long P, const long long *seg_end, const float *lr,
-                       float *params, const float *grad, float *m, float *v, int *d_t, float beta1,
-                       float beta2, float eps, int rule = 0, float eps_root = 0.f);
+                       float *params, float *grad, float *m, float *v, int *d_t, float beta1,
+                       float beta2, float eps, int rule = 0, float eps_root = 0.f, const float *gadd = nullptr,
+                       long long ga0 = 0, long long ga1 = 0);
 hipError_t launch_set_step(hipStream_t st, int *d_t, int value);
 
 hipError_t launch_fill(hipStream_t st, float *p, long long n, float v);
@@ -214,19 +216,19 @@ hipError_t launch_history(hipStream_t st, long long n, const float *xn, float *x
 hipError_t launch_psf_render(hipStream_t st, int N, const float *params, float *s_out);
 hipError_t launch_psf_render64(hipStream_t st, int N, const float *params, double *s64);
 hipError_t launch_psf_fwd(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
-                          const double *s64, const float *data, const float *invvar, float *rho,
-                          double *part_chi, float *grad);
+                          const double *s64, const float *data, const float *invvar, float *rho, double *part);
 hipError_t launch_psf_model(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
                             const float *s_img, float *model);
-hipError_t launch_psf_adj(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
-                          const float *rho, float *gstar);
-hipError_t launch_psf_sum(hipStream_t st, int S, int N, const float *params, const float *gstar,
-                          const float *prior, float *grad, double *part_eta);
-hipError_t launch_psf_finalize_small(hipStream_t st, int S, int n_chi, const double *part_chi, int n_l1,
-                                     const double *part_l1, int n_eta, const double *part_eta, float *grad,
-                                     double *loss, int *tick = nullptr);
-int psf_sum_blocks(int N);
-size_t psf_fwd_lds(int n, int s);
-size_t psf_adj_lds(int n, int N);
+hipError_t launch_psf_adjsum(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
+                             const float *rho, float *grad, double *part_eta);
+hipError_t launch_psf_gadd(hipStream_t st, int N, const float *prior, float *grad);
+hipError_t launch_psf_finalize_small(hipStream_t st, int S, int N, int tiles, const double *part, int n_l1,
+                                     const double *part_l1, int n_eta, const double *part_eta, const float *params,
+                                     float *grad, double *loss, int *tick = nullptr);
+int psf_fwd_tiles(int n);   // forward tiles per star (four FP64 partials each)
+int psf_adj_tiles(int N);   // adjoint tiles (five FP64 partials each)
+size_t psf_fwd_lds(int s);
+size_t psf_adj_lds(int s, int S);
+size_t psf_model_lds(int n, int N);
 
 }  // namespace starred

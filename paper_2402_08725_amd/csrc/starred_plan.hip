@@ -162,7 +162,7 @@ struct starred_plan {
 
     // PSF mode
     int psf_n = 0;
-    float *d_simg = nullptr, *d_gstar = nullptr;
+    float *d_simg = nullptr;
     double *d_s64 = nullptr;
     double *d_part_eta = nullptr;
     int algo_req = STARRED_CONV_AUTO;
@@ -934,15 +934,14 @@ static int build_psf(starred_plan *p)
     p->ndata = (long long)S * n * n;
     p->nfine = (long long)N * N;
     const long long NN = (long long)N * N;
-    if (psf_fwd_lds(n, p->s) > kMaxLds || psf_adj_lds(n, N) > kMaxLds)
+    if (psf_fwd_lds(p->s) > kMaxLds || psf_adj_lds(p->s, S) > kMaxLds || psf_model_lds(n, N) > kMaxLds)
         return fail(STARRED_EUNSUPPORTED, "PSF grid too large for one work group");
     int rc;
     if ((rc = p->alloc(&p->d_simg, NN))) return rc;
     if ((rc = p->alloc(&p->d_s64, NN))) return rc;
     if ((rc = p->alloc(&p->d_rho, p->ndata))) return rc;
-    if ((rc = p->alloc(&p->d_gstar, (size_t)S * NN))) return rc;
-    if ((rc = p->alloc(&p->d_part_chi, S))) return rc;
-    if ((rc = p->alloc(&p->d_part_eta, (size_t)psf_sum_blocks(N) * 5))) return rc;
+    if ((rc = p->alloc(&p->d_part_chi, (size_t)S * psf_fwd_tiles(n) * 4))) return rc;
+    if ((rc = p->alloc(&p->d_part_eta, (size_t)psf_adj_tiles(N) * 5))) return rc;
     if ((rc = dense_setup(p, 1))) return rc;
     if ((rc = p->alloc(&p->d_part_l1, std::max((size_t)starlet_l1_slots(p->N, p->J), dense_l1_slots(p))))) return rc;
     if ((rc = p->alloc(&p->d_z, (size_t)p->J * NN))) return rc;
@@ -1781,10 +1780,12 @@ static int autotune(starred_plan *p)
     return rc;
 }
 
-static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out, int *tick = nullptr)
+// prior_in_adam: the Adam update that follows adds the prior's gradient to
+// grad_b (and writes it back); otherwise a small launch adds it here.
+static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out, int *tick = nullptr,
+                              bool prior_in_adam = false)
 {
     const int S = p->E, n = p->psf_n, N = p->N;
-    const long long NN = (long long)N * N;
     int n_l1 = 0;
     int rc = starlet_branch(p, params + 5, grad != nullptr, &n_l1);
     if (rc) return rc;
@@ -1793,25 +1794,20 @@ static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad,
     p->prof_stop(STARRED_STAGE_RENDER, e0);
     e0 = p->prof_start();
     HIP_TRY(launch_psf_fwd(p->st, S, n, p->s, N, p->sigma, params, p->d_s64, p->data, p->invvar, p->d_rho,
-                           p->d_part_chi, grad));
+                           p->d_part_chi));
     p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
     if (grad) {
         e0 = p->prof_start();
-        HIP_TRY(launch_psf_adj(p->st, S, n, p->s, N, p->sigma, params, p->d_rho, p->d_gstar));
+        HIP_TRY(launch_psf_adjsum(p->st, S, n, p->s, N, p->sigma, params, p->d_rho, grad, p->d_part_eta));
         p->prof_stop(STARRED_STAGE_CONV_ADJ, e0);
     }
-    // the sums read the prior's gradient: the starlet branch joins first
+    // the L1 partials and the prior's gradient come from the starlet branch
     HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
-    if (grad) {
-        e0 = p->prof_start();
-        HIP_TRY(launch_psf_sum(p->st, S, N, params, p->d_gstar, p->d_prior, grad, p->d_part_eta));
-        p->prof_stop(STARRED_STAGE_GRAD_SUMS, e0);
-    }
     e0 = p->prof_start();
-    HIP_TRY(launch_psf_finalize_small(p->st, S, S, p->d_part_chi, n_l1, p->d_part_l1, psf_sum_blocks(N),
-                                      p->d_part_eta, grad, loss_out, tick));
+    HIP_TRY(launch_psf_finalize_small(p->st, S, N, psf_fwd_tiles(n), p->d_part_chi, n_l1, p->d_part_l1,
+                                      psf_adj_tiles(N), p->d_part_eta, params, grad, loss_out, tick));
+    if (grad && !prior_in_adam) HIP_TRY(launch_psf_gadd(p->st, N, p->d_prior, grad));
     p->prof_stop(STARRED_STAGE_FINALIZE, e0);
-    (void)NN;
     return STARRED_OK;
 }
 
@@ -2023,21 +2019,23 @@ static int run_steps(starred_plan *p, float *params, float *m, float *v, int32_t
     ad.rule = hp->rule;
     ad.eps_root = hp->eps_root;
     auto one = [&]() -> int {
-        int rc = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t)
+        int rc = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t, true)
                                           : loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t,
                                                            fused_adam ? &ad : nullptr);
         if (rc) return rc;
         if (fused_adam) return STARRED_OK;
         const long long NN = (long long)p->N * p->N;
         long long seg[3] = {NN, NN + p->E, NN + p->E + (long long)p->E * p->M};
-        if (p->mode == STARRED_PSF) {
+        const bool psf = p->mode == STARRED_PSF;
+        if (psf) {
             seg[0] = 5;
             seg[1] = 5 + NN;
             seg[2] = 5 + NN + p->E;
         }
         hipEvent_t e0 = p->prof_start();
+        // PSF mode: the update adds the prior's gradient to grad_b
         HIP_TRY(launch_adam(p->st, p->nparams, seg, hp->lr, params, p->d_grad, m, v, p->d_t, hp->beta1, hp->beta2,
-                            hp->eps, hp->rule, hp->eps_root));
+                            hp->eps, hp->rule, hp->eps_root, psf ? p->d_prior : nullptr, 5, 5 + NN));
         p->prof_stop(STARRED_STAGE_ADAM, e0);
         return STARRED_OK;
     };
@@ -2405,8 +2403,6 @@ int starred_time_stage(starred_plan *p, const float *params, int32_t stage, int3
     if (!p->frames_set) return fail(STARRED_ESTATE, "set_frames has not been called");
     const bool fft = (p->algo == STARRED_CONV_FFT);
     const bool fused = fft && p->fft_fused && p->fd.n_fused > 0;
-    // the one-launch forward beside the line passes when both have frames
-    const bool split = fused && p->fwd_split && p->fd.frows_lg.n_items > 0;
     int n_l1 = 0;
     auto launch = [&]() -> int {
         switch (stage) {

@@ -8,7 +8,9 @@
 //   m_k(p, q) = a_k sum_t Gy[t] sum_u Gx[u] s(yb(p) + t, xb(q) + u),
 // so each star is two banded passes over the grid (no dependence of the taps on
 // p or q). Derivative taps dGx (the derivative of Gx with respect to cx) give
-// the centre gradient. One work group per star; everything deterministic.
+// the centre gradient. The forward runs one work group per (data tile, star),
+// the adjoint one per grid tile with every star summed inside it, so a few tens
+// of stars still fill the chip; every reduction runs in a fixed order.
 #include "starred_internal.h"
 #include "starred_fft.h"
 
@@ -122,91 +124,122 @@ __device__ __forceinline__ void psf_taps64(double c, int s, double sigma, int T,
     }
 }
 
-constexpr int kPsfRowChunk = 8;  // data rows per pass of the forward
+constexpr int kPsfRowChunk = 8;   // data rows of one forward tile
+constexpr int kPsfColTile = 32;   // data columns of one forward tile
+static_assert(kPsfRowChunk * kPsfColTile == kPsfThreads, "one thread per data pixel of a forward tile");
 
-// One work group per star: unit model u and centre derivatives ux, uy (FP64),
-// residual rho = w (m - d) (stored FP32 for the adjoint), chi-square, and
-// dchi/da, dchi/dc of the star. params = [eta 5 | b N^2 | a S | c 2S]
-__global__ __launch_bounds__(kPsfThreads) void k_psf_fwd(
-    int S, int n, int s, int N, float sigma, const float *__restrict__ params,
-    const double *__restrict__ s64, const float *__restrict__ data, const float *__restrict__ invvar,
-    float *__restrict__ rho, double *__restrict__ part_chi, float *__restrict__ grad)
+int psf_fwd_tiles(int n) { return ((n + kPsfRowChunk - 1) / kPsfRowChunk) * ((n + kPsfColTile - 1) / kPsfColTile); }
+
+// Grid window one forward tile reads: rows x columns
+template <int SS> struct PsfFwdWin {
+    static constexpr int T = 2 * kGaussRadius + SS + 2;
+    static constexpr int RM = SS * (kPsfRowChunk - 1) + T;
+    static constexpr int CM = SS * (kPsfColTile - 1) + T;
+    static_assert(CM <= 128, "the window's columns map onto 128 lanes");
+    static constexpr size_t lds = ((size_t)RM * CM + 2 * (size_t)RM * kPsfColTile) * sizeof(double);
+};
+
+// LDS of one forward tile: the grid window it reads (FP64) and its two x-pass planes
+size_t psf_fwd_lds(int s)
 {
+    return s == 1 ? PsfFwdWin<1>::lds : s == 2 ? PsfFwdWin<2>::lds : PsfFwdWin<3>::lds;
+}
+
+// One work group per (8-row x 32-column data tile, star): unit model u and centre
+// derivatives ux, uy (FP64), residual rho = w (m - d) (stored FP32 for the
+// adjoint), and the tile's chi-square, dchi/da and the two sums dchi/dc needs
+// (divided by a_k), as four FP64 partials in part[(k * tiles + tile) * 4 ..].
+// params = [eta 5 | b N^2 | a S | c 2S]
+template <int SS>
+__global__ __launch_bounds__(kPsfThreads) void k_psf_fwd(
+    int S, int n, int N, float sigma, const float *__restrict__ params,
+    const double *__restrict__ s64, const float *__restrict__ data, const float *__restrict__ invvar,
+    float *__restrict__ rho, double *__restrict__ part)
+{
+    using Win = PsfFwdWin<SS>;
+    constexpr int T = Win::T, RM = Win::RM, CM = Win::CM, QT = kPsfColTile;
     extern __shared__ double smd[];
     __shared__ double G[2][kPsfMaxT], dG[2][kPsfMaxT];
     __shared__ double red[kPsfThreads / 64];
-    const int k = blockIdx.x;
+    const int k = blockIdx.z;
     const long long NN = (long long)N * N;
     const double a = params[5 + NN + k];
     const double cx = params[5 + NN + S + 2 * k], cy = params[5 + NN + S + 2 * k + 1];
-    const int T = 2 * kGaussRadius + s + 2;
-    psf_taps64(cx, s, (double)sigma, T, G[0], dG[0]);
-    psf_taps64(cy, s, (double)sigma, T, G[1], dG[1]);
-    __syncthreads();
+    psf_taps64(cx, SS, (double)sigma, T, G[0], dG[0]);
+    psf_taps64(cy, SS, (double)sigma, T, G[1], dG[1]);
     const int fx = (int)floor(cx), fy = (int)floor(cy);
-    const int rows = kPsfRowChunk * s + T;  // grid rows one chunk of data rows needs
-    double *T1 = smd;
-    double *T1x = smd + (long long)rows * n;
-    double chi = 0.0, sa = 0.0, sx = 0.0, sy = 0.0;
-    const long long doff = (long long)k * n * n;
-    for (int p0 = 0; p0 < n; p0 += kPsfRowChunk) {
-        const int y0 = s * p0 - fy - kGaussRadius - 1;  // grid row of T1 row 0
-        __syncthreads();
-        // T1(y', q) = sum_u Gx[u] s(y', xb(q) + u), T1x with dGx
-        for (int e = threadIdx.x; e < rows * n; e += blockDim.x) {
-            const int r = e / n, q = e - r * n;
-            const int yp = y0 + r;
-            double acc = 0.0, accx = 0.0;
-            if (yp >= 0 && yp < N) {
-                const int xb = s * q - fx - kGaussRadius - 1;
-                const double *row = s64 + (long long)yp * N;
-                for (int u = 0; u < T; ++u) {
-                    const int xx = xb + u;
-                    if (xx >= 0 && xx < N) {
-                        const double v = row[xx];
-                        acc = fma(G[0][u], v, acc);
-                        accx = fma(dG[0][u], v, accx);
-                    }
-                }
-            }
-            T1[e] = acc;
-            T1x[e] = accx;
+    const int p0 = blockIdx.x * kPsfRowChunk, q0 = blockIdx.y * QT;
+    const int y0 = SS * p0 - fy - kGaussRadius - 1;  // grid row of window row 0
+    const int x0 = SS * q0 - fx - kGaussRadius - 1;  // grid column of window column 0
+    double *W = smd;              // RM x CM window of s, zero off the grid
+    double *T1 = W + RM * CM;     // T1(y', q) = sum_u Gx[u] s(y', xb(q) + u): RM x 32
+    double *T1x = T1 + RM * QT;   // the same with dGx
+    {
+        // the window, two rows per pass of the work group, every load of a thread in flight at once
+        const int c = threadIdx.x & 127, r0 = threadIdx.x >> 7;
+        const int xx = x0 + c;
+        const bool cin = c < CM && xx >= 0 && xx < N;
+        constexpr int NR = (RM + 1) / 2;
+        double v[NR];
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const int yy = y0 + r0 + 2 * i;
+            v[i] = (cin && r0 + 2 * i < RM && yy >= 0 && yy < N) ? s64[(long long)yy * N + xx] : 0.0;
         }
-        __syncthreads();
-        const int np = min(kPsfRowChunk, n - p0);
-        for (int e = threadIdx.x; e < np * n; e += blockDim.x) {
-            const int pl = e / n, q = e - pl * n;
-            const int p = p0 + pl;
-            const int rb = s * pl;  // T1 row of tap 0 for this data row
+#pragma unroll
+        for (int i = 0; i < NR; ++i)
+            if (c < CM && r0 + 2 * i < RM) W[(r0 + 2 * i) * CM + c] = v[i];
+    }
+    __syncthreads();
+    {
+        const int q = threadIdx.x % QT;
+        for (int r = threadIdx.x / QT; r < RM; r += kPsfThreads / QT) {
+            const double *w = W + r * CM + SS * q;
+            double acc = 0.0, accx = 0.0;
+#pragma unroll
+            for (int u = 0; u < T; ++u) {
+                acc = fma(G[0][u], w[u], acc);
+                accx = fma(dG[0][u], w[u], accx);
+            }
+            T1[r * QT + q] = acc;
+            T1x[r * QT + q] = accx;
+        }
+    }
+    __syncthreads();
+    double chi = 0.0, sa = 0.0, sx = 0.0, sy = 0.0;
+    {
+        const int pl = threadIdx.x / QT, q = threadIdx.x % QT;
+        if (p0 + pl < n && q0 + q < n) {
+            const int rb = SS * pl;  // window row of tap 0 for this data row
             double u = 0.0, ux = 0.0, uy = 0.0;
+#pragma unroll
             for (int t = 0; t < T; ++t) {
-                const double v = T1[(rb + t) * n + q];
+                const double v = T1[(rb + t) * QT + q];
                 u = fma(G[1][t], v, u);
                 uy = fma(dG[1][t], v, uy);
-                ux = fma(G[1][t], T1x[(rb + t) * n + q], ux);
+                ux = fma(G[1][t], T1x[(rb + t) * QT + q], ux);
             }
-            const long long idx = doff + (long long)p * n + q;
+            const long long idx = (long long)k * n * n + (long long)(p0 + pl) * n + q0 + q;
             const double r = a * u - (double)data[idx];
             const double w = invvar[idx];
             const double rh = w * r;
             rho[idx] = (float)rh;
-            chi += 0.5 * w * r * r;
-            sa += rh * u;
-            sx += rh * ux;
-            sy += rh * uy;
+            chi = 0.5 * w * r * r;
+            sa = rh * u;
+            sx = rh * ux;
+            sy = rh * uy;
         }
     }
-    chi = block_sum_d_fft(chi, red);
-    sa = block_sum_d_fft(sa, red);
-    sx = block_sum_d_fft(sx, red);
-    sy = block_sum_d_fft(sy, red);
-    if (threadIdx.x == 0) {
-        if (part_chi) part_chi[k] = chi;
-        if (grad) {
-            grad[5 + NN + k] = (float)sa;
-            grad[5 + NN + S + 2 * k] = (float)(a * sx);
-            grad[5 + NN + S + 2 * k + 1] = (float)(a * sy);
-        }
+    chi = block_sum_d_fft<kPsfThreads>(chi, red);
+    sa = block_sum_d_fft<kPsfThreads>(sa, red);
+    sx = block_sum_d_fft<kPsfThreads>(sx, red);
+    sy = block_sum_d_fft<kPsfThreads>(sy, red);
+    if (threadIdx.x == 0 && part) {
+        double *o = part + ((long long)k * gridDim.x * gridDim.y + (long long)blockIdx.y * gridDim.x + blockIdx.x) * 4;
+        o[0] = chi;
+        o[1] = sa;
+        o[2] = sx;
+        o[3] = sy;
     }
 }
 
@@ -252,158 +285,313 @@ __global__ __launch_bounds__(kPsfThreads) void k_psf_model(int S, int n, int s, 
     }
 }
 
-// Adjoint of star k: gstar_k(y', x') = a_k sum_p Gy[t(p,y')] sum_q Gx[u(q,x')] rho_k(p, q),
-// written per star (summed over stars, in star order, by k_psf_sum).
-__global__ __launch_bounds__(kPsfThreads) void k_psf_adj(int S, int n, int s, int N, float sigma,
-                                                         const float *__restrict__ params,
-                                                         const float *__restrict__ rho,
-                                                         float *__restrict__ gstar)
+// Adjoint, summed over stars: dchi/ds(y', x') = sum_k a_k sum_p Gy_k[t(p,y')]
+// sum_q Gx_k[u(q,x')] rho_k(p, q), with t = y' + floor(cy_k) + R + 1 - s p and
+// u likewise. One work group per 8 x 16 tile of the grid; stars are taken in
+// batches: the batch's residual windows and taps go to LDS, then
+// U_k(p, x') = sum_q Gx_k[u] rho_k(p, q) for the window's rows, then each of four
+// thread groups adds a contiguous quarter of the batch's stars per pixel, in star
+// order, and the four sums are added in group order. The pixel then writes grad_b = dchi/ds
+// (the prior's L1 gradient Phi z is added after the starlet branch joins) and its share of dchi/deta = sum_x dchi/ds(x)
+// dm/deta(x), one block partial per tile (five values).
+constexpr int kPsfAdjTy = 8, kPsfAdjTx = 16, kPsfAdjPix = kPsfAdjTy * kPsfAdjTx;
+constexpr int kPsfAdjGroups = 4;  // thread groups of a tile, each adding a quarter of the batch's stars
+constexpr int kPsfAdjThreads = kPsfAdjGroups * kPsfAdjPix;
+constexpr size_t kPsfAdjLds = 48 * 1024;
+
+template <int SS> struct PsfAdjWin {
+    static constexpr int T = 2 * kGaussRadius + SS + 2;
+    static constexpr int PR = (kPsfAdjTy + T - 2) / SS + 1;  // residual rows one tile reads
+    static constexpr int QC = (kPsfAdjTx + T - 2) / SS + 1;  // residual columns
+    static constexpr int KT = (T - 1) / SS + 1;               // taps per output, at most
+    // per star: window, U rows, taps (x then y), four ints, a_k and c_k
+    static constexpr size_t per_star = ((size_t)PR * QC + (size_t)PR * kPsfAdjTx + 2 * T + 7) * sizeof(float);
+};
+
+static size_t psf_adj_per_star(int s)
 {
-    extern __shared__ float sm[];
-    __shared__ float G[2][kPsfMaxT], dG[2][kPsfMaxT];
-    const int k = blockIdx.x;
-    const long long NN = (long long)N * N;
-    const float a = params[5 + NN + k];
-    const float cx = params[5 + NN + S + 2 * k], cy = params[5 + NN + S + 2 * k + 1];
-    const int T = 2 * kGaussRadius + s + 2;
-    psf_taps(cx, s, sigma, T, G[0], dG[0]);
-    psf_taps(cy, s, sigma, T, G[1], dG[1]);
-    __syncthreads();
-    const int fx = (int)floorf(cx), fy = (int)floorf(cy);
-    const float *rk = rho + (long long)k * n * n;
-    // U(p, x') = sum_q rho(p, q) Gx[x' - xb(q)]   (n rows x N columns)
-    float *U = sm;
-    for (int e = threadIdx.x; e < n * N; e += blockDim.x) {
-        const int p = e / N, xp = e - p * N;
-        float acc = 0.f;
-        // q with 0 <= xp - (s q - fx - R - 1) < T
-        const int base = xp + fx + kGaussRadius + 1;  // = s q + u
-        int qhi = base / s;
-        int qlo = (base - T + 1 + s - 1) / s;
-        if (base - T + 1 < 0) qlo = 0;
-        if (qhi > n - 1) qhi = n - 1;
-        for (int q = max(qlo, 0); q <= qhi; ++q) {
-            const int u = base - s * q;
-            if (u >= 0 && u < T) acc = fmaf(G[0][u], rk[p * n + q], acc);
-        }
-        U[e] = acc;
-    }
-    __syncthreads();
-    float *gk = gstar + (long long)k * NN;
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int yp = e / N, xp = e - yp * N;
-        const int base = yp + fy + kGaussRadius + 1;
-        int phi = base / s;
-        int plo = (base - T + 1 + s - 1) / s;
-        if (base - T + 1 < 0) plo = 0;
-        if (phi > n - 1) phi = n - 1;
-        float acc = 0.f;
-        for (int p = max(plo, 0); p <= phi; ++p) {
-            const int t = base - s * p;
-            if (t >= 0 && t < T) acc = fmaf(G[1][t], U[p * N + xp], acc);
-        }
-        gk[e] = a * acc;
-    }
+    return s == 1 ? PsfAdjWin<1>::per_star : s == 2 ? PsfAdjWin<2>::per_star : PsfAdjWin<3>::per_star;
 }
 
-// dchi/ds = sum over stars (in order); dchi/deta = sum_x dchi/ds(x) dm/deta(x);
-// grad_b = dchi/ds + prior (the L1 gradient, Phi z).
-constexpr int kPsfSumThreads = 256;
-__global__ __launch_bounds__(kPsfSumThreads) void k_psf_sum(int S, int N, const float *__restrict__ params,
-                                                            const float *__restrict__ gstar,
-                                                            const float *__restrict__ prior,
-                                                            float *__restrict__ grad,
-                                                            double *__restrict__ part_eta)
+static int psf_adj_batch(int s, int S)
 {
-    __shared__ double red[kPsfSumThreads / 64];
+    return (int)std::max<size_t>(1, std::min<size_t>((size_t)S, kPsfAdjLds / psf_adj_per_star(s)));
+}
+
+int psf_adj_tiles(int N) { return ((N + kPsfAdjTx - 1) / kPsfAdjTx) * ((N + kPsfAdjTy - 1) / kPsfAdjTy); }
+
+// floor(a / b) for b > 0
+__device__ __forceinline__ int psf_fdiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+template <int SS>
+__global__ __launch_bounds__(kPsfAdjThreads) void k_psf_adjsum(int S, int n, int N, float sigma, int kb,
+                                                               const float *__restrict__ params,
+                                                               const float *__restrict__ rho,
+                                                               float *__restrict__ grad,
+                                                               double *__restrict__ part_eta)
+{
+    using Win = PsfAdjWin<SS>;
+    constexpr int T = Win::T, PR = Win::PR, QC = Win::QC, KT = Win::KT, TX = kPsfAdjTx;
+    extern __shared__ float sm[];
+    __shared__ double red[kPsfAdjThreads / 64];
+    int *sp = (int *)sm;                    // per star: first residual row, first column, floor(cx), floor(cy)
+    float *sa = sm + 4 * kb;                // a_k
+    float *sc = sa + kb;                    // c_k: [kb][2]
+    float *Gt = sc + 2 * kb;                // taps: [kb][2][T] (x, then y)
+    float *Rt = Gt + 2 * kb * T;            // residual windows [kb][PR][QC]
+    float *U = Rt + (size_t)kb * PR * QC;   // [kb][PR][TX]
     const long long NN = (long long)N * N;
-    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    const int X0 = blockIdx.x * TX, Y0 = blockIdx.y * kPsfAdjTy;
+    const int pix_l = threadIdx.x % kPsfAdjPix, grp = threadIdx.x / kPsfAdjPix;
+    const int xl = pix_l % TX, yl = pix_l / TX;
+    const int xp = X0 + xl, yp = Y0 + yl;
+    const float fc_norm = 1.0f / (2.50662827463100050f * sigma);
+    const float inv2s2 = 1.0f / (2.0f * sigma * sigma);
+    constexpr int R1 = kGaussRadius + 1;
+    float gs = 0.f;
+    for (int k0 = 0; k0 < S; k0 += kb) {
+        const int nk = min(kb, S - k0);
+        __syncthreads();  // the previous batch is done with the LDS
+        // per (star, direction): c, floor(c) and the first residual row (column)
+        for (int j = threadIdx.x; j < 2 * nk; j += kPsfAdjThreads) {
+            const int kk = j >> 1, dir = j & 1, k = k0 + kk;
+            const float c = params[5 + NN + S + 2 * k + dir];
+            const int f = (int)floorf(c);
+            // rows p (columns q) with 0 <= y' + f + R + 1 - s p < T for some y' (x') of the tile
+            sp[4 * kk + 1 - dir] = -psf_fdiv(-((dir ? Y0 : X0) + f + R1 - T + 1), SS);
+            sp[4 * kk + 2 + dir] = f;
+            sc[j] = c;
+            if (dir == 0) sa[kk] = params[5 + NN + k];
+        }
+        __syncthreads();
+        // taps G[t] = sum_{b < s} g(b + floor(c) + R + 1 - t - c) and the residual
+        // windows, sixteen loads of a thread in flight at once
+        for (int e = threadIdx.x; e < nk * 2 * T; e += kPsfAdjThreads) {
+            const int j = e / T, t = e - j * T;
+            const float c = sc[j];
+            const float fc = floorf(c);
+            float g = 0.f;
+#pragma unroll
+            for (int b = 0; b < SS; ++b) {
+                const float arg = ((float)b + fc + (float)(R1 - t)) - c;
+                g += fc_norm * expf(-arg * arg * inv2s2);
+            }
+            Gt[e] = g;
+        }
+        {
+            const int tot = nk * PR * QC;
+            for (int e0 = threadIdx.x; e0 < tot; e0 += 16 * kPsfAdjThreads) {
+                float v[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int e = e0 + j * kPsfAdjThreads;
+                    const int kk = e / (PR * QC), r = e - kk * (PR * QC), i = r / QC, c = r - i * QC;
+                    const int pp = e < tot ? sp[4 * kk] + i : -1, qq = e < tot ? sp[4 * kk + 1] + c : -1;
+                    v[j] = (pp >= 0 && pp < n && qq >= 0 && qq < n)
+                               ? rho[(long long)(k0 + kk) * n * n + (long long)pp * n + qq]
+                               : 0.f;
+                }
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (e0 + j * kPsfAdjThreads < tot) Rt[e0 + j * kPsfAdjThreads] = v[j];
+            }
+        }
+        __syncthreads();
+        // U_k(p, x') over the tile's columns, one thread per (star, column) for all the
+        // window's rows: q ascending from the first that reaches x'. Taps past the
+        // last q are zero and read a clamped (finite) residual.
+        for (int e = threadIdx.x; e < nk * TX; e += kPsfAdjThreads) {
+            const int kk = e / TX, xc = e - kk * TX;
+            const int base = X0 + xc + sp[4 * kk + 2] + R1;  // = s q + u
+            const int qa = -psf_fdiv(-(base - T + 1), SS);
+            const int u0 = base - SS * qa;                   // tap of q = qa, < T
+            const int j0 = qa - sp[4 * kk + 1];               // window column of q = qa, >= 0
+            const float *g = Gt + kk * 2 * T;
+            float gj[KT];
+            int jc[KT];
+#pragma unroll
+            for (int jj = 0; jj < KT; ++jj) {
+                const int u = u0 - SS * jj;
+                gj[jj] = u >= 0 ? g[max(u, 0)] : 0.f;
+                jc[jj] = min(j0 + jj, QC - 1);
+            }
+            const float *rr = Rt + (size_t)kk * PR * QC;
+            float *uo = U + (size_t)kk * PR * TX + xc;
+#pragma unroll
+            for (int i = 0; i < PR; ++i) {
+                float acc = 0.f;
+#pragma unroll
+                for (int jj = 0; jj < KT; ++jj) acc = fmaf(gj[jj], rr[i * QC + jc[jj]], acc);
+                uo[i * TX] = acc;
+            }
+        }
+        __syncthreads();
+        const int base_y = yp + R1;
+        const int qk = (nk + kPsfAdjGroups - 1) / kPsfAdjGroups;
+        const int kk_end = min(nk, (grp + 1) * qk);
+#pragma unroll 2
+        for (int kk = grp * qk; kk < kk_end; ++kk) {
+            const int by = base_y + sp[4 * kk + 3];
+            const int pa = -psf_fdiv(-(by - T + 1), SS);
+            const int t0 = by - SS * pa;       // tap of p = pa, < T
+            const int i0 = pa - sp[4 * kk];    // window row of p = pa, >= 0
+            const float *g = Gt + kk * 2 * T + T;
+            const float *uu = U + (size_t)kk * PR * TX + xl;
+            float acc = 0.f;
+#pragma unroll
+            for (int ii = 0; ii < KT; ++ii) {
+                const int t = t0 - SS * ii;
+                acc = fmaf(t >= 0 ? g[max(t, 0)] : 0.f, uu[min(i0 + ii, PR - 1) * TX], acc);
+            }
+            gs += sa[kk] * acc;
+        }
+    }
+    __shared__ float gsum[kPsfAdjGroups][kPsfAdjPix];
+    gsum[grp][pix_l] = gs;
+    __syncthreads();
     float de[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    if (pix < NN) {
-        float gs = 0.f;
-        for (int k = 0; k < S; ++k) gs += gstar[(long long)k * NN + pix];
+    if (grp == 0 && xp < N && yp < N) {
+        gs = gsum[0][pix_l];
+#pragma unroll
+        for (int g = 1; g < kPsfAdjGroups; ++g) gs += gsum[g][pix_l];
+        const int pix = yp * N + xp;
         float m;
         float d[5];
-        moffat_eval(params, N, pix / N, pix % N, m, d);
+        moffat_eval(params, N, yp, xp, m, d);
         for (int e = 0; e < 5; ++e) de[e] = gs * d[e];
-        grad[5 + pix] = gs + (prior ? prior[pix] : 0.f);
+        grad[5 + pix] = gs;
     }
+    const long long tile = (long long)blockIdx.y * gridDim.x + blockIdx.x;
     for (int e = 0; e < 5; ++e) {
-        const double t = block_sum_d_fft((double)de[e], red);
-        if (threadIdx.x == 0) part_eta[(long long)blockIdx.x * 5 + e] = t;
+        const double t = block_sum_d_fft<kPsfAdjThreads>((double)de[e], red);
+        if (threadIdx.x == 0) part_eta[tile * 5 + e] = t;
     }
 }
 
-__global__ __launch_bounds__(256) void k_psf_finalize_small(int S, int n_chi, const double *__restrict__ part_chi,
+size_t psf_adj_lds(int s, int S) { return psf_adj_per_star(s) * psf_adj_batch(s, S); }
+
+// Loss and the small gradient blocks: chi-square over every forward tile, the L1
+// partials, dchi/da_k and dchi/dc_k = a_k sum rho du/dc from the star's tiles
+// (in tile order), dchi/deta from the adjoint tiles. Every sum is a fixed-order
+// strided pass and a fixed-order block reduction.
+__global__ __launch_bounds__(256) void k_psf_finalize_small(int S, int N, int tiles, const double *__restrict__ part,
                                                             int n_l1, const double *__restrict__ part_l1,
                                                             int n_eta, const double *__restrict__ part_eta,
+                                                            const float *__restrict__ params,
                                                             float *__restrict__ grad, double *__restrict__ loss,
                                                             int *__restrict__ tick)
 {
     if (tick && threadIdx.x == 0) *tick += 1;  // the Adam step that follows reads it
-    __shared__ double red[4];
-    double a = 0.0;
-    for (int i = threadIdx.x; i < n_chi; i += 256) a += part_chi[i];
-    const double chi = block_sum_d_fft(a, red);
-    double b = 0.0;
-    for (int i = threadIdx.x; i < n_l1; i += 256) b += part_l1[i];
-    const double l1 = block_sum_d_fft(b, red);
-    if (threadIdx.x == 0 && loss) {
-        loss[0] = chi;
-        loss[1] = l1;
-        loss[2] = chi + l1;
+    const long long NN = (long long)N * N;
+    if (grad) {
+        for (int k = threadIdx.x; k < S; k += 256) {
+            const double *o = part + (long long)k * tiles * 4;
+            double sa = 0.0, sx = 0.0, sy = 0.0;
+#pragma unroll 8
+            for (int t = 0; t < tiles; ++t) {
+                sa += o[4 * t + 1];
+                sx += o[4 * t + 2];
+                sy += o[4 * t + 3];
+            }
+            const double ak = params[5 + NN + k];
+            grad[5 + NN + k] = (float)sa;
+            grad[5 + NN + S + 2 * k] = (float)(ak * sx);
+            grad[5 + NN + S + 2 * k + 1] = (float)(ak * sy);
+        }
     }
-    if (grad && threadIdx.x < 5) {
-        double acc = 0.0;
-        for (int i = 0; i < n_eta; ++i) acc += part_eta[(long long)i * 5 + threadIdx.x];
-        grad[threadIdx.x] = (float)acc;
+    // chi-square, L1 and the five dchi/deta sums: strided per-thread sums, then one
+    // fixed-order reduction of all seven
+    double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const long long n_chi = (long long)S * tiles;
+#pragma unroll 4
+    for (long long i = threadIdx.x; i < n_chi; i += 256) v[0] += part[i * 4];
+#pragma unroll 4
+    for (int i = threadIdx.x; i < n_l1; i += 256) v[1] += part_l1[i];
+    if (grad) {
+#pragma unroll 2
+        for (int i = threadIdx.x; i < n_eta; i += 256)
+#pragma unroll
+            for (int e = 0; e < 5; ++e) v[2 + e] += part_eta[(long long)i * 5 + e];
+    }
+    __shared__ double red[4][7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int j = 0; j < 7; ++j) red[threadIdx.x >> 6][j] = v[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r[7];
+#pragma unroll
+        for (int j = 0; j < 7; ++j) r[j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+        if (loss) {
+            loss[0] = r[0];
+            loss[1] = r[1];
+            loss[2] = r[0] + r[1];
+        }
+        if (grad) {
+#pragma unroll
+            for (int e = 0; e < 5; ++e) grad[e] = (float)r[2 + e];
+        }
     }
 }
 
-size_t psf_fwd_lds(int n, int s) { return (size_t)2 * (kPsfRowChunk * s + 2 * kGaussRadius + s + 2) * n * sizeof(double); }
-size_t psf_adj_lds(int n, int N) { return (size_t)n * N * sizeof(float); }
+size_t psf_model_lds(int n, int N) { return (size_t)n * N * sizeof(float); }
 
 hipError_t launch_psf_fwd(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
-                          const double *s64, const float *data, const float *invvar, float *rho,
-                          double *part_chi, float *grad)
+                          const double *s64, const float *data, const float *invvar, float *rho, double *part)
 {
-    hipLaunchKernelGGL(k_psf_fwd, dim3(S), dim3(kPsfThreads), psf_fwd_lds(n, ss), st, S, n, ss, N, sigma, params,
-                       s64, data, invvar, rho, part_chi, grad);
+    const dim3 grid((n + kPsfRowChunk - 1) / kPsfRowChunk, (n + kPsfColTile - 1) / kPsfColTile, S);
+    auto kern = ss == 1 ? k_psf_fwd<1> : ss == 2 ? k_psf_fwd<2> : k_psf_fwd<3>;
+    hipLaunchKernelGGL(kern, grid, dim3(kPsfThreads), psf_fwd_lds(ss), st, S, n, N, sigma, params, s64, data, invvar,
+                       rho, part);
     return hipGetLastError();
 }
 
 hipError_t launch_psf_model(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
                             const float *s_img, float *model)
 {
-    hipLaunchKernelGGL(k_psf_model, dim3(S), dim3(kPsfThreads), psf_adj_lds(n, N), st, S, n, ss, N, sigma,
+    hipLaunchKernelGGL(k_psf_model, dim3(S), dim3(kPsfThreads), psf_model_lds(n, N), st, S, n, ss, N, sigma,
                        params, s_img, model);
     return hipGetLastError();
 }
 
-hipError_t launch_psf_adj(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
-                          const float *rho, float *gstar)
+hipError_t launch_psf_adjsum(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
+                             const float *rho, float *grad, double *part_eta)
 {
-    hipLaunchKernelGGL(k_psf_adj, dim3(S), dim3(kPsfThreads), psf_adj_lds(n, N), st, S, n, ss, N, sigma, params,
-                       rho, gstar);
+    const int kb = psf_adj_batch(ss, S);
+    const dim3 grid((N + kPsfAdjTx - 1) / kPsfAdjTx, (N + kPsfAdjTy - 1) / kPsfAdjTy);
+    auto kern = ss == 1 ? k_psf_adjsum<1> : ss == 2 ? k_psf_adjsum<2> : k_psf_adjsum<3>;
+    hipLaunchKernelGGL(kern, grid, dim3(kPsfAdjThreads), psf_adj_per_star(ss) * kb, st, S, n, N, sigma, kb, params,
+                       rho, grad, part_eta);
     return hipGetLastError();
 }
 
-int psf_sum_blocks(int N) { return (N * N + kPsfSumThreads - 1) / kPsfSumThreads; }
-
-hipError_t launch_psf_sum(hipStream_t st, int S, int N, const float *params, const float *gstar,
-                          const float *prior, float *grad, double *part_eta)
+// grad_b += the prior's L1 gradient (the evaluation without an Adam update; the
+// update adds it itself)
+__global__ void k_psf_gadd(long long NN, const float *__restrict__ prior, float *__restrict__ gb)
 {
-    hipLaunchKernelGGL(k_psf_sum, dim3(psf_sum_blocks(N)), dim3(kPsfSumThreads), 0, st, S, N, params, gstar, prior,
-                       grad, part_eta);
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < NN) gb[i] += prior[i];
+}
+
+hipError_t launch_psf_gadd(hipStream_t st, int N, const float *prior, float *grad)
+{
+    const long long NN = (long long)N * N;
+    hipLaunchKernelGGL(k_psf_gadd, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, st, NN, prior, grad + 5);
     return hipGetLastError();
 }
 
-hipError_t launch_psf_finalize_small(hipStream_t st, int S, int n_chi, const double *part_chi, int n_l1,
-                                     const double *part_l1, int n_eta, const double *part_eta, float *grad,
-                                     double *loss, int *tick)
+hipError_t launch_psf_finalize_small(hipStream_t st, int S, int N, int tiles, const double *part, int n_l1,
+                                     const double *part_l1, int n_eta, const double *part_eta, const float *params,
+                                     float *grad, double *loss, int *tick)
 {
-    hipLaunchKernelGGL(k_psf_finalize_small, dim3(1), dim3(256), 0, st, S, n_chi, part_chi, n_l1, part_l1, n_eta,
-                       part_eta, grad, loss, tick);
+    hipLaunchKernelGGL(k_psf_finalize_small, dim3(1), dim3(256), 0, st, S, N, tiles, part, n_l1, part_l1, n_eta,
+                       part_eta, params, grad, loss, tick);
     return hipGetLastError();
 }
 

@@ -429,6 +429,10 @@ def test_loss_grad_before_set_frames_is_an_error():
 PSF_CASES = [
     ("psf_small_s3", dict(S=4, n=16, s=3, J=4)),
     ("psf_s2", dict(S=5, n=24, s=2, J=4)),
+    # ragged data tiles (37 = 4 x 8 + 5 rows, 32 + 5 columns) and grid tiles (111)
+    ("psf_s3_ragged", dict(S=3, n=37, s=3, J=4)),
+    # s = 1: more stars than one adjoint batch holds, ragged 21 x 21 grid
+    ("psf_s1_batches", dict(S=12, n=21, s=1, J=3)),
     ("psf_cfg3", dict()),
 ]
 
@@ -598,6 +602,49 @@ def test_graph_mode_psf():
         plan.loss_grad(p, grad_out=grad, loss_out=loss)
         torch.cuda.synchronize()
         assert torch.equal(loss, le) and torch.equal(grad, ge), rep
+
+
+def test_psf_adam_steps_match_oracle():
+    """PSF-mode Adam steps: the update adds the prior's gradient to dchi/db itself
+    (the adjoint runs beside the starlet branch), so four steps are checked against
+    the oracle's Adam on the oracle's whole gradient, and graph steps against eager ones."""
+    st = _st()
+    prob, d, w, rng, plan = _psf_setup(dict(S=4, n=16, s=3, J=4), 45)
+    p0 = synth.psf_eval_point(prob, "near", rng)
+    NN = prob.N * prob.N
+    lr4 = [1e-4, 1e-7, 1e-4 * float(np.median(prob.a)), 1e-3]
+    lrv = np.concatenate([np.full(5, lr4[0]), np.full(NN, lr4[1]), np.full(prob.S, lr4[2]),
+                          np.full(2 * prob.S, lr4[3])])
+    x = torch.tensor(p0, dtype=torch.float32, device="cuda")
+    m = torch.zeros_like(x)
+    v = torch.zeros_like(x)
+    po = p0.astype(np.float64)
+    mo, vo = np.zeros_like(po), np.zeros_like(po)
+    # the first Adam step moves each entry by lr sign(g); later ones weigh magnitudes,
+    # so a missing or doubled prior term in dchi/db shows by the fourth
+    for t in range(1, 5):
+        plan.step(x, m, v, t, lr4)
+        alpha_dev = plan.starlet_fwd(synth.f32(po[5:5 + NN])).cpu().numpy()
+        so, _ = parity.tie_override(prob.N, prob.J, po[5:5 + NN], alpha_dev)
+        _, go = ora.psf_loss_grad(prob, d, w, po, sgn_override=so)
+        ora.adam_step(po, go, mo, vo, t, lrv)
+    good = np.abs(vo) > 1e-6 * np.abs(vo).max()
+    xf = x.cpu().numpy().astype(np.float64)
+    err = np.abs(xf - po)[good] / np.maximum(np.abs(po[good]), lrv[good])
+    _say(f"psf adam 4 steps: {good.sum()} entries, max rel err {err.max():.2e}")
+    assert err.max() <= 1e-4
+    # eager and graph steps agree bit for bit
+    xe, me, ve = x.clone(), m.clone(), v.clone()
+    xg, mg, vg = x.clone(), m.clone(), v.clone()
+    le = torch.empty(3, dtype=torch.float64, device="cuda")
+    lg = torch.empty(3, dtype=torch.float64, device="cuda")
+    for t in range(2, 12):
+        plan.step(xe, me, ve, t, lr4, loss_out=le)
+    plan.set_graph_mode(True)
+    plan.steps(xg, mg, vg, 2, lr4, 10, loss_out=lg)
+    plan.set_graph_mode(False)
+    torch.cuda.synchronize()
+    assert torch.equal(xg, xe) and torch.equal(mg, me) and torch.equal(vg, ve) and torch.equal(lg, le)
 
 
 # --------------------------------------------------------------------------- #
