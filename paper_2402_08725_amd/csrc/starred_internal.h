@@ -214,13 +214,14 @@ hipError_t launch_history(hipStream_t st, long long n, const float *xn, float *x
 
 // PSF mode (starred_psf.hip)
 hipError_t launch_psf_render(hipStream_t st, int N, const float *params, float *s_out);
-hipError_t launch_psf_render64(hipStream_t st, int N, const float *params, double *s64);
+// dm (or null): the Moffat derivatives per pixel, [5][N^2]
+hipError_t launch_psf_render64(hipStream_t st, int N, const float *params, double *s64, float *dm);
 hipError_t launch_psf_fwd(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
                           const double *s64, const float *data, const float *invvar, float *rho, double *part);
 hipError_t launch_psf_model(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
                             const float *s_img, float *model);
 hipError_t launch_psf_adjsum(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
-                             const float *rho, float *grad, double *part_eta);
+                             const float *rho, const float *dm, float *grad, double *part_eta);
 hipError_t launch_psf_gadd(hipStream_t st, int N, const float *prior, float *grad);
 hipError_t launch_psf_finalize_small(hipStream_t st, int S, int N, int tiles, const double *part, int n_l1,
                                      const double *part_l1, int n_eta, const double *part_eta, const float *params,

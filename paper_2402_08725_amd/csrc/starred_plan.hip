@@ -162,7 +162,7 @@ struct starred_plan {
 
     // PSF mode
     int psf_n = 0;
-    float *d_simg = nullptr;
+    float *d_simg = nullptr, *d_dm = nullptr;
     double *d_s64 = nullptr;
     double *d_part_eta = nullptr;
     int algo_req = STARRED_CONV_AUTO;
@@ -939,6 +939,7 @@ static int build_psf(starred_plan *p)
     int rc;
     if ((rc = p->alloc(&p->d_simg, NN))) return rc;
     if ((rc = p->alloc(&p->d_s64, NN))) return rc;
+    if ((rc = p->alloc(&p->d_dm, 5 * NN))) return rc;
     if ((rc = p->alloc(&p->d_rho, p->ndata))) return rc;
     if ((rc = p->alloc(&p->d_part_chi, (size_t)S * psf_fwd_tiles(n) * 4))) return rc;
     if ((rc = p->alloc(&p->d_part_eta, (size_t)psf_adj_tiles(N) * 5))) return rc;
@@ -1790,7 +1791,7 @@ static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad,
     int rc = starlet_branch(p, params + 5, grad != nullptr, &n_l1);
     if (rc) return rc;
     hipEvent_t e0 = p->prof_start();
-    HIP_TRY(launch_psf_render64(p->st, N, params, p->d_s64));
+    HIP_TRY(launch_psf_render64(p->st, N, params, p->d_s64, grad ? p->d_dm : nullptr));
     p->prof_stop(STARRED_STAGE_RENDER, e0);
     e0 = p->prof_start();
     HIP_TRY(launch_psf_fwd(p->st, S, n, p->s, N, p->sigma, params, p->d_s64, p->data, p->invvar, p->d_rho,
@@ -1798,7 +1799,7 @@ static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad,
     p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
     if (grad) {
         e0 = p->prof_start();
-        HIP_TRY(launch_psf_adjsum(p->st, S, n, p->s, N, p->sigma, params, p->d_rho, grad, p->d_part_eta));
+        HIP_TRY(launch_psf_adjsum(p->st, S, n, p->s, N, p->sigma, params, p->d_rho, p->d_dm, grad, p->d_part_eta));
         p->prof_stop(STARRED_STAGE_CONV_ADJ, e0);
     }
     // the L1 partials and the prior's gradient come from the starlet branch

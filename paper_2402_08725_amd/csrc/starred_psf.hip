@@ -21,10 +21,36 @@ namespace starred {
 constexpr int kPsfThreads = 256;
 constexpr int kPsfMaxT = 2 * kGaussRadius + 3 + 2;  // s <= 3
 
+// Deterministic block sums of NV doubles per thread (NT threads) with one barrier:
+// each wave's butterfly, then thread 0 adds the waves in order (v holds the sums there).
+template <int NT, int NV>
+__device__ __forceinline__ void block_sum_vec(double (&v)[NV], double (*sh)[NV])
+{
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) sh[threadIdx.x >> 6][j] = v[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double r = 0.0;
+#pragma unroll
+            for (int i = 0; i < NT / 64; ++i) r += sh[i][j];
+            v[j] = r;
+        }
+    }
+}
+
 // Moffat profile and its parameter derivatives at pixel (y, x). The profile's
 // wings enter the chi-square multiplied by star amplitudes up to 1e6, so the
 // transcendental part is evaluated in FP64 (N^2 evaluations per call) and rounded.
-__device__ __forceinline__ void moffat_eval(const float *eta, int N, int y, int x, float &m, float d[5])
+__device__ __forceinline__ void moffat_eval(const float *eta, int N, int y, int x, double &m, float d[5])
 {
     const double A = eta[0], ax = eta[1], ay = eta[2], phi = eta[3], beta = eta[4];
     double sn, cs;
@@ -37,7 +63,7 @@ __device__ __forceinline__ void moffat_eval(const float *eta, int N, int y, int 
     const double l1q = log1p(Q);
     const double base = exp(-beta * l1q);
     const double md = A * base;
-    m = (float)md;
+    m = md;
     if (d) {
         const double dQ = -beta * md / (1.0 + Q);
         d[0] = (float)base;
@@ -53,9 +79,9 @@ __global__ void k_psf_render(int N, const float *__restrict__ params, float *__r
 {
     const int pix = blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= N * N) return;
-    float m;
+    double m;
     moffat_eval(params, N, pix / N, pix % N, m, nullptr);
-    s_img[pix] = m + params[5 + pix];
+    s_img[pix] = (float)m + params[5 + pix];
 }
 
 hipError_t launch_psf_render(hipStream_t st, int N, const float *params, float *s_out)
@@ -86,23 +112,26 @@ __device__ __forceinline__ void psf_taps(float c, int s, float sigma, int T, flo
 // FP64 copy of the narrow PSF for the forward model: with star amplitudes up to
 // 1e6 the chi-square near the truth is set by model errors far below an FP32
 // ulp of the brightest pixels, so the (small) PSF-mode forward runs in FP64.
-__global__ void k_psf_render64(int N, const float *__restrict__ params, double *__restrict__ s64)
+// dm (or null): the Moffat derivatives dm/deta per pixel, [5][N^2], for the adjoint.
+__global__ void k_psf_render64(int N, const float *__restrict__ params, double *__restrict__ s64,
+                               float *__restrict__ dm)
 {
     const int pix = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix >= N * N) return;
-    const int y = pix / N, x = pix % N;
-    const double A = params[0], ax = params[1], ay = params[2], phi = params[3], beta = params[4];
-    double sn, cs;
-    sincos(phi, &sn, &cs);
-    const double dx = (double)(x - N / 2), dy = (double)(y - N / 2);
-    const double u = cs * dx + sn * dy, v = -sn * dx + cs * dy;
-    const double Q = (u / ax) * (u / ax) + (v / ay) * (v / ay);
-    s64[pix] = A * exp(-beta * log1p(Q)) + (double)params[5 + pix];
+    const long long NN = (long long)N * N;
+    if (pix >= NN) return;
+    double m;
+    float d[5];
+    moffat_eval(params, N, pix / N, pix % N, m, d);
+    s64[pix] = m + (double)params[5 + pix];
+    if (dm) {
+#pragma unroll
+        for (int e = 0; e < 5; ++e) dm[e * NN + pix] = d[e];
+    }
 }
 
-hipError_t launch_psf_render64(hipStream_t st, int N, const float *params, double *s64)
+hipError_t launch_psf_render64(hipStream_t st, int N, const float *params, double *s64, float *dm)
 {
-    hipLaunchKernelGGL(k_psf_render64, dim3((N * N + 255) / 256), dim3(256), 0, st, N, params, s64);
+    hipLaunchKernelGGL(k_psf_render64, dim3((N * N + 255) / 256), dim3(256), 0, st, N, params, s64, dm);
     return hipGetLastError();
 }
 
@@ -160,36 +189,42 @@ __global__ __launch_bounds__(kPsfThreads) void k_psf_fwd(
     constexpr int T = Win::T, RM = Win::RM, CM = Win::CM, QT = kPsfColTile;
     extern __shared__ double smd[];
     __shared__ double G[2][kPsfMaxT], dG[2][kPsfMaxT];
-    __shared__ double red[kPsfThreads / 64];
+    __shared__ double red[kPsfThreads / 64][4];
     const int k = blockIdx.z;
     const long long NN = (long long)N * N;
+    const int p0 = blockIdx.x * kPsfRowChunk, q0 = blockIdx.y * QT;
+    // this thread's data pixel, loaded first: it does not depend on the star's centre
+    const int pl = threadIdx.x / QT, ql = threadIdx.x % QT;
+    const bool own = p0 + pl < n && q0 + ql < n;
+    const long long idx = (long long)k * n * n + (long long)(p0 + pl) * n + q0 + ql;
+    const double dat = own ? (double)data[idx] : 0.0, wgt = own ? (double)invvar[idx] : 0.0;
     const double a = params[5 + NN + k];
     const double cx = params[5 + NN + S + 2 * k], cy = params[5 + NN + S + 2 * k + 1];
-    psf_taps64(cx, SS, (double)sigma, T, G[0], dG[0]);
-    psf_taps64(cy, SS, (double)sigma, T, G[1], dG[1]);
     const int fx = (int)floor(cx), fy = (int)floor(cy);
-    const int p0 = blockIdx.x * kPsfRowChunk, q0 = blockIdx.y * QT;
     const int y0 = SS * p0 - fy - kGaussRadius - 1;  // grid row of window row 0
     const int x0 = SS * q0 - fx - kGaussRadius - 1;  // grid column of window column 0
     double *W = smd;              // RM x CM window of s, zero off the grid
     double *T1 = W + RM * CM;     // T1(y', q) = sum_u Gx[u] s(y', xb(q) + u): RM x 32
     double *T1x = T1 + RM * QT;   // the same with dGx
+    // the window, two rows per pass of the work group, every load of a thread in
+    // flight at once (and in flight while the taps are computed)
+    const int wc = threadIdx.x & 127, wr = threadIdx.x >> 7;
+    constexpr int NR = (RM + 1) / 2;
+    double win[NR];
     {
-        // the window, two rows per pass of the work group, every load of a thread in flight at once
-        const int c = threadIdx.x & 127, r0 = threadIdx.x >> 7;
-        const int xx = x0 + c;
-        const bool cin = c < CM && xx >= 0 && xx < N;
-        constexpr int NR = (RM + 1) / 2;
-        double v[NR];
+        const int xx = x0 + wc;
+        const bool cin = wc < CM && xx >= 0 && xx < N;
 #pragma unroll
         for (int i = 0; i < NR; ++i) {
-            const int yy = y0 + r0 + 2 * i;
-            v[i] = (cin && r0 + 2 * i < RM && yy >= 0 && yy < N) ? s64[(long long)yy * N + xx] : 0.0;
+            const int yy = y0 + wr + 2 * i;
+            win[i] = (cin && wr + 2 * i < RM && yy >= 0 && yy < N) ? s64[(long long)yy * N + xx] : 0.0;
         }
-#pragma unroll
-        for (int i = 0; i < NR; ++i)
-            if (c < CM && r0 + 2 * i < RM) W[(r0 + 2 * i) * CM + c] = v[i];
     }
+    psf_taps64(cx, SS, (double)sigma, T, G[0], dG[0]);
+    psf_taps64(cy, SS, (double)sigma, T, G[1], dG[1]);
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+        if (wc < CM && wr + 2 * i < RM) W[(wr + 2 * i) * CM + wc] = win[i];
     __syncthreads();
     {
         const int q = threadIdx.x % QT;
@@ -206,40 +241,30 @@ __global__ __launch_bounds__(kPsfThreads) void k_psf_fwd(
         }
     }
     __syncthreads();
-    double chi = 0.0, sa = 0.0, sx = 0.0, sy = 0.0;
-    {
-        const int pl = threadIdx.x / QT, q = threadIdx.x % QT;
-        if (p0 + pl < n && q0 + q < n) {
-            const int rb = SS * pl;  // window row of tap 0 for this data row
-            double u = 0.0, ux = 0.0, uy = 0.0;
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};  // chi-square, then rho u, rho ux, rho uy
+    if (own) {
+        const int rb = SS * pl;  // window row of tap 0 for this data row
+        double u = 0.0, ux = 0.0, uy = 0.0;
 #pragma unroll
-            for (int t = 0; t < T; ++t) {
-                const double v = T1[(rb + t) * QT + q];
-                u = fma(G[1][t], v, u);
-                uy = fma(dG[1][t], v, uy);
-                ux = fma(G[1][t], T1x[(rb + t) * QT + q], ux);
-            }
-            const long long idx = (long long)k * n * n + (long long)(p0 + pl) * n + q0 + q;
-            const double r = a * u - (double)data[idx];
-            const double w = invvar[idx];
-            const double rh = w * r;
-            rho[idx] = (float)rh;
-            chi = 0.5 * w * r * r;
-            sa = rh * u;
-            sx = rh * ux;
-            sy = rh * uy;
+        for (int t = 0; t < T; ++t) {
+            const double v = T1[(rb + t) * QT + ql];
+            u = fma(G[1][t], v, u);
+            uy = fma(dG[1][t], v, uy);
+            ux = fma(G[1][t], T1x[(rb + t) * QT + ql], ux);
         }
+        const double r = a * u - dat;
+        const double rh = wgt * r;
+        rho[idx] = (float)rh;
+        sums[0] = 0.5 * wgt * r * r;
+        sums[1] = rh * u;
+        sums[2] = rh * ux;
+        sums[3] = rh * uy;
     }
-    chi = block_sum_d_fft<kPsfThreads>(chi, red);
-    sa = block_sum_d_fft<kPsfThreads>(sa, red);
-    sx = block_sum_d_fft<kPsfThreads>(sx, red);
-    sy = block_sum_d_fft<kPsfThreads>(sy, red);
+    block_sum_vec<kPsfThreads, 4>(sums, red);
     if (threadIdx.x == 0 && part) {
         double *o = part + ((long long)k * gridDim.x * gridDim.y + (long long)blockIdx.y * gridDim.x + blockIdx.x) * 4;
-        o[0] = chi;
-        o[1] = sa;
-        o[2] = sx;
-        o[3] = sy;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] = sums[j];
     }
 }
 
@@ -327,13 +352,14 @@ template <int SS>
 __global__ __launch_bounds__(kPsfAdjThreads) void k_psf_adjsum(int S, int n, int N, float sigma, int kb,
                                                                const float *__restrict__ params,
                                                                const float *__restrict__ rho,
+                                                               const float *__restrict__ dm,
                                                                float *__restrict__ grad,
                                                                double *__restrict__ part_eta)
 {
     using Win = PsfAdjWin<SS>;
     constexpr int T = Win::T, PR = Win::PR, QC = Win::QC, KT = Win::KT, TX = kPsfAdjTx;
     extern __shared__ float sm[];
-    __shared__ double red[kPsfAdjThreads / 64];
+    __shared__ double red[kPsfAdjThreads / 64][5];
     int *sp = (int *)sm;                    // per star: first residual row, first column, floor(cx), floor(cy)
     float *sa = sm + 4 * kb;                // a_k
     float *sc = sa + kb;                    // c_k: [kb][2]
@@ -345,6 +371,13 @@ __global__ __launch_bounds__(kPsfAdjThreads) void k_psf_adjsum(int S, int n, int
     const int pix_l = threadIdx.x % kPsfAdjPix, grp = threadIdx.x / kPsfAdjPix;
     const int xl = pix_l % TX, yl = pix_l / TX;
     const int xp = X0 + xl, yp = Y0 + yl;
+    const bool own = grp == 0 && xp < N && yp < N;
+    // this pixel's Moffat derivatives dm/deta, loaded first (used at the end)
+    float dmp[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    if (own) {
+#pragma unroll
+        for (int e = 0; e < 5; ++e) dmp[e] = dm[e * NN + (long long)yp * N + xp];
+    }
     const float fc_norm = 1.0f / (2.50662827463100050f * sigma);
     const float inv2s2 = 1.0f / (2.0f * sigma * sigma);
     constexpr int R1 = kGaussRadius + 1;
@@ -352,8 +385,9 @@ __global__ __launch_bounds__(kPsfAdjThreads) void k_psf_adjsum(int S, int n, int
     for (int k0 = 0; k0 < S; k0 += kb) {
         const int nk = min(kb, S - k0);
         __syncthreads();  // the previous batch is done with the LDS
-        // per (star, direction): c, floor(c) and the first residual row (column)
-        for (int j = threadIdx.x; j < 2 * nk; j += kPsfAdjThreads) {
+        // per (star, direction): c, floor(c) and the first residual row (column), by the
+        // last threads (the first group's are loading their pixel's derivatives)
+        for (int j = kPsfAdjThreads - 1 - threadIdx.x; j < 2 * nk; j += kPsfAdjThreads) {
             const int kk = j >> 1, dir = j & 1, k = k0 + kk;
             const float c = params[5 + NN + S + 2 * k + dir];
             const int f = (int)floorf(c);
@@ -449,31 +483,29 @@ __global__ __launch_bounds__(kPsfAdjThreads) void k_psf_adjsum(int S, int n, int
     __shared__ float gsum[kPsfAdjGroups][kPsfAdjPix];
     gsum[grp][pix_l] = gs;
     __syncthreads();
-    float de[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    if (grp == 0 && xp < N && yp < N) {
+    double de[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (own) {
         gs = gsum[0][pix_l];
 #pragma unroll
         for (int g = 1; g < kPsfAdjGroups; ++g) gs += gsum[g][pix_l];
-        const int pix = yp * N + xp;
-        float m;
-        float d[5];
-        moffat_eval(params, N, yp, xp, m, d);
-        for (int e = 0; e < 5; ++e) de[e] = gs * d[e];
-        grad[5 + pix] = gs;
+#pragma unroll
+        for (int e = 0; e < 5; ++e) de[e] = (double)(gs * dmp[e]);
+        grad[5 + (long long)yp * N + xp] = gs;
     }
-    const long long tile = (long long)blockIdx.y * gridDim.x + blockIdx.x;
-    for (int e = 0; e < 5; ++e) {
-        const double t = block_sum_d_fft<kPsfAdjThreads>((double)de[e], red);
-        if (threadIdx.x == 0) part_eta[tile * 5 + e] = t;
+    block_sum_vec<kPsfAdjThreads, 5>(de, red);
+    if (threadIdx.x == 0) {
+        const long long tile = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+        for (int e = 0; e < 5; ++e) part_eta[tile * 5 + e] = de[e];
     }
 }
 
 size_t psf_adj_lds(int s, int S) { return psf_adj_per_star(s) * psf_adj_batch(s, S); }
 
 // Loss and the small gradient blocks: chi-square over every forward tile, the L1
-// partials, dchi/da_k and dchi/dc_k = a_k sum rho du/dc from the star's tiles
-// (in tile order), dchi/deta from the adjoint tiles. Every sum is a fixed-order
-// strided pass and a fixed-order block reduction.
+// partials, dchi/da_k and dchi/dc_k = a_k sum rho du/dc from the star's tiles,
+// dchi/deta from the adjoint tiles. Every sum is a fixed-order strided pass and a
+// fixed-order reduction.
 __global__ __launch_bounds__(256) void k_psf_finalize_small(int S, int N, int tiles, const double *__restrict__ part,
                                                             int n_l1, const double *__restrict__ part_l1,
                                                             int n_eta, const double *__restrict__ part_eta,
@@ -484,19 +516,32 @@ __global__ __launch_bounds__(256) void k_psf_finalize_small(int S, int N, int ti
     if (tick && threadIdx.x == 0) *tick += 1;  // the Adam step that follows reads it
     const long long NN = (long long)N * N;
     if (grad) {
-        for (int k = threadIdx.x; k < S; k += 256) {
-            const double *o = part + (long long)k * tiles * 4;
+        // eight lanes per star: lane l adds tiles l, l + 8, ... in order, then a
+        // butterfly over the eight lanes (lane 0's order fixed)
+        for (int k0 = 0; k0 < S; k0 += 32) {
+            const int k = k0 + (threadIdx.x >> 3), l = threadIdx.x & 7;
             double sa = 0.0, sx = 0.0, sy = 0.0;
-#pragma unroll 8
-            for (int t = 0; t < tiles; ++t) {
-                sa += o[4 * t + 1];
-                sx += o[4 * t + 2];
-                sy += o[4 * t + 3];
+            if (k < S) {
+                const double *o = part + (long long)k * tiles * 4;
+#pragma unroll 4
+                for (int t = l; t < tiles; t += 8) {
+                    sa += o[4 * t + 1];
+                    sx += o[4 * t + 2];
+                    sy += o[4 * t + 3];
+                }
             }
-            const double ak = params[5 + NN + k];
-            grad[5 + NN + k] = (float)sa;
-            grad[5 + NN + S + 2 * k] = (float)(ak * sx);
-            grad[5 + NN + S + 2 * k + 1] = (float)(ak * sy);
+#pragma unroll
+            for (int off = 4; off > 0; off >>= 1) {
+                sa += __shfl_xor(sa, off, 64);
+                sx += __shfl_xor(sx, off, 64);
+                sy += __shfl_xor(sy, off, 64);
+            }
+            if (k < S && l == 0) {
+                const double ak = params[5 + NN + k];
+                grad[5 + NN + k] = (float)sa;
+                grad[5 + NN + S + 2 * k] = (float)(ak * sx);
+                grad[5 + NN + S + 2 * k + 1] = (float)(ak * sy);
+            }
         }
     }
     // chi-square, L1 and the five dchi/deta sums: strided per-thread sums, then one
@@ -561,13 +606,13 @@ hipError_t launch_psf_model(hipStream_t st, int S, int n, int ss, int N, float s
 }
 
 hipError_t launch_psf_adjsum(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
-                             const float *rho, float *grad, double *part_eta)
+                             const float *rho, const float *dm, float *grad, double *part_eta)
 {
     const int kb = psf_adj_batch(ss, S);
     const dim3 grid((N + kPsfAdjTx - 1) / kPsfAdjTx, (N + kPsfAdjTy - 1) / kPsfAdjTy);
     auto kern = ss == 1 ? k_psf_adjsum<1> : ss == 2 ? k_psf_adjsum<2> : k_psf_adjsum<3>;
     hipLaunchKernelGGL(kern, grid, dim3(kPsfAdjThreads), psf_adj_per_star(ss) * kb, st, S, n, N, sigma, kb, params,
-                       rho, grad, part_eta);
+                       rho, dm, grad, part_eta);
     return hipGetLastError();
 }
 
