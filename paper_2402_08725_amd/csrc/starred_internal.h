@@ -170,11 +170,9 @@ hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, floa
                               float *v_a, float *v_b, float *tmp);
 
 
-// gadd (or null): added to grad over [ga0, ga1) before the update and written back
 hipError_t launch_adam(hipStream_t st, long long P, const long long *seg_end, const float *lr,
-                       float *params, float *grad, float *m, float *v, int *d_t, float beta1,
-                       float beta2, float eps, int rule = 0, float eps_root = 0.f, const float *gadd = nullptr,
-                       long long ga0 = 0, long long ga1 = 0);
+                       float *params, const float *grad, float *m, float *v, int *d_t, float beta1,
+                       float beta2, float eps, int rule = 0, float eps_root = 0.f);
 hipError_t launch_set_step(hipStream_t st, int *d_t, int value);
 
 hipError_t launch_fill(hipStream_t st, float *p, long long n, float v);
@@ -214,18 +212,20 @@ hipError_t launch_history(hipStream_t st, long long n, const float *xn, float *x
 
 // PSF mode (starred_psf.hip)
 hipError_t launch_psf_render(hipStream_t st, int N, const float *params, float *s_out);
-// dm (or null): the Moffat derivatives per pixel, [5][N^2]
-hipError_t launch_psf_render64(hipStream_t st, int N, const float *params, double *s64, float *dm);
+// dm (or null): the Moffat derivatives per pixel, [5][N^2]; tick (or null): the step
+// counter, advanced by this launch
+hipError_t launch_psf_render64(hipStream_t st, int N, const float *params, double *s64, float *dm,
+                               int *tick = nullptr);
 hipError_t launch_psf_fwd(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
                           const double *s64, const float *data, const float *invvar, float *rho, double *part);
 hipError_t launch_psf_model(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
                             const float *s_img, float *model);
 hipError_t launch_psf_adjsum(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
                              const float *rho, const float *dm, float *grad, double *part_eta);
-hipError_t launch_psf_gadd(hipStream_t st, int N, const float *prior, float *grad);
-hipError_t launch_psf_finalize_small(hipStream_t st, int S, int N, int tiles, const double *part, int n_l1,
-                                     const double *part_l1, int n_eta, const double *part_eta, const float *params,
-                                     float *grad, double *loss, int *tick = nullptr);
+// the loss, the gradient's small blocks, grad_b += prior, and (adam.params non-null) the update
+hipError_t launch_psf_finalize(hipStream_t st, int S, int N, int tiles, const double *part, int n_l1,
+                               const double *part_l1, int n_eta, const double *part_eta, const float *params,
+                               const float *prior, float *grad, double *loss, const AdamDev &adam = AdamDev());
 int psf_fwd_tiles(int n);   // forward tiles per star (four FP64 partials each)
 int psf_adj_tiles(int N);   // adjoint tiles (five FP64 partials each)
 size_t psf_fwd_lds(int s);

@@ -1353,14 +1353,11 @@ hipError_t launch_copy_probe(hipStream_t st, const float *src, float *dst, long 
     return hipGetLastError();
 }
 
-// gadd (or null): a term added to grad over [ga0, ga1) first (gadd[i - ga0]); the
-// sum is written back to grad, which then holds the whole gradient
 __global__ void k_adam(long long P, long long e0, long long e1, long long e2, float lr0, float lr1,
                        float lr2, float lr3, float *__restrict__ params,
-                       float *__restrict__ grad, float *__restrict__ m,
+                       const float *__restrict__ grad, float *__restrict__ m,
                        float *__restrict__ v, float beta1, float beta2, float eps,
-                       const int *__restrict__ d_t, int rule, float eps_root,
-                       const float *__restrict__ gadd, long long ga0, long long ga1)
+                       const int *__restrict__ d_t, int rule, float eps_root)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
@@ -1368,13 +1365,8 @@ __global__ void k_adam(long long P, long long e0, long long e1, long long e2, fl
     const float bc1 = 1.f - powf(beta1, t);
     const float bc2 = 1.f - powf(beta2, t);
     const float lr = i < e0 ? lr0 : (i < e1 ? lr1 : (i < e2 ? lr2 : lr3));
-    float g = grad[i];
-    if (gadd && i >= ga0 && i < ga1) {
-        g += gadd[i - ga0];
-        grad[i] = g;
-    }
     float pi = params[i], mi = m[i], vi = v[i];
-    adam_update(pi, mi, vi, g, lr, beta1, beta2, bc1, bc2, eps, rule == 1, eps_root);
+    adam_update(pi, mi, vi, grad[i], lr, beta1, beta2, bc1, bc2, eps, rule == 1, eps_root);
     m[i] = mi;
     v[i] = vi;
     params[i] = pi;
@@ -1387,14 +1379,12 @@ hipError_t launch_set_step(hipStream_t st, int *d_t, int value)
 }
 
 hipError_t launch_adam(hipStream_t st, long long P, const long long *seg_end, const float *lr,
-                       float *params, float *grad, float *m, float *v, int *d_t, float beta1,
-                       float beta2, float eps, int rule, float eps_root, const float *gadd, long long ga0,
-                       long long ga1)
+                       float *params, const float *grad, float *m, float *v, int *d_t, float beta1,
+                       float beta2, float eps, int rule, float eps_root)
 {
     const int nb = (int)((P + 255) / 256);
     hipLaunchKernelGGL(k_adam, dim3(nb), dim3(256), 0, st, P, seg_end[0], seg_end[1], seg_end[2],
-                       lr[0], lr[1], lr[2], lr[3], params, grad, m, v, beta1, beta2, eps, d_t, rule, eps_root,
-                       gadd, ga0, ga1);
+                       lr[0], lr[1], lr[2], lr[3], params, grad, m, v, beta1, beta2, eps, d_t, rule, eps_root);
     return hipGetLastError();
 }
 

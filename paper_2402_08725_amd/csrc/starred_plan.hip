@@ -1781,17 +1781,17 @@ static int autotune(starred_plan *p)
     return rc;
 }
 
-// prior_in_adam: the Adam update that follows adds the prior's gradient to
-// grad_b (and writes it back); otherwise a small launch adds it here.
+// tick: the device step counter the step advances (its first launch); adam: the update
+// fused into the final launch (which also adds the prior's gradient to grad_b)
 static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad, double *loss_out, int *tick = nullptr,
-                              bool prior_in_adam = false)
+                              const AdamDev *adam = nullptr)
 {
     const int S = p->E, n = p->psf_n, N = p->N;
     int n_l1 = 0;
     int rc = starlet_branch(p, params + 5, grad != nullptr, &n_l1);
     if (rc) return rc;
     hipEvent_t e0 = p->prof_start();
-    HIP_TRY(launch_psf_render64(p->st, N, params, p->d_s64, grad ? p->d_dm : nullptr));
+    HIP_TRY(launch_psf_render64(p->st, N, params, p->d_s64, grad ? p->d_dm : nullptr, tick));
     p->prof_stop(STARRED_STAGE_RENDER, e0);
     e0 = p->prof_start();
     HIP_TRY(launch_psf_fwd(p->st, S, n, p->s, N, p->sigma, params, p->d_s64, p->data, p->invvar, p->d_rho,
@@ -1805,9 +1805,9 @@ static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad,
     // the L1 partials and the prior's gradient come from the starlet branch
     HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
     e0 = p->prof_start();
-    HIP_TRY(launch_psf_finalize_small(p->st, S, N, psf_fwd_tiles(n), p->d_part_chi, n_l1, p->d_part_l1,
-                                      psf_adj_tiles(N), p->d_part_eta, params, grad, loss_out, tick));
-    if (grad && !prior_in_adam) HIP_TRY(launch_psf_gadd(p->st, N, p->d_prior, grad));
+    HIP_TRY(launch_psf_finalize(p->st, S, N, psf_fwd_tiles(n), p->d_part_chi, n_l1, p->d_part_l1, psf_adj_tiles(N),
+                                p->d_part_eta, params, grad ? p->d_prior : nullptr, grad, loss_out,
+                                adam ? *adam : AdamDev()));
     p->prof_stop(STARRED_STAGE_FINALIZE, e0);
     return STARRED_OK;
 }
@@ -2006,8 +2006,8 @@ static int run_steps(starred_plan *p, float *params, float *m, float *v, int32_t
     // the caller's step number is not the next one
     if (t != p->next_t) HIP_TRY(launch_set_step(p->st, p->d_t, t - 1));
     if (p->prof_on) HIP_TRY(launch_idle(p->st, kProfIdleIters));
-    // FFT path: the update runs inside the final reduction launch
-    const bool fused_adam = p->mode == STARRED_DECONV && p->algo == STARRED_CONV_FFT;
+    // FFT path and PSF mode: the update runs inside the final reduction launch
+    const bool fused_adam = p->mode == STARRED_PSF || p->algo == STARRED_CONV_FFT;
     AdamDev ad;
     ad.params = params;
     ad.m = m;
@@ -2020,23 +2020,16 @@ static int run_steps(starred_plan *p, float *params, float *m, float *v, int32_t
     ad.rule = hp->rule;
     ad.eps_root = hp->eps_root;
     auto one = [&]() -> int {
-        int rc = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t, true)
+        int rc = (p->mode == STARRED_PSF) ? psf_loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t, &ad)
                                           : loss_grad_impl(p, params, p->d_grad, loss_out, p->d_t,
                                                            fused_adam ? &ad : nullptr);
         if (rc) return rc;
         if (fused_adam) return STARRED_OK;
         const long long NN = (long long)p->N * p->N;
-        long long seg[3] = {NN, NN + p->E, NN + p->E + (long long)p->E * p->M};
-        const bool psf = p->mode == STARRED_PSF;
-        if (psf) {
-            seg[0] = 5;
-            seg[1] = 5 + NN;
-            seg[2] = 5 + NN + p->E;
-        }
+        const long long seg[3] = {NN, NN + p->E, NN + p->E + (long long)p->E * p->M};
         hipEvent_t e0 = p->prof_start();
-        // PSF mode: the update adds the prior's gradient to grad_b
         HIP_TRY(launch_adam(p->st, p->nparams, seg, hp->lr, params, p->d_grad, m, v, p->d_t, hp->beta1, hp->beta2,
-                            hp->eps, hp->rule, hp->eps_root, psf ? p->d_prior : nullptr, 5, 5 + NN));
+                            hp->eps, hp->rule, hp->eps_root));
         p->prof_stop(STARRED_STAGE_ADAM, e0);
         return STARRED_OK;
     };

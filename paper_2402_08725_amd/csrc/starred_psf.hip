@@ -113,12 +113,15 @@ __device__ __forceinline__ void psf_taps(float c, int s, float sigma, int T, flo
 // 1e6 the chi-square near the truth is set by model errors far below an FP32
 // ulp of the brightest pixels, so the (small) PSF-mode forward runs in FP64.
 // dm (or null): the Moffat derivatives dm/deta per pixel, [5][N^2], for the adjoint.
+// tick (or null): the step counter, advanced here (the step's first launch) for the
+// update at its end.
 __global__ void k_psf_render64(int N, const float *__restrict__ params, double *__restrict__ s64,
-                               float *__restrict__ dm)
+                               float *__restrict__ dm, int *__restrict__ tick)
 {
     const int pix = blockIdx.x * blockDim.x + threadIdx.x;
     const long long NN = (long long)N * N;
     if (pix >= NN) return;
+    if (tick && pix == 0) *tick += 1;
     double m;
     float d[5];
     moffat_eval(params, N, pix / N, pix % N, m, d);
@@ -129,9 +132,9 @@ __global__ void k_psf_render64(int N, const float *__restrict__ params, double *
     }
 }
 
-hipError_t launch_psf_render64(hipStream_t st, int N, const float *params, double *s64, float *dm)
+hipError_t launch_psf_render64(hipStream_t st, int N, const float *params, double *s64, float *dm, int *tick)
 {
-    hipLaunchKernelGGL(k_psf_render64, dim3((N * N + 255) / 256), dim3(256), 0, st, N, params, s64, dm);
+    hipLaunchKernelGGL(k_psf_render64, dim3((N * N + 255) / 256), dim3(256), 0, st, N, params, s64, dm, tick);
     return hipGetLastError();
 }
 
@@ -502,18 +505,37 @@ __global__ __launch_bounds__(kPsfAdjThreads) void k_psf_adjsum(int S, int n, int
 
 size_t psf_adj_lds(int s, int S) { return psf_adj_per_star(s) * psf_adj_batch(s, S); }
 
-// Loss and the small gradient blocks: chi-square over every forward tile, the L1
-// partials, dchi/da_k and dchi/dc_k = a_k sum rho du/dc from the star's tiles,
-// dchi/deta from the adjoint tiles. Every sum is a fixed-order strided pass and a
-// fixed-order reduction.
-__global__ __launch_bounds__(256) void k_psf_finalize_small(int S, int N, int tiles, const double *__restrict__ part,
-                                                            int n_l1, const double *__restrict__ part_l1,
-                                                            int n_eta, const double *__restrict__ part_eta,
-                                                            const float *__restrict__ params,
-                                                            float *__restrict__ grad, double *__restrict__ loss,
-                                                            int *__restrict__ tick)
+// Completion of the loss and gradient once the starlet branch has joined, and (ad.params
+// non-null) the optimiser update of every parameter. Work group 0: the chi-square over
+// every forward tile and the L1 partials, dchi/da_k and dchi/dc_k = a_k sum rho du/dc
+// from the star's tiles, dchi/deta from the adjoint tiles (every sum a fixed-order
+// strided pass and a fixed-order reduction), then the update of eta, a and c. Work
+// groups 1..: grad_b = dchi/ds + the prior's gradient, per pixel, and its update.
+__global__ __launch_bounds__(256) void k_psf_finalize(int S, int N, int tiles, const double *__restrict__ part,
+                                                      int n_l1, const double *__restrict__ part_l1,
+                                                      int n_eta, const double *__restrict__ part_eta,
+                                                      const float *params,  // updated through ad.params
+                                                      const float *__restrict__ prior,
+                                                      float *__restrict__ grad, double *__restrict__ loss,
+                                                      AdamDev ad)
 {
-    if (tick && threadIdx.x == 0) *tick += 1;  // the Adam step that follows reads it
+    if (blockIdx.x > 0) {
+        const long long NN = (long long)N * N;
+        const long long i = (long long)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
+        if (!grad || i >= NN) return;
+        const float g = grad[5 + i] + (prior ? prior[i] : 0.f);
+        grad[5 + i] = g;
+        if (ad.params) {
+            const float t = (float)(*ad.d_t);
+            const float bc1 = 1.f - powf(ad.beta1, t), bc2 = 1.f - powf(ad.beta2, t);
+            float pi = ad.params[5 + i], mi = ad.m[5 + i], vi = ad.v[5 + i];
+            adam_update(pi, mi, vi, g, ad.lr[1], ad.beta1, ad.beta2, bc1, bc2, ad.eps, ad.rule == 1, ad.eps_root);
+            ad.m[5 + i] = mi;
+            ad.v[5 + i] = vi;
+            ad.params[5 + i] = pi;
+        }
+        return;
+    }
     const long long NN = (long long)N * N;
     if (grad) {
         // eight lanes per star: lane l adds tiles l, l + 8, ... in order, then a
@@ -583,6 +605,21 @@ __global__ __launch_bounds__(256) void k_psf_finalize_small(int S, int N, int ti
             for (int e = 0; e < 5; ++e) grad[e] = (float)r[2 + e];
         }
     }
+    if (!grad || !ad.params) return;
+    // eta, a and c: their gradients are final (written above by this group); the a
+    // values read for dchi/dc were taken before the reduction's barrier
+    __syncthreads();
+    const float t = (float)(*ad.d_t);
+    const float bc1 = 1.f - powf(ad.beta1, t), bc2 = 1.f - powf(ad.beta2, t);
+    for (long long e = threadIdx.x; e < 5 + 3LL * S; e += blockDim.x) {
+        const long long i = e < 5 ? e : NN + e;  // past the b block
+        const float lr = i < 5 ? ad.lr[0] : (i < 5 + NN + S ? ad.lr[2] : ad.lr[3]);
+        float pi = ad.params[i], mi = ad.m[i], vi = ad.v[i];
+        adam_update(pi, mi, vi, grad[i], lr, ad.beta1, ad.beta2, bc1, bc2, ad.eps, ad.rule == 1, ad.eps_root);
+        ad.m[i] = mi;
+        ad.v[i] = vi;
+        ad.params[i] = pi;
+    }
 }
 
 size_t psf_model_lds(int n, int N) { return (size_t)n * N * sizeof(float); }
@@ -616,27 +653,14 @@ hipError_t launch_psf_adjsum(hipStream_t st, int S, int n, int ss, int N, float 
     return hipGetLastError();
 }
 
-// grad_b += the prior's L1 gradient (the evaluation without an Adam update; the
-// update adds it itself)
-__global__ void k_psf_gadd(long long NN, const float *__restrict__ prior, float *__restrict__ gb)
-{
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < NN) gb[i] += prior[i];
-}
-
-hipError_t launch_psf_gadd(hipStream_t st, int N, const float *prior, float *grad)
+hipError_t launch_psf_finalize(hipStream_t st, int S, int N, int tiles, const double *part, int n_l1,
+                               const double *part_l1, int n_eta, const double *part_eta, const float *params,
+                               const float *prior, float *grad, double *loss, const AdamDev &adam)
 {
     const long long NN = (long long)N * N;
-    hipLaunchKernelGGL(k_psf_gadd, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, st, NN, prior, grad + 5);
-    return hipGetLastError();
-}
-
-hipError_t launch_psf_finalize_small(hipStream_t st, int S, int N, int tiles, const double *part, int n_l1,
-                                     const double *part_l1, int n_eta, const double *part_eta, const float *params,
-                                     float *grad, double *loss, int *tick)
-{
-    hipLaunchKernelGGL(k_psf_finalize_small, dim3(1), dim3(256), 0, st, S, N, tiles, part, n_l1, part_l1, n_eta,
-                       part_eta, params, grad, loss, tick);
+    const unsigned groups = grad ? 1 + (unsigned)((NN + 255) / 256) : 1;
+    hipLaunchKernelGGL(k_psf_finalize, dim3(groups), dim3(256), 0, st, S, N, tiles, part, n_l1, part_l1, n_eta,
+                       part_eta, params, prior, grad, loss, adam);
     return hipGetLastError();
 }
 

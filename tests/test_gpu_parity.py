@@ -209,6 +209,22 @@ def test_loss_grad_parity_seven_scales(algo):
     _compare_loss_grad(prob, d, w, p, plan, f"J7/{ALGO_ID[algo]}")
 
 
+@pytest.mark.parametrize("algo", ALGOS, ids=lambda a: ALGO_ID[a])
+def test_widest_accepted_gaussian(algo):
+    """r_k at the widest FWHM a plan accepts (3 fine px: the +-8 px box the kernels
+    evaluate it in holds 6.3 sigma): the render and the loss and gradient against the
+    oracle's untruncated Gaussian, s = 3 with three sources."""
+    prob = synth.make_small_deconv(103, 3, [8, 12, 16], [13, 24, 6], 3, 48, 3, 4)
+    prob.fwhm = 3.0
+    d, w, rng = _data(prob, seed=303)
+    plan = _plan(prob, d, w, algo)
+    p = synth.eval_point(prob, "near", rng)
+    got = plan.render_scene(p).cpu().numpy()
+    ref = ora.render_scene(prob.n, prob.s, prob.N, prob.M, prob.fwhm, p)
+    _check_frames(got, ref, [prob.s * n for n in prob.n], 2e-6)
+    _compare_loss_grad(prob, d, w, p, plan, f"fwhm3/{ALGO_ID[algo]}")
+
+
 @pytest.mark.parametrize("E", [1, 3, 5])
 def test_loss_grad_parity_few_epochs_fft(E):
     """The frequency-domain adjoint with fewer frame chunks than the chunk sums' runs per
