@@ -17,6 +17,7 @@ constexpr int kProdPairQ = 128;        // one-launch forward: columns of at leas
 constexpr int kAdjFrames = 2;          // spectral adjoint: frames of a work group (a chunk), default
 constexpr int kAdjMaxFrames = 8;       // spectral adjoint: most frames of a chunk
 constexpr int kAdjSB = 4;              // spectral adjoint: sources per pass over the rows (M > 1)
+constexpr int kAdjSBWide = 8;          // the same with 2-frame chunks and more than kAdjSB sources
 constexpr int kAdjBlocks = 512;        // spectral adjoint: work groups aimed at per launch
 constexpr int kAdjMinRows = 4;         // spectral adjoint: fewest rows per thread
 constexpr int kAdjMaxRows = 64;        // spectral adjoint: most rows per work group

@@ -1298,9 +1298,11 @@ __device__ void tables_part(const ClassFft &c, const float2 *__restrict__ tw, co
 //   sum_Kx wgt(Kx) Re( conj(tx(Kx)) V_ty(Kx) ),  V_ty(Kx) = sum_Ky G(Ky, Kx) conj(ty(Ky)),
 // with one column sum V per y-table (window, gy_k, dgy_k). A block takes a chunk of
 // FC frames and the rows of a range of representatives y (rows congruent to y or
-// -y modulo Q, see below), SB sources per pass (one when M <= 1); a thread owns columns Kx (lanes) and every RG-th row
-// of the range, accumulates V over its rows, folds it with the x-tables, and the
-// block reduces the dot products once per group of kAdjSB sources through LDS.
+// -y modulo Q, see below), SB sources per pass (one when M <= 1; four, or eight with
+// 2-frame chunks and more than four sources, otherwise); a thread owns columns Kx (lanes)
+// and every RG-th row of the range, accumulates V over its rows, folds it with the
+// x-tables, and the block reduces the dot products once per group of SB sources through
+// LDS. Each pass reads the chunk's spectra again, so fewer, wider passes save reads.
 // The per-block partials are summed per frame (and the chunk spectra over chunks)
 // by k_adj_sums.
 template <int FC, int SB>
@@ -1831,7 +1833,12 @@ hipError_t fft_spec_adj(hipStream_t st, const FftPlanDev &d, int M)
         }
     } else {
         switch (d.adj_fc) {
-        case 2: SPEC_ADJ(2, kAdjSB); break;
+        case 2:
+            if (M > kAdjSB)
+                SPEC_ADJ(2, kAdjSBWide);
+            else
+                SPEC_ADJ(2, kAdjSB);
+            break;
         case 4: SPEC_ADJ(4, kAdjSB); break;
         default: return hipErrorInvalidValue;
         }

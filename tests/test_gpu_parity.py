@@ -1240,13 +1240,19 @@ def test_mixed_class_algorithms_graph_steps_match_eager():
     assert abs(lf[2].item() - lm[2].item()) <= 1e-6 * abs(lf[2].item())
 
 
-@pytest.mark.parametrize("case,fcs", [("cfg4_sub", (2, 4, 8)), ("cfg2_E5", (2, 4))])
+@pytest.mark.parametrize("case,fcs", [("cfg4_sub", (2, 4, 8)), ("cfg2_E5", (2, 4)), ("eleven_sources", (2, 4))])
 def test_fft_adjoint_chunk_sizes(case, fcs):
     """The frequency-domain adjoint with 2, 4 and 8 frames per chunk (8 only with one
     point source), including a last chunk that is not full, against the oracle and
-    against each other."""
+    against each other. Eleven sources: 2-frame chunks take eight sources per pass (a
+    full pass and a pass of three), 4-frame chunks four (two full passes and one of three)."""
     st = _st()
-    prob = synth.make_deconv(4, E=13) if case == "cfg4_sub" else synth.make_deconv(2, E=5)
+    if case == "cfg4_sub":
+        prob = synth.make_deconv(4, E=13)
+    elif case == "cfg2_E5":
+        prob = synth.make_deconv(2, E=5)
+    else:
+        prob = synth.make_small_deconv(331, 5, [24, 32], [15, 21], 2, 80, 11, 4)
     d, w, rng = _data(prob, seed=71)
     plan = _plan(prob, d, w, algo=st.CONV_FFT)
     p = synth.eval_point(prob, "near", rng)
