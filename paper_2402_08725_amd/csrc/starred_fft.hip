@@ -426,9 +426,11 @@ __device__ __forceinline__ float2 half_get(const float2 *__restrict__ X, int P, 
 }
 
 // ---- pass A: rows of the h window of each class (real -> half spectrum) ----
-// Its launch carries kTabBlocks extra work groups per class (when M > 0) that
-// compute the per-evaluation factor tables (k_tables' work) alongside.
-constexpr int kTabBlocks = 16;
+// Its launch carries extra work groups per class (when M > 0) that compute the
+// per-evaluation factor tables alongside: 16 for up to four sources,
+// more with more sources (the (1 + 4M) P entries each sum 17 Gaussian samples), so
+// that the tables are not the launch's longest work groups.
+__host__ __device__ inline int tab_blocks(int M) { return M <= 4 ? 16 : (M >= 32 ? 128 : 4 * M); }
 __device__ void tables_part(const ClassFft &c, const float2 *__restrict__ tw, const float *__restrict__ params,
                             int N, int E, int M, float sigma, float2 *__restrict__ tab, int e0, int estep);
 struct OpHRows {
@@ -442,8 +444,9 @@ struct OpHRows {
     static constexpr bool extra = true;
     __device__ void run_extra(int xb, const ClassFft *classes, const float2 *tw) const
     {
-        tables_part(classes[xb / kTabBlocks], tw, h, N, E, M, sigma, tab,
-                    threadIdx.x + (xb % kTabBlocks) * blockDim.x, blockDim.x * kTabBlocks);
+        const int tb = tab_blocks(M);
+        tables_part(classes[xb / tb], tw, h, N, E, M, sigma, tab, threadIdx.x + (xb % tb) * blockDim.x,
+                    blockDim.x * tb);
     }
     static constexpr bool col = false;
     static constexpr bool rowsum = false;
@@ -658,29 +661,64 @@ __global__ __launch_bounds__(kFftThreads) void k_spec_fwd(const SpecItem *__rest
                     for (int b = 0; b < S; ++b) sv[u][a * S + b] = half_get(Sp + fi.s_off, P, Kys[a], Kxs[b]);
             }
         }
-        #pragma unroll
-        for (int u = 0; u < FG; ++u) {
-            if (u < nfg) {
-                float2 acc = make_float2(0.f, 0.f);
+        if (MS > 0) {
+            #pragma unroll
+            for (int u = 0; u < FG; ++u) {
+                if (u < nfg) {
+                    float2 acc = make_float2(0.f, 0.f);
+                    #pragma unroll
+                    for (int a = 0; a < S; ++a)
+                        #pragma unroll
+                        for (int b = 0; b < S; ++b) {
+                            float2 F = cadd(hv[a * S + b], cscale(wv[a * S + b], Gv[u]));
+                            #pragma unroll
+                            for (int k = 0; k < MR; ++k) F = cadd(F, cscale(rk[a * S + b][k], av[u][k]));
+                            acc = cadd(acc, cmul(sv[u][a * S + b], F));
+                        }
+                    Mh[roff[u] + bin] = acc;
+                }
+            }
+        } else {
+            // many sources: source-major over the frame group, so each source's 1-D table
+            // values are loaded once per group, not once per frame and alias (the sums per
+            // frame and alias keep their order: H + Gamma W, then the sources in order)
+            float2 F[FG][S * S];
+            const float *ai[FG];
+            #pragma unroll
+            for (int u = 0; u < FG; ++u) {
+                const int i = cls_frames[c.cf_off + f0 + (u < nfg ? u : 0)];
+                ai[u] = params + (long long)N * N + E + (long long)i * M;
+                #pragma unroll
+                for (int ab = 0; ab < S * S; ++ab) F[u][ab] = cadd(hv[ab], cscale(wv[ab], Gv[u < nfg ? u : 0]));
+            }
+            for (int k = 0; k < M; ++k) {
+                const float2 *tk = t + (long long)(1 + 4 * k) * P;  // [gx | gy | dgx | dgy]
+                float2 ty[S], tx[S];
+                #pragma unroll
+                for (int a = 0; a < S; ++a) {
+                    ty[a] = tk[P + Kys[a]];
+                    tx[a] = tk[Kxs[a]];
+                }
+                float ak[FG];
+                #pragma unroll
+                for (int u = 0; u < FG; ++u) ak[u] = ai[u][k];
                 #pragma unroll
                 for (int a = 0; a < S; ++a)
                     #pragma unroll
                     for (int b = 0; b < S; ++b) {
-                        float2 F = cadd(hv[a * S + b], cscale(wv[a * S + b], Gv[u]));
-                        if (MS > 0) {
-                            #pragma unroll
-                            for (int k = 0; k < MR; ++k) F = cadd(F, cscale(rk[a * S + b][k], av[u][k]));
-                        } else {
-                            const int i = cls_frames[c.cf_off + f0 + u];
-                            const float *ai = params + (long long)N * N + E + (long long)i * M;
-                            for (int k = 0; k < M; ++k) {
-                                const float2 *tk = t + (long long)(1 + 4 * k) * P;
-                                F = cadd(F, cscale(cmul(tk[P + Kys[a]], tk[Kxs[b]]), ai[k]));
-                            }
-                        }
-                        acc = cadd(acc, cmul(sv[u][a * S + b], F));
+                        const float2 R = cmul(ty[a], tx[b]);
+                        #pragma unroll
+                        for (int u = 0; u < FG; ++u) F[u][a * S + b] = cadd(F[u][a * S + b], cscale(R, ak[u]));
                     }
-                Mh[roff[u] + bin] = acc;
+            }
+            #pragma unroll
+            for (int u = 0; u < FG; ++u) {
+                if (u < nfg) {
+                    float2 acc = make_float2(0.f, 0.f);
+                    #pragma unroll
+                    for (int ab = 0; ab < S * S; ++ab) acc = cadd(acc, cmul(sv[u][ab], F[u][ab]));
+                    Mh[roff[u] + bin] = acc;
+                }
             }
         }
     }
@@ -1275,13 +1313,17 @@ __device__ void tables_part(const ClassFft &c, const float2 *__restrict__ tw, co
         const int lo = max(0, (int)ceilf(ctr - c.o - kGaussRadius));
         const int hi = min(c.F - 1, (int)floorf(ctr - c.o + kGaussRadius));
         float2 acc = make_float2(0.f, 0.f);
+        // twiddle index K x mod P, advanced by K per sample (K < P)
+        int kx = lo <= hi ? (int)(((long long)K * lo) % P) : 0;
         for (int x = lo; x <= hi; ++x) {
             const float d = (float)(x + c.o) - ctr;
             float g = norm * expf(-d * d * inv2s2);
             if (deriv) g *= d * invs2;
-            const float2 w = twP[(int)(((long long)K * x) % P)];
+            const float2 w = twP[kx];
             acc.x += g * w.x;
             acc.y += g * w.y;
+            kx += K;
+            if (kx >= P) kx -= P;
         }
         t[e] = acc;
     }
@@ -1669,7 +1711,7 @@ hipError_t fft_spectra(hipStream_t st, const FftPlanDev &d, const float *params,
                        float sigma, int *tick, DensePiece *pa, DensePiece *pb)
 {
     // rows of the h windows, with the factor tables in extra work groups
-    const int extra = M > 0 ? d.n_classes * kTabBlocks : 0;
+    const int extra = M > 0 ? d.n_classes * tab_blocks(M) : 0;
     const OpHRows op{params, N, d.Th, d.hrows.n_items, E, M, sigma, d.tab, tick};
     hipError_t e = run_lines(st, d.hrows, d.classes, d.tw, op, d.hrows.n_items + extra, pa);
     if (e != hipSuccess) return e;

@@ -225,6 +225,19 @@ def test_widest_accepted_gaussian(algo):
     _compare_loss_grad(prob, d, w, p, plan, f"fwhm3/{ALGO_ID[algo]}")
 
 
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_many_sources_fft(s):
+    """More than sixteen point sources (the spectral product's source-major form) at
+    s = 1, 2 and 3, five ragged frames (a frame group of four and one of one), FFT path,
+    against the oracle."""
+    N = {1: 40, 2: 64, 3: 72}[s]
+    prob = synth.make_small_deconv(340 + s, 5, [N // s - 8, N // s], [11, 16], s, N, 17, 4)
+    d, w, rng = _data(prob, seed=341 + s)
+    plan = _plan(prob, d, w, 2)
+    p = synth.eval_point(prob, "near", rng)
+    _compare_loss_grad(prob, d, w, p, plan, f"M17/s{s}/fft")
+
+
 @pytest.mark.parametrize("E", [1, 3, 5])
 def test_loss_grad_parity_few_epochs_fft(E):
     """The frequency-domain adjoint with fewer frame chunks than the chunk sums' runs per
