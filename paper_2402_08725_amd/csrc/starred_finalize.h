@@ -63,25 +63,47 @@ __device__ void finalize_small_body(const FinalArgs &a)
     const int stride = 1 + 3 * M;
     if (a.tick && threadIdx.x == 0) *a.tick += 1;  // the update that follows reads it
     const float *pa = a.params + NN + E;
-    const int nred = 2 + (a.grad ? 2 * M : 0);
-    for (int r = 0; r < nred; ++r) {
+    for (int r = 0; r < 2; ++r) {
         double acc = 0.0;
         if (r == 0) {
             for (int i = threadIdx.x; i < a.n_chi; i += NT) acc += a.part_chi[i];
-        } else if (r == 1) {
-            for (int i = threadIdx.x; i < a.n_l1; i += NT) acc += a.part_l1[i];
         } else {
-            // dL/dc_k = sum_i a_ik <g_i, dr_k/dc>
-            const int q = r - 2, k = q >> 1, axis = q & 1;
-            for (int i = threadIdx.x; i < E; i += NT)
-                acc += (double)pa[(long long)i * M + k] * a.fsum[(long long)i * stride + 1 + (1 + axis) * M + k];
+            for (int i = threadIdx.x; i < a.n_l1; i += NT) acc += a.part_l1[i];
         }
         acc = group_sum<NT>(acc, gsh);
-        if (threadIdx.x == 0) {
-            if (r < 2) sums[r] = acc;
-            else {
-                // plus the point-source prior's share (pts[3k+1+axis])
-                const int q = r - 2;
+        if (threadIdx.x == 0) sums[r] = acc;
+    }
+    // dL/dc_k = sum_i a_ik <g_i, dr_k/dc> (plus the point-source prior's share pts[3k+1+axis])
+    const int nq = a.grad ? 2 * M : 0;
+    if (nq <= 4) {
+        // few sources (and often many frames): one whole-group sum per quantity
+        for (int q = 0; q < nq; ++q) {
+            const int k = q >> 1, axis = q & 1;
+            double acc = 0.0;
+            for (int i = threadIdx.x; i < E; i += NT)
+                acc += (double)pa[(long long)i * M + k] * a.fsum[(long long)i * stride + 1 + (1 + axis) * M + k];
+            acc = group_sum<NT>(acc, gsh);
+            if (threadIdx.x == 0) {
+                if (a.pts) acc += a.pts[3 * k + 1 + axis];
+                a.grad[NN + E + (long long)E * M + q] = (float)acc;
+            }
+        }
+    } else {
+        // many sources: the 2M sums side by side, L lanes per sum (each lane takes frames
+        // l, l + L, ... in order, then a fixed butterfly over the L lanes), so that they
+        // cost a pass or two rather than one group sum each
+        int L = 64;
+        while (L > 8 && L * nq > NT) L >>= 1;
+        for (int q0 = 0; q0 < nq; q0 += NT / L) {
+            const int q = q0 + threadIdx.x / L, l = threadIdx.x % L;
+            double acc = 0.0;
+            if (q < nq) {
+                const int k = q >> 1, axis = q & 1;
+                for (int i = l; i < E; i += L)
+                    acc += (double)pa[(long long)i * M + k] * a.fsum[(long long)i * stride + 1 + (1 + axis) * M + k];
+            }
+            for (int off = L >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (q < nq && l == 0) {
                 if (a.pts) acc += a.pts[3 * (q >> 1) + 1 + (q & 1)];
                 a.grad[NN + E + (long long)E * M + q] = (float)acc;
             }
