@@ -712,8 +712,11 @@ static int build_fft_lists(starred_plan *p)
             if (is_direct(c) || (lg && cl.fused)) continue;
             const int nbins = cl.Q * (cl.Q / 2 + 1);
             const int nbb = (nbins + kFftThreads - 1) / kFftThreads;
-            // enough frame chunks to give every compute unit several groups
+            // enough frame chunks to give every compute unit several groups; with more than
+            // 16 point sources a chunk holds at least a whole frame group of the product
+            // (the sources' table values are loaded once per group)
             int fch = std::max(1, std::min(8, (int)((long long)nbb * cl.ncf / 1024)));
+            if (p->M > 16) fch = std::max(fch, std::min(cl.ncf, kFwdFrames));
             for (int f0 = 0; f0 < cl.ncf; f0 += fch)
                 for (int bb = 0; bb < nbb; ++bb)
                     sp.push_back(SpecItem{c, f0, std::min(fch, cl.ncf - f0), bb * kFftThreads});
