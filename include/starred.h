@@ -335,8 +335,11 @@ int starred_frame_transforms_info(const starred_plan *plan, int32_t *algo_out, d
 
 /* Launch shapes of the deconvolution FFT path (what the autotuner chooses; 0 keeps
  * the current value): adj_frames, frames per chunk of the frequency-domain adjoint
- * (2 or 4; 8 with at most one point source; one summed spectrum per chunk goes
- * through memory); adj_blocks, work groups its launch aims at; line_groups, work groups a line pass aims at; split_forward (-1 keeps it): 1
+ * (2 or 4; 8 with at most one point source; 1 with more than eight; one summed
+ * spectrum per chunk goes through memory; a chunk of one frame takes 16 sources per
+ * pass over its spectra, two frames 8 when there are more than four, otherwise 4);
+ * adj_blocks, work groups its launch aims at; line_groups, work groups a line pass
+ * aims at; split_forward (-1 keeps it): 1
  * runs the one-launch forward of the smaller classes on a second stream of the plan,
  * beside the line passes of the larger ones (forked from and joined back into the
  * plan's stream, also inside captured graphs), 0 runs everything in order. Results

@@ -18,6 +18,7 @@ constexpr int kAdjFrames = 2;          // spectral adjoint: frames of a work gro
 constexpr int kAdjMaxFrames = 8;       // spectral adjoint: most frames of a chunk
 constexpr int kAdjSB = 4;              // spectral adjoint: sources per pass over the rows (M > 1)
 constexpr int kAdjSBWide = 8;          // the same with 2-frame chunks and more than kAdjSB sources
+constexpr int kAdjSBOne = 16;          // the same with 1-frame chunks (more than kAdjSBWide sources)
 constexpr int kAdjBlocks = 512;        // spectral adjoint: work groups aimed at per launch
 constexpr int kAdjMinRows = 4;         // spectral adjoint: fewest rows per thread
 constexpr int kAdjMaxRows = 64;        // spectral adjoint: most rows per work group
@@ -51,6 +52,7 @@ struct ClassFft {
     int ncf;            // number of frames of the class
     int ngch;           // frame chunks of the frequency-domain adjoint
     int gfch;           // frames per chunk
+    int ngch_cap;       // chunks the class's gp region holds (its smallest allowed chunks)
     long long gp_off;   // [ngch][P][P/2+1] summed adjoint spectra of each chunk (total in chunk 0)
     long long hc_off;   // [F][F] the class's contribution to dL/dh (its window)
     int fused;          // frames of this class take the one-launch forward (spectra fit in LDS)

@@ -1875,6 +1875,7 @@ hipError_t fft_spec_adj(hipStream_t st, const FftPlanDev &d, int M)
         }
     } else {
         switch (d.adj_fc) {
+        case 1: SPEC_ADJ(1, kAdjSBOne); break;
         case 2:
             if (M > kAdjSB)
                 SPEC_ADJ(2, kAdjSBWide);

@@ -635,13 +635,16 @@ static int build_fft(starred_plan *p)
         t3o += (long long)c.P * HP;
     }
     // frequency-domain adjoint: summed spectra per chunk of frames, room for the
-    // smallest chunks (the chunk size is chosen with the work lists)
+    // smallest chunks allowed (the chunk size is chosen with the work lists): one frame
+    // with more than kAdjSBWide point sources, else two
+    const int min_fc = p->M > kAdjSBWide ? 1 : 2;
     long long gp = 0, hc = 0;
     for (ClassFft &cl : p->cls) {
         cl.gfch = kAdjFrames;
         cl.ngch = (cl.ncf + kAdjFrames - 1) / kAdjFrames;
+        cl.ngch_cap = (cl.ncf + min_fc - 1) / min_fc;
         cl.gp_off = gp;
-        gp += (long long)cl.ngch * cl.P * (cl.P / 2 + 1);
+        gp += (long long)cl.ngch_cap * cl.P * (cl.P / 2 + 1);
         cl.hc_off = hc;
         hc += (long long)cl.F * cl.F;
     }
@@ -767,7 +770,7 @@ static int build_fft_lists(starred_plan *p)
     }
     // frequency-domain adjoint: items over chunks of p->adj_fc frames x ranges of
     // rows of the P half spectrum, about p->adj_blocks of them per launch (chunks of
-    // up to 8 frames with one source per pass, up to 4 with four)
+    // up to 8 frames with one source per pass, up to 4 with four, 2 with eight, 1 with 16)
     {
         const int fc = p->adj_fc;
         d.adj_fc = fc;
@@ -776,6 +779,8 @@ static int build_fft_lists(starred_plan *p)
         for (ClassFft &cl : p->cls) {
             cl.gfch = fc;
             cl.ngch = (cl.ncf + fc - 1) / fc;
+            if (cl.ngch > cl.ngch_cap)  // the chunk spectra would overrun the class's region
+                return fail(STARRED_EINVAL, "adjoint chunk size below the smallest the plan was built for");
         }
         for (int c = 0; c < (int)p->cls.size(); ++c)
             if (!is_direct(c)) nchunks += p->cls[c].ngch;
@@ -1142,7 +1147,10 @@ int starred_set_class_algo(starred_plan *p, int32_t c, int32_t algo, int32_t fus
 
 // chunk sizes of the frequency-domain adjoint (8 only with at most one point source:
 // four sources per pass need the registers)
-static bool adj_shape_ok(int fc, int M) { return fc == 2 || fc == 4 || (fc == 8 && M <= 1); }
+static bool adj_shape_ok(int fc, int M)
+{
+    return fc == 2 || fc == 4 || (fc == 8 && M <= 1) || (fc == 1 && M > kAdjSBWide);
+}
 
 int starred_set_fft_shapes(starred_plan *p, int32_t adj_frames, int32_t adj_blocks, int32_t line_groups,
                            int32_t split_forward, int32_t prior_late)
@@ -1150,7 +1158,8 @@ int starred_set_fft_shapes(starred_plan *p, int32_t adj_frames, int32_t adj_bloc
     if (!p) return fail(STARRED_EINVAL, "plan is NULL");
     if (p->mode != STARRED_DECONV) return fail(STARRED_EUNSUPPORTED, "launch shapes of the deconvolution FFT path");
     if (adj_frames && !adj_shape_ok(adj_frames, p->M))
-        return fail(STARRED_EINVAL, "adj_frames must be 2 or 4 (or 8 with at most one point source)");
+        return fail(STARRED_EINVAL,
+                    "adj_frames must be 2 or 4 (or 8 with at most one point source, 1 with more than eight)");
     if (adj_blocks < 0 || adj_blocks > (1 << 20) || line_groups < 0 || line_groups > (1 << 20))
         return fail(STARRED_EINVAL, "work-group targets must lie in [1, 2^20] (0 keeps the current one)");
     if (split_forward < -1 || split_forward > 1) return fail(STARRED_EINVAL, "split_forward must be -1, 0 or 1");
@@ -1723,7 +1732,7 @@ static int autotune(starred_plan *p)
         const std::vector<int> abs_ = {256, 512, 1024, 2048};
         const int keep_fc = p->adj_fc, keep_ab = p->adj_blocks;
         int best_fc = keep_fc, best_ab = keep_ab;
-        for (int fc : {2, 4, 8})
+        for (int fc : {1, 2, 4, 8})
             for (int ab : abs_) {
                 if (rc || !adj_shape_ok(fc, p->M) || (fc == keep_fc && ab == keep_ab)) continue;
                 p->adj_fc = fc;

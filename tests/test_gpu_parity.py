@@ -1253,19 +1253,23 @@ def test_mixed_class_algorithms_graph_steps_match_eager():
     assert abs(lf[2].item() - lm[2].item()) <= 1e-6 * abs(lf[2].item())
 
 
-@pytest.mark.parametrize("case,fcs", [("cfg4_sub", (2, 4, 8)), ("cfg2_E5", (2, 4)), ("eleven_sources", (2, 4))])
+@pytest.mark.parametrize("case,fcs", [("cfg4_sub", (2, 4, 8)), ("cfg2_E5", (2, 4)), ("eleven_sources", (1, 2, 4)),
+                                      ("seventeen_sources", (1, 2))])
 def test_fft_adjoint_chunk_sizes(case, fcs):
     """The frequency-domain adjoint with 2, 4 and 8 frames per chunk (8 only with one
     point source), including a last chunk that is not full, against the oracle and
-    against each other. Eleven sources: 2-frame chunks take eight sources per pass (a
-    full pass and a pass of three), 4-frame chunks four (two full passes and one of three)."""
+    against each other. Eleven sources: 1-frame chunks take sixteen sources per pass (one
+    pass, not full), 2-frame chunks eight (a full pass and a pass of three), 4-frame chunks
+    four (two full passes and one of three); seventeen: a full 16-source pass and one of one."""
     st = _st()
     if case == "cfg4_sub":
         prob = synth.make_deconv(4, E=13)
     elif case == "cfg2_E5":
         prob = synth.make_deconv(2, E=5)
-    else:
+    elif case == "eleven_sources":
         prob = synth.make_small_deconv(331, 5, [24, 32], [15, 21], 2, 80, 11, 4)
+    else:
+        prob = synth.make_small_deconv(332, 3, [20, 28], [13, 17], 3, 96, 17, 4)
     d, w, rng = _data(prob, seed=71)
     plan = _plan(prob, d, w, algo=st.CONV_FFT)
     p = synth.eval_point(prob, "near", rng)
@@ -1277,7 +1281,7 @@ def test_fft_adjoint_chunk_sizes(case, fcs):
         grads.append(g)
     for g in grads[1:]:
         assert parity.rel_err(g, grads[0]) <= 1e-5
-    for bad in (3, 16) + ((8,) if prob.M > 1 else ()):
+    for bad in (3, 16) + ((8,) if prob.M > 1 else ()) + ((1,) if prob.M <= 8 else ()):
         with pytest.raises(RuntimeError):
             plan.set_fft_shapes(adj_frames=bad)
 
