@@ -866,13 +866,19 @@ __device__ __forceinline__ float sgnf(float v) { return (float)((v > 0.f) - (v <
 // Virtual row v maps to image row mirror(v); 2d < N keeps one reflection enough.
 constexpr int kStarTile = 16;
 static_assert(kStarTile * kStarTile == kStarThreads, "one output pixel per thread");
+// The lines a level's second 1-D pass reads for a tile: the kStarTile + 4d contiguous
+// ones while the five taps' sets overlap (d <= kStarTile), otherwise only the five sets
+// of kStarTile lines (line kStarTile t' + l, t' = t + 2, holds the tile's line l moved
+// by t d), so the staged work stops growing with the hole size.
+__host__ __device__ constexpr int star_lines(int d) { return d > kStarTile ? 5 * kStarTile : kStarTile + 4 * d; }
+static size_t star_lds(int d) { return sizeof(float) * (size_t)star_lines(d) * kStarTile; }
 
 __global__ __launch_bounds__(kStarThreads) void k_star_level(
     const float *__restrict__ cj, float *__restrict__ cnext, float *__restrict__ coeffs, float *__restrict__ z,
     const float *__restrict__ W, int w_stride, float lam, int N, int d, int j, int last,
     double *__restrict__ part_l1, long long img_stride, long long co_stride, float lam1, long long l1_stride)
 {
-    extern __shared__ float tmp[];  // (kStarTile + 4d) rows x kStarTile
+    extern __shared__ float tmp[];  // star_lines(d) rows x kStarTile
     __shared__ double red[kStarThreads / 64];
     // a batch of images along blockIdx.z: image b's planes, subgradient and L1
     // partials sit b strides further; image 1 takes the weight lam1
@@ -883,13 +889,18 @@ __global__ __launch_bounds__(kStarThreads) void k_star_level(
     if (part_l1) part_l1 += blockIdx.z * l1_stride;
     if (blockIdx.z == 1) lam = lam1;
     const int x0 = blockIdx.x * kStarTile, y0 = blockIdx.y * kStarTile;
-    const int R = kStarTile + 4 * d, vy0 = y0 - 2 * d;
+    const bool gath = d > kStarTile;  // the five taps' row sets apart: stage only those
+    const int R = star_lines(d), vy0 = y0 - 2 * d;
     const int vmax = min(y0 + kStarTile, N) - 1 + 2 * d;  // last virtual row a tap reaches
     for (int e = threadIdx.x; e < R * kStarTile; e += kStarThreads) {
         const int r = e / kStarTile, x = x0 + (e % kStarTile);
+        // virtual row of staged row r, and whether an output row of the tile reads it
+        const int rl = r % kStarTile;
+        const int vy = gath ? y0 + rl + (r / kStarTile - 2) * d : vy0 + r;
+        const bool need = gath ? y0 + rl < N : vy <= vmax;
         float acc = 0.f;
-        if (x < N && vy0 + r <= vmax) {
-            const float *row = cj + (long long)mirror_idx(vy0 + r, N) * N;
+        if (x < N && need) {
+            const float *row = cj + (long long)mirror_idx(vy, N) * N;
             #pragma unroll
             for (int t = -2; t <= 2; ++t) acc = fmaf(kB3[t + 2], row[mirror_idx(x + t * d, N)], acc);
         }
@@ -904,7 +915,10 @@ __global__ __launch_bounds__(kStarThreads) void k_star_level(
         const long long pix = (long long)y * N + x;
         float acc = 0.f;
         #pragma unroll
-        for (int t = -2; t <= 2; ++t) acc = fmaf(kB3[t + 2], tmp[(yl + 2 * d + t * d) * kStarTile + xl], acc);
+        for (int t = -2; t <= 2; ++t) {
+            const int r = gath ? (t + 2) * kStarTile + yl : yl + 2 * d + t * d;
+            acc = fmaf(kB3[t + 2], tmp[r * kStarTile + xl], acc);
+        }
         cnext[pix] = acc;
         const float al = cj[pix] - acc;
         const float wj = w_stride ? W[j * NN + pix] : W[j];
@@ -966,7 +980,7 @@ hipError_t launch_starlet_fwd(hipStream_t st, int N, int J, const float *img, fl
     for (int j = 0; j < J - 1; ++j) {
         float *nxt = (j % 2 == 0) ? c_a : c_b;
         const int d = 1 << j;
-        const size_t lds = sizeof(float) * (size_t)(kStarTile + 4 * d) * kStarTile;
+        const size_t lds = star_lds(d);
         hipLaunchKernelGGL(k_star_level, dim3(nt, nt), dim3(kStarThreads), lds, st, cur, nxt, coeffs, z, W,
                            w_stride, lam, N, d, j, (int)(j == J - 2),
                            part_l1 ? part_l1 + (long long)j * nt * nt : nullptr, 0LL, 0LL, lam, 0LL);
@@ -1015,23 +1029,54 @@ __global__ __launch_bounds__(kStarThreads) void k_star_levelT(const float *__res
                                                               long long v_stride, long long out_stride,
                                                               long long z_stride)
 {
-    extern __shared__ float tmp[];  // kStarTile rows x (kStarTile + 4d) columns
+    extern __shared__ float tmp[];  // kStarTile rows x (kStarTile + 4d) columns, or [5][tile] (d > kStarTile)
     // a batch of images along blockIdx.z
     v += blockIdx.z * v_stride;
     vout += blockIdx.z * out_stride;
     zj += blockIdx.z * z_stride;
     const int x0 = blockIdx.x * kStarTile, y0 = blockIdx.y * kStarTile;
+    const int yl = threadIdx.x / kStarTile, xl = threadIdx.x % kStarTile;
+    const int y = y0 + yl, x = x0 + xl;
+    if (d > kStarTile) {
+        // the taps' column sets apart: stage, per tap t and output (y, x), the column
+        // transpose summed over the columns the row transpose gathers for that tap
+        // (x - t d and its mirror images; one of them away from the edges)
+        constexpr int TT = kStarTile * kStarTile;
+        for (int e = threadIdx.x; e < 5 * TT; e += kStarThreads) {
+            const int t = e / TT - 2, rem = e % TT, y2 = y0 + rem / kStarTile, x2 = x0 + rem % kStarTile;
+            float acc = 0.f;
+            if (y2 < N && x2 < N) {
+                int xc = x2 - t * d;
+                if (xc >= 0 && xc < N) acc += mirrorT_gather(v + xc, N, y2, N, d, zj + xc, true);
+                if (x2 > 0) {
+                    xc = -x2 - t * d;
+                    if (xc >= 0 && xc < N) acc += mirrorT_gather(v + xc, N, y2, N, d, zj + xc, true);
+                }
+                if (x2 < N - 1) {
+                    xc = 2 * (N - 1) - x2 - t * d;
+                    if (xc >= 0 && xc < N) acc += mirrorT_gather(v + xc, N, y2, N, d, zj + xc, true);
+                }
+            }
+            tmp[e] = acc;
+        }
+        __syncthreads();
+        if (y >= N || x >= N) return;
+        float acc = 0.f;
+        #pragma unroll
+        for (int t = -2; t <= 2; ++t) acc = fmaf(kB3[t + 2], tmp[(t + 2) * TT + yl * kStarTile + xl], acc);
+        const long long pix = (long long)y * N + x;
+        vout[pix] = zj[pix] + acc;
+        return;
+    }
     const int C = kStarTile + 4 * d, cx0 = x0 - 2 * d;
     for (int e = threadIdx.x; e < kStarTile * C; e += kStarThreads) {
-        const int yl = e / C, c = e - yl * C;
-        const int y = y0 + yl, xc = cx0 + c;
+        const int yl2 = e / C, c = e - yl2 * C;
+        const int y2 = y0 + yl2, xc = cx0 + c;
         float acc = 0.f;
-        if (y < N && xc >= 0 && xc < N) acc = mirrorT_gather(v + xc, N, y, N, d, zj + xc, true);
+        if (y2 < N && xc >= 0 && xc < N) acc = mirrorT_gather(v + xc, N, y2, N, d, zj + xc, true);
         tmp[e] = acc;
     }
     __syncthreads();
-    const int yl = threadIdx.x / kStarTile, xl = threadIdx.x % kStarTile;
-    const int y = y0 + yl, x = x0 + xl;
     if (y >= N || x >= N) return;
     // the row transpose gathers tmp at every column xc with mirror(xc + t d) == x;
     // all of them lie in [x0 - 2d, x0 + kStarTile + 2d)
@@ -1087,7 +1132,7 @@ hipError_t launch_starlet_prior(hipStream_t st, int N, int J, int B, const float
     for (int j = 0; j < J - 1; ++j) {
         float *nxt = (j % 2 == 0) ? c_a : c_b;
         const int d = 1 << j;
-        const size_t lds = sizeof(float) * (size_t)(kStarTile + 4 * d) * kStarTile;
+        const size_t lds = star_lds(d);
         hipLaunchKernelGGL(k_star_level, dim3(nt, nt, B), dim3(kStarThreads), lds, st, cur, nxt, nullptr, z, W,
                            w_stride, lam0, N, d, j, (int)(j == J - 2),
                            part_l1 ? part_l1 + (long long)j * nt * nt : nullptr, NN, (long long)J * NN, lam1, l1s);
@@ -1108,7 +1153,7 @@ hipError_t launch_starlet_fwd_batch(hipStream_t st, int N, int J, int B, const f
     for (int j = 0; j < J - 1; ++j) {
         float *nxt = (j % 2 == 0) ? c_a : c_b;
         const int d = 1 << j;
-        const size_t lds = sizeof(float) * (size_t)(kStarTile + 4 * d) * kStarTile;
+        const size_t lds = star_lds(d);
         hipLaunchKernelGGL(k_star_level, dim3(nt, nt, B), dim3(kStarThreads), lds, st, cur, nxt, coeffs,
                            nullptr, wzero, 0, 0.f, N, d, j, (int)(j == J - 2), nullptr, NN, (long long)J * NN,
                            0.f, 0LL);
@@ -1131,7 +1176,7 @@ hipError_t launch_starlet_adj(hipStream_t st, int N, int J, const float *z, floa
     for (int j = J - 2; j >= 0; --j) {
         float *vn = (j == 0) ? out : ((j % 2 == 0) ? v_a : v_b);
         const int d = 1 << j;
-        const size_t lds = sizeof(float) * (size_t)kStarTile * (kStarTile + 4 * d);
+        const size_t lds = star_lds(d);
         hipLaunchKernelGGL(k_star_levelT, dim3(nt, nt), dim3(kStarThreads), lds, st, v, z + j * NN, vn, N, d, 0LL,
                            0LL, 0LL);
         v = vn;
@@ -1156,7 +1201,7 @@ hipError_t launch_starlet_adj_batch(hipStream_t st, int N, int J, int B, const f
     for (int j = J - 2; j >= 0; --j) {
         float *vn = (j == 0) ? out : ((j % 2 == 0) ? v_a : v_b);
         const int d = 1 << j;
-        const size_t lds = sizeof(float) * (size_t)kStarTile * (kStarTile + 4 * d);
+        const size_t lds = star_lds(d);
         // the first level reads plane J-1 of each image's z: stride J N^2 for it, N^2 after
         hipLaunchKernelGGL(k_star_levelT, dim3(nt, nt, B), dim3(kStarThreads), lds, st, v, z + j * NN, vn, N, d,
                            (j == J - 2) ? (long long)J * NN : NN, NN, (long long)J * NN);

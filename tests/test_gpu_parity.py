@@ -108,9 +108,11 @@ def test_convolve_subsample_and_adjoint(case, algo):
 
 
 # (128, 7) reaches level 6, whose composite taps are read from the padded table rather
-# than compiled in; (256, 8) and (300, 5) run the cascade (eight scales, and grids above
-# 256, are beyond the composite filters)
-@pytest.mark.parametrize("N,J", [(48, 4), (64, 3), (128, 6), (33, 5), (128, 7), (256, 8), (300, 5)])
+# than compiled in; (256, 8), (300, 5) and (300, 7) run the cascade (eight scales, and grids
+# above 256, are beyond the composite filters); in (256, 8) and (300, 7) the holes of the
+# top levels exceed the 16-pixel tiles, so those levels stage only the taps' lines (with
+# ragged tiles and mirror images at both edges in (300, 7))
+@pytest.mark.parametrize("N,J", [(48, 4), (64, 3), (128, 6), (33, 5), (128, 7), (256, 8), (300, 5), (300, 7)])
 def test_starlet_forward_and_adjoint(N, J):
     prob = synth.make_small_deconv(7, 1, [N], [5], 1, N, 1, J)
     d, w, rng = _data(prob)
