@@ -230,17 +230,33 @@ __global__ __launch_bounds__(kPsfThreads) void k_psf_fwd(
         if (wc < CM && wr + 2 * i < RM) W[(wr + 2 * i) * CM + wc] = win[i];
     __syncthreads();
     {
-        const int q = threadIdx.x % QT;
-        for (int r = threadIdx.x / QT; r < RM; r += kPsfThreads / QT) {
-            const double *w = W + r * CM + SS * q;
-            double acc = 0.0, accx = 0.0;
+        // four consecutive outputs of a window row per thread: together they read
+        // 3s + T window values, each loaded once for every output its taps reach
+        // (rather than 4T loads); each output still adds its taps in order
+        constexpr int QB = 4, NW = SS * (QB - 1) + T, NG = QT / QB;
+        for (int task = threadIdx.x; task < RM * NG; task += kPsfThreads) {
+            const int r = task / NG, q0 = (task % NG) * QB;
+            const double *w = W + r * CM + SS * q0;
+            double acc[QB], accx[QB];
 #pragma unroll
-            for (int u = 0; u < T; ++u) {
-                acc = fma(G[0][u], w[u], acc);
-                accx = fma(dG[0][u], w[u], accx);
+            for (int i = 0; i < QB; ++i) acc[i] = accx[i] = 0.0;
+#pragma unroll
+            for (int j = 0; j < NW; ++j) {
+                const double v = w[j];
+#pragma unroll
+                for (int i = 0; i < QB; ++i) {
+                    const int u = j - SS * i;
+                    if (u >= 0 && u < T) {
+                        acc[i] = fma(G[0][u], v, acc[i]);
+                        accx[i] = fma(dG[0][u], v, accx[i]);
+                    }
+                }
             }
-            T1[r * QT + q] = acc;
-            T1x[r * QT + q] = accx;
+#pragma unroll
+            for (int i = 0; i < QB; ++i) {
+                T1[r * QT + q0 + i] = acc[i];
+                T1x[r * QT + q0 + i] = accx[i];
+            }
         }
     }
     __syncthreads();
