@@ -85,7 +85,7 @@ hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, c
 // work groups of the direct kernels that fit on the device at once (persistent grid)
 int direct_fwd_groups(int s, int Tmax);
 int direct_adj_groups(int s, int Ar_max, int Bpad_max);
-int finalize_h_chunks(int E);
+int finalize_h_chunks(int E, bool xf = false);
 // Update of one parameter (bias-corrected moments, per-block learning rate):
 // Adam (v tracks g^2) or, with belief, AdaBelief (v tracks (g - m)^2 + eps_root
 // with the updated m).

@@ -520,12 +520,14 @@ hipError_t launch_adj_direct(hipStream_t st, int s, const FrameDev *fr, const It
 // --------------------------------------------------------------------------
 
 constexpr int kSumThreads = 256;
+constexpr int kSumThreadsXf = 1024;
 
 // Frame sums under a per-frame transform: block 0 dL/dGamma_i; block 1+k the sums of
 // g r_k(u) and g r_k(u) (u - c_k)/sigma^2 (scene coordinates u, so dL/dc_k needs no
 // rotation); block 1+M (when gxf is given) dL/d(dx_i, dy_i, theta_i) from
 // q(X) = grad h(u) - sum_k a_ik r_k(u) (u - c_k)/sigma^2:  <g, q> and
 // <g, q . R'(theta)(X - C)>.
+template <int NT>
 __device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, int M, float sigma,
                               const float *__restrict__ params, const float *__restrict__ gi,
                               double *__restrict__ fsum, const float *__restrict__ xf, float *__restrict__ gxf,
@@ -542,8 +544,8 @@ __device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, i
     const FrameMap fm(xf, i, N);
     if (by == 0) {
         double acc = 0.0;
-        for (int p = threadIdx.x; p < tot; p += kSumThreads) acc += (double)gi[p];
-        const double sm = block_sum_d<kSumThreads>(acc, red);
+        for (int p = threadIdx.x; p < tot; p += NT) acc += (double)gi[p];
+        const double sm = block_sum_d<NT>(acc, red);
         if (threadIdx.x == 0) fsum[(long long)i * stride] = sm;
         return;
     }
@@ -560,7 +562,7 @@ __device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, i
         const int wx = x_hi - x_lo + 1, wy = y_hi - y_lo + 1;
         double sa = 0.0, sx = 0.0, sy = 0.0;
         if (wx > 0 && wy > 0) {
-            for (int e = threadIdx.x; e < wx * wy; e += kSumThreads) {
+            for (int e = threadIdx.x; e < wx * wy; e += NT) {
                 const int Y = y_lo + e / wx, X = x_lo + e % wx;
                 double ux, uy;
                 fm.map((double)X, (double)Y, ux, uy);
@@ -573,9 +575,9 @@ __device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, i
                 sy += (double)(gr * dy * invs2);
             }
         }
-        sa = block_sum_d<kSumThreads>(sa, red);
-        sx = block_sum_d<kSumThreads>(sx, red);
-        sy = block_sum_d<kSumThreads>(sy, red);
+        sa = block_sum_d<NT>(sa, red);
+        sx = block_sum_d<NT>(sx, red);
+        sy = block_sum_d<NT>(sy, red);
         if (threadIdx.x == 0) {
             fsum[(long long)i * stride + 1 + k] = sa;
             fsum[(long long)i * stride + 1 + M + k] = sx;
@@ -585,7 +587,7 @@ __device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, i
     }
     // by == 1 + M: the transform's gradient
     double gdx = 0.0, gdy = 0.0, gth = 0.0;
-    for (int p = threadIdx.x; p < tot; p += kSumThreads) {
+    for (int p = threadIdx.x; p < tot; p += NT) {
         const double X = (double)(fr.o + p % fr.F), Y = (double)(fr.o + p / fr.F);
         double ux, uy;
         float qx, qy;
@@ -606,9 +608,9 @@ __device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, i
         gdy += (double)(gv * qy);
         gth += (double)(gv * (qx * (-sn * vx - cs * vy) + qy * (cs * vx - sn * vy)));
     }
-    gdx = block_sum_d<kSumThreads>(gdx, red);
-    gdy = block_sum_d<kSumThreads>(gdy, red);
-    gth = block_sum_d<kSumThreads>(gth, red);
+    gdx = block_sum_d<NT>(gdx, red);
+    gdy = block_sum_d<NT>(gdy, red);
+    gth = block_sum_d<NT>(gth, red);
     if (threadIdx.x == 0) {
         gxf[3 * i] = (float)gdx;
         gxf[3 * i + 1] = (float)gdy;
@@ -616,26 +618,29 @@ __device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, i
     }
 }
 
-__global__ __launch_bounds__(kSumThreads) void k_frame_sums(
+// NT threads per block: kSumThreads, or kSumThreadsXf for frames under transforms
+// (whose blocks map and interpolate every pixel: more waves to hide the loads)
+template <int NT>
+__global__ __launch_bounds__(NT) void k_frame_sums(
     const FrameDev *__restrict__ frames, int E, int frame0, int N, int M, float sigma,
     const float *__restrict__ params, const float *__restrict__ g, double *__restrict__ fsum, int yofs,
     const int *__restrict__ flist, const float *__restrict__ xf, float *__restrict__ gxf)
 {
-    __shared__ double red[kSumThreads / 64];
+    __shared__ double red[NT / 64];
     const int i = flist ? flist[blockIdx.x] : frame0 + blockIdx.x;
     const int by = blockIdx.y + yofs;  // yofs = 1: the frame sums of g come from elsewhere
     const FrameDev fr = frames[i];
     const float *gi = g + fr.fine_off;
     const int stride = 1 + 3 * M;
     if (xf) {
-        frame_sums_xf(fr, i, by, E, N, M, sigma, params, gi, fsum, xf, gxf, red);
+        frame_sums_xf<NT>(fr, i, by, E, N, M, sigma, params, gi, fsum, xf, gxf, red);
         return;
     }
     if (by == 0) {
         double acc = 0.0;
         const int tot = fr.F * fr.F;
-        for (int p = threadIdx.x; p < tot; p += kSumThreads) acc += (double)gi[p];
-        const double s = block_sum_d<kSumThreads>(acc, red);
+        for (int p = threadIdx.x; p < tot; p += NT) acc += (double)gi[p];
+        const double s = block_sum_d<NT>(acc, red);
         if (threadIdx.x == 0) fsum[(long long)i * stride] = s;
         return;
     }
@@ -650,7 +655,7 @@ __global__ __launch_bounds__(kSumThreads) void k_frame_sums(
     const int wx = x_hi - x_lo + 1, wy = y_hi - y_lo + 1;
     double sa = 0.0, sx = 0.0, sy = 0.0;
     if (wx > 0 && wy > 0) {
-        for (int e = threadIdx.x; e < wx * wy; e += kSumThreads) {
+        for (int e = threadIdx.x; e < wx * wy; e += NT) {
             const int Y = y_lo + e / wx, X = x_lo + e % wx;
             const float dx = (float)X - cx, dy = (float)Y - cy;
             const float r = norm * expf(-(dx * dx + dy * dy) * inv2s2);
@@ -661,9 +666,9 @@ __global__ __launch_bounds__(kSumThreads) void k_frame_sums(
             sy += (double)(gr * dy * invs2);
         }
     }
-    sa = block_sum_d<kSumThreads>(sa, red);
-    sx = block_sum_d<kSumThreads>(sx, red);
-    sy = block_sum_d<kSumThreads>(sy, red);
+    sa = block_sum_d<NT>(sa, red);
+    sx = block_sum_d<NT>(sx, red);
+    sy = block_sum_d<NT>(sy, red);
     if (threadIdx.x == 0) {
         fsum[(long long)i * stride + 1 + k] = sa;
         fsum[(long long)i * stride + 1 + M + k] = sx;
@@ -680,16 +685,20 @@ hipError_t launch_frame_sums(hipStream_t st, const FrameDev *fr, int E, int N, i
     const int yofs = with_gamma ? 0 : 1;
     const int ny = 1 + M - yofs + ((xf && gxf) ? 1 : 0);  // + the transform's gradient block
     if (ny <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_frame_sums, dim3(nf, ny), dim3(kSumThreads), 0, st, fr, E, 0, N, M, sigma,
-                       params, g, fsum, yofs, flist, xf, gxf);
+    if (xf)
+        hipLaunchKernelGGL(k_frame_sums<kSumThreadsXf>, dim3(nf, ny), dim3(kSumThreadsXf), 0, st, fr, E, 0, N, M,
+                           sigma, params, g, fsum, yofs, flist, xf, gxf);
+    else
+        hipLaunchKernelGGL(k_frame_sums<kSumThreads>, dim3(nf, ny), dim3(kSumThreads), 0, st, fr, E, 0, N, M,
+                           sigma, params, g, fsum, yofs, flist, xf, gxf);
     return hipGetLastError();
 }
 
 hipError_t launch_frame_sums_one(hipStream_t st, const FrameDev *fr, int E, int i, int N, int M, float sigma,
                                  const float *params, const float *g, double *fsum)
 {
-    hipLaunchKernelGGL(k_frame_sums, dim3(1, 1 + M), dim3(kSumThreads), 0, st, fr, E, i, N, M, sigma,
-                       params, g, fsum, 0, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_frame_sums<kSumThreads>, dim3(1, 1 + M), dim3(kSumThreads), 0, st, fr, E, i, N, M,
+                       sigma, params, g, fsum, 0, nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -697,7 +706,8 @@ hipError_t launch_frame_sums_one(hipStream_t st, const FrameDev *fr, int E, int 
 // dL/dh = Phi z + sum over frames covering the pixel of g_i (frame order)
 // --------------------------------------------------------------------------
 
-constexpr int kFinChunk = 16;  // frames summed by one thread of k_finalize_h_part
+constexpr int kFinChunk = 16;   // frames summed by one thread of k_finalize_h_part
+constexpr int kFinChunkXf = 4;  // the same for frames under transforms (25 candidates each)
 
 // Two-stage cross-frame sum (frame order within a chunk, then chunk order):
 // part[c][Y,X] = sum over frames of chunk c covering (Y,X) of g_i(Y - o_i, X - o_i)
@@ -741,7 +751,8 @@ __global__ void k_finalize_h_part(const FrameDev *__restrict__ frames, int E, in
     const int pix = blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= N * N) return;
     const int Y = pix / N, X = pix % N;
-    const int i0 = blockIdx.y * kFinChunk, i1 = min(E, i0 + kFinChunk);
+    const int chunk = xf ? kFinChunkXf : kFinChunk;
+    const int i0 = blockIdx.y * chunk, i1 = min(E, i0 + chunk);
     float acc = 0.f;
     if (xf) {
         for (int q = i0; q < i1; ++q) {
@@ -771,7 +782,12 @@ __global__ void k_finalize_h_sum(int nchunk, int N, const float *__restrict__ pa
     grad_h[pix] = acc;
 }
 
-int finalize_h_chunks(int E) { return (E + kFinChunk - 1) / kFinChunk; }
+// partial planes the chunked sum needs (frames under transforms take smaller chunks)
+int finalize_h_chunks(int E, bool xf)
+{
+    const int chunk = xf ? kFinChunkXf : kFinChunk;
+    return (E + chunk - 1) / chunk;
+}
 
 hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, const float *g,
                              const float *prior, float *grad_h, float *part, const int *flist, int nlist,
@@ -779,7 +795,7 @@ hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, c
 {
     const int nb = (N * N + 255) / 256;
     const int nf = flist ? nlist : E;
-    const int nc = finalize_h_chunks(nf);
+    const int nc = finalize_h_chunks(nf, xf != nullptr);
     hipLaunchKernelGGL(k_finalize_h_part, dim3(nb, nc), dim3(256), 0, st, fr, nf, N, g, part, flist, xf);
     hipLaunchKernelGGL(k_finalize_h_sum, dim3(nb), dim3(256), 0, st, nc, N, part, prior, grad_h);
     return hipGetLastError();

@@ -106,6 +106,7 @@ struct starred_plan {
     int dense_b = 0;
     double *d_dense_taps = nullptr, *d_dense_T = nullptr, *d_dense_C = nullptr, *d_dense_U = nullptr;
     float *d_hpart = nullptr;
+    int hpart_chunks = 0;  // partial planes d_hpart holds
     std::vector<void *> owned;
     // noise propagation: an s = 1 plan applying S_f^T to a batch of noise fields
     starred_plan *noise_aux = nullptr;
@@ -434,7 +435,8 @@ static int build_deconv(starred_plan *p)
     if ((rc = p->alloc(&p->d_pts, (size_t)3 * std::max(1, p->M)))) return rc;
     if ((rc = p->alloc(&p->d_tmp, NN))) return rc;
     if ((rc = p->alloc(&p->d_prior, 2 * NN))) return rc;
-    if ((rc = p->alloc(&p->d_hpart, (size_t)finalize_h_chunks(E) * NN))) return rc;
+    p->hpart_chunks = finalize_h_chunks(E);
+    if ((rc = p->alloc(&p->d_hpart, (size_t)p->hpart_chunks * NN))) return rc;
     if ((rc = p->alloc(&p->d_hdir, NN))) return rc;
     if ((rc = p->alloc(&p->d_grad, p->nparams))) return rc;
     if ((rc = p->alloc(&p->d_wzero, (size_t)p->J * NN))) return rc;
@@ -1252,6 +1254,12 @@ int starred_set_frame_transforms(starred_plan *p, const float *xf, float *grad_x
     p->xf = xf;
     p->gxf = xf ? grad_xf : nullptr;
     if (!xf) return STARRED_OK;
+    if (p->hpart_chunks < finalize_h_chunks(p->E, true)) {
+        // transformed frames are summed into dL/dh in smaller chunks: more partial planes
+        p->hpart_chunks = finalize_h_chunks(p->E, true);
+        int rc = p->alloc(&p->d_hpart, (size_t)p->hpart_chunks * p->N * p->N);
+        if (rc) return rc;
+    }
     int rc = choose_xf_algo(p, algo);
     p->drop_graphs();
     return rc;
