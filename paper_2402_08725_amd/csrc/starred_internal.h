@@ -75,10 +75,12 @@ hipError_t launch_adj_direct(hipStream_t st, int s, const FrameDev *fr, const It
                              int n_items, int Ar_max, int Bpad_max, const float *rho,
                              const float *ka, float *g, int groups = 0);
 // with xf: sums in scene coordinates, and (gxf non-null) dL/d(dx, dy, theta) per frame
+// gxf (with xf): the transforms' gradient, through gxfp (xf_grad_parts(E) FP64 partials)
 hipError_t launch_frame_sums(hipStream_t st, const FrameDev *fr, int E, int N, int M, float sigma,
                              const float *params, const float *g, double *fsum, bool with_gamma,
                              const int *flist = nullptr, int nlist = 0, const float *xf = nullptr,
-                             float *gxf = nullptr);
+                             float *gxf = nullptr, double *gxfp = nullptr);
+int xf_grad_parts(int E);
 hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, const float *g,
                              const float *prior, float *grad_h, float *part, const int *flist = nullptr,
                              int nlist = 0, const float *xf = nullptr);

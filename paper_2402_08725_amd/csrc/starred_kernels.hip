@@ -521,16 +521,17 @@ hipError_t launch_adj_direct(hipStream_t st, int s, const FrameDev *fr, const It
 
 constexpr int kSumThreads = 256;
 constexpr int kSumThreadsXf = 1024;
+constexpr int kXfSplit = 4;  // blocks per frame for the transform's gradient (partials added in order)
 
 // Frame sums under a per-frame transform: block 0 dL/dGamma_i; block 1+k the sums of
 // g r_k(u) and g r_k(u) (u - c_k)/sigma^2 (scene coordinates u, so dL/dc_k needs no
-// rotation); block 1+M (when gxf is given) dL/d(dx_i, dy_i, theta_i) from
+// rotation); blocks 1+M.. (kXfSplit of them, when gxf is given) dL/d(dx_i, dy_i, theta_i) from
 // q(X) = grad h(u) - sum_k a_ik r_k(u) (u - c_k)/sigma^2:  <g, q> and
 // <g, q . R'(theta)(X - C)>.
 template <int NT>
 __device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, int M, float sigma,
                               const float *__restrict__ params, const float *__restrict__ gi,
-                              double *__restrict__ fsum, const float *__restrict__ xf, float *__restrict__ gxf,
+                              double *__restrict__ fsum, const float *__restrict__ xf, double *__restrict__ gxfp,
                               double *red)
 {
     const int stride = 1 + 3 * M;
@@ -585,9 +586,11 @@ __device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, i
         }
         return;
     }
-    // by == 1 + M: the transform's gradient
+    // by == 1 + M + sp: the transform's gradient over the frame's pixels sp, sp + NS, ...
+    // (in strides of NT), as partials gxfp[i][sp][3] that k_xf_grad_sum adds in order
+    const int sp = by - 1 - M;
     double gdx = 0.0, gdy = 0.0, gth = 0.0;
-    for (int p = threadIdx.x; p < tot; p += NT) {
+    for (int p = sp * NT + threadIdx.x; p < tot; p += kXfSplit * NT) {
         const double X = (double)(fr.o + p % fr.F), Y = (double)(fr.o + p / fr.F);
         double ux, uy;
         float qx, qy;
@@ -612,10 +615,24 @@ __device__ void frame_sums_xf(const FrameDev &fr, int i, int by, int E, int N, i
     gdy = block_sum_d<NT>(gdy, red);
     gth = block_sum_d<NT>(gth, red);
     if (threadIdx.x == 0) {
-        gxf[3 * i] = (float)gdx;
-        gxf[3 * i + 1] = (float)gdy;
-        gxf[3 * i + 2] = (float)gth;
+        double *o = gxfp + ((long long)i * kXfSplit + sp) * 3;
+        o[0] = gdx;
+        o[1] = gdy;
+        o[2] = gth;
     }
+}
+
+// dL/d(dx_i, dy_i, theta_i) = the sum of frame i's kXfSplit partials, in order
+__global__ void k_xf_grad_sum(int nf, const int *__restrict__ flist, const double *__restrict__ gxfp,
+                              float *__restrict__ gxf)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nf * 3) return;
+    const int q = e / 3, c = e - 3 * q;
+    const int i = flist ? flist[q] : q;
+    double acc = 0.0;
+    for (int sp = 0; sp < kXfSplit; ++sp) acc += gxfp[((long long)i * kXfSplit + sp) * 3 + c];
+    gxf[3 * i + c] = (float)acc;
 }
 
 // NT threads per block: kSumThreads, or kSumThreadsXf for frames under transforms
@@ -624,7 +641,7 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_frame_sums(
     const FrameDev *__restrict__ frames, int E, int frame0, int N, int M, float sigma,
     const float *__restrict__ params, const float *__restrict__ g, double *__restrict__ fsum, int yofs,
-    const int *__restrict__ flist, const float *__restrict__ xf, float *__restrict__ gxf)
+    const int *__restrict__ flist, const float *__restrict__ xf, double *__restrict__ gxfp)
 {
     __shared__ double red[NT / 64];
     const int i = flist ? flist[blockIdx.x] : frame0 + blockIdx.x;
@@ -633,7 +650,7 @@ __global__ __launch_bounds__(NT) void k_frame_sums(
     const float *gi = g + fr.fine_off;
     const int stride = 1 + 3 * M;
     if (xf) {
-        frame_sums_xf<NT>(fr, i, by, E, N, M, sigma, params, gi, fsum, xf, gxf, red);
+        frame_sums_xf<NT>(fr, i, by, E, N, M, sigma, params, gi, fsum, xf, gxfp, red);
         return;
     }
     if (by == 0) {
@@ -678,21 +695,27 @@ __global__ __launch_bounds__(NT) void k_frame_sums(
 
 hipError_t launch_frame_sums(hipStream_t st, const FrameDev *fr, int E, int N, int M, float sigma,
                              const float *params, const float *g, double *fsum, bool with_gamma,
-                             const int *flist, int nlist, const float *xf, float *gxf)
+                             const int *flist, int nlist, const float *xf, float *gxf, double *gxfp)
 {
     const int nf = flist ? nlist : E;
     if (nf <= 0) return hipSuccess;
     const int yofs = with_gamma ? 0 : 1;
-    const int ny = 1 + M - yofs + ((xf && gxf) ? 1 : 0);  // + the transform's gradient block
+    const bool xgrad = xf && gxf && gxfp;
+    const int ny = 1 + M - yofs + (xgrad ? kXfSplit : 0);  // + the transform's gradient blocks
     if (ny <= 0) return hipSuccess;
-    if (xf)
+    if (xf) {
         hipLaunchKernelGGL(k_frame_sums<kSumThreadsXf>, dim3(nf, ny), dim3(kSumThreadsXf), 0, st, fr, E, 0, N, M,
-                           sigma, params, g, fsum, yofs, flist, xf, gxf);
-    else
+                           sigma, params, g, fsum, yofs, flist, xf, xgrad ? gxfp : nullptr);
+        if (xgrad)
+            hipLaunchKernelGGL(k_xf_grad_sum, dim3((nf * 3 + 255) / 256), dim3(256), 0, st, nf, flist, gxfp, gxf);
+    } else {
         hipLaunchKernelGGL(k_frame_sums<kSumThreads>, dim3(nf, ny), dim3(kSumThreads), 0, st, fr, E, 0, N, M,
-                           sigma, params, g, fsum, yofs, flist, xf, gxf);
+                           sigma, params, g, fsum, yofs, flist, xf, nullptr);
+    }
     return hipGetLastError();
 }
+
+int xf_grad_parts(int E) { return E * kXfSplit * 3; }
 
 hipError_t launch_frame_sums_one(hipStream_t st, const FrameDev *fr, int E, int i, int N, int M, float sigma,
                                  const float *params, const float *g, double *fsum)
@@ -721,13 +744,18 @@ __device__ float transpose_bilerp(const FrameDev &fr, int i, int N, const float 
     const FrameMap fm(xf, i, N);
     const double ex = (double)PX - fm.C - fm.dx, ey = (double)PY - fm.C - fm.dy;
     const double px = fm.cs * ex + fm.sn * ey + fm.C, py = -fm.sn * ex + fm.cs * ey + fm.C;
-    const int bx = (int)floor(px), byy = (int)floor(py);
+    // a frame pixel X reads (PX, PY) when its image u lies in [PX - 1, PX + 1) on both
+    // axes, so X - p is the inverse rotation of a vector with components in [-1, 1):
+    // within |cos| + |sin| (<= sqrt 2) of p on each axis, at most three candidates each
+    const double w = fabs(fm.cs) + fabs(fm.sn) + 1e-9;
+    const int xlo = (int)ceil(px - w), xhi = (int)floor(px + w);
+    const int ylo = (int)ceil(py - w), yhi = (int)floor(py + w);
     const float *gi = g + fr.fine_off;
     float acc = 0.f;
-    for (int Y = byy - 2; Y <= byy + 2; ++Y) {
+    for (int Y = ylo; Y <= yhi; ++Y) {
         const int y = Y - fr.o;
         if (y < 0 || y >= fr.F) continue;
-        for (int X = bx - 2; X <= bx + 2; ++X) {
+        for (int X = xlo; X <= xhi; ++X) {
             const int x = X - fr.o;
             if (x < 0 || x >= fr.F) continue;
             double ux, uy;

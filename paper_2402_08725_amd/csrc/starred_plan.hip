@@ -107,6 +107,7 @@ struct starred_plan {
     double *d_dense_taps = nullptr, *d_dense_T = nullptr, *d_dense_C = nullptr, *d_dense_U = nullptr;
     float *d_hpart = nullptr;
     int hpart_chunks = 0;  // partial planes d_hpart holds
+    double *d_gxfp = nullptr;  // partials of the transforms' gradient
     std::vector<void *> owned;
     // noise propagation: an s = 1 plan applying S_f^T to a batch of noise fields
     starred_plan *noise_aux = nullptr;
@@ -437,6 +438,7 @@ static int build_deconv(starred_plan *p)
     if ((rc = p->alloc(&p->d_prior, 2 * NN))) return rc;
     p->hpart_chunks = finalize_h_chunks(E);
     if ((rc = p->alloc(&p->d_hpart, (size_t)p->hpart_chunks * NN))) return rc;
+    if ((rc = p->alloc(&p->d_gxfp, (size_t)xf_grad_parts(E)))) return rc;
     if ((rc = p->alloc(&p->d_hdir, NN))) return rc;
     if ((rc = p->alloc(&p->d_grad, p->nparams))) return rc;
     if ((rc = p->alloc(&p->d_wzero, (size_t)p->J * NN))) return rc;
@@ -1568,7 +1570,7 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         if (dir) {
             e0 = p->prof_start();
             HIP_TRY(launch_frame_sums(p->st, p->d_fr, p->E, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum, true,
-                                      fft ? p->d_fdir : nullptr, (int)p->fdir.size(), p->xf, p->gxf));
+                                      fft ? p->d_fdir : nullptr, (int)p->fdir.size(), p->xf, p->gxf, p->d_gxfp));
             p->prof_stop(STARRED_STAGE_GRAD_SUMS, e0);
         }
     }
@@ -2490,7 +2492,7 @@ int starred_time_stage(starred_plan *p, const float *params, int32_t stage, int3
         case STARRED_STAGE_GRAD_SUMS:
             if (p->fdir.empty()) break;
             HIP_TRY(launch_frame_sums(p->st, p->d_fr, p->E, p->N, p->M, p->sigma, params, p->d_g, p->d_fsum, true,
-                                      p->d_fdir, (int)p->fdir.size(), p->xf, p->gxf));
+                                      p->d_fdir, (int)p->fdir.size(), p->xf, p->gxf, p->d_gxfp));
             return STARRED_OK;
         default:
             break;
