@@ -176,6 +176,50 @@ def committed_traffic(workload, kernel):
     return rec.get("bytes_per_launch", {}).get(kernel)
 
 
+def write_traffic(workload, fetch_dir, write_dir):
+    """Write profiles/fft_pass_traffic_<workload>.json from two rocprofv3 --pmc runs of
+    this script with --copy-calibrate (FETCH_SIZE, then WRITE_SIZE; csv output): HBM bytes
+    per launch of each kernel's most frequent launch shape, FETCH_SIZE and WRITE_SIZE (KiB)
+    scaled by what they read for the 256 MiB copy kernel, stamped with the sources' hash.
+    Prints the per-kernel rows."""
+    import csv
+    import collections
+    import statistics
+
+    def load(d, cname):
+        by = collections.defaultdict(list)
+        with open(os.path.join(d, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != cname:
+                    continue
+                n = r["Kernel_Name"].replace("void ", "").replace("starred::", "").split("(")[0]
+                by[(n, int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+        return by
+    F, W = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy_kib = 256 * 1024
+    fc = statistics.median(F[next(k for k in F if k[0] == "k_copy_probe")])
+    wc = statistics.median(W[next(k for k in W if k[0] == "k_copy_probe")])
+    fs, ws = copy_kib / fc, copy_kib / wc
+    best = {}
+    for (n, g), v in F.items():
+        if n not in best or len(v) > len(F[(n, best[n])]):
+            best[n] = g
+    per = {}
+    print(f"FETCH scale {fs:.4f} (copy {fc:.0f} KiB), WRITE scale {ws:.4f} (copy {wc:.0f} KiB)")
+    for n in sorted(best):
+        g = best[n]
+        f_ = statistics.median(F[(n, g)])
+        w_ = statistics.median(W.get((n, g), [float("nan")]))
+        b = (f_ * fs + w_ * ws) * 1024
+        per[n] = b
+        per[n.split("<")[0]] = b
+        print(f"| `{n}` | {g} | {len(F[(n, g)])} | {f_:.1f} | {w_:.1f} | {b / 1e6:.3f} |")
+    rec = {"workload": workload, "source_sha256": sources_hash(), "fetch_scale": fs, "write_scale": ws,
+           "bytes_per_launch": per}
+    with open(os.path.join(ROOT, "profiles", f"fft_pass_traffic_{workload}.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+
+
 def sources_hash():
     import hashlib
     h = hashlib.sha256()
@@ -266,7 +310,13 @@ def main():
     ap.add_argument("--stats-s", type=float, default=1.0, help="least seconds of each event series")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="also run one plain 256 MiB device copy (memory-counter calibration)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the committed traffic record of --config from two rocprofv3 --pmc "
+                         "runs (FETCH_SIZE, WRITE_SIZE) and exit (no GPU)")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.config, *args.write_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
