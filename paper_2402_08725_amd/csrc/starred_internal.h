@@ -116,6 +116,7 @@ struct AdamDev {
 };
 
 struct ClassFft;
+struct DenseStar;
 // With classes (FFT path), the launch also writes dL/dh = prior + the classes'
 // window contributions hcls. pts (3M, or null): the point-source prior's
 // additions to dL/da_ik (every i) and dL/dc_k.
@@ -126,7 +127,8 @@ hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const 
                                  const int *gcsr_item = nullptr, const double *gpart = nullptr,
                                  int *tick = nullptr, const ClassFft *classes = nullptr, int ncls = 0,
                                  const float *hcls = nullptr, const float *prior = nullptr,
-                                 const AdamDev &adam = AdamDev(), const double *pts = nullptr);
+                                 const AdamDev &adam = AdamDev(), const double *pts = nullptr,
+                                 const DenseStar *psum = nullptr);
 hipError_t launch_copy_probe(hipStream_t st, const float *src, float *dst, long long n);
 hipError_t launch_idle(hipStream_t st, int iters);
 

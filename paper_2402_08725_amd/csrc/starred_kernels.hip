@@ -834,9 +834,11 @@ hipError_t launch_finalize_h(hipStream_t st, const FrameDev *fr, int E, int N, c
 // window contribution of every shape class, in class order (and update h).
 constexpr int kFinThreads = 1024;
 
+// psum.U (or null): the prior's gradient summed per pixel from its per-level planes (its
+// passes rode in the step's launches) instead of read from prior
 __global__ __launch_bounds__(kFinThreads) void k_finalize_small(FinalArgs fa, const ClassFft *__restrict__ classes,
                                                                 int ncls, const float *__restrict__ hcls,
-                                                                const float *__restrict__ prior)
+                                                                const float *__restrict__ prior, DenseStar psum)
 {
     if (blockIdx.x == 0) {
         finalize_small_body<kFinThreads>(fa);
@@ -849,7 +851,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize_small(FinalArgs fa, co
     float bc1, bc2;
     adam_bias(fa.adam, bc1, bc2);
     const int Y = (int)(pix / N), X = (int)(pix % N);
-    float acc = prior ? prior[pix] : 0.f;
+    float acc = psum.U ? (float)dense_prior_at(psum, 0, pix) : (prior ? prior[pix] : 0.f);
     for (int ci = 0; ci < ncls; ++ci) {
         const ClassFft &c = classes[ci];
         if (c.direct) continue;  // its frames' windows are in prior (the direct path's sum)
@@ -864,7 +866,8 @@ hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const 
                                  const double *fsum, const float *params, int N,
                                  float *grad, double *loss, const int *gcsr_off, const int *gcsr_item,
                                  const double *gpart, int *tick, const ClassFft *classes, int ncls,
-                                 const float *hcls, const float *prior, const AdamDev &adam, const double *pts)
+                                 const float *hcls, const float *prior, const AdamDev &adam, const double *pts,
+                                 const DenseStar *psum)
 {
     const long long NN = (long long)N * N;
     const int hblocks = (classes && grad) ? (int)((NN + kFinThreads - 1) / kFinThreads) : 0;
@@ -888,7 +891,8 @@ hipError_t launch_finalize_small(hipStream_t st, int E, int M, int n_chi, const 
     fa.tick = tick;
     fa.adam = adam;
     fa.pts = pts;
-    hipLaunchKernelGGL(k_finalize_small, dim3(1 + hblocks), dim3(kFinThreads), 0, st, fa, classes, ncls, hcls, prior);
+    hipLaunchKernelGGL(k_finalize_small, dim3(1 + hblocks), dim3(kFinThreads), 0, st, fa, classes, ncls, hcls, prior,
+                       psum ? *psum : DenseStar());
     return hipGetLastError();
 }
 

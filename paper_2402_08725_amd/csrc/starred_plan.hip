@@ -1167,7 +1167,7 @@ int starred_set_fft_shapes(starred_plan *p, int32_t adj_frames, int32_t adj_bloc
     if (adj_blocks < 0 || adj_blocks > (1 << 20) || line_groups < 0 || line_groups > (1 << 20))
         return fail(STARRED_EINVAL, "work-group targets must lie in [1, 2^20] (0 keeps the current one)");
     if (split_forward < -1 || split_forward > 1) return fail(STARRED_EINVAL, "split_forward must be -1, 0 or 1");
-    if (prior_late < -1 || prior_late > 1) return fail(STARRED_EINVAL, "prior_late must be -1, 0 or 1");
+    if (prior_late < -1 || prior_late > 2) return fail(STARRED_EINVAL, "prior_late must be -1, 0, 1 or 2");
     if (prior_late >= 0) p->prior_late = prior_late;
     if (split_forward >= 0) p->fwd_split = split_forward;
     if (adj_frames) p->adj_fc = adj_frames;
@@ -1446,7 +1446,10 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     // terms per pixel); otherwise, and with the point-source term, the prior runs
     // on the forked stream.
     const bool pts = p->lam_pts != 0.0;
-    const bool ride = fused && p->dense && !pts && (!grad || fin_rows);
+    // several FFT classes, no direct frames: the passes ride too when asked (prior_late 2),
+    // the final launch summing the per-level terms per pixel
+    const bool ride_multi = p->prior_late == 2 && fft && !dir;
+    const bool ride = fused && p->dense && !pts && (!grad || fin_rows || ride_multi);
     DensePiece pa, pb, pc, pd;
     DenseStar dd;
     if (ride) {
@@ -1606,9 +1609,9 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     HIP_TRY(launch_finalize_small(p->st, p->E, p->M, n_chi, part_chi, n_l1, p->d_part_l1, p->lam, p->d_fsum,
                                   params, p->N, grad, loss_out, nullptr, nullptr, nullptr,
                                   (fft && adam) ? nullptr : tick, fft ? p->fd.classes : nullptr, p->fd.n_classes,
-                                  p->fd.hcls, (fft && dir) ? p->d_hdir : p->d_prior,
+                                  p->fd.hcls, ride ? nullptr : ((fft && dir) ? p->d_hdir : p->d_prior),
                                   (fft && adam) ? *adam : AdamDev(),
-                                  (p->lam_pts != 0.0 && grad) ? p->d_pts : nullptr));
+                                  (p->lam_pts != 0.0 && grad) ? p->d_pts : nullptr, (ride && grad) ? &dd : nullptr));
     p->prof_stop(STARRED_STAGE_FINALIZE, e0);
     return STARRED_OK;
 }
@@ -1762,7 +1765,11 @@ static int autotune(starred_plan *p)
             int &knob = which == 0 ? p->line_groups : (which == 1 ? p->fwd_split : p->prior_late);
             const int keep = knob;
             int best_v = keep;
-            const std::vector<int> cands = which == 0 ? std::vector<int>{512, 1024, 2048} : std::vector<int>{0, 1};
+            // prior placement: forked at the start (0) or after the forward (1), or its
+            // passes carried by the step's own launches (2, where they can ride)
+            const std::vector<int> cands = which == 0   ? std::vector<int>{512, 1024, 2048}
+                                           : which == 1 ? std::vector<int>{0, 1}
+                                                        : std::vector<int>{0, 1, 2};
             for (int v : cands) {
                 if (v == keep) continue;
                 knob = v;

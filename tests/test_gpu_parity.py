@@ -1348,6 +1348,51 @@ def test_split_forward_is_bitwise_the_same(graph):
     _compare_loss_grad(prob, d, w, p0, plan, "split forward, late prior")
 
 
+@pytest.mark.parametrize("split", [0, 1])
+def test_prior_riding_in_multi_class_launches(split):
+    """Several FFT classes with the prior's passes carried by the evaluation's own launches
+    (prior_late 2; the final launch sums the per-level terms per pixel): against the oracle,
+    against the forked prior (rounding of the per-pixel sum only), and graph steps equal to
+    eager ones; with the one-launch forward beside the line passes or in order."""
+    st = _st()
+    prob = synth.make_deconv(4, E=13)
+    d, w, rng = _data(prob, seed=74)
+    plan = _plan(prob, d, w, algo=st.CONV_FFT)
+    if split:
+        for c, ci in enumerate(plan.classes()):
+            if ci["n"] == 128:
+                plan.set_class_algo(c, st.CONV_FFT, fused=False)
+    assert len(plan.classes()) > 1
+    p0 = synth.eval_point(prob, "near", rng)
+    plan.set_fft_shapes(split_forward=split, prior_late=1)
+    lf, gf = plan.loss_grad(p0)
+    lf, gf = lf.cpu().numpy(), gf.cpu().numpy().astype(np.float64)
+    plan.set_fft_shapes(prior_late=2)
+    assert plan.autotune_info()["prior_late"] == 2
+    lr_, gr_ = plan.loss_grad(p0)
+    lr_, gr_ = lr_.cpu().numpy(), gr_.cpu().numpy().astype(np.float64)
+    assert abs(lr_[2] - lf[2]) <= 1e-12 * abs(lf[2])
+    assert parity.rel_err(gr_, gf) <= 1e-6
+    _compare_loss_grad(prob, d, w, p0, plan, f"riding prior, split {split}")
+    lr4 = [prob.adam_lr[k] for k in ("h", "Gamma", "a", "c")]
+    outs = []
+    for graph in (False, True):
+        plan.set_graph_mode(graph)
+        x = torch.tensor(p0, dtype=torch.float32, device="cuda")
+        m = torch.zeros_like(x)
+        v = torch.zeros_like(x)
+        for t in range(1, 4):
+            plan.step(x, m, v, t, lr4)
+        torch.cuda.synchronize()
+        outs.append((x.clone(), m.clone(), v.clone()))
+    plan.set_graph_mode(False)
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+    for bad in (3, -2):
+        with pytest.raises(RuntimeError):
+            plan.set_fft_shapes(prior_late=bad)
+
+
 def test_autotuner_per_class_choices_cache_and_parity():
     """The automatic choice times each class's alternatives; a second plan of the same
     shapes takes the cached decision; the tuned plan matches the oracle."""
