@@ -348,8 +348,9 @@ int starred_frame_transforms_info(const starred_plan *plan, int32_t *algo_out, d
  * that it runs beside the adjoint, 0 at the start of the evaluation, beside the forward
  * (bitwise the same results); 2 carries its passes in the evaluation's own launches as
  * extra work groups where they can ride (every frame on the FFT algorithm with the
- * one-launch forward, composite filters, no point-source prior; otherwise as 1). Drops
- * captured graphs. EINVAL for other values. */
+ * one-launch forward, composite filters, no point-source prior; otherwise as 1); 3 forks
+ * it after the adjoint's spectral products, beside the chunk sums and the dL/dh inverse
+ * (with a gradient; otherwise as 1). Drops captured graphs. EINVAL for other values. */
 int starred_set_fft_shapes(starred_plan *plan, int32_t adj_frames, int32_t adj_blocks, int32_t line_groups,
                            int32_t split_forward, int32_t prior_late);
 

@@ -1167,7 +1167,7 @@ int starred_set_fft_shapes(starred_plan *p, int32_t adj_frames, int32_t adj_bloc
     if (adj_blocks < 0 || adj_blocks > (1 << 20) || line_groups < 0 || line_groups > (1 << 20))
         return fail(STARRED_EINVAL, "work-group targets must lie in [1, 2^20] (0 keeps the current one)");
     if (split_forward < -1 || split_forward > 1) return fail(STARRED_EINVAL, "split_forward must be -1, 0 or 1");
-    if (prior_late < -1 || prior_late > 2) return fail(STARRED_EINVAL, "prior_late must be -1, 0, 1 or 2");
+    if (prior_late < -1 || prior_late > 3) return fail(STARRED_EINVAL, "prior_late must be -1, 0, 1, 2 or 3");
     if (prior_late >= 0) p->prior_late = prior_late;
     if (split_forward >= 0) p->fwd_split = split_forward;
     if (adj_frames) p->adj_fc = adj_frames;
@@ -1471,8 +1471,11 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         }
         n_l1 = pc.d.l1_slots();
     }
-    const bool late = !ride && fft && p->prior_late;
-    if (!ride && !late) {
+    // the fork of the prior: at the start, after the forward's launches (1, and 2 where it
+    // cannot ride), or after the adjoint's spectral products (3, with a gradient)
+    const bool late_adj = !ride && fft && grad && p->prior_late == 3;
+    const bool late = !ride && fft && p->prior_late && !late_adj;
+    if (!ride && !late && !late_adj) {
         int rc = starlet_branch(p, params, grad != nullptr, &n_l1);
         if (rc) return rc;
     }
@@ -1552,6 +1555,10 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
             e1 = p->prof_start();
             HIP_TRY(fft_spec_adj(p->st, p->fd, p->M));
             p->prof_stop(STARRED_STAGE_FFT_ACOLS, e1);
+            if (late_adj) {
+                int rc = starlet_branch(p, params, true, &n_l1);
+                if (rc) return rc;
+            }
             e1 = p->prof_start();
             HIP_TRY(fft_adj_sums(p->st, p->fd, p->M, p->d_fsum));
             p->prof_stop(STARRED_STAGE_FFT_FSUM, e1);
@@ -1765,11 +1772,12 @@ static int autotune(starred_plan *p)
             int &knob = which == 0 ? p->line_groups : (which == 1 ? p->fwd_split : p->prior_late);
             const int keep = knob;
             int best_v = keep;
-            // prior placement: forked at the start (0) or after the forward (1), or its
-            // passes carried by the step's own launches (2, where they can ride)
+            // prior placement: forked at the start (0), after the forward (1) or after the
+            // adjoint's spectral products (3), or its passes carried by the step's own
+            // launches (2, where they can ride)
             const std::vector<int> cands = which == 0   ? std::vector<int>{512, 1024, 2048}
                                            : which == 1 ? std::vector<int>{0, 1}
-                                                        : std::vector<int>{0, 1, 2};
+                                                        : std::vector<int>{0, 1, 2, 3};
             for (int v : cands) {
                 if (v == keep) continue;
                 knob = v;

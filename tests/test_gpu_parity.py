@@ -1388,7 +1388,11 @@ def test_prior_riding_in_multi_class_launches(split):
     plan.set_graph_mode(False)
     for a, b in zip(*outs):
         assert torch.equal(a, b)
-    for bad in (3, -2):
+    # the fork after the adjoint's spectral products: bitwise the forked prior's results
+    plan.set_fft_shapes(prior_late=3)
+    l3, g3 = plan.loss_grad(p0)
+    assert np.array_equal(l3.cpu().numpy(), lf) and np.array_equal(g3.cpu().numpy().astype(np.float64), gf)
+    for bad in (4, -2):
         with pytest.raises(RuntimeError):
             plan.set_fft_shapes(prior_late=bad)
 
