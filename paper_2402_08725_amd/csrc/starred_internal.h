@@ -220,10 +220,10 @@ hipError_t launch_psf_render(hipStream_t st, int N, const float *params, float *
 // counter, advanced by this launch
 hipError_t launch_psf_render64(hipStream_t st, int N, const float *params, double *s64, float *dm,
                                int *tick = nullptr);
+// model (or null): the star models alone into model (S x n^2; data, invvar, rho and part unused)
 hipError_t launch_psf_fwd(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
-                          const double *s64, const float *data, const float *invvar, float *rho, double *part);
-hipError_t launch_psf_model(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
-                            const float *s_img, float *model);
+                          const double *s64, const float *data, const float *invvar, float *rho, double *part,
+                          float *model = nullptr);
 hipError_t launch_psf_adjsum(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
                              const float *rho, const float *dm, float *grad, double *part_eta);
 // the loss, the gradient's small blocks, grad_b += prior, and (adam.params non-null) the update
@@ -234,6 +234,5 @@ int psf_fwd_tiles(int n);   // forward tiles per star (four FP64 partials each)
 int psf_adj_tiles(int N);   // adjoint tiles (five FP64 partials each)
 size_t psf_fwd_lds(int s);
 size_t psf_adj_lds(int s, int S);
-size_t psf_model_lds(int n, int N);
 
 }  // namespace starred

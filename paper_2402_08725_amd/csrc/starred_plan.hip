@@ -164,7 +164,7 @@ struct starred_plan {
 
     // PSF mode
     int psf_n = 0;
-    float *d_simg = nullptr, *d_dm = nullptr;
+    float *d_dm = nullptr;
     double *d_s64 = nullptr;
     double *d_part_eta = nullptr;
     int algo_req = STARRED_CONV_AUTO;
@@ -946,10 +946,9 @@ static int build_psf(starred_plan *p)
     p->ndata = (long long)S * n * n;
     p->nfine = (long long)N * N;
     const long long NN = (long long)N * N;
-    if (psf_fwd_lds(p->s) > kMaxLds || psf_adj_lds(p->s, S) > kMaxLds || psf_model_lds(n, N) > kMaxLds)
-        return fail(STARRED_EUNSUPPORTED, "PSF grid too large for one work group");
+    if (psf_fwd_lds(p->s) > kMaxLds || psf_adj_lds(p->s, S) > kMaxLds)
+        return fail(STARRED_EUNSUPPORTED, "PSF tiles too large for one work group");
     int rc;
-    if ((rc = p->alloc(&p->d_simg, NN))) return rc;
     if ((rc = p->alloc(&p->d_s64, NN))) return rc;
     if ((rc = p->alloc(&p->d_dm, 5 * NN))) return rc;
     if ((rc = p->alloc(&p->d_rho, p->ndata))) return rc;
@@ -1853,8 +1852,10 @@ int starred_psf_model(starred_plan *p, const float *params, float *model)
 {
     if (!p || !params || !model) return fail(STARRED_EINVAL, "NULL argument");
     if (p->mode != STARRED_PSF) return fail(STARRED_EUNSUPPORTED, "starred_psf_model needs a PSF-mode plan");
-    HIP_TRY(launch_psf_render(p->st, p->N, params, p->d_simg));
-    HIP_TRY(launch_psf_model(p->st, p->E, p->psf_n, p->s, p->N, p->sigma, params, p->d_simg, model));
+    // the forward's tiles in model mode over the FP64 PSF
+    HIP_TRY(launch_psf_render64(p->st, p->N, params, p->d_s64, nullptr));
+    HIP_TRY(launch_psf_fwd(p->st, p->E, p->psf_n, p->s, p->N, p->sigma, params, p->d_s64, nullptr, nullptr, nullptr,
+                           nullptr, model));
     return STARRED_OK;
 }
 

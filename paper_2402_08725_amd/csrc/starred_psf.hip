@@ -186,7 +186,7 @@ template <int SS>
 __global__ __launch_bounds__(kPsfThreads) void k_psf_fwd(
     int S, int n, int N, float sigma, const float *__restrict__ params,
     const double *__restrict__ s64, const float *__restrict__ data, const float *__restrict__ invvar,
-    float *__restrict__ rho, double *__restrict__ part)
+    float *__restrict__ rho, double *__restrict__ part, float *__restrict__ model)
 {
     using Win = PsfFwdWin<SS>;
     constexpr int T = Win::T, RM = Win::RM, CM = Win::CM, QT = kPsfColTile;
@@ -200,7 +200,9 @@ __global__ __launch_bounds__(kPsfThreads) void k_psf_fwd(
     const int pl = threadIdx.x / QT, ql = threadIdx.x % QT;
     const bool own = p0 + pl < n && q0 + ql < n;
     const long long idx = (long long)k * n * n + (long long)(p0 + pl) * n + q0 + ql;
-    const double dat = own ? (double)data[idx] : 0.0, wgt = own ? (double)invvar[idx] : 0.0;
+    // (model != null: the star models alone, m_k = a_k u, no data)
+    const bool fit = own && !model;
+    const double dat = fit ? (double)data[idx] : 0.0, wgt = fit ? (double)invvar[idx] : 0.0;
     const double a = params[5 + NN + k];
     const double cx = params[5 + NN + S + 2 * k], cy = params[5 + NN + S + 2 * k + 1];
     const int fx = (int)floor(cx), fy = (int)floor(cy);
@@ -271,61 +273,23 @@ __global__ __launch_bounds__(kPsfThreads) void k_psf_fwd(
             uy = fma(dG[1][t], v, uy);
             ux = fma(G[1][t], T1x[(rb + t) * QT + ql], ux);
         }
-        const double r = a * u - dat;
-        const double rh = wgt * r;
-        rho[idx] = (float)rh;
-        sums[0] = 0.5 * wgt * r * r;
-        sums[1] = rh * u;
-        sums[2] = rh * ux;
-        sums[3] = rh * uy;
+        if (model) {
+            model[idx] = (float)(a * u);
+        } else {
+            const double r = a * u - dat;
+            const double rh = wgt * r;
+            rho[idx] = (float)rh;
+            sums[0] = 0.5 * wgt * r * r;
+            sums[1] = rh * u;
+            sums[2] = rh * ux;
+            sums[3] = rh * uy;
+        }
     }
     block_sum_vec<kPsfThreads, 4>(sums, red);
     if (threadIdx.x == 0 && part) {
         double *o = part + ((long long)k * gridDim.x * gridDim.y + (long long)blockIdx.y * gridDim.x + blockIdx.x) * 4;
 #pragma unroll
         for (int j = 0; j < 4; ++j) o[j] = sums[j];
-    }
-}
-
-// star models only (no data): m_k packed S x n^2
-__global__ __launch_bounds__(kPsfThreads) void k_psf_model(int S, int n, int s, int N, float sigma,
-                                                           const float *__restrict__ params,
-                                                           const float *__restrict__ s_img,
-                                                           float *__restrict__ model)
-{
-    extern __shared__ float sm[];
-    __shared__ float G[2][kPsfMaxT], dG[2][kPsfMaxT];
-    const int k = blockIdx.x;
-    const long long NN = (long long)N * N;
-    const float a = params[5 + NN + k];
-    const float cx = params[5 + NN + S + 2 * k], cy = params[5 + NN + S + 2 * k + 1];
-    const int T = 2 * kGaussRadius + s + 2;
-    psf_taps(cx, s, sigma, T, G[0], dG[0]);
-    psf_taps(cy, s, sigma, T, G[1], dG[1]);
-    __syncthreads();
-    const int fx = (int)floorf(cx), fy = (int)floorf(cy);
-    float *T1 = sm;
-    for (int e = threadIdx.x; e < N * n; e += blockDim.x) {
-        const int yp = e / n, q = e - yp * n;
-        const int xb = s * q - fx - kGaussRadius - 1;
-        const float *row = s_img + (long long)yp * N;
-        float acc = 0.f;
-        for (int u = 0; u < T; ++u) {
-            const int xx = xb + u;
-            if (xx >= 0 && xx < N) acc = fmaf(G[0][u], row[xx], acc);
-        }
-        T1[e] = acc;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-        const int p = e / n, q = e - p * n;
-        const int yb = s * p - fy - kGaussRadius - 1;
-        float u = 0.f;
-        for (int t = 0; t < T; ++t) {
-            const int yy = yb + t;
-            if (yy >= 0 && yy < N) u = fmaf(G[1][t], T1[yy * n + q], u);
-        }
-        model[(long long)k * n * n + e] = a * u;
     }
 }
 
@@ -638,23 +602,14 @@ __global__ __launch_bounds__(256) void k_psf_finalize(int S, int N, int tiles, c
     }
 }
 
-size_t psf_model_lds(int n, int N) { return (size_t)n * N * sizeof(float); }
-
 hipError_t launch_psf_fwd(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
-                          const double *s64, const float *data, const float *invvar, float *rho, double *part)
+                          const double *s64, const float *data, const float *invvar, float *rho, double *part,
+                          float *model)
 {
     const dim3 grid((n + kPsfRowChunk - 1) / kPsfRowChunk, (n + kPsfColTile - 1) / kPsfColTile, S);
     auto kern = ss == 1 ? k_psf_fwd<1> : ss == 2 ? k_psf_fwd<2> : k_psf_fwd<3>;
     hipLaunchKernelGGL(kern, grid, dim3(kPsfThreads), psf_fwd_lds(ss), st, S, n, N, sigma, params, s64, data, invvar,
-                       rho, part);
-    return hipGetLastError();
-}
-
-hipError_t launch_psf_model(hipStream_t st, int S, int n, int ss, int N, float sigma, const float *params,
-                            const float *s_img, float *model)
-{
-    hipLaunchKernelGGL(k_psf_model, dim3(S), dim3(kPsfThreads), psf_model_lds(n, N), st, S, n, ss, N, sigma,
-                       params, s_img, model);
+                       rho, part, model);
     return hipGetLastError();
 }
 

@@ -464,6 +464,8 @@ PSF_CASES = [
     ("psf_s3_ragged", dict(S=3, n=37, s=3, J=4)),
     # s = 1: more stars than one adjoint batch holds, ragged 21 x 21 grid
     ("psf_s1_batches", dict(S=12, n=21, s=1, J=3)),
+    # a 384 x 384 grid: the tiles are the same size at any grid (no per-star planes in LDS)
+    ("psf_n128_s3", dict(S=2, n=128, s=3, J=5)),
     ("psf_cfg3", dict()),
 ]
 
