@@ -1402,10 +1402,21 @@ static int prior_launches(starred_plan *p, hipStream_t st, const float *img, boo
 }
 
 // The prior on the second stream: fork from st, join with ev_join (the caller
-// waits on it before the final reductions).
-static int starlet_branch(starred_plan *p, const float *img, bool want_grad, int *n_l1)
+// waits on it before the final reductions). The fork point is the work st holds
+// when starlet_fork records it; starlet_launch may follow later launches on st.
+// (A captured graph's executor keeps a node's hardware queue for the child that
+// was captured first and moves the others to further queues; launching the main
+// stream's next kernel before the branch keeps a step's longer chain on one queue,
+// so that the prior is the one crossing queues, each crossing costing several
+// microseconds.)
+static int starlet_fork(starred_plan *p)
 {
     HIP_TRY(hipEventRecord(p->ev_fork, p->st));
+    return STARRED_OK;
+}
+
+static int starlet_launch(starred_plan *p, const float *img, bool want_grad, int *n_l1)
+{
     HIP_TRY(hipStreamWaitEvent(p->st2, p->ev_fork, 0));
     hipEvent_t e0 = p->prof_start(p->st2);
     int rc = prior_launches(p, p->st2, img, want_grad, n_l1);
@@ -1474,9 +1485,17 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
     // cannot ride), or after the adjoint's spectral products (3, with a gradient)
     const bool late_adj = !ride && fft && grad && p->prior_late == 3;
     const bool late = !ride && fft && p->prior_late && !late_adj;
+    // the prior's branch is launched after the main stream's next launch (see starlet_fork)
+    bool prior_pending = false;
+    auto prior_flush = [&]() -> int {
+        if (!prior_pending) return STARRED_OK;
+        prior_pending = false;
+        return starlet_launch(p, params, grad != nullptr, &n_l1);
+    };
     if (!ride && !late && !late_adj) {
-        int rc = starlet_branch(p, params, grad != nullptr, &n_l1);
+        int rc = starlet_fork(p);
         if (rc) return rc;
+        prior_pending = true;
     }
     if (fft) {
         e0 = p->prof_start();
@@ -1484,6 +1503,7 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         HIP_TRY(fft_spectra(p->st, p->fd, params, p->N, p->E, p->M, p->sigma, adam ? tick : nullptr,
                             ride ? &pa : nullptr, ride ? &pb : nullptr));
         p->prof_stop(STARRED_STAGE_SPECTRA, e0);
+        if (int rc = prior_flush()) return rc;
         e0 = p->prof_start();
         hipEvent_t e1;
         // chi-square partials: the line-pass frames' row groups, then one per fused frame
@@ -1514,8 +1534,9 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         p->prof_stop(STARRED_STAGE_CONV_FWD, e0);
         n_chi = n_rows + (fused ? p->fd.n_fused : 0);
         if (late) {
-            int rc = starlet_branch(p, params, grad != nullptr, &n_l1);
+            int rc = starlet_fork(p);
             if (rc) return rc;
+            prior_pending = true;
         }
     }
     if (dir) {
@@ -1525,6 +1546,7 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
         HIP_TRY(launch_render(p->st, p->d_fr, p->E, p->Fdir, p->N, p->M, p->sigma, params, p->d_scene,
                               all ? nullptr : p->d_fdir, (int)p->fdir.size(), p->xf));
         p->prof_stop(STARRED_STAGE_RENDER, e0);
+        if (int rc = prior_flush()) return rc;
         e0 = p->prof_start();
         hipEvent_t e1 = p->prof_start();
         if (xf_fft) {
@@ -1554,13 +1576,16 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
             e1 = p->prof_start();
             HIP_TRY(fft_spec_adj(p->st, p->fd, p->M));
             p->prof_stop(STARRED_STAGE_FFT_ACOLS, e1);
+            if (int rc = prior_flush()) return rc;
             if (late_adj) {
-                int rc = starlet_branch(p, params, true, &n_l1);
+                int rc = starlet_fork(p);
                 if (rc) return rc;
+                prior_pending = true;
             }
             e1 = p->prof_start();
             HIP_TRY(fft_adj_sums(p->st, p->fd, p->M, p->d_fsum));
             p->prof_stop(STARRED_STAGE_FFT_FSUM, e1);
+            if (int rc = prior_flush()) return rc;
             e1 = p->prof_start();
             HIP_TRY(fin_rows ? fft_grad_h_cols(p->st, p->fd, ride ? &pd : nullptr)
                              : fft_grad_h_inverse(p->st, p->fd, ride ? &pd : nullptr));
@@ -1583,6 +1608,7 @@ static int loss_grad_impl(starred_plan *p, const float *params, float *grad, dou
             p->prof_stop(STARRED_STAGE_GRAD_SUMS, e0);
         }
     }
+    if (int rc = prior_flush()) return rc;
     if (split && !grad) HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join3, 0));
     if (!ride) HIP_TRY(hipStreamWaitEvent(p->st, p->ev_join, 0));
     e0 = p->prof_start();
@@ -1824,7 +1850,10 @@ static int psf_loss_grad_impl(starred_plan *p, const float *params, float *grad,
 {
     const int S = p->E, n = p->psf_n, N = p->N;
     int n_l1 = 0;
-    int rc = starlet_branch(p, params + 5, grad != nullptr, &n_l1);
+    // the prior's branch first: its chain is about as long as the stars' (render, forward,
+    // adjoint), and launching it ahead of them measured faster than after the render
+    int rc = starlet_fork(p);
+    if (!rc) rc = starlet_launch(p, params + 5, grad != nullptr, &n_l1);
     if (rc) return rc;
     hipEvent_t e0 = p->prof_start();
     HIP_TRY(launch_psf_render64(p->st, N, params, p->d_s64, grad ? p->d_dm : nullptr, tick));
